@@ -1,0 +1,219 @@
+/*
+ * l1ls.h -- C ABI of the MI355X (gfx950) solver core for l1-regularised
+ * least squares,
+ *
+ *     minimise  f_tau(x) = tau * ||x||_1 + 0.5 * ||A x - b||_2^2      (1)
+ *
+ * (Fountoulakis & Gondzio, arXiv:1503.03520, section 1, problem (1)), on
+ * instances from the paper's scalable generator (section 3.1 Procedure
+ * IGen with the SVD-known A = Q Sigma G^T of eq. (16), section 4).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP
+ *    device); all other pointers are host pointers.
+ *  - Vectors are dense, contiguous, 0-based.  x-like vectors have n FP64
+ *    entries, b-like vectors m FP64 entries, unless stated otherwise.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Every call returns an l1ls_status; nothing aborts, exits or throws
+ *    across the ABI.  On an error return no output is written and the
+ *    objects passed in stay valid.
+ *  - Objects (l1ls_instance, l1ls_fista) are owned by the library; the
+ *    caller releases them with the matching *_free / *_destroy call.
+ *    Caller-owned buffers are never retained after a call returns.
+ *  - Calls on different objects may run concurrently on different streams.
+ *    Calls on the same object must not overlap.
+ */
+#ifndef L1LS_H
+#define L1LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    L1LS_OK = 0,
+    L1LS_NOT_CONVERGED = 1,  /* max_iter reached; outputs are valid */
+    L1LS_E_ARG = -1,         /* invalid argument (sizes, NULL, ranges) */
+    L1LS_E_NOMEM = -2,       /* device allocation failed */
+    L1LS_E_HIP = -3,         /* a HIP runtime call failed */
+    L1LS_E_NONFINITE = -4,   /* NaN/Inf met in the data or the iterates */
+    L1LS_E_STATE = -5,       /* object not in a state that allows the call */
+    L1LS_E_UNSUPPORTED = -6  /* option combination not built */
+} l1ls_status;
+
+/* Arithmetic of the bulk iteration. */
+typedef enum { L1LS_F32 = 0, L1LS_F64 = 1 } l1ls_precision;
+
+/* Operator used for products with A and A^T. */
+typedef enum {
+    L1LS_OP_STORED = 0,      /* stored CSR (A x) and CSC (A^T y) */
+    L1LS_OP_MATRIX_FREE = 1  /* Givens stages applied on the fly (MvPA/MvPAt) */
+} l1ls_operator;
+
+/* Storage kept by l1ls_generate_ex (bit mask). */
+#define L1LS_STORE_F32 1u    /* CSR + CSC values in FP32 (int32 indices)   */
+#define L1LS_STORE_F64 2u    /* CSR + CSC values in FP64 (same indices)     */
+
+typedef struct {
+    int32_t rounds;      /* Givens stages per side, 1 or 2 (nnz/col <= 4^rounds) */
+    uint32_t storage;    /* L1LS_STORE_* mask; 0 = matrix-free only            */
+    void* stream;        /* stream the build runs on                            */
+} l1ls_gen_opts;
+
+/* Read-only description of an instance.  Device pointers stay valid until
+ * l1ls_free.  CSR/CSC pointers are NULL when that storage was not built. */
+typedef struct {
+    int64_t m, n, s, nnz;
+    int32_t rounds;
+    uint32_t storage;
+    double kappa, tau;
+    double L;            /* lambda_max(A^T A) = sigma_1^2 (= 1)                 */
+    double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2              */
+    uint64_t seed;
+    const double* b_dev;       /* m  */
+    const double* x_star_dev;  /* n, planted minimiser                         */
+    const double* g_dev;       /* n, subgradient chosen in IGen step 2         */
+    const double* e_dev;       /* m, e = b - A x*                               */
+    const double* sigma_dev;   /* n, singular values                            */
+    const int32_t* support_dev;/* s, supp(x*) in draw order                     */
+    const int32_t* perm_n_dev; /* n, bijection pi of the n side                 */
+    const int32_t* perm_m_dev; /* m, bijection pi of the m side                 */
+    const double* cs_n_dev[2]; /* per stage: n/2 pairs of (c, s), interleaved   */
+    const double* cs_m_dev[2]; /* per stage: m/2 pairs of (c, s), interleaved   */
+    const int32_t* csr_ptr_dev;  /* m+1 */
+    const int32_t* csr_col_dev;  /* nnz, sorted within each row    */
+    const float* csr_val32_dev;  /* nnz */
+    const double* csr_val64_dev; /* nnz */
+    const int32_t* csc_ptr_dev;  /* n+1 */
+    const int32_t* csc_row_dev;  /* nnz, sorted within each column */
+    const float* csc_val32_dev;  /* nnz */
+    const double* csc_val64_dev; /* nnz */
+} l1ls_info;
+
+typedef struct l1ls_instance l1ls_instance;
+
+/*
+ * Build an instance on the current device (section 3.1 Procedure IGen with
+ * A = Q Sigma G^T, eq. (16), section 4):
+ *   sigma_j = kappa^(-(j-1)/(n-1)); G, Q = `rounds` Givens stages of random
+ *   disjoint pairs with angles uniform on [0, 2 pi); x* has s nonzeros at
+ *   random positions with N(0,1) values; g = sign(x*) on the support and
+ *   U[-0.9, 0.9] elsewhere; e = tau Q Sigma^{+T} G^T g; b = A x* + e.
+ * All random draws come from Philox-4x32-10 keyed by `seed`, so an instance
+ * is a function of (m, n, kappa, s, tau, seed, rounds).
+ * Requires m >= n >= 2, m and n even, m < 2^31, 0 <= s <= n, kappa >= 1,
+ * tau > 0, 1 <= rounds <= 2.  l1ls_generate uses rounds = 1 and both
+ * storages on the null stream.  The call returns after the build finished.
+ */
+l1ls_status l1ls_generate(int64_t m, int64_t n, double kappa, int64_t s,
+                          double tau, uint64_t seed, l1ls_instance** out);
+l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int64_t s,
+                             double tau, uint64_t seed, const l1ls_gen_opts* opts,
+                             l1ls_instance** out);
+l1ls_status l1ls_instance_info(const l1ls_instance* inst, l1ls_info* out);
+void l1ls_free(l1ls_instance* inst);
+
+/*
+ * Products with the instance's operator (section 4, Algorithms MvPA and
+ * MvPAt, or the stored CSR/CSC of the same A):
+ *   trans = 0: out_dev (m) = A in_dev (n);  trans = 1: out_dev (n) = A^T in_dev (m).
+ * prec selects the value type of in_dev/out_dev and of the arithmetic
+ * (float for L1LS_F32, double for L1LS_F64).  Asynchronous on `stream`.
+ */
+l1ls_status l1ls_apply(const l1ls_instance* inst, int32_t trans, int32_t op,
+                       int32_t prec, const void* in_dev, void* out_dev, void* stream);
+
+/*
+ * Duality gap of problem (1) at x (FP64 stored operator):
+ *   P = f_tau(x), r = A x - b, theta = min(1, tau/||A^T r||_inf),
+ *   D = -0.5 ||theta r||^2 - b^T (theta r)  (Lasso dual, a lower bound on
+ *   the optimum of (1)),  rel_gap = (P - D)/|P|.
+ * Outputs are host doubles; the call synchronises `stream`.
+ */
+l1ls_status l1ls_objective_gap(const l1ls_instance* inst, double tau, const double* x_dev,
+                               double* primal, double* dual, double* rel_gap, void* stream);
+
+typedef struct {
+    double tau;            /* <= 0: the instance's tau                          */
+    double rel_gap_tol;    /* stop when (P - D)/|P| <= tol; 0: run max_iter     */
+    int64_t max_iter;
+    int32_t check_every;   /* gap evaluated every this many iterations (>= 1)   */
+    int32_t precision;     /* l1ls_precision of the bulk iteration              */
+    int32_t op;            /* l1ls_operator                                     */
+    int32_t polish;        /* 1: FP64 polish of the reduced problem at the end  */
+    double L;              /* <= 0: the instance's L (sigma_1^2)                 */
+    const double* x0_dev;  /* n, warm start; NULL: x0 = 0                       */
+    void* stream;
+    int32_t time_kernels;  /* 1: accumulate per-kernel HIP-event times          */
+    /* CG-Newton only (section 8.1 item pdNCG, section 8.3): */
+    double mu;             /* pseudo-Huber parameter; <= 0: 1e-5                */
+    double pcg_rtol;       /* <= 0: 0.1                                         */
+    int32_t max_backtrack; /* <= 0: 50                                          */
+    int32_t pcg_maxit;     /* <= 0: 1000                                        */
+    int32_t hessian;       /* 0: primal-dual diagonal, 1: exact primal Hessian  */
+} l1ls_solve_opts;
+
+typedef struct {
+    int64_t iterations;    /* FISTA iterations, or Newton steps                 */
+    int64_t inner;         /* total PCG iterations (CG-Newton, polish)          */
+    double primal, dual, rel_gap;   /* FP64 gap at the returned x              */
+    double rel_err;        /* ||x - x*|| / ||x*|| against the planted x*        */
+    double seconds;        /* wall time of the solve                             */
+    int32_t converged;
+    int32_t polish_rounds;
+} l1ls_report;
+
+/* Fill opts with defaults: tau from the instance, tol 1e-8, 10000 iters,
+ * check every 32, FP64, stored operator, no polish. */
+void l1ls_solve_opts_default(l1ls_solve_opts* opts);
+
+/*
+ * FISTA (section 8.1; separable model (4) with H = L I, exact
+ * soft-threshold step of section 2) from x0, then optionally the FP64
+ * polish.  x_out_dev receives n FP64 values.  Returns L1LS_OK when the
+ * relative gap reached rel_gap_tol, L1LS_NOT_CONVERGED at max_iter.
+ */
+l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* opts,
+                             double* x_out_dev, l1ls_report* report);
+
+/*
+ * Second-order path (section 2, problem (8) with the pseudo-Huber function
+ * (7) and Newton model (9); section 8.1 item pdNCG, section 8.3): Newton
+ * directions from preconditioned CG with the inverse Hessian diagonal as
+ * preconditioner, relative residual pcg_rtol, Armijo backtracking of at most
+ * max_backtrack halvings; then the FP64 polish if opts.polish.
+ */
+l1ls_status l1ls_solve_cg_newton(const l1ls_instance* inst, const l1ls_solve_opts* opts,
+                                 double* x_out_dev, l1ls_report* report);
+
+/*
+ * Stepping interface of FISTA (the iteration above, state kept on the
+ * device).  create: x_0 = x0 (or 0), one residual pass.  iterate: enqueue
+ * `iters` iterations on opts.stream without synchronising; once the gap test
+ * has passed, further iterations are no-ops on the device.  report:
+ * synchronises and returns the last evaluated gap.  get_x: copies the
+ * current iterate (FP64) to x_out_dev.
+ */
+typedef struct l1ls_fista l1ls_fista;
+l1ls_status l1ls_fista_create(const l1ls_instance* inst, const l1ls_solve_opts* opts,
+                              l1ls_fista** out);
+l1ls_status l1ls_fista_iterate(l1ls_fista* st, int64_t iters);
+l1ls_status l1ls_fista_report(l1ls_fista* st, l1ls_report* report);
+l1ls_status l1ls_fista_get_x(l1ls_fista* st, double* x_out_dev);
+/* Per-kernel HIP-event times (ms, summed) and launch counts accumulated since
+ * create when opts.time_kernels = 1: [0] residual pass (CSR A x),
+ * [1] transpose pass (CSC A^T r + prox), [2] gap evaluation. */
+l1ls_status l1ls_fista_kernel_times(l1ls_fista* st, double ms[3], int64_t launches[3]);
+void l1ls_fista_destroy(l1ls_fista* st);
+
+const char* l1ls_status_string(int32_t status);
+/* ABI version of this header (incremented on incompatible changes). */
+int32_t l1ls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* L1LS_H */

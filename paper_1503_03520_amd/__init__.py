@@ -1,0 +1,298 @@
+"""Python binding of the l1ls HIP library (``include/l1ls.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of ``libl1ls.so``.  PyTorch supplies device memory (output tensors) and
+streams.  Importing this package never falls back to another
+implementation: if the shared library is missing, ``lib()`` raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libl1ls.so")
+
+L1LS_OK = 0
+L1LS_NOT_CONVERGED = 1
+F32, F64 = 0, 1
+OP_STORED, OP_MATRIX_FREE = 0, 1
+STORE_F32, STORE_F64 = 1, 2
+
+_STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "device allocation failed",
+           -3: "HIP runtime error", -4: "non-finite value", -5: "invalid state", -6: "unsupported"}
+
+
+class L1lsError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: l1ls status {status} ({_STATUS.get(status, '?')})")
+
+
+class GenOpts(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("s", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32),
+        ("kappa", ctypes.c_double), ("tau", ctypes.c_double), ("L", ctypes.c_double),
+        ("f_star", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("b_dev", ctypes.c_void_p), ("x_star_dev", ctypes.c_void_p), ("g_dev", ctypes.c_void_p),
+        ("e_dev", ctypes.c_void_p), ("sigma_dev", ctypes.c_void_p), ("support_dev", ctypes.c_void_p),
+        ("perm_n_dev", ctypes.c_void_p), ("perm_m_dev", ctypes.c_void_p),
+        ("cs_n_dev", ctypes.c_void_p * 2), ("cs_m_dev", ctypes.c_void_p * 2),
+        ("csr_ptr_dev", ctypes.c_void_p), ("csr_col_dev", ctypes.c_void_p),
+        ("csr_val32_dev", ctypes.c_void_p), ("csr_val64_dev", ctypes.c_void_p),
+        ("csc_ptr_dev", ctypes.c_void_p), ("csc_row_dev", ctypes.c_void_p),
+        ("csc_val32_dev", ctypes.c_void_p), ("csc_val64_dev", ctypes.c_void_p),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double), ("rel_gap_tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
+        ("check_every", ctypes.c_int32), ("precision", ctypes.c_int32), ("op", ctypes.c_int32),
+        ("polish", ctypes.c_int32), ("L", ctypes.c_double), ("x0_dev", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("time_kernels", ctypes.c_int32),
+        ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
+        ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int64), ("inner", ctypes.c_int64), ("primal", ctypes.c_double),
+        ("dual", ctypes.c_double), ("rel_gap", ctypes.c_double), ("rel_err", ctypes.c_double),
+        ("seconds", ctypes.c_double), ("converged", ctypes.c_int32), ("polish_rounds", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Every symbol include/l1ls.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_SIGS = {
+    "l1ls_generate": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "l1ls_generate_ex": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int64,
+                                        ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(GenOpts),
+                                        ctypes.POINTER(_P)]),
+    "l1ls_instance_info": (ctypes.c_int, [_P, ctypes.POINTER(Info)]),
+    "l1ls_free": (None, [_P]),
+    "l1ls_apply": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "l1ls_objective_gap": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
+    "l1ls_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
+    "l1ls_solve_fista": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_fista_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), ctypes.POINTER(_P)]),
+    "l1ls_fista_iterate": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "l1ls_fista_report": (ctypes.c_int, [_P, ctypes.POINTER(Report)]),
+    "l1ls_fista_get_x": (ctypes.c_int, [_P, _P]),
+    "l1ls_fista_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "l1ls_fista_destroy": (None, [_P]),
+    "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "l1ls_version": (ctypes.c_int32, []),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """The loaded libl1ls.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status, where, allow=(L1LS_OK,)):
+    if status not in allow:
+        raise L1lsError(status, where)
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Instance:
+    """Owns an l1ls_instance (l1ls_generate / l1ls_generate_ex)."""
+
+    def __init__(self, handle, params):
+        self._h = handle
+        self.params = params
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        inf = Info()
+        _check(lib().l1ls_instance_info(self._h, ctypes.byref(inf)), "l1ls_instance_info")
+        return inf
+
+    def free(self):
+        if self._h:
+            lib().l1ls_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def l1ls_generate(m, n, kappa, s, tau, seed, rounds=1, storage=STORE_F32 | STORE_F64, stream=None):
+    h = ctypes.c_void_p()
+    o = GenOpts(rounds, storage, _stream(stream))
+    _check(lib().l1ls_generate_ex(m, n, kappa, s, tau, seed, ctypes.byref(o), ctypes.byref(h)),
+           "l1ls_generate_ex")
+    return Instance(h, dict(m=m, n=n, kappa=kappa, s=s, tau=tau, seed=seed, rounds=rounds, storage=storage))
+
+
+generate = l1ls_generate
+
+
+def solve_opts(**kw):
+    o = SolveOpts()
+    lib().l1ls_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "stream":
+            o.stream = _stream(v)
+        elif k == "x0":
+            o.x0_dev = _ptr(v)
+        else:
+            setattr(o, k, v)
+    if "stream" not in kw:
+        o.stream = _stream(None)
+    return o
+
+
+def l1ls_apply(inst, trans, op, prec, x_in, x_out, stream=None):
+    _check(lib().l1ls_apply(inst.handle, trans, op, prec, _ptr(x_in), _ptr(x_out), _stream(stream)),
+           "l1ls_apply")
+
+
+def l1ls_objective_gap(inst, tau, x, stream=None):
+    P, D, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().l1ls_objective_gap(inst.handle, tau, _ptr(x), ctypes.byref(P), ctypes.byref(D),
+                                    ctypes.byref(g), _stream(stream)), "l1ls_objective_gap")
+    return P.value, D.value, g.value
+
+
+def _solve(fn, name, inst, x_out, kw):
+    import torch
+    n = inst.params["n"]
+    if x_out is None:
+        x_out = torch.empty(n, dtype=torch.float64, device="cuda")
+    o = solve_opts(**kw)
+    rep = Report()
+    st = _check(fn(inst.handle, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)), name,
+                allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+    return x_out, rep.as_dict(), st
+
+
+def l1ls_solve_fista(inst, x_out=None, **kw):
+    return _solve(lib().l1ls_solve_fista, "l1ls_solve_fista", inst, x_out, kw)
+
+
+def l1ls_solve_cg_newton(inst, x_out=None, **kw):
+    return _solve(lib().l1ls_solve_cg_newton, "l1ls_solve_cg_newton", inst, x_out, kw)
+
+
+class Fista:
+    """The stepping interface (l1ls_fista_create / iterate / report / get_x)."""
+
+    def __init__(self, inst, **kw):
+        self.inst = inst
+        self._opts = solve_opts(**kw)
+        self._keep = kw.get("x0")
+        h = ctypes.c_void_p()
+        _check(lib().l1ls_fista_create(inst.handle, ctypes.byref(self._opts), ctypes.byref(h)),
+               "l1ls_fista_create")
+        self._h = h
+
+    def iterate(self, iters):
+        _check(lib().l1ls_fista_iterate(self._h, int(iters)), "l1ls_fista_iterate")
+
+    def report(self):
+        rep = Report()
+        _check(lib().l1ls_fista_report(self._h, ctypes.byref(rep)), "l1ls_fista_report")
+        return rep.as_dict()
+
+    def get_x(self, x_out=None):
+        import torch
+        if x_out is None:
+            x_out = torch.empty(self.inst.params["n"], dtype=torch.float64, device="cuda")
+        _check(lib().l1ls_fista_get_x(self._h, _ptr(x_out)), "l1ls_fista_get_x")
+        return x_out
+
+    def kernel_times(self):
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_int64 * 3)()
+        _check(lib().l1ls_fista_kernel_times(self._h, ms, cnt), "l1ls_fista_kernel_times")
+        return list(ms), list(cnt)
+
+    def destroy(self):
+        if self._h:
+            lib().l1ls_fista_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# device -> host copies of raw device pointers (instance arrays)
+# --------------------------------------------------------------------------
+_hip = None
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipDeviceSynchronize.restype = ctypes.c_int
+    return _hip
+
+
+def device_to_numpy(ptr, count, dtype):
+    """Copy `count` elements of numpy `dtype` from a raw device pointer."""
+    import numpy as np
+    out = np.empty(int(count), dtype=dtype)
+    if count == 0:
+        return out
+    rt = _hiprt()
+    if rt.hipDeviceSynchronize() != 0:
+        raise RuntimeError("hipDeviceSynchronize failed")
+    rc = rt.hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out

@@ -1,0 +1,157 @@
+// Shared internals of the l1ls HIP library: status helpers, the instance
+// object, wave64 reductions and the deterministic FP64 block reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "../../include/l1ls.h"
+
+#define L1LS_MAX_ROUNDS 2
+#define L1LS_WAVE 64
+#define L1LS_BLOCK 256
+
+// Return L1LS_E_HIP from the enclosing function when a HIP call fails.
+#define HIP_TRY(expr)                                                        \
+    do {                                                                     \
+        hipError_t _e = (expr);                                              \
+        if (_e != hipSuccess) {                                              \
+            if (std::getenv("L1LS_DEBUG"))                                   \
+                std::fprintf(stderr, "l1ls: %s failed: %s (%s:%d)\n", #expr, \
+                             hipGetErrorString(_e), __FILE__, __LINE__);     \
+            return _e == hipErrorOutOfMemory ? L1LS_E_NOMEM : L1LS_E_HIP;    \
+        }                                                                    \
+    } while (0)
+
+#define L1LS_TRY(expr)                        \
+    do {                                      \
+        l1ls_status _s = (expr);              \
+        if (_s != L1LS_OK) return _s;         \
+    } while (0)
+
+// Device allocation list owned by one object; freed in reverse order.
+struct DevArena {
+    std::vector<void*> ptrs;
+    template <typename T>
+    l1ls_status alloc(T** p, size_t count) {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? L1LS_E_NOMEM : L1LS_E_HIP;
+        ptrs.push_back(q);
+        *p = static_cast<T*>(q);
+        return L1LS_OK;
+    }
+    void release() {
+        for (size_t i = ptrs.size(); i-- > 0;) (void)hipFree(ptrs[i]);
+        ptrs.clear();
+    }
+};
+
+// Pair tables of one side: bijection pi (position -> index), its inverse,
+// and per stage the (c, s) of each of the N/2 rotations (FP64, interleaved).
+struct SideTables {
+    int64_t N = 0;
+    int32_t* perm = nullptr;
+    int32_t* pinv = nullptr;
+    double* cs[L1LS_MAX_ROUNDS] = {nullptr, nullptr};
+};
+
+struct l1ls_instance {
+    int64_t m = 0, n = 0, s = 0, nnz = 0;
+    int32_t rounds = 1;
+    uint32_t storage = 0;
+    double kappa = 1, tau = 1, L = 1, fstar = 0;
+    uint64_t seed = 0;
+    int device = 0;
+    SideTables side[2];           // [0] = n side (G), [1] = m side (Q)
+    double* sigma = nullptr;      // n
+    double* xstar = nullptr;      // n
+    double* g = nullptr;          // n
+    double* e = nullptr;          // m
+    double* b = nullptr;          // m
+    float* b32 = nullptr;         // m
+    int32_t* support = nullptr;   // s
+    double* colnorm2 = nullptr;   // n, diag(A^T A)
+    int32_t* csr_ptr = nullptr;   // m+1
+    int32_t* csr_col = nullptr;
+    double* csr_v64 = nullptr;
+    float* csr_v32 = nullptr;
+    int32_t* csc_ptr = nullptr;   // n+1
+    int32_t* csc_row = nullptr;
+    double* csc_v64 = nullptr;
+    float* csc_v32 = nullptr;
+    DevArena arena;
+};
+
+// ---------------------------------------------------------------------------
+// wave64 / block reductions
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = L1LS_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L1LS_WAVE);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = L1LS_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, L1LS_WAVE));
+    return v;
+}
+
+// Sum over a segment of W consecutive lanes (W a power of two <= 64); every
+// lane of the segment ends with the segment total.
+template <int W, typename T>
+__device__ __forceinline__ T segment_sum(T v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// Deterministic block reduction of NS FP64 statistics: stats with index in
+// [0, NSUM) are summed, the rest take the maximum.  The result is valid in
+// thread 0.  Fixed order: butterfly inside each wave, then waves in order.
+template <int NS, int NSUM>
+__device__ __forceinline__ void block_reduce_stats(double (&v)[NS]) {
+    __shared__ double red[L1LS_BLOCK / L1LS_WAVE][NS];
+    const int lane = threadIdx.x % L1LS_WAVE;
+    const int wid = threadIdx.x / L1LS_WAVE;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = (i < NSUM) ? wave_sum(v[i]) : wave_max(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) red[wid][i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            double a = red[0][i];
+            for (int w = 1; w < (int)(blockDim.x / L1LS_WAVE); ++w)
+                a = (i < NSUM) ? a + red[w][i] : fmax(a, red[w][i]);
+            v[i] = a;
+        }
+    }
+    __syncthreads();
+}
+
+inline int grid_for(int64_t work_items, int items_per_block, int cap) {
+    int64_t g = (work_items + items_per_block - 1) / items_per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// Exclusive prefix sum of int32 counts into int32 offsets (n+1 outputs).
+l1ls_status exclusive_scan_i32(const int32_t* counts, int32_t* offsets, int64_t n,
+                               hipStream_t stream, DevArena& tmp);
+
+// Host-side checks of pointer validity for the ABI.
+inline bool is_finite(double v) { return v == v && v - v == 0.0; }

@@ -1,0 +1,564 @@
+// FISTA driver (section 8.1: the separable model (4) with H = L I and the
+// exact soft-threshold step of section 2, t_k momentum), the stepping API,
+// operator products and the FP64 duality gap of problem (1).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace l1ls;
+
+template <typename T>
+l1ls_status apply_side(const SideTables& tab, int rounds, bool transpose, T* v, T* scratch, hipStream_t stream);
+l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
+                        int64_t* pcg_iters_out);
+
+namespace {
+
+constexpr int kW_rows = 8;    // lanes per CSR row (<= 16 entries, 8 on average at 2 stages)
+constexpr int kW_cols = 16;   // lanes per CSC column (<= 16 entries, ~16 at 2 stages)
+constexpr int kGridCap = 2048;
+
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, evaluated without contraction.
+inline double next_t(double t) {
+#pragma clang fp contract(off)
+    return (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ o, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) o[i] = (float)a[i];
+}
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ o, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) o[i] = (double)a[i];
+}
+template <typename T>
+__global__ void k_fill(T* __restrict__ a, T v, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) a[i] = v;
+}
+__global__ void k_init_gap(GapState* gs) {
+    gs->P = gs->D = gs->gap = 0.0;
+    gs->ginf = gs->l1 = gs->rr = 0.0;
+    gs->iter = 0;
+    gs->conv_iter = -1;
+    gs->done = 0;
+    gs->nonfinite = 0;
+}
+
+// Column statistics for the gap at an arbitrary x: max |A^T r|, sum |x|.
+template <typename T, int W>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_colstats(const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ row,
+                                                         const T* __restrict__ val, const T* __restrict__ r,
+                                                         const T* __restrict__ x, int64_t n,
+                                                         double* __restrict__ part) {
+    const int lane = threadIdx.x % W;
+    const int64_t nseg = (int64_t)gridDim.x * (blockDim.x / W);
+    double v[2] = {0.0, 0.0};
+    for (int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / W; j < n; j += nseg) {
+        const int32_t beg = ptr[j], end = ptr[j + 1];
+        T acc = T(0);
+        for (int32_t k = beg + lane; k < end; k += W) acc += val[k] * r[row[k]];
+        acc = segment_sum<W>(acc);
+        if (lane == 0) {
+            v[0] += fabs((double)x[j]);
+            v[1] = fmax(v[1], fabs((double)acc));
+        }
+    }
+    block_reduce_stats<2, 1>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = v[1];
+        part[2 * blockIdx.x + 1] = v[0];
+    }
+}
+
+// sum (x - x*)^2 and sum x*^2
+__global__ __launch_bounds__(L1LS_BLOCK) void k_err_partials(const double* __restrict__ x,
+                                                             const double* __restrict__ xs, int64_t n,
+                                                             double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double d = x[i] - xs[i];
+        v[0] += d * d;
+        v[1] += xs[i] * xs[i];
+    }
+    block_reduce_stats<2, 2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+inline dim3 g1d(int64_t N) { return dim3((unsigned)std::max<int64_t>(1, (N + L1LS_BLOCK - 1) / L1LS_BLOCK)); }
+
+}  // namespace
+
+struct l1ls_fista {
+    const l1ls_instance* I = nullptr;
+    l1ls_solve_opts o;
+    hipStream_t stream = nullptr;
+    int prec = L1LS_F64;
+    double tau = 1, L = 1;
+    void* x[2] = {nullptr, nullptr};  // x_k lives in x[k & 1]
+    void* rx = nullptr;
+    void* ry = nullptr;
+    double* k1part = nullptr;  // [2][g1][3], slot k & 1 written by the residual pass of iteration k
+    double* k2part = nullptr;  // [g2][2]
+    GapState* gs = nullptr;
+    int g1 = 0, g2 = 0;
+    int64_t k = 0;             // iterations enqueued
+    double t_k = 1.0;          // t_k for the next iteration k+1 (t_1 = 1)
+    double beta_prev = 0.0;    // beta_{k-1}
+    // kernel timing
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+    DevArena arena;
+};
+
+namespace {
+
+hipEvent_t take_event(l1ls_fista* F) {
+    if (!F->ev_free.empty()) {
+        hipEvent_t e = F->ev_free.back();
+        F->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+l1ls_status drain_events(l1ls_fista* F) {
+    for (auto& p : F->ev_pending) {
+        HIP_TRY(hipEventSynchronize(p.second.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        F->ms[p.first] += ms;
+        F->launches[p.first] += 1;
+        F->ev_free.push_back(p.second.first);
+        F->ev_free.push_back(p.second.second);
+    }
+    F->ev_pending.clear();
+    return L1LS_OK;
+}
+
+template <typename Launch>
+l1ls_status timed(l1ls_fista* F, int which, Launch&& launch) {
+    if (!F->o.time_kernels) {
+        launch();
+        return L1LS_OK;
+    }
+    hipEvent_t a = take_event(F), b = take_event(F);
+    if (!a || !b) return L1LS_E_HIP;
+    HIP_TRY(hipEventRecord(a, F->stream));
+    launch();
+    HIP_TRY(hipEventRecord(b, F->stream));
+    F->ev_pending.push_back({which, {a, b}});
+    if (F->ev_pending.size() > 4096) L1LS_TRY(drain_events(F));
+    return L1LS_OK;
+}
+
+template <typename T>
+const T* csr_vals(const l1ls_instance* I);
+template <>
+const float* csr_vals<float>(const l1ls_instance* I) { return I->csr_v32; }
+template <>
+const double* csr_vals<double>(const l1ls_instance* I) { return I->csr_v64; }
+template <typename T>
+const T* csc_vals(const l1ls_instance* I);
+template <>
+const float* csc_vals<float>(const l1ls_instance* I) { return I->csc_v32; }
+template <>
+const double* csc_vals<double>(const l1ls_instance* I) { return I->csc_v64; }
+template <typename T>
+const T* b_vec(const l1ls_instance* I);
+template <>
+const float* b_vec<float>(const l1ls_instance* I) { return I->b32; }
+template <>
+const double* b_vec<double>(const l1ls_instance* I) { return I->b; }
+
+template <typename T>
+l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot) {
+    const l1ls_instance* I = F->I;
+    return timed(F, 0, [&] {
+        hipLaunchKernelGGL((k_residual<T, kW_rows>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
+                           I->csr_col, csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
+                           F->k1part + (size_t)slot * 3 * F->g1, F->gs);
+    });
+}
+
+template <typename T>
+l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta) {
+    const l1ls_instance* I = F->I;
+    return timed(F, 1, [&] {
+        hipLaunchKernelGGL((k_transpose_prox<T, kW_cols>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
+                           I->csc_ptr, I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L,
+                           (T)(F->tau / F->L), I->n, F->k2part, F->gs);
+    });
+}
+
+template <typename T>
+l1ls_status fista_iterate_t(l1ls_fista* F, int64_t iters) {
+    const double tol = F->o.rel_gap_tol;
+    const int check = std::max(1, F->o.check_every);
+    for (int64_t q = 0; q < iters; ++q) {
+        const int64_t k = F->k + 1;  // iteration being enqueued
+        const double t_next = next_t(F->t_k);
+        const double beta_k = (F->t_k - 1.0) / t_next;
+        T* xcur = (T*)F->x[(k - 1) & 1];
+        T* xslot = (T*)F->x[k & 1];  // holds x_{k-2}, receives x_k
+        L1LS_TRY(launch_transpose<T>(F, xcur, xslot, F->beta_prev));
+        L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1)));
+        if (k % check == 0) {
+            L1LS_TRY(timed(F, 2, [&] {
+                hipLaunchKernelGGL(k_gap, dim3(1), dim3(L1LS_BLOCK), 0, F->stream,
+                                   F->k1part + (size_t)(k & 1) * 3 * F->g1,
+                                   F->k1part + (size_t)((k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2,
+                                   F->tau, tol, k, F->gs);
+            }));
+        }
+        F->beta_prev = beta_k;
+        F->t_k = t_next;
+        F->k = k;
+    }
+    HIP_TRY(hipGetLastError());
+    return L1LS_OK;
+}
+
+l1ls_status check_stored(const l1ls_instance* I, int prec) {
+    if (!I->csr_ptr || !I->csc_ptr) return L1LS_E_UNSUPPORTED;
+    if (prec == L1LS_F32 && (!I->csr_v32 || !I->csc_v32)) return L1LS_E_UNSUPPORTED;
+    if (prec == L1LS_F64 && (!I->csr_v64 || !I->csc_v64)) return L1LS_E_UNSUPPORTED;
+    return L1LS_OK;
+}
+
+}  // namespace
+
+extern "C" void l1ls_solve_opts_default(l1ls_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tau = 0.0;
+    o->rel_gap_tol = 1e-8;
+    o->max_iter = 10000;
+    o->check_every = 32;
+    o->precision = L1LS_F64;
+    o->op = L1LS_OP_STORED;
+    o->polish = 0;
+    o->L = 0.0;
+    o->x0_dev = nullptr;
+    o->stream = nullptr;
+    o->time_kernels = 0;
+    o->mu = 1e-5;
+    o->pcg_rtol = 0.1;
+    o->max_backtrack = 50;
+    o->pcg_maxit = 1000;
+    o->hessian = 0;
+}
+
+extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solve_opts* opts, l1ls_fista** out) {
+    if (!I || !opts || !out) return L1LS_E_ARG;
+    *out = nullptr;
+    if (opts->precision != L1LS_F32 && opts->precision != L1LS_F64) return L1LS_E_ARG;
+    if (opts->op != L1LS_OP_STORED) return L1LS_E_UNSUPPORTED;
+    if (opts->check_every < 1 || opts->max_iter < 0 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
+    L1LS_TRY(check_stored(I, opts->precision));
+    const double tau = opts->tau > 0 ? opts->tau : I->tau;
+    const double L = opts->L > 0 ? opts->L : I->L;
+    if (!is_finite(tau) || !is_finite(L)) return L1LS_E_ARG;
+
+    l1ls_fista* F = new l1ls_fista();
+    F->I = I;
+    F->o = *opts;
+    F->stream = (hipStream_t)opts->stream;
+    F->prec = opts->precision;
+    F->tau = tau;
+    F->L = L;
+    F->g1 = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
+    F->g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+    const size_t es = (F->prec == L1LS_F32) ? sizeof(float) : sizeof(double);
+    auto fail = [&](l1ls_status s) {
+        F->arena.release();
+        delete F;
+        return s;
+    };
+    unsigned char *x0 = nullptr, *x1 = nullptr, *rx = nullptr, *ry = nullptr;
+    l1ls_status st;
+    if ((st = F->arena.alloc(&x0, I->n * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&x1, I->n * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&rx, I->m * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&ry, I->m * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&F->k1part, (size_t)2 * 3 * F->g1)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&F->k2part, (size_t)2 * F->g2)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&F->gs, 1)) != L1LS_OK) return fail(st);
+    F->x[0] = x0;
+    F->x[1] = x1;
+    F->rx = rx;
+    F->ry = ry;
+    hipStream_t s = F->stream;
+    // x_0 = x0 (or 0) in both slots (x_{-1} = x_0); one residual pass gives
+    // r_x,0 = A x_0 - b and r_y,1 = r_x,0 (beta_0 = 0).
+    if (F->prec == L1LS_F64) {
+        if (opts->x0_dev) {
+            if (hipMemcpyAsync(x0, opts->x0_dev, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(L1LS_E_HIP);
+        } else {
+            hipLaunchKernelGGL(k_fill<double>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (double*)x0, 0.0, I->n);
+        }
+    } else {
+        if (opts->x0_dev)
+            hipLaunchKernelGGL(k_f64_to_f32, g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev, (float*)x0, I->n);
+        else
+            hipLaunchKernelGGL(k_fill<float>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (float*)x0, 0.0f, I->n);
+    }
+    if (hipMemcpyAsync(x1, x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(L1LS_E_HIP);
+    hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
+    if (F->prec == L1LS_F64)
+        st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0);
+    else
+        st = launch_residual<float>(F, (const float*)x0, 0.0, 1, 0);
+    if (st != L1LS_OK) return fail(st);
+    if (hipGetLastError() != hipSuccess) return fail(L1LS_E_HIP);
+    *out = F;
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_fista_iterate(l1ls_fista* F, int64_t iters) {
+    if (!F || iters < 0) return L1LS_E_ARG;
+    if (F->prec == L1LS_F64) return fista_iterate_t<double>(F, iters);
+    return fista_iterate_t<float>(F, iters);
+}
+
+extern "C" l1ls_status l1ls_fista_report(l1ls_fista* F, l1ls_report* rep) {
+    if (!F || !rep) return L1LS_E_ARG;
+    GapState g;
+    HIP_TRY(hipMemcpyAsync(&g, F->gs, sizeof(g), hipMemcpyDeviceToHost, F->stream));
+    HIP_TRY(hipStreamSynchronize(F->stream));
+    std::memset(rep, 0, sizeof(*rep));
+    rep->iterations = (g.conv_iter >= 0) ? g.conv_iter : F->k;
+    rep->primal = g.P;
+    rep->dual = g.D;
+    rep->rel_gap = g.gap;
+    rep->converged = (g.conv_iter >= 0) ? 1 : 0;
+    rep->rel_err = -1.0;
+    if (g.nonfinite) return L1LS_E_NONFINITE;
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_fista_get_x(l1ls_fista* F, double* x_out) {
+    if (!F || !x_out) return L1LS_E_ARG;
+    GapState g;
+    HIP_TRY(hipMemcpyAsync(&g, F->gs, sizeof(g), hipMemcpyDeviceToHost, F->stream));
+    HIP_TRY(hipStreamSynchronize(F->stream));
+    const int64_t kk = (g.conv_iter >= 0) ? g.conv_iter : F->k;
+    void* src = F->x[kk & 1];
+    const int64_t n = F->I->n;
+    if (F->prec == L1LS_F64) {
+        HIP_TRY(hipMemcpyAsync(x_out, src, n * sizeof(double), hipMemcpyDeviceToDevice, F->stream));
+    } else {
+        hipLaunchKernelGGL(k_f32_to_f64, g1d(n), dim3(L1LS_BLOCK), 0, F->stream, (const float*)src, x_out, n);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(F->stream));
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_fista_kernel_times(l1ls_fista* F, double ms[3], int64_t launches[3]) {
+    if (!F || !ms || !launches) return L1LS_E_ARG;
+    L1LS_TRY(drain_events(F));
+    for (int i = 0; i < 3; ++i) {
+        ms[i] = F->ms[i];
+        launches[i] = F->launches[i];
+    }
+    return L1LS_OK;
+}
+
+extern "C" void l1ls_fista_destroy(l1ls_fista* F) {
+    if (!F) return;
+    (void)hipStreamSynchronize(F->stream);
+    (void)drain_events(F);
+    for (hipEvent_t e : F->ev_free) (void)hipEventDestroy(e);
+    F->arena.release();
+    delete F;
+}
+
+// ---------------------------------------------------------------------------
+// Operator products and the FP64 gap
+// ---------------------------------------------------------------------------
+template <typename T>
+l1ls_status apply_matrix_free(const l1ls_instance* I, int trans, const T* in, T* out, hipStream_t s);
+
+extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t op, int32_t prec,
+                                  const void* in, void* out, void* stream) {
+    if (!I || !in || !out || (trans != 0 && trans != 1)) return L1LS_E_ARG;
+    if (prec != L1LS_F32 && prec != L1LS_F64) return L1LS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (op == L1LS_OP_MATRIX_FREE) {
+        if (prec == L1LS_F64) return apply_matrix_free<double>(I, trans, (const double*)in, (double*)out, s);
+        return apply_matrix_free<float>(I, trans, (const float*)in, (float*)out, s);
+    }
+    if (op != L1LS_OP_STORED) return L1LS_E_ARG;
+    L1LS_TRY(check_stored(I, prec));
+    if (trans == 0) {
+        const int g = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
+        if (prec == L1LS_F64)
+            hipLaunchKernelGGL((k_spmv<double, kW_rows>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                               I->csr_v64, (const double*)in, (double*)out, I->m);
+        else
+            hipLaunchKernelGGL((k_spmv<float, kW_rows>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                               I->csr_v32, (const float*)in, (float*)out, I->m);
+    } else {
+        const int g = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+        if (prec == L1LS_F64)
+            hipLaunchKernelGGL((k_spmv<double, kW_cols>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                               I->csc_v64, (const double*)in, (double*)out, I->n);
+        else
+            hipLaunchKernelGGL((k_spmv<float, kW_cols>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                               I->csc_v32, (const float*)in, (float*)out, I->n);
+    }
+    HIP_TRY(hipGetLastError());
+    return L1LS_OK;
+}
+
+// FP64 gap at x through the stored FP64 operator.  Used by the solvers too.
+l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
+                     hipStream_t s) {
+    L1LS_TRY(check_stored(I, L1LS_F64));
+    DevArena tmp;
+    double *r = nullptr, *ry = nullptr, *p1 = nullptr, *p2 = nullptr;
+    const int g1 = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
+    const int g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+    auto done = [&](l1ls_status st) {
+        tmp.release();
+        return st;
+    };
+    l1ls_status st;
+    if ((st = tmp.alloc(&r, I->m)) != L1LS_OK) return done(st);
+    if ((st = tmp.alloc(&ry, I->m)) != L1LS_OK) return done(st);
+    if ((st = tmp.alloc(&p1, 3 * (size_t)g1)) != L1LS_OK) return done(st);
+    if ((st = tmp.alloc(&p2, 2 * (size_t)g2)) != L1LS_OK) return done(st);
+    hipLaunchKernelGGL((k_residual<double, kW_rows>), dim3(g1), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                       I->csr_v64, x, I->b, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr);
+    hipLaunchKernelGGL((k_colstats<double, kW_cols>), dim3(g2), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                       I->csc_v64, r, x, I->n, p2);
+    std::vector<double> h1(3 * (size_t)g1), h2(2 * (size_t)g2);
+    if (hipMemcpyAsync(h1.data(), p1, h1.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return done(L1LS_E_HIP);
+    if (hipMemcpyAsync(h2.data(), p2, h2.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return done(L1LS_E_HIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return done(L1LS_E_HIP);
+    double rr = 0, br = 0, l1 = 0, ginf = 0;
+    for (int b = 0; b < g1; ++b) {
+        rr += h1[3 * b];
+        br += h1[3 * b + 2];
+    }
+    for (int b = 0; b < g2; ++b) {
+        ginf = std::max(ginf, h2[2 * b]);
+        l1 += h2[2 * b + 1];
+    }
+    const double Pv = tau * l1 + 0.5 * rr;
+    const double theta = (ginf <= tau) ? 1.0 : tau / ginf;
+    const double Dv = -0.5 * theta * theta * rr - theta * br;
+    *P = Pv;
+    *D = Dv;
+    *gap = (Pv - Dv) / std::fabs(Pv);
+    tmp.release();
+    if (!is_finite(Pv) || !is_finite(Dv)) return L1LS_E_NONFINITE;
+    return L1LS_OK;
+}
+
+l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out, hipStream_t s) {
+    DevArena tmp;
+    double* p = nullptr;
+    const int g = 256;
+    L1LS_TRY(tmp.alloc(&p, 2 * g));
+    hipLaunchKernelGGL(k_err_partials, dim3(g), dim3(L1LS_BLOCK), 0, s, x, I->xstar, I->n, p);
+    std::vector<double> h(2 * g);
+    hipError_t e = hipMemcpyAsync(h.data(), p, h.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    tmp.release();
+    if (e != hipSuccess) return L1LS_E_HIP;
+    double a = 0, b = 0;
+    for (int i = 0; i < g; ++i) {
+        a += h[2 * i];
+        b += h[2 * i + 1];
+    }
+    *out = (b > 0) ? std::sqrt(a / b) : std::sqrt(a);
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_objective_gap(const l1ls_instance* I, double tau, const double* x, double* P, double* D,
+                                          double* gap, void* stream) {
+    if (!I || !x || !P || !D || !gap) return L1LS_E_ARG;
+    if (!(tau > 0) || !is_finite(tau)) return L1LS_E_ARG;
+    return gap_fp64(I, tau, x, P, D, gap, (hipStream_t)stream);
+}
+
+extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve_opts* opts, double* x_out,
+                                        l1ls_report* rep) {
+    if (!I || !opts || !x_out) return L1LS_E_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    l1ls_fista* F = nullptr;
+    L1LS_TRY(l1ls_fista_create(I, opts, &F));
+    l1ls_report r;
+    l1ls_status st = L1LS_OK;
+    const int check = std::max(1, opts->check_every);
+    // Enqueue several gap blocks ahead; passes after convergence are no-ops.
+    const int64_t ahead = (int64_t)check * 4;
+    while (F->k < opts->max_iter) {
+        const int64_t step = std::min<int64_t>(ahead, opts->max_iter - F->k);
+        if ((st = l1ls_fista_iterate(F, step)) != L1LS_OK) break;
+        st = l1ls_fista_report(F, &r);
+        if (st != L1LS_OK || r.converged) break;
+    }
+    if (st == L1LS_OK && opts->max_iter % check != 0) {
+        // evaluate the gap at the last iterate as well
+        hipLaunchKernelGGL(k_gap, dim3(1), dim3(L1LS_BLOCK), 0, F->stream,
+                           F->k1part + (size_t)(F->k & 1) * 3 * F->g1,
+                           F->k1part + (size_t)((F->k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2, F->tau,
+                           opts->rel_gap_tol, F->k, F->gs);
+    }
+    if (st == L1LS_OK) st = l1ls_fista_report(F, &r);
+    if (st == L1LS_OK || st == L1LS_E_NONFINITE) {
+        const l1ls_status s2 = l1ls_fista_get_x(F, x_out);
+        if (st == L1LS_OK) st = s2;
+    }
+    hipStream_t s = F->stream;
+    const double tau = F->tau;
+    l1ls_fista_destroy(F);
+    if (st != L1LS_OK) return st;
+    int prounds = 0;
+    int64_t pcg = 0;
+    if (opts->polish) L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &pcg));
+    // Final certificate in FP64 with the FP64 operator when it is stored.
+    if (I->csr_v64) {
+        L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));
+        r.converged = (r.rel_gap <= opts->rel_gap_tol) ? 1 : r.converged;
+    }
+    L1LS_TRY(rel_err_planted(I, x_out, &r.rel_err, s));
+    r.polish_rounds = prounds;
+    r.inner = pcg;
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    return r.converged ? L1LS_OK : L1LS_NOT_CONVERGED;
+}
+
+extern "C" const char* l1ls_status_string(int32_t s) {
+    switch (s) {
+        case L1LS_OK: return "ok";
+        case L1LS_NOT_CONVERGED: return "not converged (max_iter reached)";
+        case L1LS_E_ARG: return "invalid argument";
+        case L1LS_E_NOMEM: return "device allocation failed";
+        case L1LS_E_HIP: return "HIP runtime error";
+        case L1LS_E_NONFINITE: return "non-finite value in data or iterates";
+        case L1LS_E_STATE: return "invalid state";
+        case L1LS_E_UNSUPPORTED: return "unsupported option combination";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int32_t l1ls_version(void) { return 1; }

@@ -1,0 +1,80 @@
+"""C-ABI library: loads, exports every declared symbol, rejects bad arguments.
+
+Runs without a GPU: the argument checks of the entry points return before
+any HIP call is made.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1503_03520_amd as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "l1ls.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(l1ls_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    declared = _declared_functions()
+    assert declared, "no declarations parsed"
+    assert sorted(L.EXPORTED) == declared
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.l1ls_version() == 1
+
+
+def test_status_strings():
+    lib = L.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.l1ls_status_string(code)
+
+
+@pytest.mark.parametrize("m,n,kappa,s,tau,rounds", [
+    (100, 200, 10.0, 1, 1.0, 1),    # m < n
+    (101, 50, 10.0, 1, 1.0, 1),     # m odd
+    (100, 51, 10.0, 1, 1.0, 1),     # n odd
+    (100, 50, 0.5, 1, 1.0, 1),      # kappa < 1
+    (100, 50, 10.0, 51, 1.0, 1),    # s > n
+    (100, 50, 10.0, -1, 1.0, 1),    # s < 0
+    (100, 50, 10.0, 1, 0.0, 1),     # tau <= 0
+    (100, 50, 10.0, 1, float("nan"), 1),
+    (100, 50, float("inf"), 1, 1.0, 1),
+    (100, 50, 10.0, 1, 1.0, 3),     # rounds > 2
+    (100, 50, 10.0, 1, 1.0, 0),
+    (2, 0, 10.0, 0, 1.0, 1),        # n < 2
+])
+def test_generate_rejects_invalid_arguments(m, n, kappa, s, tau, rounds):
+    h = ctypes.c_void_p()
+    o = L.GenOpts(rounds, 3, None)
+    st = L.lib().l1ls_generate_ex(m, n, kappa, s, tau, 1, ctypes.byref(o), ctypes.byref(h))
+    assert st == -1 and not h.value
+
+
+def test_null_arguments_rejected():
+    lib = L.lib()
+    assert lib.l1ls_generate(100, 50, 10.0, 1, 1.0, 1, None) == -1
+    assert lib.l1ls_instance_info(None, None) == -1
+    assert lib.l1ls_apply(None, 0, 0, 1, None, None, None) == -1
+    assert lib.l1ls_solve_fista(None, None, None, None) == -1
+    assert lib.l1ls_solve_cg_newton(None, None, None, None) == -1
+    assert lib.l1ls_fista_create(None, None, None) == -1
+    assert lib.l1ls_fista_iterate(None, 1) == -1
+    lib.l1ls_free(None)
+    lib.l1ls_fista_destroy(None)
+
+
+def test_solve_opts_defaults():
+    o = L.SolveOpts()
+    L.lib().l1ls_solve_opts_default(ctypes.byref(o))
+    assert o.rel_gap_tol == 1e-8 and o.check_every == 32 and o.precision == L.F64
+    assert o.mu == 1e-5 and o.pcg_rtol == 0.1 and o.max_backtrack == 50
