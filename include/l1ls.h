@@ -53,6 +53,14 @@ typedef enum {
     L1LS_OP_MATRIX_FREE = 1  /* Givens stages applied on the fly (MvPA/MvPAt) */
 } l1ls_operator;
 
+/* Row/column order of the stored CSR/CSC.  NATURAL: A as defined.  STAGE:
+ * rows ordered by the m-side bijection pi_m and columns by pi_n (position p
+ * holds original index pi(p)), so that every Givens stage pairs neighbours
+ * and the gathers of a row (column) fall into runs of consecutive entries.
+ * The order is internal: every entry point takes and returns vectors in
+ * the original order of A. */
+typedef enum { L1LS_LAYOUT_NATURAL = 0, L1LS_LAYOUT_STAGE = 1 } l1ls_layout;
+
 /* Storage kept by l1ls_generate_ex (bit mask). */
 #define L1LS_STORE_F32 1u    /* CSR + CSC values in FP32 (int32 indices)   */
 #define L1LS_STORE_F64 2u    /* CSR + CSC values in FP64 (same indices)     */
@@ -61,6 +69,7 @@ typedef struct {
     int32_t rounds;      /* Givens stages per side, 1 or 2 (nnz/col <= 4^rounds) */
     uint32_t storage;    /* L1LS_STORE_* mask; 0 = matrix-free only            */
     void* stream;        /* stream the build runs on                            */
+    int32_t layout;      /* l1ls_layout of the stored CSR/CSC                   */
 } l1ls_gen_opts;
 
 /* Read-only description of an instance.  Device pointers stay valid until
@@ -69,6 +78,7 @@ typedef struct {
     int64_t m, n, s, nnz;
     int32_t rounds;
     uint32_t storage;
+    int32_t layout;      /* l1ls_layout of the CSR/CSC below                    */
     double kappa, tau;
     double L;            /* lambda_max(A^T A) = sigma_1^2 (= 1)                 */
     double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2              */
@@ -83,6 +93,8 @@ typedef struct {
     const int32_t* perm_m_dev; /* m, bijection pi of the m side                 */
     const double* cs_n_dev[2]; /* per stage: n/2 pairs of (c, s), interleaved   */
     const double* cs_m_dev[2]; /* per stage: m/2 pairs of (c, s), interleaved   */
+    /* Stored A in `layout` order: row r of the CSR is original row pi_m(r),
+     * column c original column pi_n(c) (identity for NATURAL). */
     const int32_t* csr_ptr_dev;  /* m+1 */
     const int32_t* csr_col_dev;  /* nnz, sorted within each row    */
     const float* csr_val32_dev;  /* nnz */
@@ -105,8 +117,9 @@ typedef struct l1ls_instance l1ls_instance;
  * All random draws come from Philox-4x32-10 keyed by `seed`, so an instance
  * is a function of (m, n, kappa, s, tau, seed, rounds).
  * Requires m >= n >= 2, m and n even, m < 2^31, 0 <= s <= n, kappa >= 1,
- * tau > 0, 1 <= rounds <= 2.  l1ls_generate uses rounds = 1 and both
- * storages on the null stream.  The call returns after the build finished.
+ * tau > 0, 1 <= rounds <= 2.  l1ls_generate uses rounds = 1, both
+ * storages and the STAGE layout on the null stream.  The call returns after
+ * the build finished.
  */
 l1ls_status l1ls_generate(int64_t m, int64_t n, double kappa, int64_t s,
                           double tau, uint64_t seed, l1ls_instance** out);

@@ -27,14 +27,18 @@ class L1lsError(RuntimeError):
         super().__init__(f"{where}: l1ls status {status} ({_STATUS.get(status, '?')})")
 
 
+LAYOUT_NATURAL, LAYOUT_STAGE = 0, 1
+
+
 class GenOpts(ctypes.Structure):
-    _fields_ = [("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32), ("stream", ctypes.c_void_p)]
+    _fields_ = [("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32), ("stream", ctypes.c_void_p),
+                ("layout", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("s", ctypes.c_int64), ("nnz", ctypes.c_int64),
-        ("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32),
+        ("rounds", ctypes.c_int32), ("storage", ctypes.c_uint32), ("layout", ctypes.c_int32),
         ("kappa", ctypes.c_double), ("tau", ctypes.c_double), ("L", ctypes.c_double),
         ("f_star", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("b_dev", ctypes.c_void_p), ("x_star_dev", ctypes.c_void_p), ("g_dev", ctypes.c_void_p),
@@ -163,12 +167,14 @@ class Instance:
             pass
 
 
-def l1ls_generate(m, n, kappa, s, tau, seed, rounds=1, storage=STORE_F32 | STORE_F64, stream=None):
+def l1ls_generate(m, n, kappa, s, tau, seed, rounds=1, storage=STORE_F32 | STORE_F64, stream=None,
+                  layout=LAYOUT_STAGE):
     h = ctypes.c_void_p()
-    o = GenOpts(rounds, storage, _stream(stream))
+    o = GenOpts(rounds, storage, _stream(stream), layout)
     _check(lib().l1ls_generate_ex(m, n, kappa, s, tau, seed, ctypes.byref(o), ctypes.byref(h)),
            "l1ls_generate_ex")
-    return Instance(h, dict(m=m, n=n, kappa=kappa, s=s, tau=tau, seed=seed, rounds=rounds, storage=storage))
+    return Instance(h, dict(m=m, n=n, kappa=kappa, s=s, tau=tau, seed=seed, rounds=rounds, storage=storage,
+                            layout=layout))
 
 
 generate = l1ls_generate

@@ -66,6 +66,7 @@ struct l1ls_instance {
     int64_t m = 0, n = 0, s = 0, nnz = 0;
     int32_t rounds = 1;
     uint32_t storage = 0;
+    int32_t layout = 0;
     double kappa = 1, tau = 1, L = 1, fstar = 0;
     uint64_t seed = 0;
     int device = 0;
@@ -77,7 +78,17 @@ struct l1ls_instance {
     double* b = nullptr;          // m
     float* b32 = nullptr;         // m
     int32_t* support = nullptr;   // s
-    double* colnorm2 = nullptr;   // n, diag(A^T A)
+    double* colnorm2 = nullptr;   // n, diag(A^T A), original order
+    // Operator order (the order of the stored CSR/CSC): b and diag(A^T A)
+    // permuted; op_col_of[p] / op_row_of[p] give the original index at
+    // position p, op_col_pos / op_row_pos the inverse (nullptr: identity).
+    double* b_op = nullptr;
+    float* b32_op = nullptr;
+    double* colnorm2_op = nullptr;
+    const int32_t* op_col_of = nullptr;
+    const int32_t* op_col_pos = nullptr;
+    const int32_t* op_row_of = nullptr;
+    const int32_t* op_row_pos = nullptr;
     int32_t* csr_ptr = nullptr;   // m+1
     int32_t* csr_col = nullptr;
     double* csr_v64 = nullptr;
@@ -120,7 +131,7 @@ __device__ __forceinline__ T segment_sum(T v) {
 // thread 0.  Fixed order: butterfly inside each wave, then waves in order.
 template <int NS, int NSUM>
 __device__ __forceinline__ void block_reduce_stats(double (&v)[NS]) {
-    __shared__ double red[L1LS_BLOCK / L1LS_WAVE][NS];
+    __shared__ double red[1024 / L1LS_WAVE][NS];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = threadIdx.x / L1LS_WAVE;
 #pragma unroll
@@ -147,6 +158,19 @@ inline int grid_for(int64_t work_items, int items_per_block, int cap) {
     if (g < 1) g = 1;
     if (g > cap) g = cap;
     return (int)g;
+}
+
+// out[p] = in[of[p]] (gather into operator order; of == nullptr: copy).
+template <typename Tout, typename Tin>
+__global__ void k_gather_perm(const Tin* __restrict__ in, Tout* __restrict__ out, const int32_t* __restrict__ of,
+                              int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    out[p] = (Tout)in[of ? of[p] : p];
+}
+
+inline dim3 grid_1d(int64_t N) {
+    return dim3((unsigned)((N + L1LS_BLOCK - 1) / L1LS_BLOCK > 0 ? (N + L1LS_BLOCK - 1) / L1LS_BLOCK : 1));
 }
 
 // Exclusive prefix sum of int32 counts into int32 offsets (n+1 outputs).

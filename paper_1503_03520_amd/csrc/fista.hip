@@ -17,9 +17,16 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
 
 namespace {
 
-constexpr int kW_rows = 8;    // lanes per CSR row (<= 16 entries, 8 on average at 2 stages)
-constexpr int kW_cols = 16;   // lanes per CSC column (<= 16 entries, ~16 at 2 stages)
+constexpr int kW_rows = 8;    // lanes per CSR row in the plain products
+constexpr int kW_cols = 16;   // lanes per CSC column in the plain products
 constexpr int kGridCap = 2048;
+constexpr int kTileGridCap = 8192;  // workgroups of the tile kernels (4 tiles of 64 each)
+constexpr int kGapThreads = 1024;
+
+inline int tile_grid(int64_t N) {
+    const int64_t tiles = (N + kTile - 1) / kTile;
+    return grid_for(tiles, L1LS_BLOCK / L1LS_WAVE, kTileGridCap);
+}
 
 // t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, evaluated without contraction.
 inline double next_t(double t) {
@@ -180,15 +187,15 @@ const double* csc_vals<double>(const l1ls_instance* I) { return I->csc_v64; }
 template <typename T>
 const T* b_vec(const l1ls_instance* I);
 template <>
-const float* b_vec<float>(const l1ls_instance* I) { return I->b32; }
+const float* b_vec<float>(const l1ls_instance* I) { return I->b32_op; }
 template <>
-const double* b_vec<double>(const l1ls_instance* I) { return I->b; }
+const double* b_vec<double>(const l1ls_instance* I) { return I->b_op; }
 
 template <typename T>
 l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot) {
     const l1ls_instance* I = F->I;
     return timed(F, 0, [&] {
-        hipLaunchKernelGGL((k_residual<T, kW_rows>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
+        hipLaunchKernelGGL((k_residual<T>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
                            I->csr_col, csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
                            F->k1part + (size_t)slot * 3 * F->g1, F->gs);
     });
@@ -198,7 +205,7 @@ template <typename T>
 l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta) {
     const l1ls_instance* I = F->I;
     return timed(F, 1, [&] {
-        hipLaunchKernelGGL((k_transpose_prox<T, kW_cols>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
+        hipLaunchKernelGGL((k_transpose_prox<T>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
                            I->csc_ptr, I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L,
                            (T)(F->tau / F->L), I->n, F->k2part, F->gs);
     });
@@ -218,7 +225,7 @@ l1ls_status fista_iterate_t(l1ls_fista* F, int64_t iters) {
         L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1)));
         if (k % check == 0) {
             L1LS_TRY(timed(F, 2, [&] {
-                hipLaunchKernelGGL(k_gap, dim3(1), dim3(L1LS_BLOCK), 0, F->stream,
+                hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
                                    F->k1part + (size_t)(k & 1) * 3 * F->g1,
                                    F->k1part + (size_t)((k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2,
                                    F->tau, tol, k, F->gs);
@@ -280,8 +287,8 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     F->prec = opts->precision;
     F->tau = tau;
     F->L = L;
-    F->g1 = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
-    F->g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+    F->g1 = tile_grid(I->m);
+    F->g2 = tile_grid(I->n);
     const size_t es = (F->prec == L1LS_F32) ? sizeof(float) : sizeof(double);
     auto fail = [&](l1ls_status s) {
         F->arena.release();
@@ -304,16 +311,17 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     hipStream_t s = F->stream;
     // x_0 = x0 (or 0) in both slots (x_{-1} = x_0); one residual pass gives
     // r_x,0 = A x_0 - b and r_y,1 = r_x,0 (beta_0 = 0).
+    // x_0 in operator order (the stored columns are permuted by op_col_of)
     if (F->prec == L1LS_F64) {
-        if (opts->x0_dev) {
-            if (hipMemcpyAsync(x0, opts->x0_dev, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return fail(L1LS_E_HIP);
-        } else {
+        if (opts->x0_dev)
+            hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev,
+                               (double*)x0, I->op_col_of, I->n);
+        else
             hipLaunchKernelGGL(k_fill<double>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (double*)x0, 0.0, I->n);
-        }
     } else {
         if (opts->x0_dev)
-            hipLaunchKernelGGL(k_f64_to_f32, g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev, (float*)x0, I->n);
+            hipLaunchKernelGGL((k_gather_perm<float, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev,
+                               (float*)x0, I->op_col_of, I->n);
         else
             hipLaunchKernelGGL(k_fill<float>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (float*)x0, 0.0f, I->n);
     }
@@ -359,12 +367,14 @@ extern "C" l1ls_status l1ls_fista_get_x(l1ls_fista* F, double* x_out) {
     const int64_t kk = (g.conv_iter >= 0) ? g.conv_iter : F->k;
     void* src = F->x[kk & 1];
     const int64_t n = F->I->n;
-    if (F->prec == L1LS_F64) {
-        HIP_TRY(hipMemcpyAsync(x_out, src, n * sizeof(double), hipMemcpyDeviceToDevice, F->stream));
-    } else {
-        hipLaunchKernelGGL(k_f32_to_f64, g1d(n), dim3(L1LS_BLOCK), 0, F->stream, (const float*)src, x_out, n);
-        HIP_TRY(hipGetLastError());
-    }
+    // back to the original order: x[j] = x_op[op_col_pos[j]]
+    if (F->prec == L1LS_F64)
+        hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, F->stream,
+                           (const double*)src, x_out, F->I->op_col_pos, n);
+    else
+        hipLaunchKernelGGL((k_gather_perm<double, float>), g1d(n), dim3(L1LS_BLOCK), 0, F->stream,
+                           (const float*)src, x_out, F->I->op_col_pos, n);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(F->stream));
     return L1LS_OK;
 }
@@ -394,6 +404,41 @@ extern "C" void l1ls_fista_destroy(l1ls_fista* F) {
 template <typename T>
 l1ls_status apply_matrix_free(const l1ls_instance* I, int trans, const T* in, T* out, hipStream_t s);
 
+template <typename T>
+const T* csr_v(const l1ls_instance* I) { return csr_vals<T>(I); }
+
+// out = A in (trans 0) or A^T in (trans 1) with vectors in the original
+// order: permute into operator order, segmented product, permute back.
+template <typename T>
+l1ls_status apply_stored(const l1ls_instance* I, int trans, const T* in, T* out, hipStream_t s) {
+    DevArena tmp;
+    T *a = nullptr, *b = nullptr;
+    const int64_t nin = trans ? I->m : I->n, nout = trans ? I->n : I->m;
+    auto done = [&](l1ls_status st) {
+        tmp.release();
+        return st;
+    };
+    l1ls_status st;
+    if ((st = tmp.alloc(&a, nin)) != L1LS_OK) return done(st);
+    if ((st = tmp.alloc(&b, nout)) != L1LS_OK) return done(st);
+    hipLaunchKernelGGL((k_gather_perm<T, T>), g1d(nin), dim3(L1LS_BLOCK), 0, s, in, a,
+                       trans ? I->op_row_of : I->op_col_of, nin);
+    if (trans == 0) {
+        const int g = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
+        hipLaunchKernelGGL((k_spmv<T, kW_rows>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                           csr_vals<T>(I), a, b, I->m);
+    } else {
+        const int g = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+        hipLaunchKernelGGL((k_spmv<T, kW_cols>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                           csc_vals<T>(I), a, b, I->n);
+    }
+    hipLaunchKernelGGL((k_gather_perm<T, T>), g1d(nout), dim3(L1LS_BLOCK), 0, s, b, out,
+                       trans ? I->op_col_pos : I->op_row_pos, nout);
+    if (hipGetLastError() != hipSuccess) return done(L1LS_E_HIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return done(L1LS_E_HIP);
+    return done(L1LS_OK);
+}
+
 extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t op, int32_t prec,
                                   const void* in, void* out, void* stream) {
     if (!I || !in || !out || (trans != 0 && trans != 1)) return L1LS_E_ARG;
@@ -405,25 +450,8 @@ extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t
     }
     if (op != L1LS_OP_STORED) return L1LS_E_ARG;
     L1LS_TRY(check_stored(I, prec));
-    if (trans == 0) {
-        const int g = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
-        if (prec == L1LS_F64)
-            hipLaunchKernelGGL((k_spmv<double, kW_rows>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
-                               I->csr_v64, (const double*)in, (double*)out, I->m);
-        else
-            hipLaunchKernelGGL((k_spmv<float, kW_rows>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
-                               I->csr_v32, (const float*)in, (float*)out, I->m);
-    } else {
-        const int g = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
-        if (prec == L1LS_F64)
-            hipLaunchKernelGGL((k_spmv<double, kW_cols>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
-                               I->csc_v64, (const double*)in, (double*)out, I->n);
-        else
-            hipLaunchKernelGGL((k_spmv<float, kW_cols>), dim3(g), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
-                               I->csc_v32, (const float*)in, (float*)out, I->n);
-    }
-    HIP_TRY(hipGetLastError());
-    return L1LS_OK;
+    if (prec == L1LS_F64) return apply_stored<double>(I, trans, (const double*)in, (double*)out, s);
+    return apply_stored<float>(I, trans, (const float*)in, (float*)out, s);
 }
 
 // FP64 gap at x through the stored FP64 operator.  Used by the solvers too.
@@ -431,8 +459,8 @@ l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double
                      hipStream_t s) {
     L1LS_TRY(check_stored(I, L1LS_F64));
     DevArena tmp;
-    double *r = nullptr, *ry = nullptr, *p1 = nullptr, *p2 = nullptr;
-    const int g1 = grid_for(I->m * kW_rows, L1LS_BLOCK, kGridCap);
+    double *r = nullptr, *ry = nullptr, *p1 = nullptr, *p2 = nullptr, *xo = nullptr;
+    const int g1 = tile_grid(I->m);
     const int g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
     auto done = [&](l1ls_status st) {
         tmp.release();
@@ -443,10 +471,13 @@ l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double
     if ((st = tmp.alloc(&ry, I->m)) != L1LS_OK) return done(st);
     if ((st = tmp.alloc(&p1, 3 * (size_t)g1)) != L1LS_OK) return done(st);
     if ((st = tmp.alloc(&p2, 2 * (size_t)g2)) != L1LS_OK) return done(st);
-    hipLaunchKernelGGL((k_residual<double, kW_rows>), dim3(g1), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
-                       I->csr_v64, x, I->b, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr);
+    if ((st = tmp.alloc(&xo, I->n)) != L1LS_OK) return done(st);
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, x, xo, I->op_col_of,
+                       I->n);
+    hipLaunchKernelGGL((k_residual<double>), dim3(g1), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                       I->csr_v64, xo, I->b_op, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr);
     hipLaunchKernelGGL((k_colstats<double, kW_cols>), dim3(g2), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
-                       I->csc_v64, r, x, I->n, p2);
+                       I->csc_v64, r, xo, I->n, p2);
     std::vector<double> h1(3 * (size_t)g1), h2(2 * (size_t)g2);
     if (hipMemcpyAsync(h1.data(), p1, h1.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return done(L1LS_E_HIP);
     if (hipMemcpyAsync(h2.data(), p2, h2.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return done(L1LS_E_HIP);
@@ -517,7 +548,7 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
     }
     if (st == L1LS_OK && opts->max_iter % check != 0) {
         // evaluate the gap at the last iterate as well
-        hipLaunchKernelGGL(k_gap, dim3(1), dim3(L1LS_BLOCK), 0, F->stream,
+        hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
                            F->k1part + (size_t)(F->k & 1) * 3 * F->g1,
                            F->k1part + (size_t)((F->k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2, F->tau,
                            opts->rel_gap_tol, F->k, F->gs);

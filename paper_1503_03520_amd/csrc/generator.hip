@@ -144,6 +144,20 @@ __global__ void k_colnorm(SideTables Gs, int rounds, const double* __restrict__ 
     colnorm2[j] = acc;
 }
 
+// Column at operator position c (original column col_of[c]); row indices
+// mapped to operator positions row_pos[i] and sorted.
+template <int MAXE>
+__device__ __forceinline__ void op_column(SideTables Gs, SideTables Qs, int rounds, const double* sigma,
+                                          const int32_t* col_of, const int32_t* row_pos, int64_t c,
+                                          SparseVec<MAXE>& col) {
+    const int32_t j = col_of ? col_of[c] : (int32_t)c;
+    column_of_A<MAXE>(Gs, Qs, rounds, sigma, j, col);
+    if (row_pos) {
+        for (int e = 0; e < col.cnt; ++e) col.idx[e] = row_pos[col.idx[e]];
+        sort_sparse(col);
+    }
+}
+
 template <int MAXE>
 __global__ void k_csc_count(SideTables Gs, SideTables Qs, int rounds, const double* __restrict__ sigma,
                             int64_t n, int32_t* __restrict__ counts) {
@@ -156,16 +170,28 @@ __global__ void k_csc_count(SideTables Gs, SideTables Qs, int rounds, const doub
 
 template <int MAXE>
 __global__ void k_csc_fill(SideTables Gs, SideTables Qs, int rounds, const double* __restrict__ sigma,
-                           int64_t n, const int32_t* __restrict__ ptr, int32_t* __restrict__ row,
-                           double* __restrict__ val) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+                           int64_t n, const int32_t* __restrict__ col_of, const int32_t* __restrict__ row_pos,
+                           const int32_t* __restrict__ ptr, int32_t* __restrict__ row, double* __restrict__ val) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
     SparseVec<MAXE> col;
-    column_of_A<MAXE>(Gs, Qs, rounds, sigma, (int32_t)j, col);
-    const int32_t base = ptr[j];
+    op_column<MAXE>(Gs, Qs, rounds, sigma, col_of, row_pos, c, col);
+    const int32_t base = ptr[c];
     for (int e = 0; e < col.cnt; ++e) {
         row[base + e] = col.idx[e];
         val[base + e] = col.val[e];
+    }
+}
+
+template <int MAXE>
+__device__ __forceinline__ void op_row(SideTables Gs, SideTables Qs, int rounds, int64_t n, const double* sigma,
+                                       const int32_t* row_of, const int32_t* col_pos, int64_t p,
+                                       SparseVec<MAXE>& r) {
+    const int32_t i = row_of ? row_of[p] : (int32_t)p;
+    row_pattern_of_A<MAXE>(Gs, Qs, rounds, n, sigma, i, r);
+    if (col_pos) {
+        for (int e = 0; e < r.cnt; ++e) r.idx[e] = col_pos[r.idx[e]];
+        sort_sparse(r);
     }
 }
 
@@ -179,18 +205,27 @@ __global__ void k_csr_count(SideTables Gs, SideTables Qs, int rounds, const doub
     counts[i] = r.cnt;
 }
 
+// counts in operator order: cnt_op[p] = cnt[of[p]]
+__global__ void k_perm_counts(const int32_t* __restrict__ cnt, int32_t* __restrict__ out,
+                              const int32_t* __restrict__ of, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    out[p] = cnt[of ? of[p] : p];
+}
+
 // Row i gets its values from the stored columns, so CSR and CSC hold the
 // same numbers bit for bit.
 template <int MAXE>
 __global__ void k_csr_fill(SideTables Gs, SideTables Qs, int rounds, const double* __restrict__ sigma,
-                           int64_t n, int64_t m, const int32_t* __restrict__ ptr, int32_t* __restrict__ col,
-                           double* __restrict__ val, const int32_t* __restrict__ csc_ptr,
+                           int64_t n, int64_t m, const int32_t* __restrict__ row_of,
+                           const int32_t* __restrict__ col_pos, const int32_t* __restrict__ ptr,
+                           int32_t* __restrict__ col, double* __restrict__ val, const int32_t* __restrict__ csc_ptr,
                            const int32_t* __restrict__ csc_row, const double* __restrict__ csc_val,
                            int32_t* __restrict__ missing) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     SparseVec<MAXE> r;
-    row_pattern_of_A<MAXE>(Gs, Qs, rounds, n, sigma, (int32_t)i, r);
+    op_row<MAXE>(Gs, Qs, rounds, n, sigma, row_of, col_pos, i, r);
     const int32_t base = ptr[i];
     for (int e = 0; e < r.cnt; ++e) {
         const int32_t j = r.idx[e];
@@ -293,6 +328,8 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
     *out = nullptr;
     const int rounds = opts ? opts->rounds : 1;
     const uint32_t storage = opts ? opts->storage : (L1LS_STORE_F32 | L1LS_STORE_F64);
+    const int layout = opts ? opts->layout : L1LS_LAYOUT_STAGE;
+    if (layout != L1LS_LAYOUT_NATURAL && layout != L1LS_LAYOUT_STAGE) return L1LS_E_ARG;
     hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
     if (!(n >= 2 && m >= n && (m % 2) == 0 && (n % 2) == 0 && m < ((int64_t)1 << 31))) return L1LS_E_ARG;
     if (!(s >= 0 && s <= n) || !(kappa >= 1.0) || !is_finite(kappa) || !(tau > 0.0) || !is_finite(tau))
@@ -310,6 +347,7 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
     I->seed = seed;
     I->rounds = rounds;
     I->storage = storage;
+    I->layout = layout;
     I->L = 1.0;  // sigma_1 = kappa^0
     HIP_TRY(hipGetDevice(&I->device));
     DevArena tmp;
@@ -411,19 +449,47 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
     I->fstar = tau * fs[0] + 0.5 * fs[1];
     I->nnz = nnz;
 
+    // Operator order of the stored A and of the vectors that go with it.
+    if (layout == L1LS_LAYOUT_STAGE) {
+        I->op_col_of = I->side[0].perm;
+        I->op_col_pos = I->side[0].pinv;
+        I->op_row_of = I->side[1].perm;
+        I->op_row_pos = I->side[1].pinv;
+    }
+    GEN_TRY(I->arena.alloc(&I->b_op, m));
+    GEN_TRY(I->arena.alloc(&I->b32_op, m));
+    GEN_TRY(I->arena.alloc(&I->colnorm2_op, n));
+    hipLaunchKernelGGL((k_gather_perm<double, double>), grid1(m), dim3(L1LS_BLOCK), 0, stream, I->b, I->b_op,
+                       I->op_row_of, m);
+    hipLaunchKernelGGL((k_gather_perm<float, double>), grid1(m), dim3(L1LS_BLOCK), 0, stream, I->b, I->b32_op,
+                       I->op_row_of, m);
+    hipLaunchKernelGGL((k_gather_perm<double, double>), grid1(n), dim3(L1LS_BLOCK), 0, stream, I->colnorm2,
+                       I->colnorm2_op, I->op_col_of, n);
+
     if (storage) {
-        // Stored CSC (columns A e_j) and CSR (rows A^T e_i); CSR values are
-        // looked up in the columns so both hold the same numbers.
+        // Stored CSC (columns A e_j) and CSR (rows A^T e_i) in operator order;
+        // CSR values are looked up in the columns so both hold the same numbers.
+        int32_t* cnt_op = nullptr;
+        GEN_TRY(tmp.alloc(&cnt_op, m));
+        if (I->op_col_of) {
+            hipLaunchKernelGGL(k_perm_counts, grid1(n), dim3(L1LS_BLOCK), 0, stream, counts, cnt_op, I->op_col_of, n);
+            GEN_TRY(exclusive_scan_i32(cnt_op, cptr, n, stream, tmp));
+        }
         I->csc_ptr = cptr;
         double* csc_v64 = nullptr;
         GEN_TRY(I->arena.alloc(&I->csc_row, nnz));
         GEN_TRY(((storage & L1LS_STORE_F64) ? I->arena : tmp).alloc(&csc_v64, nnz));
         hipLaunchKernelGGL(k_csc_fill<16>, grid1(n), dim3(L1LS_BLOCK), 0, stream, I->side[0], I->side[1],
-                           rounds, I->sigma, n, I->csc_ptr, I->csc_row, csc_v64);
+                           rounds, I->sigma, n, I->op_col_of, I->op_row_pos, I->csc_ptr, I->csc_row, csc_v64);
         GEN_TRY(I->arena.alloc(&I->csr_ptr, m + 1));
         hipLaunchKernelGGL(k_csr_count<16>, grid1(m), dim3(L1LS_BLOCK), 0, stream, I->side[0], I->side[1],
                            rounds, I->sigma, n, m, counts);
-        GEN_TRY(exclusive_scan_i32(counts, I->csr_ptr, m, stream, tmp));
+        if (I->op_row_of) {
+            hipLaunchKernelGGL(k_perm_counts, grid1(m), dim3(L1LS_BLOCK), 0, stream, counts, cnt_op, I->op_row_of, m);
+            GEN_TRY(exclusive_scan_i32(cnt_op, I->csr_ptr, m, stream, tmp));
+        } else {
+            GEN_TRY(exclusive_scan_i32(counts, I->csr_ptr, m, stream, tmp));
+        }
         double* csr_v64 = nullptr;
         int32_t* missing = nullptr;
         GEN_TRY(tmp.alloc(&missing, 1));
@@ -431,8 +497,8 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
         GEN_TRY(I->arena.alloc(&I->csr_col, nnz));
         GEN_TRY(((storage & L1LS_STORE_F64) ? I->arena : tmp).alloc(&csr_v64, nnz));
         hipLaunchKernelGGL(k_csr_fill<16>, grid1(m), dim3(L1LS_BLOCK), 0, stream, I->side[0], I->side[1],
-                           rounds, I->sigma, n, m, I->csr_ptr, I->csr_col, csr_v64, I->csc_ptr, I->csc_row,
-                           csc_v64, missing);
+                           rounds, I->sigma, n, m, I->op_row_of, I->op_col_pos, I->csr_ptr, I->csr_col, csr_v64,
+                           I->csc_ptr, I->csc_row, csc_v64, missing);
         if (storage & L1LS_STORE_F32) {
             GEN_TRY(I->arena.alloc(&I->csc_v32, nnz));
             GEN_TRY(I->arena.alloc(&I->csr_v32, nnz));
@@ -471,6 +537,7 @@ extern "C" l1ls_status l1ls_generate(int64_t m, int64_t n, double kappa, int64_t
     o.rounds = 1;
     o.storage = L1LS_STORE_F32 | L1LS_STORE_F64;
     o.stream = nullptr;
+    o.layout = L1LS_LAYOUT_STAGE;
     return l1ls_generate_ex(m, n, kappa, s, tau, seed, &o, out);
 }
 
@@ -482,6 +549,7 @@ extern "C" l1ls_status l1ls_instance_info(const l1ls_instance* I, l1ls_info* o) 
     o->nnz = I->nnz;
     o->rounds = I->rounds;
     o->storage = I->storage;
+    o->layout = I->layout;
     o->kappa = I->kappa;
     o->tau = I->tau;
     o->L = I->L;

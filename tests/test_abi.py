@@ -55,7 +55,7 @@ def test_status_strings():
 ])
 def test_generate_rejects_invalid_arguments(m, n, kappa, s, tau, rounds):
     h = ctypes.c_void_p()
-    o = L.GenOpts(rounds, 3, None)
+    o = L.GenOpts(rounds, 3, None, 1)
     st = L.lib().l1ls_generate_ex(m, n, kappa, s, tau, 1, ctypes.byref(o), ctypes.byref(h))
     assert st == -1 and not h.value
 

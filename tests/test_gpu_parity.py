@@ -39,14 +39,26 @@ def _np(ptr, count, dtype):
 _cache = {}
 
 
-def pair(cfg):
-    if cfg not in _cache:
+def pair(cfg, layout=L.LAYOUT_STAGE):
+    key = (cfg, layout)
+    if key not in _cache:
         m, n, kappa, s, tau, seed, r = cfg
-        print(f"\n[case] generate m={m} n={n} kappa={kappa} s={s} tau={tau} seed={seed} rounds={r}", flush=True)
-        g = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r)
+        print(f"\n[case] generate m={m} n={n} kappa={kappa} s={s} tau={tau} seed={seed} rounds={r} "
+              f"layout={layout}", flush=True)
+        g = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, layout=layout)
         o = OI.Instance(m, n, kappa, s, tau, seed, rounds=r)
-        _cache[cfg] = (g, o, o.sparse_A())
-    return _cache[cfg]
+        _cache[key] = (g, o, o.sparse_A())
+    return _cache[key]
+
+
+def operator_order(o, A, layout):
+    """The oracle's A with rows/columns in the library's storage order."""
+    if layout == L.LAYOUT_NATURAL:
+        B = A.tocsr()
+    else:
+        B = A.tocsr()[o.perm_m, :][:, o.perm_n].tocsr()
+    B.sort_indices()
+    return B
 
 
 def ulp_close(a, b, ulps):
@@ -57,20 +69,28 @@ def ulp_close(a, b, ulps):
 
 
 @pytest.mark.parametrize("cfg", CASES)
-def test_generator_integers_bit_exact(cfg):
-    g, o, A = pair(cfg)
+@pytest.mark.parametrize("layout", [L.LAYOUT_NATURAL, L.LAYOUT_STAGE])
+def test_generator_integers_bit_exact(cfg, layout):
+    g, o, A = pair(cfg, layout)
     inf = g.info()
     m, n = o.m, o.n
+    assert inf.layout == layout
     assert _np(inf.perm_n_dev, n, np.int32).tolist() == o.perm_n.tolist()
     assert _np(inf.perm_m_dev, m, np.int32).tolist() == o.perm_m.tolist()
     assert _np(inf.support_dev, o.s, np.int32).tolist() == o.support.tolist()
     assert inf.nnz == A.nnz
-    Ac = A.tocsc()
-    Ac.sort_indices()
-    assert np.array_equal(_np(inf.csr_ptr_dev, m + 1, np.int32), A.indptr)
-    assert np.array_equal(_np(inf.csr_col_dev, A.nnz, np.int32), A.indices)
-    assert np.array_equal(_np(inf.csc_ptr_dev, n + 1, np.int32), Ac.indptr)
-    assert np.array_equal(_np(inf.csc_row_dev, A.nnz, np.int32), Ac.indices)
+    B = operator_order(o, A, layout)
+    Bc = B.tocsc()
+    Bc.sort_indices()
+    assert np.array_equal(_np(inf.csr_ptr_dev, m + 1, np.int32), B.indptr)
+    assert np.array_equal(_np(inf.csr_col_dev, A.nnz, np.int32), B.indices)
+    assert np.array_equal(_np(inf.csc_ptr_dev, n + 1, np.int32), Bc.indptr)
+    assert np.array_equal(_np(inf.csc_row_dev, A.nnz, np.int32), Bc.indices)
+    v64 = _np(inf.csr_val64_dev, A.nnz, np.float64)
+    assert np.abs(v64 - B.data).max() <= 1e-14 * max(1.0, np.abs(B.data).max())
+    assert np.abs(_np(inf.csc_val64_dev, A.nnz, np.float64) - Bc.data).max() <= 1e-14
+    v32 = _np(inf.csr_val32_dev, A.nnz, np.float32)
+    assert np.array_equal(v32, v64.astype(np.float32))
 
 
 @pytest.mark.parametrize("cfg", CASES)
@@ -98,13 +118,6 @@ def test_generator_floats(cfg):
         got = _np(dev, m, np.float64)
         scale = max(1.0, np.abs(ref).max())
         assert np.abs(got - ref).max() <= 1e-13 * scale, name
-    v64 = _np(inf.csr_val64_dev, A.nnz, np.float64)
-    assert np.abs(v64 - A.data).max() <= 1e-14 * max(1.0, np.abs(A.data).max())
-    v32 = _np(inf.csr_val32_dev, A.nnz, np.float32)
-    assert np.array_equal(v32, v64.astype(np.float32))
-    Ac = A.tocsc()
-    Ac.sort_indices()
-    assert np.abs(_np(inf.csc_val64_dev, A.nnz, np.float64) - Ac.data).max() <= 1e-14
     assert math.isclose(inf.f_star, o.fstar, rel_tol=1e-12)
     assert inf.L == 1.0
 
@@ -114,9 +127,10 @@ def _dev(v, dtype=torch.float64):
 
 
 @pytest.mark.parametrize("cfg", CASES)
-@pytest.mark.parametrize("op", [L.OP_STORED, L.OP_MATRIX_FREE])
-def test_operator_products(cfg, op):
-    g, o, A = pair(cfg)
+@pytest.mark.parametrize("op,layout", [(L.OP_STORED, L.LAYOUT_NATURAL), (L.OP_STORED, L.LAYOUT_STAGE),
+                                       (L.OP_MATRIX_FREE, L.LAYOUT_STAGE)])
+def test_operator_products(cfg, op, layout):
+    g, o, A = pair(cfg, layout)
     x = SI.normal_vector(o.n, 101)
     y = SI.normal_vector(o.m, 102)
     ax = o.matvec(x)
@@ -151,9 +165,10 @@ def test_objective_gap(cfg):
 
 @pytest.mark.parametrize("cfg", CASES)
 @pytest.mark.parametrize("iters", [1, 2, 10, 100])
-def test_fista_trajectory_fp64(cfg, iters):
+@pytest.mark.parametrize("layout", [L.LAYOUT_NATURAL, L.LAYOUT_STAGE])
+def test_fista_trajectory_fp64(cfg, iters, layout):
     # FP64 x_k of the fused kernels against the oracle's x_k, same L.
-    g, o, A = pair(cfg)
+    g, o, A = pair(cfg, layout)
     x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=1, precision=L.F64)
     ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
     scale = max(1.0, np.abs(ref).max())
