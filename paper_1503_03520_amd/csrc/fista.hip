@@ -20,12 +20,12 @@ namespace {
 constexpr int kW_rows = 8;    // lanes per CSR row in the plain products
 constexpr int kW_cols = 16;   // lanes per CSC column in the plain products
 constexpr int kGridCap = 2048;
-constexpr int kTileGridCap = 8192;  // workgroups of the tile kernels (4 tiles of 64 each)
 constexpr int kGapThreads = 1024;
 
+// One wave per tile of 64 rows (columns), four waves per workgroup.
 inline int tile_grid(int64_t N) {
     const int64_t tiles = (N + kTile - 1) / kTile;
-    return grid_for(tiles, L1LS_BLOCK / L1LS_WAVE, kTileGridCap);
+    return (int)std::max<int64_t>(1, (tiles + 3) / 4);
 }
 
 // t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, evaluated without contraction.
@@ -121,6 +121,7 @@ struct l1ls_fista {
     int64_t k = 0;             // iterations enqueued
     double t_k = 1.0;          // t_k for the next iteration k+1 (t_1 = 1)
     double beta_prev = 0.0;    // beta_{k-1}
+    int64_t stats_until = -1;  // iteration whose statistics a final gap evaluation will read
     // kernel timing
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
@@ -192,22 +193,22 @@ template <>
 const double* b_vec<double>(const l1ls_instance* I) { return I->b_op; }
 
 template <typename T>
-l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot) {
+l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
     const l1ls_instance* I = F->I;
     return timed(F, 0, [&] {
         hipLaunchKernelGGL((k_residual<T>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
                            I->csr_col, csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
-                           F->k1part + (size_t)slot * 3 * F->g1, F->gs);
+                           F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
     });
 }
 
 template <typename T>
-l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta) {
+l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta, int stats) {
     const l1ls_instance* I = F->I;
     return timed(F, 1, [&] {
         hipLaunchKernelGGL((k_transpose_prox<T>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
                            I->csc_ptr, I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L,
-                           (T)(F->tau / F->L), I->n, F->k2part, F->gs);
+                           (T)(F->tau / F->L), I->n, F->k2part, F->gs, stats);
     });
 }
 
@@ -221,8 +222,14 @@ l1ls_status fista_iterate_t(l1ls_fista* F, int64_t iters) {
         const double beta_k = (F->t_k - 1.0) / t_next;
         T* xcur = (T*)F->x[(k - 1) & 1];
         T* xslot = (T*)F->x[k & 1];  // holds x_{k-2}, receives x_k
-        L1LS_TRY(launch_transpose<T>(F, xcur, xslot, F->beta_prev));
-        L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1)));
+        // FP64 statistics only where a gap evaluation reads them: the
+        // transpose and residual passes of iteration k when k is a check
+        // iteration, and the r_y statistics of the pass just before one.
+        const bool last = (k == F->stats_until);
+        const int st2 = (k % check == 0 || last) ? 1 : 0;
+        const int st1 = (k % check == 0 || (k + 1) % check == 0 || last || k + 1 == F->stats_until) ? 1 : 0;
+        L1LS_TRY(launch_transpose<T>(F, xcur, xslot, F->beta_prev, st2));
+        L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1), st1));
         if (k % check == 0) {
             L1LS_TRY(timed(F, 2, [&] {
                 hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
@@ -328,9 +335,9 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if (hipMemcpyAsync(x1, x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(L1LS_E_HIP);
     hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
     if (F->prec == L1LS_F64)
-        st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0);
+        st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0, 1);
     else
-        st = launch_residual<float>(F, (const float*)x0, 0.0, 1, 0);
+        st = launch_residual<float>(F, (const float*)x0, 0.0, 1, 0, 1);
     if (st != L1LS_OK) return fail(st);
     if (hipGetLastError() != hipSuccess) return fail(L1LS_E_HIP);
     *out = F;
@@ -475,7 +482,7 @@ l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double
     hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, x, xo, I->op_col_of,
                        I->n);
     hipLaunchKernelGGL((k_residual<double>), dim3(g1), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
-                       I->csr_v64, xo, I->b_op, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr);
+                       I->csr_v64, xo, I->b_op, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr, 1);
     hipLaunchKernelGGL((k_colstats<double, kW_cols>), dim3(g2), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
                        I->csc_v64, r, xo, I->n, p2);
     std::vector<double> h1(3 * (size_t)g1), h2(2 * (size_t)g2);
@@ -540,6 +547,7 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
     const int check = std::max(1, opts->check_every);
     // Enqueue several gap blocks ahead; passes after convergence are no-ops.
     const int64_t ahead = (int64_t)check * 4;
+    F->stats_until = opts->max_iter;
     while (F->k < opts->max_iter) {
         const int64_t step = std::min<int64_t>(ahead, opts->max_iter - F->k);
         if ((st = l1ls_fista_iterate(F, step)) != L1LS_OK) break;

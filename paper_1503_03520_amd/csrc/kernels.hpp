@@ -37,133 +37,142 @@ __device__ __forceinline__ T ld_stream(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-// Products val[k] * vec[idx[k]] of the entries [beg, end) of one wave's tile
-// (at most kTile * kMaxNnz) into the wave's LDS slice.  All index and value
-// loads are issued before the gathers, and all gathers before the stores,
-// so a wave keeps up to 3 x 16 independent loads in flight.
 template <typename T>
-__device__ __forceinline__ void tile_products(const int32_t* __restrict__ idx, const T* __restrict__ val,
-                                              const T* __restrict__ vec, int32_t beg, int32_t end,
-                                              T* __restrict__ lds, int lane) {
-    int32_t c[kMaxNnz];
-    T v[kMaxNnz];
-    T g[kMaxNnz];
-#pragma unroll
-    for (int q = 0; q < kMaxNnz; ++q) {
-        const int32_t k = beg + q * kTile + lane;
-        c[q] = (k < end) ? ld_stream(idx + k) : -1;
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxNnz; ++q) {
-        const int32_t k = beg + q * kTile + lane;
-        v[q] = (k < end) ? ld_stream(val + k) : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxNnz; ++q) g[q] = (c[q] >= 0) ? vec[c[q]] : T(0);
-#pragma unroll
-    for (int q = 0; q < kMaxNnz; ++q)
-        if (c[q] >= 0) lds[q * kTile + lane] = v[q] * g[q];
+__device__ __forceinline__ void st_stream(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
 }
 
-// Residual pass over one tile of 64 rows per wave.
+// Element `i` of a device array addressed as base + 32-bit byte offset, so
+// that the load takes its base from scalar registers (one VGPR per address).
+// Valid for arrays below 4 GiB.
+template <typename T>
+__device__ __forceinline__ T ld_off32(const T* __restrict__ base, int32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
+// Products val[k] * vec[idx[k]] of the entries [beg, beg + cnt) of one wave's
+// tile (cnt <= kTile * kMaxNnz) into the wave's LDS slice.  The first
+// NQ * 64 entries are handled without branches: lanes past the end load the
+// last entry again (in bounds) and store a zero product, so the NQ index
+// loads, NQ value loads and NQ gathers of a lane are all in flight together.
+// The tile's base pointers are wave-uniform (scalar registers); per-lane
+// offsets are 32-bit.  Entries beyond NQ * 64 go through a tail loop.
+template <typename T, int NQ>
+__device__ __forceinline__ void tile_products(const int32_t* __restrict__ idx, const T* __restrict__ val,
+                                              const T* __restrict__ vec, int32_t beg, int32_t cnt,
+                                              T* __restrict__ lds, int lane) {
+    if (cnt <= 0) return;  // wave-uniform
+    const int32_t* __restrict__ ib = idx + beg;
+    const T* __restrict__ vb = val + beg;
+    const int32_t last = cnt - 1;
+    int32_t c[NQ];
+    T v[NQ];
+    T g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[q] = __builtin_nontemporal_load(ib + min(q * kTile + lane, last));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = __builtin_nontemporal_load(vb + min(q * kTile + lane, last));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) g[q] = ld_off32(vec, c[q]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q * kTile + lane] = (q * kTile + lane <= last) ? v[q] * g[q] : T(0);
+    for (int32_t k = NQ * kTile + lane; k <= last; k += kTile) lds[k] = vb[k] * ld_off32(vec, ib[k]);
+}
+
+// Residual pass: one tile of 64 rows per wave, one wave-tile per launch slot.
 // part[3*block + {0,1,2}] = sum r_x^2, sum r_y^2, sum b r_y (FP64).
 // init = 1: r_y = r_x (first pass, beta_0 = 0, r_x,prev undefined).
 template <typename T>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_residual(
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ col, const T* __restrict__ val,
     const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ rx, T* __restrict__ ry, T beta,
-    int64_t m, int init, double* __restrict__ part, const GapState* __restrict__ gs) {
-    if (gs && gs->done) return;
+    int64_t m, int init, double* __restrict__ part, const GapState* __restrict__ gs, int stats) {
+    // Once the gap test has passed, the pass changes nothing.  The flag is
+    // read together with the first loads and only guards the stores, so it
+    // adds no round trip to a wave's critical path.
+    const int32_t done = gs ? __builtin_nontemporal_load(&gs->done) : 0;
     __shared__ T lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = threadIdx.x / L1LS_WAVE;
-    double v[3] = {0.0, 0.0, 0.0};
-    const int64_t ntiles = (m + kTile - 1) / kTile;
-    const int64_t wstride = (int64_t)gridDim.x * (L1LS_BLOCK / L1LS_WAVE);
-    // uniform trip count across the block: every wave reaches the barriers
-    const int64_t first = (int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE);
-    for (int64_t tb = first; tb < ntiles; tb += wstride) {
-        const int64_t tile = tb + wid;
-        const int64_t row0 = tile * kTile;
-        const int64_t i = row0 + lane;
-        const bool live = i < m;
-        int32_t pb = 0, pe = 0;
-        if (live) {
-            pb = ptr[i];
-            pe = ptr[i + 1];
-        }
-        const int64_t last = (row0 + kTile <= m) ? kTile - 1 : (m > row0 ? m - row0 - 1 : 0);
-        const int32_t beg = __shfl(pb, 0, L1LS_WAVE);
-        const int32_t end = __shfl(pe, (int)last, L1LS_WAVE);
-        if (row0 < m) tile_products<T>(col, val, x, beg, end, lds[wid], lane);
-        __syncthreads();
-        if (live) {
-            T acc = T(0);
-            for (int32_t k = pb; k < pe; ++k) acc += lds[wid][k - beg];
-            const T bi = b[i];
-            const T r = acc - bi;
-            const T yv = init ? r : (T(1) + beta) * r - beta * rx[i];
-            rx[i] = r;
-            ry[i] = yv;
-            v[0] += (double)r * (double)r;
-            v[1] += (double)yv * (double)yv;
-            v[2] += (double)bi * (double)yv;
-        }
-        __syncthreads();
+    const int64_t row0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t i = row0 + lane;
+    const bool live = i < m;
+    int32_t pb = 0, pe = 0;
+    T bi = T(0), rprev = T(0);
+    if (live) {
+        pb = ptr[i];
+        pe = ptr[i + 1];
+        // epilogue operands do not depend on the products: load them now
+        bi = __builtin_nontemporal_load(b + i);
+        if (!init) rprev = __builtin_nontemporal_load(rx + i);
     }
+    const int lastlane = (row0 + kTile <= m) ? kTile - 1 : (m > row0 ? (int)(m - row0 - 1) : 0);
+    const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+    const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+    if (row0 < m) tile_products<T, 10>(col, val, x, beg, end - beg, lds[wid], lane);
+    __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+    if (live && !done) {
+        T acc = T(0);
+        for (int32_t k = pb - beg; k < pe - beg; ++k) acc += lds[wid][k];
+        const T r = acc - bi;
+        const T yv = init ? r : (T(1) + beta) * r - beta * rprev;
+        st_stream(rx + i, r);
+        st_stream(ry + i, yv);
+        v[0] = (double)r * (double)r;
+        v[1] = (double)yv * (double)yv;
+        v[2] = (double)bi * (double)yv;
+    }
+    if (!stats) return;  // launch-uniform: the gap test does not read this pass
     block_reduce_stats<3, 3>(v);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !done) {
         part[3 * blockIdx.x + 0] = v[0];
         part[3 * blockIdx.x + 1] = v[1];
         part[3 * blockIdx.x + 2] = v[2];
     }
 }
 
-// Transpose pass with the prox step over one tile of 64 columns per wave.
+// Transpose pass with the prox step: one tile of 64 columns per wave.
 // xc = x_{k-1}; xp = x_{k-2} on entry and x_k on exit (same slot).
 // part[2*block + {0,1}] = max |g|, sum |x_k|.
 template <typename T>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ row, const T* __restrict__ val,
     const T* __restrict__ ry, const T* __restrict__ xc, T* __restrict__ xp, T beta, T L, T thr,
-    int64_t n, double* __restrict__ part, const GapState* __restrict__ gs) {
-    if (gs && gs->done) return;
+    int64_t n, double* __restrict__ part, const GapState* __restrict__ gs, int stats) {
+    const int32_t done = gs ? __builtin_nontemporal_load(&gs->done) : 0;  // guards the stores only
     __shared__ T lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = threadIdx.x / L1LS_WAVE;
-    double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
-    const int64_t ntiles = (n + kTile - 1) / kTile;
-    const int64_t wstride = (int64_t)gridDim.x * (L1LS_BLOCK / L1LS_WAVE);
-    const int64_t first = (int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE);
-    for (int64_t tb = first; tb < ntiles; tb += wstride) {
-        const int64_t tile = tb + wid;
-        const int64_t col0 = tile * kTile;
-        const int64_t j = col0 + lane;
-        const bool live = j < n;
-        int32_t pb = 0, pe = 0;
-        if (live) {
-            pb = ptr[j];
-            pe = ptr[j + 1];
-        }
-        const int64_t last = (col0 + kTile <= n) ? kTile - 1 : (n > col0 ? n - col0 - 1 : 0);
-        const int32_t beg = __shfl(pb, 0, L1LS_WAVE);
-        const int32_t end = __shfl(pe, (int)last, L1LS_WAVE);
-        if (col0 < n) tile_products<T>(row, val, ry, beg, end, lds[wid], lane);
-        __syncthreads();
-        if (live) {
-            T acc = T(0);
-            for (int32_t k = pb; k < pe; ++k) acc += lds[wid][k - beg];
-            const T xcur = xc[j];
-            const T y = xcur + beta * (xcur - xp[j]);
-            const T xn = soft_threshold<T>(y - acc / L, thr);
-            xp[j] = xn;
-            v[0] += fabs((double)xn);
-            v[1] = fmax(v[1], fabs((double)acc));
-        }
-        __syncthreads();
+    const int64_t col0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t j = col0 + lane;
+    const bool live = j < n;
+    int32_t pb = 0, pe = 0;
+    T xcur = T(0), xprev = T(0);
+    if (live) {
+        pb = ptr[j];
+        pe = ptr[j + 1];
+        xcur = __builtin_nontemporal_load(xc + j);
+        xprev = __builtin_nontemporal_load(xp + j);
     }
+    const int lastlane = (col0 + kTile <= n) ? kTile - 1 : (n > col0 ? (int)(n - col0 - 1) : 0);
+    const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+    const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+    if (col0 < n) tile_products<T, 16>(row, val, ry, beg, end - beg, lds[wid], lane);
+    __syncthreads();
+    double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
+    if (live && !done) {
+        T acc = T(0);
+        for (int32_t k = pb - beg; k < pe - beg; ++k) acc += lds[wid][k];
+        const T y = xcur + beta * (xcur - xprev);
+        const T xn = soft_threshold<T>(y - acc / L, thr);
+        st_stream(xp + j, xn);
+        v[0] = fabs((double)xn);
+        v[1] = fabs((double)acc);
+    }
+    if (!stats) return;  // launch-uniform
     block_reduce_stats<2, 1>(v);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !done) {
         part[2 * blockIdx.x + 0] = v[1];
         part[2 * blockIdx.x + 1] = v[0];
     }
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(1024) void k_gap(
         if (!finite) {
             gs->nonfinite = 1;
             gs->done = 1;
-        } else if (gap <= tol) {
+        } else if (tol > 0.0 && gap <= tol) {
             gs->conv_iter = iter;
             gs->done = 1;
         }

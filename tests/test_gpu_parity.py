@@ -178,14 +178,17 @@ def test_fista_trajectory_fp64(cfg, iters, layout):
 
 @pytest.mark.parametrize("cfg", CASES[:2])
 def test_fista_trajectory_fp32(cfg):
-    # FP32 bulk: each iteration is a 1-Lipschitz-in-z prox of an FP32 gradient
-    # step; relative error per step ~ 1e-7 * ||A^T r|| / L; 50 steps.
+    # FP32 bulk against the FP64 oracle.  The dominant rounding is that of
+    # r = A x - b, whose entries start at the size of b: each step perturbs the
+    # gradient by about eps32 * ||b||_inf (unit column norms, L = 1), and the
+    # prox map is 1-Lipschitz; allowing linear growth over k steps gives
+    # |x_k - x_k^oracle| <= k * eps32 * ||b||_inf.
     g, o, A = pair(cfg)
     iters = 50
     x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=5, precision=L.F32)
     ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
-    grad_scale = np.abs(A.T @ o.b).max()
-    assert np.abs(x.cpu().numpy() - ref).max() <= 2e-5 * grad_scale
+    bound = iters * np.finfo(np.float32).eps * np.abs(o.b).max()
+    assert np.abs(x.cpu().numpy() - ref).max() <= bound
 
 
 @pytest.mark.parametrize("cfg", CASES)
