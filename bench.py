@@ -22,6 +22,89 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "fista_stored_f32_n2p20.txt")
+KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp"]
+
+
+def kernel_source_hash():
+    """Hash of the sources the timed kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1503_03520_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_profile_summary(path=PROFILE_SUMMARY):
+    """key: value lines of a committed rocprofv3 summary (or None)."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def write_profile_summary(args):
+    """Summarise rocprofv3 CSV output (kernel trace + FETCH_SIZE / WRITE_SIZE runs
+    of this script, and the same counters for a plain 1 GiB copy) into a text file."""
+    import csv
+    import statistics
+
+    def kernel_rows(d, kind):
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith(kind):
+                    return list(csv.DictReader(open(os.path.join(root, f))))
+        raise SystemExit(f"no *{kind} under {d}")
+
+    names = {"residual": "k_residual<float>", "transpose_prox": "k_transpose_prox<float>", "gap": "k_gap"}
+    stats = kernel_rows(args.kt, "kernel_stats.csv")
+    dur = {}
+    for key, pat in names.items():
+        for r in stats:
+            if pat in r["Name"]:
+                dur[key] = (float(r["AverageNs"]), int(r["Calls"]))
+
+    def counter(d, cname, pat):
+        vals = [float(r["Counter_Value"]) for r in kernel_rows(d, "counter_collection.csv")
+                if pat in r["Kernel_Name"] and r["Counter_Name"] == cname]
+        return statistics.median(vals), len(vals)
+
+    copy_f, _ = counter(args.copyf, "FETCH_SIZE", "copyBuffer")
+    copy_w, _ = counter(args.copyw, "WRITE_SIZE", "copyBuffer")
+    gib_kib = float(1 << 20)            # the copy moves 1 GiB = 2^20 KiB each way
+    f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
+    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC, FP32 bulk, n=2^20, m=2^21, 2 stages",
+             f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
+             f"python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline",
+             f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
+             f"python3 bench.py --steps 40 --warmup 4 --no-cpu-baseline",
+             f"# copy scale:   rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) ... -- python3 bench.py --copy-calibration",
+             f"# summary:      python3 bench.py --profile-summary --kt ... --fetch ... --write ... --copyf ... --copyw ...",
+             f"kernel_source_hash: {kernel_source_hash()}",
+             f"copy_fetch_kib_per_gib: {copy_f:.1f}",
+             f"copy_write_kib_per_gib: {copy_w:.1f}",
+             f"fetch_scale: {f_scale:.4f}",
+             f"write_scale: {w_scale:.4f}"]
+    for key, pat in names.items():
+        if key in dur:
+            lines.append(f"{key}_avg_ns: {dur[key][0]:.0f}")
+            lines.append(f"{key}_calls: {dur[key][1]}")
+        if key == "gap":
+            continue
+        fk, nf = counter(args.fetch, "FETCH_SIZE", pat)
+        wk, nw = counter(args.write, "WRITE_SIZE", pat)
+        lines.append(f"{key}_fetch_kib_median: {fk:.1f}")
+        lines.append(f"{key}_write_kib_median: {wk:.1f}")
+        lines.append(f"{key}_traffic_bytes: {(fk * f_scale + wk * w_scale) * 1024:.0f}")
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def algorithmic_bytes(m, n, nnz, es=4, ie=4):
@@ -73,7 +156,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (torch copy_) five times, to scale HBM counters")
+    ap.add_argument("--profile-summary", action="store_true",
+                    help="summarise rocprofv3 CSV directories (--kt, --fetch, --write, --copyf, --copyw) into --out")
+    for d in ("kt", "fetch", "write", "copyf", "copyw"):
+        ap.add_argument(f"--{d}")
+    ap.add_argument("--out", default=PROFILE_SUMMARY)
     args = ap.parse_args()
+    if args.profile_summary:
+        write_profile_summary(args)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -141,6 +232,14 @@ def main():
     achieved = dom_bytes / (avg[dominant] * 1e-3) / 1e9
     pair_gbs = (k1_bytes + k2_bytes) / ((avg[0] + avg[1]) * 1e-3) / 1e9
 
+    # HBM traffic per launch from the committed counter summary, when it was
+    # taken on the kernels built from the current sources
+    traffic = None
+    summ = read_profile_summary()
+    key = ("residual", "transpose_prox")[dominant]
+    if summ and summ.get("kernel_source_hash") == kernel_source_hash() and f"{key}_traffic_bytes" in summ:
+        traffic = float(summ[f"{key}_traffic_bytes"])
+
     # FP64 certificate of the final iterate (outside the timed region)
     P, D, gap = L.l1ls_objective_gap(inst, tau, plain["x"])
 
@@ -161,7 +260,7 @@ def main():
                    "n": n, "m": m, "kappa": kappa, "givens_stages": rounds, "s": s, "tau": tau,
                    "nnz": nnz, "check_every": args.check_every},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("k_residual (CSR A x - b + momentum residual)",
                                 "k_transpose_prox (CSC A^T r + prox)")[dominant],
                      "algorithmic_bytes_per_launch": dom_bytes},

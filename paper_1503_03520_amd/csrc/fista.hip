@@ -139,7 +139,9 @@ hipEvent_t take_event(l1ls_fista* F) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing events without the system-scope release: device-scope ordering
+    // is enough and the fence would stretch the kernel it brackets
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
