@@ -13,7 +13,7 @@ using namespace l1ls;
 template <typename T>
 l1ls_status apply_side(const SideTables& tab, int rounds, bool transpose, T* v, T* scratch, hipStream_t stream);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
-                        int64_t* pcg_iters_out);
+                        int64_t* pcg_iters_out, double support_tol);
 
 namespace {
 
@@ -574,7 +574,7 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
     if (st != L1LS_OK) return st;
     int prounds = 0;
     int64_t pcg = 0;
-    if (opts->polish) L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &pcg));
+    if (opts->polish) L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &pcg, 0.0));
     // Final certificate in FP64 with the FP64 operator when it is stored.
     if (I->csr_v64) {
         L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));

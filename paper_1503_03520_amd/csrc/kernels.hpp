@@ -184,7 +184,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
 //   D = -0.5 theta^2 ||r_y,k||^2 - theta b^T r_y,k,
 //   gap = (P - D) / |P|.
 // One workgroup; fixed-order sums.
-__global__ __launch_bounds__(1024) void k_gap(
+static __global__ __launch_bounds__(1024) void k_gap(
     const double* __restrict__ k1_cur, const double* __restrict__ k1_prev, int g1,
     const double* __restrict__ k2, int g2, double tau, double tol, int64_t iter, GapState* gs) {
     if (gs->done) return;

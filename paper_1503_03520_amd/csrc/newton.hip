@@ -1,15 +1,593 @@
-// Second-order path and FP64 polish (placeholders until the PCG kernels land).
-#include "common.hpp"
+// Second-order path and FP64 polish, on the stored FP64 operator in
+// operator order.
+//
+// CG-Newton (section 2: pseudo-Huber function (7), smoothed problem (8),
+// Newton model (9); section 8.1 item pdNCG and section 8.3 parameters):
+// the Newton direction solves grad^2 f_mu(x) d = -grad f_mu(x) by
+// preconditioned CG with the inverse Hessian diagonal as preconditioner,
+// stopped at relative residual pcg_rtol; an Armijo backtracking line search
+// of at most max_backtrack halvings sets the step.
+//
+// Polish: the reduced problem (13) of section 3.2 on the support S and signs
+// of a given x, A_S^T A_S x_S = A_S^T b - tau sign_S, by preconditioned CG
+// from x_S, followed by the optimality check of problem (1) (drop sign
+// violators, add coordinates with |A_j^T (A x - b)| > tau), repeated.
+//
+// Both use one PCG whose Hessian-vector product is a CSR pass (t = A p) and
+// a CSC pass with the epilogue Hp = mask (A^T t + d p) and the partial sums
+// of p^T Hp; alpha and beta are formed on the device.
+#include <chrono>
+#include <cmath>
+#include <cstring>
 
-l1ls_status polish_fp64(const l1ls_instance*, double, double*, hipStream_t, int* r, int64_t* p) {
-    *r = 0;
-    *p = 0;
-    return L1LS_E_UNSUPPORTED;
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace l1ls;
+
+l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
+                     hipStream_t s);
+l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out, hipStream_t s);
+
+namespace {
+
+inline dim3 g1d(int64_t N) { return dim3((unsigned)std::max<int64_t>(1, (N + L1LS_BLOCK - 1) / L1LS_BLOCK)); }
+inline int tgrid(int64_t N) { return (int)std::max<int64_t>(1, ((N + kTile - 1) / kTile + 3) / 4); }
+constexpr int kRedBlocks = 512;   // grid of the vector kernels with partial sums
+
+struct CgScalars {
+    double rz, pHp, alpha, beta, rr, stop2;
+    int32_t done, pad;
+};
+
+// out = A in (CSR) or A^T in (CSC): one tile of 64 rows per wave.
+__global__ __launch_bounds__(L1LS_BLOCK) void k_tile_spmv(const int32_t* __restrict__ ptr,
+                                                          const int32_t* __restrict__ idx,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ in, double* __restrict__ out,
+                                                          int64_t rows) {
+    __shared__ double lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
+    const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
+    const int64_t row0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t i = row0 + lane;
+    int32_t pb = 0, pe = 0;
+    if (i < rows) {
+        pb = ptr[i];
+        pe = ptr[i + 1];
+    }
+    const int lastlane = (row0 + kTile <= rows) ? kTile - 1 : (rows > row0 ? (int)(rows - row0 - 1) : 0);
+    const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+    const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+    if (row0 < rows) tile_products<double, 16>(idx, val, in, beg, end - beg, lds[wid], lane);
+    __syncthreads();
+    if (i < rows) {
+        double acc = 0.0;
+        for (int32_t k = pb - beg; k < pe - beg; ++k) acc += lds[wid][k];
+        out[i] = acc;
+    }
 }
 
-extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_solve_opts* o, double* x,
+// Hp = mask (A^T t + d p) over the CSC; part[block] = sum p Hp.
+__global__ __launch_bounds__(L1LS_BLOCK) void k_hess(const int32_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ row,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ t, const double* __restrict__ p,
+                                                     const double* __restrict__ d, const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ hp, int64_t n, double* __restrict__ part,
+                                                     const CgScalars* __restrict__ cs) {
+    if (cs->done) return;
+    __shared__ double lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
+    const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
+    const int64_t col0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t j = col0 + lane;
+    int32_t pb = 0, pe = 0;
+    if (j < n) {
+        pb = ptr[j];
+        pe = ptr[j + 1];
+    }
+    const int lastlane = (col0 + kTile <= n) ? kTile - 1 : (n > col0 ? (int)(n - col0 - 1) : 0);
+    const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+    const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+    if (col0 < n) tile_products<double, 16>(row, val, t, beg, end - beg, lds[wid], lane);
+    __syncthreads();
+    double v[1] = {0.0};
+    if (j < n) {
+        double acc = 0.0;
+        for (int32_t k = pb - beg; k < pe - beg; ++k) acc += lds[wid][k];
+        const double pj = p[j];
+        double h = acc + (d ? d[j] * pj : 0.0);
+        if (mask && !mask[j]) h = 0.0;
+        hp[j] = h;
+        v[0] = pj * h;
+    }
+    block_reduce_stats<1, 1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// alpha = rz / p^T Hp  (one workgroup, fixed-order sum of the partials)
+__global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ part, int np, CgScalars* cs) {
+    if (cs->done) return;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < np; b += blockDim.x) v[0] += part[b];
+    block_reduce_stats<1, 1>(v);
+    if (threadIdx.x == 0) {
+        cs->pHp = v[0];
+        cs->alpha = (v[0] > 0.0) ? cs->rz / v[0] : 0.0;
+        if (!(v[0] > 0.0)) cs->done = 1;  // no descent left (H p = 0) or breakdown
+    }
+}
+
+// x += alpha p; r -= alpha Hp; z = minv r (masked); part = (r z, r r)
+__global__ __launch_bounds__(L1LS_BLOCK) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                          double* __restrict__ z, const double* __restrict__ p,
+                                                          const double* __restrict__ hp,
+                                                          const double* __restrict__ minv,
+                                                          const uint8_t* __restrict__ mask, int64_t n,
+                                                          double* __restrict__ part, const CgScalars* __restrict__ cs) {
+    if (cs->done) return;
+    const double a = cs->alpha;
+    double v[2] = {0.0, 0.0};
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        x[j] += a * p[j];
+        const double rj = r[j] - a * hp[j];
+        r[j] = rj;
+        const double zj = (mask && !mask[j]) ? 0.0 : minv[j] * rj;
+        z[j] = zj;
+        v[0] += rj * zj;
+        v[1] += rj * rj;
+    }
+    block_reduce_stats<2, 2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// beta = rz_new / rz; stop when ||r||^2 <= stop2
+__global__ __launch_bounds__(1024) void k_cg_beta(const double* __restrict__ part, int np, CgScalars* cs,
+                                                  int32_t* __restrict__ iters) {
+    if (cs->done) return;
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
+        v[0] += part[2 * b];
+        v[1] += part[2 * b + 1];
+    }
+    block_reduce_stats<2, 2>(v);
+    if (threadIdx.x == 0) {
+        cs->beta = (cs->rz != 0.0) ? v[0] / cs->rz : 0.0;
+        cs->rz = v[0];
+        cs->rr = v[1];
+        *iters += 1;
+        if (v[1] <= cs->stop2 || !(v[1] == v[1])) cs->done = 1;
+    }
+}
+
+// p = z + beta p
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, int64_t n,
+                         const CgScalars* __restrict__ cs) {
+    if (cs->done) return;
+    const double be = cs->beta;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        p[j] = z[j] + be * p[j];
+}
+
+// Start of PCG: r = rhs - H x0 (hx given), z = minv r, p = z; part = (r z, r r, rhs rhs)
+__global__ __launch_bounds__(L1LS_BLOCK) void k_cg_start(const double* __restrict__ rhs,
+                                                         const double* __restrict__ hx, double* __restrict__ r,
+                                                         double* __restrict__ z, double* __restrict__ p,
+                                                         const double* __restrict__ minv,
+                                                         const uint8_t* __restrict__ mask, int64_t n,
+                                                         double* __restrict__ part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const bool on = !mask || mask[j];
+        const double rj = on ? rhs[j] - (hx ? hx[j] : 0.0) : 0.0;
+        const double zj = on ? minv[j] * rj : 0.0;
+        r[j] = rj;
+        z[j] = zj;
+        p[j] = zj;
+        v[0] += rj * zj;
+        v[1] += rj * rj;
+        v[2] += on ? rhs[j] * rhs[j] : 0.0;
+    }
+    block_reduce_stats<3, 3>(v);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_cg_init(const double* __restrict__ part, int np, CgScalars* cs,
+                                                  double rtol, int32_t* __restrict__ iters) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
+        v[0] += part[3 * b];
+        v[1] += part[3 * b + 1];
+        v[2] += part[3 * b + 2];
+    }
+    block_reduce_stats<3, 3>(v);
+    if (threadIdx.x == 0) {
+        cs->rz = v[0];
+        cs->rr = v[1];
+        cs->stop2 = rtol * rtol * v[2];
+        cs->alpha = cs->beta = cs->pHp = 0.0;
+        cs->done = (v[1] <= cs->stop2) ? 1 : 0;
+        *iters = 0;
+    }
+}
+
+__global__ void k_cg_reset(CgScalars* cs) {
+    cs->rz = cs->pHp = cs->alpha = cs->beta = cs->rr = cs->stop2 = 0.0;
+    cs->done = 0;
+    cs->pad = 0;
+}
+
+// ---- CG-Newton vector kernels -------------------------------------------
+// From g = A^T r (r = A x - b), form grad f_mu, the Hessian diagonal d,
+// the preconditioner 1/(diag(A^T A) + d); part = (max |grad|, sum psi_mu(x)).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_newton_grad(const double* __restrict__ atr,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ gd,
+                                                            const double* __restrict__ colnorm2, double tau,
+                                                            double mu, int primal, double* __restrict__ grad,
+                                                            double* __restrict__ d, double* __restrict__ minv,
+                                                            int64_t n, double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};  // psi sum | max |grad|
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double xj = x[j];
+        const double w = sqrt(mu * mu + xj * xj);
+        const double gj = tau * xj / w + atr[j];
+        const double dj = primal ? tau * mu * mu / (w * w * w) : tau * (1.0 - xj * gd[j] / w) / w;
+        grad[j] = gj;
+        d[j] = dj;
+        minv[j] = 1.0 / (colnorm2[j] + dj);
+        v[0] += w - mu;
+        v[1] = fmax(v[1], fabs(gj));
+    }
+    block_reduce_stats<2, 1>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// part = (grad . dx, sum psi_mu(x + a dx) | over m: sum (r + a q)^2)
+__global__ __launch_bounds__(L1LS_BLOCK) void k_ls_terms(const double* __restrict__ x,
+                                                         const double* __restrict__ dx,
+                                                         const double* __restrict__ grad,
+                                                         const double* __restrict__ r, const double* __restrict__ q,
+                                                         double a, double mu, int64_t n, int64_t m,
+                                                         double* __restrict__ part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    const int64_t N = n > m ? n : m;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n) {
+            const double xn = x[i] + a * dx[i];
+            v[0] += grad[i] * dx[i];
+            v[1] += sqrt(mu * mu + xn * xn) - mu;
+        }
+        if (i < m) {
+            const double ri = r[i] + a * q[i];
+            v[2] += ri * ri;
+        }
+    }
+    block_reduce_stats<3, 3>(v);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
+    }
+}
+
+// dual update of the primal-dual diagonal, then x += a dx
+__global__ void k_newton_step(double* __restrict__ x, double* __restrict__ gd, const double* __restrict__ dx,
+                              double a, double mu, int primal, int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double xj = x[j];
+    if (!primal) {
+        const double w = sqrt(mu * mu + xj * xj);
+        const double g0 = gd[j];
+        const double g1 = g0 + (-g0 + xj / w + (1.0 - xj * g0 / w) * dx[j] / w);
+        gd[j] = fmin(1.0, fmax(-1.0, g1));
+    }
+    x[j] = xj + a * dx[j];
+}
+
+// ---- polish kernels --------------------------------------------------------
+// S = {j : |x_j| > thr}: mask and sign
+__global__ void k_support_from_x(const double* __restrict__ x, uint8_t* __restrict__ mask,
+                                 double* __restrict__ sgn, double thr, int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double xj = x[j];
+    const bool on = fabs(xj) > thr;
+    mask[j] = on ? 1 : 0;
+    sgn[j] = !on ? 0.0 : ((xj > 0.0) ? 1.0 : -1.0);
+}
+
+// rhs_j = (A^T b)_j - tau sgn_j on S; minv_j = 1 / diag(A^T A)_j
+__global__ void k_polish_rhs(const double* __restrict__ atb, const double* __restrict__ sgn,
+                             const uint8_t* __restrict__ mask, const double* __restrict__ colnorm2, double tau,
+                             double* __restrict__ rhs, double* __restrict__ minv, int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    rhs[j] = mask[j] ? atb[j] - tau * sgn[j] : 0.0;
+    minv[j] = 1.0 / colnorm2[j];
+}
+
+// After a reduced solve: count (sign violators on S, KKT violators off S);
+// violators change the mask/sign (drops first, adds only when none drop).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_polish_check(double* __restrict__ x, uint8_t* __restrict__ mask,
+                                                             double* __restrict__ sgn, const double* __restrict__ atr,
+                                                             double tau, double slack, int64_t n,
+                                                             int32_t* __restrict__ counts) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (mask[j]) {
+        const double xj = x[j];
+        if (!(xj * sgn[j] > 0.0)) atomicAdd(counts + 0, 1);
+    } else if (fabs(atr[j]) > tau * (1.0 + slack)) {
+        atomicAdd(counts + 1, 1);
+    }
+}
+
+__global__ void k_polish_apply(double* __restrict__ x, uint8_t* __restrict__ mask, double* __restrict__ sgn,
+                               const double* __restrict__ atr, double tau, double slack, int drop, int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (drop) {
+        if (mask[j] && !(x[j] * sgn[j] > 0.0)) {
+            mask[j] = 0;
+            sgn[j] = 0.0;
+            x[j] = 0.0;
+        }
+    } else if (!mask[j] && fabs(atr[j]) > tau * (1.0 + slack)) {
+        mask[j] = 1;
+        sgn[j] = (atr[j] > 0.0) ? -1.0 : 1.0;
+    }
+}
+
+__global__ void k_mask_mul(double* __restrict__ x, const uint8_t* __restrict__ mask, int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n && !mask[j]) x[j] = 0.0;
+}
+
+__global__ void k_axpby(const double* __restrict__ a, double alpha, const double* __restrict__ b, double beta,
+                        double* __restrict__ out, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) out[i] = alpha * a[i] + beta * (b ? b[i] : 0.0);
+}
+
+// ---- host side ------------------------------------------------------------
+struct Work {
+    const l1ls_instance* I;
+    hipStream_t s;
+    DevArena arena;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *hp = nullptr, *minv = nullptr;
+    double *d = nullptr, *rhs = nullptr, *tm = nullptr, *tm2 = nullptr, *grad = nullptr, *gd = nullptr;
+    double* rres = nullptr;  // Newton residual A x - b (m); tm is PCG scratch
+    double *xs = nullptr, *atr = nullptr, *atb = nullptr;
+    double* part = nullptr;
+    uint8_t* mask = nullptr;
+    int32_t* counts = nullptr;
+    int32_t* iters = nullptr;
+    CgScalars* cs = nullptr;
+    std::vector<double> h;
+    ~Work() { arena.release(); }
+    l1ls_status init(const l1ls_instance* inst, hipStream_t stream) {
+        I = inst;
+        s = stream;
+        const int64_t n = I->n, m = I->m;
+        for (double** v : {&x, &r, &z, &p, &hp, &minv, &d, &rhs, &grad, &gd, &xs, &atr, &atb})
+            L1LS_TRY(arena.alloc(v, n));
+        L1LS_TRY(arena.alloc(&tm, m));
+        L1LS_TRY(arena.alloc(&tm2, m));
+        L1LS_TRY(arena.alloc(&rres, m));
+        L1LS_TRY(arena.alloc(&part, 3 * (size_t)std::max(kRedBlocks, tgrid(n))));
+        L1LS_TRY(arena.alloc(&mask, n));
+        L1LS_TRY(arena.alloc(&counts, 2));
+        L1LS_TRY(arena.alloc(&iters, 1));
+        L1LS_TRY(arena.alloc(&cs, 1));
+        h.resize(3 * (size_t)std::max(kRedBlocks, tgrid(n)));
+        return L1LS_OK;
+    }
+    // host sums of `k` statistics over `nb` partial slots (fixed order)
+    l1ls_status host_sums(int k, int nb, double* out, bool max_last = false) {
+        HIP_TRY(hipMemcpyAsync(h.data(), part, (size_t)k * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int q = 0; q < k; ++q) out[q] = 0.0;
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < k; ++q) {
+                const double v = h[(size_t)k * b + q];
+                out[q] = (max_last && q == k - 1) ? std::max(out[q], v) : out[q] + v;
+            }
+        return L1LS_OK;
+    }
+    void spmv(const double* in, double* out) {  // out (m) = A in
+        hipLaunchKernelGGL(k_tile_spmv, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                           I->csr_v64, in, out, I->m);
+    }
+    void spmv_t(const double* in, double* out) {  // out (n) = A^T in
+        hipLaunchKernelGGL(k_tile_spmv, dim3(tgrid(I->n)), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                           I->csc_v64, in, out, I->n);
+    }
+    // PCG on H v = rhs from v = x (in place), H = mask (A^T A + diag(dv)) mask.
+    // zero_start: v is known to be 0, so H v = 0 is not computed.
+    l1ls_status pcg(double* v, const double* rhs_v, const double* dv, const uint8_t* mk, double rtol, int maxit,
+                    int* out_iters, bool zero_start = false) {
+        const int64_t n = I->n;
+        const int gt = tgrid(n);
+        hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(1), 0, s, cs);
+        if (!zero_start) {  // H v for the starting residual
+            spmv(v, tm);
+            hipLaunchKernelGGL(k_hess, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row, I->csc_v64, tm, v,
+                               dv, mk, hp, n, part, (const CgScalars*)cs);
+        }
+        hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, rhs_v,
+                           zero_start ? (const double*)nullptr : hp, r, z, p, minv, mk, n, part);
+        hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1024), 0, s, part, kRedBlocks, cs, rtol, iters);
+        HIP_TRY(hipGetLastError());
+        const int batch = 8;
+        int done_iters = 0;
+        for (int it = 0; it < maxit; it += batch) {
+            const int nb = std::min(batch, maxit - it);
+            for (int q = 0; q < nb; ++q) {
+                spmv(p, tm);
+                hipLaunchKernelGGL(k_hess, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row, I->csc_v64,
+                                   tm, p, dv, mk, hp, n, part, (const CgScalars*)cs);
+                hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, part, gt, cs);
+                hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, v, r, z, p, hp, minv, mk,
+                                   n, part, (const CgScalars*)cs);
+                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, part, kRedBlocks, cs, iters);
+                hipLaunchKernelGGL(k_cg_dir, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, p, z, n,
+                                   (const CgScalars*)cs);
+            }
+            HIP_TRY(hipGetLastError());
+            CgScalars c;
+            HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&done_iters, iters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (c.done) break;
+        }
+        *out_iters = done_iters;
+        return L1LS_OK;
+    }
+};
+
+}  // namespace
+
+// FP64 polish of x_dev (original order, n entries), in place; the starting
+// support is {j : |x_j| > support_tol}.
+l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t s, int* rounds_out,
+                        int64_t* pcg_iters_out, double support_tol) {
+    *rounds_out = 0;
+    *pcg_iters_out = 0;
+    if (!I->csr_v64 || !I->csc_v64) return L1LS_E_UNSUPPORTED;
+    Work W;
+    L1LS_TRY(W.init(I, s));
+    const int64_t n = I->n;
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, x_dev, W.x, I->op_col_of, n);
+    hipLaunchKernelGGL(k_support_from_x, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, support_tol, n);
+    W.spmv_t(I->b_op, W.atb);
+    const double slack = 1e-10;
+    int64_t total = 0;
+    int rounds = 0;
+    for (rounds = 1; rounds <= 10; ++rounds) {
+        hipLaunchKernelGGL(k_polish_rhs, g1d(n), dim3(L1LS_BLOCK), 0, s, W.atb, W.xs, W.mask, I->colnorm2_op, tau,
+                           W.rhs, W.minv, n);
+        hipLaunchKernelGGL(k_mask_mul, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, n);
+        int it = 0;
+        L1LS_TRY(W.pcg(W.x, W.rhs, nullptr, W.mask, 1e-13, 2000, &it));
+        total += it;
+        // A^T (A x - b)
+        W.spmv(W.x, W.tm);
+        hipLaunchKernelGGL(k_axpby, g1d(I->m), dim3(L1LS_BLOCK), 0, s, W.tm, 1.0, I->b_op, -1.0, W.tm, I->m);
+        W.spmv_t(W.tm, W.atr);
+        HIP_TRY(hipMemsetAsync(W.counts, 0, 2 * sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_polish_check, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, W.atr, tau, slack, n,
+                           W.counts);
+        int32_t cnt[2];
+        HIP_TRY(hipMemcpyAsync(cnt, W.counts, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (cnt[0] == 0 && cnt[1] == 0) break;
+        hipLaunchKernelGGL(k_polish_apply, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, W.atr, tau, slack,
+                           cnt[0] > 0 ? 1 : 0, n);
+    }
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, x_dev, I->op_col_pos, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    *rounds_out = std::min(rounds, 10);
+    *pcg_iters_out = total;
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_solve_opts* o, double* x_out,
                                             l1ls_report* rep) {
-    if (!I || !o || !x) return L1LS_E_ARG;
-    (void)rep;
-    return L1LS_E_UNSUPPORTED;
+    if (!I || !o || !x_out) return L1LS_E_ARG;
+    if (!I->csr_v64 || !I->csc_v64) return L1LS_E_UNSUPPORTED;
+    if (o->max_iter < 0) return L1LS_E_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o->stream;
+    const double tau = o->tau > 0 ? o->tau : I->tau;
+    const double mu = o->mu > 0 ? o->mu : 1e-5;
+    const double prtol = o->pcg_rtol > 0 ? o->pcg_rtol : 0.1;
+    const int maxbt = o->max_backtrack > 0 ? o->max_backtrack : 50;
+    const int pcgmax = o->pcg_maxit > 0 ? o->pcg_maxit : 1000;
+    const int primal = o->hessian == 1 ? 1 : 0;
+    const double gtol = (o->rel_gap_tol > 0 ? o->rel_gap_tol : 1e-9) * tau;
+    if (!is_finite(tau) || !is_finite(mu)) return L1LS_E_ARG;
+    const int64_t n = I->n, m = I->m;
+    Work W;
+    L1LS_TRY(W.init(I, s));
+    if (o->x0_dev)
+        hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, o->x0_dev, W.x,
+                           I->op_col_of, n);
+    else
+        HIP_TRY(hipMemsetAsync(W.x, 0, n * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(W.gd, 0, n * sizeof(double), s));
+    int64_t newton = 0, pcg_total = 0;
+    double gnorm = INFINITY;
+    const double armijo = 1e-4;
+    for (newton = 0; newton < o->max_iter; ++newton) {
+        // r = A x - b; grad, diagonal, preconditioner
+        W.spmv(W.x, W.rres);
+        hipLaunchKernelGGL(k_axpby, g1d(m), dim3(L1LS_BLOCK), 0, s, W.rres, 1.0, I->b_op, -1.0, W.rres, m);
+        W.spmv_t(W.rres, W.atr);
+        hipLaunchKernelGGL(k_newton_grad, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.atr, W.x, W.gd,
+                           I->colnorm2_op, tau, mu, primal, W.grad, W.d, W.minv, n, W.part);
+        double gs[2];
+        L1LS_TRY(W.host_sums(2, kRedBlocks, gs, true));
+        gnorm = gs[1];
+        if (!is_finite(gnorm)) return L1LS_E_NONFINITE;
+        if (gnorm <= gtol) break;
+        // Newton direction: H dx = -grad, from dx = 0
+        hipLaunchKernelGGL(k_axpby, g1d(n), dim3(L1LS_BLOCK), 0, s, W.grad, -1.0, (const double*)nullptr, 0.0,
+                           W.rhs, n);
+        HIP_TRY(hipMemsetAsync(W.xs, 0, n * sizeof(double), s));
+        int it = 0;
+        L1LS_TRY(W.pcg(W.xs, W.rhs, W.d, nullptr, prtol, pcgmax, &it, true));
+        pcg_total += it;
+        // line search on f_mu(x + a dx) = tau sum psi + 0.5 ||r + a A dx||^2
+        W.spmv(W.xs, W.tm2);
+        double t0s[3];
+        hipLaunchKernelGGL(k_ls_terms, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.x, W.xs, W.grad, W.rres, W.tm2,
+                           0.0, mu, n, m, W.part);
+        L1LS_TRY(W.host_sums(3, kRedBlocks, t0s));
+        const double f0 = tau * t0s[1] + 0.5 * t0s[2];
+        const double slope = t0s[0];
+        double a = 1.0;
+        for (int bt = 0; bt < maxbt; ++bt) {
+            double ta[3];
+            hipLaunchKernelGGL(k_ls_terms, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.x, W.xs, W.grad, W.rres,
+                               W.tm2, a, mu, n, m, W.part);
+            L1LS_TRY(W.host_sums(3, kRedBlocks, ta));
+            if (tau * ta[1] + 0.5 * ta[2] <= f0 + armijo * a * slope) break;
+            if (bt + 1 < maxbt) a *= 0.5;
+        }
+        hipLaunchKernelGGL(k_newton_step, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.gd, W.xs, a, mu, primal, n);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, x_out, I->op_col_pos,
+                       n);
+    HIP_TRY(hipStreamSynchronize(s));
+    l1ls_report r;
+    std::memset(&r, 0, sizeof(r));
+    r.iterations = newton;
+    r.inner = pcg_total;
+    int prounds = 0;
+    int64_t ppcg = 0;
+    if (o->polish) {
+        // smoothed iterates carry |x_j| <~ 2 mu off the support (|x/w| < 1)
+        L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &ppcg, 10.0 * mu));
+        r.inner += ppcg;
+    }
+    r.polish_rounds = prounds;
+    L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));
+    L1LS_TRY(rel_err_planted(I, x_out, &r.rel_err, s));
+    r.converged = (gnorm <= gtol) ? 1 : 0;
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    return r.converged ? L1LS_OK : L1LS_NOT_CONVERGED;
 }

@@ -1,0 +1,104 @@
+"""GPU parity of the second-order path (CG-Newton) and of the FP64 polish.
+
+CG-Newton is compared with the oracle's smoothed Newton-CG on the same
+generated instance: both minimise the same smooth problem (8), so their
+final iterates agree to the Newton stopping tolerance; trajectories (Newton
+step and PCG counts) are compared only loosely (parity unpinned beyond the
+minimiser).  The polish solves the reduced problem (13) exactly, so it is
+compared with the oracle's polish and with the planted x*.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1503_03520_amd as L  # noqa: E402
+from oracle import instance as OI  # noqa: E402
+from oracle import newton as ON  # noqa: E402
+from oracle import polish as OP  # noqa: E402
+from oracle import fista as F  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+C1 = (2048, 1024, 1e2, 10, 1.0, 1503035200, 1)
+TWO_STAGE = (4096, 2048, 1e3, 20, 1.0, 1503035202, 2)
+RAGGED = (1010, 502, 1e2, 7, 0.5, 17, 2)
+
+_cache = {}
+
+
+def pair(cfg):
+    if cfg not in _cache:
+        m, n, kappa, s, tau, seed, r = cfg
+        print(f"\n[case] m={m} n={n} kappa={kappa} s={s} tau={tau} seed={seed} rounds={r}", flush=True)
+        g = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r)
+        o = OI.Instance(m, n, kappa, s, tau, seed, rounds=r)
+        _cache[cfg] = (g, o, o.sparse_A())
+    return _cache[cfg]
+
+
+def _dev(v):
+    return torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED])
+@pytest.mark.parametrize("hessian", [0, 1])
+def test_cg_newton_reaches_oracle_minimiser(cfg, hessian):
+    g, o, A = pair(cfg)
+    mu = 1e-5
+    x, rep, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, hessian=hessian)
+    assert st == L.L1LS_OK and rep["converged"] == 1
+    cn = np.asarray(A.multiply(A).sum(0)).ravel()
+    xo, so = ON.newton_cg(lambda v: A @ v, lambda v: A.T @ v, cn, o.b, o.tau, mu=mu,
+                          hessian="primal" if hessian == 1 else "primal_dual", max_newton=300)
+    xg = x.cpu().numpy()
+    scale = max(1.0, np.abs(xo).max())
+    # both stop at ||grad f_mu||_inf <= 1e-9 tau; the minimiser of (8) is unique
+    assert np.abs(xg - xo).max() <= 1e-5 * scale
+    # O(mu) distance to the l1 minimiser x*
+    assert np.abs(xg - o.xstar).max() <= 200 * mu * scale
+    print(f"newton gpu {rep['iterations']}/{rep['inner']}  oracle {so['newton']}/{so['pcg']}")
+    assert rep["iterations"] <= 3 * so["newton"] + 5
+
+
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE])
+def test_cg_newton_with_polish_recovers_planted(cfg):
+    g, o, A = pair(cfg)
+    x, rep, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, polish=1)
+    err = np.linalg.norm(x.cpu().numpy() - o.xstar) / np.linalg.norm(o.xstar)
+    assert err <= 1e-9 and math.isclose(err, rep["rel_err"], rel_tol=1e-6, abs_tol=1e-15)
+    assert abs(rep["rel_gap"]) <= 1e-12
+    assert rep["polish_rounds"] >= 1
+
+
+def test_polish_matches_oracle_from_perturbed_support():
+    g, o, A = pair(TWO_STAGE)
+    guess = o.xstar.copy()
+    guess[o.support[0]] = 0.0
+    wrong = np.setdiff1d(np.arange(o.n), o.support)[5]
+    guess[wrong] = 0.3
+    xo, ro = OP.polish(A, o.b, o.tau, guess)
+    # the polish runs after FISTA; 0 FISTA iterations from x0 = guess polishes the guess
+    x, rep, _ = L.l1ls_solve_fista(g, x0=_dev(guess), max_iter=0, rel_gap_tol=0.0, check_every=1,
+                                   precision=L.F64, polish=1)
+    xg = x.cpu().numpy()
+    assert np.abs(xg - xo).max() <= 1e-10 * max(1.0, np.abs(xo).max())
+    assert np.linalg.norm(xg - o.xstar) <= 1e-10 * np.linalg.norm(o.xstar)
+    assert rep["polish_rounds"] >= 2
+
+
+def test_fista_fp32_then_polish_recovers_planted():
+    g, o, A = pair(C1)
+    x, rep, _ = L.l1ls_solve_fista(g, max_iter=3000, rel_gap_tol=1e-7, check_every=32, precision=L.F32,
+                                   polish=1)
+    err = np.linalg.norm(x.cpu().numpy() - o.xstar) / np.linalg.norm(o.xstar)
+    assert err <= 1e-10 and abs(rep["rel_gap"]) <= 1e-12
+
+
+def test_cg_newton_zero_when_tau_dominates():
+    g, o, A = pair(RAGGED)
+    tau = 1.01 * np.abs(A.T @ o.b).max()
+    x, rep, st = L.l1ls_solve_cg_newton(g, tau=tau, max_iter=100, rel_gap_tol=1e-9, polish=1)
+    assert np.array_equal(x.cpu().numpy(), np.zeros(o.n))
