@@ -120,6 +120,21 @@ def algorithmic_bytes(m, n, nnz, es=4, ie=4):
     return k1, k2
 
 
+def mf_bytes(m, n, es=4):
+    """Algorithmic bytes of one matrix-free FISTA iteration (FP32, two stages).
+
+    residual: n side reads x (n) and two stages of (c, s) (n/2 pairs each),
+    writes w (n); m side reads emb (int32, m), sigma (m), gathers w once (n),
+    two stages of (c, s) (m/2 pairs each), b and r_x, writes r_x and r_y.
+    transpose: m side reads r_y (m), (c, s) tables, sigma, writes v (m);
+    n side reads inv (int32, n), gathers v once (n), (c, s) tables,
+    x_{k-1}, x_{k-2}, writes x_k.
+    """
+    res = es * (n + 2 * n + n) + 4 * m + es * m + es * n + es * 2 * m + es * 2 * m + es * 2 * m
+    tr = es * (m + 2 * m + m + m) + 4 * n + es * n + es * 2 * n + es * 3 * n
+    return res + tr
+
+
 def cpu_baseline(m, n, kappa, s, tau, seed, rounds, budget_s):
     """The oracle's FISTA (plain FP64 numpy/scipy) on the same workload."""
     import numpy as np
@@ -194,9 +209,9 @@ def main():
     gen_s = time.perf_counter() - t0
     nnz = inst.info().nnz
 
-    def run(steps, warmup, time_kernels):
+    def run(steps, warmup, time_kernels, op=L.OP_STORED):
         fs = L.Fista(inst, precision=L.F32, rel_gap_tol=0.0, check_every=args.check_every,
-                     max_iter=warmup + steps, time_kernels=time_kernels, stream=stream)
+                     max_iter=warmup + steps, time_kernels=time_kernels, stream=stream, op=op)
         fs.iterate(warmup)
         torch.cuda.synchronize()
         if time_kernels:
@@ -221,6 +236,10 @@ def main():
 
     plain = run(args.steps, args.warmup, 0)
     timed = run(args.steps, args.warmup, 1)
+    # the same iteration over the matrix-free operator (rotation triplets
+    # applied on the fly), reported beside the stored-operator figure
+    mfree = run(args.steps, args.warmup, 0, op=L.OP_MATRIX_FREE)
+    mfree_t = run(args.steps, args.warmup, 1, op=L.OP_MATRIX_FREE)
     ms_per_step = plain["ms"] / args.steps
     value = args.steps / (plain["ms"] / 1e3)
 
@@ -271,6 +290,13 @@ def main():
             "generate_s": gen_s,
             "final_rel_gap_fp64": gap,
             "timed_ms_with_kernel_events": timed["ms"],
+            "matrix_free": {
+                "iters_per_s": args.steps / (mfree["ms"] / 1e3),
+                "ms_per_step": mfree["ms"] / args.steps,
+                "kernel_avg_us": {k: mfree_t["kernel_ms"][i] / max(mfree_t["kernel_launches"][i], 1) * 1e3
+                                  for i, k in enumerate(("residual_pair", "transpose_pair", "gap"))},
+                "bytes_per_iter": mf_bytes(m, n),
+            },
         },
     }
     if not args.no_cpu_baseline:

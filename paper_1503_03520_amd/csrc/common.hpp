@@ -89,6 +89,18 @@ struct l1ls_instance {
     const int32_t* op_col_pos = nullptr;
     const int32_t* op_row_of = nullptr;
     const int32_t* op_row_pos = nullptr;
+    // Matrix-free operator in stage order (see mf.hip): Sigma links
+    // m-position i and n-position mf_emb[i] (or none, -1); mf_inv is the
+    // inverse on the n side; mf_sig* = sigma at m-positions (0 if none).
+    int32_t* mf_emb = nullptr;
+    int32_t* mf_inv = nullptr;
+    double* mf_sig64 = nullptr;
+    float* mf_sig32 = nullptr;
+    double* mf_sign64 = nullptr;  // sigma at n-positions
+    float* mf_sign32 = nullptr;
+    double* mf_b64 = nullptr;     // b in m-stage order
+    float* mf_b32 = nullptr;
+    float* mf_cs32[2][L1LS_MAX_ROUNDS] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int32_t* csr_ptr = nullptr;   // m+1
     int32_t* csr_col = nullptr;
     double* csr_v64 = nullptr;

@@ -12,6 +12,13 @@ using namespace l1ls;
 
 template <typename T>
 l1ls_status apply_side(const SideTables& tab, int rounds, bool transpose, T* v, T* scratch, hipStream_t stream);
+template <typename T>
+void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, T* rx, T* ry, T beta, int init,
+                        double* part, const GapState* gs, int stats, hipStream_t s);
+template <typename T>
+void mf_transpose_launch(const l1ls_instance* I, const T* ry, T* vt, const T* xc, T* xp, T beta, T L, T thr,
+                         double* part, const GapState* gs, int stats, hipStream_t s);
+int mf_grid(int64_t pairs);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol);
 
@@ -114,6 +121,11 @@ struct l1ls_fista {
     void* x[2] = {nullptr, nullptr};  // x_k lives in x[k & 1]
     void* rx = nullptr;
     void* ry = nullptr;
+    void* wbuf = nullptr;      // matrix-free: Sigma G^T x in m-stage order (m)
+    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in n-stage order (n)
+    bool mf = false;           // matrix-free operator (stage order)
+    const int32_t* col_of = nullptr;   // position -> original index of x
+    const int32_t* col_pos = nullptr;  // original index -> position
     double* k1part = nullptr;  // [2][g1][3], slot k & 1 written by the residual pass of iteration k
     double* k2part = nullptr;  // [g2][2]
     GapState* gs = nullptr;
@@ -195,8 +207,20 @@ template <>
 const double* b_vec<double>(const l1ls_instance* I) { return I->b_op; }
 
 template <typename T>
+const T* mf_b(const l1ls_instance* I);
+template <>
+const float* mf_b<float>(const l1ls_instance* I) { return I->mf_b32; }
+template <>
+const double* mf_b<double>(const l1ls_instance* I) { return I->mf_b64; }
+
+template <typename T>
 l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
     const l1ls_instance* I = F->I;
+    if (F->mf)
+        return timed(F, 0, [&] {
+            mf_residual_launch<T>(I, x, (T*)F->wbuf, mf_b<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, init,
+                                  F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats, F->stream);
+        });
     return timed(F, 0, [&] {
         hipLaunchKernelGGL((k_residual<T>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
                            I->csr_col, csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
@@ -207,6 +231,11 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
 template <typename T>
 l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta, int stats) {
     const l1ls_instance* I = F->I;
+    if (F->mf)
+        return timed(F, 1, [&] {
+            mf_transpose_launch<T>(I, (const T*)F->ry, (T*)F->tbuf, xc, xp, (T)beta, (T)F->L, (T)(F->tau / F->L),
+                                   F->k2part, F->gs, stats, F->stream);
+        });
     return timed(F, 1, [&] {
         hipLaunchKernelGGL((k_transpose_prox<T>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
                            I->csc_ptr, I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L,
@@ -282,9 +311,10 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if (!I || !opts || !out) return L1LS_E_ARG;
     *out = nullptr;
     if (opts->precision != L1LS_F32 && opts->precision != L1LS_F64) return L1LS_E_ARG;
-    if (opts->op != L1LS_OP_STORED) return L1LS_E_UNSUPPORTED;
+    if (opts->op != L1LS_OP_STORED && opts->op != L1LS_OP_MATRIX_FREE) return L1LS_E_ARG;
     if (opts->check_every < 1 || opts->max_iter < 0 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
-    L1LS_TRY(check_stored(I, opts->precision));
+    if (opts->op == L1LS_OP_STORED) L1LS_TRY(check_stored(I, opts->precision));
+    if (opts->op == L1LS_OP_MATRIX_FREE && !I->mf_emb) return L1LS_E_UNSUPPORTED;
     const double tau = opts->tau > 0 ? opts->tau : I->tau;
     const double L = opts->L > 0 ? opts->L : I->L;
     if (!is_finite(tau) || !is_finite(L)) return L1LS_E_ARG;
@@ -296,8 +326,11 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     F->prec = opts->precision;
     F->tau = tau;
     F->L = L;
-    F->g1 = tile_grid(I->m);
-    F->g2 = tile_grid(I->n);
+    F->mf = (opts->op == L1LS_OP_MATRIX_FREE);
+    F->g1 = F->mf ? mf_grid(I->m / 2) : tile_grid(I->m);
+    F->g2 = F->mf ? mf_grid(I->n / 2) : tile_grid(I->n);
+    F->col_of = F->mf ? I->side[0].perm : I->op_col_of;
+    F->col_pos = F->mf ? I->side[0].pinv : I->op_col_pos;
     const size_t es = (F->prec == L1LS_F32) ? sizeof(float) : sizeof(double);
     auto fail = [&](l1ls_status s) {
         F->arena.release();
@@ -310,6 +343,18 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if ((st = F->arena.alloc(&x1, I->n * es)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&rx, I->m * es)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&ry, I->m * es)) != L1LS_OK) return fail(st);
+    if (F->mf) {
+        // Sigma G^T x in m-stage order: zero at the inactive positions, which
+        // the n-side pass never writes; Sigma^T Q^T r_y in n-stage order: all
+        // positions rewritten by every transpose pass.
+        unsigned char* wb = nullptr;
+        unsigned char* tb = nullptr;
+        if ((st = F->arena.alloc(&wb, I->m * es)) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&tb, I->n * es)) != L1LS_OK) return fail(st);
+        if (hipMemsetAsync(wb, 0, I->m * es, F->stream) != hipSuccess) return fail(L1LS_E_HIP);
+        F->wbuf = wb;
+        F->tbuf = tb;
+    }
     if ((st = F->arena.alloc(&F->k1part, (size_t)2 * 3 * F->g1)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&F->k2part, (size_t)2 * F->g2)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&F->gs, 1)) != L1LS_OK) return fail(st);
@@ -324,13 +369,13 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if (F->prec == L1LS_F64) {
         if (opts->x0_dev)
             hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev,
-                               (double*)x0, I->op_col_of, I->n);
+                               (double*)x0, F->col_of, I->n);
         else
             hipLaunchKernelGGL(k_fill<double>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (double*)x0, 0.0, I->n);
     } else {
         if (opts->x0_dev)
             hipLaunchKernelGGL((k_gather_perm<float, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, opts->x0_dev,
-                               (float*)x0, I->op_col_of, I->n);
+                               (float*)x0, F->col_of, I->n);
         else
             hipLaunchKernelGGL(k_fill<float>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (float*)x0, 0.0f, I->n);
     }
@@ -379,10 +424,10 @@ extern "C" l1ls_status l1ls_fista_get_x(l1ls_fista* F, double* x_out) {
     // back to the original order: x[j] = x_op[op_col_pos[j]]
     if (F->prec == L1LS_F64)
         hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, F->stream,
-                           (const double*)src, x_out, F->I->op_col_pos, n);
+                           (const double*)src, x_out, F->col_pos, n);
     else
         hipLaunchKernelGGL((k_gather_perm<double, float>), g1d(n), dim3(L1LS_BLOCK), 0, F->stream,
-                           (const float*)src, x_out, F->I->op_col_pos, n);
+                           (const float*)src, x_out, F->col_pos, n);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(F->stream));
     return L1LS_OK;

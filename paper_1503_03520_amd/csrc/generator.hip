@@ -322,6 +322,8 @@ l1ls_status apply_side(const SideTables& tab, int rounds, bool transpose, T* v, 
 template l1ls_status apply_side<double>(const SideTables&, int, bool, double*, double*, hipStream_t);
 template l1ls_status apply_side<float>(const SideTables&, int, bool, float*, float*, hipStream_t);
 
+l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s);
+
 extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int64_t s, double tau,
                                         uint64_t seed, const l1ls_gen_opts* opts, l1ls_instance** out) {
     if (!out) return L1LS_E_ARG;
@@ -448,6 +450,8 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
     }
     I->fstar = tau * fs[0] + 0.5 * fs[1];
     I->nnz = nnz;
+
+    GEN_TRY(build_mf_tables(I, stream));
 
     // Operator order of the stored A and of the vectors that go with it.
     if (layout == L1LS_LAYOUT_STAGE) {

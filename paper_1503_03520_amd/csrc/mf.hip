@@ -1,0 +1,362 @@
+// Matrix-free FISTA passes (section 4, Algorithms MvPA and MvPAt: A as the
+// operator Q Sigma G^T from the rotation triplets, without a stored A) in
+// stage order.
+//
+// In stage order (position p of a side holds original index pi(p)) stage 1
+// pairs positions (2k, 2k+1) and stage 2 pairs (2k+1, 2k+2 mod N), so every
+// Givens stage is a local stencil.  The only non-local step is Sigma, which
+// links n-position a and m-position i when pi_n(a) = pi_m(i):
+//   emb[i] = a (or -1 when pi_m(i) >= n),  inv[a] = i,
+//   sig[i] = sigma_{pi_m(i)} (0 when inactive).
+// A x   = Q (Sigma (G^T x)):  pass 1 (n side) w = G^T x;
+//                             pass 2 (m side) z_i = sig_i w_{emb_i}, r = Q z,
+//                             fused with the residual/momentum epilogue.
+// A^T r = G (Sigma^T (Q^T r)): pass 1 (m side) v_i = sig_i (Q^T r)_i;
+//                             pass 2 (n side) t_a = v_{inv_a}, g = G t,
+//                             fused with the gradient step, prox, momentum.
+// Each thread owns one rotation pair of the last stage it applies and reads
+// the 4 consecutive positions that feed it.
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace l1ls;
+
+namespace {
+
+template <typename T>
+struct MfTabs {
+    const T* csn[L1LS_MAX_ROUNDS];  // n side, per stage: (c, s) per pair
+    const T* csm[L1LS_MAX_ROUNDS];  // m side
+    const int32_t* emb;             // m
+    const int32_t* inv;             // n
+    const T* sig;                   // m: sigma at m-positions (0 if inactive)
+    const T* sig_n;                 // n: sigma at n-positions
+    int64_t n, m;
+};
+
+template <typename T>
+struct CS {
+    T c, s;
+};
+
+template <typename T>
+__device__ __forceinline__ CS<T> cs_of(const T* tab, int64_t k) {
+    return CS<T>{tab[2 * k], tab[2 * k + 1]};
+}
+
+__device__ __forceinline__ int64_t wrap(int64_t p, int64_t N) { return p < 0 ? p + N : (p >= N ? p - N : p); }
+
+// G(f,g): (zf, zg) -> (c zf - s zg, s zf + c zg); transpose: (c zf + s zg, -s zf + c zg)
+template <typename T>
+__device__ __forceinline__ void rot(CS<T> r, T zf, T zg, bool transpose, T& of, T& og) {
+    if (transpose) {
+        of = r.c * zf + r.s * zg;
+        og = -r.s * zf + r.c * zg;
+    } else {
+        of = r.c * zf - r.s * zg;
+        og = r.s * zf + r.c * zg;
+    }
+}
+
+// z = Sigma G^T x in m-stage order: the n-side stages are applied locally,
+// then sigma_a w_a is written to m-position inv[a] (a permutation onto the
+// active m-positions; inactive ones keep the 0 they were initialised with).
+// R = 2: G^T = S_1^T S_2^T (S_2^T first); thread k handles stage-1 pair
+// (2k, 2k+1) from x at 2k-1 .. 2k+2.
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ zm, MfTabs<T> tb,
+                                                       const GapState* __restrict__ gs) {
+    if (gs && gs->done) return;
+    const int64_t n = tb.n, np = n / 2;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
+        T z0 = x[2 * k], z1 = x[2 * k + 1];
+        if (R == 2) {
+            const T xm = x[wrap(2 * k - 1, n)], xp = x[wrap(2 * k + 2, n)];
+            T a, b;
+            rot(cs_of(tb.csn[1], wrap(k - 1, np)), xm, z0, true, a, b);  // 2k is second of stage-2 pair k-1
+            const T z0n = b;
+            rot(cs_of(tb.csn[1], k), z1, xp, true, a, b);                // 2k+1 is first of stage-2 pair k
+            z0 = z0n;
+            z1 = a;
+        }
+        T o0, o1;
+        rot(cs_of(tb.csn[0], k), z0, z1, true, o0, o1);
+        const int32_t i0 = tb.inv[2 * k], i1 = tb.inv[2 * k + 1];
+        zm[i0] = tb.sig_n[2 * k] * o0;
+        zm[i1] = tb.sig_n[2 * k + 1] * o1;
+    }
+}
+
+// r_x = Q z - b, r_y = (1+beta) r_x - beta r_x,prev, z read in m-stage order.
+// R = 2: Q = S~_2 S~_1 (S~_1 first); thread k writes stage-2 pair
+// (2k+1, 2k+2 mod m) from z at 2k .. 2k+3.  R = 1: stage-1 pair (2k, 2k+1).
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restrict__ zm, const T* __restrict__ b,
+                                                               T* __restrict__ rx, T* __restrict__ ry, T beta,
+                                                               int init, MfTabs<T> tb, double* __restrict__ part,
+                                                               const GapState* __restrict__ gs, int stats) {
+    const int32_t done = gs ? gs->done : 0;
+    if (done) return;
+    const int64_t m = tb.m, mp = m / 2;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < mp; k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t pf, pg;
+        T rf, rg;
+        if (R == 2) {
+            const int64_t p0 = 2 * k, p1 = 2 * k + 1, p2 = wrap(2 * k + 2, m), p3 = wrap(2 * k + 3, m);
+            T a, u1, u2, bb;
+            rot(cs_of(tb.csm[0], k), zm[p0], zm[p1], false, a, u1);                 // p1 second of pair k
+            rot(cs_of(tb.csm[0], wrap(k + 1, mp)), zm[p2], zm[p3], false, u2, bb);  // p2 first of pair k+1
+            rot(cs_of(tb.csm[1], k), u1, u2, false, rf, rg);
+            pf = p1;
+            pg = p2;
+        } else {
+            pf = 2 * k;
+            pg = 2 * k + 1;
+            rot(cs_of(tb.csm[0], k), zm[pf], zm[pg], false, rf, rg);
+        }
+        const int64_t ps[2] = {pf, pg};
+        const T rr[2] = {rf, rg};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t i = ps[e];
+            const T bi = b[i];
+            const T r = rr[e] - bi;
+            const T yv = init ? r : (T(1) + beta) * r - beta * rx[i];
+            rx[i] = r;
+            ry[i] = yv;
+            v[0] += (double)r * (double)r;
+            v[1] += (double)yv * (double)yv;
+            v[2] += (double)bi * (double)yv;
+        }
+    }
+    if (!stats) return;
+    block_reduce_stats<3, 3>(v);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
+    }
+}
+
+// t = Sigma^T Q^T y in n-stage order: the m-side stages are applied locally,
+// then sigma_i u_i is written to n-position emb[i] for active m-positions
+// (a permutation onto [0, n)).  R = 2: Q^T = S~_1^T S~_2^T (S~_2^T first);
+// thread k handles stage-1 pair (2k, 2k+1) from y at 2k-1 .. 2k+2.
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ tn, MfTabs<T> tb,
+                                                       const GapState* __restrict__ gs) {
+    if (gs && gs->done) return;
+    const int64_t m = tb.m, mp = m / 2;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < mp; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a0 = tb.emb[2 * k], a1 = tb.emb[2 * k + 1];
+        if (a0 < 0 && a1 < 0) continue;
+        T z0 = y[2 * k], z1 = y[2 * k + 1];
+        if (R == 2) {
+            const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
+            T a, b;
+            rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, z0, true, a, b);
+            const T z0n = b;
+            rot(cs_of(tb.csm[1], k), z1, yp, true, a, b);
+            z0 = z0n;
+            z1 = a;
+        }
+        T o0, o1;
+        rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
+        if (a0 >= 0) tn[a0] = tb.sig[2 * k] * o0;
+        if (a1 >= 0) tn[a1] = tb.sig[2 * k + 1] * o1;
+    }
+}
+
+// g = G t (t in n-stage order); then y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
+// x_k = soft(y - g/L, tau/L) written over x_{k-2}.  R = 2: G = S_2 S_1 (S_1
+// first); thread k writes stage-2 pair (2k+1, 2k+2 mod n) from t at 2k..2k+3.
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_prox(const T* __restrict__ tn, const T* __restrict__ xc,
+                                                           T* __restrict__ xp, T beta, T L, T thr, MfTabs<T> tb,
+                                                           double* __restrict__ part,
+                                                           const GapState* __restrict__ gs, int stats) {
+    const int32_t done = gs ? gs->done : 0;
+    if (done) return;
+    const int64_t n = tb.n, np = n / 2;
+    double v[2] = {0.0, 0.0};
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t pf, pg;
+        T gf, gg;
+        if (R == 2) {
+            const int64_t p0 = 2 * k, p1 = 2 * k + 1, p2 = wrap(2 * k + 2, n), p3 = wrap(2 * k + 3, n);
+            T a, u1, u2, bb;
+            rot(cs_of(tb.csn[0], k), tn[p0], tn[p1], false, a, u1);
+            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tn[p2], tn[p3], false, u2, bb);
+            rot(cs_of(tb.csn[1], k), u1, u2, false, gf, gg);
+            pf = p1;
+            pg = p2;
+        } else {
+            pf = 2 * k;
+            pg = 2 * k + 1;
+            rot(cs_of(tb.csn[0], k), tn[pf], tn[pg], false, gf, gg);
+        }
+        const int64_t ps[2] = {pf, pg};
+        const T gv[2] = {gf, gg};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t j = ps[e];
+            const T xcur = xc[j];
+            const T y = xcur + beta * (xcur - xp[j]);
+            const T xn = soft_threshold<T>(y - gv[e] / L, thr);
+            xp[j] = xn;
+            v[0] += fabs((double)xn);
+            v[1] = fmax(v[1], fabs((double)gv[e]));
+        }
+    }
+    if (!stats) return;
+    block_reduce_stats<2, 1>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = v[1];
+        part[2 * blockIdx.x + 1] = v[0];
+    }
+}
+
+// ---- tables ------------------------------------------------------------------
+__global__ void k_mf_emb(const int32_t* __restrict__ perm_m, const int32_t* __restrict__ pinv_n,
+                         const double* __restrict__ sigma, int64_t n, int64_t m, int32_t* __restrict__ emb,
+                         double* __restrict__ sig64, float* __restrict__ sig32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t o = perm_m[i];
+    const bool on = o < n;
+    emb[i] = on ? pinv_n[o] : -1;
+    const double sg = on ? sigma[o] : 0.0;
+    sig64[i] = sg;
+    sig32[i] = (float)sg;
+}
+
+__global__ void k_mf_inv(const int32_t* __restrict__ perm_n, const int32_t* __restrict__ pinv_m,
+                         const double* __restrict__ sigma, int64_t n, int32_t* __restrict__ inv,
+                         double* __restrict__ sn64, float* __restrict__ sn32) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int32_t j = perm_n[a];
+    inv[a] = pinv_m[j];
+    sn64[a] = sigma[j];
+    sn32[a] = (float)sigma[j];
+}
+
+__global__ void k_to_f32_mf(const double* __restrict__ a, float* __restrict__ o, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) o[i] = (float)a[i];
+}
+
+inline dim3 g1d(int64_t N) { return dim3((unsigned)std::max<int64_t>(1, (N + L1LS_BLOCK - 1) / L1LS_BLOCK)); }
+
+template <typename T>
+MfTabs<T> tabs_of(const l1ls_instance* I);
+template <>
+MfTabs<double> tabs_of<double>(const l1ls_instance* I) {
+    MfTabs<double> t;
+    for (int q = 0; q < L1LS_MAX_ROUNDS; ++q) {
+        t.csn[q] = I->side[0].cs[q];
+        t.csm[q] = I->side[1].cs[q];
+    }
+    t.emb = I->mf_emb;
+    t.inv = I->mf_inv;
+    t.sig = I->mf_sig64;
+    t.sig_n = I->mf_sign64;
+    t.n = I->n;
+    t.m = I->m;
+    return t;
+}
+template <>
+MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
+    MfTabs<float> t;
+    for (int q = 0; q < L1LS_MAX_ROUNDS; ++q) {
+        t.csn[q] = I->mf_cs32[0][q];
+        t.csm[q] = I->mf_cs32[1][q];
+    }
+    t.emb = I->mf_emb;
+    t.inv = I->mf_inv;
+    t.sig = I->mf_sig32;
+    t.sig_n = I->mf_sign32;
+    t.n = I->n;
+    t.m = I->m;
+    return t;
+}
+
+}  // namespace
+
+// Tables of the stage-order matrix-free operator (called by the generator).
+l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
+    const int64_t n = I->n, m = I->m;
+    L1LS_TRY(I->arena.alloc(&I->mf_emb, m));
+    L1LS_TRY(I->arena.alloc(&I->mf_inv, n));
+    L1LS_TRY(I->arena.alloc(&I->mf_sig64, m));
+    L1LS_TRY(I->arena.alloc(&I->mf_sig32, m));
+    L1LS_TRY(I->arena.alloc(&I->mf_sign64, n));
+    L1LS_TRY(I->arena.alloc(&I->mf_sign32, n));
+    L1LS_TRY(I->arena.alloc(&I->mf_b64, m));
+    L1LS_TRY(I->arena.alloc(&I->mf_b32, m));
+    hipLaunchKernelGGL(k_mf_emb, g1d(m), dim3(L1LS_BLOCK), 0, s, I->side[1].perm, I->side[0].pinv, I->sigma, n, m,
+                       I->mf_emb, I->mf_sig64, I->mf_sig32);
+    hipLaunchKernelGGL(k_mf_inv, g1d(n), dim3(L1LS_BLOCK), 0, s, I->side[0].perm, I->side[1].pinv, I->sigma, n,
+                       I->mf_inv, I->mf_sign64, I->mf_sign32);
+    for (int sd = 0; sd < 2; ++sd)
+        for (int t = 0; t < I->rounds; ++t) {
+            const int64_t N = I->side[sd].N;
+            L1LS_TRY(I->arena.alloc(&I->mf_cs32[sd][t], N));
+            hipLaunchKernelGGL(k_to_f32_mf, g1d(N), dim3(L1LS_BLOCK), 0, s, I->side[sd].cs[t], I->mf_cs32[sd][t], N);
+        }
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(m), dim3(L1LS_BLOCK), 0, s, I->b, I->mf_b64,
+                       I->side[1].perm, m);
+    hipLaunchKernelGGL((k_gather_perm<float, double>), g1d(m), dim3(L1LS_BLOCK), 0, s, I->b, I->mf_b32,
+                       I->side[1].perm, m);
+    HIP_TRY(hipGetLastError());
+    return L1LS_OK;
+}
+
+// Grid of the matrix-free streaming passes (one thread per rotation pair,
+// grid-stride beyond this many workgroups).
+int mf_grid(int64_t pairs) {
+    const int64_t g = (pairs + L1LS_BLOCK - 1) / L1LS_BLOCK;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+// zm (m entries) must hold zeros at the inactive m-positions (emb = -1):
+// the n-side pass never writes them.  tn has n entries.
+template <typename T>
+void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, T* rx, T* ry, T beta, int init,
+                        double* part, const GapState* gs, int stats, hipStream_t s) {
+    const MfTabs<T> tb = tabs_of<T>(I);
+    if (I->rounds == 2) {
+        hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        hipLaunchKernelGGL((k_mf_q_residual<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx, ry,
+                           beta, init, tb, part, gs, stats);
+    } else {
+        hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        hipLaunchKernelGGL((k_mf_q_residual<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx, ry,
+                           beta, init, tb, part, gs, stats);
+    }
+}
+
+template <typename T>
+void mf_transpose_launch(const l1ls_instance* I, const T* ry, T* vt, const T* xc, T* xp, T beta, T L, T thr,
+                         double* part, const GapState* gs, int stats, hipStream_t s) {
+    const MfTabs<T> tb = tabs_of<T>(I);
+    if (I->rounds == 2) {
+        hipLaunchKernelGGL((k_mf_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, ry, vt, tb, gs);
+        hipLaunchKernelGGL((k_mf_g_prox<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, beta, L,
+                           thr, tb, part, gs, stats);
+    } else {
+        hipLaunchKernelGGL((k_mf_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, ry, vt, tb, gs);
+        hipLaunchKernelGGL((k_mf_g_prox<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, beta, L,
+                           thr, tb, part, gs, stats);
+    }
+}
+
+template void mf_residual_launch<float>(const l1ls_instance*, const float*, float*, const float*, float*, float*,
+                                        float, int, double*, const GapState*, int, hipStream_t);
+template void mf_residual_launch<double>(const l1ls_instance*, const double*, double*, const double*, double*,
+                                         double*, double, int, double*, const GapState*, int, hipStream_t);
+template void mf_transpose_launch<float>(const l1ls_instance*, const float*, float*, const float*, float*, float,
+                                         float, float, double*, const GapState*, int, hipStream_t);
+template void mf_transpose_launch<double>(const l1ls_instance*, const double*, double*, const double*, double*,
+                                          double, double, double, double*, const GapState*, int, hipStream_t);

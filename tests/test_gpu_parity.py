@@ -176,6 +176,33 @@ def test_fista_trajectory_fp64(cfg, iters, layout):
     assert rep["iterations"] == iters
 
 
+@pytest.mark.parametrize("cfg", CASES)
+@pytest.mark.parametrize("iters", [1, 2, 10, 100])
+def test_fista_trajectory_fp64_matrix_free(cfg, iters):
+    # FISTA over the matrix-free operator (rotation triplets applied on the
+    # fly, Algorithms MvPA/MvPAt) against the oracle's x_k.
+    g, o, A = pair(cfg)
+    x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=1, precision=L.F64,
+                                   op=L.OP_MATRIX_FREE)
+    ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(x.cpu().numpy() - ref).max() <= 1e-11 * scale
+    assert rep["iterations"] == iters
+
+
+@pytest.mark.parametrize("cfg", CASES[:2])
+def test_fista_matrix_free_fp32_equals_stored_gap(cfg):
+    # FP32 bulk on both operators: same tolerance to the FP64 oracle, and the
+    # device gap of each matches the oracle's at the same iterate.
+    g, o, A = pair(cfg)
+    iters = 50
+    ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
+    bound = iters * np.finfo(np.float32).eps * np.abs(o.b).max()
+    for op in (L.OP_STORED, L.OP_MATRIX_FREE):
+        x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=5, precision=L.F32, op=op)
+        assert np.abs(x.cpu().numpy() - ref).max() <= bound
+
+
 @pytest.mark.parametrize("cfg", CASES[:2])
 def test_fista_trajectory_fp32(cfg):
     # FP32 bulk against the FP64 oracle.  The dominant rounding is that of
