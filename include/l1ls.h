@@ -225,6 +225,43 @@ l1ls_status l1ls_fista_get_x(l1ls_fista* st, double* x_out_dev);
 l1ls_status l1ls_fista_kernel_times(l1ls_fista* st, double ms[3], int64_t launches[3]);
 void l1ls_fista_destroy(l1ls_fista* st);
 
+/*
+ * Batched FISTA (the iteration of l1ls_solve_fista, FP32 bulk, stored
+ * operator) over many instances in shared launches.  Each slot keeps its own
+ * iteration count, momentum and gap state on the device, so instances may be
+ * added and removed between calls (continuous batching); a slot's iterates and
+ * its convergence test do not depend on which other slots are resident.
+ *   create: capacity slots; hbm_budget_bytes > 0 makes batch_add refuse
+ *           (L1LS_E_NOMEM) an instance whose l1ls_instance_footprint would
+ *           exceed the budget; opts: rel_gap_tol, check_every, stream
+ *           (precision must be L1LS_F32, op L1LS_OP_STORED).
+ *   add:    admit an instance (not owned; it must outlive its slot) with its
+ *           tau (<= 0: the instance's); x_0 = 0; returns the slot.
+ *           L1LS_E_STATE when no slot is free.
+ *   iterate: enqueue `iters` iterations of every running slot (async).
+ *   poll:   synchronise; reports[capacity] (iterations = -1 for free slots;
+ *           converged = 1 once the gap test passed); *active_out = slots
+ *           still iterating.
+ *   get_x:  the slot's current iterate (FP64, original order) to x_out_dev.
+ *   remove: free the slot and its buffers.
+ */
+typedef struct l1ls_batch l1ls_batch;
+l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_bytes, const l1ls_solve_opts* opts,
+                              l1ls_batch** out);
+l1ls_status l1ls_batch_add(l1ls_batch* batch, const l1ls_instance* inst, double tau, int32_t* slot_out);
+l1ls_status l1ls_batch_iterate(l1ls_batch* batch, int64_t iters);
+l1ls_status l1ls_batch_poll(l1ls_batch* batch, l1ls_report* reports, int32_t* active_out);
+l1ls_status l1ls_batch_get_x(l1ls_batch* batch, int32_t slot, double* x_out_dev);
+l1ls_status l1ls_batch_remove(l1ls_batch* batch, int32_t slot);
+void l1ls_batch_destroy(l1ls_batch* batch);
+/* Device bytes an instance occupies while resident in a batch (its stored
+ * operator, vectors and the slot's iterates): the admission footprint. */
+size_t l1ls_instance_footprint(const l1ls_instance* inst);
+/* Solve `count` instances together (taus may be NULL); x_outs[i] receives
+ * n_i FP64 values; reports[i] per instance.  L1LS_OK when all converged. */
+l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const double* taus, int32_t count,
+                                     const l1ls_solve_opts* opts, double* const* x_outs, l1ls_report* reports);
+
 const char* l1ls_status_string(int32_t status);
 /* ABI version of this header (incremented on incompatible changes). */
 int32_t l1ls_version(void);

@@ -97,6 +97,18 @@ _SIGS = {
     "l1ls_fista_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_int64)]),
     "l1ls_fista_destroy": (None, [_P]),
+    "l1ls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(SolveOpts),
+                                         ctypes.POINTER(_P)]),
+    "l1ls_batch_add": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]),
+    "l1ls_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "l1ls_batch_poll": (ctypes.c_int, [_P, ctypes.POINTER(Report), ctypes.POINTER(ctypes.c_int32)]),
+    "l1ls_batch_get_x": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "l1ls_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "l1ls_batch_destroy": (None, [_P]),
+    "l1ls_instance_footprint": (ctypes.c_size_t, [_P]),
+    "l1ls_solve_fista_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                ctypes.POINTER(SolveOpts), ctypes.POINTER(_P),
+                                                ctypes.POINTER(Report)]),
     "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "l1ls_version": (ctypes.c_int32, []),
 }
@@ -302,3 +314,83 @@ def device_to_numpy(ptr, count, dtype):
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed ({rc})")
     return out
+
+
+class Batch:
+    """Continuous batching of FISTA solves (l1ls_batch_*)."""
+
+    def __init__(self, capacity, hbm_budget_bytes=0, **kw):
+        self.capacity = int(capacity)
+        self._opts = solve_opts(**kw)
+        h = ctypes.c_void_p()
+        _check(lib().l1ls_batch_create(self.capacity, int(hbm_budget_bytes), ctypes.byref(self._opts),
+                                       ctypes.byref(h)), "l1ls_batch_create")
+        self._h = h
+        self._inst = {}
+
+    def add(self, inst, tau=0.0):
+        slot = ctypes.c_int32(-1)
+        st = lib().l1ls_batch_add(self._h, inst.handle, float(tau), ctypes.byref(slot))
+        if st != L1LS_OK:
+            raise L1lsError(st, "l1ls_batch_add")
+        self._inst[slot.value] = inst
+        return slot.value
+
+    def try_add(self, inst, tau=0.0):
+        """Slot index, or None when the budget or the slots are exhausted."""
+        slot = ctypes.c_int32(-1)
+        st = lib().l1ls_batch_add(self._h, inst.handle, float(tau), ctypes.byref(slot))
+        if st in (-2, -5):
+            return None
+        _check(st, "l1ls_batch_add")
+        self._inst[slot.value] = inst
+        return slot.value
+
+    def iterate(self, iters):
+        _check(lib().l1ls_batch_iterate(self._h, int(iters)), "l1ls_batch_iterate")
+
+    def poll(self):
+        reps = (Report * self.capacity)()
+        act = ctypes.c_int32(0)
+        _check(lib().l1ls_batch_poll(self._h, reps, ctypes.byref(act)), "l1ls_batch_poll")
+        return [r.as_dict() for r in reps], act.value
+
+    def get_x(self, slot, x_out=None):
+        import torch
+        if x_out is None:
+            x_out = torch.empty(self._inst[slot].params["n"], dtype=torch.float64, device="cuda")
+        _check(lib().l1ls_batch_get_x(self._h, int(slot), _ptr(x_out)), "l1ls_batch_get_x")
+        return x_out
+
+    def remove(self, slot):
+        _check(lib().l1ls_batch_remove(self._h, int(slot)), "l1ls_batch_remove")
+        self._inst.pop(slot, None)
+
+    def destroy(self):
+        if self._h:
+            lib().l1ls_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def instance_footprint(inst):
+    return int(lib().l1ls_instance_footprint(inst.handle))
+
+
+def l1ls_solve_fista_batched(insts, taus=None, **kw):
+    import torch
+    count = len(insts)
+    handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
+    tv = (ctypes.c_double * count)(*(taus if taus is not None else [0.0] * count))
+    xs = [torch.empty(i.params["n"], dtype=torch.float64, device="cuda") for i in insts]
+    xp = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    reps = (Report * count)()
+    o = solve_opts(**kw)
+    st = _check(lib().l1ls_solve_fista_batched(handles, tv, count, ctypes.byref(o), xp, reps),
+                "l1ls_solve_fista_batched", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+    return xs, [r.as_dict() for r in reps], st

@@ -35,7 +35,8 @@ inline int tile_grid(int64_t N) {
     return (int)std::max<int64_t>(1, (tiles + 3) / 4);
 }
 
-// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, evaluated without contraction.
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, evaluated without contraction as
+// (1 + sqrt(1 + (4 t) t)) / 2 (the batched driver uses the same order).
 inline double next_t(double t) {
 #pragma clang fp contract(off)
     return (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
