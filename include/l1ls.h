@@ -262,6 +262,16 @@ size_t l1ls_instance_footprint(const l1ls_instance* inst);
 l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const double* taus, int32_t count,
                                      const l1ls_solve_opts* opts, double* const* x_outs, l1ls_report* reports);
 
+/*
+ * Regularisation path (section 8.6 varies tau): FISTA for k <= 64 values of
+ * tau on one instance at once, FP32 bulk over the stored operator, all
+ * columns from x_0 = 0.  X_out_dev receives n x k FP64 values, column-major
+ * (column c is the solution for taus[c], original order); reports[c] per
+ * column.  opts: rel_gap_tol, max_iter, check_every, L, stream.
+ */
+l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus, int32_t k,
+                                  const l1ls_solve_opts* opts, double* X_out_dev, l1ls_report* reports);
+
 const char* l1ls_status_string(int32_t status);
 /* ABI version of this header (incremented on incompatible changes). */
 int32_t l1ls_version(void);

@@ -109,6 +109,8 @@ _SIGS = {
     "l1ls_solve_fista_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                                 ctypes.POINTER(SolveOpts), ctypes.POINTER(_P),
                                                 ctypes.POINTER(Report)]),
+    "l1ls_solve_fista_path": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                             ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "l1ls_version": (ctypes.c_int32, []),
 }
@@ -394,3 +396,17 @@ def l1ls_solve_fista_batched(insts, taus=None, **kw):
     st = _check(lib().l1ls_solve_fista_batched(handles, tv, count, ctypes.byref(o), xp, reps),
                 "l1ls_solve_fista_batched", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
     return xs, [r.as_dict() for r in reps], st
+
+
+def l1ls_solve_fista_path(inst, taus, **kw):
+    """Solutions for every tau in `taus` (<= 64): an n x k FP64 tensor (column c for taus[c])."""
+    import torch
+    k = len(taus)
+    n = inst.params["n"]
+    X = torch.empty((k, n), dtype=torch.float64, device="cuda")   # row c = column c of the n x k output
+    tv = (ctypes.c_double * k)(*[float(t) for t in taus])
+    reps = (Report * k)()
+    o = solve_opts(**kw)
+    st = _check(lib().l1ls_solve_fista_path(inst.handle, tv, k, ctypes.byref(o), _ptr(X), reps),
+                "l1ls_solve_fista_path", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+    return X, [r.as_dict() for r in reps], st
