@@ -160,6 +160,157 @@ def cpu_baseline(m, n, kappa, s, tau, seed, rounds, budget_s):
                       f"on the same n=2^20 instance generated by the oracle ({gen_s:.1f} s, not timed)"}
 
 
+def _even(v):
+    return max(2, int(round(v / 2.0)) * 2)
+
+
+def serve_requests(count, seed, log2n_lo=10, log2n_hi=22):
+    """Solve requests of the serving workload: n log-uniform in [2^lo, 2^hi]
+    (even), m = 2n, kappa log-uniform in [1e2, 1e6], s = n/100, tau
+    log-uniform in [1e-2, 1], two Givens stages, relative-gap tolerance 1e-6."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = _even(2.0 ** rng.uniform(log2n_lo, log2n_hi))
+        out.append(dict(m=2 * n, n=n, kappa=float(10 ** rng.uniform(2, 6)), s=max(1, n // 100),
+                        tau=float(10 ** rng.uniform(-2, 0)), seed=1503035204 * 1000 + i, rounds=2))
+    return out
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_serve(args):
+    """Continuous-batching server vs the one-at-a-time single-solve path.
+
+    Both serve the same request list with the same tolerance, check period
+    and iteration cap.  1) Calibration: the plain path solves every request
+    alone, back to back (generation + FISTA), giving its capacity mu.
+    2) Arrival times: a Poisson process at rate lambda = rate_mult * mu
+    (separate random stream).  3) The plain path serves the arrivals in real
+    time, first come first served, one at a time.  4) The server serves the
+    same arrivals in real time.  Latency = arrival -> result available on the
+    host; solves/s = requests / (last result - first arrival)."""
+    import numpy as np
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    tol, check, cap = args.serve_tol, args.check_every, args.serve_max_iter
+    reqs = serve_requests(args.requests + args.serve_warmup, 1503035204, args.serve_log2n_lo, args.serve_log2n_hi)
+    warm, reqs = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
+
+    def plain_one(r):
+        inst = L.l1ls_generate(r["m"], r["n"], r["kappa"], r["s"], r["tau"], r["seed"], rounds=r["rounds"],
+                               storage=L.STORE_F32, stream=stream)
+        x, rep, _ = L.l1ls_solve_fista(inst, max_iter=cap, rel_gap_tol=tol, check_every=check, precision=L.F32,
+                                       polish=0, stream=stream)
+        torch.cuda.synchronize()
+        inst.free()
+        return rep
+
+    for r in warm:
+        plain_one(r)
+    service, conv_plain, iters_plain = [], 0, []
+    for r in reqs:
+        t0 = time.perf_counter()
+        rep = plain_one(r)
+        service.append(time.perf_counter() - t0)
+        conv_plain += rep["converged"] == 1
+        iters_plain.append(rep["iterations"])
+    mu = len(reqs) / sum(service)
+
+    def arrivals(rate_mult):
+        rng = np.random.default_rng(1503035205)
+        gaps = rng.exponential(1.0 / (rate_mult * mu), size=len(reqs))
+        return np.cumsum(gaps) - gaps[0]
+
+    def run_plain(arr):
+        lat = []
+        t0 = time.perf_counter()
+        for r, a in zip(reqs, arr):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            plain_one(r)
+            lat.append(time.perf_counter() - t0 - a)
+        span = time.perf_counter() - t0
+        return lat, span
+
+    def run_server(arr):
+        S = L.Server(args.serve_slots, hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)),
+                     iters_per_tick=args.serve_iters_per_tick, check_every=check, stream=stream)
+        lat, conv, iters, peak, nxt = {}, 0, [], 0, 0
+        ids = {}
+        t0 = time.perf_counter()
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arr[nxt] <= now:
+                r = reqs[nxt]
+                rid = S.submit(r["m"], r["n"], r["kappa"], r["s"], r["tau"], r["seed"], rounds=r["rounds"],
+                               rel_gap_tol=tol, max_iter=cap)
+                ids[rid] = nxt
+                nxt += 1
+            q, res, _ = S.stats()
+            if q == 0 and res == 0:
+                if nxt < len(reqs):
+                    time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+                continue
+            S.tick()
+            peak = max(peak, S.stats()[1])
+            done_t = time.perf_counter() - t0
+            for rid in S.completed():
+                _, rep = S.take(rid, want_x=False)
+                i = ids[rid]
+                lat[i] = done_t - arr[i]
+                conv += rep["converged"] == 1
+                iters.append(rep["iterations"])
+        span = time.perf_counter() - t0
+        S.destroy()
+        return [lat[i] for i in range(len(reqs))], span, conv, iters, peak
+
+    results = []
+    for mult in args.rate_mults:
+        arr = arrivals(mult)
+        lp, sp = run_plain(arr) if mult <= args.plain_max_mult else (None, None)
+        ls, ss, conv_s, iters_s, peak = run_server(arr)
+        row = {"rate_mult": mult, "rate_per_s": mult * mu,
+               "server": {"solves_per_s": len(reqs) / ss, "p50_s": _pct(ls, 50), "p99_s": _pct(ls, 99),
+                          "converged": conv_s, "peak_resident": peak},
+               }
+        if lp is not None:
+            row["plain_fifo"] = {"solves_per_s": len(reqs) / sp, "p50_s": _pct(lp, 50), "p99_s": _pct(lp, 99)}
+        results.append(row)
+        print(json.dumps({"progress": "serve", **row}), file=sys.stderr, flush=True)
+    head = results[0]
+    line = {
+        "metric": "served solves/sec at a Poisson rate of %.2g x plain-path capacity (p50/p99 latency beside)"
+                  % args.rate_mults[0],
+        "value": head["server"]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": len(warm),
+        "ms_per_step": 1e3 / head["server"]["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (instances generated on the device at admission, seeds 1503035204000+i)",
+        "config": {"workload": "serving: Poisson arrivals, n log-uniform [2^%d, 2^%d], m = 2n, kappa log-uniform "
+                               "[1e2, 1e6], s = n/100, tau log-uniform [1e-2, 1], 2 Givens stages"
+                               % (args.serve_log2n_lo, args.serve_log2n_hi),
+                   "requests": len(reqs), "rel_gap_tol": tol, "check_every": check, "max_iter": cap,
+                   "slots": args.serve_slots, "iters_per_tick": args.serve_iters_per_tick,
+                   "hbm_budget_gib": args.serve_budget_gib},
+        "p50_s": head["server"]["p50_s"], "p99_s": head["server"]["p99_s"],
+        "extra": {"plain_capacity_solves_per_s": mu, "plain_converged": conv_plain,
+                  "plain_iters_median": _pct(iters_plain, 50), "plain_service_s_mean": float(np.mean(service)),
+                  "plain_service_s_p99": _pct(service, 99), "rates": results},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +327,20 @@ def main():
     for d in ("kt", "fetch", "write", "copyf", "copyw"):
         ap.add_argument(f"--{d}")
     ap.add_argument("--out", default=PROFILE_SUMMARY)
+    ap.add_argument("--workload", default="fista", choices=["fista", "serve"],
+                    help="fista: the single large instance (default); serve: the request stream")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serve-warmup", type=int, default=10)
+    ap.add_argument("--serve-tol", type=float, default=1e-6)
+    ap.add_argument("--serve-max-iter", type=int, default=5000)
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-iters-per-tick", type=int, default=16)
+    ap.add_argument("--serve-budget-gib", type=float, default=160.0)
+    ap.add_argument("--serve-log2n-lo", type=int, default=10)
+    ap.add_argument("--serve-log2n-hi", type=int, default=22)
+    ap.add_argument("--rate-mults", type=float, nargs="+", default=[0.7])
+    ap.add_argument("--plain-max-mult", type=float, default=1.0,
+                    help="skip the real-time plain run above this rate multiple (its queue grows without bound)")
     args = ap.parse_args()
     if args.profile_summary:
         write_profile_summary(args)
@@ -193,6 +358,12 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "serve":
+        if args.check_every == 32 and "--check-every" not in sys.argv:
+            args.check_every = 16
+        bench_serve(args)
+        return
 
     import torch
 

@@ -249,6 +249,12 @@ typedef struct l1ls_batch l1ls_batch;
 l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_bytes, const l1ls_solve_opts* opts,
                               l1ls_batch** out);
 l1ls_status l1ls_batch_add(l1ls_batch* batch, const l1ls_instance* inst, double tau, int32_t* slot_out);
+/* As l1ls_batch_add, with this slot's own relative-gap tolerance
+ * (rel_gap_tol < 0: the batch's; 0: never converge) and iteration cap
+ * (max_iter <= 0: none; at the cap the slot stops with converged = 0 and
+ * iterations = max_iter).  L1LS_E_ARG for a NaN tolerance. */
+l1ls_status l1ls_batch_add_ex(l1ls_batch* batch, const l1ls_instance* inst, double tau, double rel_gap_tol,
+                              int64_t max_iter, int32_t* slot_out);
 l1ls_status l1ls_batch_iterate(l1ls_batch* batch, int64_t iters);
 l1ls_status l1ls_batch_poll(l1ls_batch* batch, l1ls_report* reports, int32_t* active_out);
 l1ls_status l1ls_batch_get_x(l1ls_batch* batch, int32_t slot, double* x_out_dev);
@@ -257,6 +263,61 @@ void l1ls_batch_destroy(l1ls_batch* batch);
 /* Device bytes an instance occupies while resident in a batch (its stored
  * operator, vectors and the slot's iterates): the admission footprint. */
 size_t l1ls_instance_footprint(const l1ls_instance* inst);
+/*
+ * Serving: a FIFO queue of solve requests in front of a batch (continuous
+ * batching).  A request names an instance of Procedure IGen (section 3.1;
+ * the arguments of l1ls_generate, with the stage-order layout and FP32
+ * storage) and its own tolerance and iteration cap.  Each tick
+ *   1. admits queued requests in arrival order while a slot is free and the
+ *      estimated footprint of the head request (16 nonzeros per column at two
+ *      stages, 4 at one) fits hbm_budget_bytes (0: no budget); admission
+ *      generates the instance on the device;
+ *   2. enqueues iters_per_tick FISTA iterations of every resident request;
+ *   3. retires requests whose gap test passed, whose iterate went
+ *      non-finite, or which reached max_iter: the iterate (FP64, original
+ *      order) moves to a result buffer held until l1ls_server_take, and the
+ *      slot and instance are freed.
+ * A result is bit-identical to the one the request would get alone in the
+ * server (the batch's per-slot independence).  report.seconds of a taken
+ * result is the time from submission to retirement (host steady clock).
+ *   create: max_slots >= 1, iters_per_tick >= 1, check_every >= 1 (gap test
+ *           period of every request), stream (NULL: default).
+ *   submit: L1LS_E_ARG for an invalid request (the checks of l1ls_generate,
+ *           rounds 1 or 2, rel_gap_tol > 0, max_iter > 0), L1LS_E_NOMEM if its
+ *           estimate alone exceeds the budget; *id_out is its id (0, 1, ...).
+ *   tick:   *admitted / *completed (either may be NULL) count this tick's
+ *           admissions and retirements.  Synchronises the stream.
+ *   completed: copies up to cap ids retired since the last call into ids,
+ *           oldest first; returns how many.
+ *   take:   copies the result of a retired id to x_out_dev (n FP64; NULL to
+ *           drop it) and its report, then frees it; L1LS_E_STATE if the id is
+ *           not retired or already taken.
+ *   stats:  queued requests, resident requests, estimated bytes resident.
+ */
+typedef struct l1ls_server l1ls_server;
+typedef struct {
+    int64_t m, n;
+    double kappa;
+    int64_t s;
+    double tau;
+    uint64_t seed;
+    int32_t rounds;
+    int32_t pad;
+    double rel_gap_tol;
+    int64_t max_iter;
+} l1ls_request;
+l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_bytes, int32_t iters_per_tick,
+                               int32_t check_every, void* stream, l1ls_server** out);
+l1ls_status l1ls_server_submit(l1ls_server* server, const l1ls_request* req, int64_t* id_out);
+l1ls_status l1ls_server_tick(l1ls_server* server, int32_t* admitted, int32_t* completed);
+int32_t l1ls_server_completed(l1ls_server* server, int64_t* ids, int32_t cap);
+l1ls_status l1ls_server_take(l1ls_server* server, int64_t id, double* x_out_dev, l1ls_report* rep);
+l1ls_status l1ls_server_stats(l1ls_server* server, int32_t* queued, int32_t* resident, size_t* used_bytes);
+void l1ls_server_destroy(l1ls_server* server);
+/* The admission estimate of a request (bytes): l1ls_instance_footprint of its
+ * FP32 instance with nnz at its bound; 0 for an invalid request or NULL. */
+size_t l1ls_request_footprint(const l1ls_request* req);
+
 /* Solve `count` instances together (taus may be NULL); x_outs[i] receives
  * n_i FP64 values; reports[i] per instance.  L1LS_OK when all converged. */
 l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const double* taus, int32_t count,

@@ -74,6 +74,14 @@ class Report(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("kappa", ctypes.c_double), ("s", ctypes.c_int64),
+        ("tau", ctypes.c_double), ("seed", ctypes.c_uint64), ("rounds", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("rel_gap_tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
+    ]
+
+
 # Every symbol include/l1ls.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
 _SIGS = {
@@ -100,12 +108,24 @@ _SIGS = {
     "l1ls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(SolveOpts),
                                          ctypes.POINTER(_P)]),
     "l1ls_batch_add": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]),
+    "l1ls_batch_add_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int32)]),
     "l1ls_batch_iterate": (ctypes.c_int, [_P, ctypes.c_int64]),
     "l1ls_batch_poll": (ctypes.c_int, [_P, ctypes.POINTER(Report), ctypes.POINTER(ctypes.c_int32)]),
     "l1ls_batch_get_x": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "l1ls_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
     "l1ls_batch_destroy": (None, [_P]),
     "l1ls_instance_footprint": (ctypes.c_size_t, [_P]),
+    "l1ls_server_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
+                                          ctypes.POINTER(_P)]),
+    "l1ls_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
+    "l1ls_server_tick": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "l1ls_server_completed": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "l1ls_server_take": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(Report)]),
+    "l1ls_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "l1ls_server_destroy": (None, [_P]),
+    "l1ls_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(Request)]),
     "l1ls_solve_fista_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                                 ctypes.POINTER(SolveOpts), ctypes.POINTER(_P),
                                                 ctypes.POINTER(Report)]),
@@ -330,9 +350,13 @@ class Batch:
         self._h = h
         self._inst = {}
 
-    def add(self, inst, tau=0.0):
+    def add(self, inst, tau=0.0, rel_gap_tol=None, max_iter=0):
         slot = ctypes.c_int32(-1)
-        st = lib().l1ls_batch_add(self._h, inst.handle, float(tau), ctypes.byref(slot))
+        if rel_gap_tol is None and not max_iter:
+            st = lib().l1ls_batch_add(self._h, inst.handle, float(tau), ctypes.byref(slot))
+        else:
+            tol = -1.0 if rel_gap_tol is None else float(rel_gap_tol)
+            st = lib().l1ls_batch_add_ex(self._h, inst.handle, float(tau), tol, int(max_iter), ctypes.byref(slot))
         if st != L1LS_OK:
             raise L1lsError(st, "l1ls_batch_add")
         self._inst[slot.value] = inst
@@ -378,6 +402,71 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+class Server:
+    """FIFO request queue in front of a batch (l1ls_server_*)."""
+
+    def __init__(self, max_slots, hbm_budget_bytes=0, iters_per_tick=16, check_every=16, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().l1ls_server_create(int(max_slots), int(hbm_budget_bytes), int(iters_per_tick),
+                                        int(check_every), _stream(stream), ctypes.byref(h)), "l1ls_server_create")
+        self._h = h
+        self._n = {}
+
+    def submit(self, m, n, kappa, s, tau, seed, rounds=2, rel_gap_tol=1e-5, max_iter=100000):
+        r = Request(int(m), int(n), float(kappa), int(s), float(tau), int(seed), int(rounds), 0,
+                    float(rel_gap_tol), int(max_iter))
+        rid = ctypes.c_int64(-1)
+        _check(lib().l1ls_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "l1ls_server_submit")
+        self._n[rid.value] = int(n)
+        return rid.value
+
+    def tick(self):
+        a = ctypes.c_int32(0)
+        c = ctypes.c_int32(0)
+        _check(lib().l1ls_server_tick(self._h, ctypes.byref(a), ctypes.byref(c)), "l1ls_server_tick")
+        return a.value, c.value
+
+    def completed(self, cap=4096):
+        ids = (ctypes.c_int64 * cap)()
+        k = lib().l1ls_server_completed(self._h, ids, cap)
+        return list(ids[:k])
+
+    def take(self, rid, want_x=True):
+        import torch
+        n = self._n.get(rid)
+        x = torch.empty(n, dtype=torch.float64, device="cuda") if (want_x and n) else None
+        rep = Report()
+        _check(lib().l1ls_server_take(self._h, int(rid), _ptr(x), ctypes.byref(rep)), "l1ls_server_take")
+        self._n.pop(rid, None)
+        return x, rep.as_dict()
+
+    def stats(self):
+        q = ctypes.c_int32(0)
+        r = ctypes.c_int32(0)
+        u = ctypes.c_size_t(0)
+        _check(lib().l1ls_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u)),
+               "l1ls_server_stats")
+        return q.value, r.value, u.value
+
+    def destroy(self):
+        if self._h:
+            lib().l1ls_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def request_footprint(m, n, rounds=2, kappa=1e2, s=0, tau=1.0, rel_gap_tol=1e-6, max_iter=1):
+    """Admission estimate of a serving request (bytes; 0 if the request is invalid)."""
+    r = Request(int(m), int(n), float(kappa), int(s), float(tau), 0, int(rounds), 0, float(rel_gap_tol),
+                int(max_iter))
+    return int(lib().l1ls_request_footprint(ctypes.byref(r)))
 
 
 def instance_footprint(inst):

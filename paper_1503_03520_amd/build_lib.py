@@ -19,7 +19,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-SOURCES = ["generator.hip", "fista.hip", "operator.hip", "newton.hip", "mf.hip", "batch.hip", "path.hip"]
+SOURCES = ["generator.hip", "fista.hip", "operator.hip", "newton.hip", "mf.hip", "batch.hip", "path.hip", "serve.hip"]
 
 
 def _compile(src):

@@ -33,6 +33,7 @@ struct BInst {  // static per slot
     float* ry;
     int64_t m, n;
     double tau, L, tol;
+    int64_t max_iter;                             // <= 0: no cap
     int32_t t1_begin, t1_end, t2_begin, t2_end;  // this slot's tiles in the tables
     int32_t check_every, pad;
 };
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(256) void kb_tail(const BInst* __restrict__ bi, BSt
     }
     if (threadIdx.x == 0) {
         S.stale = 0;
+        if (I.max_iter > 0 && kn >= I.max_iter) stop = true;  // iteration cap: done, not converged
         if (stop) {
             S.done = 1;
             S.k = kn;
@@ -389,8 +391,10 @@ extern "C" size_t l1ls_instance_footprint(const l1ls_instance* I) {
     return b + slot_footprint(I);
 }
 
-extern "C" l1ls_status l1ls_batch_add(l1ls_batch* B, const l1ls_instance* I, double tau, int32_t* slot_out) {
+extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, double tau, double rel_gap_tol,
+                                         int64_t max_iter, int32_t* slot_out) {
     if (!B || !I || !slot_out) return L1LS_E_ARG;
+    if (rel_gap_tol != rel_gap_tol) return L1LS_E_ARG;
     *slot_out = -1;
     if (!I->csr_v32 || !I->csc_v32) return L1LS_E_UNSUPPORTED;
     if (!(tau > 0.0) || !is_finite(tau)) tau = I->tau;
@@ -431,7 +435,8 @@ extern "C" l1ls_status l1ls_batch_add(l1ls_batch* B, const l1ls_instance* I, dou
     h.n = I->n;
     h.tau = tau;
     h.L = I->L;
-    h.tol = B->o.rel_gap_tol;
+    h.tol = rel_gap_tol >= 0.0 ? rel_gap_tol : B->o.rel_gap_tol;
+    h.max_iter = max_iter > 0 ? max_iter : 0;
     h.check_every = B->o.check_every;
     B->inst[slot] = I;
     B->bufs[slot] = bufs;
@@ -449,6 +454,10 @@ extern "C" l1ls_status l1ls_batch_add(l1ls_batch* B, const l1ls_instance* I, dou
     B->init_pending = true;
     *slot_out = slot;
     return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_batch_add(l1ls_batch* B, const l1ls_instance* I, double tau, int32_t* slot_out) {
+    return l1ls_batch_add_ex(B, I, tau, -1.0, 0, slot_out);
 }
 
 extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {

@@ -78,3 +78,29 @@ def test_solve_opts_defaults():
     L.lib().l1ls_solve_opts_default(ctypes.byref(o))
     assert o.rel_gap_tol == 1e-8 and o.check_every == 32 and o.precision == L.F64
     assert o.mu == 1e-5 and o.pcg_rtol == 0.1 and o.max_backtrack == 50
+
+
+def test_server_null_and_invalid_arguments():
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    assert lib.l1ls_server_create(0, 0, 16, 16, None, ctypes.byref(h)) == -1      # no slots
+    assert lib.l1ls_server_create(4, 0, 0, 16, None, ctypes.byref(h)) == -1       # no iterations per tick
+    assert lib.l1ls_server_create(4, 0, 16, 0, None, ctypes.byref(h)) == -1       # no check period
+    r = L.Request(2048, 1024, 100.0, 10, 1.0, 1, 2, 0, 1e-5, 1000)
+    rid = ctypes.c_int64(-1)
+    assert lib.l1ls_server_submit(None, ctypes.byref(r), ctypes.byref(rid)) == -1
+    assert lib.l1ls_server_tick(None, None, None) == -1
+    assert lib.l1ls_server_take(None, 0, None, None) == -1
+    assert lib.l1ls_server_completed(None, None, 0) == 0
+    assert lib.l1ls_server_stats(None, None, None, None) == -1
+    assert lib.l1ls_batch_add_ex(None, None, 1.0, 1e-5, 10, None) == -1
+    lib.l1ls_server_destroy(None)
+
+
+def test_request_footprint_estimate():
+    f = L.request_footprint
+    assert f(2048, 1024, rounds=2) > f(2048, 1024, rounds=1) > 0
+    assert f(4096, 2048) > f(2048, 1024)
+    assert f(2048, 1023) == 0 and f(1024, 2048) == 0 and f(2048, 1024, rounds=3) == 0
+    assert f(2048, 1024, rel_gap_tol=0.0) == 0 and f(2048, 1024, max_iter=0) == 0
+    assert L.lib().l1ls_request_footprint(None) == 0

@@ -1,0 +1,148 @@
+"""Serving scheduler on the GPU (l1ls_server_*): FIFO admission by footprint,
+continuous batching, retirement.
+
+The invariant continuous batching must keep: a request's result does not
+depend on what else is resident.  A request served in a mix of uneven sizes
+(admitted late, with slots and memory freed by others) gives the same iterate
+bits, iteration count and convergence flag as the same request served alone,
+and as the single-instance FP32 path with the same tolerance and check period.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1503_03520_amd as L  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# (m, n, kappa, s, tau, seed, rounds, tol): uneven sizes, tolerances, both stage counts
+REQS = [
+    (2048, 1024, 1e2, 10, 1.0, 201, 2, 1e-6),
+    (8192, 4096, 1e4, 40, 0.3, 202, 2, 1e-5),
+    (3004, 1502, 1e3, 15, 1.0, 203, 2, 1e-6),
+    (1030, 514, 1e2, 5, 0.05, 204, 1, 1e-5),
+    (32768, 16384, 1e5, 163, 1.0, 205, 2, 1e-6),
+    (4096, 2048, 1e6, 20, 0.1, 206, 2, 1e-6),
+    (2048, 1024, 1e4, 10, 0.5, 207, 2, 1e-6),
+]
+CHECK, PER_TICK, CAP = 16, 16, 20000
+
+
+def _serve(reqs, max_slots, budget=0, stagger=0):
+    """Submit reqs (one more every `stagger` ticks when > 0), tick until all
+    retire; returns {index: (x, report)} and the largest resident count."""
+    S = L.Server(max_slots, hbm_budget_bytes=budget, iters_per_tick=PER_TICK, check_every=CHECK)
+    ids, out, pending, peak = {}, {}, list(range(len(reqs))), 0
+    if stagger == 0:
+        for q in pending:
+            m, n, kappa, s, tau, seed, r, tol = reqs[q]
+            ids[S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=tol, max_iter=CAP)] = q
+        pending = []
+    ticks = 0
+    while len(out) < len(reqs):
+        if pending and ticks % max(stagger, 1) == 0:
+            q = pending.pop(0)
+            m, n, kappa, s, tau, seed, r, tol = reqs[q]
+            ids[S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=tol, max_iter=CAP)] = q
+        S.tick()
+        ticks += 1
+        peak = max(peak, S.stats()[1])
+        for rid in S.completed():
+            out[ids[rid]] = S.take(rid)
+        assert ticks < 100000
+    assert S.stats() == (0, 0, 0)
+    S.destroy()
+    return out, peak
+
+
+def test_served_result_same_alone_and_in_mix():
+    print("\n[case] serve mix of 7 requests, 3 slots, staggered arrivals", flush=True)
+    mix, peak = _serve(REQS, max_slots=3, stagger=3)
+    assert peak == 3
+    for q, req in enumerate(REQS):
+        print(f"[case] serve alone request {q} {req}", flush=True)
+        alone, _ = _serve([req], max_slots=1)
+        xa, ra = alone[0]
+        xm, rm = mix[q]
+        assert rm["converged"] == ra["converged"] == 1, (q, rm, ra)
+        assert rm["iterations"] == ra["iterations"], (q, rm["iterations"], ra["iterations"])
+        assert rm["rel_gap"] == ra["rel_gap"] and rm["rel_gap"] <= req[7]
+        assert torch.equal(xa, xm), q
+
+
+def test_served_result_equals_single_path():
+    out, _ = _serve(REQS[:4], max_slots=4)
+    for q, (m, n, kappa, s, tau, seed, r, tol) in enumerate(REQS[:4]):
+        inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r)    # FP32 + FP64 (for the certificate)
+        x1, r1, _ = L.l1ls_solve_fista(inst, max_iter=CAP, rel_gap_tol=tol, check_every=CHECK, precision=L.F32,
+                                       polish=0)
+        xs, rs = out[q]
+        assert rs["iterations"] == r1["iterations"], (q, rs["iterations"], r1["iterations"])
+        assert torch.equal(xs, x1), q
+        P, D, gap = L.l1ls_objective_gap(inst, tau, xs)
+        assert gap <= 3 * tol       # FP64 certificate of the FP32 iterate
+
+
+def test_admission_by_footprint_serialises_when_budget_fits_one():
+    reqs = REQS[:3]
+    S = L.Server(8, hbm_budget_bytes=1, iters_per_tick=PER_TICK, check_every=CHECK)
+    with pytest.raises(L.L1lsError):      # larger than the whole budget: refused at submission
+        S.submit(*reqs[0][:6], rounds=2, rel_gap_tol=1e-6)
+    S.destroy()
+    est = [L.request_footprint(m, n, rounds=r) for (m, n, k, s, t, sd, r, _) in reqs]
+    inst = L.l1ls_generate(*reqs[1][:6], rounds=reqs[1][6], storage=L.STORE_F32)
+    assert L.instance_footprint(inst) <= est[1]   # the estimate bounds the actual use
+    budget = max(est)                              # holds any one request, never two
+    S = L.Server(8, hbm_budget_bytes=budget, iters_per_tick=PER_TICK, check_every=CHECK)
+    for (m, n, kappa, s, tau, seed, r, tol) in reqs:
+        S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=tol, max_iter=CAP)
+    order, peak = [], 0
+    while len(order) < len(reqs):
+        S.tick()
+        q, res, used = S.stats()
+        assert used <= budget and res <= 1
+        peak = max(peak, res)
+        for rid in S.completed():
+            S.take(rid, want_x=False)
+            order.append(rid)
+    assert peak == 1 and order == [0, 1, 2]      # FIFO
+    S.destroy()
+
+
+def test_iteration_cap_retires_unconverged_and_matches_fixed_iterations():
+    m, n, kappa, s, tau, seed, r, _ = REQS[4]
+    S = L.Server(2, iters_per_tick=PER_TICK, check_every=CHECK)
+    rid = S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=1e-14, max_iter=50)
+    ids = []
+    for _ in range(100):
+        S.tick()
+        ids = S.completed()
+        if ids:
+            break
+    assert ids == [rid]
+    x, rep = S.take(rid)
+    assert rep["converged"] == 0 and rep["iterations"] == 50
+    with pytest.raises(L.L1lsError):       # taken already
+        S.take(rid)
+    S.destroy()
+    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=L.STORE_F32)
+    x1, _, _ = L.l1ls_solve_fista(inst, max_iter=50, rel_gap_tol=0.0, check_every=CHECK, precision=L.F32, polish=0)
+    assert torch.equal(x, x1)
+
+
+def test_latency_report_is_submission_to_retirement():
+    S = L.Server(2, iters_per_tick=PER_TICK, check_every=CHECK)
+    m, n, kappa, s, tau, seed, r, tol = REQS[0]
+    rid = S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=tol)
+    import time
+    t0 = time.perf_counter()
+    while True:
+        S.tick()
+        if S.completed():
+            break
+    wall = time.perf_counter() - t0
+    _, rep = S.take(rid, want_x=False)
+    assert 0 < rep["seconds"] <= wall + 0.05
+    assert np.isfinite(rep["primal"]) and rep["converged"] == 1
+    S.destroy()
