@@ -1,15 +1,19 @@
 // Batched FISTA: many instances of problem (1) advanced together (section
 // 8.1 FISTA on each), FP32 bulk over each instance's stored CSR/CSC.
 //
-// Every resident instance ("slot") keeps its own device state: iteration
-// count k, momentum t_k and beta, gap and converged flag, so instances that
-// joined at different times run side by side.  One launch runs the transpose
-// pass of all slots and one the residual pass, over a table of 64-row
-// (64-column) tiles tagged with their slot; a per-slot tail kernel evaluates
-// the gap on that slot's check iterations and advances its momentum state.
-// Tiles never mix slots and each slot's partial sums are reduced in a fixed
-// order, so a slot's iterates and its convergence test are bit-for-bit the
-// same alone and in any mix of other slots.
+// The batch counts global iterations G.  A slot ("resident instance")
+// records the G at which it was admitted, so its own iteration number is
+// k = G - admit and instances that joined at different times run side by
+// side.  The momentum coefficients beta_k depend on k alone: a host-built
+// table (same arithmetic as the single-instance driver) serves every slot.
+// One launch runs the transpose pass of all slots and one the residual pass,
+// over a table of 64-row (64-column) tiles tagged with their slot; the gap
+// kernel runs on the iterations where some slot reaches a check iteration.
+// Tiles never mix slots, each slot keeps its partial sums in its own buffer
+// (indexed by its own tile number) and reduces them in a fixed order, so a
+// slot's iterates and its convergence test are bit-for-bit the same alone
+// and in any mix of other slots.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -20,7 +24,7 @@
 
 using namespace l1ls;
 
-struct BInst {  // static per slot
+struct BInst {  // static per slot (device copy refreshed on add/remove)
     const int32_t* csr_ptr;
     const int32_t* csr_col;
     const float* csr_val;
@@ -31,22 +35,20 @@ struct BInst {  // static per slot
     float* x[2];
     float* rx;
     float* ry;
+    double* part1;  // [2 parities][nt1][3]: ||r_x||^2, ||r_y||^2, b^T r_y per row tile
+    double* part2;  // [nt2][2]: max |A^T r_y|, sum |x| per column tile
     int64_t m, n;
+    int64_t admit;     // G when x_0 was set: the slot's iteration k = G - admit
+    int64_t max_iter;  // <= 0: no cap
     double tau, L, tol;
-    int64_t max_iter;                             // <= 0: no cap
-    int32_t t1_begin, t1_end, t2_begin, t2_end;  // this slot's tiles in the tables
-    int32_t check_every, pad;
+    int32_t nt1, nt2;
+    int32_t check_every, active;
 };
 
-struct BState {  // dynamic per slot
-    int64_t k;          // iterations done
-    double t;           // t_{k+1}
-    double beta_prev;   // beta_k, used by the next transpose pass
+struct BState {  // written by the gap kernel only
     double P, D, gap;
-    int64_t conv_iter;  // -1 until the gap test passes
-    int32_t active, done, nonfinite, init_pending;
-    int32_t stale;      // tile tables were rebuilt: previous-parity partials are void
-    int32_t pad;
+    int64_t stop_iter;  // iteration at which the slot stopped (done = 1)
+    int32_t done, converged, nonfinite, pad;
 };
 
 struct BTile {
@@ -56,204 +58,177 @@ struct BTile {
 
 namespace {
 
-// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2 with the same operation order as the
-// single-instance driver ((4 t) t), so both produce the same beta bits.
-__device__ __forceinline__ double next_t_dev(double t) {
-    return __ddiv_rn(__dadd_rn(1.0, __dsqrt_rn(__dadd_rn(1.0, __dmul_rn(__dmul_rn(4.0, t), t)))), 2.0);
+// A slot's iteration number in global iteration G, and whether it runs then.
+__device__ __forceinline__ bool slot_live(const BInst& I, const BState& S, int64_t G, int64_t* kn) {
+    *kn = G - I.admit;
+    return I.active && !S.done && *kn >= 1 && (I.max_iter <= 0 || *kn <= I.max_iter);
 }
 
-__device__ __forceinline__ bool slot_runs(const BState& st, int mode) {
-    return mode == 1 ? (st.active && st.init_pending) : (st.active && !st.done && !st.init_pending);
-}
-
-// Transpose pass of iteration k+1 of every running slot.
+// Transpose pass of global iteration G: x_k = soft(y_k - A^T r_y,k / L), with
+// y_k = x_{k-1} + beta_{k-1} (x_{k-1} - x_{k-2}).
 __global__ __launch_bounds__(L1LS_BLOCK) void kb_transpose(const BTile* __restrict__ tiles, int32_t ntiles,
                                                            const BInst* __restrict__ bi,
                                                            const BState* __restrict__ bs,
-                                                           double* __restrict__ k2part) {
+                                                           const float* __restrict__ btab, int64_t G) {
     __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
-    const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
+    const int lane = threadIdx.x % L1LS_WAVE;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
     const int32_t tile = (int32_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid;
     bool run = false;
-    BTile tl{0, 0};
-    if (tile < ntiles) {
-        tl = tiles[tile];
-        run = slot_runs(bs[tl.slot], 0);
-    }
+    int64_t kn = 0;
+    const BTile tl = tiles[tile < ntiles ? tile : 0];
     const BInst& I = bi[tl.slot];
-    const BState& S = bs[tl.slot];
+    if (tile < ntiles) run = slot_live(I, bs[tl.slot], G, &kn);
     const int64_t j = (int64_t)tl.first + lane;
     const bool live = run && j < I.n;
-    const int64_t k = S.k;
-    const float* xc = I.x[k & 1];
-    float* xp = I.x[(k + 1) & 1];
+    const float* __restrict__ xc = I.x[(kn - 1) & 1];
+    float* __restrict__ xp = I.x[kn & 1];
     int32_t pb = 0, pe = 0;
     float xcur = 0.f, xprev = 0.f;
     if (live) {
         pb = I.csc_ptr[j];
         pe = I.csc_ptr[j + 1];
-        xcur = xc[j];
-        xprev = xp[j];
+        xcur = __builtin_nontemporal_load(xc + j);
+        xprev = __builtin_nontemporal_load(xp + j);
     }
-    int32_t beg = 0, end = 0;
     if (run) {
         const int lastlane = (tl.first + kTile <= I.n) ? kTile - 1 : (int)(I.n - tl.first - 1);
-        beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
-        end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+        const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+        const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
         tile_products<float, 16>(I.csc_row, I.csc_val, I.ry, beg, end - beg, lds[wid], lane);
+        pb -= beg;
+        pe -= beg;
     }
     __syncthreads();
     if (!run) return;
-    double v[2] = {0.0, 0.0};  // sum |x|, max |g|
+    double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
     if (live) {
         float acc = 0.f;
-        for (int32_t q = pb - beg; q < pe - beg; ++q) acc += lds[wid][q];
-        const float beta = (float)S.beta_prev;
+        for (int32_t q = pb; q < pe; ++q) acc += lds[wid][q];
+        const float beta = btab[kn - 1];
         const float y = xcur + beta * (xcur - xprev);
         const float xn = soft_threshold<float>(y - acc / (float)I.L, (float)(I.tau / I.L));
-        xp[j] = xn;
+        st_stream(xp + j, xn);
         v[0] = fabs((double)xn);
         v[1] = fabs((double)acc);
     }
+    if (kn % I.check_every != 0) return;  // wave-uniform: no gap test reads this pass
     v[0] = wave_sum(v[0]);
     v[1] = wave_max(v[1]);
     if (lane == 0) {
-        k2part[2 * tile + 0] = v[1];
-        k2part[2 * tile + 1] = v[0];
+        double* p = I.part2 + 2 * (size_t)(tl.first / kTile);
+        p[0] = v[1];
+        p[1] = v[0];
     }
 }
 
-// Residual pass of iteration k+1 (mode 0) or the first pass r = A x_0 - b
-// of slots just admitted (mode 1); partial sums go to parity slot (k+1) & 1
-// (0 for mode 1).
+// Residual pass of global iteration G (mode 0): r_x,k = A x_k - b and
+// r_y,k+1 = (1 + beta_k) r_x,k - beta_k r_x,k-1; or, for the slots admitted
+// at G (mode 1), the first pass r_x,0 = r_y,1 = A x_0 - b.  Partial sums go
+// to parity k & 1 of the slot's buffer (0 for mode 1).
 __global__ __launch_bounds__(L1LS_BLOCK) void kb_residual(const BTile* __restrict__ tiles, int32_t ntiles,
                                                           const BInst* __restrict__ bi,
                                                           const BState* __restrict__ bs,
-                                                          double* __restrict__ k1part, int32_t ntiles_total,
-                                                          int mode) {
+                                                          const float* __restrict__ btab, int64_t G, int mode) {
     __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
-    const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
+    const int lane = threadIdx.x % L1LS_WAVE;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
     const int32_t tile = (int32_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid;
     bool run = false;
-    BTile tl{0, 0};
-    if (tile < ntiles) {
-        tl = tiles[tile];
-        run = slot_runs(bs[tl.slot], mode);
-    }
+    int64_t kn = 0;
+    const BTile tl = tiles[tile < ntiles ? tile : 0];
     const BInst& I = bi[tl.slot];
-    const BState& S = bs[tl.slot];
+    if (tile < ntiles) {
+        if (mode == 1)
+            run = I.active && I.admit == G;
+        else
+            run = slot_live(I, bs[tl.slot], G, &kn);
+    }
     const int64_t i = (int64_t)tl.first + lane;
     const bool live = run && i < I.m;
-    const int64_t k1 = (mode == 1) ? 0 : S.k + 1;
-    const float* x = I.x[k1 & 1];
+    const float* __restrict__ x = I.x[kn & 1];
     int32_t pb = 0, pe = 0;
     float b = 0.f, rprev = 0.f;
     if (live) {
         pb = I.csr_ptr[i];
         pe = I.csr_ptr[i + 1];
-        b = I.b[i];
-        if (mode == 0) rprev = I.rx[i];
+        b = __builtin_nontemporal_load(I.b + i);
+        if (mode == 0) rprev = __builtin_nontemporal_load(I.rx + i);
     }
-    int32_t beg = 0, end = 0;
     if (run) {
         const int lastlane = (tl.first + kTile <= I.m) ? kTile - 1 : (int)(I.m - tl.first - 1);
-        beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
-        end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+        const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+        const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
         tile_products<float, 10>(I.csr_col, I.csr_val, x, beg, end - beg, lds[wid], lane);
+        pb -= beg;
+        pe -= beg;
     }
     __syncthreads();
     if (!run) return;
-    // beta_{k+1} = (t_{k+1} - 1) / t_{k+2}
-    const float beta = (mode == 1) ? 0.f : (float)((S.t - 1.0) / next_t_dev(S.t));
     double v[3] = {0.0, 0.0, 0.0};
     if (live) {
         float acc = 0.f;
-        for (int32_t q = pb - beg; q < pe - beg; ++q) acc += lds[wid][q];
+        for (int32_t q = pb; q < pe; ++q) acc += lds[wid][q];
+        const float beta = (mode == 1) ? 0.f : btab[kn];
         const float r = acc - b;
         const float yv = (mode == 1) ? r : (1.f + beta) * r - beta * rprev;
-        I.rx[i] = r;
-        I.ry[i] = yv;
+        st_stream(I.rx + i, r);
+        st_stream(I.ry + i, yv);
         v[0] = (double)r * (double)r;
         v[1] = (double)yv * (double)yv;
         v[2] = (double)b * (double)yv;
     }
+    // a gap test at k reads ||r_x,k|| from this pass, and the r_y terms of
+    // the pass of k - 1 (the point whose gradient the transpose pass of k used)
+    const int ce = I.check_every;
+    if (mode == 0 && kn % ce != 0 && (kn + 1) % ce != 0) return;  // wave-uniform
     for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
     if (lane == 0) {
-        double* p = k1part + (size_t)(k1 & 1) * 3 * ntiles_total + 3 * (size_t)tile;
+        double* p = I.part1 + ((size_t)(kn & 1) * I.nt1 + (size_t)(tl.first / kTile)) * 3;
         p[0] = v[0];
         p[1] = v[1];
         p[2] = v[2];
     }
 }
 
-// One workgroup per slot: gap test on check iterations, then advance t, beta, k.
-__global__ __launch_bounds__(256) void kb_tail(const BInst* __restrict__ bi, BState* __restrict__ bs,
-                                               const double* __restrict__ k1part, const double* __restrict__ k2part,
-                                               int32_t ntiles_total, int mode) {
-    const int slot = blockIdx.x;
-    BState& S = bs[slot];
-    const BInst& I = bi[slot];
-    if (mode == 1) {
-        if (threadIdx.x == 0 && S.active && S.init_pending) S.init_pending = 0;
-        return;
+// One workgroup per slot: the duality gap on the slot's check iterations
+// (the terms of k_gap, from the slot's own partials in tile order).
+__global__ __launch_bounds__(256) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G) {
+    const BInst& I = bi[blockIdx.x];
+    BState& S = bs[blockIdx.x];
+    int64_t kn = 0;
+    if (!slot_live(I, S, G, &kn) || kn % I.check_every != 0) return;  // block-uniform
+    const double* cur = I.part1 + (size_t)(kn & 1) * 3 * I.nt1;
+    const double* prev = I.part1 + (size_t)((kn - 1) & 1) * 3 * I.nt1;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rr, ryy, bry, l1 | ginf
+    for (int t = threadIdx.x; t < I.nt1; t += blockDim.x) {
+        v[0] += cur[3 * t];
+        v[1] += prev[3 * t + 1];
+        v[2] += prev[3 * t + 2];
     }
-    if (!slot_runs(S, 0)) return;
-    const int64_t kn = S.k + 1;
-    const bool eval = (kn % I.check_every == 0) && !S.stale;
-    __syncthreads();  // every thread has read S before thread 0 writes it
-    bool stop = false;
-    if (eval) {
-        const double* cur = k1part + (size_t)(kn & 1) * 3 * ntiles_total;
-        const double* prev = k1part + (size_t)((kn - 1) & 1) * 3 * ntiles_total;
-        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rr, ryy, bry, l1 | ginf
-        for (int t = I.t1_begin + threadIdx.x; t < I.t1_end; t += blockDim.x) {
-            v[0] += cur[3 * t];
-            v[1] += prev[3 * t + 1];
-            v[2] += prev[3 * t + 2];
-        }
-        for (int t = I.t2_begin + threadIdx.x; t < I.t2_end; t += blockDim.x) {
-            v[3] += k2part[2 * t + 1];
-            v[4] = fmax(v[4], k2part[2 * t]);
-        }
-        block_reduce_stats<5, 4>(v);
-        if (threadIdx.x == 0) {
-            const double P = I.tau * v[3] + 0.5 * v[0];
-            const double theta = (v[4] <= I.tau) ? 1.0 : I.tau / v[4];
-            const double D = -0.5 * theta * theta * v[1] - theta * v[2];
-            const double gap = (P - D) / fabs(P);
-            S.P = P;
-            S.D = D;
-            S.gap = gap;
-            const bool finite = (P == P) && (D == D) && (P - P == 0.0) && (D - D == 0.0);
-            if (!finite) {
-                S.nonfinite = 1;
-                stop = true;
-            } else if (I.tol > 0.0 && gap <= I.tol) {
-                S.conv_iter = kn;
-                stop = true;
-            }
-        }
+    for (int t = threadIdx.x; t < I.nt2; t += blockDim.x) {
+        v[3] += I.part2[2 * t + 1];
+        v[4] = fmax(v[4], I.part2[2 * t]);
     }
-    if (threadIdx.x == 0) {
-        S.stale = 0;
-        if (I.max_iter > 0 && kn >= I.max_iter) stop = true;  // iteration cap: done, not converged
-        if (stop) {
-            S.done = 1;
-            S.k = kn;
-        } else {
-            const double tn = next_t_dev(S.t);
-            S.beta_prev = (S.t - 1.0) / tn;
-            S.t = tn;
-            S.k = kn;
-        }
+    block_reduce_stats<5, 4>(v);
+    if (threadIdx.x != 0) return;
+    const double P = I.tau * v[3] + 0.5 * v[0];
+    const double theta = (v[4] <= I.tau) ? 1.0 : I.tau / v[4];
+    const double D = -0.5 * theta * theta * v[1] - theta * v[2];
+    const double gap = (P - D) / fabs(P);
+    S.P = P;
+    S.D = D;
+    S.gap = gap;
+    const bool finite = (P == P) && (D == D) && (P - P == 0.0) && (D - D == 0.0);
+    if (!finite) {
+        S.nonfinite = 1;
+        S.done = 1;
+        S.stop_iter = kn;
+    } else if (I.tol > 0.0 && gap <= I.tol) {
+        S.converged = 1;
+        S.done = 1;
+        S.stop_iter = kn;
     }
-}
-
-// After the tile tables change, the previous-parity partial sums of running
-// slots sit at stale positions: skip their next gap evaluation.
-__global__ void kb_mark_stale(BState* __restrict__ bs, int32_t capacity) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < capacity && bs[s].active && !bs[s].init_pending) bs[s].stale = 1;
 }
 
 __global__ void kb_zero(float* __restrict__ a, int64_t N) {
@@ -269,6 +244,15 @@ __global__ void kb_to_f64_perm(const float* __restrict__ x, double* __restrict__
 
 inline dim3 g1d(int64_t N) { return dim3((unsigned)std::max<int64_t>(1, (N + L1LS_BLOCK - 1) / L1LS_BLOCK)); }
 
+inline int64_t tiles_of(int64_t N) { return (N + kTile - 1) / kTile; }
+
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2 in the operation order of the
+// single-instance driver, so both produce the same beta bits.
+inline double next_t_host(double t) {
+#pragma clang fp contract(off)
+    return (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+}
+
 }  // namespace
 
 struct l1ls_batch {
@@ -276,49 +260,46 @@ struct l1ls_batch {
     size_t budget = 0, used = 0;
     hipStream_t stream = nullptr;
     l1ls_solve_opts o;
+    int64_t G = 0;                            // global iterations enqueued
     std::vector<const l1ls_instance*> inst;   // per slot (nullptr: free)
     std::vector<BInst> hinst;
     std::vector<size_t> footprint;
-    std::vector<std::vector<float*>> bufs;    // per-slot device buffers
+    std::vector<void*> buf;                   // per-slot device block (iterates + partials)
     BInst* dinst = nullptr;
     BState* dstate = nullptr;
     BTile* dt1 = nullptr;
     BTile* dt2 = nullptr;
     int32_t cap1 = 0, cap2 = 0, nt1 = 0, nt2 = 0;
-    double* k1part = nullptr;
-    double* k2part = nullptr;
+    float* btab = nullptr;                    // beta_k, k = 0 .. nbeta-1
+    int64_t nbeta = 0;
     bool tables_dirty = false, init_pending = false;
     DevArena arena;
 };
 
 namespace {
 
-size_t slot_footprint(const l1ls_instance* I) {
-    // iterate buffers of the slot (the instance's own arrays are counted by
-    // the caller's admission policy through l1ls_instance_footprint)
-    return (size_t)(2 * I->n + 2 * I->m) * sizeof(float);
+// Device bytes of a slot's own block: two x slots, r_x, r_y (FP32) and its
+// FP64 partial sums.
+size_t slot_fbytes(int64_t m, int64_t n) { return (((size_t)(2 * n + 2 * m) * sizeof(float) + 255) / 256) * 256; }
+
+size_t slot_bytes(int64_t m, int64_t n) {
+    return slot_fbytes(m, n) + (size_t)(6 * tiles_of(m) + 2 * tiles_of(n)) * sizeof(double);
 }
 
 l1ls_status rebuild_tables(l1ls_batch* B) {
     std::vector<BTile> t1, t2;
     for (int s = 0; s < B->capacity; ++s) {
-        BInst& hi = B->hinst[s];
         if (!B->inst[s]) continue;
-        hi.t1_begin = (int32_t)t1.size();
+        const BInst& hi = B->hinst[s];
         for (int64_t r = 0; r < hi.m; r += kTile) t1.push_back(BTile{s, (int32_t)r});
-        hi.t1_end = (int32_t)t1.size();
-        hi.t2_begin = (int32_t)t2.size();
         for (int64_t c = 0; c < hi.n; c += kTile) t2.push_back(BTile{s, (int32_t)c});
-        hi.t2_end = (int32_t)t2.size();
     }
     if ((int32_t)t1.size() > B->cap1 || (int32_t)t2.size() > B->cap2) {
-        // grow the tile tables and partial arrays (old ones stay in the arena)
+        // grow the tile tables (old ones stay in the arena until destroy)
         B->cap1 = std::max<int32_t>((int32_t)t1.size(), 2 * B->cap1);
         B->cap2 = std::max<int32_t>((int32_t)t2.size(), 2 * B->cap2);
         L1LS_TRY(B->arena.alloc(&B->dt1, B->cap1));
         L1LS_TRY(B->arena.alloc(&B->dt2, B->cap2));
-        L1LS_TRY(B->arena.alloc(&B->k1part, (size_t)2 * 3 * B->cap1));
-        L1LS_TRY(B->arena.alloc(&B->k2part, (size_t)2 * B->cap2));
     }
     B->nt1 = (int32_t)t1.size();
     B->nt2 = (int32_t)t2.size();
@@ -327,28 +308,57 @@ l1ls_status rebuild_tables(l1ls_batch* B) {
     if (!t2.empty())
         HIP_TRY(hipMemcpyAsync(B->dt2, t2.data(), t2.size() * sizeof(BTile), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(B->dinst, B->hinst.data(), B->capacity * sizeof(BInst), hipMemcpyHostToDevice, B->stream));
-    hipLaunchKernelGGL(kb_mark_stale, dim3((B->capacity + 255) / 256), dim3(256), 0, B->stream, B->dstate,
-                       B->capacity);
-    HIP_TRY(hipGetLastError());
     // the copies read host vectors that go out of scope: wait for them
     HIP_TRY(hipStreamSynchronize(B->stream));
     B->tables_dirty = false;
     return L1LS_OK;
 }
 
+// beta_k = (t_k - 1) / t_{k+1} for k < need (beta_0 = 0, t_1 = 1), as FP32.
+l1ls_status ensure_beta(l1ls_batch* B, int64_t need) {
+    if (need <= B->nbeta) return L1LS_OK;
+    const int64_t len = std::max<int64_t>(need, std::max<int64_t>(4096, 2 * B->nbeta));
+    std::vector<float> h((size_t)len);
+    h[0] = 0.f;
+    double t = 1.0;
+    for (int64_t k = 1; k < len; ++k) {
+        const double tn = next_t_host(t);
+        h[(size_t)k] = (float)((t - 1.0) / tn);
+        t = tn;
+    }
+    float* d = nullptr;
+    L1LS_TRY(B->arena.alloc(&d, (size_t)len));
+    HIP_TRY(hipMemcpyAsync(d, h.data(), (size_t)len * sizeof(float), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    B->btab = d;
+    B->nbeta = len;
+    return L1LS_OK;
+}
+
 l1ls_status run_init(l1ls_batch* B) {
-    if (B->nt1 == 0) return L1LS_OK;
-    const int g1 = (B->nt1 + 3) / 4;
-    hipLaunchKernelGGL(kb_residual, dim3(g1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->nt1, B->dinst, B->dstate,
-                       B->k1part, B->cap1, 1);
-    hipLaunchKernelGGL(kb_tail, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, B->k1part,
-                       B->k2part, B->cap1, 1);
-    HIP_TRY(hipGetLastError());
+    if (B->nt1 > 0) {
+        const int g1 = (B->nt1 + 3) / 4;
+        hipLaunchKernelGGL(kb_residual, dim3(g1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->nt1, B->dinst,
+                           B->dstate, B->btab, B->G, 1);
+        HIP_TRY(hipGetLastError());
+    }
     B->init_pending = false;
     return L1LS_OK;
 }
 
+// Iteration a slot has reached: where it stopped, else its count capped.
+int64_t slot_iterations(const l1ls_batch* B, int s, const BState& st) {
+    if (st.done) return st.stop_iter;
+    const BInst& h = B->hinst[s];
+    const int64_t k = B->G - h.admit;
+    return (h.max_iter > 0) ? std::min(k, h.max_iter) : k;
+}
+
 }  // namespace
+
+// A slot's own device bytes (for admission estimates made before an
+// instance exists).
+size_t batch_slot_bytes(int64_t m, int64_t n) { return slot_bytes(m, n); }
 
 extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_bytes, const l1ls_solve_opts* opts,
                                          l1ls_batch** out) {
@@ -364,7 +374,7 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     B->inst.assign(capacity, nullptr);
     B->hinst.assign(capacity, BInst{});
     B->footprint.assign(capacity, 0);
-    B->bufs.assign(capacity, {});
+    B->buf.assign(capacity, nullptr);
     auto fail = [&](l1ls_status s) {
         B->arena.release();
         delete B;
@@ -373,6 +383,7 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     l1ls_status st;
     if ((st = B->arena.alloc(&B->dinst, capacity)) != L1LS_OK) return fail(st);
     if ((st = B->arena.alloc(&B->dstate, capacity)) != L1LS_OK) return fail(st);
+    if ((st = ensure_beta(B, 4096)) != L1LS_OK) return fail(st);
     if (hipMemsetAsync(B->dstate, 0, capacity * sizeof(BState), B->stream) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipMemsetAsync(B->dinst, 0, capacity * sizeof(BInst), B->stream) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipStreamSynchronize(B->stream) != hipSuccess) return fail(L1LS_E_HIP);
@@ -383,12 +394,12 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
 extern "C" size_t l1ls_instance_footprint(const l1ls_instance* I) {
     if (!I) return 0;
     // stored FP32 CSR + CSC, FP64 copies if kept, vectors and tables, plus the
-    // batch slot's iterate buffers
+    // batch slot's iterates and partial sums
     size_t b = 0;
     if (I->csr_v32) b += (size_t)I->nnz * 16 + (size_t)(I->m + I->n + 2) * 4;
     if (I->csr_v64) b += (size_t)I->nnz * 16;
     b += (size_t)(I->m + I->n) * 48;
-    return b + slot_footprint(I);
+    return b + slot_bytes(I->m, I->n);
 }
 
 extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, double tau, double rel_gap_tol,
@@ -407,19 +418,13 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     if (slot < 0) return L1LS_E_STATE;  // no free slot
     const size_t fp = l1ls_instance_footprint(I);
     if (B->budget && B->used + fp > B->budget) return L1LS_E_NOMEM;
-    std::vector<float*> bufs(4, nullptr);
-    for (int q = 0; q < 4; ++q) {
-        const int64_t N = (q < 2) ? I->n : I->m;
-        void* p = nullptr;
-        if (hipMalloc(&p, N * sizeof(float)) != hipSuccess) {
-            for (float* f : bufs)
-                if (f) (void)hipFree(f);
-            return L1LS_E_NOMEM;
-        }
-        bufs[q] = (float*)p;
-        hipLaunchKernelGGL(kb_zero, g1d(N), dim3(L1LS_BLOCK), 0, B->stream, bufs[q], N);
-    }
+    const int64_t m = I->m, n = I->n;
+    void* blk = nullptr;
+    if (hipMalloc(&blk, slot_bytes(m, n)) != hipSuccess) return L1LS_E_NOMEM;
+    float* f = (float*)blk;
+    hipLaunchKernelGGL(kb_zero, g1d(2 * n), dim3(L1LS_BLOCK), 0, B->stream, f, 2 * n);  // x_0 = x_{-1} = 0
     BInst& h = B->hinst[slot];
+    h = BInst{};
     h.csr_ptr = I->csr_ptr;
     h.csr_col = I->csr_col;
     h.csr_val = I->csr_v32;
@@ -427,28 +432,31 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     h.csc_row = I->csc_row;
     h.csc_val = I->csc_v32;
     h.b = I->b32_op;
-    h.x[0] = bufs[0];
-    h.x[1] = bufs[1];
-    h.rx = bufs[2];
-    h.ry = bufs[3];
-    h.m = I->m;
-    h.n = I->n;
+    h.x[0] = f;
+    h.x[1] = f + n;
+    h.rx = f + 2 * n;
+    h.ry = f + 2 * n + m;
+    h.part1 = (double*)((char*)blk + slot_fbytes(m, n));
+    h.part2 = h.part1 + 6 * tiles_of(m);
+    h.m = m;
+    h.n = n;
+    h.admit = B->G;
+    h.max_iter = max_iter > 0 ? max_iter : 0;
     h.tau = tau;
     h.L = I->L;
     h.tol = rel_gap_tol >= 0.0 ? rel_gap_tol : B->o.rel_gap_tol;
-    h.max_iter = max_iter > 0 ? max_iter : 0;
+    h.nt1 = (int32_t)tiles_of(m);
+    h.nt2 = (int32_t)tiles_of(n);
     h.check_every = B->o.check_every;
+    h.active = 1;
     B->inst[slot] = I;
-    B->bufs[slot] = bufs;
+    B->buf[slot] = blk;
     B->footprint[slot] = fp;
     B->used += fp;
     BState s0;
     std::memset(&s0, 0, sizeof(s0));
-    s0.t = 1.0;
-    s0.conv_iter = -1;
-    s0.active = 1;
-    s0.init_pending = 1;
     HIP_TRY(hipMemcpyAsync(B->dstate + slot, &s0, sizeof(s0), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(B->stream));
     B->tables_dirty = true;
     B->init_pending = true;
@@ -464,15 +472,30 @@ extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {
     if (!B || iters < 0) return L1LS_E_ARG;
     if (B->tables_dirty) L1LS_TRY(rebuild_tables(B));
     if (B->init_pending) L1LS_TRY(run_init(B));
-    if (B->nt1 == 0) return L1LS_OK;
+    if (B->nt1 == 0) {
+        B->G += iters;  // nothing resident: the count still advances
+        return L1LS_OK;
+    }
+    // the beta table must reach the largest k any slot can take; the gap
+    // kernel runs on the G at which some slot's k is a multiple of check_every
+    const int64_t ce = B->o.check_every;
+    int64_t oldest = B->G;
+    std::vector<char> phase((size_t)ce, 0);
+    for (int s = 0; s < B->capacity; ++s)
+        if (B->inst[s]) {
+            oldest = std::min(oldest, B->hinst[s].admit);
+            phase[(size_t)(B->hinst[s].admit % ce)] = 1;
+        }
+    L1LS_TRY(ensure_beta(B, B->G + iters - oldest + 2));
     const int g1 = (B->nt1 + 3) / 4, g2 = (B->nt2 + 3) / 4;
     for (int64_t q = 0; q < iters; ++q) {
+        const int64_t G = ++B->G;
         hipLaunchKernelGGL(kb_transpose, dim3(g2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->nt2, B->dinst,
-                           B->dstate, B->k2part);
+                           B->dstate, B->btab, G);
         hipLaunchKernelGGL(kb_residual, dim3(g1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->nt1, B->dinst,
-                           B->dstate, B->k1part, B->cap1, 0);
-        hipLaunchKernelGGL(kb_tail, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, B->k1part,
-                           B->k2part, B->cap1, 0);
+                           B->dstate, B->btab, G, 0);
+        if (phase[(size_t)(G % ce)])
+            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, G);
     }
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
@@ -491,13 +514,15 @@ extern "C" l1ls_status l1ls_batch_poll(l1ls_batch* B, l1ls_report* reports, int3
             r.iterations = -1;
             continue;
         }
-        r.iterations = (st[s].conv_iter >= 0) ? st[s].conv_iter : st[s].k;
+        const BInst& h = B->hinst[s];
+        r.iterations = slot_iterations(B, s, st[s]);
         r.primal = st[s].P;
         r.dual = st[s].D;
         r.rel_gap = st[s].gap;
-        r.converged = st[s].conv_iter >= 0 ? 1 : (st[s].nonfinite ? -1 : 0);
+        r.converged = st[s].converged ? 1 : (st[s].nonfinite ? -1 : 0);
         r.rel_err = -1.0;
-        if (!st[s].done) ++act;
+        const bool capped = h.max_iter > 0 && r.iterations >= h.max_iter;
+        if (!st[s].done && !capped) ++act;
     }
     if (active_out) *active_out = act;
     return L1LS_OK;
@@ -509,7 +534,8 @@ extern "C" l1ls_status l1ls_batch_get_x(l1ls_batch* B, int32_t slot, double* x_o
     HIP_TRY(hipMemcpyAsync(&st, B->dstate + slot, sizeof(st), hipMemcpyDeviceToHost, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
     const l1ls_instance* I = B->inst[slot];
-    hipLaunchKernelGGL(kb_to_f64_perm, g1d(I->n), dim3(L1LS_BLOCK), 0, B->stream, B->hinst[slot].x[st.k & 1], x_out,
+    const int64_t k = slot_iterations(B, slot, st);
+    hipLaunchKernelGGL(kb_to_f64_perm, g1d(I->n), dim3(L1LS_BLOCK), 0, B->stream, B->hinst[slot].x[k & 1], x_out,
                        I->op_col_pos, I->n);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(B->stream));
@@ -519,13 +545,8 @@ extern "C" l1ls_status l1ls_batch_get_x(l1ls_batch* B, int32_t slot, double* x_o
 extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
     if (!B || slot < 0 || slot >= B->capacity || !B->inst[slot]) return L1LS_E_ARG;
     HIP_TRY(hipStreamSynchronize(B->stream));
-    BState s0;
-    std::memset(&s0, 0, sizeof(s0));
-    s0.conv_iter = -1;
-    HIP_TRY(hipMemcpyAsync(B->dstate + slot, &s0, sizeof(s0), hipMemcpyHostToDevice, B->stream));
-    HIP_TRY(hipStreamSynchronize(B->stream));
-    for (float* f : B->bufs[slot]) (void)hipFree(f);
-    B->bufs[slot].clear();
+    (void)hipFree(B->buf[slot]);
+    B->buf[slot] = nullptr;
     B->used -= B->footprint[slot];
     B->footprint[slot] = 0;
     B->inst[slot] = nullptr;
@@ -537,8 +558,8 @@ extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
 extern "C" void l1ls_batch_destroy(l1ls_batch* B) {
     if (!B) return;
     (void)hipStreamSynchronize(B->stream);
-    for (auto& v : B->bufs)
-        for (float* f : v) (void)hipFree(f);
+    for (void* p : B->buf)
+        if (p) (void)hipFree(p);
     B->arena.release();
     delete B;
 }
@@ -552,7 +573,8 @@ extern "C" l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* inst
     L1LS_TRY(l1ls_batch_create(count, 0, opts, &B));
     l1ls_status st = L1LS_OK;
     std::vector<int32_t> slot(count, -1);
-    for (int q = 0; q < count && st == L1LS_OK; ++q) st = l1ls_batch_add(B, insts[q], taus ? taus[q] : 0.0, &slot[q]);
+    for (int q = 0; q < count && st == L1LS_OK; ++q)
+        st = l1ls_batch_add_ex(B, insts[q], taus ? taus[q] : 0.0, -1.0, opts->max_iter, &slot[q]);
     std::vector<l1ls_report> rep(count);
     const int64_t chunk = (int64_t)opts->check_every * 4;
     int64_t done_iters = 0;

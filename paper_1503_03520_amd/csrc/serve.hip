@@ -55,13 +55,15 @@ struct l1ls_server {
     int64_t ticks = 0;
 };
 
+size_t batch_slot_bytes(int64_t m, int64_t n);
+
 namespace {
 
 // The terms of l1ls_instance_footprint for an FP32-only instance, with nnz
 // at its bound (each Givens stage at most doubles a column's support).
 size_t estimate_footprint(const l1ls_request& r) {
     const size_t nnz = (size_t)r.n * (r.rounds >= 2 ? 16 : 4);
-    return nnz * 16 + (size_t)(r.m + r.n + 2) * 4 + (size_t)(r.m + r.n) * 48 + (size_t)(2 * r.n + 2 * r.m) * 4;
+    return nnz * 16 + (size_t)(r.m + r.n + 2) * 4 + (size_t)(r.m + r.n) * 48 + batch_slot_bytes(r.m, r.n);
 }
 
 bool valid_request(const l1ls_request& r) {
