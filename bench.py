@@ -287,6 +287,13 @@ def bench_serve(args):
             row["plain_fifo"] = {"solves_per_s": len(reqs) / sp, "p50_s": _pct(lp, 50), "p99_s": _pct(lp, 99)}
         results.append(row)
         print(json.dumps({"progress": "serve", **row}), file=sys.stderr, flush=True)
+        if args.serve_dump:
+            with open(args.serve_dump, "a") as fh:
+                for i, r in enumerate(reqs):
+                    fh.write(json.dumps({"mult": mult, "i": i, "n": r["n"], "kappa": r["kappa"], "tau": r["tau"],
+                                         "arrival": float(arr[i]), "service": service[i],
+                                         "iters": iters_plain[i], "lat_plain": lp[i] if lp else None,
+                                         "lat_server": ls[i]}) + "\n")
     head = results[0]
     line = {
         "metric": "served solves/sec at a Poisson rate of %.2g x plain-path capacity (p50/p99 latency beside)"
@@ -311,6 +318,190 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_batched(args):
+    """Many uneven instances in shared launches vs the single-solve path.
+
+    256 instances, n log-uniform in [2^10, 2^16] (even), m = 2n, kappa drawn
+    from {1e2, 1e3, 1e4, 1e5, 1e6}, s = n/100, tau = 1, two Givens stages,
+    FP32.  Both paths stop at the same device gap test (relative gap <= tol,
+    every check_every iterations) with the same cap; instances are generated
+    before timing.  value = solves/s of the batched path."""
+    import numpy as np
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(1503035203)
+    cfgs = []
+    for j in range(args.instances):
+        n = _even(2.0 ** rng.uniform(10, 16))
+        cfgs.append((2 * n, n, float(10 ** rng.integers(2, 7)), max(1, n // 100), 1.0, 1503035203000 + j, 2))
+    insts = [L.l1ls_generate(*c[:6], rounds=c[6], storage=L.STORE_F32, stream=stream) for c in cfgs]
+    torch.cuda.synchronize()
+    kw = dict(max_iter=args.batch_max_iter, rel_gap_tol=args.batch_tol, check_every=args.check_every,
+              precision=L.F32, stream=stream)
+    L.l1ls_solve_fista_batched(insts[:8], **kw)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, reps, _ = L.l1ls_solve_fista_batched(insts, **kw)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    same, conv_p, iters_p = 0, 0, 0
+    xp = []
+    for inst in insts:
+        x1, r1, _ = L.l1ls_solve_fista(inst, polish=0, **kw)
+        xp.append(x1)
+        conv_p += r1["converged"] == 1
+        iters_p += r1["iterations"]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = sum(int(torch.equal(a, b)) for a, b in zip(xs, xp))
+    iters_b = sum(r["iterations"] for r in reps)
+    nnz = sum(i.info().nnz for i in insts)
+    line = {
+        "metric": "batched solves/sec (uneven instances in shared launches) vs the single-solve path",
+        "value": len(insts) / tb, "unit": "solves/s", "n_gpus": 1, "steps": len(insts), "warmup": 1,
+        "ms_per_step": tb * 1e3 / len(insts), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (instances from the device generator, seeds 1503035203000+j)",
+        "config": {"workload": "batched: %d instances, n log-uniform [2^10, 2^16], m = 2n, kappa in "
+                               "{1e2..1e6}, s = n/100, tau = 1, 2 Givens stages" % len(insts),
+                   "rel_gap_tol": args.batch_tol, "check_every": args.check_every,
+                   "max_iter": args.batch_max_iter, "total_nnz": nnz},
+        "extra": {"batched_s": tb, "plain_s": tp, "plain_solves_per_s": len(insts) / tp, "speedup": tp / tb,
+                  "converged_batched": sum(r["converged"] == 1 for r in reps), "converged_plain": conv_p,
+                  "iterations_batched": iters_b, "iterations_plain": iters_p,
+                  "bitwise_equal_results": same},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_path(args):
+    """64 tau values on one shared instance as one sparse-times-dense FISTA vs
+    64 single solves.  n = 2^16, m = 2^17, kappa = 1e4, two Givens stages,
+    s = n/100; tau log-spaced over [1e-3, 1] * ||A^T b||_inf.  Both stop at
+    the same per-column device gap test with the same cap."""
+    import numpy as np
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = 1 << args.path_log2n
+    m = 2 * n
+    inst = L.l1ls_generate(m, n, 1e4, max(1, n // 100), 1.0, 1503035203, rounds=2, stream=stream)
+    b = torch.from_numpy(L.device_to_numpy(inst.info().b_dev, m, np.float64)).cuda()
+    atb = torch.empty(n, dtype=torch.float64, device="cuda")
+    L.l1ls_apply(inst, 1, L.OP_STORED, L.F64, b, atb, stream=stream)
+    torch.cuda.synchronize()
+    tmax = float(atb.abs().max())
+    taus = list(np.geomspace(1e-3, 1.0, args.path_k) * tmax)
+    kw = dict(max_iter=args.path_max_iter, rel_gap_tol=args.batch_tol, check_every=args.check_every,
+              precision=L.F32, stream=stream)
+    L.l1ls_solve_fista_path(inst, taus[:4], **dict(kw, max_iter=64))   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, reps, _ = L.l1ls_solve_fista_path(inst, taus, **kw)
+    torch.cuda.synchronize()
+    tpath = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    conv_p, iters_p = 0, 0
+    for t in taus:
+        x1, r1, _ = L.l1ls_solve_fista(inst, tau=t, polish=0, **kw)
+        conv_p += r1["converged"] == 1
+        iters_p += r1["iterations"]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    gaps = []
+    for c in range(len(taus)):
+        gaps.append(L.l1ls_objective_gap(inst, taus[c], X[c].contiguous())[2])
+    line = {
+        "metric": "regularisation-path columns/sec (%d taus as one SpMM FISTA) vs single solves" % len(taus),
+        "value": len(taus) / tpath, "unit": "solves/s", "n_gpus": 1, "steps": len(taus), "warmup": 1,
+        "ms_per_step": tpath * 1e3 / len(taus), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (device generator, seed 1503035203)",
+        "config": {"workload": "path: n = 2^%d, m = 2n, kappa = 1e4, 2 Givens stages, s = n/100, %d taus "
+                               "log-spaced over [1e-3, 1] * ||A^T b||_inf" % (args.path_log2n, len(taus)),
+                   "rel_gap_tol": args.batch_tol, "check_every": args.check_every, "max_iter": args.path_max_iter},
+        "extra": {"path_s": tpath, "plain_s": tp, "speedup": tp / tpath,
+                  "converged_path": sum(r["converged"] == 1 for r in reps), "converged_plain": conv_p,
+                  "iterations_path_max": max(r["iterations"] for r in reps),
+                  "iterations_path_sum": sum(r["iterations"] for r in reps), "iterations_plain_sum": iters_p,
+                  "fp64_gap_max_converged": max([g for g, r in zip(gaps, reps) if r["converged"] == 1] or [0.0]),
+                  "fp64_gap_max": max(gaps)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_large(args):
+    """Memory-scale instance on one GPU: n = 2^26, m = 2^27, kappa = 1e6, two
+    Givens stages, s = n/1000, tau = 1.  FISTA iterations/s on the stored
+    FP32 CSR + CSC and on the matrix-free operator (rotations and sigma
+    applied on the fly), and CG-Newton (FP64 stored operator) Newton steps
+    and Hessian-vector products per second."""
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = 1 << args.large_log2n
+    m = 2 * n
+    kappa, s, tau, seed = 1e6, max(1, n // 1000), 1.0, 1503035202
+    t0 = time.perf_counter()
+    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=2, stream=stream)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    nnz = inst.info().nnz
+    print(json.dumps({"progress": "generated", "seconds": gen_s, "nnz": nnz}), file=sys.stderr, flush=True)
+
+    def fista_rate(op, steps, warmup):
+        fs = L.Fista(inst, precision=L.F32, rel_gap_tol=0.0, check_every=32, max_iter=warmup + steps,
+                     stream=stream, op=op)
+        fs.iterate(warmup)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fs.iterate(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        x = fs.get_x()
+        fs.destroy()
+        return steps / dt, x
+
+    stored, x_s = fista_rate(L.OP_STORED, args.steps, args.warmup)
+    print(json.dumps({"progress": "stored", "iters_per_s": stored}), file=sys.stderr, flush=True)
+    mfree, x_m = fista_rate(L.OP_MATRIX_FREE, args.steps, args.warmup)
+    print(json.dumps({"progress": "matrix_free", "iters_per_s": mfree}), file=sys.stderr, flush=True)
+    same = float((x_s - x_m).abs().max())
+    t = time.perf_counter()
+    xn, rn, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, stream=stream)
+    torch.cuda.synchronize()
+    tn = time.perf_counter() - t
+    P, D, gap = L.l1ls_objective_gap(inst, tau, xn)
+    k1, k2 = algorithmic_bytes(m, n, nnz)
+    line = {
+        "metric": "FISTA iters/sec on the memory-scale instance, stored vs matrix-free; CG-Newton steps/sec",
+        "value": stored, "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / stored, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (device generator, seed %d)" % seed,
+        "config": {"workload": "memory-scale instance: n = 2^%d, m = 2n, kappa = 1e6, 2 Givens stages, "
+                               "s = n/1000, tau = 1" % args.large_log2n, "nnz": nnz},
+        "extra": {"generate_s": gen_s, "stored_iters_per_s": stored,
+                  "stored_gbs_algorithmic": (k1 + k2) * stored / 1e9,
+                  "matrix_free_iters_per_s": mfree, "matrix_free_gbs_algorithmic": mf_bytes(m, n) * mfree / 1e9,
+                  "matrix_free_speedup": mfree / stored,
+                  "stored_vs_matrix_free_max_abs_diff": same,
+                  "cg_newton": {"newton_steps": rn["iterations"], "pcg_iterations": rn["inner"],
+                                "seconds": tn, "newton_steps_per_s": rn["iterations"] / tn,
+                                "hessian_products_per_s": rn["inner"] / tn, "fp64_rel_gap": gap,
+                                "precision": "f64"}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,8 +518,18 @@ def main():
     for d in ("kt", "fetch", "write", "copyf", "copyw"):
         ap.add_argument(f"--{d}")
     ap.add_argument("--out", default=PROFILE_SUMMARY)
-    ap.add_argument("--workload", default="fista", choices=["fista", "serve"],
-                    help="fista: the single large instance (default); serve: the request stream")
+    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large"],
+                    help="fista: the single large instance (default); serve: the request stream; "
+                         "batched: 256 uneven instances; path: 64 taus on one instance; "
+                         "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton")
+    ap.add_argument("--large-log2n", type=int, default=26)
+    ap.add_argument("--newton-steps", type=int, default=3)
+    ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--batch-tol", type=float, default=1e-5)
+    ap.add_argument("--batch-max-iter", type=int, default=20000)
+    ap.add_argument("--path-log2n", type=int, default=16)
+    ap.add_argument("--path-k", type=int, default=64)
+    ap.add_argument("--path-max-iter", type=int, default=4000)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--serve-tol", type=float, default=1e-6)
@@ -339,6 +540,7 @@ def main():
     ap.add_argument("--serve-log2n-lo", type=int, default=10)
     ap.add_argument("--serve-log2n-hi", type=int, default=22)
     ap.add_argument("--rate-mults", type=float, nargs="+", default=[0.7])
+    ap.add_argument("--serve-dump", default=None, help="append per-request rows (JSON lines) to this file")
     ap.add_argument("--plain-max-mult", type=float, default=1.0,
                     help="skip the real-time plain run above this rate multiple (its queue grows without bound)")
     args = ap.parse_args()
@@ -359,10 +561,13 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
-    if args.workload == "serve":
-        if args.check_every == 32 and "--check-every" not in sys.argv:
+    if args.workload != "fista":
+        if "--check-every" not in sys.argv:
             args.check_every = 16
-        bench_serve(args)
+        if args.workload == "large" and "--steps" not in sys.argv:
+            args.steps, args.warmup = 50, 5
+        {"serve": bench_serve, "batched": bench_batched, "path": bench_path,
+         "large": bench_large}[args.workload](args)
         return
 
     import torch

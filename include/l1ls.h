@@ -264,29 +264,37 @@ void l1ls_batch_destroy(l1ls_batch* batch);
  * operator, vectors and the slot's iterates): the admission footprint. */
 size_t l1ls_instance_footprint(const l1ls_instance* inst);
 /*
- * Serving: a FIFO queue of solve requests in front of a batch (continuous
+ * Serving: a FIFO queue of solve requests in front of batches (continuous
  * batching).  A request names an instance of Procedure IGen (section 3.1;
  * the arguments of l1ls_generate, with the stage-order layout and FP32
- * storage) and its own tolerance and iteration cap.  Each tick
- *   1. admits queued requests in arrival order while a slot is free and the
- *      estimated footprint of the head request (16 nonzeros per column at two
- *      stages, 4 at one) fits hbm_budget_bytes (0: no budget); admission
- *      generates the instance on the device;
- *   2. enqueues iters_per_tick FISTA iterations of every resident request;
+ * storage) and its own tolerance and iteration cap.  Requests are grouped
+ * by size (n < 2^14, n < 2^18, larger), with a FIFO queue per group; each
+ * group's residents are a batch on a stream of its own, so small requests
+ * iterate at their own rate while large ones run.  The largest group holds
+ * one resident at a time (its iterations alone saturate HBM).  Each tick
+ *   1. enqueues iterations of every group: the slowest at least
+ *      iters_per_tick, the others as many as fit the same time (multiples of
+ *      check_every);
+ *   2. admits, oldest first, group-queue heads while fewer than max_slots
+ *      are resident, the group is below its limit and the head's estimated
+ *      footprint (l1ls_request_footprint) fits hbm_budget_bytes (0: no
+ *      budget); admission generates the instance on the device;
  *   3. retires requests whose gap test passed, whose iterate went
  *      non-finite, or which reached max_iter: the iterate (FP64, original
  *      order) moves to a result buffer held until l1ls_server_take, and the
  *      slot and instance are freed.
- * A result is bit-identical to the one the request would get alone in the
- * server (the batch's per-slot independence).  report.seconds of a taken
- * result is the time from submission to retirement (host steady clock).
- *   create: max_slots >= 1, iters_per_tick >= 1, check_every >= 1 (gap test
- *           period of every request), stream (NULL: default).
+ * A result is bit-identical to the one the request gets alone in the server,
+ * and to l1ls_solve_fista (FP32, the same tolerance and check period) on the
+ * same instance.  report.seconds of a taken result is the time from
+ * submission to retirement (host steady clock).
+ *   create: 1 <= max_slots <= 65535, iters_per_tick >= 1, check_every >= 1
+ *           (gap test period of every request); stream (NULL: default)
+ *           orders the copies of take.
  *   submit: L1LS_E_ARG for an invalid request (the checks of l1ls_generate,
  *           rounds 1 or 2, rel_gap_tol > 0, max_iter > 0), L1LS_E_NOMEM if its
  *           estimate alone exceeds the budget; *id_out is its id (0, 1, ...).
  *   tick:   *admitted / *completed (either may be NULL) count this tick's
- *           admissions and retirements.  Synchronises the stream.
+ *           admissions and retirements.  Returns after the tick's work.
  *   completed: copies up to cap ids retired since the last call into ids,
  *           oldest first; returns how many.
  *   take:   copies the result of a retired id to x_out_dev (n FP64; NULL to

@@ -1,18 +1,33 @@
 // Serving scheduler: continuous batching of l1-LS solve requests on one GPU.
 //
 // Requests (instance parameters of Procedure IGen, section 3.1, and a
-// relative-gap tolerance) wait in a FIFO queue.  Each tick:
-//  1. admission: while the head of the queue fits the HBM budget (its
-//     footprint estimated before generation from the bound of 4^rounds
-//     nonzeros per column of A = Q Sigma G^T, eq. (16)) and a batch slot is
-//     free, generate its instance on the device and add it to the batch;
-//  2. run `iters_per_tick` FISTA iterations of every resident slot (one
-//     shared launch per pass, see batch.hip);
-//  3. retire the slots whose gap test passed (or hit their iteration cap):
-//     copy the iterate to a result buffer, free the slot and the instance.
-// Iterates stay on the device from admission to retirement.
+// relative-gap tolerance) wait in one FIFO queue per size class (n < 2^14,
+// n < 2^18, larger).  Resident requests live in one batch per class, each
+// on its own stream, so a small instance advances at its own iteration rate
+// alongside a large one instead of in lockstep with it.  The largest class
+// holds one request at a time: its iterations already saturate HBM, so
+// sharing the device among several would only delay the first to finish.
+// Each tick:
+//  1. enqueue iterations of every class with residents: the slowest class
+//     runs at least `iters_per_tick` iterations (and the tick at least
+//     kMinTickS), the others as many as fit the same time (estimated from
+//     bytes per iteration with a launch floor), in multiples of the
+//     gap-check period;
+//  2. admission, while those run: repeatedly take the oldest class-queue
+//     head that fits (a slot free, its class below its resident limit, its
+//     footprint, estimated before generation from the bound of 4^rounds
+//     nonzeros per column of A = Q Sigma G^T, eq. (16), within the HBM
+//     budget), generate its instance on the device (own stream) and add it
+//     to its class's batch; it starts iterating in the next tick;
+//  3. retire the slots whose gap test passed, whose iterate went
+//     non-finite, or which reached their cap: copy the iterate to a result
+//     buffer, free the slot and the instance.
+// A request's arithmetic depends only on its own instance and iteration
+// count (the batch's per-slot independence), so a result is the same in any
+// mix, any class schedule and any tick length.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <unordered_map>
@@ -20,7 +35,24 @@
 
 #include "common.hpp"
 
+size_t batch_slot_bytes(int64_t m, int64_t n);
+
+namespace {
+
 using ServeClock = std::chrono::steady_clock;
+
+constexpr int kClasses = 3;
+constexpr double kIterFloorS = 9e-6;   // launch-bound floor of one batched iteration
+constexpr double kBytesPerS = 4.5e12;  // sustained rate of the SpMV pair
+constexpr double kMinTickS = 1e-3;     // shortest tick (host work per tick is ~0.1 ms)
+constexpr int kMaxTickMultiple = 64;   // cap on a class's iterations per tick, in iters_per_tick
+
+constexpr int32_t kClassLimit[kClasses] = {65535, 65535, 1};  // residents per class
+
+int class_of(int64_t n) { return n < (1 << 14) ? 0 : (n < (1 << 18) ? 1 : 2); }
+
+// Algorithmic bytes of one FISTA iteration of an instance (FP32, int32).
+double iter_bytes(int64_t m, int64_t n, int64_t nnz) { return 16.0 * nnz + 24.0 * m + 20.0 * n; }
 
 struct ServeReq {
     int64_t id;
@@ -32,6 +64,8 @@ struct ServeSlot {
     int64_t id = -1;
     l1ls_instance* inst = nullptr;
     int64_t max_iter = 0;
+    size_t est = 0;
+    double bytes = 0.0;
     ServeClock::time_point submitted;
 };
 
@@ -41,21 +75,27 @@ struct ServeDone {
     l1ls_report rep;
 };
 
-struct l1ls_server {
-    int32_t max_slots = 0, iters_per_tick = 0;
-    size_t budget = 0, used = 0;
-    hipStream_t stream = nullptr;
+struct ServeClass {
     l1ls_batch* batch = nullptr;
-    int64_t next_id = 0;
-    std::deque<ServeReq> queue;
-    std::vector<ServeSlot> slots;
-    std::vector<size_t> est;
-    std::unordered_map<int64_t, ServeDone> done;
-    std::vector<int64_t> fresh;  // completed since the last l1ls_server_completed call
-    int64_t ticks = 0;
+    hipStream_t stream = nullptr;
+    std::vector<ServeSlot> slots;  // by batch slot
+    int32_t resident = 0;
+    double bytes = 0.0;  // per-iteration bytes of the residents
 };
 
-size_t batch_slot_bytes(int64_t m, int64_t n);
+}  // namespace
+
+struct l1ls_server {
+    int32_t max_slots = 0, iters_per_tick = 0, check_every = 0;
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;  // caller's stream: result copies
+    hipStream_t gen_stream = nullptr;
+    ServeClass cls[kClasses];
+    int64_t next_id = 0;
+    std::deque<ServeReq> queue[kClasses];
+    std::unordered_map<int64_t, ServeDone> done;
+    std::vector<int64_t> fresh;  // retired since the last l1ls_server_completed call
+};
 
 namespace {
 
@@ -67,34 +107,55 @@ size_t estimate_footprint(const l1ls_request& r) {
 }
 
 bool valid_request(const l1ls_request& r) {
-    return r.n >= 2 && r.m >= r.n && r.m % 2 == 0 && r.n % 2 == 0 && r.s >= 0 && r.s <= r.n && r.kappa >= 1.0 &&
-           r.tau > 0.0 && (r.rounds == 1 || r.rounds == 2) && r.rel_gap_tol > 0.0 && r.max_iter > 0;
+    return r.n >= 2 && r.m >= r.n && r.m % 2 == 0 && r.n % 2 == 0 && r.m < ((int64_t)1 << 31) && r.s >= 0 &&
+           r.s <= r.n && r.kappa >= 1.0 && is_finite(r.kappa) && r.tau > 0.0 && is_finite(r.tau) &&
+           (r.rounds == 1 || r.rounds == 2) && r.rel_gap_tol > 0.0 && r.max_iter > 0;
+}
+
+void destroy_streams(l1ls_server* S) {
+    for (ServeClass& c : S->cls)
+        if (c.stream) (void)hipStreamDestroy(c.stream);
+    if (S->gen_stream) (void)hipStreamDestroy(S->gen_stream);
+}
+
+int32_t total_resident(const l1ls_server* S) {
+    int32_t r = 0;
+    for (const ServeClass& c : S->cls) r += c.resident;
+    return r;
 }
 
 }  // namespace
 
 extern "C" l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_bytes, int32_t iters_per_tick,
                                           int32_t check_every, void* stream, l1ls_server** out) {
-    if (!out || max_slots < 1 || iters_per_tick < 1 || check_every < 1) return L1LS_E_ARG;
+    if (!out || max_slots < 1 || max_slots > 65535 || iters_per_tick < 1 || check_every < 1) return L1LS_E_ARG;
     *out = nullptr;
-    l1ls_solve_opts o;
-    l1ls_solve_opts_default(&o);
-    o.precision = L1LS_F32;
-    o.op = L1LS_OP_STORED;
-    o.check_every = check_every;
-    o.rel_gap_tol = 1e-6;  // per slot tolerances are set at admission
-    o.stream = stream;
     l1ls_server* S = new l1ls_server();
     S->max_slots = max_slots;
     S->iters_per_tick = iters_per_tick;
+    S->check_every = check_every;
     S->budget = hbm_budget_bytes;
     S->stream = (hipStream_t)stream;
-    S->slots.assign(max_slots, ServeSlot{});
-    S->est.assign(max_slots, 0);
-    l1ls_status st = l1ls_batch_create(max_slots, 0, &o, &S->batch);
-    if (st != L1LS_OK) {
+    auto fail = [&](l1ls_status st) {
+        for (ServeClass& c : S->cls)
+            if (c.batch) l1ls_batch_destroy(c.batch);
+        destroy_streams(S);
         delete S;
         return st;
+    };
+    if (hipStreamCreateWithFlags(&S->gen_stream, hipStreamNonBlocking) != hipSuccess) return fail(L1LS_E_HIP);
+    for (ServeClass& c : S->cls) {
+        if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return fail(L1LS_E_HIP);
+        l1ls_solve_opts o;
+        l1ls_solve_opts_default(&o);
+        o.precision = L1LS_F32;
+        o.op = L1LS_OP_STORED;
+        o.check_every = check_every;
+        o.rel_gap_tol = 1e-6;  // every slot gets its request's own tolerance
+        o.stream = c.stream;
+        l1ls_status st = l1ls_batch_create(max_slots, 0, &o, &c.batch);
+        if (st != L1LS_OK) return fail(st);
+        c.slots.assign(max_slots, ServeSlot{});
     }
     *out = S;
     return L1LS_OK;
@@ -107,7 +168,7 @@ extern "C" l1ls_status l1ls_server_submit(l1ls_server* S, const l1ls_request* r,
     q.id = S->next_id++;
     q.r = *r;
     q.submitted = ServeClock::now();
-    S->queue.push_back(q);
+    S->queue[class_of(r->n)].push_back(q);
     *id_out = q.id;
     return L1LS_OK;
 }
@@ -115,67 +176,98 @@ extern "C" l1ls_status l1ls_server_submit(l1ls_server* S, const l1ls_request* r,
 extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32_t* completed) {
     if (!S) return L1LS_E_ARG;
     int32_t na = 0, nc = 0;
-    // 1. admission (FIFO, by footprint and free slots)
-    while (!S->queue.empty()) {
-        const l1ls_request& r = S->queue.front().r;
-        const size_t fp = estimate_footprint(r);
-        if (S->budget && S->used + fp > S->budget) break;
-        int slot = -1;
-        for (int q = 0; q < S->max_slots; ++q)
-            if (S->slots[q].id < 0) {
-                slot = q;
-                break;
-            }
-        if (slot < 0) break;
+    const int64_t ce = S->check_every;
+    // 1. iterations of the resident classes, sized to one common tick length
+    double tmax = 0.0;
+    double tc[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+        tc[c] = std::max(kIterFloorS, S->cls[c].bytes / kBytesPerS);
+        if (S->cls[c].resident) tmax = std::max(tmax, tc[c]);
+    }
+    const double tick_s = std::max(kMinTickS, tmax * S->iters_per_tick);
+    const int64_t lo = ((S->iters_per_tick + ce - 1) / ce) * ce;
+    const int64_t hi = std::max<int64_t>(lo, ((int64_t)kMaxTickMultiple * S->iters_per_tick / ce) * ce);
+    for (int c = 0; c < kClasses; ++c) {
+        ServeClass& C = S->cls[c];
+        if (!C.resident) continue;
+        int64_t it = (int64_t)std::floor(tick_s / tc[c] / (double)ce) * ce;
+        it = std::min(std::max(it, lo), hi);
+        L1LS_TRY(l1ls_batch_iterate(C.batch, it));
+    }
+    // 2. admission: the oldest class-queue head that fits, repeatedly, while those run
+    for (;;) {
+        int pick = -1;
+        for (int c = 0; c < kClasses; ++c) {
+            if (S->queue[c].empty() || S->cls[c].resident >= kClassLimit[c]) continue;
+            if (total_resident(S) >= S->max_slots) continue;
+            const ServeReq& h = S->queue[c].front();
+            if (S->budget && S->used + estimate_footprint(h.r) > S->budget) continue;
+            if (pick < 0 || h.id < S->queue[pick].front().id) pick = c;
+        }
+        if (pick < 0) break;
+        const ServeReq q = S->queue[pick].front();
+        const l1ls_request& r = q.r;
+        ServeClass& C = S->cls[pick];
         l1ls_gen_opts go;
         go.rounds = r.rounds;
         go.storage = L1LS_STORE_F32;
-        go.stream = S->stream;
+        go.stream = S->gen_stream;
         go.layout = L1LS_LAYOUT_STAGE;
         l1ls_instance* inst = nullptr;
         L1LS_TRY(l1ls_generate_ex(r.m, r.n, r.kappa, r.s, r.tau, r.seed, &go, &inst));
         int32_t bslot = -1;
-        l1ls_status st = l1ls_batch_add_ex(S->batch, inst, r.tau, r.rel_gap_tol, r.max_iter, &bslot);
+        l1ls_status st = l1ls_batch_add_ex(C.batch, inst, r.tau, r.rel_gap_tol, r.max_iter, &bslot);
         if (st != L1LS_OK) {
             l1ls_free(inst);
             return st;
         }
-        S->slots[bslot].id = S->queue.front().id;
-        S->slots[bslot].inst = inst;
-        S->slots[bslot].max_iter = r.max_iter;
-        S->slots[bslot].submitted = S->queue.front().submitted;
-        S->est[bslot] = fp;
+        const size_t fp = estimate_footprint(r);
+        ServeSlot& sl = C.slots[bslot];
+        sl.id = q.id;
+        sl.inst = inst;
+        sl.max_iter = r.max_iter;
+        sl.est = fp;
+        sl.bytes = iter_bytes(inst->m, inst->n, inst->nnz);
+        sl.submitted = q.submitted;
+        C.resident += 1;
+        C.bytes += sl.bytes;
         S->used += fp;
-        S->queue.pop_front();
+        S->queue[pick].pop_front();
         ++na;
     }
-    // 2. iterations of the resident set
-    L1LS_TRY(l1ls_batch_iterate(S->batch, S->iters_per_tick));
-    ++S->ticks;
     // 3. retirement
     std::vector<l1ls_report> reps(S->max_slots);
-    L1LS_TRY(l1ls_batch_poll(S->batch, reps.data(), nullptr));
-    for (int q = 0; q < S->max_slots; ++q) {
-        ServeSlot& sl = S->slots[q];
-        if (sl.id < 0) continue;
-        const l1ls_report& rp = reps[q];
-        if (rp.converged == 0 && rp.iterations < sl.max_iter) continue;  // still iterating
-        ServeDone d;
-        d.n = sl.inst->n;
-        d.rep = rp;
-        d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - sl.submitted).count();
-        void* p = nullptr;
-        HIP_TRY(hipMalloc(&p, d.n * sizeof(double)));
-        d.x = (double*)p;
-        L1LS_TRY(l1ls_batch_get_x(S->batch, q, d.x));
-        L1LS_TRY(l1ls_batch_remove(S->batch, q));
-        l1ls_free(sl.inst);
-        S->used -= S->est[q];
-        S->est[q] = 0;
-        S->done[sl.id] = d;
-        S->fresh.push_back(sl.id);
-        sl = ServeSlot{};
-        ++nc;
+    for (ServeClass& C : S->cls) {
+        if (!C.resident) continue;
+        L1LS_TRY(l1ls_batch_poll(C.batch, reps.data(), nullptr));
+        for (int q = 0; q < S->max_slots; ++q) {
+            ServeSlot& sl = C.slots[q];
+            if (sl.id < 0) continue;
+            const l1ls_report& rp = reps[q];
+            if (rp.converged == 0 && rp.iterations < sl.max_iter) continue;  // still iterating
+            ServeDone d;
+            d.n = sl.inst->n;
+            d.rep = rp;
+            void* p = nullptr;
+            HIP_TRY(hipMalloc(&p, d.n * sizeof(double)));
+            d.x = (double*)p;
+            l1ls_status st = l1ls_batch_get_x(C.batch, q, d.x);
+            if (st == L1LS_OK) st = l1ls_batch_remove(C.batch, q);
+            if (st != L1LS_OK) {
+                (void)hipFree(p);
+                return st;
+            }
+            d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - sl.submitted).count();
+            l1ls_free(sl.inst);
+            S->used -= sl.est;
+            C.resident -= 1;
+            C.bytes -= sl.bytes;
+            if (C.resident == 0) C.bytes = 0.0;
+            S->done[sl.id] = d;
+            S->fresh.push_back(sl.id);
+            sl = ServeSlot{};
+            ++nc;
+        }
     }
     if (admitted) *admitted = na;
     if (completed) *completed = nc;
@@ -206,10 +298,12 @@ extern "C" l1ls_status l1ls_server_take(l1ls_server* S, int64_t id, double* x_ou
 
 extern "C" l1ls_status l1ls_server_stats(l1ls_server* S, int32_t* queued, int32_t* resident, size_t* used_bytes) {
     if (!S) return L1LS_E_ARG;
-    int32_t res = 0;
-    for (const ServeSlot& s : S->slots) res += (s.id >= 0);
-    if (queued) *queued = (int32_t)S->queue.size();
-    if (resident) *resident = res;
+    if (queued) {
+        size_t qn = 0;
+        for (const auto& q : S->queue) qn += q.size();
+        *queued = (int32_t)qn;
+    }
+    if (resident) *resident = total_resident(S);
     if (used_bytes) *used_bytes = S->used;
     return L1LS_OK;
 }
@@ -220,10 +314,13 @@ extern "C" size_t l1ls_request_footprint(const l1ls_request* r) {
 
 extern "C" void l1ls_server_destroy(l1ls_server* S) {
     if (!S) return;
-    (void)hipStreamSynchronize(S->stream);
-    for (ServeSlot& s : S->slots)
-        if (s.inst) l1ls_free(s.inst);
+    for (ServeClass& C : S->cls) {
+        if (C.stream) (void)hipStreamSynchronize(C.stream);
+        for (ServeSlot& s : C.slots)
+            if (s.inst) l1ls_free(s.inst);
+        if (C.batch) l1ls_batch_destroy(C.batch);
+    }
     for (auto& kv : S->done) (void)hipFree(kv.second.x);
-    l1ls_batch_destroy(S->batch);
+    destroy_streams(S);
     delete S;
 }

@@ -57,18 +57,22 @@ def _serve(reqs, max_slots, budget=0, stagger=0):
 
 
 def test_served_result_same_alone_and_in_mix():
-    print("\n[case] serve mix of 7 requests, 3 slots, staggered arrivals", flush=True)
-    mix, peak = _serve(REQS, max_slots=3, stagger=3)
-    assert peak == 3
+    print("\n[case] serve mix of 7 requests: all at once into 3 slots", flush=True)
+    burst, peak_b = _serve(REQS, max_slots=3)
+    assert peak_b == 3                   # full, with later requests admitted as slots free up
+    print("[case] serve mix of 7 requests: one arrival per tick, 7 slots", flush=True)
+    stag, peak_s = _serve(REQS, max_slots=7, stagger=1)
+    assert peak_s >= 2
     for q, req in enumerate(REQS):
         print(f"[case] serve alone request {q} {req}", flush=True)
         alone, _ = _serve([req], max_slots=1)
         xa, ra = alone[0]
-        xm, rm = mix[q]
-        assert rm["converged"] == ra["converged"] == 1, (q, rm, ra)
-        assert rm["iterations"] == ra["iterations"], (q, rm["iterations"], ra["iterations"])
-        assert rm["rel_gap"] == ra["rel_gap"] and rm["rel_gap"] <= req[7]
-        assert torch.equal(xa, xm), q
+        for mix in (burst, stag):
+            xm, rm = mix[q]
+            assert rm["converged"] == ra["converged"] == 1, (q, rm, ra)
+            assert rm["iterations"] == ra["iterations"], (q, rm["iterations"], ra["iterations"])
+            assert rm["rel_gap"] == ra["rel_gap"] and rm["rel_gap"] <= req[7]
+            assert torch.equal(xa, xm), q
 
 
 def test_served_result_equals_single_path():
@@ -145,4 +149,28 @@ def test_latency_report_is_submission_to_retirement():
     _, rep = S.take(rid, want_x=False)
     assert 0 < rep["seconds"] <= wall + 0.05
     assert np.isfinite(rep["primal"]) and rep["converged"] == 1
+    S.destroy()
+
+
+def test_largest_class_holds_one_request_and_small_ones_overtake():
+    big = (1 << 19, 1 << 18, 1e3, (1 << 18) // 100, 1.0, 301, 2)
+    small = (2048, 1024, 1e2, 10, 1.0, 302, 2)
+    S = L.Server(8, iters_per_tick=PER_TICK, check_every=CHECK)
+    b0 = S.submit(*big[:6], rounds=2, rel_gap_tol=1e-14, max_iter=96)
+    b1 = S.submit(*big[:5], 303, rounds=2, rel_gap_tol=1e-14, max_iter=96)
+    s0 = S.submit(*small[:6], rounds=2, rel_gap_tol=1e-6, max_iter=CAP)
+    order, peak = [], 0
+    for _ in range(1000):
+        S.tick()
+        peak = max(peak, S.stats()[1])
+        for rid in S.completed():
+            _, rep = S.take(rid, want_x=False)
+            order.append(rid)
+            if rid in (b0, b1):
+                assert rep["iterations"] == 96 and rep["converged"] == 0
+        if len(order) == 3:
+            break
+    assert peak == 2                              # one large + the small one
+    assert order.index(s0) < order.index(b1)      # the small request did not wait for the second large one
+    assert order.index(b0) < order.index(b1)      # FIFO within the large class
     S.destroy()
