@@ -107,6 +107,29 @@ def write_profile_summary(args):
     print("\n".join(lines))
 
 
+def write_stats_summary(args):
+    """Top kernels of a rocprofv3 --kernel-trace --stats run as a short text table."""
+    import csv
+    rows = None
+    for root, _, files in os.walk(args.kt):
+        for f in files:
+            if f.endswith("kernel_stats.csv"):
+                rows = list(csv.DictReader(open(os.path.join(root, f))))
+    if rows is None:
+        raise SystemExit(f"no *kernel_stats.csv under {args.kt}")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 --kernel-trace --stats, kernel statistics (top entries)",
+             f"# command: {args.stats_command}",
+             f"# workload: {args.stats_title}",
+             f"{'kernel':<62}{'calls':>7}{'avg_us':>10}{'min_us':>10}{'max_us':>10}{'pct':>7}"]
+    for r in rows[:args.stats_top]:
+        lines.append(f"{r['Name'][:60]:<62}{int(r['Calls']):>7}{float(r['AverageNs']) / 1e3:>10.2f}"
+                     f"{float(r['MinNs']) / 1e3:>10.2f}{float(r['MaxNs']) / 1e3:>10.2f}{float(r['Percentage']):>7.2f}")
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def algorithmic_bytes(m, n, nnz, es=4, ie=4):
     """Bytes one launch of each pass must move at minimum (FP32 values, int32 indices).
 
@@ -517,6 +540,11 @@ def main():
                     help="summarise rocprofv3 CSV directories (--kt, --fetch, --write, --copyf, --copyw) into --out")
     for d in ("kt", "fetch", "write", "copyf", "copyw"):
         ap.add_argument(f"--{d}")
+    ap.add_argument("--stats-summary", action="store_true",
+                    help="write the top kernels of the rocprofv3 --stats run in --kt to --out")
+    ap.add_argument("--stats-title", default="")
+    ap.add_argument("--stats-command", default="")
+    ap.add_argument("--stats-top", type=int, default=14)
     ap.add_argument("--out", default=PROFILE_SUMMARY)
     ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large"],
                     help="fista: the single large instance (default); serve: the request stream; "
@@ -546,6 +574,9 @@ def main():
     args = ap.parse_args()
     if args.profile_summary:
         write_profile_summary(args)
+        return
+    if args.stats_summary:
+        write_stats_summary(args)
         return
     if args.copy_calibration:
         import torch
