@@ -122,8 +122,8 @@ struct l1ls_fista {
     void* x[2] = {nullptr, nullptr};  // x_k lives in x[k & 1]
     void* rx = nullptr;
     void* ry = nullptr;
-    void* wbuf = nullptr;      // matrix-free: Sigma G^T x in m-stage order (m)
-    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in n-stage order (n)
+    void* wbuf = nullptr;      // matrix-free: Sigma G^T x in n-stage order (n)
+    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in m-stage order (m)
     bool mf = false;           // matrix-free operator (stage order)
     const int32_t* col_of = nullptr;   // position -> original index of x
     const int32_t* col_pos = nullptr;  // original index -> position
@@ -345,14 +345,12 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if ((st = F->arena.alloc(&rx, I->m * es)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&ry, I->m * es)) != L1LS_OK) return fail(st);
     if (F->mf) {
-        // Sigma G^T x in m-stage order: zero at the inactive positions, which
-        // the n-side pass never writes; Sigma^T Q^T r_y in n-stage order: all
-        // positions rewritten by every transpose pass.
+        // Sigma G^T x in n-stage order; Sigma^T Q^T r_y in m-stage order (its
+        // inactive positions are never read)
         unsigned char* wb = nullptr;
         unsigned char* tb = nullptr;
-        if ((st = F->arena.alloc(&wb, I->m * es)) != L1LS_OK) return fail(st);
-        if ((st = F->arena.alloc(&tb, I->n * es)) != L1LS_OK) return fail(st);
-        if (hipMemsetAsync(wb, 0, I->m * es, F->stream) != hipSuccess) return fail(L1LS_E_HIP);
+        if ((st = F->arena.alloc(&wb, I->n * es)) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&tb, I->m * es)) != L1LS_OK) return fail(st);
         F->wbuf = wb;
         F->tbuf = tb;
     }

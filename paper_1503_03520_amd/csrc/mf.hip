@@ -8,14 +8,19 @@
 // links n-position a and m-position i when pi_n(a) = pi_m(i):
 //   emb[i] = a (or -1 when pi_m(i) >= n),  inv[a] = i,
 //   sig[i] = sigma_{pi_m(i)} (0 when inactive).
-// A x   = Q (Sigma (G^T x)):  pass 1 (n side) w = G^T x;
-//                             pass 2 (m side) z_i = sig_i w_{emb_i}, r = Q z,
-//                             fused with the residual/momentum epilogue.
-// A^T r = G (Sigma^T (Q^T r)): pass 1 (m side) v_i = sig_i (Q^T r)_i;
-//                             pass 2 (n side) t_a = v_{inv_a}, g = G t,
-//                             fused with the gradient step, prox, momentum.
-// Each thread owns one rotation pair of the last stage it applies and reads
-// the 4 consecutive positions that feed it.
+// A x   = Q (Sigma (G^T x)):  pass 1 (n side) w_a = sigma_a (G^T x)_a, written
+//                             in n order; pass 2 (m side) gathers
+//                             z_i = w_{emb_i}, r = Q z, fused with the
+//                             residual/momentum epilogue.
+// A^T r = G (Sigma^T (Q^T r)): pass 1 (m side) v_i = sig_i (Q^T r)_i, written
+//                             in m order; pass 2 (n side) gathers
+//                             t_a = v_{inv_a}, g = G t, fused with the
+//                             gradient step, prox, momentum.
+// The embedding is a random permutation, so its accesses are random: they
+// are made as gathers (one per position, staged in LDS for the stencil that
+// follows), never as scattered stores.  Each thread owns one rotation pair
+// of the last stage it applies and reads the 4 consecutive positions that
+// feed it.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -58,62 +63,77 @@ __device__ __forceinline__ void rot(CS<T> r, T zf, T zg, bool transpose, T& of, 
     }
 }
 
-// z = Sigma G^T x in m-stage order: the n-side stages are applied locally,
-// then sigma_a w_a is written to m-position inv[a] (a permutation onto the
-// active m-positions; inactive ones keep the 0 they were initialised with).
-// R = 2: G^T = S_1^T S_2^T (S_2^T first); thread k handles stage-1 pair
-// (2k, 2k+1) from x at 2k-1 .. 2k+2.
+// Position p + q of a side of N positions, reduced mod N (q >= 0 small).
+__device__ __forceinline__ int64_t ring(int64_t p, int64_t N) {
+    if (p >= N) p -= N;
+    if (p >= N) p %= N;  // only for sides shorter than a block's reach
+    return p;
+}
+
+// w = Sigma_n G^T x in n-stage order (sigma at n-positions, 0 where the
+// column has no sigma).  R = 2: G^T = S_1^T S_2^T (S_2^T first); thread k
+// handles stage-1 pair (2k, 2k+1) from x at 2k-1 .. 2k+2.
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ zm, MfTabs<T> tb,
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ w, MfTabs<T> tb,
                                                        const GapState* __restrict__ gs) {
     if (gs && gs->done) return;
     const int64_t n = tb.n, np = n / 2;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
-        T z0 = x[2 * k], z1 = x[2 * k + 1];
-        if (R == 2) {
-            const T xm = x[wrap(2 * k - 1, n)], xp = x[wrap(2 * k + 2, n)];
-            T a, b;
-            rot(cs_of(tb.csn[1], wrap(k - 1, np)), xm, z0, true, a, b);  // 2k is second of stage-2 pair k-1
-            const T z0n = b;
-            rot(cs_of(tb.csn[1], k), z1, xp, true, a, b);                // 2k+1 is first of stage-2 pair k
-            z0 = z0n;
-            z1 = a;
-        }
-        T o0, o1;
-        rot(cs_of(tb.csn[0], k), z0, z1, true, o0, o1);
-        const int32_t i0 = tb.inv[2 * k], i1 = tb.inv[2 * k + 1];
-        zm[i0] = tb.sig_n[2 * k] * o0;
-        zm[i1] = tb.sig_n[2 * k + 1] * o1;
+    const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
+    if (k >= np) return;
+    T z0 = x[2 * k], z1 = x[2 * k + 1];
+    if (R == 2) {
+        const T xm = x[wrap(2 * k - 1, n)], xp = x[wrap(2 * k + 2, n)];
+        T a, b;
+        rot(cs_of(tb.csn[1], wrap(k - 1, np)), xm, z0, true, a, b);  // 2k is second of stage-2 pair k-1
+        const T z0n = b;
+        rot(cs_of(tb.csn[1], k), z1, xp, true, a, b);                // 2k+1 is first of stage-2 pair k
+        z0 = z0n;
+        z1 = a;
     }
+    T o0, o1;
+    rot(cs_of(tb.csn[0], k), z0, z1, true, o0, o1);
+    w[2 * k] = tb.sig_n[2 * k] * o0;
+    w[2 * k + 1] = tb.sig_n[2 * k + 1] * o1;
 }
 
-// r_x = Q z - b, r_y = (1+beta) r_x - beta r_x,prev, z read in m-stage order.
-// R = 2: Q = S~_2 S~_1 (S~_1 first); thread k writes stage-2 pair
+// r_x = Q z - b, r_y = (1+beta) r_x - beta r_x,prev, where z_i = w[emb[i]]
+// (0 at inactive m-positions) is gathered once per position into LDS: a
+// workgroup owns pairs k0 .. k0+255 and the positions 2k0 .. 2k0+513 they
+// read.  R = 2: Q = S~_2 S~_1 (S~_1 first); thread k writes stage-2 pair
 // (2k+1, 2k+2 mod m) from z at 2k .. 2k+3.  R = 1: stage-1 pair (2k, 2k+1).
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restrict__ zm, const T* __restrict__ b,
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restrict__ w, const T* __restrict__ b,
                                                                T* __restrict__ rx, T* __restrict__ ry, T beta,
                                                                int init, MfTabs<T> tb, double* __restrict__ part,
                                                                const GapState* __restrict__ gs, int stats) {
+    __shared__ T zl[2 * L1LS_BLOCK + 2];
     const int32_t done = gs ? gs->done : 0;
-    if (done) return;
+    if (done) return;  // launch-uniform
     const int64_t m = tb.m, mp = m / 2;
+    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK;
+    for (int q = threadIdx.x; q < 2 * L1LS_BLOCK + 2; q += L1LS_BLOCK) {
+        const int64_t p = ring(2 * k0 + q, m);
+        const int32_t a = tb.emb[p];
+        zl[q] = (a >= 0) ? ld_off32(w, a) : T(0);
+    }
+    __syncthreads();
+    const int64_t k = k0 + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < mp; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < mp) {
+        const int t2 = 2 * (int)threadIdx.x;
         int64_t pf, pg;
         T rf, rg;
         if (R == 2) {
-            const int64_t p0 = 2 * k, p1 = 2 * k + 1, p2 = wrap(2 * k + 2, m), p3 = wrap(2 * k + 3, m);
             T a, u1, u2, bb;
-            rot(cs_of(tb.csm[0], k), zm[p0], zm[p1], false, a, u1);                 // p1 second of pair k
-            rot(cs_of(tb.csm[0], wrap(k + 1, mp)), zm[p2], zm[p3], false, u2, bb);  // p2 first of pair k+1
+            rot(cs_of(tb.csm[0], k), zl[t2], zl[t2 + 1], false, a, u1);                 // 2k+1 second of pair k
+            rot(cs_of(tb.csm[0], wrap(k + 1, mp)), zl[t2 + 2], zl[t2 + 3], false, u2, bb);  // 2k+2 first of k+1
             rot(cs_of(tb.csm[1], k), u1, u2, false, rf, rg);
-            pf = p1;
-            pg = p2;
+            pf = 2 * k + 1;
+            pg = wrap(2 * k + 2, m);
         } else {
             pf = 2 * k;
             pg = 2 * k + 1;
-            rot(cs_of(tb.csm[0], k), zm[pf], zm[pg], false, rf, rg);
+            rot(cs_of(tb.csm[0], k), zl[t2], zl[t2 + 1], false, rf, rg);
         }
         const int64_t ps[2] = {pf, pg};
         const T rr[2] = {rf, rg};
@@ -139,62 +159,71 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restric
     }
 }
 
-// t = Sigma^T Q^T y in n-stage order: the m-side stages are applied locally,
-// then sigma_i u_i is written to n-position emb[i] for active m-positions
-// (a permutation onto [0, n)).  R = 2: Q^T = S~_1^T S~_2^T (S~_2^T first);
-// thread k handles stage-1 pair (2k, 2k+1) from y at 2k-1 .. 2k+2.
+// v = Sigma_m Q^T y in m-stage order (sigma at m-positions, 0 where
+// inactive; pairs with both positions inactive are skipped, since no
+// n-position reads them).  R = 2: Q^T = S~_1^T S~_2^T (S~_2^T first); thread
+// k handles stage-1 pair (2k, 2k+1) from y at 2k-1 .. 2k+2.
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ tn, MfTabs<T> tb,
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ vm, MfTabs<T> tb,
                                                        const GapState* __restrict__ gs) {
     if (gs && gs->done) return;
     const int64_t m = tb.m, mp = m / 2;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < mp; k += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a0 = tb.emb[2 * k], a1 = tb.emb[2 * k + 1];
-        if (a0 < 0 && a1 < 0) continue;
-        T z0 = y[2 * k], z1 = y[2 * k + 1];
-        if (R == 2) {
-            const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
-            T a, b;
-            rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, z0, true, a, b);
-            const T z0n = b;
-            rot(cs_of(tb.csm[1], k), z1, yp, true, a, b);
-            z0 = z0n;
-            z1 = a;
-        }
-        T o0, o1;
-        rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
-        if (a0 >= 0) tn[a0] = tb.sig[2 * k] * o0;
-        if (a1 >= 0) tn[a1] = tb.sig[2 * k + 1] * o1;
+    const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
+    if (k >= mp) return;
+    const T s0 = tb.sig[2 * k], s1 = tb.sig[2 * k + 1];
+    if (s0 == T(0) && s1 == T(0)) return;
+    T z0 = y[2 * k], z1 = y[2 * k + 1];
+    if (R == 2) {
+        const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
+        T a, b;
+        rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, z0, true, a, b);
+        const T z0n = b;
+        rot(cs_of(tb.csm[1], k), z1, yp, true, a, b);
+        z0 = z0n;
+        z1 = a;
     }
+    T o0, o1;
+    rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
+    vm[2 * k] = s0 * o0;
+    vm[2 * k + 1] = s1 * o1;
 }
 
-// g = G t (t in n-stage order); then y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
+// g = G t with t_a = v[inv[a]] gathered once per position into LDS (as in
+// k_mf_q_residual); then y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
 // x_k = soft(y - g/L, tau/L) written over x_{k-2}.  R = 2: G = S_2 S_1 (S_1
 // first); thread k writes stage-2 pair (2k+1, 2k+2 mod n) from t at 2k..2k+3.
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_prox(const T* __restrict__ tn, const T* __restrict__ xc,
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_prox(const T* __restrict__ vm, const T* __restrict__ xc,
                                                            T* __restrict__ xp, T beta, T L, T thr, MfTabs<T> tb,
                                                            double* __restrict__ part,
                                                            const GapState* __restrict__ gs, int stats) {
+    __shared__ T tl[2 * L1LS_BLOCK + 2];
     const int32_t done = gs ? gs->done : 0;
-    if (done) return;
+    if (done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
+    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK;
+    for (int q = threadIdx.x; q < 2 * L1LS_BLOCK + 2; q += L1LS_BLOCK) {
+        const int64_t p = ring(2 * k0 + q, n);
+        tl[q] = ld_off32(vm, tb.inv[p]);
+    }
+    __syncthreads();
+    const int64_t k = k0 + threadIdx.x;
     double v[2] = {0.0, 0.0};
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < np) {
+        const int t2 = 2 * (int)threadIdx.x;
         int64_t pf, pg;
         T gf, gg;
         if (R == 2) {
-            const int64_t p0 = 2 * k, p1 = 2 * k + 1, p2 = wrap(2 * k + 2, n), p3 = wrap(2 * k + 3, n);
             T a, u1, u2, bb;
-            rot(cs_of(tb.csn[0], k), tn[p0], tn[p1], false, a, u1);
-            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tn[p2], tn[p3], false, u2, bb);
+            rot(cs_of(tb.csn[0], k), tl[t2], tl[t2 + 1], false, a, u1);
+            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tl[t2 + 2], tl[t2 + 3], false, u2, bb);
             rot(cs_of(tb.csn[1], k), u1, u2, false, gf, gg);
-            pf = p1;
-            pg = p2;
+            pf = 2 * k + 1;
+            pg = wrap(2 * k + 2, n);
         } else {
             pf = 2 * k;
             pg = 2 * k + 1;
-            rot(cs_of(tb.csn[0], k), tn[pf], tn[pg], false, gf, gg);
+            rot(cs_of(tb.csn[0], k), tl[t2], tl[t2 + 1], false, gf, gg);
         }
         const int64_t ps[2] = {pf, pg};
         const T gv[2] = {gf, gg};
@@ -313,15 +342,11 @@ l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
     return L1LS_OK;
 }
 
-// Grid of the matrix-free streaming passes (one thread per rotation pair,
-// grid-stride beyond this many workgroups).
-int mf_grid(int64_t pairs) {
-    const int64_t g = (pairs + L1LS_BLOCK - 1) / L1LS_BLOCK;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
-}
+// Grid of the matrix-free passes: one thread per rotation pair, one
+// workgroup per 256 pairs.
+int mf_grid(int64_t pairs) { return (int)std::max<int64_t>(1, (pairs + L1LS_BLOCK - 1) / L1LS_BLOCK); }
 
-// zm (m entries) must hold zeros at the inactive m-positions (emb = -1):
-// the n-side pass never writes them.  tn has n entries.
+// w has n entries (n order), vt has m entries (m order).
 template <typename T>
 void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, T* rx, T* ry, T beta, int init,
                         double* part, const GapState* gs, int stats, hipStream_t s) {
