@@ -32,12 +32,13 @@ struct PathCol {  // per tau column, device
     int32_t done, nonfinite;
 };
 
-// sum_k val[k] * V[idx[k], lane] over entries [pb, pe) (at most kMaxNnz)
+// sum_k val[k] * V[idx[k], lane] over entries [pb, pe) (at most kMaxNnz):
+// lanes 0..15 fetch the entries, every lane gathers its column of the rows
+// of V they name (the second 8 only when the row has more than 8 entries).
 __device__ __forceinline__ float row_dot(const int32_t* __restrict__ idx, const float* __restrict__ val,
                                          const float* __restrict__ V, int32_t pb, int32_t pe, int lane) {
     const int32_t cnt = pe - pb;
     if (cnt <= 0) return 0.f;
-    // lanes 0..15 fetch the entries, then every lane gathers its column
     const int32_t q = min(lane, cnt - 1);
     const int32_t my_c = (lane < kMaxNnz) ? idx[pb + q] : 0;
     const float my_v = (lane < kMaxNnz && lane < cnt) ? val[pb + q] : 0.f;
@@ -45,14 +46,84 @@ __device__ __forceinline__ float row_dot(const int32_t* __restrict__ idx, const 
     float w[kMaxNnz];
 #pragma unroll
     for (int e = 0; e < kMaxNnz; ++e) {
+        w[e] = 0.f;
+        g[e] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < kMaxNnz / 2; ++e) {
         const int32_t c = __builtin_amdgcn_readlane(my_c, e);
         w[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, my_v), e));
         g[e] = V[(size_t)c * kCols + lane];
+    }
+    if (cnt > kMaxNnz / 2) {  // wave-uniform
+#pragma unroll
+        for (int e = kMaxNnz / 2; e < kMaxNnz; ++e) {
+            const int32_t c = __builtin_amdgcn_readlane(my_c, e);
+            w[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, my_v), e));
+            g[e] = V[(size_t)c * kCols + lane];
+        }
     }
     float acc = 0.f;
 #pragma unroll
     for (int e = 0; e < kMaxNnz; ++e) acc += w[e] * g[e];
     return acc;
+}
+
+// Two rows of A with the same column list (a stage-2 pair of rows, or of
+// columns in the CSC: both members reach the same positions through the
+// stages, so they share their pattern): one gather of V per entry serves
+// both dot products.  Falls back to two row_dot calls when the lists differ.
+__device__ __forceinline__ void row_dot_pair(const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                             const float* __restrict__ V, int32_t pb0, int32_t pe0, int32_t pb1,
+                                             int32_t pe1, int lane, float& acc0, float& acc1) {
+    const int32_t cnt = pe0 - pb0;
+    bool same = (cnt == pe1 - pb1) && cnt > 0;
+    int32_t c0 = 0;
+    if (same) {  // wave-uniform
+        const int32_t q = min(lane, cnt - 1);
+        c0 = (lane < kMaxNnz) ? idx[pb0 + q] : 0;
+        const int32_t c1 = (lane < kMaxNnz) ? idx[pb1 + q] : 0;
+        same = __ballot(c0 != c1) == 0;
+    }
+    if (!same) {
+        acc0 = row_dot(idx, val, V, pb0, pe0, lane);
+        acc1 = row_dot(idx, val, V, pb1, pe1, lane);
+        return;
+    }
+    const int32_t q = min(lane, cnt - 1);
+    const float v0 = (lane < kMaxNnz && lane < cnt) ? val[pb0 + q] : 0.f;
+    const float v1 = (lane < kMaxNnz && lane < cnt) ? val[pb1 + q] : 0.f;
+    float g[kMaxNnz], w0[kMaxNnz], w1[kMaxNnz];
+#pragma unroll
+    for (int e = 0; e < kMaxNnz; ++e) {
+        g[e] = 0.f;
+        w0[e] = 0.f;
+        w1[e] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < kMaxNnz / 2; ++e) {
+        const int32_t c = __builtin_amdgcn_readlane(c0, e);
+        w0[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v0), e));
+        w1[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v1), e));
+        g[e] = V[(size_t)c * kCols + lane];
+    }
+    if (cnt > kMaxNnz / 2) {  // wave-uniform
+#pragma unroll
+        for (int e = kMaxNnz / 2; e < kMaxNnz; ++e) {
+            const int32_t c = __builtin_amdgcn_readlane(c0, e);
+            w0[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v0), e));
+            w1[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v1), e));
+            g[e] = V[(size_t)c * kCols + lane];
+        }
+    }
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int e = 0; e < kMaxNnz; ++e) {
+        a0 += w0[e] * g[e];
+        a1 += w1[e] * g[e];
+    }
+    acc0 = a0;
+    acc1 = a1;
 }
 
 template <int NS, int NSUM>
@@ -82,23 +153,27 @@ __global__ __launch_bounds__(kPathWaves * L1LS_WAVE) void kp_residual(
     const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
     const bool on = lane < ncols && !pc[lane].done;
     double v[3] = {0.0, 0.0, 0.0};
+    // wave w owns the stage-2 pair of rows (2w+1, 2w+2 mod m)
     const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave;
+    if (row0 < m) {
+        const int64_t rows[2] = {row0 + 1, (row0 + 2 == m) ? 0 : row0 + 2};
+        float acc[2];
+        row_dot_pair(col, val, X, ptr[rows[0]], ptr[rows[0] + 1], ptr[rows[1]], ptr[rows[1] + 1], lane, acc[0],
+                     acc[1]);
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-        const int64_t i = row0 + q;
-        if (i >= m) break;
-        const int32_t pb = ptr[i], pe = ptr[i + 1];
-        const float acc = row_dot(col, val, X, pb, pe, lane);
-        const float bi = b[i];
-        const size_t o = (size_t)i * kCols + lane;
-        const float r = acc - bi;
-        const float yv = init ? r : (1.f + beta) * r - beta * Rx[o];
-        if (on) {
-            Rx[o] = r;
-            Ry[o] = yv;
-            v[0] += (double)r * (double)r;
-            v[1] += (double)yv * (double)yv;
-            v[2] += (double)bi * (double)yv;
+        for (int q = 0; q < 2; ++q) {
+            const int64_t i = rows[q];
+            const float bi = b[i];
+            const size_t o = (size_t)i * kCols + lane;
+            const float r = acc[q] - bi;
+            const float yv = init ? r : (1.f + beta) * r - beta * Rx[o];
+            if (on) {
+                Rx[o] = r;
+                Ry[o] = yv;
+                v[0] += (double)r * (double)r;
+                v[1] += (double)yv * (double)yv;
+                v[2] += (double)bi * (double)yv;
+            }
         }
     }
     if (!stats) return;
@@ -114,51 +189,77 @@ __global__ __launch_bounds__(kPathWaves * L1LS_WAVE) void kp_transpose(
     const bool on = lane < ncols && !pc[lane].done;
     const float thr = on ? (float)pc[lane].thr : 0.f;
     double v[2] = {0.0, 0.0};  // sum |x| | max |g|
+    // wave w owns the stage-2 pair of columns (2w+1, 2w+2 mod n)
     const int64_t col0 = (int64_t)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave;
+    if (col0 < n) {
+        const int64_t cols[2] = {col0 + 1, (col0 + 2 == n) ? 0 : col0 + 2};
+        float gq[2];
+        row_dot_pair(row, val, Ry, ptr[cols[0]], ptr[cols[0] + 1], ptr[cols[1]], ptr[cols[1] + 1], lane, gq[0],
+                     gq[1]);
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-        const int64_t j = col0 + q;
-        if (j >= n) break;
-        const int32_t pb = ptr[j], pe = ptr[j + 1];
-        const float g = row_dot(row, val, Ry, pb, pe, lane);
-        const size_t o = (size_t)j * kCols + lane;
-        const float xcur = Xc[o];
-        const float y = xcur + beta * (xcur - Xp[o]);
-        const float xn = soft_threshold<float>(y - g / L, thr);
-        if (on) {
-            Xp[o] = xn;
-            v[0] += fabs((double)xn);
-            v[1] = fmax(v[1], fabs((double)g));
+        for (int q = 0; q < 2; ++q) {
+            const int64_t j = cols[q];
+            const float g = gq[q];
+            const size_t o = (size_t)j * kCols + lane;
+            const float xcur = Xc[o];
+            const float y = xcur + beta * (xcur - Xp[o]);
+            const float xn = soft_threshold<float>(y - g / L, thr);
+            if (on) {
+                Xp[o] = xn;
+                v[0] += fabs((double)xn);
+                v[1] = fmax(v[1], fabs((double)g));
+            }
         }
     }
     if (!stats) return;
     block_reduce_cols<2, 1>(v, part + (size_t)blockIdx.x * 2 * kCols);
 }
 
-// per-column gap from the partials (one workgroup of 1024 threads: 16 groups
-// of blocks per column, combined in a fixed order)
-__global__ __launch_bounds__(1024) void kp_gap(const double* __restrict__ p1cur, const double* __restrict__ p1prev,
-                                               int g1, const double* __restrict__ p2, int g2, PathCol* __restrict__ pc,
-                                               int32_t ncols, double tol, int64_t iter) {
+// Per-column gap from the partials, in two fixed-order stages: kp_gap_sum
+// (kGapBlocks workgroups) folds contiguous slices of the workgroup partials
+// into [kGapBlocks][5][64]; kp_gap (one workgroup) folds those and applies
+// the gap test per column.
+constexpr int kGapBlocks = 64;
+
+__global__ __launch_bounds__(1024) void kp_gap_sum(const double* __restrict__ p1cur,
+                                                   const double* __restrict__ p1prev, int g1,
+                                                   const double* __restrict__ p2, int g2, double* __restrict__ out) {
     __shared__ double red[16][5][kCols];
     const int c = threadIdx.x % kCols, grp = threadIdx.x / kCols;
+    const int s1 = (g1 + kGapBlocks - 1) / kGapBlocks, s2 = (g2 + kGapBlocks - 1) / kGapBlocks;
+    const int b1 = blockIdx.x * s1, e1 = min(g1, b1 + s1), b2 = blockIdx.x * s2, e2 = min(g2, b2 + s2);
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int bk = grp; bk < g1; bk += 16) {
+    for (int bk = b1 + grp; bk < e1; bk += 16) {
         v[0] += p1cur[((size_t)bk * 3 + 0) * kCols + c];
         v[1] += p1prev[((size_t)bk * 3 + 1) * kCols + c];
         v[2] += p1prev[((size_t)bk * 3 + 2) * kCols + c];
     }
-    for (int bk = grp; bk < g2; bk += 16) {
+    for (int bk = b2 + grp; bk < e2; bk += 16) {
         v[3] += p2[((size_t)bk * 2 + 0) * kCols + c];
         v[4] = fmax(v[4], p2[((size_t)bk * 2 + 1) * kCols + c]);
     }
-    for (int s = 0; s < 5; ++s) red[grp][s][c] = v[s];
+    for (int q = 0; q < 5; ++q) red[grp][q][c] = v[q];
     __syncthreads();
-    if (grp != 0 || c >= ncols) return;
-    for (int s = 0; s < 5; ++s) {
-        double a = red[0][s][c];
-        for (int q = 1; q < 16; ++q) a = (s < 4) ? a + red[q][s][c] : fmax(a, red[q][s][c]);
-        v[s] = a;
+    if (grp != 0) return;
+    for (int q = 0; q < 5; ++q) {
+        double a = red[0][q][c];
+        for (int r = 1; r < 16; ++r) a = (q < 4) ? a + red[r][q][c] : fmax(a, red[r][q][c]);
+        out[((size_t)blockIdx.x * 5 + q) * kCols + c] = a;
+    }
+}
+
+__global__ __launch_bounds__(kCols) void kp_gap(const double* __restrict__ sums, PathCol* __restrict__ pc,
+                                                int32_t ncols, double tol, int64_t iter) {
+    const int c = threadIdx.x;
+    if (c >= ncols) return;
+    double v[5];
+    for (int q = 0; q < 5; ++q) {
+        double a = sums[(size_t)q * kCols + c];
+        for (int b = 1; b < kGapBlocks; ++b) {
+            const double x = sums[((size_t)b * 5 + q) * kCols + c];
+            a = (q < 4) ? a + x : fmax(a, x);
+        }
+        v[q] = a;
     }
     PathCol& P = pc[c];
     if (P.done) return;
@@ -233,6 +334,8 @@ extern "C" l1ls_status l1ls_solve_fista_path(const l1ls_instance* I, const doubl
     L1LS_TRY(A.alloc(&p1, (size_t)2 * g1 * 3 * kCols));
     L1LS_TRY(A.alloc(&p2, (size_t)g2 * 2 * kCols));
     L1LS_TRY(A.alloc(&pc, kCols));
+    double* gsum = nullptr;
+    L1LS_TRY(A.alloc(&gsum, (size_t)kGapBlocks * 5 * kCols));
     std::vector<PathCol> hc(kCols);
     for (int c = 0; c < kCols; ++c) {
         std::memset(&hc[c], 0, sizeof(PathCol));
@@ -266,10 +369,12 @@ extern "C" l1ls_status l1ls_solve_fista_path(const l1ls_instance* I, const doubl
                                (float)beta_prev, (float)L, n, pc, k, p2, chk);
             hipLaunchKernelGGL(kp_residual, dim3(g1), blk, 0, s, I->csr_ptr, I->csr_col, I->csr_v32, Xs, I->b32_op,
                                Rx, Ry, (float)beta, 0, m, pc, k, p1 + (size_t)(kk & 1) * g1 * 3 * kCols, st1);
-            if (chk)
-                hipLaunchKernelGGL(kp_gap, dim3(1), dim3(1024), 0, s, p1 + (size_t)(kk & 1) * g1 * 3 * kCols,
-                                   p1 + (size_t)((kk - 1) & 1) * g1 * 3 * kCols, g1, p2, g2, pc, k,
-                                   o->rel_gap_tol, kk);
+            if (chk) {
+                hipLaunchKernelGGL(kp_gap_sum, dim3(kGapBlocks), dim3(1024), 0, s,
+                                   p1 + (size_t)(kk & 1) * g1 * 3 * kCols,
+                                   p1 + (size_t)((kk - 1) & 1) * g1 * 3 * kCols, g1, p2, g2, gsum);
+                hipLaunchKernelGGL(kp_gap, dim3(1), dim3(kCols), 0, s, gsum, pc, k, o->rel_gap_tol, kk);
+            }
             beta_prev = beta;
             t = tn;
             it = kk;
