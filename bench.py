@@ -228,19 +228,30 @@ def bench_serve(args):
     reqs = serve_requests(args.requests + args.serve_warmup, 1503035204, args.serve_log2n_lo, args.serve_log2n_hi)
     warm, reqs = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
 
+    finish = args.serve_finish
+    storage = (L.STORE_F32 | L.STORE_F64) if finish else L.STORE_F32
+
     def plain_one(r):
         inst = L.l1ls_generate(r["m"], r["n"], r["kappa"], r["s"], r["tau"], r["seed"], rounds=r["rounds"],
-                               storage=L.STORE_F32, stream=stream)
+                               storage=storage, stream=stream)
         x, rep, _ = L.l1ls_solve_fista(inst, max_iter=cap, rel_gap_tol=tol, check_every=check, precision=L.F32,
-                                       polish=0, stream=stream)
+                                       polish=2 if finish else 0, stream=stream)
         torch.cuda.synchronize()
         inst.free()
         return rep
 
+    last = [time.perf_counter()]
+
+    def progress(**kv):  # a line every 10 s, so a long run is seen to be alive
+        if time.perf_counter() - last[0] > 10.0:
+            last[0] = time.perf_counter()
+            print(json.dumps({"progress": "serve", **kv}), file=sys.stderr, flush=True)
+
     for r in warm:
         plain_one(r)
     service, conv_plain, iters_plain = [], 0, []
-    for r in reqs:
+    for i, r in enumerate(reqs):
+        progress(phase="calibration", done=i)
         t0 = time.perf_counter()
         rep = plain_one(r)
         service.append(time.perf_counter() - t0)
@@ -256,7 +267,8 @@ def bench_serve(args):
     def run_plain(arr):
         lat = []
         t0 = time.perf_counter()
-        for r, a in zip(reqs, arr):
+        for i, (r, a) in enumerate(zip(reqs, arr)):
+            progress(phase="plain", done=i)
             now = time.perf_counter() - t0
             if now < a:
                 time.sleep(a - now)
@@ -272,11 +284,12 @@ def bench_serve(args):
         ids = {}
         t0 = time.perf_counter()
         while len(lat) < len(reqs):
+            progress(phase="server", done=len(lat))
             now = time.perf_counter() - t0
             while nxt < len(reqs) and arr[nxt] <= now:
                 r = reqs[nxt]
                 rid = S.submit(r["m"], r["n"], r["kappa"], r["s"], r["tau"], r["seed"], rounds=r["rounds"],
-                               rel_gap_tol=tol, max_iter=cap)
+                               rel_gap_tol=tol, max_iter=cap, fp64_finish=finish)
                 ids[rid] = nxt
                 nxt += 1
             q, res, _ = S.stats()
@@ -332,7 +345,9 @@ def bench_serve(args):
                                % (args.serve_log2n_lo, args.serve_log2n_hi),
                    "requests": len(reqs), "rel_gap_tol": tol, "check_every": check, "max_iter": cap,
                    "slots": args.serve_slots, "iters_per_tick": args.serve_iters_per_tick,
-                   "hbm_budget_gib": args.serve_budget_gib},
+                   "hbm_budget_gib": args.serve_budget_gib,
+                   "accuracy": ("FP64 gap <= tol (FP32 FISTA, then FP64 polish of the reduced problem when the "
+                                "FP64 gap misses tol)") if finish else "FP32 device gap <= tol (FISTA in FP32)"},
         "p50_s": head["server"]["p50_s"], "p99_s": head["server"]["p99_s"],
         "extra": {"plain_capacity_solves_per_s": mu, "plain_converged": conv_plain,
                   "plain_iters_median": _pct(iters_plain, 50), "plain_service_s_mean": float(np.mean(service)),
@@ -569,6 +584,8 @@ def main():
     ap.add_argument("--serve-log2n-hi", type=int, default=22)
     ap.add_argument("--rate-mults", type=float, nargs="+", default=[0.7])
     ap.add_argument("--serve-dump", default=None, help="append per-request rows (JSON lines) to this file")
+    ap.add_argument("--serve-finish", action="store_true",
+                    help="FP64 finish: certify each result in FP64 and polish when it misses the tolerance")
     ap.add_argument("--plain-max-mult", type=float, default=1.0,
                     help="skip the real-time plain run above this rate multiple (its queue grows without bound)")
     args = ap.parse_args()

@@ -156,7 +156,9 @@ typedef struct {
     int32_t check_every;   /* gap evaluated every this many iterations (>= 1)   */
     int32_t precision;     /* l1ls_precision of the bulk iteration              */
     int32_t op;            /* l1ls_operator                                     */
-    int32_t polish;        /* 1: FP64 polish of the reduced problem at the end  */
+    int32_t polish;        /* FP64 polish of the reduced problem (13) at the end:
+                              0 never, 1 always, 2 only when the FP64 gap of
+                              the FISTA result exceeds rel_gap_tol            */
     double L;              /* <= 0: the instance's L (sigma_1^2)                 */
     const double* x0_dev;  /* n, warm start; NULL: x0 = 0                       */
     void* stream;
@@ -283,6 +285,15 @@ size_t l1ls_instance_footprint(const l1ls_instance* inst);
  *      non-finite, or which reached max_iter: the iterate (FP64, original
  *      order) moves to a result buffer held until l1ls_server_take, and the
  *      slot and instance are freed.
+ * A request with flags & L1LS_REQ_FP64_FINISH is generated with the FP64
+ * operator as well; on retirement a worker thread of the server (its own
+ * stream) evaluates the FP64 gap of the iterate and, when it exceeds
+ * rel_gap_tol, runs the FP64 polish of the reduced problem (13) (section
+ * 3.2), exactly as l1ls_solve_fista with polish = 2; the result is then the
+ * one that function returns for the same instance, tolerance, check period
+ * and max_iter, and its report carries the FP64 gap (converged = 1 when it
+ * is within rel_gap_tol).  Such requests count against the budget until
+ * finished.
  * A result is bit-identical to the one the request gets alone in the server,
  * and to l1ls_solve_fista (FP32, the same tolerance and check period) on the
  * same instance.  report.seconds of a taken result is the time from
@@ -300,7 +311,8 @@ size_t l1ls_instance_footprint(const l1ls_instance* inst);
  *   take:   copies the result of a retired id to x_out_dev (n FP64; NULL to
  *           drop it) and its report, then frees it; L1LS_E_STATE if the id is
  *           not retired or already taken.
- *   stats:  queued requests, resident requests, estimated bytes resident.
+ *   stats:  queued requests, resident requests (in a batch or being
+ *           finished), estimated bytes resident.
  */
 typedef struct l1ls_server l1ls_server;
 typedef struct {
@@ -310,10 +322,11 @@ typedef struct {
     double tau;
     uint64_t seed;
     int32_t rounds;
-    int32_t pad;
+    int32_t flags;         /* L1LS_REQ_FP64_FINISH: see below                   */
     double rel_gap_tol;
     int64_t max_iter;
 } l1ls_request;
+#define L1LS_REQ_FP64_FINISH 1
 l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_bytes, int32_t iters_per_tick,
                                int32_t check_every, void* stream, l1ls_server** out);
 l1ls_status l1ls_server_submit(l1ls_server* server, const l1ls_request* req, int64_t* id_out);

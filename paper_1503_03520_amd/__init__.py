@@ -16,6 +16,7 @@ L1LS_NOT_CONVERGED = 1
 F32, F64 = 0, 1
 OP_STORED, OP_MATRIX_FREE = 0, 1
 STORE_F32, STORE_F64 = 1, 2
+REQ_FP64_FINISH = 1
 
 _STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "device allocation failed",
            -3: "HIP runtime error", -4: "non-finite value", -5: "invalid state", -6: "unsupported"}
@@ -77,7 +78,7 @@ class Report(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("kappa", ctypes.c_double), ("s", ctypes.c_int64),
-        ("tau", ctypes.c_double), ("seed", ctypes.c_uint64), ("rounds", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("seed", ctypes.c_uint64), ("rounds", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("rel_gap_tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
     ]
 
@@ -414,9 +415,9 @@ class Server:
         self._h = h
         self._n = {}
 
-    def submit(self, m, n, kappa, s, tau, seed, rounds=2, rel_gap_tol=1e-5, max_iter=100000):
-        r = Request(int(m), int(n), float(kappa), int(s), float(tau), int(seed), int(rounds), 0,
-                    float(rel_gap_tol), int(max_iter))
+    def submit(self, m, n, kappa, s, tau, seed, rounds=2, rel_gap_tol=1e-5, max_iter=100000, fp64_finish=False):
+        r = Request(int(m), int(n), float(kappa), int(s), float(tau), int(seed), int(rounds),
+                    REQ_FP64_FINISH if fp64_finish else 0, float(rel_gap_tol), int(max_iter))
         rid = ctypes.c_int64(-1)
         _check(lib().l1ls_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "l1ls_server_submit")
         self._n[rid.value] = int(n)
@@ -462,10 +463,10 @@ class Server:
             pass
 
 
-def request_footprint(m, n, rounds=2, kappa=1e2, s=0, tau=1.0, rel_gap_tol=1e-6, max_iter=1):
+def request_footprint(m, n, rounds=2, kappa=1e2, s=0, tau=1.0, rel_gap_tol=1e-6, max_iter=1, fp64_finish=False):
     """Admission estimate of a serving request (bytes; 0 if the request is invalid)."""
-    r = Request(int(m), int(n), float(kappa), int(s), float(tau), 0, int(rounds), 0, float(rel_gap_tol),
-                int(max_iter))
+    r = Request(int(m), int(n), float(kappa), int(s), float(tau), 0, int(rounds),
+                REQ_FP64_FINISH if fp64_finish else 0, float(rel_gap_tol), int(max_iter))
     return int(lib().l1ls_request_footprint(ctypes.byref(r)))
 
 

@@ -13,11 +13,11 @@ using namespace l1ls;
 template <typename T>
 l1ls_status apply_side(const SideTables& tab, int rounds, bool transpose, T* v, T* scratch, hipStream_t stream);
 template <typename T>
-void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, T* rx, T* ry, T beta, int init,
-                        double* part, const GapState* gs, int stats, hipStream_t s);
+void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, const T* rx_prev, T* rx, T* vt,
+                        T beta, int init, double* part, const GapState* gs, int stats, hipStream_t s);
 template <typename T>
-void mf_transpose_launch(const l1ls_instance* I, const T* ry, T* vt, const T* xc, T* xp, T beta, T L, T thr,
-                         double* part, const GapState* gs, int stats, hipStream_t s);
+void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
+                         T thr, double* part, const GapState* gs, int stats, hipStream_t s);
 int mf_grid(int64_t pairs);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol);
@@ -119,11 +119,16 @@ struct l1ls_fista {
     hipStream_t stream = nullptr;
     int prec = L1LS_F64;
     double tau = 1, L = 1;
-    void* x[2] = {nullptr, nullptr};  // x_k lives in x[k & 1]
+    // x_k lives in x[k % nslots].  The stored passes overwrite x_{k-2} in
+    // place (2 slots); the matrix-free passes read a neighbour's x_{k-2}
+    // across workgroups, so x_k goes to a third slot and r_x to a second one.
+    void* x[3] = {nullptr, nullptr, nullptr};
+    int nslots = 2;
     void* rx = nullptr;
+    void* rx2 = nullptr;       // matrix-free: r_x,k lives in (k & 1) ? rx2 : rx
     void* ry = nullptr;
-    void* wbuf = nullptr;      // matrix-free: Sigma G^T x in n-stage order (n)
-    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in m-stage order (m)
+    void* wbuf = nullptr;      // matrix-free: Sigma G^T x_k in n-stage order (n), made by the transpose pass
+    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in m-stage order (m), made by the residual pass
     bool mf = false;           // matrix-free operator (stage order)
     const int32_t* col_of = nullptr;   // position -> original index of x
     const int32_t* col_pos = nullptr;  // original index -> position
@@ -219,7 +224,9 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
     const l1ls_instance* I = F->I;
     if (F->mf)
         return timed(F, 0, [&] {
-            mf_residual_launch<T>(I, x, (T*)F->wbuf, mf_b<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, init,
+            T* rx_out = (T*)(slot ? F->rx2 : F->rx);
+            const T* rx_prev = (const T*)(slot ? F->rx : F->rx2);
+            mf_residual_launch<T>(I, x, (T*)F->wbuf, mf_b<T>(I), rx_prev, rx_out, (T*)F->tbuf, (T)beta, init,
                                   F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats, F->stream);
         });
     return timed(F, 0, [&] {
@@ -229,13 +236,14 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
     });
 }
 
+// xp holds x_{k-2}; x_k goes to xo (== xp for the stored passes).
 template <typename T>
-l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, double beta, int stats) {
+l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double beta, int stats) {
     const l1ls_instance* I = F->I;
     if (F->mf)
         return timed(F, 1, [&] {
-            mf_transpose_launch<T>(I, (const T*)F->ry, (T*)F->tbuf, xc, xp, (T)beta, (T)F->L, (T)(F->tau / F->L),
-                                   F->k2part, F->gs, stats, F->stream);
+            mf_transpose_launch<T>(I, (const T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
+                                   (T)(F->tau / F->L), F->k2part, F->gs, stats, F->stream);
         });
     return timed(F, 1, [&] {
         hipLaunchKernelGGL((k_transpose_prox<T>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
@@ -252,15 +260,17 @@ l1ls_status fista_iterate_t(l1ls_fista* F, int64_t iters) {
         const int64_t k = F->k + 1;  // iteration being enqueued
         const double t_next = next_t(F->t_k);
         const double beta_k = (F->t_k - 1.0) / t_next;
-        T* xcur = (T*)F->x[(k - 1) & 1];
-        T* xslot = (T*)F->x[k & 1];  // holds x_{k-2}, receives x_k
+        const int ns = F->nslots;
+        T* xcur = (T*)F->x[(k - 1) % ns];
+        T* xprev = (T*)F->x[(k + ns - 2) % ns];  // x_{k-2}
+        T* xslot = (T*)F->x[k % ns];             // receives x_k (== xprev with 2 slots)
         // FP64 statistics only where a gap evaluation reads them: the
         // transpose and residual passes of iteration k when k is a check
         // iteration, and the r_y statistics of the pass just before one.
         const bool last = (k == F->stats_until);
         const int st2 = (k % check == 0 || last) ? 1 : 0;
         const int st1 = (k % check == 0 || (k + 1) % check == 0 || last || k + 1 == F->stats_until) ? 1 : 0;
-        L1LS_TRY(launch_transpose<T>(F, xcur, xslot, F->beta_prev, st2));
+        L1LS_TRY(launch_transpose<T>(F, xcur, xprev, xslot, F->beta_prev, st2));
         L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1), st1));
         if (k % check == 0) {
             L1LS_TRY(timed(F, 2, [&] {
@@ -351,6 +361,12 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
         unsigned char* tb = nullptr;
         if ((st = F->arena.alloc(&wb, I->n * es)) != L1LS_OK) return fail(st);
         if ((st = F->arena.alloc(&tb, I->m * es)) != L1LS_OK) return fail(st);
+        unsigned char *x2 = nullptr, *rx2 = nullptr;
+        if ((st = F->arena.alloc(&x2, I->n * es)) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&rx2, I->m * es)) != L1LS_OK) return fail(st);
+        F->x[2] = x2;
+        F->rx2 = rx2;
+        F->nslots = 3;
         F->wbuf = wb;
         F->tbuf = tb;
     }
@@ -379,6 +395,8 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
             hipLaunchKernelGGL(k_fill<float>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (float*)x0, 0.0f, I->n);
     }
     if (hipMemcpyAsync(x1, x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(L1LS_E_HIP);
+    if (F->x[2] && hipMemcpyAsync(F->x[2], x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(L1LS_E_HIP);
     hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
     if (F->prec == L1LS_F64)
         st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0, 1);
@@ -418,7 +436,7 @@ extern "C" l1ls_status l1ls_fista_get_x(l1ls_fista* F, double* x_out) {
     HIP_TRY(hipMemcpyAsync(&g, F->gs, sizeof(g), hipMemcpyDeviceToHost, F->stream));
     HIP_TRY(hipStreamSynchronize(F->stream));
     const int64_t kk = (g.conv_iter >= 0) ? g.conv_iter : F->k;
-    void* src = F->x[kk & 1];
+    void* src = F->x[kk % F->nslots];
     const int64_t n = F->I->n;
     // back to the original order: x[j] = x_op[op_col_pos[j]]
     if (F->prec == L1LS_F64)
@@ -618,7 +636,14 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
     if (st != L1LS_OK) return st;
     int prounds = 0;
     int64_t pcg = 0;
-    if (opts->polish) L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &pcg, 0.0));
+    bool do_polish = opts->polish == 1;
+    if (opts->polish == 2) {  // only when the FP64 gap of the FISTA result misses the tolerance
+        if (!I->csr_v64) return L1LS_E_UNSUPPORTED;
+        double P, D, gap;
+        L1LS_TRY(gap_fp64(I, tau, x_out, &P, &D, &gap, s));
+        do_polish = !(gap <= opts->rel_gap_tol);
+    }
+    if (do_polish) L1LS_TRY(polish_fp64(I, tau, x_out, s, &prounds, &pcg, 0.0));
     // Final certificate in FP64 with the FP64 operator when it is stored.
     if (I->csr_v64) {
         L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));

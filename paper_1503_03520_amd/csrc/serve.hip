@@ -25,17 +25,31 @@
 // A request's arithmetic depends only on its own instance and iteration
 // count (the batch's per-slot independence), so a result is the same in any
 // mix, any class schedule and any tick length.
+//
+// Requests flagged for an FP64 finish leave the batch into a queue served
+// by a worker thread of their size class, on its own stream: FP64 gap of the
+// iterate, and the FP64 polish of the reduced problem (13) (section 3.2)
+// when the gap misses the tolerance.  The tick loop never waits for a
+// polish, and a small request's certificate never waits for a large one's
+// polish.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
 
 size_t batch_slot_bytes(int64_t m, int64_t n);
+l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
+                     hipStream_t s);
+l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
+                        int64_t* pcg_iters_out, double support_tol);
 
 namespace {
 
@@ -66,6 +80,8 @@ struct ServeSlot {
     int64_t max_iter = 0;
     size_t est = 0;
     double bytes = 0.0;
+    double tau = 0.0, tol = 0.0;
+    bool finish = false;
     ServeClock::time_point submitted;
 };
 
@@ -73,6 +89,16 @@ struct ServeDone {
     double* x = nullptr;  // n FP64 on the device
     int64_t n = 0;
     l1ls_report rep;
+};
+
+struct FinishJob {  // a retired FP64-finish request waiting for its worker
+    int64_t id = -1;
+    int cls = 0;
+    l1ls_instance* inst = nullptr;
+    ServeDone d;
+    double tau = 0.0, tol = 0.0;
+    size_t est = 0;
+    ServeClock::time_point submitted;
 };
 
 struct ServeClass {
@@ -87,14 +113,25 @@ struct ServeClass {
 
 struct l1ls_server {
     int32_t max_slots = 0, iters_per_tick = 0, check_every = 0;
-    size_t budget = 0, used = 0;
+    int device = 0;
+    size_t budget = 0;
     hipStream_t stream = nullptr;  // caller's stream: result copies
     hipStream_t gen_stream = nullptr;
+    hipStream_t fin_stream[kClasses] = {nullptr, nullptr, nullptr};
     ServeClass cls[kClasses];
     int64_t next_id = 0;
     std::deque<ServeReq> queue[kClasses];
+    // shared with the finishing worker (under mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    size_t used = 0;
+    std::deque<FinishJob> jobs[kClasses];
+    int32_t finishing = 0;  // jobs queued or running
+    bool stop = false;
+    l1ls_status worker_status = L1LS_OK;
     std::unordered_map<int64_t, ServeDone> done;
     std::vector<int64_t> fresh;  // retired since the last l1ls_server_completed call
+    std::thread worker[kClasses];
 };
 
 namespace {
@@ -103,25 +140,81 @@ namespace {
 // at its bound (each Givens stage at most doubles a column's support).
 size_t estimate_footprint(const l1ls_request& r) {
     const size_t nnz = (size_t)r.n * (r.rounds >= 2 ? 16 : 4);
-    return nnz * 16 + (size_t)(r.m + r.n + 2) * 4 + (size_t)(r.m + r.n) * 48 + batch_slot_bytes(r.m, r.n);
+    const size_t f64 = (r.flags & L1LS_REQ_FP64_FINISH) ? nnz * 16 : 0;
+    return nnz * 16 + f64 + (size_t)(r.m + r.n + 2) * 4 + (size_t)(r.m + r.n) * 48 + batch_slot_bytes(r.m, r.n);
 }
 
 bool valid_request(const l1ls_request& r) {
     return r.n >= 2 && r.m >= r.n && r.m % 2 == 0 && r.n % 2 == 0 && r.m < ((int64_t)1 << 31) && r.s >= 0 &&
            r.s <= r.n && r.kappa >= 1.0 && is_finite(r.kappa) && r.tau > 0.0 && is_finite(r.tau) &&
-           (r.rounds == 1 || r.rounds == 2) && r.rel_gap_tol > 0.0 && r.max_iter > 0;
+           (r.rounds == 1 || r.rounds == 2) && r.rel_gap_tol > 0.0 && r.max_iter > 0 &&
+           (r.flags & ~L1LS_REQ_FP64_FINISH) == 0;
 }
 
 void destroy_streams(l1ls_server* S) {
     for (ServeClass& c : S->cls)
         if (c.stream) (void)hipStreamDestroy(c.stream);
     if (S->gen_stream) (void)hipStreamDestroy(S->gen_stream);
+    for (hipStream_t& f : S->fin_stream)
+        if (f) (void)hipStreamDestroy(f);
 }
 
+// Requests holding a slot or waiting for / in the finishing worker (call
+// with mu held or from the tick thread, which alone changes the slots).
 int32_t total_resident(const l1ls_server* S) {
-    int32_t r = 0;
+    int32_t r = S->finishing;
     for (const ServeClass& c : S->cls) r += c.resident;
     return r;
+}
+
+// The finishing worker of size class c: FP64 gap, polish when the gap
+// misses the tolerance, FP64 gap again; then the result joins the completed
+// ones.
+void finish_worker(l1ls_server* S, int c) {
+    (void)hipSetDevice(S->device);
+    hipStream_t fs = S->fin_stream[c];
+    for (;;) {
+        FinishJob j;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [S, c] { return S->stop || !S->jobs[c].empty(); });
+            if (S->jobs[c].empty()) return;  // stop requested and nothing left
+            j = S->jobs[c].front();
+            S->jobs[c].pop_front();
+        }
+        double P = 0.0, D = 0.0, gap = INFINITY;
+        int rounds = 0;
+        int64_t pcg = 0;
+        l1ls_status st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs);
+        if (st == L1LS_OK && !(gap <= j.tol)) {
+            st = polish_fp64(j.inst, j.tau, j.d.x, fs, &rounds, &pcg, 0.0);
+            if (st == L1LS_OK) st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs);
+        }
+        j.d.rep.primal = P;
+        j.d.rep.dual = D;
+        j.d.rep.rel_gap = gap;
+        j.d.rep.polish_rounds = rounds;
+        j.d.rep.inner = pcg;
+        j.d.rep.converged = (st == L1LS_OK && gap <= j.tol) ? 1 : (j.d.rep.converged < 0 ? -1 : 0);
+        j.d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - j.submitted).count();
+        l1ls_free(j.inst);
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (st != L1LS_OK) S->worker_status = st;
+        S->used -= j.est;
+        S->finishing -= 1;
+        S->done[j.id] = j.d;
+        S->fresh.push_back(j.id);
+    }
+}
+
+void stop_workers(l1ls_server* S) {
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (std::thread& w : S->worker)
+        if (w.joinable()) w.join();
 }
 
 }  // namespace
@@ -143,7 +236,10 @@ extern "C" l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_b
         delete S;
         return st;
     };
+    if (hipGetDevice(&S->device) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipStreamCreateWithFlags(&S->gen_stream, hipStreamNonBlocking) != hipSuccess) return fail(L1LS_E_HIP);
+    for (hipStream_t& f : S->fin_stream)
+        if (hipStreamCreateWithFlags(&f, hipStreamNonBlocking) != hipSuccess) return fail(L1LS_E_HIP);
     for (ServeClass& c : S->cls) {
         if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return fail(L1LS_E_HIP);
         l1ls_solve_opts o;
@@ -156,6 +252,12 @@ extern "C" l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_b
         l1ls_status st = l1ls_batch_create(max_slots, 0, &o, &c.batch);
         if (st != L1LS_OK) return fail(st);
         c.slots.assign(max_slots, ServeSlot{});
+    }
+    try {
+        for (int c = 0; c < kClasses; ++c) S->worker[c] = std::thread(finish_worker, S, c);
+    } catch (...) {
+        stop_workers(S);
+        return fail(L1LS_E_STATE);
     }
     *out = S;
     return L1LS_OK;
@@ -199,8 +301,9 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
         int pick = -1;
         for (int c = 0; c < kClasses; ++c) {
             if (S->queue[c].empty() || S->cls[c].resident >= kClassLimit[c]) continue;
-            if (total_resident(S) >= S->max_slots) continue;
             const ServeReq& h = S->queue[c].front();
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (total_resident(S) >= S->max_slots) continue;
             if (S->budget && S->used + estimate_footprint(h.r) > S->budget) continue;
             if (pick < 0 || h.id < S->queue[pick].front().id) pick = c;
         }
@@ -210,7 +313,7 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
         ServeClass& C = S->cls[pick];
         l1ls_gen_opts go;
         go.rounds = r.rounds;
-        go.storage = L1LS_STORE_F32;
+        go.storage = (r.flags & L1LS_REQ_FP64_FINISH) ? (L1LS_STORE_F32 | L1LS_STORE_F64) : L1LS_STORE_F32;
         go.stream = S->gen_stream;
         go.layout = L1LS_LAYOUT_STAGE;
         l1ls_instance* inst = nullptr;
@@ -228,10 +331,16 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
         sl.max_iter = r.max_iter;
         sl.est = fp;
         sl.bytes = iter_bytes(inst->m, inst->n, inst->nnz);
+        sl.tau = r.tau;
+        sl.tol = r.rel_gap_tol;
+        sl.finish = (r.flags & L1LS_REQ_FP64_FINISH) != 0;
         sl.submitted = q.submitted;
         C.resident += 1;
         C.bytes += sl.bytes;
-        S->used += fp;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->used += fp;
+        }
         S->queue[pick].pop_front();
         ++na;
     }
@@ -257,25 +366,46 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
                 (void)hipFree(p);
                 return st;
             }
-            d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - sl.submitted).count();
-            l1ls_free(sl.inst);
-            S->used -= sl.est;
             C.resident -= 1;
             C.bytes -= sl.bytes;
             if (C.resident == 0) C.bytes = 0.0;
-            S->done[sl.id] = d;
-            S->fresh.push_back(sl.id);
+            if (sl.finish) {  // to the worker; it frees the instance and releases the budget
+                FinishJob j;
+                j.id = sl.id;
+                j.cls = (int)(&C - S->cls);
+                j.inst = sl.inst;
+                j.d = d;
+                j.tau = sl.tau;
+                j.tol = sl.tol;
+                j.est = sl.est;
+                j.submitted = sl.submitted;
+                {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    S->finishing += 1;
+                    S->jobs[j.cls].push_back(j);
+                }
+                S->cv.notify_all();
+            } else {
+                d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - sl.submitted).count();
+                l1ls_free(sl.inst);
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->used -= sl.est;
+                S->done[sl.id] = d;
+                S->fresh.push_back(sl.id);
+                ++nc;
+            }
             sl = ServeSlot{};
-            ++nc;
         }
     }
     if (admitted) *admitted = na;
     if (completed) *completed = nc;
-    return L1LS_OK;
+    std::lock_guard<std::mutex> lk(S->mu);
+    return S->worker_status;
 }
 
 extern "C" int32_t l1ls_server_completed(l1ls_server* S, int64_t* ids, int32_t cap) {
     if (!S || !ids || cap < 1) return 0;
+    std::lock_guard<std::mutex> lk(S->mu);
     const int32_t k = (int32_t)std::min<size_t>((size_t)cap, S->fresh.size());
     for (int32_t q = 0; q < k; ++q) ids[q] = S->fresh[q];
     S->fresh.erase(S->fresh.begin(), S->fresh.begin() + k);
@@ -284,20 +414,27 @@ extern "C" int32_t l1ls_server_completed(l1ls_server* S, int64_t* ids, int32_t c
 
 extern "C" l1ls_status l1ls_server_take(l1ls_server* S, int64_t id, double* x_out_dev, l1ls_report* rep) {
     if (!S) return L1LS_E_ARG;
-    auto it = S->done.find(id);
-    if (it == S->done.end()) return L1LS_E_STATE;
-    if (x_out_dev)
-        HIP_TRY(hipMemcpyAsync(x_out_dev, it->second.x, it->second.n * sizeof(double), hipMemcpyDeviceToDevice,
-                               S->stream));
-    HIP_TRY(hipStreamSynchronize(S->stream));
-    if (rep) *rep = it->second.rep;
-    (void)hipFree(it->second.x);
-    S->done.erase(it);
-    return L1LS_OK;
+    ServeDone d;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->done.find(id);
+        if (it == S->done.end()) return L1LS_E_STATE;
+        d = it->second;
+        S->done.erase(it);
+    }
+    l1ls_status st = L1LS_OK;
+    if (x_out_dev &&
+        hipMemcpyAsync(x_out_dev, d.x, d.n * sizeof(double), hipMemcpyDeviceToDevice, S->stream) != hipSuccess)
+        st = L1LS_E_HIP;
+    if (hipStreamSynchronize(S->stream) != hipSuccess) st = L1LS_E_HIP;
+    if (rep) *rep = d.rep;
+    (void)hipFree(d.x);
+    return st;
 }
 
 extern "C" l1ls_status l1ls_server_stats(l1ls_server* S, int32_t* queued, int32_t* resident, size_t* used_bytes) {
     if (!S) return L1LS_E_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
     if (queued) {
         size_t qn = 0;
         for (const auto& q : S->queue) qn += q.size();
@@ -314,6 +451,7 @@ extern "C" size_t l1ls_request_footprint(const l1ls_request* r) {
 
 extern "C" void l1ls_server_destroy(l1ls_server* S) {
     if (!S) return;
+    stop_workers(S);  // finish the queued jobs first
     for (ServeClass& C : S->cls) {
         if (C.stream) (void)hipStreamSynchronize(C.stream);
         for (ServeSlot& s : C.slots)

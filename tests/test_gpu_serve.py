@@ -174,3 +174,38 @@ def test_largest_class_holds_one_request_and_small_ones_overtake():
     assert order.index(s0) < order.index(b1)      # the small request did not wait for the second large one
     assert order.index(b0) < order.index(b1)      # FIFO within the large class
     S.destroy()
+
+
+def test_fp64_finish_matches_solve_fista_with_conditional_polish():
+    # one request converges in FP32 and is certified as is; the others stop at
+    # their cap and are polished in FP64 by the server's worker thread
+    reqs = [(2048, 1024, 1e2, 10, 1.0, 401, 2, 1e-6, CAP),
+            (8192, 4096, 1e5, 40, 0.05, 402, 2, 1e-6, 96),
+            (1 << 15, 1 << 14, 1e6, 163, 0.3, 403, 2, 1e-6, 160)]
+    S = L.Server(4, iters_per_tick=PER_TICK, check_every=CHECK)
+    ids = {}
+    for q, (m, n, kappa, s, tau, seed, r, tol, cap) in enumerate(reqs):
+        ids[S.submit(m, n, kappa, s, tau, seed, rounds=r, rel_gap_tol=tol, max_iter=cap, fp64_finish=True)] = q
+    out = {}
+    for _ in range(20000):
+        S.tick()
+        for rid in S.completed():
+            out[ids[rid]] = S.take(rid)
+        if len(out) == len(reqs):
+            break
+    assert S.stats() == (0, 0, 0)
+    S.destroy()
+    polished = 0
+    for q, (m, n, kappa, s, tau, seed, r, tol, cap) in enumerate(reqs):
+        print(f"[case] fp64 finish request {q}", flush=True)
+        xs, rs = out[q]
+        inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r)
+        x1, r1, _ = L.l1ls_solve_fista(inst, max_iter=cap, rel_gap_tol=tol, check_every=CHECK, precision=L.F32,
+                                       polish=2)
+        assert torch.equal(xs, x1), q
+        assert rs["rel_gap"] == r1["rel_gap"] and rs["polish_rounds"] == r1["polish_rounds"]
+        assert rs["converged"] == 1 and rs["rel_gap"] <= tol
+        P, D, gap = L.l1ls_objective_gap(inst, tau, xs)
+        assert gap <= tol
+        polished += rs["polish_rounds"] > 0
+    assert polished >= 1
