@@ -96,58 +96,107 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T
     w[2 * k + 1] = tb.sig_n[2 * k + 1] * o1;
 }
 
-// r_x = Q z - b, r_y = (1+beta) r_x - beta r_x,prev, where z_i = w[emb[i]]
-// (0 at inactive m-positions) is gathered once per position into LDS: a
-// workgroup owns pairs k0 .. k0+255 and the positions 2k0 .. 2k0+513 they
-// read.  R = 2: Q = S~_2 S~_1 (S~_1 first); thread k writes stage-2 pair
-// (2k+1, 2k+2 mod m) from z at 2k .. 2k+3.  R = 1: stage-1 pair (2k, 2k+1).
+// Residual pass fused with the m side of the next transpose product.
+// r_x = Q z - b and r_y = (1+beta) r_x - beta r_x,prev with z_i = w[emb[i]]
+// (0 at inactive m-positions), then v = Sigma_m Q^T r_y written in m order.
+// A workgroup owns pairs k0 .. k0+B-1.  R = 2: Q = S~_2 S~_1; stage-2 pair j
+// yields r at (2j+1, 2j+2) from z at 2j .. 2j+3, and the Q^T of stage-1 pair
+// k reads r_y at 2k-1 .. 2k+2, so the workgroup also evaluates stage-2 pair
+// k0-1 (its left neighbour's, not stored) and gathers z at 2k0-2 ..
+// 2k0+2B+1.  r_y never leaves LDS.  R = 1: pair k only.  r_x,prev (rxp) and
+// r_x (rx) are separate buffers: a neighbour's r_x,prev is read for the halo
+// while its owner writes r_x.
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restrict__ w, const T* __restrict__ b,
-                                                               T* __restrict__ rx, T* __restrict__ ry, T beta,
-                                                               int init, MfTabs<T> tb, double* __restrict__ part,
-                                                               const GapState* __restrict__ gs, int stats) {
-    __shared__ T zl[2 * L1LS_BLOCK + 2];
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ w, const T* __restrict__ b,
+                                                           const T* __restrict__ rxp, T* __restrict__ rx,
+                                                           T* __restrict__ vm, T beta,
+                                                           int init, MfTabs<T> tb, double* __restrict__ part,
+                                                           const GapState* __restrict__ gs, int stats) {
+    constexpr int B = L1LS_BLOCK;
+    constexpr int H = (R == 2) ? 2 : 0;  // halo positions on the left
+    __shared__ T zl[2 * B + 2 * H];
+    __shared__ T yl[2 * B + H];  // r_y at positions 2k0 - H/2 .. (R = 2: from 2k0-1)
     const int32_t done = gs ? gs->done : 0;
     if (done) return;  // launch-uniform
     const int64_t m = tb.m, mp = m / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK;
-    for (int q = threadIdx.x; q < 2 * L1LS_BLOCK + 2; q += L1LS_BLOCK) {
-        const int64_t p = ring(2 * k0 + q, m);
+    const int64_t k0 = (int64_t)blockIdx.x * B;
+    for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
+        const int64_t p = ring(2 * k0 - H + q + m, m);
         const int32_t a = tb.emb[p];
         zl[q] = (a >= 0) ? ld_off32(w, a) : T(0);
     }
     __syncthreads();
-    const int64_t k = k0 + threadIdx.x;
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
     double v[3] = {0.0, 0.0, 0.0};
-    if (k < mp) {
-        const int t2 = 2 * (int)threadIdx.x;
-        int64_t pf, pg;
-        T rf, rg;
-        if (R == 2) {
-            T a, u1, u2, bb;
-            rot(cs_of(tb.csm[0], k), zl[t2], zl[t2 + 1], false, a, u1);                 // 2k+1 second of pair k
-            rot(cs_of(tb.csm[0], wrap(k + 1, mp)), zl[t2 + 2], zl[t2 + 3], false, u2, bb);  // 2k+2 first of k+1
-            rot(cs_of(tb.csm[1], k), u1, u2, false, rf, rg);
-            pf = 2 * k + 1;
-            pg = wrap(2 * k + 2, m);
-        } else {
-            pf = 2 * k;
-            pg = 2 * k + 1;
-            rot(cs_of(tb.csm[0], k), zl[t2], zl[t2 + 1], false, rf, rg);
+    if (R == 2) {
+        // own stage-2 pair k (t < B) and, in thread 0, the left neighbour pair k0-1
+        for (int h = 0; h < (t == 0 ? 2 : 1); ++h) {
+            const bool own = (h == 0);
+            const int64_t j = own ? k : wrap(k0 - 1, mp);
+            if (own && j >= mp) break;
+            const int q0 = own ? 2 * t + 2 : 0;  // z at 2j .. 2j+3
+            T a, u1, u2, bb, rf, rg;
+            rot(cs_of(tb.csm[0], j), zl[q0], zl[q0 + 1], false, a, u1);
+            rot(cs_of(tb.csm[0], wrap(j + 1, mp)), zl[q0 + 2], zl[q0 + 3], false, u2, bb);
+            rot(cs_of(tb.csm[1], j), u1, u2, false, rf, rg);
+            const int64_t ps[2] = {2 * j + 1, wrap(2 * j + 2, m)};
+            const T rr[2] = {rf, rg};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t i = ps[e];
+                const T bi = b[i];
+                const T r = rr[e] - bi;
+                const T yv = init ? r : (T(1) + beta) * r - beta * rxp[i];
+                yl[(own ? 2 * t + 2 : 0) + e] = yv;
+                if (own) {
+                    rx[i] = r;
+                    v[0] += (double)r * (double)r;
+                    v[1] += (double)yv * (double)yv;
+                    v[2] += (double)bi * (double)yv;
+                }
+            }
         }
-        const int64_t ps[2] = {pf, pg};
+    } else if (k < mp) {
+        T rf, rg;
+        rot(cs_of(tb.csm[0], k), zl[2 * t], zl[2 * t + 1], false, rf, rg);
+        const int64_t ps[2] = {2 * k, 2 * k + 1};
         const T rr[2] = {rf, rg};
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t i = ps[e];
             const T bi = b[i];
             const T r = rr[e] - bi;
-            const T yv = init ? r : (T(1) + beta) * r - beta * rx[i];
+            const T yv = init ? r : (T(1) + beta) * r - beta * rxp[i];
+            yl[2 * t + e] = yv;
             rx[i] = r;
-            ry[i] = yv;
             v[0] += (double)r * (double)r;
             v[1] += (double)yv * (double)yv;
             v[2] += (double)bi * (double)yv;
+        }
+    }
+    __syncthreads();
+    if (k < mp) {
+        // v for stage-1 pair k; pairs with both positions inactive are not read
+        const T s0 = tb.sig[2 * k], s1 = tb.sig[2 * k + 1];
+        if (s0 != T(0) || s1 != T(0)) {
+            T z0, z1;
+            if (R == 2) {
+                const T ym = yl[2 * t], yp = yl[2 * t + 3];  // r_y at 2k-1 and 2k+2
+                T a, bq;
+                rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, yl[2 * t + 1], true, a, bq);
+                const T z0n = bq;
+                rot(cs_of(tb.csm[1], k), yl[2 * t + 2], yp, true, a, bq);
+                z0 = z0n;
+                z1 = a;
+            } else {
+                z0 = yl[2 * t];
+                z1 = yl[2 * t + 1];
+            }
+            T o0, o1;
+            rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
+            vm[2 * k] = s0 * o0;
+            vm[2 * k + 1] = s1 * o1;
         }
     }
     if (!stats) return;
@@ -159,84 +208,97 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_q_residual(const T* __restric
     }
 }
 
-// v = Sigma_m Q^T y in m-stage order (sigma at m-positions, 0 where
-// inactive; pairs with both positions inactive are skipped, since no
-// n-position reads them).  R = 2: Q^T = S~_1^T S~_2^T (S~_2^T first); thread
-// k handles stage-1 pair (2k, 2k+1) from y at 2k-1 .. 2k+2.
+// Transpose pass fused with the n side of the next residual product.
+// g = G t with t_a = v[inv[a]]; y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
+// x_k = soft(y - g/L, tau/L) written to xo (a buffer other than xp: a
+// neighbour's x_{k-2} is read for the halo while its owner writes x_k); then
+// w = Sigma_n G^T x_k written in n order.  The halo is as in k_mf_res_qt
+// (R = 2: stage-2 pair k0-1 is evaluated again, not stored; t gathered at
+// 2k0-2 .. 2k0+2B+1).  x_k of the workgroup's pairs stays in LDS for G^T.
 template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ vm, MfTabs<T> tb,
-                                                       const GapState* __restrict__ gs) {
-    if (gs && gs->done) return;
-    const int64_t m = tb.m, mp = m / 2;
-    const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
-    if (k >= mp) return;
-    const T s0 = tb.sig[2 * k], s1 = tb.sig[2 * k + 1];
-    if (s0 == T(0) && s1 == T(0)) return;
-    T z0 = y[2 * k], z1 = y[2 * k + 1];
-    if (R == 2) {
-        const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
-        T a, b;
-        rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, z0, true, a, b);
-        const T z0n = b;
-        rot(cs_of(tb.csm[1], k), z1, yp, true, a, b);
-        z0 = z0n;
-        z1 = a;
-    }
-    T o0, o1;
-    rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
-    vm[2 * k] = s0 * o0;
-    vm[2 * k + 1] = s1 * o1;
-}
-
-// g = G t with t_a = v[inv[a]] gathered once per position into LDS (as in
-// k_mf_q_residual); then y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
-// x_k = soft(y - g/L, tau/L) written over x_{k-2}.  R = 2: G = S_2 S_1 (S_1
-// first); thread k writes stage-2 pair (2k+1, 2k+2 mod n) from t at 2k..2k+3.
-template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_prox(const T* __restrict__ vm, const T* __restrict__ xc,
-                                                           T* __restrict__ xp, T beta, T L, T thr, MfTabs<T> tb,
-                                                           double* __restrict__ part,
-                                                           const GapState* __restrict__ gs, int stats) {
-    __shared__ T tl[2 * L1LS_BLOCK + 2];
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__ vm, const T* __restrict__ xc,
+                                                            const T* __restrict__ xp, T* __restrict__ xo,
+                                                            T* __restrict__ w, T beta, T L,
+                                                            T thr, MfTabs<T> tb, double* __restrict__ part,
+                                                            const GapState* __restrict__ gs, int stats) {
+    constexpr int B = L1LS_BLOCK;
+    constexpr int H = (R == 2) ? 2 : 0;
+    __shared__ T tl[2 * B + 2 * H];
+    __shared__ T xl[2 * B + H];
     const int32_t done = gs ? gs->done : 0;
     if (done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK;
-    for (int q = threadIdx.x; q < 2 * L1LS_BLOCK + 2; q += L1LS_BLOCK) {
-        const int64_t p = ring(2 * k0 + q, n);
+    const int64_t k0 = (int64_t)blockIdx.x * B;
+    for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
+        const int64_t p = ring(2 * k0 - H + q + n, n);
         tl[q] = ld_off32(vm, tb.inv[p]);
     }
     __syncthreads();
-    const int64_t k = k0 + threadIdx.x;
-    double v[2] = {0.0, 0.0};
-    if (k < np) {
-        const int t2 = 2 * (int)threadIdx.x;
-        int64_t pf, pg;
-        T gf, gg;
-        if (R == 2) {
-            T a, u1, u2, bb;
-            rot(cs_of(tb.csn[0], k), tl[t2], tl[t2 + 1], false, a, u1);
-            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tl[t2 + 2], tl[t2 + 3], false, u2, bb);
-            rot(cs_of(tb.csn[1], k), u1, u2, false, gf, gg);
-            pf = 2 * k + 1;
-            pg = wrap(2 * k + 2, n);
-        } else {
-            pf = 2 * k;
-            pg = 2 * k + 1;
-            rot(cs_of(tb.csn[0], k), tl[t2], tl[t2 + 1], false, gf, gg);
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
+    double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
+    if (R == 2) {
+        for (int h = 0; h < (t == 0 ? 2 : 1); ++h) {
+            const bool own = (h == 0);
+            const int64_t j = own ? k : wrap(k0 - 1, np);
+            if (own && j >= np) break;
+            const int q0 = own ? 2 * t + 2 : 0;
+            T a, u1, u2, bb, gf, gg;
+            rot(cs_of(tb.csn[0], j), tl[q0], tl[q0 + 1], false, a, u1);
+            rot(cs_of(tb.csn[0], wrap(j + 1, np)), tl[q0 + 2], tl[q0 + 3], false, u2, bb);
+            rot(cs_of(tb.csn[1], j), u1, u2, false, gf, gg);
+            const int64_t ps[2] = {2 * j + 1, wrap(2 * j + 2, n)};
+            const T gv[2] = {gf, gg};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t jj = ps[e];
+                const T xcur = xc[jj];
+                const T y = xcur + beta * (xcur - xp[jj]);
+                const T xn = soft_threshold<T>(y - gv[e] / L, thr);
+                xl[(own ? 2 * t + 2 : 0) + e] = xn;
+                if (own) {
+                    xo[jj] = xn;
+                    v[0] += fabs((double)xn);
+                    v[1] = fmax(v[1], fabs((double)gv[e]));
+                }
+            }
         }
-        const int64_t ps[2] = {pf, pg};
+    } else if (k < np) {
+        T gf, gg;
+        rot(cs_of(tb.csn[0], k), tl[2 * t], tl[2 * t + 1], false, gf, gg);
+        const int64_t ps[2] = {2 * k, 2 * k + 1};
         const T gv[2] = {gf, gg};
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int64_t j = ps[e];
-            const T xcur = xc[j];
-            const T y = xcur + beta * (xcur - xp[j]);
+            const int64_t jj = ps[e];
+            const T xcur = xc[jj];
+            const T y = xcur + beta * (xcur - xp[jj]);
             const T xn = soft_threshold<T>(y - gv[e] / L, thr);
-            xp[j] = xn;
+            xl[2 * t + e] = xn;
+            xo[jj] = xn;
             v[0] += fabs((double)xn);
             v[1] = fmax(v[1], fabs((double)gv[e]));
         }
+    }
+    __syncthreads();
+    if (k < np) {
+        T z0, z1;
+        if (R == 2) {
+            const T xm = xl[2 * t], xq = xl[2 * t + 3];  // x_k at 2k-1 and 2k+2
+            T a, bq;
+            rot(cs_of(tb.csn[1], wrap(k - 1, np)), xm, xl[2 * t + 1], true, a, bq);
+            const T z0n = bq;
+            rot(cs_of(tb.csn[1], k), xl[2 * t + 2], xq, true, a, bq);
+            z0 = z0n;
+            z1 = a;
+        } else {
+            z0 = xl[2 * t];
+            z1 = xl[2 * t + 1];
+        }
+        T o0, o1;
+        rot(cs_of(tb.csn[0], k), z0, z1, true, o0, o1);
+        w[2 * k] = tb.sig_n[2 * k] * o0;
+        w[2 * k + 1] = tb.sig_n[2 * k + 1] * o1;
     }
     if (!stats) return;
     block_reduce_stats<2, 1>(v);
@@ -347,41 +409,45 @@ l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
 int mf_grid(int64_t pairs) { return (int)std::max<int64_t>(1, (pairs + L1LS_BLOCK - 1) / L1LS_BLOCK); }
 
 // w has n entries (n order), vt has m entries (m order).
+// Residual pass: on the first pass (init) w = Sigma_n G^T x is formed first;
+// afterwards it comes from the preceding transpose pass.  vt (m entries)
+// receives Sigma_m Q^T r_y for the next transpose pass; w has n entries.
 template <typename T>
-void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, T* rx, T* ry, T beta, int init,
-                        double* part, const GapState* gs, int stats, hipStream_t s) {
+void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, const T* rx_prev, T* rx, T* vt,
+                        T beta, int init, double* part, const GapState* gs, int stats, hipStream_t s) {
     const MfTabs<T> tb = tabs_of<T>(I);
     if (I->rounds == 2) {
-        hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
-        hipLaunchKernelGGL((k_mf_q_residual<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx, ry,
-                           beta, init, tb, part, gs, stats);
+        if (init) hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        hipLaunchKernelGGL((k_mf_res_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
+                           vt, beta, init, tb, part, gs, stats);
     } else {
-        hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
-        hipLaunchKernelGGL((k_mf_q_residual<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx, ry,
-                           beta, init, tb, part, gs, stats);
+        if (init) hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        hipLaunchKernelGGL((k_mf_res_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
+                           vt, beta, init, tb, part, gs, stats);
     }
 }
 
+// Transpose pass (with prox) from vt; also forms w = Sigma_n G^T x_k for the
+// residual pass that follows.
 template <typename T>
-void mf_transpose_launch(const l1ls_instance* I, const T* ry, T* vt, const T* xc, T* xp, T beta, T L, T thr,
-                         double* part, const GapState* gs, int stats, hipStream_t s) {
+void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
+                         T thr, double* part, const GapState* gs, int stats, hipStream_t s) {
     const MfTabs<T> tb = tabs_of<T>(I);
-    if (I->rounds == 2) {
-        hipLaunchKernelGGL((k_mf_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, ry, vt, tb, gs);
-        hipLaunchKernelGGL((k_mf_g_prox<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, beta, L,
-                           thr, tb, part, gs, stats);
-    } else {
-        hipLaunchKernelGGL((k_mf_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, ry, vt, tb, gs);
-        hipLaunchKernelGGL((k_mf_g_prox<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, beta, L,
-                           thr, tb, part, gs, stats);
-    }
+    if (I->rounds == 2)
+        hipLaunchKernelGGL((k_mf_prox_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, xo,
+                           w, beta, L, thr, tb, part, gs, stats);
+    else
+        hipLaunchKernelGGL((k_mf_prox_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, xo,
+                           w, beta, L, thr, tb, part, gs, stats);
 }
 
-template void mf_residual_launch<float>(const l1ls_instance*, const float*, float*, const float*, float*, float*,
-                                        float, int, double*, const GapState*, int, hipStream_t);
-template void mf_residual_launch<double>(const l1ls_instance*, const double*, double*, const double*, double*,
-                                         double*, double, int, double*, const GapState*, int, hipStream_t);
-template void mf_transpose_launch<float>(const l1ls_instance*, const float*, float*, const float*, float*, float,
-                                         float, float, double*, const GapState*, int, hipStream_t);
-template void mf_transpose_launch<double>(const l1ls_instance*, const double*, double*, const double*, double*,
-                                          double, double, double, double*, const GapState*, int, hipStream_t);
+template void mf_residual_launch<float>(const l1ls_instance*, const float*, float*, const float*, const float*,
+                                        float*, float*, float, int, double*, const GapState*, int, hipStream_t);
+template void mf_residual_launch<double>(const l1ls_instance*, const double*, double*, const double*,
+                                         const double*, double*, double*, double, int, double*, const GapState*, int,
+                                         hipStream_t);
+template void mf_transpose_launch<float>(const l1ls_instance*, const float*, float*, const float*, const float*,
+                                         float*, float, float, float, double*, const GapState*, int, hipStream_t);
+template void mf_transpose_launch<double>(const l1ls_instance*, const double*, double*, const double*,
+                                          const double*, double*, double, double, double, double*, const GapState*,
+                                          int, hipStream_t);
