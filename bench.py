@@ -146,16 +146,16 @@ def algorithmic_bytes(m, n, nnz, es=4, ie=4):
 def mf_bytes(m, n, es=4):
     """Algorithmic bytes of one matrix-free FISTA iteration (FP32, two stages).
 
-    residual: n side reads x (n) and two stages of (c, s) (n/2 pairs each),
-    writes w (n); m side reads emb (int32, m), sigma (m), gathers w once (n),
-    two stages of (c, s) (m/2 pairs each), b and r_x, writes r_x and r_y.
-    transpose: m side reads r_y (m), (c, s) tables, sigma, writes v (m);
-    n side reads inv (int32, n), gathers v once (n), (c, s) tables,
-    x_{k-1}, x_{k-2}, writes x_k.
+    transpose pass fused with G^T (n side): inv (int32, n), v gathered once (n),
+    the n-side (c, s) of both stages (n/2 pairs each), x_{k-1} and x_{k-2}
+    read, x_k written, sigma (n), w written (n).
+    residual pass fused with Q^T (m side): emb (int32, m), w gathered once (n),
+    the m-side (c, s) of both stages, b and r_x,prev read, r_x written, sigma
+    (m), v written (m).  r_y stays on chip.
     """
-    res = es * (n + 2 * n + n) + 4 * m + es * m + es * n + es * 2 * m + es * 2 * m + es * 2 * m
-    tr = es * (m + 2 * m + m + m) + 4 * n + es * n + es * 2 * n + es * 3 * n
-    return res + tr
+    tr = 4 * n + es * n + es * 2 * n + es * 3 * n + es * n + es * n
+    res = 4 * m + es * n + es * 2 * m + es * 2 * m + es * m + es * m + es * m
+    return tr + res
 
 
 def cpu_baseline(m, n, kappa, s, tau, seed, rounds, budget_s):

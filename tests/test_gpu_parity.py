@@ -190,6 +190,21 @@ def test_fista_trajectory_fp64_matrix_free(cfg, iters):
     assert rep["iterations"] == iters
 
 
+MF_MULTIBLOCK = (4096, 2050, 1e3, 20, 1.0, 23, 2)   # several 256-pair workgroups per side, last one ragged
+
+
+@pytest.mark.parametrize("iters", [1, 2, 25])
+def test_fista_trajectory_fp64_matrix_free_multiblock(iters):
+    # The fused matrix-free passes recompute a neighbour workgroup's stage pair
+    # at each workgroup edge; both sides here span several workgroups.
+    g, o, A = pair(MF_MULTIBLOCK)
+    x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=1, precision=L.F64,
+                                   op=L.OP_MATRIX_FREE)
+    ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(x.cpu().numpy() - ref).max() <= 1e-11 * scale
+
+
 @pytest.mark.parametrize("cfg", CASES[:2])
 def test_fista_matrix_free_fp32_equals_stored_gap(cfg):
     # FP32 bulk on both operators: same tolerance to the FP64 oracle, and the
