@@ -169,6 +169,9 @@ typedef struct {
     int32_t max_backtrack; /* <= 0: 50                                          */
     int32_t pcg_maxit;     /* <= 0: 1000                                        */
     int32_t hessian;       /* 0: primal-dual diagonal, 1: exact primal Hessian  */
+    /* Batch only: rounds of 4 tiles per workgroup task; 0: chosen per slot
+     * size by the library's autotuner (timed on a slot's first pass). */
+    int32_t tile_chunk;
 } l1ls_solve_opts;
 
 typedef struct {

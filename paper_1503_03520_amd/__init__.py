@@ -60,7 +60,7 @@ class SolveOpts(ctypes.Structure):
         ("polish", ctypes.c_int32), ("L", ctypes.c_double), ("x0_dev", ctypes.c_void_p),
         ("stream", ctypes.c_void_p), ("time_kernels", ctypes.c_int32),
         ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
-        ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32),
+        ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
     ]
 
 

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -43,6 +45,7 @@ struct BInst {  // static per slot (device copy refreshed on add/remove)
     double tau, L, tol;
     int32_t nt1, nt2;
     int32_t check_every, active;
+    int32_t admit_mod, pad2;  // admit mod check_every
 };
 
 struct BState {  // written by the gap kernel only
@@ -51,9 +54,16 @@ struct BState {  // written by the gap kernel only
     int32_t done, converged, nonfinite, pad;
 };
 
-struct BTile {
+// A workgroup's share of one slot's pass: `steps` rounds of 4 consecutive
+// 64-row (64-column) tiles from row (column) `first`; wave w takes tile
+// 4 s + w of round s.  The number of rounds per task is the tile schedule,
+// chosen per slot size by the autotuner (more rounds amortise the slot
+// lookups of a workgroup; fewer keep small slots spread over more CUs).
+struct BTask {
     int32_t slot;
-    int32_t first;  // first row (column) of the 64-tile
+    int32_t first;
+    int32_t steps;
+    int32_t pad;
 };
 
 namespace {
@@ -64,140 +74,181 @@ __device__ __forceinline__ bool slot_live(const BInst& I, const BState& S, int64
     return I.active && !S.done && *kn >= 1 && (I.max_iter <= 0 || *kn <= I.max_iter);
 }
 
-// Transpose pass of global iteration G: x_k = soft(y_k - A^T r_y,k / L), with
-// y_k = x_{k-1} + beta_{k-1} (x_{k-1} - x_{k-2}).
-__global__ __launch_bounds__(L1LS_BLOCK) void kb_transpose(const BTile* __restrict__ tiles, int32_t ntiles,
-                                                           const BInst* __restrict__ bi,
-                                                           const BState* __restrict__ bs,
-                                                           const float* __restrict__ btab, int64_t G) {
-    __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
-    const int lane = threadIdx.x % L1LS_WAVE;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
-    const int32_t tile = (int32_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid;
-    bool run = false;
-    int64_t kn = 0;
-    const BTile tl = tiles[tile < ntiles ? tile : 0];
-    const BInst& I = bi[tl.slot];
-    if (tile < ntiles) run = slot_live(I, bs[tl.slot], G, &kn);
-    const int64_t j = (int64_t)tl.first + lane;
-    const bool live = run && j < I.n;
-    const float* __restrict__ xc = I.x[(kn - 1) & 1];
-    float* __restrict__ xp = I.x[kn & 1];
+// k mod check_every for the slot, from gmod = G mod check_every (32-bit).
+__device__ __forceinline__ int slot_phase(const BInst& I, int gmod) {
+    const int r = gmod - I.admit_mod;
+    return r < 0 ? r + I.check_every : r;
+}
+
+// One 64-column tile of the transpose pass (pointers as restrict parameters:
+// inlined, the compiler keeps their no-alias scopes).
+__device__ __forceinline__ void transpose_tile(const int32_t* __restrict__ ptr, const int32_t* __restrict__ row,
+                                               const float* __restrict__ val, const float* __restrict__ ry,
+                                               const float* __restrict__ xc, float* __restrict__ xp,
+                                               double* __restrict__ part2, int64_t n, int64_t first, float beta,
+                                               float Lf, float thr, bool stats, float* lds, int lane) {
+    const bool run = first < n;  // wave-uniform
+    const int64_t j = first + lane;
+    const bool live = run && j < n;
     int32_t pb = 0, pe = 0;
     float xcur = 0.f, xprev = 0.f;
     if (live) {
-        pb = I.csc_ptr[j];
-        pe = I.csc_ptr[j + 1];
+        pb = ptr[j];
+        pe = ptr[j + 1];
         xcur = __builtin_nontemporal_load(xc + j);
         xprev = __builtin_nontemporal_load(xp + j);
     }
     if (run) {
-        const int lastlane = (tl.first + kTile <= I.n) ? kTile - 1 : (int)(I.n - tl.first - 1);
+        const int lastlane = (first + kTile <= n) ? kTile - 1 : (int)(n - first - 1);
         const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
         const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-        tile_products<float, 16>(I.csc_row, I.csc_val, I.ry, beg, end - beg, lds[wid], lane);
+        tile_products<float, 16>(row, val, ry, beg, end - beg, lds, lane);
         pb -= beg;
         pe -= beg;
     }
     __syncthreads();
-    if (!run) return;
     double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
     if (live) {
         float acc = 0.f;
-        for (int32_t q = pb; q < pe; ++q) acc += lds[wid][q];
-        const float beta = btab[kn - 1];
+        for (int32_t q = pb; q < pe; ++q) acc += lds[q];
         const float y = xcur + beta * (xcur - xprev);
-        const float xn = soft_threshold<float>(y - acc / (float)I.L, (float)(I.tau / I.L));
+        const float xn = soft_threshold<float>(y - acc / Lf, thr);
         st_stream(xp + j, xn);
         v[0] = fabs((double)xn);
         v[1] = fabs((double)acc);
     }
-    if (kn % I.check_every != 0) return;  // wave-uniform: no gap test reads this pass
-    v[0] = wave_sum(v[0]);
-    v[1] = wave_max(v[1]);
-    if (lane == 0) {
-        double* p = I.part2 + 2 * (size_t)(tl.first / kTile);
-        p[0] = v[1];
-        p[1] = v[0];
+    if (run && stats) {
+        v[0] = wave_sum(v[0]);
+        v[1] = wave_max(v[1]);
+        if (lane == 0) {
+            double* p = part2 + 2 * (size_t)(first / kTile);
+            p[0] = v[1];
+            p[1] = v[0];
+        }
     }
+    __syncthreads();  // the wave's LDS slice is rewritten by the next round
+}
+
+// Transpose pass of global iteration G: x_k = soft(y_k - A^T r_y,k / L), with
+// y_k = x_{k-1} + beta_{k-1} (x_{k-1} - x_{k-2}).  ONE: every task is a single
+// round (no loop; the register budget of the single-instance kernel).  The
+// occupancy hints are the largest without register spills.
+template <bool ONE>
+__global__ __launch_bounds__(L1LS_BLOCK, ONE ? 7 : 5) void kb_transpose(const BTask* __restrict__ tasks,
+                                                           const BInst* __restrict__ bi,
+                                                           const BState* __restrict__ bs,
+                                                           const float* __restrict__ btab, int64_t G, int gmod) {
+    __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
+    const int lane = threadIdx.x % L1LS_WAVE;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
+    const BTask tk = tasks[blockIdx.x];
+    const BInst& I = bi[tk.slot];
+    int64_t kn = 0;
+    if (!slot_live(I, bs[tk.slot], G, &kn)) return;  // block-uniform
+    const bool stats = slot_phase(I, gmod) == 0;    // a gap test reads this pass
+    const float beta = btab[kn - 1];
+    const float Lf = (float)I.L, thr = (float)(I.tau / I.L);
+    const int steps = ONE ? 1 : tk.steps;
+    for (int st = 0; st < steps; ++st)
+        transpose_tile(I.csc_ptr, I.csc_row, I.csc_val, I.ry, I.x[(kn - 1) & 1], I.x[kn & 1], I.part2, I.n,
+                       (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, Lf, thr, stats, lds[wid], lane);
+}
+
+// One 64-row tile of the residual pass (mode 1: first pass, no momentum).
+__device__ __forceinline__ void residual_tile(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                              const float* __restrict__ val, const float* __restrict__ x,
+                                              const float* __restrict__ bvec, float* __restrict__ rx,
+                                              float* __restrict__ ry, double* __restrict__ part1, int64_t m,
+                                              int64_t first, float beta, int mode, bool stats, float* lds,
+                                              int lane) {
+    const bool run = first < m;  // wave-uniform
+    const int64_t i = first + lane;
+    const bool live = run && i < m;
+    int32_t pb = 0, pe = 0;
+    float b = 0.f, rprev = 0.f;
+    if (live) {
+        pb = ptr[i];
+        pe = ptr[i + 1];
+        b = __builtin_nontemporal_load(bvec + i);
+        if (mode == 0) rprev = __builtin_nontemporal_load(rx + i);
+    }
+    if (run) {
+        const int lastlane = (first + kTile <= m) ? kTile - 1 : (int)(m - first - 1);
+        const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
+        const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
+        tile_products<float, 10>(col, val, x, beg, end - beg, lds, lane);
+        pb -= beg;
+        pe -= beg;
+    }
+    __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        float acc = 0.f;
+        for (int32_t q = pb; q < pe; ++q) acc += lds[q];
+        const float r = acc - b;
+        const float yv = (mode == 1) ? r : (1.f + beta) * r - beta * rprev;
+        st_stream(rx + i, r);
+        st_stream(ry + i, yv);
+        v[0] = (double)r * (double)r;
+        v[1] = (double)yv * (double)yv;
+        v[2] = (double)b * (double)yv;
+    }
+    if (run && stats) {
+        for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+        if (lane == 0) {
+            double* p = part1 + (size_t)(first / kTile) * 3;
+            p[0] = v[0];
+            p[1] = v[1];
+            p[2] = v[2];
+        }
+    }
+    __syncthreads();  // the wave's LDS slice is rewritten by the next round
 }
 
 // Residual pass of global iteration G (mode 0): r_x,k = A x_k - b and
 // r_y,k+1 = (1 + beta_k) r_x,k - beta_k r_x,k-1; or, for the slots admitted
 // at G (mode 1), the first pass r_x,0 = r_y,1 = A x_0 - b.  Partial sums go
 // to parity k & 1 of the slot's buffer (0 for mode 1).
-__global__ __launch_bounds__(L1LS_BLOCK) void kb_residual(const BTile* __restrict__ tiles, int32_t ntiles,
+template <bool ONE>
+__global__ __launch_bounds__(L1LS_BLOCK, 8) void kb_residual(const BTask* __restrict__ tasks,
                                                           const BInst* __restrict__ bi,
                                                           const BState* __restrict__ bs,
-                                                          const float* __restrict__ btab, int64_t G, int mode) {
+                                                          const float* __restrict__ btab, int64_t G, int gmod,
+                                                          int mode) {
     __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
-    const int32_t tile = (int32_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid;
-    bool run = false;
+    const BTask tk = tasks[blockIdx.x];
+    const BInst& I = bi[tk.slot];
     int64_t kn = 0;
-    const BTile tl = tiles[tile < ntiles ? tile : 0];
-    const BInst& I = bi[tl.slot];
-    if (tile < ntiles) {
-        if (mode == 1)
-            run = I.active && I.admit == G;
-        else
-            run = slot_live(I, bs[tl.slot], G, &kn);
-    }
-    const int64_t i = (int64_t)tl.first + lane;
-    const bool live = run && i < I.m;
-    const float* __restrict__ x = I.x[kn & 1];
-    int32_t pb = 0, pe = 0;
-    float b = 0.f, rprev = 0.f;
-    if (live) {
-        pb = I.csr_ptr[i];
-        pe = I.csr_ptr[i + 1];
-        b = __builtin_nontemporal_load(I.b + i);
-        if (mode == 0) rprev = __builtin_nontemporal_load(I.rx + i);
-    }
-    if (run) {
-        const int lastlane = (tl.first + kTile <= I.m) ? kTile - 1 : (int)(I.m - tl.first - 1);
-        const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
-        const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-        tile_products<float, 10>(I.csr_col, I.csr_val, x, beg, end - beg, lds[wid], lane);
-        pb -= beg;
-        pe -= beg;
-    }
-    __syncthreads();
-    if (!run) return;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (live) {
-        float acc = 0.f;
-        for (int32_t q = pb; q < pe; ++q) acc += lds[wid][q];
-        const float beta = (mode == 1) ? 0.f : btab[kn];
-        const float r = acc - b;
-        const float yv = (mode == 1) ? r : (1.f + beta) * r - beta * rprev;
-        st_stream(I.rx + i, r);
-        st_stream(I.ry + i, yv);
-        v[0] = (double)r * (double)r;
-        v[1] = (double)yv * (double)yv;
-        v[2] = (double)b * (double)yv;
+    if (mode == 1) {
+        if (!(I.active && I.admit == G)) return;  // block-uniform
+    } else if (!slot_live(I, bs[tk.slot], G, &kn)) {
+        return;
     }
     // a gap test at k reads ||r_x,k|| from this pass, and the r_y terms of
     // the pass of k - 1 (the point whose gradient the transpose pass of k used)
-    const int ce = I.check_every;
-    if (mode == 0 && kn % ce != 0 && (kn + 1) % ce != 0) return;  // wave-uniform
-    for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
-    if (lane == 0) {
-        double* p = I.part1 + ((size_t)(kn & 1) * I.nt1 + (size_t)(tl.first / kTile)) * 3;
-        p[0] = v[0];
-        p[1] = v[1];
-        p[2] = v[2];
+    bool stats = true;
+    if (mode == 0) {
+        const int ph = slot_phase(I, gmod);
+        stats = (ph == 0 || ph == I.check_every - 1);
     }
+    const float beta = (mode == 1) ? 0.f : btab[kn];
+    double* part1 = I.part1 + (size_t)(kn & 1) * I.nt1 * 3;
+    const int steps = ONE ? 1 : tk.steps;
+    for (int st = 0; st < steps; ++st)
+        residual_tile(I.csr_ptr, I.csr_col, I.csr_val, I.x[kn & 1], I.b, I.rx, I.ry, part1, I.m,
+                      (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, mode, stats, lds[wid], lane);
 }
 
 // One workgroup per slot: the duality gap on the slot's check iterations
 // (the terms of k_gap, from the slot's own partials in tile order).
-__global__ __launch_bounds__(256) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G) {
+__global__ __launch_bounds__(256) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G,
+                                              int gmod) {
     const BInst& I = bi[blockIdx.x];
     BState& S = bs[blockIdx.x];
     int64_t kn = 0;
-    if (!slot_live(I, S, G, &kn) || kn % I.check_every != 0) return;  // block-uniform
+    if (!slot_live(I, S, G, &kn) || slot_phase(I, gmod) != 0) return;  // block-uniform
     const double* cur = I.part1 + (size_t)(kn & 1) * 3 * I.nt1;
     const double* prev = I.part1 + (size_t)((kn - 1) & 1) * 3 * I.nt1;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rr, ryy, bry, l1 | ginf
@@ -267,9 +318,11 @@ struct l1ls_batch {
     std::vector<void*> buf;                   // per-slot device block (iterates + partials)
     BInst* dinst = nullptr;
     BState* dstate = nullptr;
-    BTile* dt1 = nullptr;
-    BTile* dt2 = nullptr;
+    BTask* dt1 = nullptr;                     // residual-pass tasks
+    BTask* dt2 = nullptr;                     // transpose-pass tasks
     int32_t cap1 = 0, cap2 = 0, nt1 = 0, nt2 = 0;
+    std::vector<int32_t> steps;               // per slot: rounds per task (tile schedule)
+    bool one = true;                          // every task has one round
     float* btab = nullptr;                    // beta_k, k = 0 .. nbeta-1
     int64_t nbeta = 0;
     bool tables_dirty = false, init_pending = false;
@@ -286,16 +339,101 @@ size_t slot_bytes(int64_t m, int64_t n) {
     return slot_fbytes(m, n) + (size_t)(6 * tiles_of(m) + 2 * tiles_of(n)) * sizeof(double);
 }
 
+// ---- tile-schedule autotuner ------------------------------------------------
+// Rounds per task for a slot, by the size class ceil(log2(m)): on the first
+// slot of a class in the process, its first residual pass (r = A x_0 - b,
+// which the batch computes anyway) is timed with 1, 2, 4 and 8 rounds per
+// task and the fastest is kept for the class.
+constexpr int kStepChoices[4] = {1, 2, 4, 8};
+std::mutex g_sched_mu;
+std::map<int, int32_t> g_sched;  // size class -> rounds per task
+
+int size_class(int64_t rows) {
+    int c = 0;
+    while (((int64_t)1 << c) < rows) ++c;
+    return c;
+}
+
+void push_tasks(std::vector<BTask>& out, int slot, int64_t rows, int32_t steps) {
+    const int64_t per = (int64_t)4 * steps * kTile;  // rows per task
+    for (int64_t r = 0; r < rows; r += per) out.push_back(BTask{slot, (int32_t)r, steps, 0});
+}
+
+// dinst must already hold the slot (admitted at B->G, init not yet run).
+l1ls_status tune_steps(l1ls_batch* B, int slot, int32_t* best) {
+    const BInst& h = B->hinst[slot];
+    BTask* dt = nullptr;
+    const int64_t max_tasks = (h.m + 4 * kTile - 1) / (4 * kTile);
+    L1LS_TRY(B->arena.alloc(&dt, (size_t)max_tasks));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    *best = 1;
+    l1ls_status st = L1LS_OK;
+    for (int c = 0; c < 4 && st == L1LS_OK; ++c) {
+        std::vector<BTask> t;
+        push_tasks(t, slot, h.m, kStepChoices[c]);
+        if (hipMemcpyAsync(dt, t.data(), t.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream) != hipSuccess) {
+            st = L1LS_E_HIP;
+            break;
+        }
+        float ms = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {  // first launch warms up, two timed
+            if (rep == 1) (void)hipEventRecord(e0, B->stream);
+            if (kStepChoices[c] == 1)
+                hipLaunchKernelGGL(kb_residual<true>, dim3((unsigned)t.size()), dim3(L1LS_BLOCK), 0, B->stream, dt,
+                                   B->dinst, B->dstate, B->btab, B->G, 0, 1);
+            else
+                hipLaunchKernelGGL(kb_residual<false>, dim3((unsigned)t.size()), dim3(L1LS_BLOCK), 0, B->stream, dt,
+                                   B->dinst, B->dstate, B->btab, B->G, 0, 1);
+        }
+        (void)hipEventRecord(e1, B->stream);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = L1LS_E_HIP;
+            break;
+        }
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            *best = kStepChoices[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 l1ls_status rebuild_tables(l1ls_batch* B) {
-    std::vector<BTile> t1, t2;
+    HIP_TRY(hipMemcpyAsync(B->dinst, B->hinst.data(), B->capacity * sizeof(BInst), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    std::vector<BTask> t1, t2;
     for (int s = 0; s < B->capacity; ++s) {
         if (!B->inst[s]) continue;
         const BInst& hi = B->hinst[s];
-        for (int64_t r = 0; r < hi.m; r += kTile) t1.push_back(BTile{s, (int32_t)r});
-        for (int64_t c = 0; c < hi.n; c += kTile) t2.push_back(BTile{s, (int32_t)c});
+        if (B->steps[s] == 0) {
+            if (B->o.tile_chunk > 0) {
+                B->steps[s] = B->o.tile_chunk;
+            } else {
+                const int cls = size_class(hi.m);
+                int32_t v = 0;
+                {
+                    std::lock_guard<std::mutex> lk(g_sched_mu);
+                    auto it = g_sched.find(cls);
+                    if (it != g_sched.end()) v = it->second;
+                }
+                if (v == 0 && hi.admit == B->G) {  // a fresh slot: its first pass can be timed
+                    L1LS_TRY(tune_steps(B, s, &v));
+                    std::lock_guard<std::mutex> lk(g_sched_mu);
+                    g_sched[cls] = v;
+                }
+                B->steps[s] = v > 0 ? v : 1;
+            }
+        }
+        push_tasks(t1, s, hi.m, B->steps[s]);
+        push_tasks(t2, s, hi.n, B->steps[s]);
     }
     if ((int32_t)t1.size() > B->cap1 || (int32_t)t2.size() > B->cap2) {
-        // grow the tile tables (old ones stay in the arena until destroy)
+        // grow the task tables (old ones stay in the arena until destroy)
         B->cap1 = std::max<int32_t>((int32_t)t1.size(), 2 * B->cap1);
         B->cap2 = std::max<int32_t>((int32_t)t2.size(), 2 * B->cap2);
         L1LS_TRY(B->arena.alloc(&B->dt1, B->cap1));
@@ -303,11 +441,12 @@ l1ls_status rebuild_tables(l1ls_batch* B) {
     }
     B->nt1 = (int32_t)t1.size();
     B->nt2 = (int32_t)t2.size();
+    B->one = true;
+    for (const BTask& t : t1) B->one = B->one && t.steps == 1;
     if (!t1.empty())
-        HIP_TRY(hipMemcpyAsync(B->dt1, t1.data(), t1.size() * sizeof(BTile), hipMemcpyHostToDevice, B->stream));
+        HIP_TRY(hipMemcpyAsync(B->dt1, t1.data(), t1.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream));
     if (!t2.empty())
-        HIP_TRY(hipMemcpyAsync(B->dt2, t2.data(), t2.size() * sizeof(BTile), hipMemcpyHostToDevice, B->stream));
-    HIP_TRY(hipMemcpyAsync(B->dinst, B->hinst.data(), B->capacity * sizeof(BInst), hipMemcpyHostToDevice, B->stream));
+        HIP_TRY(hipMemcpyAsync(B->dt2, t2.data(), t2.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream));
     // the copies read host vectors that go out of scope: wait for them
     HIP_TRY(hipStreamSynchronize(B->stream));
     B->tables_dirty = false;
@@ -337,9 +476,12 @@ l1ls_status ensure_beta(l1ls_batch* B, int64_t need) {
 
 l1ls_status run_init(l1ls_batch* B) {
     if (B->nt1 > 0) {
-        const int g1 = (B->nt1 + 3) / 4;
-        hipLaunchKernelGGL(kb_residual, dim3(g1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->nt1, B->dinst,
-                           B->dstate, B->btab, B->G, 1);
+        if (B->one)
+            hipLaunchKernelGGL(kb_residual<true>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
+                               B->dstate, B->btab, B->G, 0, 1);
+        else
+            hipLaunchKernelGGL(kb_residual<false>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
+                               B->dstate, B->btab, B->G, 0, 1);
         HIP_TRY(hipGetLastError());
     }
     B->init_pending = false;
@@ -366,6 +508,7 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     *out = nullptr;
     if (opts->precision != L1LS_F32 || opts->op != L1LS_OP_STORED) return L1LS_E_UNSUPPORTED;
     if (opts->check_every < 1 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
+    if (opts->tile_chunk < 0 || opts->tile_chunk > 64) return L1LS_E_ARG;
     l1ls_batch* B = new l1ls_batch();
     B->capacity = capacity;
     B->budget = hbm_budget_bytes;
@@ -375,6 +518,7 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     B->hinst.assign(capacity, BInst{});
     B->footprint.assign(capacity, 0);
     B->buf.assign(capacity, nullptr);
+    B->steps.assign(capacity, 0);
     auto fail = [&](l1ls_status s) {
         B->arena.release();
         delete B;
@@ -448,6 +592,7 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     h.nt1 = (int32_t)tiles_of(m);
     h.nt2 = (int32_t)tiles_of(n);
     h.check_every = B->o.check_every;
+    h.admit_mod = (int32_t)(B->G % B->o.check_every);
     h.active = 1;
     B->inst[slot] = I;
     B->buf[slot] = blk;
@@ -487,15 +632,22 @@ extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {
             phase[(size_t)(B->hinst[s].admit % ce)] = 1;
         }
     L1LS_TRY(ensure_beta(B, B->G + iters - oldest + 2));
-    const int g1 = (B->nt1 + 3) / 4, g2 = (B->nt2 + 3) / 4;
     for (int64_t q = 0; q < iters; ++q) {
         const int64_t G = ++B->G;
-        hipLaunchKernelGGL(kb_transpose, dim3(g2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->nt2, B->dinst,
-                           B->dstate, B->btab, G);
-        hipLaunchKernelGGL(kb_residual, dim3(g1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->nt1, B->dinst,
-                           B->dstate, B->btab, G, 0);
-        if (phase[(size_t)(G % ce)])
-            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, G);
+        const int gmod = (int)(G % ce);
+        if (B->one) {
+            hipLaunchKernelGGL(kb_transpose<true>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->dinst,
+                               B->dstate, B->btab, G, gmod);
+            hipLaunchKernelGGL(kb_residual<true>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
+                               B->dstate, B->btab, G, gmod, 0);
+        } else {
+            hipLaunchKernelGGL(kb_transpose<false>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->dinst,
+                               B->dstate, B->btab, G, gmod);
+            hipLaunchKernelGGL(kb_residual<false>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
+                               B->dstate, B->btab, G, gmod, 0);
+        }
+        if (phase[(size_t)gmod])
+            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, G, gmod);
     }
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
@@ -551,6 +703,7 @@ extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
     B->footprint[slot] = 0;
     B->inst[slot] = nullptr;
     B->hinst[slot] = BInst{};
+    B->steps[slot] = 0;
     B->tables_dirty = true;
     return L1LS_OK;
 }

@@ -316,6 +316,7 @@ extern "C" void l1ls_solve_opts_default(l1ls_solve_opts* o) {
     o->max_backtrack = 50;
     o->pcg_maxit = 1000;
     o->hessian = 0;
+    o->tile_chunk = 0;
 }
 
 extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solve_opts* opts, l1ls_fista** out) {

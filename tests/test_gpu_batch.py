@@ -140,3 +140,20 @@ def test_batched_solve_converges_all():
         assert rep["converged"] == 1 and rep["rel_gap"] <= 1e-5
         P, D, gap = L.l1ls_objective_gap(inst, inst.params["tau"], x)
         assert gap <= 2e-5      # FP64 certificate of the FP32 iterate
+
+
+def test_tile_schedule_does_not_change_results():
+    # rounds of tiles per workgroup task (fixed, or chosen by the autotuner)
+    # only regroup the same per-tile work
+    iters = 40
+    insts = [gen(c) for c in CFGS[:4]]
+    ref = None
+    for chunk in (0, 1, 3, 8):
+        xs, reps, _ = L.l1ls_solve_fista_batched(insts, max_iter=iters, rel_gap_tol=0.0, check_every=8,
+                                                 precision=L.F32, tile_chunk=chunk)
+        if ref is None:
+            ref = (xs, reps)
+            continue
+        for a, b, ra, rb in zip(ref[0], xs, ref[1], reps):
+            assert torch.equal(a, b), chunk
+            assert ra["rel_gap"] == rb["rel_gap"] and ra["primal"] == rb["primal"], chunk
