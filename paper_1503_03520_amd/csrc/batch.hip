@@ -86,7 +86,7 @@ __device__ __forceinline__ void transpose_tile(const int32_t* __restrict__ ptr, 
                                                const float* __restrict__ val, const float* __restrict__ ry,
                                                const float* __restrict__ xc, float* __restrict__ xp,
                                                double* __restrict__ part2, int64_t n, int64_t first, float beta,
-                                               float Lf, float thr, bool stats, float* lds, int lane) {
+                                               float Lf, float thr, bool stats, bool more, float* lds, int lane) {
     const bool run = first < n;  // wave-uniform
     const int64_t j = first + lane;
     const bool live = run && j < n;
@@ -126,7 +126,7 @@ __device__ __forceinline__ void transpose_tile(const int32_t* __restrict__ ptr, 
             p[1] = v[0];
         }
     }
-    __syncthreads();  // the wave's LDS slice is rewritten by the next round
+    if (more) __syncthreads();  // the wave's LDS slice is rewritten by the next round
 }
 
 // Transpose pass of global iteration G: x_k = soft(y_k - A^T r_y,k / L), with
@@ -151,7 +151,8 @@ __global__ __launch_bounds__(L1LS_BLOCK, ONE ? 7 : 5) void kb_transpose(const BT
     const int steps = ONE ? 1 : tk.steps;
     for (int st = 0; st < steps; ++st)
         transpose_tile(I.csc_ptr, I.csc_row, I.csc_val, I.ry, I.x[(kn - 1) & 1], I.x[kn & 1], I.part2, I.n,
-                       (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, Lf, thr, stats, lds[wid], lane);
+                       (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, Lf, thr, stats, st + 1 < steps,
+                       lds[wid], lane);
 }
 
 // One 64-row tile of the residual pass (mode 1: first pass, no momentum).
@@ -159,7 +160,7 @@ __device__ __forceinline__ void residual_tile(const int32_t* __restrict__ ptr, c
                                               const float* __restrict__ val, const float* __restrict__ x,
                                               const float* __restrict__ bvec, float* __restrict__ rx,
                                               float* __restrict__ ry, double* __restrict__ part1, int64_t m,
-                                              int64_t first, float beta, int mode, bool stats, float* lds,
+                                              int64_t first, float beta, int mode, bool stats, bool more, float* lds,
                                               int lane) {
     const bool run = first < m;  // wave-uniform
     const int64_t i = first + lane;
@@ -202,7 +203,7 @@ __device__ __forceinline__ void residual_tile(const int32_t* __restrict__ ptr, c
             p[2] = v[2];
         }
     }
-    __syncthreads();  // the wave's LDS slice is rewritten by the next round
+    if (more) __syncthreads();  // the wave's LDS slice is rewritten by the next round
 }
 
 // Residual pass of global iteration G (mode 0): r_x,k = A x_k - b and
@@ -238,12 +239,13 @@ __global__ __launch_bounds__(L1LS_BLOCK, 8) void kb_residual(const BTask* __rest
     const int steps = ONE ? 1 : tk.steps;
     for (int st = 0; st < steps; ++st)
         residual_tile(I.csr_ptr, I.csr_col, I.csr_val, I.x[kn & 1], I.b, I.rx, I.ry, part1, I.m,
-                      (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, mode, stats, lds[wid], lane);
+                      (int64_t)tk.first + (int64_t)(4 * st + wid) * kTile, beta, mode, stats, st + 1 < steps,
+                      lds[wid], lane);
 }
 
 // One workgroup per slot: the duality gap on the slot's check iterations
 // (the terms of k_gap, from the slot's own partials in tile order).
-__global__ __launch_bounds__(256) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G,
+__global__ __launch_bounds__(1024) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G,
                                               int gmod) {
     const BInst& I = bi[blockIdx.x];
     BState& S = bs[blockIdx.x];
@@ -326,6 +328,7 @@ struct l1ls_batch {
     float* btab = nullptr;                    // beta_k, k = 0 .. nbeta-1
     int64_t nbeta = 0;
     bool tables_dirty = false, init_pending = false;
+    DevAlloc* al = nullptr;                   // source of the slot blocks (nullptr: hipMalloc)
     DevArena arena;
 };
 
@@ -502,6 +505,10 @@ int64_t slot_iterations(const l1ls_batch* B, int s, const BState& st) {
 // instance exists).
 size_t batch_slot_bytes(int64_t m, int64_t n) { return slot_bytes(m, n); }
 
+// Take the slot blocks of a batch from `al` (set before any add; the
+// batch's own tables stay on hipMalloc and are freed with the batch).
+void batch_set_alloc(l1ls_batch* B, DevAlloc* al) { B->al = al; }
+
 extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_bytes, const l1ls_solve_opts* opts,
                                          l1ls_batch** out) {
     if (!out || !opts || capacity < 1 || capacity > 65535) return L1LS_E_ARG;
@@ -564,7 +571,7 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     if (B->budget && B->used + fp > B->budget) return L1LS_E_NOMEM;
     const int64_t m = I->m, n = I->n;
     void* blk = nullptr;
-    if (hipMalloc(&blk, slot_bytes(m, n)) != hipSuccess) return L1LS_E_NOMEM;
+    L1LS_TRY(dev_alloc(B->al, &blk, slot_bytes(m, n)));
     float* f = (float*)blk;
     hipLaunchKernelGGL(kb_zero, g1d(2 * n), dim3(L1LS_BLOCK), 0, B->stream, f, 2 * n);  // x_0 = x_{-1} = 0
     BInst& h = B->hinst[slot];
@@ -647,7 +654,7 @@ extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {
                                B->dstate, B->btab, G, gmod, 0);
         }
         if (phase[(size_t)gmod])
-            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(256), 0, B->stream, B->dinst, B->dstate, G, gmod);
+            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(1024), 0, B->stream, B->dinst, B->dstate, G, gmod);
     }
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
@@ -697,7 +704,7 @@ extern "C" l1ls_status l1ls_batch_get_x(l1ls_batch* B, int32_t slot, double* x_o
 extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
     if (!B || slot < 0 || slot >= B->capacity || !B->inst[slot]) return L1LS_E_ARG;
     HIP_TRY(hipStreamSynchronize(B->stream));
-    (void)hipFree(B->buf[slot]);
+    dev_free(B->al, B->buf[slot], slot_bytes(B->hinst[slot].m, B->hinst[slot].n));
     B->buf[slot] = nullptr;
     B->used -= B->footprint[slot];
     B->footprint[slot] = 0;
@@ -711,8 +718,8 @@ extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
 extern "C" void l1ls_batch_destroy(l1ls_batch* B) {
     if (!B) return;
     (void)hipStreamSynchronize(B->stream);
-    for (void* p : B->buf)
-        if (p) (void)hipFree(p);
+    for (int s = 0; s < B->capacity; ++s)
+        if (B->buf[s]) dev_free(B->al, B->buf[s], slot_bytes(B->hinst[s].m, B->hinst[s].n));
     B->arena.release();
     delete B;
 }

@@ -33,22 +33,49 @@
         if (_s != L1LS_OK) return _s;         \
     } while (0)
 
+// A source of device memory.  The default (no DevAlloc) is hipMalloc /
+// hipFree; hipFree waits for all work queued on the device, so a caller that
+// allocates and frees while other streams run (the serving loop) supplies a
+// caching allocator instead.  free() is only called once nothing in flight
+// uses the block.
+struct DevAlloc {
+    virtual ~DevAlloc() = default;
+    virtual l1ls_status alloc(void** p, size_t bytes) = 0;
+    virtual void free(void* p, size_t bytes) = 0;
+};
+
+inline l1ls_status dev_alloc(DevAlloc* al, void** p, size_t bytes) {
+    *p = nullptr;
+    if (al) return al->alloc(p, bytes);
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? L1LS_E_NOMEM : L1LS_E_HIP;
+    return L1LS_OK;
+}
+
+inline void dev_free(DevAlloc* al, void* p, size_t bytes) {
+    if (!p) return;
+    if (al)
+        al->free(p, bytes);
+    else
+        (void)hipFree(p);
+}
+
 // Device allocation list owned by one object; freed in reverse order.
 struct DevArena {
-    std::vector<void*> ptrs;
+    std::vector<std::pair<void*, size_t>> ptrs;
+    DevAlloc* al = nullptr;
     template <typename T>
     l1ls_status alloc(T** p, size_t count) {
         *p = nullptr;
         if (count == 0) count = 1;
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T));
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? L1LS_E_NOMEM : L1LS_E_HIP;
-        ptrs.push_back(q);
+        L1LS_TRY(dev_alloc(al, &q, count * sizeof(T)));
+        ptrs.push_back({q, count * sizeof(T)});
         *p = static_cast<T*>(q);
         return L1LS_OK;
     }
     void release() {
-        for (size_t i = ptrs.size(); i-- > 0;) (void)hipFree(ptrs[i]);
+        for (size_t i = ptrs.size(); i-- > 0;) dev_free(al, ptrs[i].first, ptrs[i].second);
         ptrs.clear();
     }
 };

@@ -20,7 +20,7 @@ void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc,
                          T thr, double* part, const GapState* gs, int stats, hipStream_t s);
 int mf_grid(int64_t pairs);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
-                        int64_t* pcg_iters_out, double support_tol);
+                        int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
 
 namespace {
 
@@ -528,13 +528,15 @@ extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t
 
 // FP64 gap at x through the stored FP64 operator.  Used by the solvers too.
 l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
-                     hipStream_t s) {
+                     hipStream_t s, DevAlloc* al = nullptr) {
     L1LS_TRY(check_stored(I, L1LS_F64));
     DevArena tmp;
+    tmp.al = al;
     double *r = nullptr, *ry = nullptr, *p1 = nullptr, *p2 = nullptr, *xo = nullptr;
     const int g1 = tile_grid(I->m);
     const int g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
     auto done = [&](l1ls_status st) {
+        (void)hipStreamSynchronize(s);
         tmp.release();
         return st;
     };

@@ -324,8 +324,10 @@ template l1ls_status apply_side<float>(const SideTables&, int, bool, float*, flo
 
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s);
 
-extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int64_t s, double tau,
-                                        uint64_t seed, const l1ls_gen_opts* opts, l1ls_instance** out) {
+// l1ls_generate_ex with the instance's device memory (and the build's
+// temporaries) from `al` (nullptr: hipMalloc).
+l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double tau, uint64_t seed,
+                          const l1ls_gen_opts* opts, DevAlloc* al, l1ls_instance** out) {
     if (!out) return L1LS_E_ARG;
     *out = nullptr;
     const int rounds = opts ? opts->rounds : 1;
@@ -352,8 +354,11 @@ extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int6
     I->layout = layout;
     I->L = 1.0;  // sigma_1 = kappa^0
     HIP_TRY(hipGetDevice(&I->device));
+    I->arena.al = al;
     DevArena tmp;
+    tmp.al = al;
     auto fail = [&](l1ls_status st) {
+        (void)hipStreamSynchronize(stream);  // nothing queued may still use the buffers
         tmp.release();
         I->arena.release();
         delete I;
@@ -580,6 +585,19 @@ extern "C" l1ls_status l1ls_instance_info(const l1ls_instance* I, l1ls_info* o) 
     o->csc_val32_dev = I->csc_v32;
     o->csc_val64_dev = I->csc_v64;
     return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int64_t s, double tau,
+                                        uint64_t seed, const l1ls_gen_opts* opts, l1ls_instance** out) {
+    return generate_with(m, n, kappa, s, tau, seed, opts, nullptr, out);
+}
+
+// Free an instance whose device work has completed (the caller synchronised
+// the streams that used it), without waiting for the rest of the device.
+void free_idle_instance(l1ls_instance* I) {
+    if (!I) return;
+    I->arena.release();
+    delete I;
 }
 
 extern "C" void l1ls_free(l1ls_instance* I) {

@@ -26,7 +26,7 @@
 using namespace l1ls;
 
 l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
-                     hipStream_t s);
+                     hipStream_t s, DevAlloc* al = nullptr);
 l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out, hipStream_t s);
 
 namespace {
@@ -362,8 +362,8 @@ __global__ void k_axpby(const double* __restrict__ a, double alpha, const double
 
 // ---- host side ------------------------------------------------------------
 struct Work {
-    const l1ls_instance* I;
-    hipStream_t s;
+    const l1ls_instance* I = nullptr;
+    hipStream_t s = nullptr;
     DevArena arena;
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *hp = nullptr, *minv = nullptr;
     double *d = nullptr, *rhs = nullptr, *tm = nullptr, *tm2 = nullptr, *grad = nullptr, *gd = nullptr;
@@ -375,7 +375,10 @@ struct Work {
     int32_t* iters = nullptr;
     CgScalars* cs = nullptr;
     std::vector<double> h;
-    ~Work() { arena.release(); }
+    ~Work() {
+        (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
+        arena.release();
+    }
     l1ls_status init(const l1ls_instance* inst, hipStream_t stream) {
         I = inst;
         s = stream;
@@ -461,11 +464,12 @@ struct Work {
 // FP64 polish of x_dev (original order, n entries), in place; the starting
 // support is {j : |x_j| > support_tol}.
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t s, int* rounds_out,
-                        int64_t* pcg_iters_out, double support_tol) {
+                        int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr) {
     *rounds_out = 0;
     *pcg_iters_out = 0;
     if (!I->csr_v64 || !I->csc_v64) return L1LS_E_UNSUPPORTED;
     Work W;
+    W.arena.al = al;
     L1LS_TRY(W.init(I, s));
     const int64_t n = I->n;
     hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, x_dev, W.x, I->op_col_of, n);

@@ -38,6 +38,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -46,10 +47,14 @@
 #include "common.hpp"
 
 size_t batch_slot_bytes(int64_t m, int64_t n);
+void batch_set_alloc(l1ls_batch* B, DevAlloc* al);
+l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double tau, uint64_t seed,
+                          const l1ls_gen_opts* opts, DevAlloc* al, l1ls_instance** out);
+void free_idle_instance(l1ls_instance* I);
 l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
-                     hipStream_t s);
+                     hipStream_t s, DevAlloc* al = nullptr);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
-                        int64_t* pcg_iters_out, double support_tol);
+                        int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
 
 namespace {
 
@@ -67,6 +72,68 @@ int class_of(int64_t n) { return n < (1 << 14) ? 0 : (n < (1 << 18) ? 1 : 2); }
 
 // Algorithmic bytes of one FISTA iteration of an instance (FP32, int32).
 double iter_bytes(int64_t m, int64_t n, int64_t nnz) { return 16.0 * nnz + 24.0 * m + 20.0 * n; }
+
+// Caching device allocator of a server.  hipFree waits for every stream of
+// the device, so a free in the serving loop would stall the other size
+// classes and workers; instead freed blocks go to per-size free lists
+// (sizes rounded up to a quarter octave, at most 25% slack) and are reused.
+// Cached bytes beyond `cap` are returned to HIP; everything is returned when
+// the server is destroyed.
+class ServePool : public DevAlloc {
+   public:
+    explicit ServePool(size_t cap) : cap_(cap) {}
+    ~ServePool() override { trim(0); }
+    static size_t round(size_t b) {
+        if (b <= 4096) return 4096;
+        int e = 63 - __builtin_clzll((unsigned long long)b);  // 2^e <= b < 2^(e+1)
+        const size_t q = (size_t)1 << (e - 2);                  // quarter octave
+        return ((b + q - 1) / q) * q;
+    }
+    l1ls_status alloc(void** p, size_t bytes) override {
+        const size_t r = round(bytes);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.find(r);
+            if (it != free_.end() && !it->second.empty()) {
+                *p = it->second.back();
+                it->second.pop_back();
+                cached_ -= r;
+                return L1LS_OK;
+            }
+        }
+        const hipError_t e = hipMalloc(p, r);
+        if (e != hipSuccess) {
+            trim(0);  // give the cache back and try once more
+            if (hipMalloc(p, r) != hipSuccess) return L1LS_E_NOMEM;
+        }
+        return L1LS_OK;
+    }
+    void free(void* p, size_t bytes) override {
+        if (!p) return;
+        const size_t r = round(bytes);
+        std::lock_guard<std::mutex> lk(mu_);
+        free_[r].push_back(p);
+        cached_ += r;
+        if (cached_ > cap_) trim_locked(cap_ / 2);
+    }
+    void trim(size_t keep) {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked(keep);
+    }
+
+   private:
+    void trim_locked(size_t keep) {  // largest blocks first
+        for (auto it = free_.rbegin(); it != free_.rend() && cached_ > keep; ++it)
+            while (!it->second.empty() && cached_ > keep) {
+                (void)hipFree(it->second.back());
+                it->second.pop_back();
+                cached_ -= it->first;
+            }
+    }
+    std::mutex mu_;
+    std::map<size_t, std::vector<void*>> free_;
+    size_t cached_ = 0, cap_;
+};
 
 struct ServeReq {
     int64_t id;
@@ -132,6 +199,7 @@ struct l1ls_server {
     std::unordered_map<int64_t, ServeDone> done;
     std::vector<int64_t> fresh;  // retired since the last l1ls_server_completed call
     std::thread worker[kClasses];
+    ServePool* pool = nullptr;
 };
 
 namespace {
@@ -185,10 +253,10 @@ void finish_worker(l1ls_server* S, int c) {
         double P = 0.0, D = 0.0, gap = INFINITY;
         int rounds = 0;
         int64_t pcg = 0;
-        l1ls_status st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs);
+        l1ls_status st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs, S->pool);
         if (st == L1LS_OK && !(gap <= j.tol)) {
-            st = polish_fp64(j.inst, j.tau, j.d.x, fs, &rounds, &pcg, 0.0);
-            if (st == L1LS_OK) st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs);
+            st = polish_fp64(j.inst, j.tau, j.d.x, fs, &rounds, &pcg, 0.0, S->pool);
+            if (st == L1LS_OK) st = gap_fp64(j.inst, j.tau, j.d.x, &P, &D, &gap, fs, S->pool);
         }
         j.d.rep.primal = P;
         j.d.rep.dual = D;
@@ -197,7 +265,8 @@ void finish_worker(l1ls_server* S, int c) {
         j.d.rep.inner = pcg;
         j.d.rep.converged = (st == L1LS_OK && gap <= j.tol) ? 1 : (j.d.rep.converged < 0 ? -1 : 0);
         j.d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - j.submitted).count();
-        l1ls_free(j.inst);
+        (void)hipStreamSynchronize(fs);
+        free_idle_instance(j.inst);
         std::lock_guard<std::mutex> lk(S->mu);
         if (st != L1LS_OK) S->worker_status = st;
         S->used -= j.est;
@@ -229,9 +298,12 @@ extern "C" l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_b
     S->check_every = check_every;
     S->budget = hbm_budget_bytes;
     S->stream = (hipStream_t)stream;
+    // cached free blocks are capped at a quarter of the budget (8 GiB without one)
+    S->pool = new ServePool(hbm_budget_bytes ? hbm_budget_bytes / 4 : ((size_t)8 << 30));
     auto fail = [&](l1ls_status st) {
         for (ServeClass& c : S->cls)
             if (c.batch) l1ls_batch_destroy(c.batch);
+        delete S->pool;
         destroy_streams(S);
         delete S;
         return st;
@@ -251,6 +323,7 @@ extern "C" l1ls_status l1ls_server_create(int32_t max_slots, size_t hbm_budget_b
         o.stream = c.stream;
         l1ls_status st = l1ls_batch_create(max_slots, 0, &o, &c.batch);
         if (st != L1LS_OK) return fail(st);
+        batch_set_alloc(c.batch, S->pool);
         c.slots.assign(max_slots, ServeSlot{});
     }
     try {
@@ -317,11 +390,11 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
         go.stream = S->gen_stream;
         go.layout = L1LS_LAYOUT_STAGE;
         l1ls_instance* inst = nullptr;
-        L1LS_TRY(l1ls_generate_ex(r.m, r.n, r.kappa, r.s, r.tau, r.seed, &go, &inst));
+        L1LS_TRY(generate_with(r.m, r.n, r.kappa, r.s, r.tau, r.seed, &go, S->pool, &inst));
         int32_t bslot = -1;
         l1ls_status st = l1ls_batch_add_ex(C.batch, inst, r.tau, r.rel_gap_tol, r.max_iter, &bslot);
         if (st != L1LS_OK) {
-            l1ls_free(inst);
+            free_idle_instance(inst);  // generation has finished and nothing else used it
             return st;
         }
         const size_t fp = estimate_footprint(r);
@@ -358,12 +431,12 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
             d.n = sl.inst->n;
             d.rep = rp;
             void* p = nullptr;
-            HIP_TRY(hipMalloc(&p, d.n * sizeof(double)));
+            L1LS_TRY(S->pool->alloc(&p, d.n * sizeof(double)));
             d.x = (double*)p;
-            l1ls_status st = l1ls_batch_get_x(C.batch, q, d.x);
+            l1ls_status st = l1ls_batch_get_x(C.batch, q, d.x);  // synchronises the class stream
             if (st == L1LS_OK) st = l1ls_batch_remove(C.batch, q);
             if (st != L1LS_OK) {
-                (void)hipFree(p);
+                S->pool->free(p, d.n * sizeof(double));
                 return st;
             }
             C.resident -= 1;
@@ -387,7 +460,7 @@ extern "C" l1ls_status l1ls_server_tick(l1ls_server* S, int32_t* admitted, int32
                 S->cv.notify_all();
             } else {
                 d.rep.seconds = std::chrono::duration<double>(ServeClock::now() - sl.submitted).count();
-                l1ls_free(sl.inst);
+                free_idle_instance(sl.inst);  // its class stream was synchronised by the removal
                 std::lock_guard<std::mutex> lk(S->mu);
                 S->used -= sl.est;
                 S->done[sl.id] = d;
@@ -428,7 +501,7 @@ extern "C" l1ls_status l1ls_server_take(l1ls_server* S, int64_t id, double* x_ou
         st = L1LS_E_HIP;
     if (hipStreamSynchronize(S->stream) != hipSuccess) st = L1LS_E_HIP;
     if (rep) *rep = d.rep;
-    (void)hipFree(d.x);
+    S->pool->free(d.x, d.n * sizeof(double));
     return st;
 }
 
@@ -452,13 +525,16 @@ extern "C" size_t l1ls_request_footprint(const l1ls_request* r) {
 extern "C" void l1ls_server_destroy(l1ls_server* S) {
     if (!S) return;
     stop_workers(S);  // finish the queued jobs first
-    for (ServeClass& C : S->cls) {
+    for (ServeClass& C : S->cls)
         if (C.stream) (void)hipStreamSynchronize(C.stream);
+    if (S->gen_stream) (void)hipStreamSynchronize(S->gen_stream);
+    for (ServeClass& C : S->cls) {
         for (ServeSlot& s : C.slots)
-            if (s.inst) l1ls_free(s.inst);
+            if (s.inst) free_idle_instance(s.inst);
         if (C.batch) l1ls_batch_destroy(C.batch);
     }
-    for (auto& kv : S->done) (void)hipFree(kv.second.x);
+    for (auto& kv : S->done) S->pool->free(kv.second.x, kv.second.n * sizeof(double));
+    delete S->pool;  // returns every cached block
     destroy_streams(S);
     delete S;
 }
