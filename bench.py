@@ -480,8 +480,9 @@ def bench_large(args):
     """Memory-scale instance on one GPU: n = 2^26, m = 2^27, kappa = 1e6, two
     Givens stages, s = n/1000, tau = 1.  FISTA iterations/s on the stored
     FP32 CSR + CSC and on the matrix-free operator (rotations and sigma
-    applied on the fly), and CG-Newton (FP64 stored operator) Newton steps
-    and Hessian-vector products per second."""
+    applied on the fly), and CG-Newton Newton steps and PCG iterations per
+    second, with the Hessian-vector products on the FP32 values of A (FP64
+    vectors and sums) and all-FP64."""
     import torch
 
     import paper_1503_03520_amd as L
@@ -516,11 +517,18 @@ def bench_large(args):
     mfree, x_m = fista_rate(L.OP_MATRIX_FREE, args.steps, args.warmup)
     print(json.dumps({"progress": "matrix_free", "iters_per_s": mfree}), file=sys.stderr, flush=True)
     same = float((x_s - x_m).abs().max())
-    t = time.perf_counter()
-    xn, rn, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, stream=stream)
-    torch.cuda.synchronize()
-    tn = time.perf_counter() - t
-    P, D, gap = L.l1ls_objective_gap(inst, tau, xn)
+    newton = {}
+    for prec, name in ((L.F32, "f32_hessian_products"), (L.F64, "f64")):
+        t = time.perf_counter()
+        xn, rn, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, stream=stream,
+                                           precision=prec)
+        torch.cuda.synchronize()
+        tn = time.perf_counter() - t
+        P, D, gap = L.l1ls_objective_gap(inst, tau, xn)
+        newton[name] = {"newton_steps": rn["iterations"], "pcg_iterations": rn["inner"], "seconds": tn,
+                        "newton_steps_per_s": rn["iterations"] / tn, "ms_per_pcg_iteration": tn / max(rn["inner"], 1) * 1e3,
+                        "fp64_rel_gap": gap}
+        print(json.dumps({"progress": "cg_newton", name: newton[name]}), file=sys.stderr, flush=True)
     k1, k2 = algorithmic_bytes(m, n, nnz)
     line = {
         "metric": "FISTA iters/sec on the memory-scale instance, stored vs matrix-free; CG-Newton steps/sec",
@@ -534,10 +542,7 @@ def bench_large(args):
                   "matrix_free_iters_per_s": mfree, "matrix_free_gbs_algorithmic": mf_bytes(m, n) * mfree / 1e9,
                   "matrix_free_speedup": mfree / stored,
                   "stored_vs_matrix_free_max_abs_diff": same,
-                  "cg_newton": {"newton_steps": rn["iterations"], "pcg_iterations": rn["inner"],
-                                "seconds": tn, "newton_steps_per_s": rn["iterations"] / tn,
-                                "hessian_products_per_s": rn["inner"] / tn, "fp64_rel_gap": gap,
-                                "precision": "f64"}},
+                  "cg_newton": newton},
     }
     print(json.dumps(line), flush=True)
 
@@ -568,7 +573,7 @@ def main():
                          "batched: 256 uneven instances; path: 64 taus on one instance; "
                          "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton")
     ap.add_argument("--large-log2n", type=int, default=26)
-    ap.add_argument("--newton-steps", type=int, default=3)
+    ap.add_argument("--newton-steps", type=int, default=8)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
     ap.add_argument("--batch-max-iter", type=int, default=20000)

@@ -202,7 +202,10 @@ l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* o
  * (7) and Newton model (9); section 8.1 item pdNCG, section 8.3): Newton
  * directions from preconditioned CG with the inverse Hessian diagonal as
  * preconditioner, relative residual pcg_rtol, Armijo backtracking of at most
- * max_backtrack halvings; then the FP64 polish if opts.polish.  The Newton
+ * max_backtrack halvings; then the FP64 polish if opts.polish.  With
+ * opts.precision = L1LS_F32 the Hessian-vector products of the Newton
+ * directions read the FP32 values of A (vectors, gradients and all sums stay
+ * FP64; both storages are needed).  The Newton
  * loop stops when ||grad f_mu(x)||_inf <= rel_gap_tol * tau, or after
  * max_iter Newton steps (report.iterations; report.inner = PCG iterations).
  * Uses the stored FP64 operator (L1LS_STORE_F64).

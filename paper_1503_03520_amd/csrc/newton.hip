@@ -40,12 +40,41 @@ struct CgScalars {
     int32_t done, pad;
 };
 
-// out = A in (CSR) or A^T in (CSC): one tile of 64 rows per wave.
+// tile_products (kernels.hpp) with stored values of type TV widened to the
+// FP64 of the vectors: val[k] * vec[idx[k]] for the tile's entries.
+template <int NQ, typename TV>
+__device__ __forceinline__ void tile_products_mixed(const int32_t* __restrict__ idx, const TV* __restrict__ val,
+                                                    const double* __restrict__ vec, int32_t beg, int32_t cnt,
+                                                    double* __restrict__ lds, int lane) {
+    if (cnt <= 0) return;  // wave-uniform
+    const int32_t* __restrict__ ib = idx + beg;
+    const TV* __restrict__ vb = val + beg;
+    const int32_t last = cnt - 1;
+    int32_t c[NQ];
+    TV v[NQ];
+    double g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[q] = __builtin_nontemporal_load(ib + min(q * kTile + lane, last));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = __builtin_nontemporal_load(vb + min(q * kTile + lane, last));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) g[q] = ld_off32(vec, c[q]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q * kTile + lane] = (q * kTile + lane <= last) ? (double)v[q] * g[q] : 0.0;
+    for (int32_t k = NQ * kTile + lane; k <= last; k += kTile) lds[k] = (double)vb[k] * ld_off32(vec, ib[k]);
+}
+
+// out = A in (CSR) or A^T in (CSC): one tile of 64 rows per wave.  TV: the
+// stored values (FP64, or FP32 for the Hessian-vector products of the
+// Newton directions); vectors and sums are FP64.  Skipped once the PCG the
+// product belongs to has finished (cs->done).
+template <typename TV>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_tile_spmv(const int32_t* __restrict__ ptr,
                                                           const int32_t* __restrict__ idx,
-                                                          const double* __restrict__ val,
+                                                          const TV* __restrict__ val,
                                                           const double* __restrict__ in, double* __restrict__ out,
-                                                          int64_t rows) {
+                                                          int64_t rows, const CgScalars* __restrict__ cs) {
+    if (cs && cs->done) return;
     __shared__ double lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE, wid = threadIdx.x / L1LS_WAVE;
     const int64_t row0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
@@ -58,7 +87,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_tile_spmv(const int32_t* __restr
     const int lastlane = (row0 + kTile <= rows) ? kTile - 1 : (rows > row0 ? (int)(rows - row0 - 1) : 0);
     const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
     const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-    if (row0 < rows) tile_products<double, 16>(idx, val, in, beg, end - beg, lds[wid], lane);
+    if (row0 < rows) tile_products_mixed<16, TV>(idx, val, in, beg, end - beg, lds[wid], lane);
     __syncthreads();
     if (i < rows) {
         double acc = 0.0;
@@ -68,9 +97,10 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_tile_spmv(const int32_t* __restr
 }
 
 // Hp = mask (A^T t + d p) over the CSC; part[block] = sum p Hp.
+template <typename TV>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_hess(const int32_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ row,
-                                                     const double* __restrict__ val,
+                                                     const TV* __restrict__ val,
                                                      const double* __restrict__ t, const double* __restrict__ p,
                                                      const double* __restrict__ d, const uint8_t* __restrict__ mask,
                                                      double* __restrict__ hp, int64_t n, double* __restrict__ part,
@@ -88,7 +118,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_hess(const int32_t* __restrict__
     const int lastlane = (col0 + kTile <= n) ? kTile - 1 : (n > col0 ? (int)(n - col0 - 1) : 0);
     const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
     const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-    if (col0 < n) tile_products<double, 16>(row, val, t, beg, end - beg, lds[wid], lane);
+    if (col0 < n) tile_products_mixed<16, TV>(row, val, t, beg, end - beg, lds[wid], lane);
     __syncthreads();
     double v[1] = {0.0};
     if (j < n) {
@@ -374,6 +404,7 @@ struct Work {
     int32_t* counts = nullptr;
     int32_t* iters = nullptr;
     CgScalars* cs = nullptr;
+    bool hv32 = false;  // Hessian-vector products of Newton directions with the FP32 values
     std::vector<double> h;
     ~Work() {
         (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
@@ -409,25 +440,39 @@ struct Work {
         return L1LS_OK;
     }
     void spmv(const double* in, double* out) {  // out (m) = A in
-        hipLaunchKernelGGL(k_tile_spmv, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
-                           I->csr_v64, in, out, I->m);
+        hipLaunchKernelGGL(k_tile_spmv<double>, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                           I->csr_v64, in, out, I->m, (const CgScalars*)nullptr);
     }
     void spmv_t(const double* in, double* out) {  // out (n) = A^T in
-        hipLaunchKernelGGL(k_tile_spmv, dim3(tgrid(I->n)), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
-                           I->csc_v64, in, out, I->n);
+        hipLaunchKernelGGL(k_tile_spmv<double>, dim3(tgrid(I->n)), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                           I->csc_v64, in, out, I->n, (const CgScalars*)nullptr);
+    }
+    // H v = mask (A^T (A v) + dv v) into hp, inside a PCG (skipped once it is done)
+    void hess(const double* v, const double* dv, const uint8_t* mk, bool f32) {
+        const int64_t n = I->n;
+        const int gt = tgrid(n);
+        if (f32) {
+            hipLaunchKernelGGL(k_tile_spmv<float>, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr,
+                               I->csr_col, I->csr_v32, v, tm, I->m, (const CgScalars*)cs);
+            hipLaunchKernelGGL(k_hess<float>, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row, I->csc_v32,
+                               tm, v, dv, mk, hp, n, part, (const CgScalars*)cs);
+        } else {
+            hipLaunchKernelGGL(k_tile_spmv<double>, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr,
+                               I->csr_col, I->csr_v64, v, tm, I->m, (const CgScalars*)cs);
+            hipLaunchKernelGGL(k_hess<double>, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                               I->csc_v64, tm, v, dv, mk, hp, n, part, (const CgScalars*)cs);
+        }
     }
     // PCG on H v = rhs from v = x (in place), H = mask (A^T A + diag(dv)) mask.
     // zero_start: v is known to be 0, so H v = 0 is not computed.
+    // f32: the products with A use its FP32 values (the Newton directions);
+    // the polish keeps FP64.
     l1ls_status pcg(double* v, const double* rhs_v, const double* dv, const uint8_t* mk, double rtol, int maxit,
-                    int* out_iters, bool zero_start = false) {
+                    int* out_iters, bool zero_start = false, bool f32 = false) {
         const int64_t n = I->n;
         const int gt = tgrid(n);
         hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(1), 0, s, cs);
-        if (!zero_start) {  // H v for the starting residual
-            spmv(v, tm);
-            hipLaunchKernelGGL(k_hess, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row, I->csc_v64, tm, v,
-                               dv, mk, hp, n, part, (const CgScalars*)cs);
-        }
+        if (!zero_start) hess(v, dv, mk, f32);  // H v for the starting residual
         hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, rhs_v,
                            zero_start ? (const double*)nullptr : hp, r, z, p, minv, mk, n, part);
         hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1024), 0, s, part, kRedBlocks, cs, rtol, iters);
@@ -437,9 +482,7 @@ struct Work {
         for (int it = 0; it < maxit; it += batch) {
             const int nb = std::min(batch, maxit - it);
             for (int q = 0; q < nb; ++q) {
-                spmv(p, tm);
-                hipLaunchKernelGGL(k_hess, dim3(gt), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row, I->csc_v64,
-                                   tm, p, dv, mk, hp, n, part, (const CgScalars*)cs);
+                hess(p, dv, mk, f32);
                 hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, part, gt, cs);
                 hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, v, r, z, p, hp, minv, mk,
                                    n, part, (const CgScalars*)cs);
@@ -524,6 +567,8 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
     if (!is_finite(tau) || !is_finite(mu)) return L1LS_E_ARG;
     const int64_t n = I->n, m = I->m;
     Work W;
+    W.hv32 = (o->precision == L1LS_F32);
+    if (W.hv32 && (!I->csr_v32 || !I->csc_v32)) return L1LS_E_UNSUPPORTED;
     L1LS_TRY(W.init(I, s));
     if (o->x0_dev)
         hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, o->x0_dev, W.x,
@@ -551,7 +596,7 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
                            W.rhs, n);
         HIP_TRY(hipMemsetAsync(W.xs, 0, n * sizeof(double), s));
         int it = 0;
-        L1LS_TRY(W.pcg(W.xs, W.rhs, W.d, nullptr, prtol, pcgmax, &it, true));
+        L1LS_TRY(W.pcg(W.xs, W.rhs, W.d, nullptr, prtol, pcgmax, &it, true, W.hv32));
         pcg_total += it;
         // line search on f_mu(x + a dx) = tau sum psi + 0.5 ||r + a A dx||^2
         W.spmv(W.xs, W.tm2);

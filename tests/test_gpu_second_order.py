@@ -102,3 +102,20 @@ def test_cg_newton_zero_when_tau_dominates():
     tau = 1.01 * np.abs(A.T @ o.b).max()
     x, rep, st = L.l1ls_solve_cg_newton(g, tau=tau, max_iter=100, rel_gap_tol=1e-9, polish=1)
     assert np.array_equal(x.cpu().numpy(), np.zeros(o.n))
+
+
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE])
+def test_cg_newton_fp32_hessian_products_reach_the_same_minimiser(cfg):
+    # FP32 values of A in the Hessian-vector products of the Newton directions
+    # (vectors, gradient and sums in FP64): the inexact directions change the
+    # path, not the minimiser of (8), which the FP64 gradient test certifies.
+    g, o, A = pair(cfg)
+    mu = 1e-5
+    x64, r64, _ = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu)
+    x32, r32, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, precision=L.F32)
+    assert st == L.L1LS_OK and r32["converged"] == 1
+    cn = np.asarray(A.multiply(A).sum(0)).ravel()
+    ref, _ = ON.newton_cg(lambda v: A @ v, lambda v: A.T @ v, cn, o.b, o.tau, mu=mu, max_newton=300)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(x32.cpu().numpy() - ref).max() <= 1e-5 * scale
+    assert np.abs(x32.cpu().numpy() - x64.cpu().numpy()).max() <= 1e-5 * scale
