@@ -547,6 +547,112 @@ def bench_large(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_huge(args):
+    """Section 8.9 (Table 1) instance: A = Sigma G^T, one stage of adjacent
+    Givens rotations with theta = 2 pi / 3, sigma 0.1 / 100, s = n / 2^10,
+    x* entries -1e4 and 0.1, tau = 1, at n = 2^30 (m = 2^31).  A step is one
+    whole CG-Newton solve of `--newton-steps` Newton steps (section 8.9
+    reports 8) from x = 0, generation excluded; value = seconds per solve."""
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    n = 1 << args.huge_log2n
+    seed = 1503035206
+    stream = torch.cuda.current_stream()
+    free, _ = torch.cuda.mem_get_info()
+    need = L.huge_bytes(n) + L.huge_solve_bytes(n) + 8 * n
+    if need > free:
+        print(json.dumps({"error": f"n = 2^{args.huge_log2n} needs {need / 2**30:.1f} GiB, {free / 2**30:.1f} free"}))
+        sys.exit(3)
+    prm = L.huge_params(n, seed)
+    t = time.perf_counter()
+    H = L.HugeInstance(prm, stream=stream)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    print(json.dumps({"progress": "generated", "seconds": gen_s}), file=sys.stderr, flush=True)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        H.solve_cg_newton(x_out=x, max_iter=1, stream=stream)
+    torch.cuda.synchronize()
+    times, rep = [], None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, rep, _ = H.solve_cg_newton(x_out=x, max_iter=args.newton_steps, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        print(json.dumps({"progress": "solve", "seconds": times[-1], "newton": rep["iterations"],
+                          "pcg": rep["inner"], "rel_err": rep["rel_err"]}), file=sys.stderr, flush=True)
+    # the same solve once more with HIP events around the passes
+    _, rep_t, _ = H.solve_cg_newton(x_out=x, max_iter=args.newton_steps, stream=stream, time_kernels=1)
+    kt = H.kernel_times()
+    avg_ms = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    # algorithmic bytes per launch: PCG pass reads r, d, p, dx and writes p,
+    # dx, r; line search reads x, dx, b; setup reads x, gd, b, writes d, r
+    it_bytes, ls_bytes, setup_bytes = 56 * n, 24 * n, 40 * n
+    achieved = it_bytes / (avg_ms["pcg_iteration"] * 1e-3) / 1e9
+    sec = sum(times) / len(times)
+    pcg = rep["inner"]
+    line = {
+        "metric": "CG-Newton seconds per solve of the section 8.9 (Table 1) instance",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": sec / 1923.0 if args.huge_log2n == 30 else None,
+        "dtype": "f64",
+        "data": "synthetic (section 8.9 instance generated on the device, seed %d)" % seed,
+        "config": {"workload": "section 8.9 instance: A = Sigma G^T (m = 2n), adjacent Givens pairs at theta = "
+                               "2 pi / 3, sigma 0.1 / 100, s = n / 2^10 with x* entries -1e4 / 0.1, tau = 1; "
+                               "CG-Newton mu = 1e-5, PCG rtol 0.1, diagonal preconditioner, from x = 0",
+                   "n": n, "m": 2 * n, "s": prm.s, "newton_steps": args.newton_steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "kh_cg_iter (PCG iteration: p, dx, r and the r.u, w.u, r.r partials)",
+                     "algorithmic_bytes_per_launch": it_bytes},
+        "extra": {
+            "newton_steps": rep["iterations"], "pcg_iterations": pcg, "rel_err": rep["rel_err"],
+            "fp64_rel_gap": rep["rel_gap"], "generate_s": gen_s, "solve_seconds": times,
+            "ms_per_pcg_iteration": sec * 1e3 / max(pcg, 1),
+            "pass_avg_ms": avg_ms,
+            "pass_gbs": {"pcg_iteration": it_bytes / (avg_ms["pcg_iteration"] * 1e-3) / 1e9,
+                         "line_search": ls_bytes / (avg_ms["line_search"] * 1e-3) / 1e9,
+                         "newton_setup": setup_bytes / (avg_ms["newton_setup"] * 1e-3) / 1e9},
+            "bytes_per_pcg_iteration": it_bytes,
+            "device_bytes": need,
+            "paper": {"seconds": 1923, "n": 2 ** 30, "cores": 64, "machine": "ARCHER Cray XC30 (section 8.2)",
+                      "newton_steps": 8, "pcg_per_newton": "about 100", "rel_err": "order 1e-4"},
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_huge(n, args.newton_steps)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_huge(n, newton_steps, log2_sample=18):
+    """The oracle's CG-Newton (numpy, FP64) on the same class at n = 2^18,
+    scaled linearly to n (section 8.9 reports the same Newton and PCG counts
+    at every size, and every pass is linear in n)."""
+    from oracle import newton as ON
+    from oracle.huge import HugeInstance
+
+    ns = 1 << log2_sample
+    I = HugeInstance(ns, ns // 1024, 1503035206)
+    cn = I.colnorm2()
+    t = time.perf_counter()
+    _, st = ON.newton_cg(I.matvec, I.rmatvec, cn, I.b, I.tau, max_newton=newton_steps)
+    sec = time.perf_counter() - t
+    return {"value": sec * n / ns, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle CG-Newton, {newton_steps} Newton steps ({st['pcg']} PCG iterations) at n = 2^"
+                      f"{log2_sample} took {sec:.2f} s on one core, scaled by n / 2^{log2_sample}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -568,11 +674,13 @@ def main():
     ap.add_argument("--stats-command", default="")
     ap.add_argument("--stats-top", type=int, default=14)
     ap.add_argument("--out", default=PROFILE_SUMMARY)
-    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large"],
+    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large", "huge"],
                     help="fista: the single large instance (default); serve: the request stream; "
                          "batched: 256 uneven instances; path: 64 taus on one instance; "
-                         "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton")
+                         "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton; "
+                         "huge: the section 8.9 (Table 1) instance at n = 2^30, CG-Newton")
     ap.add_argument("--large-log2n", type=int, default=26)
+    ap.add_argument("--huge-log2n", type=int, default=30)
     ap.add_argument("--newton-steps", type=int, default=8)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
@@ -621,8 +729,10 @@ def main():
             args.check_every = 16
         if args.workload == "large" and "--steps" not in sys.argv:
             args.steps, args.warmup = 50, 5
+        if args.workload == "huge" and "--steps" not in sys.argv:
+            args.steps, args.warmup = 1, 1
         {"serve": bench_serve, "batched": bench_batched, "path": bench_path,
-         "large": bench_large}[args.workload](args)
+         "large": bench_large, "huge": bench_huge}[args.workload](args)
         return
 
     import torch

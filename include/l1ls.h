@@ -360,6 +360,99 @@ l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const do
 l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus, int32_t k,
                                   const l1ls_solve_opts* opts, double* X_out_dev, l1ls_report* reports);
 
+/* ---------------------------------------------------------------------------
+ * Huge-scale instance class of section 8.9 (Table 1).
+ *
+ * A = Sigma G^T with m >= n rows (section 8.9: m = 2n) and rank n: Sigma has
+ * sigma_i = sigma_odd for odd i and sigma_even for even i (1-based) on its
+ * top n x n diagonal and zeros below (section 4); G is the product of the
+ * n/2 Givens rotations G(2k-1, 2k, theta), k = 1..n/2, on adjacent pairs
+ * with one shared angle (section 4.1 without Q-side rotations or
+ * permutation), G(i, j, theta) mapping (z_i, z_j) to
+ * (c z_i - s z_j, s z_i + c z_j).  x* has s nonzeros at the first s outputs
+ * of the support bijection (the same Philox-keyed Feistel bijection as
+ * l1ls_generate); the first floor(s/2) of them are x_neg, the rest x_pos.
+ * The subgradient g is sign(x*) on the support and U[-0.9, 0.9] elsewhere;
+ * e = tau Sigma^{+T} G^T g and b = A x* + e (Procedure IGen, section 3.1).
+ * A is block diagonal with one 2 x 2 block per pair and rows n..m-1 of A
+ * and b are zero: the library stores the top n entries of b only (8 n
+ * bytes) and recomputes x* and g from (seed, index) where it needs them.
+ *
+ * Device vectors passed to these calls must be 16-byte aligned
+ * (L1LS_E_ARG otherwise).  Calls on the same instance must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct l1ls_huge l1ls_huge;
+
+typedef struct {
+    int64_t n;          /* variables: even, 2 <= n <= 2^32                      */
+    int64_t m;          /* rows: even, m >= n (section 8.9: 2n)                 */
+    int64_t s;          /* nonzeros of x*, 0 <= s <= n (section 8.9: n / 2^10)  */
+    double theta;       /* angle of every rotation of G (section 8.9: 2 pi / 3) */
+    double sigma_odd;   /* sigma_i, odd i (section 8.9: 0.1); > 0               */
+    double sigma_even;  /* sigma_i, even i (section 8.9: 100); > 0              */
+    double x_neg;       /* first floor(s/2) support values (section 8.9: -1e4)  */
+    double x_pos;       /* other support values (section 8.9: 0.1)              */
+    double tau;         /* > 0 (section 8.3: 1)                                 */
+    uint64_t seed;
+} l1ls_huge_params;
+
+typedef struct {
+    l1ls_huge_params params;
+    double L;            /* lambda_max(A^T A) = max(sigma_odd, sigma_even)^2      */
+    double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2               */
+    double c, s_rot;     /* cos theta, sin theta as used by the kernels          */
+    const double* b_dev; /* n: the top n entries of b (the others are zero)       */
+} l1ls_huge_desc;
+
+/* params = the section 8.9 values for n: m = 2n, s = floor(n / 1024),
+ * theta = 2 pi / 3, sigma 0.1 / 100, x* values -1e4 / 0.1, tau = 1. */
+void l1ls_huge_params_default(int64_t n, uint64_t seed, l1ls_huge_params* params);
+/* Device bytes of an instance, and the extra device bytes of a CG-Newton
+ * solve on it (besides the caller's x): 8 n + O(1) and 40 n + O(1). */
+size_t l1ls_huge_bytes(int64_t n);
+size_t l1ls_huge_solve_bytes(int64_t n);
+
+/* Build an instance on the current device (b and f_star); returns after
+ * the build finished.  L1LS_E_ARG for parameters outside the ranges above. */
+l1ls_status l1ls_huge_generate(const l1ls_huge_params* params, void* stream, l1ls_huge** out);
+l1ls_status l1ls_huge_describe(const l1ls_huge* inst, l1ls_huge_desc* out);
+void l1ls_huge_free(l1ls_huge* inst);
+
+/* x_star_dev, g_dev (n each, either may be NULL, not both): the planted x*
+ * and the subgradient g of IGen step 2.  Asynchronous on `stream`. */
+l1ls_status l1ls_huge_planted(const l1ls_huge* inst, double* x_star_dev, double* g_dev, void* stream);
+
+/* trans = 0: out_dev (m) = A in_dev (n); trans = 1: out_dev (n) =
+ * A^T in_dev (m; entries n..m-1 are not read).  FP64, asynchronous. */
+l1ls_status l1ls_huge_apply(const l1ls_huge* inst, int32_t trans, const double* in_dev,
+                            double* out_dev, void* stream);
+
+/* FP64 P = f_tau(x), the dual value at the scaled residual and the relative
+ * gap, as l1ls_objective_gap.  Blocks until done. */
+l1ls_status l1ls_huge_objective_gap(const l1ls_huge* inst, double tau, const double* x_dev,
+                                    double* primal, double* dual, double* rel_gap, void* stream);
+
+/*
+ * CG-Newton on problem (8) (section 2, section 8.1 item pdNCG, section 8.3),
+ * as l1ls_solve_cg_newton: pseudo-Huber mu, PCG with the inverse Hessian
+ * diagonal as preconditioner to relative residual pcg_rtol, Armijo
+ * backtracking (constant 1e-4) by halving at most max_backtrack times,
+ * stop when ||grad f_mu||_inf <= rel_gap_tol * tau or after max_iter Newton
+ * steps.  All arithmetic FP64 (opts.precision must be L1LS_F64 and
+ * opts.polish 0, else L1LS_E_UNSUPPORTED).  x_dev (n) holds the iterate
+ * throughout and the result at the end; opts.x0_dev (may equal x_dev) is the
+ * start, NULL for 0.  report: Newton steps, PCG iterations, FP64 gap,
+ * ||x - x*|| / ||x*||.  Allocates l1ls_huge_solve_bytes(n) for the call.
+ */
+l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* inst, const l1ls_solve_opts* opts,
+                                      double* x_dev, l1ls_report* report);
+
+/* HIP-event times of the passes of the last l1ls_huge_solve_cg_newton on
+ * inst that ran with opts.time_kernels = 1: ms[q] total milliseconds and
+ * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r), 1 the
+ * line-search pass, 2 the Newton setup pass (gradient, d, PCG start). */
+l1ls_status l1ls_huge_kernel_times(const l1ls_huge* inst, double* ms, int64_t* calls);
+
 const char* l1ls_status_string(int32_t status);
 /* ABI version of this header (incremented on incompatible changes). */
 int32_t l1ls_version(void);

@@ -19,7 +19,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-SOURCES = ["generator.hip", "fista.hip", "operator.hip", "newton.hip", "mf.hip", "batch.hip", "path.hip", "serve.hip"]
+SOURCES = ["generator.hip", "fista.hip", "operator.hip", "newton.hip", "mf.hip", "batch.hip", "path.hip", "serve.hip",
+           "huge.hip"]
 
 
 def _compile(src):

@@ -1,0 +1,800 @@
+// Huge-scale instance class of section 8.9 (Table 1) and its CG-Newton.
+//
+// The instances of section 8.9 are A = Sigma G^T with m = 2n rows and rank
+// n: Sigma carries sigma_i = sigma_odd for odd i and sigma_even for even i
+// (1-based) on its top n x n diagonal (section 4, the display of Sigma), and
+// G is one stage of n/2 Givens rotations G(2k-1, 2k, theta) on adjacent
+// pairs with one shared angle (section 4.1 with Q = I and no permutation).
+// x* has s nonzeros, the first floor(s/2) support draws at x_neg and the
+// rest at x_pos; b comes from Procedure IGen (section 3.1).
+//
+// Every row and column of A couples the two elements of one pair and rows
+// n..m-1 are zero, so A is block diagonal with one 2 x 2 block per pair.
+// Nothing is gathered: a thread owns whole pairs, reads each vector as one
+// 16-byte double2 per pair, and every product with A, A^T, A^T A and the
+// Hessian of (8) is formed in registers.  The instance stores b only (its
+// top n entries; the others are zero); x* and the subgradient g are pure
+// functions of (seed, index), recomputed wherever they are needed.
+//
+// CG-Newton follows section 8.1 (item pdNCG) and section 8.3 exactly as the
+// stored-operator solver does: smoothed problem (8) with the pseudo-Huber
+// function (7), Newton directions from PCG with the inverse Hessian diagonal
+// as preconditioner, Armijo backtracking by halving.  PCG runs in the
+// single-reduction form of Chronopoulos and Gear (J. Comput. Appl. Math. 25,
+// 1989): the preconditioned residual u = M r, w = H u and s = H p are
+// products with the block-diagonal Hessian, formed in registers from r, p
+// and the Hessian diagonal d, so one PCG iteration is one streaming pass
+// (read r, d, p, dx; write p, dx, r: 56 bytes per variable) and one
+// reduction of (r.u, w.u, r.r).  In exact arithmetic its iterates are those
+// of the textbook recurrence the oracle runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "rng.hpp"
+
+using namespace l1ls;
+
+namespace {
+
+constexpr int kHB = 256;            // threads per block of the streaming kernels
+constexpr int kHMaxBlocks = 16384;  // grid cap (64 blocks per CU); partial sums per block
+constexpr int kHU = 2;              // pairs per thread per trip of the PCG pass
+constexpr bool kHNT = true;         // nontemporal loads and stores in the PCG pass
+constexpr int kLsBatch = 8;        // step lengths tried per line-search pass
+constexpr int kLsStats = 3 + 2 * kLsBatch;
+constexpr int64_t kHugeMaxN = (int64_t)1 << 32;  // Philox counter word 0 holds the index
+
+// Constants of one instance, passed by value to every kernel.
+struct HugeK {
+    int64_t n, s;
+    double c, sn;        // cos, sin of the shared angle
+    double so, se;       // sigma at the first / second element of a pair
+    double cn0, cn1;     // diag(A^T A) at the first / second element
+    double tau, xneg, xpos;
+    Key key;
+};
+
+struct HCg {
+    double gamma, rr0, stop, alpha, beta, gmax;
+    int32_t iters, done;
+};
+
+// 16-byte vector type the nontemporal builtins accept
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+// (y_i, y_j) = block of A x: sigma (G^T x) on the pair
+__device__ __forceinline__ void a_pair(const HugeK& H, double xi, double xj, double& yi, double& yj) {
+    yi = H.so * (H.c * xi + H.sn * xj);
+    yj = H.se * (-H.sn * xi + H.c * xj);
+}
+
+// (x_i, x_j) = block of A^T y: G (sigma y) on the pair
+__device__ __forceinline__ void at_pair(const HugeK& H, double yi, double yj, double& xi, double& xj) {
+    const double ti = H.so * yi, tj = H.se * yj;
+    xi = H.c * ti - H.sn * tj;
+    xj = H.sn * ti + H.c * tj;
+}
+
+// H p = A^T (A p) + d p on the pair
+__device__ __forceinline__ double2 hess_pair(const HugeK& H, double2 p, double2 d) {
+    double yi, yj, hi, hj;
+    a_pair(H, p.x, p.y, yi, yj);
+    at_pair(H, yi, yj, hi, hj);
+    return make_double2(hi + d.x * p.x, hj + d.y * p.y);
+}
+
+// x*_i and the subgradient g_i of IGen step 2: i is in supp(x*) when its
+// position q under the inverse support bijection is < s (the support is the
+// first s outputs of that bijection); off the support g_i = 0.9 (2u - 1).
+__device__ __forceinline__ void planted_at(const HugeK& H, int64_t i, double& xs, double& g) {
+    const int64_t q = H.s > 0 ? bijection_inverse(i, H.n, kTagPerm | 2u, H.key) : H.n;
+    if (q < H.s) {
+        xs = (q < H.s / 2) ? H.xneg : H.xpos;
+        g = xs > 0.0 ? 1.0 : (xs < 0.0 ? -1.0 : 0.0);
+    } else {
+        const U4 w = philox4x32_10((uint32_t)i, 0u, kTagSubgrad, 0u, H.key.k0, H.key.k1);
+        xs = 0.0;
+        g = 0.9 * (2.0 * unit_double(w.x, w.y) - 1.0);  // 2u is exact: a fused form rounds the same
+    }
+}
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+template <int NS, int NSUM>
+__device__ __forceinline__ void store_partials(double (&v)[NS], double* __restrict__ part) {
+    block_reduce_stats<NS, NSUM>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) part[(size_t)NS * blockIdx.x + q] = v[q];
+    }
+}
+
+// ---- instance ----------------------------------------------------------------
+// IGen steps 3 and 4 on one pair: e = tau Sigma^{-1} G^T g and b = A x* + e,
+// each operation rounded on its own (no fused multiply-add), in the order
+// the definition writes them.
+__device__ __forceinline__ void igen_pair(const HugeK& H, double xi, double xj, double gi, double gj, double& bi,
+                                          double& bj, double& ei, double& ej) {
+#pragma clang fp contract(off)
+    ei = H.tau * (H.c * gi + H.sn * gj) / H.so;
+    ej = H.tau * (-H.sn * gi + H.c * gj) / H.se;
+    bi = H.so * (H.c * xi + H.sn * xj) + ei;
+    bj = H.se * (-H.sn * xi + H.c * xj) + ej;
+}
+
+// b for every pair; part = sum e^2
+__global__ __launch_bounds__(kHB) void kh_generate(HugeK H, double2* __restrict__ b, double* __restrict__ part) {
+    double v[1] = {0.0};
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        double xi, gi, xj, gj, bi, bj, ei, ej;
+        planted_at(H, 2 * k, xi, gi);
+        planted_at(H, 2 * k + 1, xj, gj);
+        igen_pair(H, xi, xj, gi, gj, bi, bj, ei, ej);
+        b[k] = make_double2(bi, bj);
+        v[0] += ei * ei + ej * ej;
+    }
+    store_partials<1, 1>(v, part);
+}
+
+__global__ __launch_bounds__(kHB) void kh_planted(HugeK H, double* __restrict__ xs, double* __restrict__ g) {
+    for (int64_t i = gtid(); i < H.n; i += gstride()) {
+        double a, b;
+        planted_at(H, i, a, b);
+        if (xs) xs[i] = a;
+        if (g) g[i] = b;
+    }
+}
+
+// part = (sum (x - x*)^2, sum x*^2)
+__global__ __launch_bounds__(kHB) void kh_err(HugeK H, const double* __restrict__ x, double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = gtid(); i < H.n; i += gstride()) {
+        double a, b;
+        planted_at(H, i, a, b);
+        const double d = x[i] - a;
+        v[0] += d * d;
+        v[1] += a * a;
+    }
+    store_partials<2, 2>(v, part);
+}
+
+// trans = 0: out (m) = A in (n), rows n..m-1 zero; trans = 1: out (n) = A^T in (top n of m)
+__global__ __launch_bounds__(kHB) void kh_apply(HugeK H, int64_t m, int trans, const double2* __restrict__ in,
+                                                double2* __restrict__ out) {
+    const int64_t np = H.n / 2;
+    const int64_t total = trans ? np : m / 2;
+    for (int64_t k = gtid(); k < total; k += gstride()) {
+        if (k >= np) {
+            out[k] = make_double2(0.0, 0.0);
+            continue;
+        }
+        const double2 a = in[k];
+        double oi, oj;
+        if (trans)
+            at_pair(H, a.x, a.y, oi, oj);
+        else
+            a_pair(H, a.x, a.y, oi, oj);
+        out[k] = make_double2(oi, oj);
+    }
+}
+
+// part = (sum |x|, sum r^2, sum b r | max |A^T r|), r = A x - b
+__global__ __launch_bounds__(kHB) void kh_gap(HugeK H, const double2* __restrict__ x, const double2* __restrict__ b,
+                                              double* __restrict__ part) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 xv = x[k], bv = b[k];
+        double yi, yj, gi, gj;
+        a_pair(H, xv.x, xv.y, yi, yj);
+        const double ri = yi - bv.x, rj = yj - bv.y;
+        at_pair(H, ri, rj, gi, gj);
+        v[0] += fabs(xv.x) + fabs(xv.y);
+        v[1] += ri * ri + rj * rj;
+        v[2] += bv.x * ri + bv.y * rj;
+        v[3] = fmax(v[3], fmax(fabs(gi), fabs(gj)));
+    }
+    store_partials<4, 3>(v, part);
+}
+
+// ---- CG-Newton ---------------------------------------------------------------
+// M = (diag(A^T A) + d)^{-1}, the Jacobi preconditioner, on the pair
+__device__ __forceinline__ dv2 precond(const HugeK& H, dv2 d) {
+    dv2 m;
+    m.x = 1.0 / (H.cn0 + d.x);
+    m.y = 1.0 / (H.cn1 + d.y);
+    return m;
+}
+
+__device__ __forceinline__ dv2 hess_v(const HugeK& H, dv2 p, dv2 d) {
+    const double2 h = hess_pair(H, make_double2(p.x, p.y), make_double2(d.x, d.y));
+    dv2 o;
+    o.x = h.x;
+    o.y = h.y;
+    return o;
+}
+
+// Start of a Newton step at x: grad f_mu = tau x / w + A^T (A x - b), the
+// Hessian diagonal d (primal: tau mu^2 / w^3; primal-dual: tau (1 - x gd / w) / w),
+// and PCG's start from dx = 0: r = -grad, u = M r.
+// part = (r.u, u.Hu, r.r | max |grad|).
+__global__ __launch_bounds__(kHB) void kh_setup(HugeK H, const double2* __restrict__ x,
+                                                const double2* __restrict__ gd, const double2* __restrict__ b,
+                                                double mu, int primal, double2* __restrict__ d,
+                                                double2* __restrict__ r, double* __restrict__ part) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 xv = x[k], bv = b[k];
+        const double2 gv = primal ? make_double2(0.0, 0.0) : gd[k];
+        double yi, yj, ai, aj;
+        a_pair(H, xv.x, xv.y, yi, yj);
+        at_pair(H, yi - bv.x, yj - bv.y, ai, aj);
+        const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
+        const double gri = H.tau * xv.x / wi + ai, grj = H.tau * xv.y / wj + aj;
+        dv2 dv, rv;
+        if (primal) {
+            dv.x = H.tau * mu * mu / (wi * wi * wi);
+            dv.y = H.tau * mu * mu / (wj * wj * wj);
+        } else {
+            dv.x = H.tau * (1.0 - xv.x * gv.x / wi) / wi;
+            dv.y = H.tau * (1.0 - xv.y * gv.y / wj) / wj;
+        }
+        rv.x = -gri;
+        rv.y = -grj;
+        const dv2 u = precond(H, dv) * rv;
+        const dv2 w = hess_v(H, u, dv);
+        d[k] = make_double2(dv.x, dv.y);
+        r[k] = make_double2(rv.x, rv.y);
+        v[0] += rv.x * u.x + rv.y * u.y;
+        v[1] += w.x * u.x + w.y * u.y;
+        v[2] += rv.x * rv.x + rv.y * rv.y;
+        v[3] = fmax(v[3], fmax(fabs(gri), fabs(grj)));
+    }
+    store_partials<4, 3>(v, part);
+}
+
+// PCG scalars after kh_setup: gamma = r.u, ||rhs||, the stop test
+// ||r|| > rtol ||rhs|| before the first iteration, alpha = gamma / u.Hu.
+__global__ __launch_bounds__(1024) void kh_cg_init(const double* __restrict__ part, int nb, HCg* cs, double rtol,
+                                                   int maxit) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        v[0] += part[4 * q];
+        v[1] += part[4 * q + 1];
+        v[2] += part[4 * q + 2];
+        v[3] = fmax(v[3], part[4 * q + 3]);
+    }
+    block_reduce_stats<4, 3>(v);
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(v[2]);
+        cs->gamma = v[0];
+        cs->rr0 = v[2];
+        cs->stop = rtol * rn;
+        cs->gmax = v[3];
+        cs->beta = 0.0;
+        cs->iters = 0;
+        cs->alpha = v[1] > 0.0 ? v[0] / v[1] : 0.0;
+        cs->done = (maxit <= 0 || !(rn > cs->stop) || !(v[1] > 0.0)) ? 1 : 0;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ dv2 ld2(const dv2* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st2(dv2 v, dv2* p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// One PCG iteration: u = M r, p = u + beta p, dx += alpha p, r -= alpha H p,
+// then for the next iteration u = M r, w = H u; part = (r.u, w.u, r.r).
+// first: p and dx are not read (beta = 0, dx = 0).  U pairs per thread per
+// trip (loads issued together), NT: nontemporal accesses.
+template <int U, bool NT>
+__global__ __launch_bounds__(kHB) void kh_cg_iter(HugeK H, dv2* __restrict__ dx, dv2* __restrict__ r,
+                                                  dv2* __restrict__ p, const dv2* __restrict__ d, int first,
+                                                  const HCg* __restrict__ cs, double* __restrict__ part) {
+    if (cs->done) return;
+    const double a = cs->alpha, be = cs->beta;
+    double v[3] = {0.0, 0.0, 0.0};
+    const int64_t np = H.n / 2;
+    const int64_t S = gstride();
+    for (int64_t base = gtid(); base < np; base += U * S) {
+        dv2 R[U], D[U], P[U], X[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t k = base + q * S;
+            if (k < np) {
+                R[q] = ld2<NT>(r + k);
+                D[q] = ld2<NT>(d + k);
+                if (!first) {
+                    P[q] = ld2<NT>(p + k);
+                    X[q] = ld2<NT>(dx + k);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t k = base + q * S;
+            if (k < np) {
+                const dv2 mq = precond(H, D[q]);
+                const dv2 u0 = mq * R[q];
+                const dv2 pv = first ? u0 : u0 + be * P[q];
+                const dv2 sv = hess_v(H, pv, D[q]);
+                const dv2 xo = first ? a * pv : X[q] + a * pv;
+                const dv2 rn = R[q] - a * sv;
+                const dv2 u1 = mq * rn;
+                const dv2 w1 = hess_v(H, u1, D[q]);
+                st2<NT>(pv, p + k);
+                st2<NT>(xo, dx + k);
+                st2<NT>(rn, r + k);
+                v[0] += rn.x * u1.x + rn.y * u1.y;
+                v[1] += w1.x * u1.x + w1.y * u1.y;
+                v[2] += rn.x * rn.x + rn.y * rn.y;
+            }
+        }
+    }
+    store_partials<3, 3>(v, part);
+}
+
+// One iteration done: stop when ||r|| <= stop or at maxit; else
+// beta = gamma' / gamma, alpha = gamma' / (w.u - beta gamma' / alpha).
+__global__ __launch_bounds__(1024) void kh_cg_next(const double* __restrict__ part, int nb, HCg* cs, int maxit) {
+    if (cs->done) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        v[0] += part[3 * q];
+        v[1] += part[3 * q + 1];
+        v[2] += part[3 * q + 2];
+    }
+    block_reduce_stats<3, 3>(v);
+    if (threadIdx.x == 0) {
+        cs->iters += 1;
+        if (cs->iters >= maxit || !(sqrt(v[2]) > cs->stop)) {
+            cs->done = 1;
+            return;
+        }
+        const double be = v[0] / cs->gamma;
+        const double den = v[1] - be * v[0] / cs->alpha;
+        if (!(den > 0.0)) {  // no curvature left along the next direction
+            cs->done = 1;
+            return;
+        }
+        cs->beta = be;
+        cs->alpha = v[0] / den;
+        cs->gamma = v[0];
+    }
+}
+
+// Line search terms at x along dx, for the step lengths a0 2^-t, t < kLsBatch:
+// part = (sum psi(x), sum r(x)^2, grad . dx, sum psi(x + a_t dx) [t], sum r(x + a_t dx)^2 [t])
+// with psi(v) = sqrt(mu^2 + v^2) - mu and r(v) = A v - b.
+__global__ __launch_bounds__(kHB) void kh_ls(HugeK H, const double2* __restrict__ x, const double2* __restrict__ dx,
+                                             const double2* __restrict__ b, double mu, double a0,
+                                             double* __restrict__ part) {
+    double v[kLsStats];
+#pragma unroll
+    for (int q = 0; q < kLsStats; ++q) v[q] = 0.0;
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 xv = x[k], sv = dx[k], bv = b[k];
+        double yi, yj, ai, aj;
+        a_pair(H, xv.x, xv.y, yi, yj);
+        const double ri = yi - bv.x, rj = yj - bv.y;
+        at_pair(H, ri, rj, ai, aj);
+        const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
+        v[0] += (wi - mu) + (wj - mu);
+        v[1] += ri * ri + rj * rj;
+        v[2] += (H.tau * xv.x / wi + ai) * sv.x + (H.tau * xv.y / wj + aj) * sv.y;
+        double a = a0;
+#pragma unroll
+        for (int t = 0; t < kLsBatch; ++t) {
+            const double ui = xv.x + a * sv.x, uj = xv.y + a * sv.y;
+            double qi, qj;
+            a_pair(H, ui, uj, qi, qj);
+            qi -= bv.x;
+            qj -= bv.y;
+            v[3 + t] += (sqrt(mu * mu + ui * ui) - mu) + (sqrt(mu * mu + uj * uj) - mu);
+            v[3 + kLsBatch + t] += qi * qi + qj * qj;
+            a *= 0.5;
+        }
+    }
+    store_partials<kLsStats, kLsStats>(v, part);
+}
+
+// dual update of the primal-dual diagonal at the old x (with the full
+// direction), then x += a dx
+__global__ __launch_bounds__(kHB) void kh_step(int64_t np, double2* __restrict__ x, double2* __restrict__ gd,
+                                               const double2* __restrict__ dx, double a, double mu, int primal) {
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 xv = x[k], sv = dx[k];
+        if (!primal) {
+            const double2 g0 = gd[k];
+            const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
+            const double g1i = g0.x + (-g0.x + xv.x / wi + (1.0 - xv.x * g0.x / wi) * sv.x / wi);
+            const double g1j = g0.y + (-g0.y + xv.y / wj + (1.0 - xv.y * g0.y / wj) * sv.y / wj);
+            gd[k] = make_double2(fmin(1.0, fmax(-1.0, g1i)), fmin(1.0, fmax(-1.0, g1j)));
+        }
+        x[k] = make_double2(xv.x + a * sv.x, xv.y + a * sv.y);
+    }
+}
+
+__global__ void kh_zero(double* __restrict__ v, int64_t n) {
+    for (int64_t i = gtid(); i < n; i += gstride()) v[i] = 0.0;
+}
+
+int blocks_for(int64_t pairs) {
+    int64_t g = (pairs + kHB - 1) / kHB;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kHMaxBlocks));
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct l1ls_huge {
+    l1ls_huge_params prm;
+    HugeK k;
+    double L = 0, fstar = 0;
+    int device = 0;
+    double* b = nullptr;  // n: the top n entries of b (rows n..m-1 of b are zero)
+    double* part = nullptr;
+    DevArena arena;
+    // HIP-event times of the last solve with opts.time_kernels set:
+    // [0] PCG iteration pass, [1] line-search pass, [2] Newton setup pass
+    mutable double kt_ms[3] = {0, 0, 0};
+    mutable int64_t kt_calls[3] = {0, 0, 0};
+    ~l1ls_huge() { arena.release(); }
+};
+
+namespace {
+
+// Sum of NS statistics over nb partial slots in fixed order (the last
+// NS - nsum of them take the maximum).
+l1ls_status host_stats(const double* part, int ns, int nsum, int nb, hipStream_t s, double* out) {
+    std::vector<double> h((size_t)ns * nb);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int q = 0; q < ns; ++q) out[q] = 0.0;
+    for (int bk = 0; bk < nb; ++bk)
+        for (int q = 0; q < ns; ++q) {
+            const double v = h[(size_t)ns * bk + q];
+            out[q] = q < nsum ? out[q] + v : std::max(out[q], v);
+        }
+    return L1LS_OK;
+}
+
+l1ls_status huge_gap(const l1ls_huge* H, double tau, const double* x, hipStream_t s, double* P, double* D,
+                     double* gap) {
+    const int nb = blocks_for(H->k.n / 2);
+    HugeK K = H->k;
+    hipLaunchKernelGGL(kh_gap, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)H->b, H->part);
+    HIP_TRY(hipGetLastError());
+    double t[4];
+    L1LS_TRY(host_stats(H->part, 4, 3, nb, s, t));
+    *P = tau * t[0] + 0.5 * t[1];
+    const double theta = (t[3] <= tau) ? 1.0 : tau / t[3];
+    *D = -0.5 * theta * theta * t[1] - theta * t[2];
+    *gap = (*P - *D) / std::fabs(*P);
+    if (!is_fin(*P) || !is_fin(*D)) return L1LS_E_NONFINITE;
+    return L1LS_OK;
+}
+
+l1ls_status huge_err(const l1ls_huge* H, const double* x, hipStream_t s, double* out) {
+    const int nb = blocks_for(H->k.n / 2);
+    hipLaunchKernelGGL(kh_err, dim3(nb), dim3(kHB), 0, s, H->k, x, H->part);
+    HIP_TRY(hipGetLastError());
+    double t[2];
+    L1LS_TRY(host_stats(H->part, 2, 2, nb, s, t));
+    *out = (t[1] > 0) ? std::sqrt(t[0] / t[1]) : std::sqrt(t[0]);
+    return L1LS_OK;
+}
+
+}  // namespace
+
+extern "C" void l1ls_huge_params_default(int64_t n, uint64_t seed, l1ls_huge_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n = n;
+    p->m = 2 * n;
+    p->s = n / 1024;
+    p->theta = 2.0 * M_PI / 3.0;
+    p->sigma_odd = 0.1;
+    p->sigma_even = 100.0;
+    p->x_neg = -1.0e4;
+    p->x_pos = 0.1;
+    p->tau = 1.0;
+    p->seed = seed;
+}
+
+extern "C" size_t l1ls_huge_bytes(int64_t n) {
+    if (n < 2) return 0;
+    return (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 4096;
+}
+
+extern "C" size_t l1ls_huge_solve_bytes(int64_t n) {
+    if (n < 2) return 0;
+    return 5 * (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 4096;
+}
+
+extern "C" l1ls_status l1ls_huge_generate(const l1ls_huge_params* p, void* stream, l1ls_huge** out) {
+    if (!p || !out) return L1LS_E_ARG;
+    *out = nullptr;
+    const int64_t n = p->n, m = p->m;
+    if (n < 2 || n % 2 || n > kHugeMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return L1LS_E_ARG;
+    if (!(p->sigma_odd > 0) || !(p->sigma_even > 0) || !(p->tau > 0) || !is_fin(p->sigma_odd) ||
+        !is_fin(p->sigma_even) || !is_fin(p->tau) || !is_fin(p->theta) || !is_fin(p->x_neg) || !is_fin(p->x_pos))
+        return L1LS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    auto* H = new (std::nothrow) l1ls_huge();
+    if (!H) return L1LS_E_NOMEM;
+    H->prm = *p;
+    HugeK& K = H->k;
+    K.n = n;
+    K.s = p->s;
+    K.c = std::cos(p->theta);
+    K.sn = std::sin(p->theta);
+    K.so = p->sigma_odd;
+    K.se = p->sigma_even;
+    K.cn0 = K.so * K.so * K.c * K.c + K.se * K.se * K.sn * K.sn;
+    K.cn1 = K.so * K.so * K.sn * K.sn + K.se * K.se * K.c * K.c;
+    K.tau = p->tau;
+    K.xneg = p->x_neg;
+    K.xpos = p->x_pos;
+    K.key = seed_key(p->seed);
+    H->L = std::max(K.so * K.so, K.se * K.se);
+    auto fail = [&](l1ls_status st) {
+        (void)hipStreamSynchronize(s);
+        delete H;
+        return st;
+    };
+    if (hipGetDevice(&H->device) != hipSuccess) return fail(L1LS_E_HIP);
+    l1ls_status st = H->arena.alloc(&H->b, (size_t)n);
+    if (st == L1LS_OK) st = H->arena.alloc(&H->part, (size_t)kHMaxBlocks * kLsStats);
+    if (st != L1LS_OK) return fail(st);
+    const int nb = blocks_for(n / 2);
+    hipLaunchKernelGGL(kh_generate, dim3(nb), dim3(kHB), 0, s, K, (double2*)H->b, H->part);
+    if (hipGetLastError() != hipSuccess) return fail(L1LS_E_HIP);
+    double e2 = 0;
+    st = host_stats(H->part, 1, 1, nb, s, &e2);
+    if (st != L1LS_OK) return fail(st);
+    // f* = tau ||x*||_1 + 0.5 ||e||^2 with floor(s/2) entries x_neg, the rest x_pos
+    const int64_t nneg = p->s / 2, npos = p->s - nneg;
+    H->fstar = p->tau * ((double)nneg * std::fabs(p->x_neg) + (double)npos * std::fabs(p->x_pos)) + 0.5 * e2;
+    *out = H;
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_huge_describe(const l1ls_huge* H, l1ls_huge_desc* out) {
+    if (!H || !out) return L1LS_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->params = H->prm;
+    out->L = H->L;
+    out->f_star = H->fstar;
+    out->c = H->k.c;
+    out->s_rot = H->k.sn;
+    out->b_dev = H->b;
+    return L1LS_OK;
+}
+
+extern "C" void l1ls_huge_free(l1ls_huge* H) {
+    if (!H) return;
+    int cur = 0;
+    const bool sw = hipGetDevice(&cur) == hipSuccess && cur != H->device;
+    if (sw) (void)hipSetDevice(H->device);
+    (void)hipDeviceSynchronize();
+    delete H;
+    if (sw) (void)hipSetDevice(cur);
+}
+
+extern "C" l1ls_status l1ls_huge_planted(const l1ls_huge* H, double* x_star_dev, double* g_dev, void* stream) {
+    if (!H || (!x_star_dev && !g_dev)) return L1LS_E_ARG;
+    hipLaunchKernelGGL(kh_planted, dim3(blocks_for(H->k.n / 2)), dim3(kHB), 0, (hipStream_t)stream, H->k,
+                       x_star_dev, g_dev);
+    HIP_TRY(hipGetLastError());
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_huge_apply(const l1ls_huge* H, int32_t trans, const double* in_dev, double* out_dev,
+                                       void* stream) {
+    if (!H || !in_dev || !out_dev || (trans != 0 && trans != 1)) return L1LS_E_ARG;
+    if (!aligned16(in_dev) || !aligned16(out_dev)) return L1LS_E_ARG;
+    const int64_t m = H->prm.m;
+    const int nb = blocks_for(trans ? H->k.n / 2 : m / 2);
+    hipLaunchKernelGGL(kh_apply, dim3(nb), dim3(kHB), 0, (hipStream_t)stream, H->k, m, (int)trans,
+                       (const double2*)in_dev, (double2*)out_dev);
+    HIP_TRY(hipGetLastError());
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_huge_objective_gap(const l1ls_huge* H, double tau, const double* x_dev, double* P,
+                                               double* D, double* gap, void* stream) {
+    if (!H || !x_dev || !P || !D || !gap || !(tau > 0) || !is_fin(tau)) return L1LS_E_ARG;
+    if (!aligned16(x_dev)) return L1LS_E_ARG;
+    return huge_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap);
+}
+
+extern "C" l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
+                                                 l1ls_report* rep) {
+    if (!H || !o || !x) return L1LS_E_ARG;
+    if (o->max_iter < 0 || !aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
+    if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o->stream;
+    const double tau = o->tau > 0 ? o->tau : H->prm.tau;
+    const double mu = o->mu > 0 ? o->mu : 1e-5;
+    const double prtol = o->pcg_rtol > 0 ? o->pcg_rtol : 0.1;
+    const int maxbt = o->max_backtrack > 0 ? o->max_backtrack : 50;
+    const int pcgmax = o->pcg_maxit > 0 ? o->pcg_maxit : 1000;
+    const int primal = o->hessian == 1 ? 1 : 0;
+    const double gtol = (o->rel_gap_tol > 0 ? o->rel_gap_tol : 1e-9) * tau;
+    if (!is_fin(tau) || !is_fin(mu)) return L1LS_E_ARG;
+    HugeK K = H->k;
+    K.tau = tau;
+    const int64_t n = K.n, np = n / 2;
+    const int nb = blocks_for(np);
+    DevArena W;
+    double *gd = nullptr, *dx = nullptr, *r = nullptr, *p = nullptr, *d = nullptr, *part = nullptr;
+    HCg* cs = nullptr;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(s);
+        W.release();
+    };
+    l1ls_status st = L1LS_OK;
+    for (double** v : {&gd, &dx, &r, &p, &d})
+        if (st == L1LS_OK) st = W.alloc(v, (size_t)n);
+    if (st == L1LS_OK) st = W.alloc(&part, (size_t)kHMaxBlocks * kLsStats);
+    if (st == L1LS_OK) st = W.alloc(&cs, 1);
+    if (st != L1LS_OK) {
+        release();
+        return st;
+    }
+    const bool tk = o->time_kernels != 0;
+    constexpr int kBatch = 8;
+    hipEvent_t ev[4 * kBatch + 2];
+    int nev = 0;
+    if (tk) {
+        for (int q = 0; q < 3; ++q) {
+            H->kt_ms[q] = 0;
+            H->kt_calls[q] = 0;
+        }
+        for (; nev < 4 * kBatch + 2; ++nev)
+            if (hipEventCreate(&ev[nev]) != hipSuccess) break;
+        if (nev < 4 * kBatch + 2) {
+            for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
+            release();
+            return L1LS_E_HIP;
+        }
+    }
+    auto elapsed = [&](int a, int b) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+        return (double)ms;
+    };
+    auto run = [&]() -> l1ls_status {
+        if (o->x0_dev) {
+            if (o->x0_dev != x) HIP_TRY(hipMemcpyAsync(x, o->x0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, x, n);
+        }
+        hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, gd, n);
+        HIP_TRY(hipGetLastError());
+        int64_t newton = 0, pcg_total = 0;
+        double gnorm = INFINITY;
+        const double armijo = 1e-4;
+        for (newton = 0; newton < o->max_iter; ++newton) {
+            if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch], s));
+            hipLaunchKernelGGL(kh_setup, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)gd,
+                               (const double2*)H->b, mu, primal, (double2*)d, (double2*)r, part);
+            if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch + 1], s));
+            hipLaunchKernelGGL(kh_cg_init, dim3(1), dim3(1024), 0, s, part, nb, cs, prtol, pcgmax);
+            HIP_TRY(hipGetLastError());
+            HCg c;
+            HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (tk) {
+                H->kt_ms[2] += elapsed(4 * kBatch, 4 * kBatch + 1);
+                H->kt_calls[2] += 1;
+            }
+            gnorm = c.gmax;
+            if (!is_fin(gnorm)) return L1LS_E_NONFINITE;
+            if (gnorm <= gtol) break;
+            // PCG from dx = 0; the first update writes dx without reading it
+            if (c.done) hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, dx, n);
+            int first = 1;
+            while (!c.done) {
+                const int before = c.iters;
+                for (int q = 0; q < kBatch; ++q) {
+                    if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
+                    hipLaunchKernelGGL((kh_cg_iter<kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K, (dv2*)dx, (dv2*)r,
+                                       (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
+                    if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
+                    hipLaunchKernelGGL(kh_cg_next, dim3(1), dim3(1024), 0, s, part, nb, cs, pcgmax);
+                    first = 0;
+                }
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (tk) {  // the passes that ran: one per iteration of this batch
+                    const int ran = c.iters - before;
+                    for (int q = 0; q < ran; ++q) H->kt_ms[0] += elapsed(2 * q, 2 * q + 1);
+                    H->kt_calls[0] += ran;
+                }
+            }
+            pcg_total += c.iters;
+            // Armijo backtracking on f_mu(x + a dx), a = 2^-t, kLsBatch lengths per pass
+            double a = std::ldexp(1.0, -maxbt);
+            bool found = false;
+            for (int t0b = 0; t0b < maxbt && !found; t0b += kLsBatch) {
+                const double a0 = std::ldexp(1.0, -t0b);
+                if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch], s));
+                hipLaunchKernelGGL(kh_ls, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)dx,
+                                   (const double2*)H->b, mu, a0, part);
+                if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch + 1], s));
+                HIP_TRY(hipGetLastError());
+                double t[kLsStats];
+                L1LS_TRY(host_stats(part, kLsStats, kLsStats, nb, s, t));
+                if (tk) {
+                    H->kt_ms[1] += elapsed(4 * kBatch, 4 * kBatch + 1);
+                    H->kt_calls[1] += 1;
+                }
+                const double f0 = tau * t[0] + 0.5 * t[1];
+                const double slope = t[2];
+                for (int q = 0; q < kLsBatch && t0b + q < maxbt; ++q) {
+                    const double at = std::ldexp(1.0, -(t0b + q));
+                    const double ft = tau * t[3 + q] + 0.5 * t[3 + kLsBatch + q];
+                    if (ft <= f0 + armijo * at * slope) {
+                        a = at;
+                        found = true;
+                        break;
+                    }
+                }
+            }
+            hipLaunchKernelGGL(kh_step, dim3(nb), dim3(kHB), 0, s, np, (double2*)x, (double2*)gd,
+                               (const double2*)dx, a, mu, primal);
+            HIP_TRY(hipGetLastError());
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        l1ls_report rr;
+        std::memset(&rr, 0, sizeof(rr));
+        rr.iterations = newton;
+        rr.inner = pcg_total;
+        L1LS_TRY(huge_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap));
+        L1LS_TRY(huge_err(H, x, s, &rr.rel_err));
+        rr.converged = (gnorm <= gtol) ? 1 : 0;
+        rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = rr;
+        return rr.converged ? L1LS_OK : L1LS_NOT_CONVERGED;
+    };
+    st = run();
+    release();
+    for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
+    return st;
+}
+
+extern "C" l1ls_status l1ls_huge_kernel_times(const l1ls_huge* H, double* ms, int64_t* calls) {
+    if (!H || !ms || !calls) return L1LS_E_ARG;
+    for (int q = 0; q < 3; ++q) {
+        ms[q] = H->kt_ms[q];
+        calls[q] = H->kt_calls[q];
+    }
+    return L1LS_OK;
+}

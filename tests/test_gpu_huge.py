@@ -1,0 +1,220 @@
+"""Section 8.9 (Table 1) instance class on the GPU against the CPU oracle.
+
+Generation is compared bit for bit (the device evaluates IGen steps 3 and
+4 in the oracle's operation order without contraction); operator products,
+the duality gap and CG-Newton trajectories within FP64 rounding bounds.  At
+the Table 1 size n = 2^30 the checks are sampled b values (the oracle
+computes single pairs through the inverse support bijection) and properties
+of the solve.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_03520_amd as L
+from oracle import fista as OF
+from oracle import newton as ON
+from oracle.huge import HugeInstance, b_at_pairs, planted_at
+
+pytestmark = pytest.mark.gpu
+
+SEED = 1503035206
+# (n, s, m, overrides): one block, ragged against the 256-pair blocks,
+# several blocks, the minimum size, square A, non-default parameters
+CASES = [
+    (64, 6, None, {}),
+    (4098, 4, None, {}),
+    (2 ** 16, 64, None, {}),
+    (2, 1, None, {}),
+    (1030, 3, 1030, {}),
+    (2050, 7, 4100, dict(theta=0.3, sigma_odd=2.0, sigma_even=0.5, x_neg=-3.0, x_pos=7.5, tau=0.37)),
+]
+
+
+def make(n, s, m, kw):
+    p = L.huge_params(n, SEED, s=s, **({} if m is None else {"m": m}), **kw)
+    H = L.HugeInstance(p)
+    O = HugeInstance(n, s, SEED, m=m, **kw)
+    return H, O
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_generation_is_bitwise_the_oracle(case):
+    n, s, m, kw = case
+    H, O = make(n, s, m, kw)
+    d = H.describe()
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty(n, dtype=torch.float64, device="cuda")
+    H.planted(xs, g)
+    assert np.array_equal(host(xs), O.xstar)
+    assert np.array_equal(host(g), O.g)
+    b = L.device_to_numpy(d.b_dev, n, np.float64)
+    diff = np.flatnonzero(b != O.b[:n])
+    assert diff.size == 0, (diff[:8], b[diff[:8]], O.b[:n][diff[:8]], np.spacing(O.b[:n][diff[:8]]))
+    assert not O.b[n:].any()
+    assert d.f_star == pytest.approx(O.fstar, rel=1e-13)
+    assert d.L == O.L and d.c == O.c and d.s_rot == O.sn
+    H.free()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_operator_products_match_oracle(case):
+    n, s, m, kw = case
+    H, O = make(n, s, m, kw)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(O.m)
+    ax = torch.full((O.m,), float("nan"), dtype=torch.float64, device="cuda")
+    aty = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    H.apply(0, dev(x), ax)
+    H.apply(1, dev(y), aty)
+    ref_ax, ref_aty = O.matvec(x), O.rmatvec(y)
+    tol = 4 * np.finfo(float).eps * max(O.sigma.max(), 1.0)
+    assert np.abs(host(ax) - ref_ax).max() <= tol * np.abs(x).max() * 2
+    assert np.abs(host(aty) - ref_aty).max() <= tol * np.abs(y).max() * 2
+    H.free()
+
+
+@pytest.mark.parametrize("case", CASES[:3] + CASES[5:])
+def test_gap_matches_oracle(case):
+    n, s, m, kw = case
+    H, O = make(n, s, m, kw)
+    A = O.sparse_A()
+    rng = np.random.default_rng(5)
+    eps = np.finfo(float).eps
+    for x in (O.xstar, O.xstar + 0.01 * rng.standard_normal(n), np.zeros(n)):
+        P, D, gap = H.objective_gap(O.tau, dev(x))
+        Po, Do, go = OF.duality_gap(lambda v: A @ v, lambda v: A.T @ v, O.b, O.tau, x)
+        # r = A x - b is formed from terms of size |A x| + |b| (up to 1e6 on the
+        # support), so each side's sums carry rounding of that size
+        ax = np.abs(A @ x)
+        scale = float(np.sum((ax + np.abs(O.b[: O.m])) * (ax + np.abs(O.b[: O.m]))))
+        assert abs(P - Po) <= 8 * eps * (scale + abs(Po))
+        assert abs(D - Do) <= 8 * eps * (scale + abs(Do))
+    H.free()
+
+
+def newton_pair(H, O, steps, **kw):
+    x, rep, st = H.solve_cg_newton(max_iter=steps, **kw)
+    hess = "primal" if kw.get("hessian", 0) == 1 else "primal_dual"
+    xo, sto = ON.newton_cg(O.matvec, O.rmatvec, O.colnorm2(), O.b, O.tau, max_newton=steps, hessian=hess)
+    return host(x), rep, st, xo, sto
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 8])
+def test_cg_newton_trajectory_matches_oracle(steps):
+    n, s = 4098, 4
+    H, O = make(n, s, None, {})
+    x, rep, st, xo, sto = newton_pair(H, O, steps)
+    assert st == L.L1LS_NOT_CONVERGED and rep["iterations"] == steps
+    assert abs(rep["inner"] - sto["pcg"]) <= 2 * steps
+    scale = np.abs(xo).max()
+    assert np.abs(x - xo).max() <= 1e-6 * scale
+    rel = np.linalg.norm(x - O.xstar) / np.linalg.norm(O.xstar)
+    assert rep["rel_err"] == pytest.approx(rel, rel=1e-6)
+    H.free()
+
+
+def test_cg_newton_primal_hessian_matches_oracle():
+    H, O = make(2050, 7, 4100, CASES[5][3])
+    x, rep, st, xo, sto = newton_pair(H, O, 3, hessian=1)
+    assert rep["iterations"] == 3
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+    H.free()
+
+
+def test_cg_newton_converges_to_oracle_minimiser():
+    n, s = 4098, 4
+    H, O = make(n, s, None, {})
+    # the FP64 floor of ||grad f_mu||_inf here is about eps sigma_even max|b| = 2e-8
+    x, rep, st = H.solve_cg_newton(max_iter=300, rel_gap_tol=1e-7)
+    xo, sto = ON.newton_cg(O.matvec, O.rmatvec, O.colnorm2(), O.b, O.tau, max_newton=300, grad_tol=1e-7)
+    assert sto["grad_inf"] <= 1e-7
+    assert st == L.L1LS_OK and rep["converged"] == 1
+    x = host(x)
+    assert np.abs(x - xo).max() <= 1e-7 * np.abs(xo).max()
+    # the smoothed minimiser sits within O(mu) of x*: relative error far below 1e-4
+    assert rep["rel_err"] <= 1e-6
+    H.free()
+
+
+def test_cg_newton_edge_cases():
+    H, O = make(64, 6, None, {})
+    n = 64
+    # no Newton step: x stays at the start
+    x, rep, st = H.solve_cg_newton(max_iter=0)
+    assert rep["iterations"] == 0 and not host(x).any()
+    # warm start at x* in place: one gradient evaluation, few steps
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    H.planted(xs)
+    x, rep, st = H.solve_cg_newton(x_out=xs, x0=xs, max_iter=50)
+    assert rep["rel_err"] <= 1e-6
+    # options this class does not build, misaligned vectors
+    buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    o = L.solve_opts(max_iter=1)
+    rep = L.Report()
+    assert L.lib().l1ls_huge_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr() + 8),
+                                             ctypes.byref(rep)) == -1
+    for kw in (dict(precision=L.F32), dict(polish=1)):
+        o = L.solve_opts(max_iter=1, **kw)
+        assert L.lib().l1ls_huge_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr()),
+                                                 ctypes.byref(rep)) == -6
+    assert L.lib().l1ls_huge_apply(H.handle, 2, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(buf.data_ptr()),
+                                   None) == -1
+    H.free()
+
+
+def test_s_zero_gives_zero_planted_solution():
+    H, O = make(256, 0, None, {})
+    xs = torch.full((256,), 1.0, dtype=torch.float64, device="cuda")
+    H.planted(xs)
+    assert not host(xs).any()
+    assert H.describe().f_star == pytest.approx(O.fstar, rel=1e-13)
+    H.free()
+
+
+def test_table_1_size_sampled_generation_and_solve():
+    # n = 2^30, m = 2^31, s = 2^20: the smallest instance of Table 1.  b is
+    # checked on sampled pairs (first, last, random) against the oracle's
+    # single-pair construction, the planted x* against the inverse bijection,
+    # and the 8-Newton-step solve against the behaviour section 8.9 reports.
+    n = 2 ** 30
+    p = L.huge_params(n, SEED)
+    H = L.HugeInstance(p)
+    d = H.describe()
+    rng = np.random.default_rng(2)
+    pairs = np.unique(np.r_[0, 1, n // 2 - 1, n // 4, rng.integers(0, n // 2, 60)])
+    bi, bj = b_at_pairs(n, p.s, SEED, pairs)
+    base = d.b_dev
+    for k, ei, ej in zip(pairs, bi, bj):
+        got = L.device_to_numpy(base + 16 * int(k), 2, np.float64)
+        assert got[0] == ei and got[1] == ej, int(k)
+    x, rep, st = H.solve_cg_newton(max_iter=8)
+    assert rep["iterations"] == 8
+    assert rep["rel_err"] <= 5e-4
+    # every Newton step ran a PCG that stopped before its 1000-iteration cap
+    # (section 8.9 reports about 100 per step; this reading of CG-Newton needs
+    # more at this size, see the oracle's growth from 2^14 to 2^18)
+    assert 8 <= rep["inner"] < 8 * 1000
+    # the planted values of the sampled indices, one by one
+    idx = np.unique(np.r_[2 * pairs, 2 * pairs + 1])
+    xs_ref, _ = planted_at(n, p.s, SEED, idx)
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    H.planted(xs)
+    got = host(xs[torch.from_numpy(idx).cuda()])
+    assert np.array_equal(got, xs_ref)
+    assert int(torch.count_nonzero(xs)) == p.s
+    del xs, x
+    H.free()
