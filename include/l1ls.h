@@ -447,9 +447,23 @@ l1ls_status l1ls_huge_objective_gap(const l1ls_huge* inst, double tau, const dou
 l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* inst, const l1ls_solve_opts* opts,
                                       double* x_dev, l1ls_report* report);
 
-/* HIP-event times of the passes of the last l1ls_huge_solve_cg_newton on
- * inst that ran with opts.time_kernels = 1: ms[q] total milliseconds and
- * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r), 1 the
+/* The same CG-Newton one call at a time, for callers that report between
+ * Newton steps.  create: validates opts as l1ls_huge_solve_cg_newton (max_iter
+ * is not used), allocates l1ls_huge_solve_bytes(n), sets x_dev to the start;
+ * x_dev must stay valid until destroy.  step: up to `steps` more Newton steps
+ * (none once converged); report: totals since create, FP64 gap and
+ * ||x - x*|| / ||x*|| at the current x_dev; returns L1LS_OK once converged,
+ * else L1LS_NOT_CONVERGED.  destroy waits for the object's stream. */
+typedef struct l1ls_huge_newton l1ls_huge_newton;
+l1ls_status l1ls_huge_newton_create(const l1ls_huge* inst, const l1ls_solve_opts* opts, double* x_dev,
+                                    l1ls_huge_newton** out);
+l1ls_status l1ls_huge_newton_step(l1ls_huge_newton* newton, int64_t steps, l1ls_report* report);
+void l1ls_huge_newton_destroy(l1ls_huge_newton* newton);
+
+/* HIP-event times of the passes of the last CG-Newton on inst (solve or
+ * stepping object) created with opts.time_kernels = 1: ms[q] total milliseconds and
+ * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r; the first
+ * iteration of each PCG, which reads neither p nor dx, is left out), 1 the
  * line-search pass, 2 the Newton setup pass (gradient, d, PCG start). */
 l1ls_status l1ls_huge_kernel_times(const l1ls_huge* inst, double* ms, int64_t* calls);
 

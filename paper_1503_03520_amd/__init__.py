@@ -159,6 +159,9 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                                _P]),
     "l1ls_huge_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_huge_newton_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
+    "l1ls_huge_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
+    "l1ls_huge_newton_destroy": (None, [_P]),
     "l1ls_huge_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "l1ls_version": (ctypes.c_int32, []),
@@ -581,6 +584,10 @@ class HugeInstance:
                     "l1ls_huge_solve_cg_newton", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
         return x_out, rep.as_dict(), st
 
+    def newton(self, x_out=None, **kw):
+        """A HugeNewton stepping object (l1ls_huge_newton_create)."""
+        return HugeNewton(self, x_out, **kw)
+
     def kernel_times(self):
         """{pass: (total ms, launches)} of the last solve with time_kernels=1."""
         ms = (ctypes.c_double * 3)()
@@ -606,3 +613,34 @@ def huge_bytes(n):
 
 def huge_solve_bytes(n):
     return lib().l1ls_huge_solve_bytes(n)
+
+
+class HugeNewton:
+    """CG-Newton on a HugeInstance one call at a time (l1ls_huge_newton_*)."""
+
+    def __init__(self, inst, x_out=None, **kw):
+        import torch
+        self.inst = inst
+        self.x = x_out if x_out is not None else torch.empty(inst.params["n"], dtype=torch.float64, device="cuda")
+        self._o = solve_opts(**kw)
+        h = ctypes.c_void_p()
+        _check(lib().l1ls_huge_newton_create(inst.handle, ctypes.byref(self._o), _ptr(self.x), ctypes.byref(h)),
+               "l1ls_huge_newton_create")
+        self._h = h
+
+    def step(self, steps=1):
+        rep = Report()
+        st = _check(lib().l1ls_huge_newton_step(self._h, steps, ctypes.byref(rep)), "l1ls_huge_newton_step",
+                    allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+        return rep.as_dict(), st
+
+    def destroy(self):
+        if self._h:
+            lib().l1ls_huge_newton_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -632,64 +632,67 @@ extern "C" l1ls_status l1ls_huge_objective_gap(const l1ls_huge* H, double tau, c
     return huge_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap);
 }
 
-extern "C" l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
-                                                 l1ls_report* rep) {
-    if (!H || !o || !x) return L1LS_E_ARG;
-    if (o->max_iter < 0 || !aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
-    if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
-    const auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = (hipStream_t)o->stream;
-    const double tau = o->tau > 0 ? o->tau : H->prm.tau;
-    const double mu = o->mu > 0 ? o->mu : 1e-5;
-    const double prtol = o->pcg_rtol > 0 ? o->pcg_rtol : 0.1;
-    const int maxbt = o->max_backtrack > 0 ? o->max_backtrack : 50;
-    const int pcgmax = o->pcg_maxit > 0 ? o->pcg_maxit : 1000;
-    const int primal = o->hessian == 1 ? 1 : 0;
-    const double gtol = (o->rel_gap_tol > 0 ? o->rel_gap_tol : 1e-9) * tau;
-    if (!is_fin(tau) || !is_fin(mu)) return L1LS_E_ARG;
-    HugeK K = H->k;
-    K.tau = tau;
-    const int64_t n = K.n, np = n / 2;
-    const int nb = blocks_for(np);
-    DevArena W;
+// CG-Newton state between l1ls_huge_newton_step calls: the iterate x (the
+// caller's buffer), the primal-dual variable gd and the PCG vectors.
+struct l1ls_huge_newton {
+    static constexpr int kBatch = 8;  // PCG iterations enqueued between host checks
+    static constexpr int kEv = 2 * kBatch + 2;
+    const l1ls_huge* H = nullptr;
+    hipStream_t s = nullptr;
+    HugeK K{};
+    double tau = 1, mu = 1e-5, prtol = 0.1, gtol = 1e-9;
+    int maxbt = 50, pcgmax = 1000, primal = 0, nb = 1;
+    bool tk = false;
+    double* x = nullptr;
     double *gd = nullptr, *dx = nullptr, *r = nullptr, *p = nullptr, *d = nullptr, *part = nullptr;
     HCg* cs = nullptr;
-    auto release = [&]() {
-        (void)hipStreamSynchronize(s);
-        W.release();
-    };
-    l1ls_status st = L1LS_OK;
-    for (double** v : {&gd, &dx, &r, &p, &d})
-        if (st == L1LS_OK) st = W.alloc(v, (size_t)n);
-    if (st == L1LS_OK) st = W.alloc(&part, (size_t)kHMaxBlocks * kLsStats);
-    if (st == L1LS_OK) st = W.alloc(&cs, 1);
-    if (st != L1LS_OK) {
-        release();
-        return st;
-    }
-    const bool tk = o->time_kernels != 0;
-    constexpr int kBatch = 8;
-    hipEvent_t ev[4 * kBatch + 2];
+    DevArena W;
+    hipEvent_t ev[kEv];
     int nev = 0;
-    if (tk) {
-        for (int q = 0; q < 3; ++q) {
-            H->kt_ms[q] = 0;
-            H->kt_calls[q] = 0;
-        }
-        for (; nev < 4 * kBatch + 2; ++nev)
-            if (hipEventCreate(&ev[nev]) != hipSuccess) break;
-        if (nev < 4 * kBatch + 2) {
-            for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
-            release();
-            return L1LS_E_HIP;
-        }
+    int64_t newton = 0, pcg_total = 0;
+    double gnorm = INFINITY;
+    bool converged = false;
+    std::chrono::steady_clock::time_point t0;
+
+    ~l1ls_huge_newton() {
+        (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
+        W.release();
+        for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
     }
-    auto elapsed = [&](int a, int b) {
+    double elapsed(int a, int b) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
         return (double)ms;
-    };
-    auto run = [&]() -> l1ls_status {
+    }
+
+    l1ls_status init(const l1ls_huge* inst, const l1ls_solve_opts* o, double* xdev) {
+        H = inst;
+        x = xdev;
+        s = (hipStream_t)o->stream;
+        tau = o->tau > 0 ? o->tau : H->prm.tau;
+        mu = o->mu > 0 ? o->mu : 1e-5;
+        prtol = o->pcg_rtol > 0 ? o->pcg_rtol : 0.1;
+        maxbt = o->max_backtrack > 0 ? o->max_backtrack : 50;
+        pcgmax = o->pcg_maxit > 0 ? o->pcg_maxit : 1000;
+        primal = o->hessian == 1 ? 1 : 0;
+        gtol = (o->rel_gap_tol > 0 ? o->rel_gap_tol : 1e-9) * tau;
+        tk = o->time_kernels != 0;
+        if (!is_fin(tau) || !is_fin(mu)) return L1LS_E_ARG;
+        K = H->k;
+        K.tau = tau;
+        const int64_t n = K.n;
+        nb = blocks_for(n / 2);
+        for (double** v : {&gd, &dx, &r, &p, &d}) L1LS_TRY(W.alloc(v, (size_t)n));
+        L1LS_TRY(W.alloc(&part, (size_t)kHMaxBlocks * kLsStats));
+        L1LS_TRY(W.alloc(&cs, 1));
+        if (tk) {
+            for (int q = 0; q < 3; ++q) {
+                H->kt_ms[q] = 0;
+                H->kt_calls[q] = 0;
+            }
+            for (; nev < kEv; ++nev) HIP_TRY(hipEventCreate(&ev[nev]));
+        }
+        t0 = std::chrono::steady_clock::now();
         if (o->x0_dev) {
             if (o->x0_dev != x) HIP_TRY(hipMemcpyAsync(x, o->x0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         } else {
@@ -697,96 +700,155 @@ extern "C" l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* H, const l1ls_
         }
         hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, gd, n);
         HIP_TRY(hipGetLastError());
-        int64_t newton = 0, pcg_total = 0;
-        double gnorm = INFINITY;
+        return L1LS_OK;
+    }
+
+    // PCG on the Newton system from dx = 0 (kh_setup has formed its start)
+    l1ls_status pcg(HCg& c) {
+        const int64_t n = K.n;
+        if (c.done) hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, dx, n);  // no iteration writes dx
+        int first = 1;
+        while (!c.done) {
+            const int before = c.iters;
+            const int skip = first;  // the first iteration reads no p, dx: not timed
+            for (int q = 0; q < kBatch; ++q) {
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
+                hipLaunchKernelGGL((kh_cg_iter<kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K, (dv2*)dx, (dv2*)r,
+                                   (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
+                hipLaunchKernelGGL(kh_cg_next, dim3(1), dim3(1024), 0, s, part, nb, cs, pcgmax);
+                first = 0;
+            }
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (tk) {  // the passes that ran: one per iteration of this batch
+                const int ran = c.iters - before;
+                for (int q = skip; q < ran; ++q) H->kt_ms[0] += elapsed(2 * q, 2 * q + 1);
+                H->kt_calls[0] += std::max(ran - skip, 0);
+            }
+        }
+        pcg_total += c.iters;
+        return L1LS_OK;
+    }
+
+    // Armijo backtracking on f_mu(x + a dx), a = 2^-t, kLsBatch lengths per pass;
+    // a = 2^-maxbt when none of the maxbt lengths passes
+    l1ls_status line_search(double* a_out) {
         const double armijo = 1e-4;
-        for (newton = 0; newton < o->max_iter; ++newton) {
-            if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch], s));
+        double a = std::ldexp(1.0, -maxbt);
+        bool found = false;
+        for (int t0b = 0; t0b < maxbt && !found; t0b += kLsBatch) {
+            const double a0 = std::ldexp(1.0, -t0b);
+            if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
+            hipLaunchKernelGGL(kh_ls, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)dx,
+                               (const double2*)H->b, mu, a0, part);
+            if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
+            HIP_TRY(hipGetLastError());
+            double t[kLsStats];
+            L1LS_TRY(host_stats(part, kLsStats, kLsStats, nb, s, t));
+            if (tk) {
+                H->kt_ms[1] += elapsed(2 * kBatch, 2 * kBatch + 1);
+                H->kt_calls[1] += 1;
+            }
+            const double f0 = tau * t[0] + 0.5 * t[1];
+            const double slope = t[2];
+            for (int q = 0; q < kLsBatch && t0b + q < maxbt; ++q) {
+                const double at = std::ldexp(1.0, -(t0b + q));
+                const double ft = tau * t[3 + q] + 0.5 * t[3 + kLsBatch + q];
+                if (ft <= f0 + armijo * at * slope) {
+                    a = at;
+                    found = true;
+                    break;
+                }
+            }
+        }
+        *a_out = a;
+        return L1LS_OK;
+    }
+
+    // up to k Newton steps; stops at ||grad f_mu||_inf <= gtol
+    l1ls_status steps(int64_t k) {
+        for (int64_t q = 0; q < k && !converged; ++q) {
+            if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
             hipLaunchKernelGGL(kh_setup, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)gd,
                                (const double2*)H->b, mu, primal, (double2*)d, (double2*)r, part);
-            if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch + 1], s));
+            if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
             hipLaunchKernelGGL(kh_cg_init, dim3(1), dim3(1024), 0, s, part, nb, cs, prtol, pcgmax);
             HIP_TRY(hipGetLastError());
             HCg c;
             HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (tk) {
-                H->kt_ms[2] += elapsed(4 * kBatch, 4 * kBatch + 1);
+                H->kt_ms[2] += elapsed(2 * kBatch, 2 * kBatch + 1);
                 H->kt_calls[2] += 1;
             }
             gnorm = c.gmax;
             if (!is_fin(gnorm)) return L1LS_E_NONFINITE;
-            if (gnorm <= gtol) break;
-            // PCG from dx = 0; the first update writes dx without reading it
-            if (c.done) hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, dx, n);
-            int first = 1;
-            while (!c.done) {
-                const int before = c.iters;
-                for (int q = 0; q < kBatch; ++q) {
-                    if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
-                    hipLaunchKernelGGL((kh_cg_iter<kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K, (dv2*)dx, (dv2*)r,
-                                       (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
-                    if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
-                    hipLaunchKernelGGL(kh_cg_next, dim3(1), dim3(1024), 0, s, part, nb, cs, pcgmax);
-                    first = 0;
-                }
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(hipMemcpyAsync(&c, cs, sizeof(c), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                if (tk) {  // the passes that ran: one per iteration of this batch
-                    const int ran = c.iters - before;
-                    for (int q = 0; q < ran; ++q) H->kt_ms[0] += elapsed(2 * q, 2 * q + 1);
-                    H->kt_calls[0] += ran;
-                }
+            if (gnorm <= gtol) {
+                converged = true;
+                break;
             }
-            pcg_total += c.iters;
-            // Armijo backtracking on f_mu(x + a dx), a = 2^-t, kLsBatch lengths per pass
-            double a = std::ldexp(1.0, -maxbt);
-            bool found = false;
-            for (int t0b = 0; t0b < maxbt && !found; t0b += kLsBatch) {
-                const double a0 = std::ldexp(1.0, -t0b);
-                if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch], s));
-                hipLaunchKernelGGL(kh_ls, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)dx,
-                                   (const double2*)H->b, mu, a0, part);
-                if (tk) HIP_TRY(hipEventRecord(ev[4 * kBatch + 1], s));
-                HIP_TRY(hipGetLastError());
-                double t[kLsStats];
-                L1LS_TRY(host_stats(part, kLsStats, kLsStats, nb, s, t));
-                if (tk) {
-                    H->kt_ms[1] += elapsed(4 * kBatch, 4 * kBatch + 1);
-                    H->kt_calls[1] += 1;
-                }
-                const double f0 = tau * t[0] + 0.5 * t[1];
-                const double slope = t[2];
-                for (int q = 0; q < kLsBatch && t0b + q < maxbt; ++q) {
-                    const double at = std::ldexp(1.0, -(t0b + q));
-                    const double ft = tau * t[3 + q] + 0.5 * t[3 + kLsBatch + q];
-                    if (ft <= f0 + armijo * at * slope) {
-                        a = at;
-                        found = true;
-                        break;
-                    }
-                }
-            }
-            hipLaunchKernelGGL(kh_step, dim3(nb), dim3(kHB), 0, s, np, (double2*)x, (double2*)gd,
+            L1LS_TRY(pcg(c));
+            double a = 0;
+            L1LS_TRY(line_search(&a));
+            hipLaunchKernelGGL(kh_step, dim3(nb), dim3(kHB), 0, s, K.n / 2, (double2*)x, (double2*)gd,
                                (const double2*)dx, a, mu, primal);
             HIP_TRY(hipGetLastError());
+            ++newton;
         }
         HIP_TRY(hipStreamSynchronize(s));
+        return L1LS_OK;
+    }
+
+    l1ls_status report(l1ls_report* out) {
         l1ls_report rr;
         std::memset(&rr, 0, sizeof(rr));
         rr.iterations = newton;
         rr.inner = pcg_total;
         L1LS_TRY(huge_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap));
         L1LS_TRY(huge_err(H, x, s, &rr.rel_err));
-        rr.converged = (gnorm <= gtol) ? 1 : 0;
+        rr.converged = converged ? 1 : 0;
         rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (rep) *rep = rr;
-        return rr.converged ? L1LS_OK : L1LS_NOT_CONVERGED;
-    };
-    st = run();
-    release();
-    for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
+        if (out) *out = rr;
+        return L1LS_OK;
+    }
+};
+
+extern "C" l1ls_status l1ls_huge_newton_create(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
+                                               l1ls_huge_newton** out) {
+    if (!H || !o || !x || !out) return L1LS_E_ARG;
+    *out = nullptr;
+    if (!aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
+    if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
+    auto* N = new (std::nothrow) l1ls_huge_newton();
+    if (!N) return L1LS_E_NOMEM;
+    const l1ls_status st = N->init(H, o, x);
+    if (st != L1LS_OK) {
+        delete N;
+        return st;
+    }
+    *out = N;
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_huge_newton_step(l1ls_huge_newton* N, int64_t steps, l1ls_report* rep) {
+    if (!N || steps < 0) return L1LS_E_ARG;
+    L1LS_TRY(N->steps(steps));
+    L1LS_TRY(N->report(rep));
+    return N->converged ? L1LS_OK : L1LS_NOT_CONVERGED;
+}
+
+extern "C" void l1ls_huge_newton_destroy(l1ls_huge_newton* N) { delete N; }
+
+extern "C" l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
+                                                 l1ls_report* rep) {
+    if (!H || !o || !x) return L1LS_E_ARG;
+    if (o->max_iter < 0) return L1LS_E_ARG;
+    l1ls_huge_newton* N = nullptr;
+    L1LS_TRY(l1ls_huge_newton_create(H, o, x, &N));
+    const l1ls_status st = l1ls_huge_newton_step(N, o->max_iter, rep);
+    l1ls_huge_newton_destroy(N);
     return st;
 }
 

@@ -140,4 +140,8 @@ def test_huge_null_arguments():
     assert lib.l1ls_huge_objective_gap(None, 1.0, None, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d),
                                        None) == -1
     assert lib.l1ls_huge_solve_cg_newton(None, None, None, None) == -1
+    h2 = ctypes.c_void_p()
+    assert lib.l1ls_huge_newton_create(None, None, None, ctypes.byref(h2)) == -1 and not h2.value
+    assert lib.l1ls_huge_newton_step(None, 1, None) == -1
+    lib.l1ls_huge_newton_destroy(None)
     lib.l1ls_huge_free(None)

@@ -176,6 +176,21 @@ def test_cg_newton_edge_cases():
     H.free()
 
 
+def test_stepping_object_equals_one_solve():
+    # l1ls_huge_newton_*: 3 + 5 Newton steps give the bits of one 8-step solve
+    H, O = make(4098, 4, None, {})
+    x1, rep1, _ = H.solve_cg_newton(max_iter=8)
+    N = H.newton()
+    r3, st3 = N.step(3)
+    assert r3["iterations"] == 3 and st3 == L.L1LS_NOT_CONVERGED
+    r8, _ = N.step(5)
+    assert r8["iterations"] == 8 and r8["inner"] == rep1["inner"]
+    assert np.array_equal(host(N.x), host(x1))
+    assert r8["rel_err"] == rep1["rel_err"] and r8["primal"] == rep1["primal"]
+    N.destroy()
+    H.free()
+
+
 def test_s_zero_gives_zero_planted_solution():
     H, O = make(256, 0, None, {})
     xs = torch.full((256,), 1.0, dtype=torch.float64, device="cuda")
