@@ -547,7 +547,7 @@ def bench_large(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_huge(args):
+def bench_table1(args):
     """Section 8.9 (Table 1) instance: A = Sigma G^T, one stage of adjacent
     Givens rotations with theta = 2 pi / 3, sigma 0.1 / 100, s = n / 2^10,
     x* entries -1e4 and 0.1, tau = 1, at n = 2^30 (m = 2^31).  A step is one
@@ -558,17 +558,17 @@ def bench_huge(args):
     import paper_1503_03520_amd as L
 
     torch.cuda.set_device(0)
-    n = 1 << args.huge_log2n
+    n = 1 << args.table1_log2n
     seed = 1503035206
     stream = torch.cuda.current_stream()
     free, _ = torch.cuda.mem_get_info()
-    need = L.huge_bytes(n) + L.huge_solve_bytes(n) + 8 * n
+    need = L.sgt_bytes(n) + L.sgt_solve_bytes(n) + 8 * n
     if need > free:
-        print(json.dumps({"error": f"n = 2^{args.huge_log2n} needs {need / 2**30:.1f} GiB, {free / 2**30:.1f} free"}))
+        print(json.dumps({"error": f"n = 2^{args.table1_log2n} needs {need / 2**30:.1f} GiB, {free / 2**30:.1f} free"}))
         sys.exit(3)
-    prm = L.huge_params(n, seed)
+    prm = L.sgt_params(n, seed)
     t = time.perf_counter()
-    H = L.HugeInstance(prm, stream=stream)
+    H = L.SgtInstance(prm, stream=stream)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     print(json.dumps({"progress": "generated", "seconds": gen_s}), file=sys.stderr, flush=True)
@@ -616,7 +616,7 @@ def bench_huge(args):
         "ms_per_step": sec * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
-        "vs_baseline": {30: sec / 1923.0, 32: sec / 1968.0}.get(args.huge_log2n),
+        "vs_baseline": {30: sec / 1923.0, 32: sec / 1968.0}.get(args.table1_log2n),
         "dtype": "f64",
         "data": "synthetic (section 8.9 instance generated on the device, seed %d)" % seed,
         "config": {"workload": "section 8.9 instance: A = Sigma G^T (m = 2n), adjacent Givens pairs at theta = "
@@ -643,19 +643,19 @@ def bench_huge(args):
         },
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_huge(n, args.newton_steps)
+        line["cpu_baseline"] = cpu_baseline_table1(n, args.newton_steps)
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline_huge(n, newton_steps, log2_sample=18):
+def cpu_baseline_table1(n, newton_steps, log2_sample=18):
     """The oracle's CG-Newton (numpy, FP64) on the same class at n = 2^18,
     scaled linearly to n (section 8.9 reports the same Newton and PCG counts
     at every size, and every pass is linear in n)."""
     from oracle import newton as ON
-    from oracle.huge import HugeInstance
+    from oracle.sgt import SgtInstance
 
     ns = 1 << log2_sample
-    I = HugeInstance(ns, ns // 1024, 1503035206)
+    I = SgtInstance(ns, ns // 1024, 1503035206)
     cn = I.colnorm2()
     t = time.perf_counter()
     _, st = ON.newton_cg(I.matvec, I.rmatvec, cn, I.b, I.tau, max_newton=newton_steps)
@@ -686,13 +686,13 @@ def main():
     ap.add_argument("--stats-command", default="")
     ap.add_argument("--stats-top", type=int, default=14)
     ap.add_argument("--out", default=PROFILE_SUMMARY)
-    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large", "huge"],
+    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large", "table1"],
                     help="fista: the single large instance (default); serve: the request stream; "
                          "batched: 256 uneven instances; path: 64 taus on one instance; "
                          "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton; "
-                         "huge: the section 8.9 (Table 1) instance at n = 2^30, CG-Newton")
+                         "table1: the section 8.9 (Table 1) instance at n = 2^30, CG-Newton")
     ap.add_argument("--large-log2n", type=int, default=26)
-    ap.add_argument("--huge-log2n", type=int, default=30)
+    ap.add_argument("--table1-log2n", type=int, default=30)
     ap.add_argument("--newton-steps", type=int, default=8)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
@@ -741,10 +741,10 @@ def main():
             args.check_every = 16
         if args.workload == "large" and "--steps" not in sys.argv:
             args.steps, args.warmup = 50, 5
-        if args.workload == "huge" and "--steps" not in sys.argv:
+        if args.workload == "table1" and "--steps" not in sys.argv:
             args.steps, args.warmup = 1, 1
         {"serve": bench_serve, "batched": bench_batched, "path": bench_path,
-         "large": bench_large, "huge": bench_huge}[args.workload](args)
+         "large": bench_large, "table1": bench_table1}[args.workload](args)
         return
 
     import torch

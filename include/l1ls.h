@@ -381,7 +381,7 @@ l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus,
  * Device vectors passed to these calls must be 16-byte aligned
  * (L1LS_E_ARG otherwise).  Calls on the same instance must not overlap.
  * ------------------------------------------------------------------------- */
-typedef struct l1ls_huge l1ls_huge;
+typedef struct l1ls_sgt l1ls_sgt;
 
 typedef struct {
     int64_t n;          /* variables: even, 2 <= n <= 2^32                      */
@@ -394,42 +394,42 @@ typedef struct {
     double x_pos;       /* other support values (section 8.9: 0.1)              */
     double tau;         /* > 0 (section 8.3: 1)                                 */
     uint64_t seed;
-} l1ls_huge_params;
+} l1ls_sgt_params;
 
 typedef struct {
-    l1ls_huge_params params;
+    l1ls_sgt_params params;
     double L;            /* lambda_max(A^T A) = max(sigma_odd, sigma_even)^2      */
     double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2               */
     double c, s_rot;     /* cos theta, sin theta as used by the kernels          */
     const double* b_dev; /* n: the top n entries of b (the others are zero)       */
-} l1ls_huge_desc;
+} l1ls_sgt_desc;
 
 /* params = the section 8.9 values for n: m = 2n, s = floor(n / 1024),
  * theta = 2 pi / 3, sigma 0.1 / 100, x* values -1e4 / 0.1, tau = 1. */
-void l1ls_huge_params_default(int64_t n, uint64_t seed, l1ls_huge_params* params);
+void l1ls_sgt_params_default(int64_t n, uint64_t seed, l1ls_sgt_params* params);
 /* Device bytes of an instance, and the extra device bytes of a CG-Newton
  * solve on it (besides the caller's x): 8 n + O(1) and 40 n + O(1). */
-size_t l1ls_huge_bytes(int64_t n);
-size_t l1ls_huge_solve_bytes(int64_t n);
+size_t l1ls_sgt_bytes(int64_t n);
+size_t l1ls_sgt_solve_bytes(int64_t n);
 
 /* Build an instance on the current device (b and f_star); returns after
  * the build finished.  L1LS_E_ARG for parameters outside the ranges above. */
-l1ls_status l1ls_huge_generate(const l1ls_huge_params* params, void* stream, l1ls_huge** out);
-l1ls_status l1ls_huge_describe(const l1ls_huge* inst, l1ls_huge_desc* out);
-void l1ls_huge_free(l1ls_huge* inst);
+l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* params, void* stream, l1ls_sgt** out);
+l1ls_status l1ls_sgt_describe(const l1ls_sgt* inst, l1ls_sgt_desc* out);
+void l1ls_sgt_free(l1ls_sgt* inst);
 
 /* x_star_dev, g_dev (n each, either may be NULL, not both): the planted x*
  * and the subgradient g of IGen step 2.  Asynchronous on `stream`. */
-l1ls_status l1ls_huge_planted(const l1ls_huge* inst, double* x_star_dev, double* g_dev, void* stream);
+l1ls_status l1ls_sgt_planted(const l1ls_sgt* inst, double* x_star_dev, double* g_dev, void* stream);
 
 /* trans = 0: out_dev (m) = A in_dev (n); trans = 1: out_dev (n) =
  * A^T in_dev (m; entries n..m-1 are not read).  FP64, asynchronous. */
-l1ls_status l1ls_huge_apply(const l1ls_huge* inst, int32_t trans, const double* in_dev,
+l1ls_status l1ls_sgt_apply(const l1ls_sgt* inst, int32_t trans, const double* in_dev,
                             double* out_dev, void* stream);
 
 /* FP64 P = f_tau(x), the dual value at the scaled residual and the relative
  * gap, as l1ls_objective_gap.  Blocks until done. */
-l1ls_status l1ls_huge_objective_gap(const l1ls_huge* inst, double tau, const double* x_dev,
+l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* inst, double tau, const double* x_dev,
                                     double* primal, double* dual, double* rel_gap, void* stream);
 
 /*
@@ -442,30 +442,30 @@ l1ls_status l1ls_huge_objective_gap(const l1ls_huge* inst, double tau, const dou
  * opts.polish 0, else L1LS_E_UNSUPPORTED).  x_dev (n) holds the iterate
  * throughout and the result at the end; opts.x0_dev (may equal x_dev) is the
  * start, NULL for 0.  report: Newton steps, PCG iterations, FP64 gap,
- * ||x - x*|| / ||x*||.  Allocates l1ls_huge_solve_bytes(n) for the call.
+ * ||x - x*|| / ||x*||.  Allocates l1ls_sgt_solve_bytes(n) for the call.
  */
-l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* inst, const l1ls_solve_opts* opts,
+l1ls_status l1ls_sgt_solve_cg_newton(const l1ls_sgt* inst, const l1ls_solve_opts* opts,
                                       double* x_dev, l1ls_report* report);
 
 /* The same CG-Newton one call at a time, for callers that report between
- * Newton steps.  create: validates opts as l1ls_huge_solve_cg_newton (max_iter
- * is not used), allocates l1ls_huge_solve_bytes(n), sets x_dev to the start;
+ * Newton steps.  create: validates opts as l1ls_sgt_solve_cg_newton (max_iter
+ * is not used), allocates l1ls_sgt_solve_bytes(n), sets x_dev to the start;
  * x_dev must stay valid until destroy.  step: up to `steps` more Newton steps
  * (none once converged); report: totals since create, FP64 gap and
  * ||x - x*|| / ||x*|| at the current x_dev; returns L1LS_OK once converged,
  * else L1LS_NOT_CONVERGED.  destroy waits for the object's stream. */
-typedef struct l1ls_huge_newton l1ls_huge_newton;
-l1ls_status l1ls_huge_newton_create(const l1ls_huge* inst, const l1ls_solve_opts* opts, double* x_dev,
-                                    l1ls_huge_newton** out);
-l1ls_status l1ls_huge_newton_step(l1ls_huge_newton* newton, int64_t steps, l1ls_report* report);
-void l1ls_huge_newton_destroy(l1ls_huge_newton* newton);
+typedef struct l1ls_sgt_newton l1ls_sgt_newton;
+l1ls_status l1ls_sgt_newton_create(const l1ls_sgt* inst, const l1ls_solve_opts* opts, double* x_dev,
+                                    l1ls_sgt_newton** out);
+l1ls_status l1ls_sgt_newton_step(l1ls_sgt_newton* newton, int64_t steps, l1ls_report* report);
+void l1ls_sgt_newton_destroy(l1ls_sgt_newton* newton);
 
 /* HIP-event times of the passes of the last CG-Newton on inst (solve or
  * stepping object) created with opts.time_kernels = 1: ms[q] total milliseconds and
  * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r; the first
  * iteration of each PCG, which reads neither p nor dx, is left out), 1 the
  * line-search pass, 2 the Newton setup pass (gradient, d, PCG start). */
-l1ls_status l1ls_huge_kernel_times(const l1ls_huge* inst, double* ms, int64_t* calls);
+l1ls_status l1ls_sgt_kernel_times(const l1ls_sgt* inst, double* ms, int64_t* calls);
 
 const char* l1ls_status_string(int32_t status);
 /* ABI version of this header (incremented on incompatible changes). */

@@ -20,6 +20,8 @@ squares problems", arXiv:1503.03520, that it follows):
                    gap, power iteration for L.
 * ``bruteforce``-- sign-pattern enumeration of the reduced problem (13) for
                    n <= 12.
+* ``sgt``       -- the A = Sigma G^T class of sections 8.4 to 8.9: sigma and
+                   x* laws (Procedures OsGen, OsGen3), kappa_rho (eq. (17)).
 * ``newton``    -- smoothed Newton-CG on the pseudo-Huber problem (8)
                    (section 2, section 8.1 item pdNCG, section 8.3 params).
 * ``polish``    -- FP64 support/sign polish on the reduced problem (13).

@@ -83,7 +83,7 @@ class Request(ctypes.Structure):
     ]
 
 
-class HugeParams(ctypes.Structure):
+class SgtParams(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("s", ctypes.c_int64), ("theta", ctypes.c_double),
         ("sigma_odd", ctypes.c_double), ("sigma_even", ctypes.c_double), ("x_neg", ctypes.c_double),
@@ -91,9 +91,9 @@ class HugeParams(ctypes.Structure):
     ]
 
 
-class HugeDesc(ctypes.Structure):
+class SgtDesc(ctypes.Structure):
     _fields_ = [
-        ("params", HugeParams), ("L", ctypes.c_double), ("f_star", ctypes.c_double), ("c", ctypes.c_double),
+        ("params", SgtParams), ("L", ctypes.c_double), ("f_star", ctypes.c_double), ("c", ctypes.c_double),
         ("s_rot", ctypes.c_double), ("b_dev", ctypes.c_void_p),
     ]
 
@@ -147,22 +147,22 @@ _SIGS = {
                                                 ctypes.POINTER(Report)]),
     "l1ls_solve_fista_path": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                              ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
-    "l1ls_huge_params_default": (None, [ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(HugeParams)]),
-    "l1ls_huge_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
-    "l1ls_huge_solve_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
-    "l1ls_huge_generate": (ctypes.c_int, [ctypes.POINTER(HugeParams), _P, ctypes.POINTER(_P)]),
-    "l1ls_huge_describe": (ctypes.c_int, [_P, ctypes.POINTER(HugeDesc)]),
-    "l1ls_huge_free": (None, [_P]),
-    "l1ls_huge_planted": (ctypes.c_int, [_P, _P, _P, _P]),
-    "l1ls_huge_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
-    "l1ls_huge_objective_gap": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
+    "l1ls_sgt_params_default": (None, [ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(SgtParams)]),
+    "l1ls_sgt_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "l1ls_sgt_solve_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "l1ls_sgt_generate": (ctypes.c_int, [ctypes.POINTER(SgtParams), _P, ctypes.POINTER(_P)]),
+    "l1ls_sgt_describe": (ctypes.c_int, [_P, ctypes.POINTER(SgtDesc)]),
+    "l1ls_sgt_free": (None, [_P]),
+    "l1ls_sgt_planted": (ctypes.c_int, [_P, _P, _P, _P]),
+    "l1ls_sgt_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "l1ls_sgt_objective_gap": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                                _P]),
-    "l1ls_huge_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
-    "l1ls_huge_newton_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
-    "l1ls_huge_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
-    "l1ls_huge_newton_destroy": (None, [_P]),
-    "l1ls_huge_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "l1ls_sgt_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_sgt_newton_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
+    "l1ls_sgt_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
+    "l1ls_sgt_newton_destroy": (None, [_P]),
+    "l1ls_sgt_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "l1ls_version": (ctypes.c_int32, []),
 }
@@ -533,45 +533,45 @@ def l1ls_solve_fista_path(inst, taus, **kw):
     return X, [r.as_dict() for r in reps], st
 
 
-# ---- huge-scale instance class (section 8.9, Table 1) -------------------------
-def huge_params(n, seed, **kw):
-    """The section 8.9 parameters for n (l1ls_huge_params_default), with overrides."""
-    p = HugeParams()
-    lib().l1ls_huge_params_default(n, seed, ctypes.byref(p))
+# ---- A = Sigma G^T instance class (sections 8.4 to 8.9) ----------------------
+def sgt_params(n, seed, **kw):
+    """The section 8.9 parameters for n (l1ls_sgt_params_default), with overrides."""
+    p = SgtParams()
+    lib().l1ls_sgt_params_default(n, seed, ctypes.byref(p))
     for k, v in kw.items():
         setattr(p, k, v)
     return p
 
 
-class HugeInstance:
-    """Owns an l1ls_huge (l1ls_huge_generate)."""
+class SgtInstance:
+    """Owns an l1ls_sgt (l1ls_sgt_generate)."""
 
     def __init__(self, params, stream=None):
         h = ctypes.c_void_p()
-        _check(lib().l1ls_huge_generate(ctypes.byref(params), _stream(stream), ctypes.byref(h)),
-               "l1ls_huge_generate")
+        _check(lib().l1ls_sgt_generate(ctypes.byref(params), _stream(stream), ctypes.byref(h)),
+               "l1ls_sgt_generate")
         self._h = h
-        self.params = {f: getattr(params, f) for f, _ in HugeParams._fields_}
+        self.params = {f: getattr(params, f) for f, _ in SgtParams._fields_}
 
     @property
     def handle(self):
         return self._h
 
     def describe(self):
-        d = HugeDesc()
-        _check(lib().l1ls_huge_describe(self._h, ctypes.byref(d)), "l1ls_huge_describe")
+        d = SgtDesc()
+        _check(lib().l1ls_sgt_describe(self._h, ctypes.byref(d)), "l1ls_sgt_describe")
         return d
 
     def planted(self, x_star=None, g=None, stream=None):
-        _check(lib().l1ls_huge_planted(self._h, _ptr(x_star), _ptr(g), _stream(stream)), "l1ls_huge_planted")
+        _check(lib().l1ls_sgt_planted(self._h, _ptr(x_star), _ptr(g), _stream(stream)), "l1ls_sgt_planted")
 
     def apply(self, trans, x_in, x_out, stream=None):
-        _check(lib().l1ls_huge_apply(self._h, trans, _ptr(x_in), _ptr(x_out), _stream(stream)), "l1ls_huge_apply")
+        _check(lib().l1ls_sgt_apply(self._h, trans, _ptr(x_in), _ptr(x_out), _stream(stream)), "l1ls_sgt_apply")
 
     def objective_gap(self, tau, x, stream=None):
         P, D, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _check(lib().l1ls_huge_objective_gap(self._h, tau, _ptr(x), ctypes.byref(P), ctypes.byref(D),
-                                             ctypes.byref(g), _stream(stream)), "l1ls_huge_objective_gap")
+        _check(lib().l1ls_sgt_objective_gap(self._h, tau, _ptr(x), ctypes.byref(P), ctypes.byref(D),
+                                             ctypes.byref(g), _stream(stream)), "l1ls_sgt_objective_gap")
         return P.value, D.value, g.value
 
     def solve_cg_newton(self, x_out=None, **kw):
@@ -580,24 +580,24 @@ class HugeInstance:
             x_out = torch.empty(self.params["n"], dtype=torch.float64, device="cuda")
         o = solve_opts(**kw)
         rep = Report()
-        st = _check(lib().l1ls_huge_solve_cg_newton(self._h, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)),
-                    "l1ls_huge_solve_cg_newton", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+        st = _check(lib().l1ls_sgt_solve_cg_newton(self._h, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)),
+                    "l1ls_sgt_solve_cg_newton", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
         return x_out, rep.as_dict(), st
 
     def newton(self, x_out=None, **kw):
-        """A HugeNewton stepping object (l1ls_huge_newton_create)."""
-        return HugeNewton(self, x_out, **kw)
+        """A SgtNewton stepping object (l1ls_sgt_newton_create)."""
+        return SgtNewton(self, x_out, **kw)
 
     def kernel_times(self):
         """{pass: (total ms, launches)} of the last solve with time_kernels=1."""
         ms = (ctypes.c_double * 3)()
         calls = (ctypes.c_int64 * 3)()
-        _check(lib().l1ls_huge_kernel_times(self._h, ms, calls), "l1ls_huge_kernel_times")
+        _check(lib().l1ls_sgt_kernel_times(self._h, ms, calls), "l1ls_sgt_kernel_times")
         return {k: (ms[q], calls[q]) for q, k in enumerate(("pcg_iteration", "line_search", "newton_setup"))}
 
     def free(self):
         if self._h:
-            lib().l1ls_huge_free(self._h)
+            lib().l1ls_sgt_free(self._h)
             self._h = None
 
     def __del__(self):
@@ -607,16 +607,16 @@ class HugeInstance:
             pass
 
 
-def huge_bytes(n):
-    return lib().l1ls_huge_bytes(n)
+def sgt_bytes(n):
+    return lib().l1ls_sgt_bytes(n)
 
 
-def huge_solve_bytes(n):
-    return lib().l1ls_huge_solve_bytes(n)
+def sgt_solve_bytes(n):
+    return lib().l1ls_sgt_solve_bytes(n)
 
 
-class HugeNewton:
-    """CG-Newton on a HugeInstance one call at a time (l1ls_huge_newton_*)."""
+class SgtNewton:
+    """CG-Newton on a SgtInstance one call at a time (l1ls_sgt_newton_*)."""
 
     def __init__(self, inst, x_out=None, **kw):
         import torch
@@ -624,19 +624,19 @@ class HugeNewton:
         self.x = x_out if x_out is not None else torch.empty(inst.params["n"], dtype=torch.float64, device="cuda")
         self._o = solve_opts(**kw)
         h = ctypes.c_void_p()
-        _check(lib().l1ls_huge_newton_create(inst.handle, ctypes.byref(self._o), _ptr(self.x), ctypes.byref(h)),
-               "l1ls_huge_newton_create")
+        _check(lib().l1ls_sgt_newton_create(inst.handle, ctypes.byref(self._o), _ptr(self.x), ctypes.byref(h)),
+               "l1ls_sgt_newton_create")
         self._h = h
 
     def step(self, steps=1):
         rep = Report()
-        st = _check(lib().l1ls_huge_newton_step(self._h, steps, ctypes.byref(rep)), "l1ls_huge_newton_step",
+        st = _check(lib().l1ls_sgt_newton_step(self._h, steps, ctypes.byref(rep)), "l1ls_sgt_newton_step",
                     allow=(L1LS_OK, L1LS_NOT_CONVERGED))
         return rep.as_dict(), st
 
     def destroy(self):
         if self._h:
-            lib().l1ls_huge_newton_destroy(self._h)
+            lib().l1ls_sgt_newton_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -48,10 +48,10 @@ constexpr int kHU = 2;              // pairs per thread per trip of the PCG pass
 constexpr bool kHNT = true;         // nontemporal loads and stores in the PCG pass
 constexpr int kLsBatch = 8;        // step lengths tried per line-search pass
 constexpr int kLsStats = 3 + 2 * kLsBatch;
-constexpr int64_t kHugeMaxN = (int64_t)1 << 32;  // Philox counter word 0 holds the index
+constexpr int64_t kSgtMaxN = (int64_t)1 << 32;  // Philox counter word 0 holds the index
 
 // Constants of one instance, passed by value to every kernel.
-struct HugeK {
+struct SgtK {
     int64_t n, s;
     double c, sn;        // cos, sin of the shared angle
     double so, se;       // sigma at the first / second element of a pair
@@ -69,20 +69,20 @@ struct HCg {
 typedef double dv2 __attribute__((ext_vector_type(2)));
 
 // (y_i, y_j) = block of A x: sigma (G^T x) on the pair
-__device__ __forceinline__ void a_pair(const HugeK& H, double xi, double xj, double& yi, double& yj) {
+__device__ __forceinline__ void a_pair(const SgtK& H, double xi, double xj, double& yi, double& yj) {
     yi = H.so * (H.c * xi + H.sn * xj);
     yj = H.se * (-H.sn * xi + H.c * xj);
 }
 
 // (x_i, x_j) = block of A^T y: G (sigma y) on the pair
-__device__ __forceinline__ void at_pair(const HugeK& H, double yi, double yj, double& xi, double& xj) {
+__device__ __forceinline__ void at_pair(const SgtK& H, double yi, double yj, double& xi, double& xj) {
     const double ti = H.so * yi, tj = H.se * yj;
     xi = H.c * ti - H.sn * tj;
     xj = H.sn * ti + H.c * tj;
 }
 
 // H p = A^T (A p) + d p on the pair
-__device__ __forceinline__ double2 hess_pair(const HugeK& H, double2 p, double2 d) {
+__device__ __forceinline__ double2 hess_pair(const SgtK& H, double2 p, double2 d) {
     double yi, yj, hi, hj;
     a_pair(H, p.x, p.y, yi, yj);
     at_pair(H, yi, yj, hi, hj);
@@ -92,7 +92,7 @@ __device__ __forceinline__ double2 hess_pair(const HugeK& H, double2 p, double2 
 // x*_i and the subgradient g_i of IGen step 2: i is in supp(x*) when its
 // position q under the inverse support bijection is < s (the support is the
 // first s outputs of that bijection); off the support g_i = 0.9 (2u - 1).
-__device__ __forceinline__ void planted_at(const HugeK& H, int64_t i, double& xs, double& g) {
+__device__ __forceinline__ void planted_at(const SgtK& H, int64_t i, double& xs, double& g) {
     const int64_t q = H.s > 0 ? bijection_inverse(i, H.n, kTagPerm | 2u, H.key) : H.n;
     if (q < H.s) {
         xs = (q < H.s / 2) ? H.xneg : H.xpos;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void store_partials(double (&v)[NS], double* __restri
 // IGen steps 3 and 4 on one pair: e = tau Sigma^{-1} G^T g and b = A x* + e,
 // each operation rounded on its own (no fused multiply-add), in the order
 // the definition writes them.
-__device__ __forceinline__ void igen_pair(const HugeK& H, double xi, double xj, double gi, double gj, double& bi,
+__device__ __forceinline__ void igen_pair(const SgtK& H, double xi, double xj, double gi, double gj, double& bi,
                                           double& bj, double& ei, double& ej) {
 #pragma clang fp contract(off)
     ei = H.tau * (H.c * gi + H.sn * gj) / H.so;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void igen_pair(const HugeK& H, double xi, double xj, 
 }
 
 // b for every pair; part = sum e^2
-__global__ __launch_bounds__(kHB) void kh_generate(HugeK H, double2* __restrict__ b, double* __restrict__ part) {
+__global__ __launch_bounds__(kHB) void kh_generate(SgtK H, double2* __restrict__ b, double* __restrict__ part) {
     double v[1] = {0.0};
     const int64_t np = H.n / 2;
     for (int64_t k = gtid(); k < np; k += gstride()) {
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kHB) void kh_generate(HugeK H, double2* __restrict_
     store_partials<1, 1>(v, part);
 }
 
-__global__ __launch_bounds__(kHB) void kh_planted(HugeK H, double* __restrict__ xs, double* __restrict__ g) {
+__global__ __launch_bounds__(kHB) void kh_planted(SgtK H, double* __restrict__ xs, double* __restrict__ g) {
     for (int64_t i = gtid(); i < H.n; i += gstride()) {
         double a, b;
         planted_at(H, i, a, b);
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kHB) void kh_planted(HugeK H, double* __restrict__ 
 }
 
 // part = (sum (x - x*)^2, sum x*^2)
-__global__ __launch_bounds__(kHB) void kh_err(HugeK H, const double* __restrict__ x, double* __restrict__ part) {
+__global__ __launch_bounds__(kHB) void kh_err(SgtK H, const double* __restrict__ x, double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
     for (int64_t i = gtid(); i < H.n; i += gstride()) {
         double a, b;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kHB) void kh_err(HugeK H, const double* __restrict_
 }
 
 // trans = 0: out (m) = A in (n), rows n..m-1 zero; trans = 1: out (n) = A^T in (top n of m)
-__global__ __launch_bounds__(kHB) void kh_apply(HugeK H, int64_t m, int trans, const double2* __restrict__ in,
+__global__ __launch_bounds__(kHB) void kh_apply(SgtK H, int64_t m, int trans, const double2* __restrict__ in,
                                                 double2* __restrict__ out) {
     const int64_t np = H.n / 2;
     const int64_t total = trans ? np : m / 2;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kHB) void kh_apply(HugeK H, int64_t m, int trans, c
 }
 
 // part = (sum |x|, sum r^2, sum b r | max |A^T r|), r = A x - b
-__global__ __launch_bounds__(kHB) void kh_gap(HugeK H, const double2* __restrict__ x, const double2* __restrict__ b,
+__global__ __launch_bounds__(kHB) void kh_gap(SgtK H, const double2* __restrict__ x, const double2* __restrict__ b,
                                               double* __restrict__ part) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t np = H.n / 2;
@@ -207,14 +207,14 @@ __global__ __launch_bounds__(kHB) void kh_gap(HugeK H, const double2* __restrict
 
 // ---- CG-Newton ---------------------------------------------------------------
 // M = (diag(A^T A) + d)^{-1}, the Jacobi preconditioner, on the pair
-__device__ __forceinline__ dv2 precond(const HugeK& H, dv2 d) {
+__device__ __forceinline__ dv2 precond(const SgtK& H, dv2 d) {
     dv2 m;
     m.x = 1.0 / (H.cn0 + d.x);
     m.y = 1.0 / (H.cn1 + d.y);
     return m;
 }
 
-__device__ __forceinline__ dv2 hess_v(const HugeK& H, dv2 p, dv2 d) {
+__device__ __forceinline__ dv2 hess_v(const SgtK& H, dv2 p, dv2 d) {
     const double2 h = hess_pair(H, make_double2(p.x, p.y), make_double2(d.x, d.y));
     dv2 o;
     o.x = h.x;
@@ -226,7 +226,7 @@ __device__ __forceinline__ dv2 hess_v(const HugeK& H, dv2 p, dv2 d) {
 // Hessian diagonal d (primal: tau mu^2 / w^3; primal-dual: tau (1 - x gd / w) / w),
 // and PCG's start from dx = 0: r = -grad, u = M r.
 // part = (r.u, u.Hu, r.r | max |grad|).
-__global__ __launch_bounds__(kHB) void kh_setup(HugeK H, const double2* __restrict__ x,
+__global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const double2* __restrict__ x,
                                                 const double2* __restrict__ gd, const double2* __restrict__ b,
                                                 double mu, int primal, double2* __restrict__ d,
                                                 double2* __restrict__ r, double* __restrict__ part) {
@@ -308,7 +308,7 @@ __device__ __forceinline__ void st2(dv2 v, dv2* p) {
 // first: p and dx are not read (beta = 0, dx = 0).  U pairs per thread per
 // trip (loads issued together), NT: nontemporal accesses.
 template <int U, bool NT>
-__global__ __launch_bounds__(kHB) void kh_cg_iter(HugeK H, dv2* __restrict__ dx, dv2* __restrict__ r,
+__global__ __launch_bounds__(kHB) void kh_cg_iter(SgtK H, dv2* __restrict__ dx, dv2* __restrict__ r,
                                                   dv2* __restrict__ p, const dv2* __restrict__ d, int first,
                                                   const HCg* __restrict__ cs, double* __restrict__ part) {
     if (cs->done) return;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(1024) void kh_cg_next(const double* __restrict__ pa
 // Line search terms at x along dx, for the step lengths a0 2^-t, t < kLsBatch:
 // part = (sum psi(x), sum r(x)^2, grad . dx, sum psi(x + a_t dx) [t], sum r(x + a_t dx)^2 [t])
 // with psi(v) = sqrt(mu^2 + v^2) - mu and r(v) = A v - b.
-__global__ __launch_bounds__(kHB) void kh_ls(HugeK H, const double2* __restrict__ x, const double2* __restrict__ dx,
+__global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const double2* __restrict__ x, const double2* __restrict__ dx,
                                              const double2* __restrict__ b, double mu, double a0,
                                              double* __restrict__ part) {
     double v[kLsStats];
@@ -450,9 +450,9 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 }  // namespace
 
-struct l1ls_huge {
-    l1ls_huge_params prm;
-    HugeK k;
+struct l1ls_sgt {
+    l1ls_sgt_params prm;
+    SgtK k;
     double L = 0, fstar = 0;
     int device = 0;
     double* b = nullptr;  // n: the top n entries of b (rows n..m-1 of b are zero)
@@ -462,7 +462,7 @@ struct l1ls_huge {
     // [0] PCG iteration pass, [1] line-search pass, [2] Newton setup pass
     mutable double kt_ms[3] = {0, 0, 0};
     mutable int64_t kt_calls[3] = {0, 0, 0};
-    ~l1ls_huge() { arena.release(); }
+    ~l1ls_sgt() { arena.release(); }
 };
 
 namespace {
@@ -482,10 +482,10 @@ l1ls_status host_stats(const double* part, int ns, int nsum, int nb, hipStream_t
     return L1LS_OK;
 }
 
-l1ls_status huge_gap(const l1ls_huge* H, double tau, const double* x, hipStream_t s, double* P, double* D,
+l1ls_status sgt_gap(const l1ls_sgt* H, double tau, const double* x, hipStream_t s, double* P, double* D,
                      double* gap) {
     const int nb = blocks_for(H->k.n / 2);
-    HugeK K = H->k;
+    SgtK K = H->k;
     hipLaunchKernelGGL(kh_gap, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)H->b, H->part);
     HIP_TRY(hipGetLastError());
     double t[4];
@@ -498,7 +498,7 @@ l1ls_status huge_gap(const l1ls_huge* H, double tau, const double* x, hipStream_
     return L1LS_OK;
 }
 
-l1ls_status huge_err(const l1ls_huge* H, const double* x, hipStream_t s, double* out) {
+l1ls_status sgt_err(const l1ls_sgt* H, const double* x, hipStream_t s, double* out) {
     const int nb = blocks_for(H->k.n / 2);
     hipLaunchKernelGGL(kh_err, dim3(nb), dim3(kHB), 0, s, H->k, x, H->part);
     HIP_TRY(hipGetLastError());
@@ -510,7 +510,7 @@ l1ls_status huge_err(const l1ls_huge* H, const double* x, hipStream_t s, double*
 
 }  // namespace
 
-extern "C" void l1ls_huge_params_default(int64_t n, uint64_t seed, l1ls_huge_params* p) {
+extern "C" void l1ls_sgt_params_default(int64_t n, uint64_t seed, l1ls_sgt_params* p) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));
     p->n = n;
@@ -525,29 +525,29 @@ extern "C" void l1ls_huge_params_default(int64_t n, uint64_t seed, l1ls_huge_par
     p->seed = seed;
 }
 
-extern "C" size_t l1ls_huge_bytes(int64_t n) {
+extern "C" size_t l1ls_sgt_bytes(int64_t n) {
     if (n < 2) return 0;
     return (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 4096;
 }
 
-extern "C" size_t l1ls_huge_solve_bytes(int64_t n) {
+extern "C" size_t l1ls_sgt_solve_bytes(int64_t n) {
     if (n < 2) return 0;
     return 5 * (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 4096;
 }
 
-extern "C" l1ls_status l1ls_huge_generate(const l1ls_huge_params* p, void* stream, l1ls_huge** out) {
+extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream, l1ls_sgt** out) {
     if (!p || !out) return L1LS_E_ARG;
     *out = nullptr;
     const int64_t n = p->n, m = p->m;
-    if (n < 2 || n % 2 || n > kHugeMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return L1LS_E_ARG;
+    if (n < 2 || n % 2 || n > kSgtMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return L1LS_E_ARG;
     if (!(p->sigma_odd > 0) || !(p->sigma_even > 0) || !(p->tau > 0) || !is_fin(p->sigma_odd) ||
         !is_fin(p->sigma_even) || !is_fin(p->tau) || !is_fin(p->theta) || !is_fin(p->x_neg) || !is_fin(p->x_pos))
         return L1LS_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    auto* H = new (std::nothrow) l1ls_huge();
+    auto* H = new (std::nothrow) l1ls_sgt();
     if (!H) return L1LS_E_NOMEM;
     H->prm = *p;
-    HugeK& K = H->k;
+    SgtK& K = H->k;
     K.n = n;
     K.s = p->s;
     K.c = std::cos(p->theta);
@@ -583,7 +583,7 @@ extern "C" l1ls_status l1ls_huge_generate(const l1ls_huge_params* p, void* strea
     return L1LS_OK;
 }
 
-extern "C" l1ls_status l1ls_huge_describe(const l1ls_huge* H, l1ls_huge_desc* out) {
+extern "C" l1ls_status l1ls_sgt_describe(const l1ls_sgt* H, l1ls_sgt_desc* out) {
     if (!H || !out) return L1LS_E_ARG;
     std::memset(out, 0, sizeof(*out));
     out->params = H->prm;
@@ -595,7 +595,7 @@ extern "C" l1ls_status l1ls_huge_describe(const l1ls_huge* H, l1ls_huge_desc* ou
     return L1LS_OK;
 }
 
-extern "C" void l1ls_huge_free(l1ls_huge* H) {
+extern "C" void l1ls_sgt_free(l1ls_sgt* H) {
     if (!H) return;
     int cur = 0;
     const bool sw = hipGetDevice(&cur) == hipSuccess && cur != H->device;
@@ -605,7 +605,7 @@ extern "C" void l1ls_huge_free(l1ls_huge* H) {
     if (sw) (void)hipSetDevice(cur);
 }
 
-extern "C" l1ls_status l1ls_huge_planted(const l1ls_huge* H, double* x_star_dev, double* g_dev, void* stream) {
+extern "C" l1ls_status l1ls_sgt_planted(const l1ls_sgt* H, double* x_star_dev, double* g_dev, void* stream) {
     if (!H || (!x_star_dev && !g_dev)) return L1LS_E_ARG;
     hipLaunchKernelGGL(kh_planted, dim3(blocks_for(H->k.n / 2)), dim3(kHB), 0, (hipStream_t)stream, H->k,
                        x_star_dev, g_dev);
@@ -613,7 +613,7 @@ extern "C" l1ls_status l1ls_huge_planted(const l1ls_huge* H, double* x_star_dev,
     return L1LS_OK;
 }
 
-extern "C" l1ls_status l1ls_huge_apply(const l1ls_huge* H, int32_t trans, const double* in_dev, double* out_dev,
+extern "C" l1ls_status l1ls_sgt_apply(const l1ls_sgt* H, int32_t trans, const double* in_dev, double* out_dev,
                                        void* stream) {
     if (!H || !in_dev || !out_dev || (trans != 0 && trans != 1)) return L1LS_E_ARG;
     if (!aligned16(in_dev) || !aligned16(out_dev)) return L1LS_E_ARG;
@@ -625,21 +625,21 @@ extern "C" l1ls_status l1ls_huge_apply(const l1ls_huge* H, int32_t trans, const 
     return L1LS_OK;
 }
 
-extern "C" l1ls_status l1ls_huge_objective_gap(const l1ls_huge* H, double tau, const double* x_dev, double* P,
+extern "C" l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* H, double tau, const double* x_dev, double* P,
                                                double* D, double* gap, void* stream) {
     if (!H || !x_dev || !P || !D || !gap || !(tau > 0) || !is_fin(tau)) return L1LS_E_ARG;
     if (!aligned16(x_dev)) return L1LS_E_ARG;
-    return huge_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap);
+    return sgt_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap);
 }
 
-// CG-Newton state between l1ls_huge_newton_step calls: the iterate x (the
+// CG-Newton state between l1ls_sgt_newton_step calls: the iterate x (the
 // caller's buffer), the primal-dual variable gd and the PCG vectors.
-struct l1ls_huge_newton {
+struct l1ls_sgt_newton {
     static constexpr int kBatch = 8;  // PCG iterations enqueued between host checks
     static constexpr int kEv = 2 * kBatch + 2;
-    const l1ls_huge* H = nullptr;
+    const l1ls_sgt* H = nullptr;
     hipStream_t s = nullptr;
-    HugeK K{};
+    SgtK K{};
     double tau = 1, mu = 1e-5, prtol = 0.1, gtol = 1e-9;
     int maxbt = 50, pcgmax = 1000, primal = 0, nb = 1;
     bool tk = false;
@@ -654,7 +654,7 @@ struct l1ls_huge_newton {
     bool converged = false;
     std::chrono::steady_clock::time_point t0;
 
-    ~l1ls_huge_newton() {
+    ~l1ls_sgt_newton() {
         (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
         W.release();
         for (int q = 0; q < nev; ++q) (void)hipEventDestroy(ev[q]);
@@ -665,7 +665,7 @@ struct l1ls_huge_newton {
         return (double)ms;
     }
 
-    l1ls_status init(const l1ls_huge* inst, const l1ls_solve_opts* o, double* xdev) {
+    l1ls_status init(const l1ls_sgt* inst, const l1ls_solve_opts* o, double* xdev) {
         H = inst;
         x = xdev;
         s = (hipStream_t)o->stream;
@@ -806,8 +806,8 @@ struct l1ls_huge_newton {
         std::memset(&rr, 0, sizeof(rr));
         rr.iterations = newton;
         rr.inner = pcg_total;
-        L1LS_TRY(huge_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap));
-        L1LS_TRY(huge_err(H, x, s, &rr.rel_err));
+        L1LS_TRY(sgt_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap));
+        L1LS_TRY(sgt_err(H, x, s, &rr.rel_err));
         rr.converged = converged ? 1 : 0;
         rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (out) *out = rr;
@@ -815,13 +815,13 @@ struct l1ls_huge_newton {
     }
 };
 
-extern "C" l1ls_status l1ls_huge_newton_create(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
-                                               l1ls_huge_newton** out) {
+extern "C" l1ls_status l1ls_sgt_newton_create(const l1ls_sgt* H, const l1ls_solve_opts* o, double* x,
+                                               l1ls_sgt_newton** out) {
     if (!H || !o || !x || !out) return L1LS_E_ARG;
     *out = nullptr;
     if (!aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
     if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
-    auto* N = new (std::nothrow) l1ls_huge_newton();
+    auto* N = new (std::nothrow) l1ls_sgt_newton();
     if (!N) return L1LS_E_NOMEM;
     const l1ls_status st = N->init(H, o, x);
     if (st != L1LS_OK) {
@@ -832,27 +832,27 @@ extern "C" l1ls_status l1ls_huge_newton_create(const l1ls_huge* H, const l1ls_so
     return L1LS_OK;
 }
 
-extern "C" l1ls_status l1ls_huge_newton_step(l1ls_huge_newton* N, int64_t steps, l1ls_report* rep) {
+extern "C" l1ls_status l1ls_sgt_newton_step(l1ls_sgt_newton* N, int64_t steps, l1ls_report* rep) {
     if (!N || steps < 0) return L1LS_E_ARG;
     L1LS_TRY(N->steps(steps));
     L1LS_TRY(N->report(rep));
     return N->converged ? L1LS_OK : L1LS_NOT_CONVERGED;
 }
 
-extern "C" void l1ls_huge_newton_destroy(l1ls_huge_newton* N) { delete N; }
+extern "C" void l1ls_sgt_newton_destroy(l1ls_sgt_newton* N) { delete N; }
 
-extern "C" l1ls_status l1ls_huge_solve_cg_newton(const l1ls_huge* H, const l1ls_solve_opts* o, double* x,
+extern "C" l1ls_status l1ls_sgt_solve_cg_newton(const l1ls_sgt* H, const l1ls_solve_opts* o, double* x,
                                                  l1ls_report* rep) {
     if (!H || !o || !x) return L1LS_E_ARG;
     if (o->max_iter < 0) return L1LS_E_ARG;
-    l1ls_huge_newton* N = nullptr;
-    L1LS_TRY(l1ls_huge_newton_create(H, o, x, &N));
-    const l1ls_status st = l1ls_huge_newton_step(N, o->max_iter, rep);
-    l1ls_huge_newton_destroy(N);
+    l1ls_sgt_newton* N = nullptr;
+    L1LS_TRY(l1ls_sgt_newton_create(H, o, x, &N));
+    const l1ls_status st = l1ls_sgt_newton_step(N, o->max_iter, rep);
+    l1ls_sgt_newton_destroy(N);
     return st;
 }
 
-extern "C" l1ls_status l1ls_huge_kernel_times(const l1ls_huge* H, double* ms, int64_t* calls) {
+extern "C" l1ls_status l1ls_sgt_kernel_times(const l1ls_sgt* H, double* ms, int64_t* calls) {
     if (!H || !ms || !calls) return L1LS_E_ARG;
     for (int q = 0; q < 3; ++q) {
         ms[q] = H->kt_ms[q];

@@ -106,14 +106,14 @@ def test_request_footprint_estimate():
     assert L.lib().l1ls_request_footprint(None) == 0
 
 
-def test_huge_params_default_is_section_8_9():
-    p = L.huge_params(2 ** 30, 7)
+def test_sgt_params_default_is_section_8_9():
+    p = L.sgt_params(2 ** 30, 7)
     assert (p.n, p.m, p.s) == (2 ** 30, 2 ** 31, 2 ** 20)
     assert p.theta == 2.0 * 3.141592653589793 / 3.0
     assert (p.sigma_odd, p.sigma_even, p.x_neg, p.x_pos, p.tau, p.seed) == (0.1, 100.0, -1.0e4, 0.1, 1.0, 7)
-    assert L.huge_bytes(2 ** 30) >= 8 * 2 ** 30
-    assert L.huge_solve_bytes(2 ** 30) >= 40 * 2 ** 30
-    assert L.huge_bytes(1) == 0 and L.huge_solve_bytes(0) == 0
+    assert L.sgt_bytes(2 ** 30) >= 8 * 2 ** 30
+    assert L.sgt_solve_bytes(2 ** 30) >= 40 * 2 ** 30
+    assert L.sgt_bytes(1) == 0 and L.sgt_solve_bytes(0) == 0
 
 
 @pytest.mark.parametrize("field,value", [
@@ -121,27 +121,27 @@ def test_huge_params_default_is_section_8_9():
     ("sigma_odd", 0.0), ("sigma_even", -1.0), ("tau", 0.0), ("theta", float("nan")),
     ("x_neg", float("inf")), ("tau", float("nan")),
 ])
-def test_huge_generate_rejects_invalid_arguments(field, value):
-    p = L.huge_params(8, 1)
+def test_sgt_generate_rejects_invalid_arguments(field, value):
+    p = L.sgt_params(8, 1)
     setattr(p, field, value)
     h = ctypes.c_void_p()
-    st = L.lib().l1ls_huge_generate(ctypes.byref(p), None, ctypes.byref(h))
+    st = L.lib().l1ls_sgt_generate(ctypes.byref(p), None, ctypes.byref(h))
     assert st == -1 and not h.value
 
 
-def test_huge_null_arguments():
+def test_sgt_null_arguments():
     lib = L.lib()
     h = ctypes.c_void_p()
-    assert lib.l1ls_huge_generate(None, None, ctypes.byref(h)) == -1
-    assert lib.l1ls_huge_describe(None, None) == -1
-    assert lib.l1ls_huge_planted(None, None, None, None) == -1
-    assert lib.l1ls_huge_apply(None, 0, None, None, None) == -1
+    assert lib.l1ls_sgt_generate(None, None, ctypes.byref(h)) == -1
+    assert lib.l1ls_sgt_describe(None, None) == -1
+    assert lib.l1ls_sgt_planted(None, None, None, None) == -1
+    assert lib.l1ls_sgt_apply(None, 0, None, None, None) == -1
     d = ctypes.c_double()
-    assert lib.l1ls_huge_objective_gap(None, 1.0, None, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d),
+    assert lib.l1ls_sgt_objective_gap(None, 1.0, None, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d),
                                        None) == -1
-    assert lib.l1ls_huge_solve_cg_newton(None, None, None, None) == -1
+    assert lib.l1ls_sgt_solve_cg_newton(None, None, None, None) == -1
     h2 = ctypes.c_void_p()
-    assert lib.l1ls_huge_newton_create(None, None, None, ctypes.byref(h2)) == -1 and not h2.value
-    assert lib.l1ls_huge_newton_step(None, 1, None) == -1
-    lib.l1ls_huge_newton_destroy(None)
-    lib.l1ls_huge_free(None)
+    assert lib.l1ls_sgt_newton_create(None, None, None, ctypes.byref(h2)) == -1 and not h2.value
+    assert lib.l1ls_sgt_newton_step(None, 1, None) == -1
+    lib.l1ls_sgt_newton_destroy(None)
+    lib.l1ls_sgt_free(None)

@@ -17,7 +17,7 @@ import torch
 import paper_1503_03520_amd as L
 from oracle import fista as OF
 from oracle import newton as ON
-from oracle.huge import HugeInstance, b_at_pairs, planted_at
+from oracle.sgt import SgtInstance, b_at_pairs, planted_at
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,9 @@ CASES = [
 
 
 def make(n, s, m, kw):
-    p = L.huge_params(n, SEED, s=s, **({} if m is None else {"m": m}), **kw)
-    H = L.HugeInstance(p)
-    O = HugeInstance(n, s, SEED, m=m, **kw)
+    p = L.sgt_params(n, SEED, s=s, **({} if m is None else {"m": m}), **kw)
+    H = L.SgtInstance(p)
+    O = SgtInstance(n, s, SEED, m=m, **kw)
     return H, O
 
 
@@ -165,19 +165,19 @@ def test_cg_newton_edge_cases():
     buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
     o = L.solve_opts(max_iter=1)
     rep = L.Report()
-    assert L.lib().l1ls_huge_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr() + 8),
+    assert L.lib().l1ls_sgt_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr() + 8),
                                              ctypes.byref(rep)) == -1
     for kw in (dict(precision=L.F32), dict(polish=1)):
         o = L.solve_opts(max_iter=1, **kw)
-        assert L.lib().l1ls_huge_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr()),
+        assert L.lib().l1ls_sgt_solve_cg_newton(H.handle, ctypes.byref(o), ctypes.c_void_p(buf.data_ptr()),
                                                  ctypes.byref(rep)) == -6
-    assert L.lib().l1ls_huge_apply(H.handle, 2, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(buf.data_ptr()),
+    assert L.lib().l1ls_sgt_apply(H.handle, 2, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(buf.data_ptr()),
                                    None) == -1
     H.free()
 
 
 def test_stepping_object_equals_one_solve():
-    # l1ls_huge_newton_*: 3 + 5 Newton steps give the bits of one 8-step solve
+    # l1ls_sgt_newton_*: 3 + 5 Newton steps give the bits of one 8-step solve
     H, O = make(4098, 4, None, {})
     x1, rep1, _ = H.solve_cg_newton(max_iter=8)
     N = H.newton()
@@ -206,8 +206,8 @@ def test_table_1_size_sampled_generation_and_solve():
     # single-pair construction, the planted x* against the inverse bijection,
     # and the 8-Newton-step solve against the behaviour section 8.9 reports.
     n = 2 ** 30
-    p = L.huge_params(n, SEED)
-    H = L.HugeInstance(p)
+    p = L.sgt_params(n, SEED)
+    H = L.SgtInstance(p)
     d = H.describe()
     rng = np.random.default_rng(2)
     pairs = np.unique(np.r_[0, 1, n // 2 - 1, n // 4, rng.integers(0, n // 2, 60)])

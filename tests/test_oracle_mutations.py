@@ -7,9 +7,9 @@ pin tests of ``test_oracle_pins`` reject it.  Nothing here touches a GPU.
 import numpy as np
 import pytest
 
-import test_oracle_huge as hpins
+import test_oracle_sgt as hpins
 import test_oracle_pins as pins
-from oracle import fista as F, huge as OH, instance as I
+from oracle import fista as F, instance as I, sgt as OH
 
 
 def _rotate_wrong_sign(z, first, second, c, s, transpose=False):
@@ -115,25 +115,25 @@ def test_wrong_dual_sign_is_caught(monkeypatch):
 
 
 # ---- section 8.9 class -------------------------------------------------------
-def test_huge_wrong_givens_sign_is_caught(monkeypatch):
+def test_sgt_wrong_givens_sign_is_caught(monkeypatch):
     monkeypatch.setattr(OH, "rotate", _rotate_wrong_sign)
     with pytest.raises(AssertionError):
         hpins.test_operator_equals_definition(64, 6)
 
 
-def test_huge_swapped_sigma_law_is_caught(monkeypatch):
-    orig = OH.HugeInstance.__init__
+def test_sgt_swapped_sigma_law_is_caught(monkeypatch):
+    orig = OH.SgtInstance.__init__
 
     def init_wrong(self, n, s, seed, **kw):
         kw["sigma_odd"], kw["sigma_even"] = kw.get("sigma_even", 100.0), kw.get("sigma_odd", 0.1)
         orig(self, n, s, seed, **kw)
-    monkeypatch.setattr(OH.HugeInstance, "__init__", init_wrong)
+    monkeypatch.setattr(OH.SgtInstance, "__init__", init_wrong)
     with pytest.raises(AssertionError):
         hpins.test_sampled_values_equal_whole_construction(64, 6)
 
 
-def test_huge_dropped_tau_in_noise_is_caught(monkeypatch):
-    orig = OH.HugeInstance.__init__
+def test_sgt_dropped_tau_in_noise_is_caught(monkeypatch):
+    orig = OH.SgtInstance.__init__
 
     def init_wrong(self, n, s, seed, **kw):
         tau = kw.get("tau", 1.0)
@@ -141,17 +141,17 @@ def test_huge_dropped_tau_in_noise_is_caught(monkeypatch):
         self.e[: self.n] = self.apply_Gt(self.g) / self.sigma     # tau dropped
         self.b = self.matvec(self.xstar) + self.e
         self.tau = tau
-    monkeypatch.setattr(OH.HugeInstance, "__init__", init_wrong)
+    monkeypatch.setattr(OH.SgtInstance, "__init__", init_wrong)
     with pytest.raises(AssertionError):
         hpins.test_planted_solution_is_optimal(130, 9, 0.37)
 
 
-def test_huge_swapped_support_values_are_caught(monkeypatch):
-    orig = OH.HugeInstance.__init__
+def test_sgt_swapped_support_values_are_caught(monkeypatch):
+    orig = OH.SgtInstance.__init__
 
     def init_wrong(self, n, s, seed, **kw):
         kw["x_neg"], kw["x_pos"] = kw.get("x_pos", 0.1), kw.get("x_neg", -1.0e4)
         orig(self, n, s, seed, **kw)
-    monkeypatch.setattr(OH.HugeInstance, "__init__", init_wrong)
+    monkeypatch.setattr(OH.SgtInstance, "__init__", init_wrong)
     with pytest.raises(AssertionError):
         hpins.test_support_values_and_subgradient(130, 9)   # odd s: floor(s/2) != s - floor(s/2)
