@@ -665,6 +665,89 @@ def cpu_baseline_table1(n, newton_steps, log2_sample=18):
                       f"{log2_sample} took {sec:.2f} s on one core, scaled by n / 2^{log2_sample}"}
 
 
+def grid_instances(log2n):
+    """The instances of sections 8.4, 8.5 and 8.6 (A = Sigma G^T, m = 2n,
+    s = n / 2^7): (section, n, label, parameter overrides)."""
+    import math
+    n = 1 << log2n
+    out = []
+    for q in range(6):
+        for g in (10.0, 1e3):
+            out.append(("8.4", n, f"q={q} OsGen gamma={g:g} theta=2pi/3",
+                        dict(sigma_law=1, sigma_scale=10.0 ** q, xstar_law=1, gamma=g)))
+    for th, tn in ((2 * math.pi / 10, "2pi/10"), (2 * math.pi / 1e3, "2pi/10^3")):
+        for q in range(4):
+            out.append(("8.5", n, f"q={q} OsGen3 gamma=100 theta={tn}",
+                        dict(theta=th, sigma_law=1, sigma_scale=10.0 ** q, xstar_law=2, gamma=100.0)))
+    for ln in (20, 22, 24, 26):
+        out.append(("8.6", 1 << ln, f"n=2^{ln} OsGen3 gamma=100 theta=2pi/10",
+                    dict(theta=2 * math.pi / 10, sigma_law=1, sigma_scale=10.0, xstar_law=2, gamma=100.0)))
+    return out
+
+
+def bench_grid(args):
+    """Sections 8.4 to 8.6 on one GPU with the paper's protocol (section 8.3):
+    CG-Newton (the paper's pdNCG reading) runs first, then FISTA runs until
+    f_tau falls to CG-Newton's objective or an iteration cap.  Every instance
+    is generated on the device; value = seconds for the whole grid."""
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows, t_all = [], time.perf_counter()
+    fista_pass = None
+    for sec, n, label, kw in grid_instances(args.grid_log2n):
+        if args.grid_sections and sec not in args.grid_sections:
+            continue
+        p = L.sgt_params(n, 1503035207, s=n // 128, **kw)
+        t = time.perf_counter()
+        H = L.SgtInstance(p, stream=stream)
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t
+        d = H.describe()
+        k_rho = H.kappa_rho(0.1)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        _, rn, _ = H.solve_cg_newton(x_out=x, max_iter=args.grid_newton, rel_gap_tol=1e-9, stream=stream)
+        f_cgn = rn["primal"]
+        _, rf, st = H.solve_fista(x_out=x, max_iter=args.grid_fista_max, rel_gap_tol=0.0, f_target=f_cgn,
+                                  check_every=args.check_every, stream=stream, time_kernels=1 if fista_pass is None else 0)
+        if fista_pass is None:
+            kt = H.fista_kernel_times()
+            fista_pass = (n, kt["iteration"][0] / max(kt["iteration"][1], 1))
+        row = {"section": sec, "instance": label, "n": n, "kappa_AtA": (d.sigma_max / d.sigma_min) ** 2,
+               "kappa_0.1_xstar": k_rho, "generate_s": gen_s,
+               "cg_newton": {"newton_steps": rn["iterations"], "pcg_iterations": rn["inner"], "seconds": rn["seconds"],
+                             "f": f_cgn, "rel_err": rn["rel_err"], "converged": rn["converged"]},
+               "fista": {"iterations": rf["iterations"], "seconds": rf["seconds"], "f": rf["primal"],
+                         "reached_cg_newton_f": st == L.L1LS_OK, "rel_err": rf["rel_err"]}}
+        rows.append(row)
+        print(json.dumps({"progress": "grid", **row}), file=sys.stderr, flush=True)
+        H.free()
+        del x
+    total = time.perf_counter() - t_all
+    n0, ms = fista_pass
+    ach = 32.0 * n0 / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "seconds for the sections 8.4-8.6 instance grid (CG-Newton, then FISTA to CG-Newton's objective)",
+        "value": total, "unit": "s", "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": total * 1e3 / max(len(rows), 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (sections 8.4-8.6 instances generated on the device, seed 1503035207)",
+        "config": {"workload": "sections 8.4-8.6: A = Sigma G^T, m = 2n, s = n/2^7, sigma uniform on [0, 10^q] + 0.1; "
+                               "8.4: OsGen gamma 10 / 1e3, q = 0..5, theta = 2 pi/3; 8.5: OsGen3 gamma = 100, q = 0..3, "
+                               "theta = 2 pi/10 and 2 pi/10^3; 8.6: OsGen3, q = 1, n = 2^20..2^26",
+                   "n": 1 << args.grid_log2n, "newton_cap": args.grid_newton, "fista_cap": args.grid_fista_max},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "kh_fista (FISTA iteration on the pairs)",
+                     "algorithmic_bytes_per_launch": 32 * n0},
+        "extra": {"instances": rows,
+                  "paper": {"8.4": "pdNCG at most 30 iterations; FISTA thousands to tens of thousands; kappa_0.1 ~ 1",
+                            "8.5": "kappa_0.1 ~ 40 on average", "8.6": "kappa_0.1 ~ 3 on average; linear-like scaling in n"}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -686,13 +769,18 @@ def main():
     ap.add_argument("--stats-command", default="")
     ap.add_argument("--stats-top", type=int, default=14)
     ap.add_argument("--out", default=PROFILE_SUMMARY)
-    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large", "table1"],
+    ap.add_argument("--workload", default="fista", choices=["fista", "serve", "batched", "path", "large", "table1", "grid"],
                     help="fista: the single large instance (default); serve: the request stream; "
                          "batched: 256 uneven instances; path: 64 taus on one instance; "
                          "large: the n = 2^26 instance, stored vs matrix-free, CG-Newton; "
-                         "table1: the section 8.9 (Table 1) instance at n = 2^30, CG-Newton")
+                         "table1: the section 8.9 (Table 1) instance at n = 2^30, CG-Newton; "
+                         "grid: the sections 8.4-8.6 instances, CG-Newton then FISTA")
     ap.add_argument("--large-log2n", type=int, default=26)
     ap.add_argument("--table1-log2n", type=int, default=30)
+    ap.add_argument("--grid-log2n", type=int, default=22)
+    ap.add_argument("--grid-newton", type=int, default=30)
+    ap.add_argument("--grid-fista-max", type=int, default=20000)
+    ap.add_argument("--grid-sections", nargs="*", default=None, help="subset of 8.4 8.5 8.6")
     ap.add_argument("--newton-steps", type=int, default=8)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
@@ -744,7 +832,7 @@ def main():
         if args.workload == "table1" and "--steps" not in sys.argv:
             args.steps, args.warmup = 1, 1
         {"serve": bench_serve, "batched": bench_batched, "path": bench_path,
-         "large": bench_large, "table1": bench_table1}[args.workload](args)
+         "large": bench_large, "table1": bench_table1, "grid": bench_grid}[args.workload](args)
         return
 
     import torch

@@ -172,6 +172,8 @@ typedef struct {
     /* Batch only: rounds of 4 tiles per workgroup task; 0: chosen per slot
      * size by the library's autotuner (timed on a slot's first pass). */
     int32_t tile_chunk;
+    /* l1ls_sgt_solve_fista only: stop once f_tau(x_k) <= f_target (0: off). */
+    double f_target;
 } l1ls_solve_opts;
 
 typedef struct {
@@ -361,26 +363,41 @@ l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus,
                                   const l1ls_solve_opts* opts, double* X_out_dev, l1ls_report* reports);
 
 /* ---------------------------------------------------------------------------
- * Huge-scale instance class of section 8.9 (Table 1).
+ * The A = Sigma G^T instance class of sections 8.4 to 8.9 (Table 1).
  *
- * A = Sigma G^T with m >= n rows (section 8.9: m = 2n) and rank n: Sigma has
- * sigma_i = sigma_odd for odd i and sigma_even for even i (1-based) on its
- * top n x n diagonal and zeros below (section 4); G is the product of the
- * n/2 Givens rotations G(2k-1, 2k, theta), k = 1..n/2, on adjacent pairs
- * with one shared angle (section 4.1 without Q-side rotations or
- * permutation), G(i, j, theta) mapping (z_i, z_j) to
- * (c z_i - s z_j, s z_i + c z_j).  x* has s nonzeros at the first s outputs
- * of the support bijection (the same Philox-keyed Feistel bijection as
- * l1ls_generate); the first floor(s/2) of them are x_neg, the rest x_pos.
+ * A = Sigma G^T with m >= n rows (m = 2n in all of these experiments) and
+ * rank n: Sigma has sigma_1..sigma_n on its top n x n diagonal and zeros
+ * below (section 4); G is the product of the n/2 Givens rotations
+ * G(2k-1, 2k, theta), k = 1..n/2, on adjacent pairs with one shared angle
+ * (section 4.1 without Q-side rotations or permutation), G(i, j, theta)
+ * mapping (z_i, z_j) to (c z_i - s z_j, s z_i + c z_j).
+ *   sigma_law ALTERNATING (section 8.9): sigma_i = sigma_odd for odd i and
+ *     sigma_even for even i (1-based).
+ *   sigma_law UNIFORM (sections 8.4 to 8.6): sigma_i = u_i sigma_scale +
+ *     sigma_shift, u_i uniform on [0, 1) (the sections' [0, 10^q] shifted by
+ *     0.1: sigma_scale = 10^q, sigma_shift = 0.1); pair k draws Philox
+ *     counter (k, 0, 0x500, 0), words (0, 1) for element 2k, (2, 3) for 2k+1.
+ *   xstar_law TABLE1 (section 8.9): s nonzeros at the first s outputs of the
+ *     support bijection (the Philox-keyed Feistel bijection of
+ *     l1ls_generate); the first floor(s/2) are x_neg, the rest x_pos.
+ *   xstar_law OSGEN (section 6, Procedure OsGen): the same positions, values
+ *     gamma (2u - 1), u from the x* counter of l1ls_generate.
+ *   xstar_law OSGEN3 (section 6, Procedure OsGen3): x = G gamma (Sigma^T
+ *     Sigma)^{-1} 1_n (the exact minimiser of eq. (19)); its s1 smallest and
+ *     s2 largest components in the order (|x_i|, i) are kept, s1 + s2 = s.
  * The subgradient g is sign(x*) on the support and U[-0.9, 0.9] elsewhere;
  * e = tau Sigma^{+T} G^T g and b = A x* + e (Procedure IGen, section 3.1).
  * A is block diagonal with one 2 x 2 block per pair and rows n..m-1 of A
  * and b are zero: the library stores the top n entries of b only (8 n
- * bytes) and recomputes x* and g from (seed, index) where it needs them.
+ * bytes) and recomputes sigma, x* and g from (seed, index) where it needs
+ * them.
  *
  * Device vectors passed to these calls must be 16-byte aligned
  * (L1LS_E_ARG otherwise).  Calls on the same instance must not overlap.
  * ------------------------------------------------------------------------- */
+enum { L1LS_SIGMA_ALTERNATING = 0, L1LS_SIGMA_UNIFORM = 1 };
+enum { L1LS_XSTAR_TABLE1 = 0, L1LS_XSTAR_OSGEN = 1, L1LS_XSTAR_OSGEN3 = 2 };
+
 typedef struct l1ls_sgt l1ls_sgt;
 
 typedef struct {
@@ -394,6 +411,12 @@ typedef struct {
     double x_pos;       /* other support values (section 8.9: 0.1)              */
     double tau;         /* > 0 (section 8.3: 1)                                 */
     uint64_t seed;
+    int32_t sigma_law;  /* L1LS_SIGMA_*                                         */
+    int32_t xstar_law;  /* L1LS_XSTAR_*                                         */
+    double sigma_scale; /* UNIFORM: >= 0 (sections 8.4-8.6: 10^q)               */
+    double sigma_shift; /* UNIFORM: > 0 (sections 8.4-8.6: 0.1)                 */
+    double gamma;       /* OSGEN, OSGEN3: > 0 (8.4: 10, 1e3; 8.5, 8.6: 100)     */
+    int64_t s1, s2;     /* OSGEN3: smallest / largest kept, s1 + s2 = s         */
 } l1ls_sgt_params;
 
 typedef struct {
@@ -402,10 +425,13 @@ typedef struct {
     double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2               */
     double c, s_rot;     /* cos theta, sin theta as used by the kernels          */
     const double* b_dev; /* n: the top n entries of b (the others are zero)       */
+    double sigma_min, sigma_max; /* kappa(A^T A) = (sigma_max / sigma_min)^2 (section 5) */
 } l1ls_sgt_desc;
 
 /* params = the section 8.9 values for n: m = 2n, s = floor(n / 1024),
- * theta = 2 pi / 3, sigma 0.1 / 100, x* values -1e4 / 0.1, tau = 1. */
+ * theta = 2 pi / 3, ALTERNATING sigma 0.1 / 100, TABLE1 x* values -1e4 /
+ * 0.1, tau = 1 (and sigma_scale 1, sigma_shift 0.1, gamma 1, s1 = floor(s/2),
+ * s2 = s - s1 for the other laws). */
 void l1ls_sgt_params_default(int64_t n, uint64_t seed, l1ls_sgt_params* params);
 /* Device bytes of an instance, and the extra device bytes of a CG-Newton
  * solve on it (besides the caller's x): 8 n + O(1) and 40 n + O(1). */
@@ -427,6 +453,12 @@ l1ls_status l1ls_sgt_planted(const l1ls_sgt* inst, double* x_star_dev, double* g
 l1ls_status l1ls_sgt_apply(const l1ls_sgt* inst, int32_t trans, const double* in_dev,
                             double* out_dev, void* stream);
 
+/* kappa_rho(x*) of eq. (17) (section 5): ||x*|| / ||P_rho x*|| with P_rho the
+ * projection on the eigenvectors of A^T A = G Sigma^2 G^T whose eigenvalues
+ * sigma_i^2 are >= rho (+inf when that projection is 0).  rho >= 0.
+ * Blocks until done. */
+l1ls_status l1ls_sgt_kappa_rho(const l1ls_sgt* inst, double rho, double* kappa, void* stream);
+
 /* FP64 P = f_tau(x), the dual value at the scaled residual and the relative
  * gap, as l1ls_objective_gap.  Blocks until done. */
 l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* inst, double tau, const double* x_dev,
@@ -447,6 +479,21 @@ l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* inst, double tau, const doubl
 l1ls_status l1ls_sgt_solve_cg_newton(const l1ls_sgt* inst, const l1ls_solve_opts* opts,
                                       double* x_dev, l1ls_report* report);
 
+/*
+ * FISTA (section 8.1) on the instance, FP64, from opts.x0_dev (NULL: 0) with
+ * L = opts.L (<= 0: sigma_max^2): x_k = soft(y_k - A^T (A y_k - b) / L,
+ * tau / L), y_{k+1} = x_k + ((t_k - 1) / t_{k+1}) (x_k - x_{k-1}), t_1 = 1.
+ * Every opts.check_every iterations the FP64 gap at x_k is evaluated; the
+ * solve stops when the relative gap is <= opts.rel_gap_tol (> 0), when
+ * f_tau(x_k) <= opts.f_target (> 0; the comparison protocol of section 8.3),
+ * or after opts.max_iter iterations.  x_dev (n) receives the result;
+ * opts.precision must be L1LS_F64 and opts.polish 0.  Allocates 8 n bytes
+ * for the call.  Returns L1LS_OK when a stop test passed, else
+ * L1LS_NOT_CONVERGED.
+ */
+l1ls_status l1ls_sgt_solve_fista(const l1ls_sgt* inst, const l1ls_solve_opts* opts, double* x_dev,
+                                 l1ls_report* report);
+
 /* The same CG-Newton one call at a time, for callers that report between
  * Newton steps.  create: validates opts as l1ls_sgt_solve_cg_newton (max_iter
  * is not used), allocates l1ls_sgt_solve_bytes(n), sets x_dev to the start;
@@ -460,11 +507,12 @@ l1ls_status l1ls_sgt_newton_create(const l1ls_sgt* inst, const l1ls_solve_opts* 
 l1ls_status l1ls_sgt_newton_step(l1ls_sgt_newton* newton, int64_t steps, l1ls_report* report);
 void l1ls_sgt_newton_destroy(l1ls_sgt_newton* newton);
 
-/* HIP-event times of the passes of the last CG-Newton on inst (solve or
- * stepping object) created with opts.time_kernels = 1: ms[q] total milliseconds and
+/* HIP-event times of the passes of the last CG-Newton (solve or stepping
+ * object) or FISTA on inst run with opts.time_kernels = 1: ms[q] total milliseconds and
  * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r; the first
  * iteration of each PCG, which reads neither p nor dx, is left out), 1 the
- * line-search pass, 2 the Newton setup pass (gradient, d, PCG start). */
+ * line-search pass, 2 the Newton setup pass (gradient, d, PCG start); after
+ * l1ls_sgt_solve_fista: 0 the iteration pass, 1 the gap pass. */
 l1ls_status l1ls_sgt_kernel_times(const l1ls_sgt* inst, double* ms, int64_t* calls);
 
 const char* l1ls_status_string(int32_t status);

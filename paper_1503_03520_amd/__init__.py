@@ -17,6 +17,8 @@ F32, F64 = 0, 1
 OP_STORED, OP_MATRIX_FREE = 0, 1
 STORE_F32, STORE_F64 = 1, 2
 REQ_FP64_FINISH = 1
+SIGMA_ALTERNATING, SIGMA_UNIFORM = 0, 1
+XSTAR_TABLE1, XSTAR_OSGEN, XSTAR_OSGEN3 = 0, 1, 2
 
 _STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "device allocation failed",
            -3: "HIP runtime error", -4: "non-finite value", -5: "invalid state", -6: "unsupported"}
@@ -61,6 +63,7 @@ class SolveOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("time_kernels", ctypes.c_int32),
         ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
         ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
+        ("f_target", ctypes.c_double),
     ]
 
 
@@ -88,13 +91,16 @@ class SgtParams(ctypes.Structure):
         ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("s", ctypes.c_int64), ("theta", ctypes.c_double),
         ("sigma_odd", ctypes.c_double), ("sigma_even", ctypes.c_double), ("x_neg", ctypes.c_double),
         ("x_pos", ctypes.c_double), ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("sigma_law", ctypes.c_int32), ("xstar_law", ctypes.c_int32), ("sigma_scale", ctypes.c_double),
+        ("sigma_shift", ctypes.c_double), ("gamma", ctypes.c_double), ("s1", ctypes.c_int64), ("s2", ctypes.c_int64),
     ]
 
 
 class SgtDesc(ctypes.Structure):
     _fields_ = [
         ("params", SgtParams), ("L", ctypes.c_double), ("f_star", ctypes.c_double), ("c", ctypes.c_double),
-        ("s_rot", ctypes.c_double), ("b_dev", ctypes.c_void_p),
+        ("s_rot", ctypes.c_double), ("b_dev", ctypes.c_void_p), ("sigma_min", ctypes.c_double),
+        ("sigma_max", ctypes.c_double),
     ]
 
 
@@ -159,6 +165,8 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                                _P]),
     "l1ls_sgt_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_sgt_kappa_rho": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P]),
+    "l1ls_sgt_solve_fista": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_sgt_newton_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
     "l1ls_sgt_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
     "l1ls_sgt_newton_destroy": (None, [_P]),
@@ -535,11 +543,16 @@ def l1ls_solve_fista_path(inst, taus, **kw):
 
 # ---- A = Sigma G^T instance class (sections 8.4 to 8.9) ----------------------
 def sgt_params(n, seed, **kw):
-    """The section 8.9 parameters for n (l1ls_sgt_params_default), with overrides."""
+    """The section 8.9 parameters for n (l1ls_sgt_params_default), with
+    overrides; s1 and s2 follow an overridden s unless given."""
     p = SgtParams()
     lib().l1ls_sgt_params_default(n, seed, ctypes.byref(p))
     for k, v in kw.items():
         setattr(p, k, v)
+    if "s" in kw and "s1" not in kw:
+        p.s1 = p.s // 2
+    if "s" in kw and "s2" not in kw:
+        p.s2 = p.s - p.s1
     return p
 
 
@@ -574,6 +587,21 @@ class SgtInstance:
                                              ctypes.byref(g), _stream(stream)), "l1ls_sgt_objective_gap")
         return P.value, D.value, g.value
 
+    def kappa_rho(self, rho, stream=None):
+        k = ctypes.c_double()
+        _check(lib().l1ls_sgt_kappa_rho(self._h, rho, ctypes.byref(k), _stream(stream)), "l1ls_sgt_kappa_rho")
+        return k.value
+
+    def solve_fista(self, x_out=None, **kw):
+        import torch
+        if x_out is None:
+            x_out = torch.empty(self.params["n"], dtype=torch.float64, device="cuda")
+        o = solve_opts(**kw)
+        rep = Report()
+        st = _check(lib().l1ls_sgt_solve_fista(self._h, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)),
+                    "l1ls_sgt_solve_fista", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+        return x_out, rep.as_dict(), st
+
     def solve_cg_newton(self, x_out=None, **kw):
         import torch
         if x_out is None:
@@ -594,6 +622,11 @@ class SgtInstance:
         calls = (ctypes.c_int64 * 3)()
         _check(lib().l1ls_sgt_kernel_times(self._h, ms, calls), "l1ls_sgt_kernel_times")
         return {k: (ms[q], calls[q]) for q, k in enumerate(("pcg_iteration", "line_search", "newton_setup"))}
+
+    def fista_kernel_times(self):
+        """{pass: (total ms, launches)} of the last FISTA solve with time_kernels=1."""
+        t = self.kernel_times()
+        return {"iteration": t["pcg_iteration"], "gap": t["line_search"]}
 
     def free(self):
         if self._h:

@@ -1,20 +1,24 @@
-// Huge-scale instance class of section 8.9 (Table 1) and its CG-Newton.
+// The A = Sigma G^T instance class of sections 8.4 to 8.9 (Table 1), its
+// CG-Newton and its FISTA.
 //
-// The instances of section 8.9 are A = Sigma G^T with m = 2n rows and rank
-// n: Sigma carries sigma_i = sigma_odd for odd i and sigma_even for even i
-// (1-based) on its top n x n diagonal (section 4, the display of Sigma), and
-// G is one stage of n/2 Givens rotations G(2k-1, 2k, theta) on adjacent
-// pairs with one shared angle (section 4.1 with Q = I and no permutation).
-// x* has s nonzeros, the first floor(s/2) support draws at x_neg and the
-// rest at x_pos; b comes from Procedure IGen (section 3.1).
+// The experiments of sections 8.4, 8.5, 8.6 and 8.9 use A = Sigma G^T with
+// m >= n rows (m = 2n there) and rank n: Sigma carries sigma_1..sigma_n on
+// its top n x n diagonal (section 4, the display of Sigma), and G is one
+// stage of n/2 Givens rotations G(2k-1, 2k, theta) on adjacent pairs with one
+// shared angle (section 4.1 with Q = I and no permutation).  The singular
+// values alternate between two values (section 8.9) or are uniform on
+// [0, 10^q] shifted by 0.1 (sections 8.4 to 8.6); x* is Table 1's
+// (section 8.9), Procedure OsGen's or Procedure OsGen3's (section 6); b comes
+// from Procedure IGen (section 3.1).
 //
 // Every row and column of A couples the two elements of one pair and rows
 // n..m-1 are zero, so A is block diagonal with one 2 x 2 block per pair.
 // Nothing is gathered: a thread owns whole pairs, reads each vector as one
 // 16-byte double2 per pair, and every product with A, A^T, A^T A and the
 // Hessian of (8) is formed in registers.  The instance stores b only (its
-// top n entries; the others are zero); x* and the subgradient g are pure
-// functions of (seed, index), recomputed wherever they are needed.
+// top n entries; the others are zero); sigma, x* and the subgradient g are
+// pure functions of (seed, index) and, for OsGen3, of two selection
+// thresholds kept in the instance, recomputed wherever they are needed.
 //
 // CG-Newton follows section 8.1 (item pdNCG) and section 8.3 exactly as the
 // stored-operator solver does: smoothed problem (8) with the pseudo-Huber
@@ -26,7 +30,8 @@
 // and the Hessian diagonal d, so one PCG iteration is one streaming pass
 // (read r, d, p, dx; write p, dx, r: 56 bytes per variable) and one
 // reduction of (r.u, w.u, r.r).  In exact arithmetic its iterates are those
-// of the textbook recurrence the oracle runs.
+// of the textbook recurrence the oracle runs.  FISTA (section 8.1) is one
+// pass per iteration (read x_k, x_{k-1}, b; write x_{k+1}: 32 bytes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +41,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "kernels.hpp"
 #include "rng.hpp"
 
 using namespace l1ls;
@@ -49,14 +55,23 @@ constexpr bool kHNT = true;         // nontemporal loads and stores in the PCG p
 constexpr int kLsBatch = 8;        // step lengths tried per line-search pass
 constexpr int kLsStats = 3 + 2 * kLsBatch;
 constexpr int64_t kSgtMaxN = (int64_t)1 << 32;  // Philox counter word 0 holds the index
+constexpr uint32_t kTagSigma = 0x500u;          // uniform singular values, per pair
+constexpr int kSelBins = 256;                   // radix-select digit of 8 bits
 
 // Constants of one instance, passed by value to every kernel.
 struct SgtK {
-    int64_t n, s;
-    double c, sn;        // cos, sin of the shared angle
-    double so, se;       // sigma at the first / second element of a pair
-    double cn0, cn1;     // diag(A^T A) at the first / second element
-    double tau, xneg, xpos;
+    int64_t n, s, s1, s2;
+    int32_t sigma_law, xstar_law;
+    double c, sn;              // cos, sin of the shared angle
+    double so, se;             // alternating law: sigma at the first / second element of a pair
+    double cn0, cn1;           // alternating law: diag(A^T A) at the first / second element
+    double scale, shift;       // uniform law: sigma = u * scale + shift
+    double tau, xneg, xpos, gamma;
+    // OsGen3: the kept components are those at or below (t1_bits, t1_idx) and at
+    // or above (t2_bits, t2_idx) in the order (|x_i|, i); has1 / has2 = 0: none
+    uint64_t t1_bits, t2_bits;
+    int64_t t1_idx, t2_idx;
+    int32_t has1, has2;
     Key key;
 };
 
@@ -68,40 +83,109 @@ struct HCg {
 // 16-byte vector type the nontemporal builtins accept
 typedef double dv2 __attribute__((ext_vector_type(2)));
 
+// Uniform law: Philox counter (k, 0, kTagSigma, 0), words (0, 1) for the
+// first element and (2, 3) for the second, each u * scale + shift with the
+// product and the sum rounded separately (no fused multiply-add).
+__device__ __forceinline__ double2 uniform_sigma_pair(const SgtK& H, int64_t k) {
+#pragma clang fp contract(off)
+    const U4 w = philox4x32_10((uint32_t)k, 0u, kTagSigma, 0u, H.key.k0, H.key.k1);
+    return make_double2(unit_double(w.x, w.y) * H.scale + H.shift, unit_double(w.z, w.w) * H.scale + H.shift);
+}
+
+// sigma of pair k (elements 2k, 2k+1)
+template <int SL>
+__device__ __forceinline__ double2 sigma_pair(const SgtK& H, int64_t k) {
+    if constexpr (SL == 0)
+        return make_double2(H.so, H.se);
+    else
+        return uniform_sigma_pair(H, k);
+}
+
+// diag(A^T A) on the pair: squared norms of the two columns of the block
+template <int SL>
+__device__ __forceinline__ double2 colnorm_pair(const SgtK& H, double2 sg) {
+    if constexpr (SL == 0) {
+        return make_double2(H.cn0, H.cn1);
+    } else {
+        const double a = sg.x * sg.x, b = sg.y * sg.y, c2 = H.c * H.c, s2 = H.sn * H.sn;
+        return make_double2(a * c2 + b * s2, a * s2 + b * c2);
+    }
+}
+
 // (y_i, y_j) = block of A x: sigma (G^T x) on the pair
-__device__ __forceinline__ void a_pair(const SgtK& H, double xi, double xj, double& yi, double& yj) {
-    yi = H.so * (H.c * xi + H.sn * xj);
-    yj = H.se * (-H.sn * xi + H.c * xj);
+__device__ __forceinline__ void a_pair(const SgtK& H, double2 sg, double xi, double xj, double& yi, double& yj) {
+    yi = sg.x * (H.c * xi + H.sn * xj);
+    yj = sg.y * (-H.sn * xi + H.c * xj);
 }
 
 // (x_i, x_j) = block of A^T y: G (sigma y) on the pair
-__device__ __forceinline__ void at_pair(const SgtK& H, double yi, double yj, double& xi, double& xj) {
-    const double ti = H.so * yi, tj = H.se * yj;
+__device__ __forceinline__ void at_pair(const SgtK& H, double2 sg, double yi, double yj, double& xi, double& xj) {
+    const double ti = sg.x * yi, tj = sg.y * yj;
     xi = H.c * ti - H.sn * tj;
     xj = H.sn * ti + H.c * tj;
 }
 
 // H p = A^T (A p) + d p on the pair
-__device__ __forceinline__ double2 hess_pair(const SgtK& H, double2 p, double2 d) {
+__device__ __forceinline__ double2 hess_pair(const SgtK& H, double2 sg, double2 p, double2 d) {
     double yi, yj, hi, hj;
-    a_pair(H, p.x, p.y, yi, yj);
-    at_pair(H, yi, yj, hi, hj);
+    a_pair(H, sg, p.x, p.y, yi, yj);
+    at_pair(H, sg, yi, yj, hi, hj);
     return make_double2(hi + d.x * p.x, hj + d.y * p.y);
 }
 
-// x*_i and the subgradient g_i of IGen step 2: i is in supp(x*) when its
-// position q under the inverse support bijection is < s (the support is the
-// first s outputs of that bijection); off the support g_i = 0.9 (2u - 1).
-__device__ __forceinline__ void planted_at(const SgtK& H, int64_t i, double& xs, double& g) {
-    const int64_t q = H.s > 0 ? bijection_inverse(i, H.n, kTagPerm | 2u, H.key) : H.n;
-    if (q < H.s) {
-        xs = (q < H.s / 2) ? H.xneg : H.xpos;
+// OsGen3 before selection: x = G gamma (Sigma^T Sigma)^{-1} 1_n on the pair,
+// the exact minimiser of eq. (19), in the operation order of the definition.
+__device__ __forceinline__ double2 osgen3_full_pair(const SgtK& H, double2 sg) {
+#pragma clang fp contract(off)
+    const double vi = H.gamma / (sg.x * sg.x), vj = H.gamma / (sg.y * sg.y);
+    return make_double2(H.c * vi - H.sn * vj, H.sn * vi + H.c * vj);
+}
+
+__device__ __forceinline__ uint64_t abs_bits(double v) { return (uint64_t)__double_as_longlong(fabs(v)); }
+
+// (a, i) <= (b, j) in the order by magnitude, then index
+__device__ __forceinline__ bool key_le(uint64_t a, int64_t i, uint64_t b, int64_t j) {
+    return a < b || (a == b && i <= j);
+}
+
+// x*_i and the subgradient g_i of IGen step 2 for element i with the value
+// xf (OsGen3's unselected x) of its pair.  Table 1 and OsGen: i is in
+// supp(x*) when its position q under the inverse support bijection is < s
+// (the support is the first s outputs of that bijection); off the support
+// g_i = 0.9 (2u - 1).
+__device__ __forceinline__ void planted_elem(const SgtK& H, int64_t i, double xf, double& xs, double& g) {
+    bool on = false;
+    xs = 0.0;
+    if (H.xstar_law == L1LS_XSTAR_OSGEN3) {
+        const uint64_t kb = abs_bits(xf);
+        on = (H.has1 && key_le(kb, i, H.t1_bits, H.t1_idx)) || (H.has2 && key_le(H.t2_bits, H.t2_idx, kb, i));
+        if (on) xs = xf;
+    } else if (H.s > 0) {
+        const int64_t q = bijection_inverse(i, H.n, kTagPerm | 2u, H.key);
+        if (q < H.s) {
+            on = true;
+            if (H.xstar_law == L1LS_XSTAR_TABLE1) {
+                xs = (q < H.s / 2) ? H.xneg : H.xpos;
+            } else {
+                const U4 w = philox4x32_10((uint32_t)q, 0u, kTagXstar, 0u, H.key.k0, H.key.k1);
+                xs = H.gamma * (2.0 * unit_double(w.x, w.y) - 1.0);  // 2u is exact: a fused form rounds the same
+            }
+        }
+    }
+    if (on) {
         g = xs > 0.0 ? 1.0 : (xs < 0.0 ? -1.0 : 0.0);
     } else {
         const U4 w = philox4x32_10((uint32_t)i, 0u, kTagSubgrad, 0u, H.key.k0, H.key.k1);
-        xs = 0.0;
         g = 0.9 * (2.0 * unit_double(w.x, w.y) - 1.0);  // 2u is exact: a fused form rounds the same
     }
+}
+
+// x* and g on pair k with singular values sg
+__device__ __forceinline__ void planted_pair(const SgtK& H, int64_t k, double2 sg, double2& xs, double2& g) {
+    double2 xf = make_double2(0.0, 0.0);
+    if (H.xstar_law == L1LS_XSTAR_OSGEN3) xf = osgen3_full_pair(H, sg);
+    planted_elem(H, 2 * k, xf.x, xs.x, g.x);
+    planted_elem(H, 2 * k + 1, xf.y, xs.y, g.y);
 }
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
@@ -120,53 +204,119 @@ __device__ __forceinline__ void store_partials(double (&v)[NS], double* __restri
 // IGen steps 3 and 4 on one pair: e = tau Sigma^{-1} G^T g and b = A x* + e,
 // each operation rounded on its own (no fused multiply-add), in the order
 // the definition writes them.
-__device__ __forceinline__ void igen_pair(const SgtK& H, double xi, double xj, double gi, double gj, double& bi,
-                                          double& bj, double& ei, double& ej) {
+__device__ __forceinline__ void igen_pair(const SgtK& H, double2 sg, double2 xs, double2 g, double2& b,
+                                          double2& e) {
 #pragma clang fp contract(off)
-    ei = H.tau * (H.c * gi + H.sn * gj) / H.so;
-    ej = H.tau * (-H.sn * gi + H.c * gj) / H.se;
-    bi = H.so * (H.c * xi + H.sn * xj) + ei;
-    bj = H.se * (-H.sn * xi + H.c * xj) + ej;
+    e.x = H.tau * (H.c * g.x + H.sn * g.y) / sg.x;
+    e.y = H.tau * (-H.sn * g.x + H.c * g.y) / sg.y;
+    b.x = sg.x * (H.c * xs.x + H.sn * xs.y) + e.x;
+    b.y = sg.y * (-H.sn * xs.x + H.c * xs.y) + e.y;
 }
 
-// b for every pair; part = sum e^2
+// b for every pair; part = (sum e^2, sum |x*| | max sigma, max -sigma)
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_generate(SgtK H, double2* __restrict__ b, double* __restrict__ part) {
-    double v[1] = {0.0};
+    double v[4] = {0.0, 0.0, -INFINITY, -INFINITY};
     const int64_t np = H.n / 2;
     for (int64_t k = gtid(); k < np; k += gstride()) {
-        double xi, gi, xj, gj, bi, bj, ei, ej;
-        planted_at(H, 2 * k, xi, gi);
-        planted_at(H, 2 * k + 1, xj, gj);
-        igen_pair(H, xi, xj, gi, gj, bi, bj, ei, ej);
-        b[k] = make_double2(bi, bj);
-        v[0] += ei * ei + ej * ej;
+        const double2 sg = sigma_pair<SL>(H, k);
+        double2 xs, g, bv, e;
+        planted_pair(H, k, sg, xs, g);
+        igen_pair(H, sg, xs, g, bv, e);
+        b[k] = bv;
+        v[0] += e.x * e.x + e.y * e.y;
+        v[1] += fabs(xs.x) + fabs(xs.y);
+        v[2] = fmax(v[2], fmax(sg.x, sg.y));
+        v[3] = fmax(v[3], fmax(-sg.x, -sg.y));
     }
-    store_partials<1, 1>(v, part);
+    store_partials<4, 2>(v, part);
 }
 
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_planted(SgtK H, double* __restrict__ xs, double* __restrict__ g) {
-    for (int64_t i = gtid(); i < H.n; i += gstride()) {
-        double a, b;
-        planted_at(H, i, a, b);
-        if (xs) xs[i] = a;
-        if (g) g[i] = b;
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        double2 a, c;
+        planted_pair(H, k, sigma_pair<SL>(H, k), a, c);
+        if (xs) {
+            xs[2 * k] = a.x;
+            xs[2 * k + 1] = a.y;
+        }
+        if (g) {
+            g[2 * k] = c.x;
+            g[2 * k + 1] = c.y;
+        }
     }
 }
 
 // part = (sum (x - x*)^2, sum x*^2)
-__global__ __launch_bounds__(kHB) void kh_err(SgtK H, const double* __restrict__ x, double* __restrict__ part) {
+template <int SL>
+__global__ __launch_bounds__(kHB) void kh_err(SgtK H, const double2* __restrict__ x, double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
-    for (int64_t i = gtid(); i < H.n; i += gstride()) {
-        double a, b;
-        planted_at(H, i, a, b);
-        const double d = x[i] - a;
-        v[0] += d * d;
-        v[1] += a * a;
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        double2 a, c;
+        planted_pair(H, k, sigma_pair<SL>(H, k), a, c);
+        const double2 xv = x[k];
+        const double di = xv.x - a.x, dj = xv.y - a.y;
+        v[0] += di * di + dj * dj;
+        v[1] += a.x * a.x + a.y * a.y;
     }
     store_partials<2, 2>(v, part);
 }
 
+// kappa_rho of eq. (17) at x = x*: the eigenvectors of A^T A = G Sigma^2 G^T
+// are the columns of G with eigenvalues sigma_i^2, so ||P_rho x||^2 sums
+// (G^T x)_i^2 over sigma_i^2 >= rho.  part = (sum x^2, sum (G^T x)_i^2 [sigma_i^2 >= rho])
+template <int SL>
+__global__ __launch_bounds__(kHB) void kh_kappa(SgtK H, double rho, double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
+        double2 a, c;
+        planted_pair(H, k, sg, a, c);
+        const double ui = H.c * a.x + H.sn * a.y, uj = -H.sn * a.x + H.c * a.y;
+        v[0] += a.x * a.x + a.y * a.y;
+        if (sg.x * sg.x >= rho) v[1] += ui * ui;
+        if (sg.y * sg.y >= rho) v[1] += uj * uj;
+    }
+    store_partials<2, 2>(v, part);
+}
+
+// One radix-select pass over the OsGen3 keys (|x_i| bits, i) before
+// selection.  by_index = 0: count the digit (bits >> shift) & 255 of the
+// elements whose bits match `prefix` under `mask`; by_index = 1: count the
+// digit (i >> shift) & 255 of the elements with bits == value whose index
+// matches prefix under mask.  Block histograms in LDS, then added to hist.
+template <int SL>
+__global__ __launch_bounds__(kHB) void kh_select_hist(SgtK H, int by_index, uint64_t value, uint64_t prefix,
+                                                      uint64_t mask, int shift,
+                                                      unsigned long long* __restrict__ hist) {
+    __shared__ uint32_t lh[kSelBins];
+    for (int q = threadIdx.x; q < kSelBins; q += blockDim.x) lh[q] = 0u;
+    __syncthreads();
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 xf = osgen3_full_pair(H, sigma_pair<SL>(H, k));
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint64_t kb = abs_bits(e ? xf.y : xf.x);
+            const uint64_t idx = (uint64_t)(2 * k + e);
+            if (!by_index) {
+                if ((kb & mask) == prefix) atomicAdd(&lh[(kb >> shift) & 255u], 1u);
+            } else if (kb == value && (idx & mask) == prefix) {
+                atomicAdd(&lh[(idx >> shift) & 255u], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kSelBins; q += blockDim.x)
+        if (lh[q]) atomicAdd(&hist[q], (unsigned long long)lh[q]);
+}
+
 // trans = 0: out (m) = A in (n), rows n..m-1 zero; trans = 1: out (n) = A^T in (top n of m)
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_apply(SgtK H, int64_t m, int trans, const double2* __restrict__ in,
                                                 double2* __restrict__ out) {
     const int64_t np = H.n / 2;
@@ -176,27 +326,30 @@ __global__ __launch_bounds__(kHB) void kh_apply(SgtK H, int64_t m, int trans, co
             out[k] = make_double2(0.0, 0.0);
             continue;
         }
+        const double2 sg = sigma_pair<SL>(H, k);
         const double2 a = in[k];
         double oi, oj;
         if (trans)
-            at_pair(H, a.x, a.y, oi, oj);
+            at_pair(H, sg, a.x, a.y, oi, oj);
         else
-            a_pair(H, a.x, a.y, oi, oj);
+            a_pair(H, sg, a.x, a.y, oi, oj);
         out[k] = make_double2(oi, oj);
     }
 }
 
 // part = (sum |x|, sum r^2, sum b r | max |A^T r|), r = A x - b
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_gap(SgtK H, const double2* __restrict__ x, const double2* __restrict__ b,
                                               double* __restrict__ part) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t np = H.n / 2;
     for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
         const double2 xv = x[k], bv = b[k];
         double yi, yj, gi, gj;
-        a_pair(H, xv.x, xv.y, yi, yj);
+        a_pair(H, sg, xv.x, xv.y, yi, yj);
         const double ri = yi - bv.x, rj = yj - bv.y;
-        at_pair(H, ri, rj, gi, gj);
+        at_pair(H, sg, ri, rj, gi, gj);
         v[0] += fabs(xv.x) + fabs(xv.y);
         v[1] += ri * ri + rj * rj;
         v[2] += bv.x * ri + bv.y * rj;
@@ -205,17 +358,40 @@ __global__ __launch_bounds__(kHB) void kh_gap(SgtK H, const double2* __restrict_
     store_partials<4, 3>(v, part);
 }
 
+// ---- FISTA -------------------------------------------------------------------
+// Iteration k of section 8.1's FISTA on the pair: y = x_{k-1} + beta
+// (x_{k-1} - x_{k-2}), x_k = soft(y - A^T (A y - b) / L, tau / L).  xc holds
+// x_{k-1}; xo holds x_{k-2} on entry and x_k on exit.
+template <int SL>
+__global__ __launch_bounds__(kHB) void kh_fista(SgtK H, const dv2* __restrict__ xc, dv2* __restrict__ xo,
+                                                const dv2* __restrict__ b, double beta, double L, double thr) {
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
+        const dv2 xv = __builtin_nontemporal_load(xc + k), xp = __builtin_nontemporal_load(xo + k);
+        const dv2 bv = __builtin_nontemporal_load(b + k);
+        const dv2 y = xv + beta * (xv - xp);
+        double ri, rj, gi, gj;
+        a_pair(H, sg, y.x, y.y, ri, rj);
+        at_pair(H, sg, ri - bv.x, rj - bv.y, gi, gj);
+        dv2 xn;
+        xn.x = soft_threshold<double>(y.x - gi / L, thr);
+        xn.y = soft_threshold<double>(y.y - gj / L, thr);
+        __builtin_nontemporal_store(xn, xo + k);
+    }
+}
+
 // ---- CG-Newton ---------------------------------------------------------------
 // M = (diag(A^T A) + d)^{-1}, the Jacobi preconditioner, on the pair
-__device__ __forceinline__ dv2 precond(const SgtK& H, dv2 d) {
+__device__ __forceinline__ dv2 precond(double2 cn, dv2 d) {
     dv2 m;
-    m.x = 1.0 / (H.cn0 + d.x);
-    m.y = 1.0 / (H.cn1 + d.y);
+    m.x = 1.0 / (cn.x + d.x);
+    m.y = 1.0 / (cn.y + d.y);
     return m;
 }
 
-__device__ __forceinline__ dv2 hess_v(const SgtK& H, dv2 p, dv2 d) {
-    const double2 h = hess_pair(H, make_double2(p.x, p.y), make_double2(d.x, d.y));
+__device__ __forceinline__ dv2 hess_v(const SgtK& H, double2 sg, dv2 p, dv2 d) {
+    const double2 h = hess_pair(H, sg, make_double2(p.x, p.y), make_double2(d.x, d.y));
     dv2 o;
     o.x = h.x;
     o.y = h.y;
@@ -226,6 +402,7 @@ __device__ __forceinline__ dv2 hess_v(const SgtK& H, dv2 p, dv2 d) {
 // Hessian diagonal d (primal: tau mu^2 / w^3; primal-dual: tau (1 - x gd / w) / w),
 // and PCG's start from dx = 0: r = -grad, u = M r.
 // part = (r.u, u.Hu, r.r | max |grad|).
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const double2* __restrict__ x,
                                                 const double2* __restrict__ gd, const double2* __restrict__ b,
                                                 double mu, int primal, double2* __restrict__ d,
@@ -233,11 +410,12 @@ __global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const double2* __restric
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t np = H.n / 2;
     for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
         const double2 xv = x[k], bv = b[k];
         const double2 gv = primal ? make_double2(0.0, 0.0) : gd[k];
         double yi, yj, ai, aj;
-        a_pair(H, xv.x, xv.y, yi, yj);
-        at_pair(H, yi - bv.x, yj - bv.y, ai, aj);
+        a_pair(H, sg, xv.x, xv.y, yi, yj);
+        at_pair(H, sg, yi - bv.x, yj - bv.y, ai, aj);
         const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
         const double gri = H.tau * xv.x / wi + ai, grj = H.tau * xv.y / wj + aj;
         dv2 dv, rv;
@@ -250,8 +428,8 @@ __global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const double2* __restric
         }
         rv.x = -gri;
         rv.y = -grj;
-        const dv2 u = precond(H, dv) * rv;
-        const dv2 w = hess_v(H, u, dv);
+        const dv2 u = precond(colnorm_pair<SL>(H, sg), dv) * rv;
+        const dv2 w = hess_v(H, sg, u, dv);
         d[k] = make_double2(dv.x, dv.y);
         r[k] = make_double2(rv.x, rv.y);
         v[0] += rv.x * u.x + rv.y * u.y;
@@ -307,7 +485,7 @@ __device__ __forceinline__ void st2(dv2 v, dv2* p) {
 // then for the next iteration u = M r, w = H u; part = (r.u, w.u, r.r).
 // first: p and dx are not read (beta = 0, dx = 0).  U pairs per thread per
 // trip (loads issued together), NT: nontemporal accesses.
-template <int U, bool NT>
+template <int SL, int U, bool NT>
 __global__ __launch_bounds__(kHB) void kh_cg_iter(SgtK H, dv2* __restrict__ dx, dv2* __restrict__ r,
                                                   dv2* __restrict__ p, const dv2* __restrict__ d, int first,
                                                   const HCg* __restrict__ cs, double* __restrict__ part) {
@@ -334,14 +512,15 @@ __global__ __launch_bounds__(kHB) void kh_cg_iter(SgtK H, dv2* __restrict__ dx, 
         for (int q = 0; q < U; ++q) {
             const int64_t k = base + q * S;
             if (k < np) {
-                const dv2 mq = precond(H, D[q]);
+                const double2 sg = sigma_pair<SL>(H, k);
+                const dv2 mq = precond(colnorm_pair<SL>(H, sg), D[q]);
                 const dv2 u0 = mq * R[q];
                 const dv2 pv = first ? u0 : u0 + be * P[q];
-                const dv2 sv = hess_v(H, pv, D[q]);
+                const dv2 sv = hess_v(H, sg, pv, D[q]);
                 const dv2 xo = first ? a * pv : X[q] + a * pv;
                 const dv2 rn = R[q] - a * sv;
                 const dv2 u1 = mq * rn;
-                const dv2 w1 = hess_v(H, u1, D[q]);
+                const dv2 w1 = hess_v(H, sg, u1, D[q]);
                 st2<NT>(pv, p + k);
                 st2<NT>(xo, dx + k);
                 st2<NT>(rn, r + k);
@@ -386,6 +565,7 @@ __global__ __launch_bounds__(1024) void kh_cg_next(const double* __restrict__ pa
 // Line search terms at x along dx, for the step lengths a0 2^-t, t < kLsBatch:
 // part = (sum psi(x), sum r(x)^2, grad . dx, sum psi(x + a_t dx) [t], sum r(x + a_t dx)^2 [t])
 // with psi(v) = sqrt(mu^2 + v^2) - mu and r(v) = A v - b.
+template <int SL>
 __global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const double2* __restrict__ x, const double2* __restrict__ dx,
                                              const double2* __restrict__ b, double mu, double a0,
                                              double* __restrict__ part) {
@@ -394,11 +574,12 @@ __global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const double2* __restrict__
     for (int q = 0; q < kLsStats; ++q) v[q] = 0.0;
     const int64_t np = H.n / 2;
     for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
         const double2 xv = x[k], sv = dx[k], bv = b[k];
         double yi, yj, ai, aj;
-        a_pair(H, xv.x, xv.y, yi, yj);
+        a_pair(H, sg, xv.x, xv.y, yi, yj);
         const double ri = yi - bv.x, rj = yj - bv.y;
-        at_pair(H, ri, rj, ai, aj);
+        at_pair(H, sg, ri, rj, ai, aj);
         const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
         v[0] += (wi - mu) + (wj - mu);
         v[1] += ri * ri + rj * rj;
@@ -408,7 +589,7 @@ __global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const double2* __restrict__
         for (int t = 0; t < kLsBatch; ++t) {
             const double ui = xv.x + a * sv.x, uj = xv.y + a * sv.y;
             double qi, qj;
-            a_pair(H, ui, uj, qi, qj);
+            a_pair(H, sg, ui, uj, qi, qj);
             qi -= bv.x;
             qj -= bv.y;
             v[3 + t] += (sqrt(mu * mu + ui * ui) - mu) + (sqrt(mu * mu + uj * uj) - mu);
@@ -448,18 +629,29 @@ int blocks_for(int64_t pairs) {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 bool is_fin(double v) { return std::isfinite(v); }
 
+// Run f(std::integral_constant<int, SL>) for the instance's sigma law.
+template <typename F>
+void by_law(int law, F&& f) {
+    if (law == L1LS_SIGMA_UNIFORM)
+        f(std::integral_constant<int, 1>{});
+    else
+        f(std::integral_constant<int, 0>{});
+}
+
 }  // namespace
 
 struct l1ls_sgt {
     l1ls_sgt_params prm;
     SgtK k;
-    double L = 0, fstar = 0;
+    double L = 0, fstar = 0, sigma_min = 0, sigma_max = 0;
     int device = 0;
     double* b = nullptr;  // n: the top n entries of b (rows n..m-1 of b are zero)
     double* part = nullptr;
+    unsigned long long* hist = nullptr;  // radix-select histogram
     DevArena arena;
     // HIP-event times of the last solve with opts.time_kernels set:
-    // [0] PCG iteration pass, [1] line-search pass, [2] Newton setup pass
+    // [0] PCG iteration pass (CG-Newton) or iteration pass (FISTA),
+    // [1] line-search pass (CG-Newton) or gap pass (FISTA), [2] Newton setup pass
     mutable double kt_ms[3] = {0, 0, 0};
     mutable int64_t kt_calls[3] = {0, 0, 0};
     ~l1ls_sgt() { arena.release(); }
@@ -473,7 +665,7 @@ l1ls_status host_stats(const double* part, int ns, int nsum, int nb, hipStream_t
     std::vector<double> h((size_t)ns * nb);
     HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int q = 0; q < ns; ++q) out[q] = 0.0;
+    for (int q = 0; q < ns; ++q) out[q] = q < nsum ? 0.0 : -INFINITY;
     for (int bk = 0; bk < nb; ++bk)
         for (int q = 0; q < ns; ++q) {
             const double v = h[(size_t)ns * bk + q];
@@ -483,13 +675,16 @@ l1ls_status host_stats(const double* part, int ns, int nsum, int nb, hipStream_t
 }
 
 l1ls_status sgt_gap(const l1ls_sgt* H, double tau, const double* x, hipStream_t s, double* P, double* D,
-                     double* gap) {
+                    double* gap, double* part) {
     const int nb = blocks_for(H->k.n / 2);
     SgtK K = H->k;
-    hipLaunchKernelGGL(kh_gap, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)H->b, H->part);
+    by_law(K.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_gap<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
+                           (const double2*)H->b, part);
+    });
     HIP_TRY(hipGetLastError());
     double t[4];
-    L1LS_TRY(host_stats(H->part, 4, 3, nb, s, t));
+    L1LS_TRY(host_stats(part, 4, 3, nb, s, t));
     *P = tau * t[0] + 0.5 * t[1];
     const double theta = (t[3] <= tau) ? 1.0 : tau / t[3];
     *D = -0.5 * theta * theta * t[1] - theta * t[2];
@@ -498,14 +693,87 @@ l1ls_status sgt_gap(const l1ls_sgt* H, double tau, const double* x, hipStream_t 
     return L1LS_OK;
 }
 
-l1ls_status sgt_err(const l1ls_sgt* H, const double* x, hipStream_t s, double* out) {
+l1ls_status sgt_err(const l1ls_sgt* H, const double* x, hipStream_t s, double* out, double* part) {
     const int nb = blocks_for(H->k.n / 2);
-    hipLaunchKernelGGL(kh_err, dim3(nb), dim3(kHB), 0, s, H->k, x, H->part);
+    by_law(H->k.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_err<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, H->k, (const double2*)x, part);
+    });
     HIP_TRY(hipGetLastError());
     double t[2];
-    L1LS_TRY(host_stats(H->part, 2, 2, nb, s, t));
+    L1LS_TRY(host_stats(part, 2, 2, nb, s, t));
     *out = (t[1] > 0) ? std::sqrt(t[0] / t[1]) : std::sqrt(t[0]);
     return L1LS_OK;
+}
+
+// The element of rank `rank` (1-based) in the order (|x_i|, i) of OsGen3's
+// unselected x: 8 passes over the magnitude bits, then 4 over the index bits
+// of the elements with that magnitude.
+l1ls_status osgen3_select(l1ls_sgt* H, int64_t rank, hipStream_t s, uint64_t* bits_out, int64_t* idx_out) {
+    const int nb = blocks_for(H->k.n / 2);
+    unsigned long long h[kSelBins];
+    auto pass = [&](int by_index, uint64_t value, uint64_t prefix, uint64_t mask, int shift) -> l1ls_status {
+        HIP_TRY(hipMemsetAsync(H->hist, 0, sizeof(h), s));
+        by_law(H->k.sigma_law, [&](auto c) {
+            hipLaunchKernelGGL(kh_select_hist<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, H->k, by_index,
+                               value, prefix, mask, shift, H->hist);
+        });
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h, H->hist, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return L1LS_OK;
+    };
+    // rank within the current bucket, walked digit by digit from the top
+    auto descend = [&](uint64_t& prefix, uint64_t& mask, int shift, int64_t& left) -> l1ls_status {
+        int d = 0;
+        for (; d < kSelBins; ++d) {
+            if (left <= (int64_t)h[d]) break;
+            left -= (int64_t)h[d];
+        }
+        if (d == kSelBins) return L1LS_E_STATE;  // counts disagree with the rank
+        prefix |= (uint64_t)d << shift;
+        mask |= (uint64_t)0xff << shift;
+        return L1LS_OK;
+    };
+    int64_t left = rank;
+    uint64_t prefix = 0, mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        L1LS_TRY(pass(0, 0, prefix, mask, shift));
+        L1LS_TRY(descend(prefix, mask, shift, left));
+    }
+    const uint64_t value = prefix;
+    uint64_t ip = 0, im = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        L1LS_TRY(pass(1, value, ip, im, shift));
+        L1LS_TRY(descend(ip, im, shift, left));
+    }
+    *bits_out = value;
+    *idx_out = (int64_t)ip;
+    return L1LS_OK;
+}
+
+bool valid_params(const l1ls_sgt_params* p) {
+    const int64_t n = p->n, m = p->m;
+    if (n < 2 || n % 2 || n > kSgtMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return false;
+    if (!(p->tau > 0) || !is_fin(p->tau) || !is_fin(p->theta)) return false;
+    if (p->sigma_law == L1LS_SIGMA_ALTERNATING) {
+        if (!(p->sigma_odd > 0) || !(p->sigma_even > 0) || !is_fin(p->sigma_odd) || !is_fin(p->sigma_even))
+            return false;
+    } else if (p->sigma_law == L1LS_SIGMA_UNIFORM) {
+        if (!(p->sigma_scale >= 0) || !(p->sigma_shift > 0) || !is_fin(p->sigma_scale) || !is_fin(p->sigma_shift))
+            return false;
+    } else {
+        return false;
+    }
+    if (p->xstar_law == L1LS_XSTAR_TABLE1) {
+        if (!is_fin(p->x_neg) || !is_fin(p->x_pos)) return false;
+    } else if (p->xstar_law == L1LS_XSTAR_OSGEN) {
+        if (!(p->gamma > 0) || !is_fin(p->gamma)) return false;
+    } else if (p->xstar_law == L1LS_XSTAR_OSGEN3) {
+        if (!(p->gamma > 0) || !is_fin(p->gamma) || p->s1 < 0 || p->s2 < 0 || p->s1 + p->s2 != p->s) return false;
+    } else {
+        return false;
+    }
+    return true;
 }
 
 }  // namespace
@@ -523,11 +791,18 @@ extern "C" void l1ls_sgt_params_default(int64_t n, uint64_t seed, l1ls_sgt_param
     p->x_pos = 0.1;
     p->tau = 1.0;
     p->seed = seed;
+    p->sigma_law = L1LS_SIGMA_ALTERNATING;
+    p->sigma_scale = 1.0;
+    p->sigma_shift = 0.1;
+    p->xstar_law = L1LS_XSTAR_TABLE1;
+    p->gamma = 1.0;
+    p->s1 = p->s / 2;
+    p->s2 = p->s - p->s1;
 }
 
 extern "C" size_t l1ls_sgt_bytes(int64_t n) {
     if (n < 2) return 0;
-    return (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 4096;
+    return (size_t)n * sizeof(double) + (size_t)kHMaxBlocks * kLsStats * sizeof(double) + 8192;
 }
 
 extern "C" size_t l1ls_sgt_solve_bytes(int64_t n) {
@@ -538,29 +813,33 @@ extern "C" size_t l1ls_sgt_solve_bytes(int64_t n) {
 extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream, l1ls_sgt** out) {
     if (!p || !out) return L1LS_E_ARG;
     *out = nullptr;
-    const int64_t n = p->n, m = p->m;
-    if (n < 2 || n % 2 || n > kSgtMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return L1LS_E_ARG;
-    if (!(p->sigma_odd > 0) || !(p->sigma_even > 0) || !(p->tau > 0) || !is_fin(p->sigma_odd) ||
-        !is_fin(p->sigma_even) || !is_fin(p->tau) || !is_fin(p->theta) || !is_fin(p->x_neg) || !is_fin(p->x_pos))
-        return L1LS_E_ARG;
+    if (!valid_params(p)) return L1LS_E_ARG;
+    const int64_t n = p->n;
     hipStream_t s = (hipStream_t)stream;
     auto* H = new (std::nothrow) l1ls_sgt();
     if (!H) return L1LS_E_NOMEM;
     H->prm = *p;
     SgtK& K = H->k;
+    std::memset(&K, 0, sizeof(K));
     K.n = n;
     K.s = p->s;
+    K.s1 = p->s1;
+    K.s2 = p->s2;
+    K.sigma_law = p->sigma_law;
+    K.xstar_law = p->xstar_law;
     K.c = std::cos(p->theta);
     K.sn = std::sin(p->theta);
     K.so = p->sigma_odd;
     K.se = p->sigma_even;
     K.cn0 = K.so * K.so * K.c * K.c + K.se * K.se * K.sn * K.sn;
     K.cn1 = K.so * K.so * K.sn * K.sn + K.se * K.se * K.c * K.c;
+    K.scale = p->sigma_scale;
+    K.shift = p->sigma_shift;
     K.tau = p->tau;
     K.xneg = p->x_neg;
     K.xpos = p->x_pos;
+    K.gamma = p->gamma;
     K.key = seed_key(p->seed);
-    H->L = std::max(K.so * K.so, K.se * K.se);
     auto fail = [&](l1ls_status st) {
         (void)hipStreamSynchronize(s);
         delete H;
@@ -569,16 +848,38 @@ extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream,
     if (hipGetDevice(&H->device) != hipSuccess) return fail(L1LS_E_HIP);
     l1ls_status st = H->arena.alloc(&H->b, (size_t)n);
     if (st == L1LS_OK) st = H->arena.alloc(&H->part, (size_t)kHMaxBlocks * kLsStats);
+    if (st == L1LS_OK) st = H->arena.alloc(&H->hist, (size_t)kSelBins);
     if (st != L1LS_OK) return fail(st);
+    if (K.xstar_law == L1LS_XSTAR_OSGEN3) {
+        // the s1 smallest: up to rank s1; the s2 largest: from rank n - s2 + 1
+        if (K.s1 > 0) {
+            st = osgen3_select(H, K.s1, s, &K.t1_bits, &K.t1_idx);
+            K.has1 = 1;
+        }
+        if (st == L1LS_OK && K.s2 > 0) {
+            st = osgen3_select(H, n - K.s2 + 1, s, &K.t2_bits, &K.t2_idx);
+            K.has2 = 1;
+        }
+        if (st != L1LS_OK) return fail(st);
+    }
     const int nb = blocks_for(n / 2);
-    hipLaunchKernelGGL(kh_generate, dim3(nb), dim3(kHB), 0, s, K, (double2*)H->b, H->part);
+    by_law(K.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_generate<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (double2*)H->b, H->part);
+    });
     if (hipGetLastError() != hipSuccess) return fail(L1LS_E_HIP);
-    double e2 = 0;
-    st = host_stats(H->part, 1, 1, nb, s, &e2);
+    double t[4] = {0, 0, 0, 0};
+    st = host_stats(H->part, 4, 2, nb, s, t);
     if (st != L1LS_OK) return fail(st);
-    // f* = tau ||x*||_1 + 0.5 ||e||^2 with floor(s/2) entries x_neg, the rest x_pos
-    const int64_t nneg = p->s / 2, npos = p->s - nneg;
-    H->fstar = p->tau * ((double)nneg * std::fabs(p->x_neg) + (double)npos * std::fabs(p->x_pos)) + 0.5 * e2;
+    H->sigma_max = t[2];
+    H->sigma_min = -t[3];
+    H->L = H->sigma_max * H->sigma_max;
+    // f* = tau ||x*||_1 + 0.5 ||e||^2; Table 1's ||x*||_1 in closed form
+    double l1 = t[1];
+    if (K.xstar_law == L1LS_XSTAR_TABLE1) {
+        const int64_t nneg = p->s / 2, npos = p->s - nneg;
+        l1 = (double)nneg * std::fabs(p->x_neg) + (double)npos * std::fabs(p->x_pos);
+    }
+    H->fstar = p->tau * l1 + 0.5 * t[0];
     *out = H;
     return L1LS_OK;
 }
@@ -592,6 +893,8 @@ extern "C" l1ls_status l1ls_sgt_describe(const l1ls_sgt* H, l1ls_sgt_desc* out) 
     out->c = H->k.c;
     out->s_rot = H->k.sn;
     out->b_dev = H->b;
+    out->sigma_min = H->sigma_min;
+    out->sigma_max = H->sigma_max;
     return L1LS_OK;
 }
 
@@ -607,29 +910,156 @@ extern "C" void l1ls_sgt_free(l1ls_sgt* H) {
 
 extern "C" l1ls_status l1ls_sgt_planted(const l1ls_sgt* H, double* x_star_dev, double* g_dev, void* stream) {
     if (!H || (!x_star_dev && !g_dev)) return L1LS_E_ARG;
-    hipLaunchKernelGGL(kh_planted, dim3(blocks_for(H->k.n / 2)), dim3(kHB), 0, (hipStream_t)stream, H->k,
-                       x_star_dev, g_dev);
+    by_law(H->k.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_planted<decltype(c)::value>, dim3(blocks_for(H->k.n / 2)), dim3(kHB), 0,
+                           (hipStream_t)stream, H->k, x_star_dev, g_dev);
+    });
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
 }
 
 extern "C" l1ls_status l1ls_sgt_apply(const l1ls_sgt* H, int32_t trans, const double* in_dev, double* out_dev,
-                                       void* stream) {
+                                      void* stream) {
     if (!H || !in_dev || !out_dev || (trans != 0 && trans != 1)) return L1LS_E_ARG;
     if (!aligned16(in_dev) || !aligned16(out_dev)) return L1LS_E_ARG;
     const int64_t m = H->prm.m;
     const int nb = blocks_for(trans ? H->k.n / 2 : m / 2);
-    hipLaunchKernelGGL(kh_apply, dim3(nb), dim3(kHB), 0, (hipStream_t)stream, H->k, m, (int)trans,
-                       (const double2*)in_dev, (double2*)out_dev);
+    by_law(H->k.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_apply<decltype(c)::value>, dim3(nb), dim3(kHB), 0, (hipStream_t)stream, H->k, m,
+                           (int)trans, (const double2*)in_dev, (double2*)out_dev);
+    });
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
 }
 
 extern "C" l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* H, double tau, const double* x_dev, double* P,
-                                               double* D, double* gap, void* stream) {
+                                              double* D, double* gap, void* stream) {
     if (!H || !x_dev || !P || !D || !gap || !(tau > 0) || !is_fin(tau)) return L1LS_E_ARG;
     if (!aligned16(x_dev)) return L1LS_E_ARG;
-    return sgt_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap);
+    return sgt_gap(H, tau, x_dev, (hipStream_t)stream, P, D, gap, H->part);
+}
+
+extern "C" l1ls_status l1ls_sgt_kappa_rho(const l1ls_sgt* H, double rho, double* kappa, void* stream) {
+    if (!H || !kappa || !(rho >= 0) || !is_fin(rho)) return L1LS_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = blocks_for(H->k.n / 2);
+    by_law(H->k.sigma_law, [&](auto c) {
+        hipLaunchKernelGGL(kh_kappa<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, H->k, rho, H->part);
+    });
+    HIP_TRY(hipGetLastError());
+    double t[2];
+    L1LS_TRY(host_stats(H->part, 2, 2, nb, s, t));
+    *kappa = (t[1] > 0) ? std::sqrt(t[0] / t[1]) : INFINITY;
+    return L1LS_OK;
+}
+
+namespace {
+
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, without contraction
+double next_t_sgt(double t) {
+#pragma clang fp contract(off)
+    return (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+}
+
+}  // namespace
+
+extern "C" l1ls_status l1ls_sgt_solve_fista(const l1ls_sgt* H, const l1ls_solve_opts* o, double* x,
+                                            l1ls_report* rep) {
+    if (!H || !o || !x) return L1LS_E_ARG;
+    if (o->max_iter < 0 || !aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
+    if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o->stream;
+    const double tau = o->tau > 0 ? o->tau : H->prm.tau;
+    const double L = o->L > 0 ? o->L : H->L;
+    const int check = std::max(1, o->check_every);
+    if (!is_fin(tau) || !is_fin(L) || !(L > 0)) return L1LS_E_ARG;
+    SgtK K = H->k;
+    K.tau = tau;
+    const int64_t n = K.n;
+    const int nb = blocks_for(n / 2);
+    const bool tk = o->time_kernels != 0;
+    DevArena W;
+    double *xb = nullptr, *part = nullptr;
+    std::vector<hipEvent_t> ev;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        W.release();
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    };
+    auto run = [&]() -> l1ls_status {
+        L1LS_TRY(W.alloc(&xb, (size_t)n));
+        L1LS_TRY(W.alloc(&part, (size_t)kHMaxBlocks * 4));
+        if (tk) {
+            for (int q = 0; q < 3; ++q) {
+                H->kt_ms[q] = 0;
+                H->kt_calls[q] = 0;
+            }
+            ev.resize(2 * (size_t)check + 2);
+            for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+        }
+        auto elapsed = [&](int a, int b) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+            return (double)ms;
+        };
+        if (o->x0_dev) {
+            if (o->x0_dev != x) HIP_TRY(hipMemcpyAsync(x, o->x0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, x, n);
+        }
+        // x_{-1} = x_0: the first step's momentum term is 0 (beta_0 = 0)
+        HIP_TRY(hipMemcpyAsync(xb, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double* cur = x;   // x_{k-1}
+        double* old = xb;  // x_{k-2}, receives x_k
+        double t = 1.0, beta = 0.0, P = 0, D = 0, gap = INFINITY;
+        int64_t k = 0;
+        bool stop = false;
+        while (k < o->max_iter && !stop) {
+            const int64_t batch = std::min<int64_t>(check - (k % check), o->max_iter - k);
+            for (int64_t q = 0; q < batch; ++q) {
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
+                by_law(K.sigma_law, [&](auto c) {
+                    hipLaunchKernelGGL(kh_fista<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const dv2*)cur,
+                                       (dv2*)old, (const dv2*)H->b, beta, L, tau / L);
+                });
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
+                const double t_next = next_t_sgt(t);
+                beta = (t - 1.0) / t_next;
+                t = t_next;
+                std::swap(cur, old);
+                ++k;
+            }
+            HIP_TRY(hipGetLastError());
+            if (tk) HIP_TRY(hipEventRecord(ev[2 * check], s));
+            L1LS_TRY(sgt_gap(H, tau, cur, s, &P, &D, &gap, part));
+            if (tk) {
+                HIP_TRY(hipEventRecord(ev[2 * check + 1], s));
+                HIP_TRY(hipEventSynchronize(ev[2 * check + 1]));
+                for (int64_t q = 0; q < batch; ++q) H->kt_ms[0] += elapsed((int)(2 * q), (int)(2 * q + 1));
+                H->kt_calls[0] += batch;
+                H->kt_ms[1] += elapsed(2 * check, 2 * check + 1);
+                H->kt_calls[1] += 1;
+            }
+            if ((o->rel_gap_tol > 0 && gap <= o->rel_gap_tol) || (o->f_target > 0 && P <= o->f_target)) stop = true;
+        }
+        if (cur != x) HIP_TRY(hipMemcpyAsync(x, cur, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (k == 0) L1LS_TRY(sgt_gap(H, tau, x, s, &P, &D, &gap, part));
+        l1ls_report rr;
+        std::memset(&rr, 0, sizeof(rr));
+        rr.iterations = k;
+        rr.primal = P;
+        rr.dual = D;
+        rr.rel_gap = gap;
+        L1LS_TRY(sgt_err(H, x, s, &rr.rel_err, part));
+        rr.converged = stop ? 1 : 0;
+        rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = rr;
+        return stop ? L1LS_OK : L1LS_NOT_CONVERGED;
+    };
+    const l1ls_status st = run();
+    cleanup();
+    return st;
 }
 
 // CG-Newton state between l1ls_sgt_newton_step calls: the iterate x (the
@@ -713,8 +1143,10 @@ struct l1ls_sgt_newton {
             const int skip = first;  // the first iteration reads no p, dx: not timed
             for (int q = 0; q < kBatch; ++q) {
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
-                hipLaunchKernelGGL((kh_cg_iter<kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K, (dv2*)dx, (dv2*)r,
-                                   (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
+                by_law(K.sigma_law, [&](auto c) {
+                    hipLaunchKernelGGL((kh_cg_iter<decltype(c)::value, kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K,
+                                       (dv2*)dx, (dv2*)r, (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
+                });
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
                 hipLaunchKernelGGL(kh_cg_next, dim3(1), dim3(1024), 0, s, part, nb, cs, pcgmax);
                 first = 0;
@@ -741,8 +1173,10 @@ struct l1ls_sgt_newton {
         for (int t0b = 0; t0b < maxbt && !found; t0b += kLsBatch) {
             const double a0 = std::ldexp(1.0, -t0b);
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
-            hipLaunchKernelGGL(kh_ls, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)dx,
-                               (const double2*)H->b, mu, a0, part);
+            by_law(K.sigma_law, [&](auto c) {
+                hipLaunchKernelGGL(kh_ls<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
+                                   (const double2*)dx, (const double2*)H->b, mu, a0, part);
+            });
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
             HIP_TRY(hipGetLastError());
             double t[kLsStats];
@@ -771,8 +1205,11 @@ struct l1ls_sgt_newton {
     l1ls_status steps(int64_t k) {
         for (int64_t q = 0; q < k && !converged; ++q) {
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
-            hipLaunchKernelGGL(kh_setup, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x, (const double2*)gd,
-                               (const double2*)H->b, mu, primal, (double2*)d, (double2*)r, part);
+            by_law(K.sigma_law, [&](auto c) {
+                hipLaunchKernelGGL(kh_setup<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
+                                   (const double2*)gd, (const double2*)H->b, mu, primal, (double2*)d, (double2*)r,
+                                   part);
+            });
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
             hipLaunchKernelGGL(kh_cg_init, dim3(1), dim3(1024), 0, s, part, nb, cs, prtol, pcgmax);
             HIP_TRY(hipGetLastError());
@@ -806,8 +1243,8 @@ struct l1ls_sgt_newton {
         std::memset(&rr, 0, sizeof(rr));
         rr.iterations = newton;
         rr.inner = pcg_total;
-        L1LS_TRY(sgt_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap));
-        L1LS_TRY(sgt_err(H, x, s, &rr.rel_err));
+        L1LS_TRY(sgt_gap(H, tau, x, s, &rr.primal, &rr.dual, &rr.rel_gap, part));
+        L1LS_TRY(sgt_err(H, x, s, &rr.rel_err, part));
         rr.converged = converged ? 1 : 0;
         rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (out) *out = rr;

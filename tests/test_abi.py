@@ -145,3 +145,12 @@ def test_sgt_null_arguments():
     assert lib.l1ls_sgt_newton_step(None, 1, None) == -1
     lib.l1ls_sgt_newton_destroy(None)
     lib.l1ls_sgt_free(None)
+
+
+def test_law_validation():
+    for kw in (dict(sigma_law=2), dict(xstar_law=3), dict(sigma_law=L.SIGMA_UNIFORM, sigma_shift=0.0),
+               dict(xstar_law=L.XSTAR_OSGEN, gamma=0.0), dict(xstar_law=L.XSTAR_OSGEN3, s1=3, s2=3),
+               dict(sigma_law=L.SIGMA_UNIFORM, sigma_scale=-1.0)):
+        p = L.sgt_params(64, 1, s=4, **kw)
+        h = ctypes.c_void_p()
+        assert L.lib().l1ls_sgt_generate(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
