@@ -222,3 +222,39 @@ def b_at_pairs(n, s, seed, pairs, theta=2.0 * math.pi / 3.0, sigma_odd=0.1, sigm
     bi = sigma_odd * (c * xi + sn * xj) + ei
     bj = sigma_even * (-sn * xi + c * xj) + ej
     return bi, bj
+
+
+TAG_PCDM = 0x600
+
+
+def pcdm(I, tau, iters, p=1.0, x0=None, omega=2):
+    """PCDM (section 8.1 item PCDM, section 8.3) on an SgtInstance.
+
+    Step k updates, in parallel and from the same x, every coordinate i of
+    the sampled set S_k: x_i <- soft(x_i - A_i^T (A x - b) / (beta L_i),
+    tau / (beta L_i)), L_i = (A^T A)_ii.  S_k holds each coordinate
+    independently with probability p (a doubly uniform sampling); for it
+    beta = 1 + (omega - 1) (E|S|^2 / E|S| - 1) / (n - 1) = 1 + (omega - 1) p,
+    omega the largest number of nonzeros in a row of A (2 in this class).
+    Coordinate 2k + e is in S_j when word e of Philox counter (k, j, 0x600, 0)
+    is below p 2^32 (every coordinate when p >= 1).
+    """
+    n = I.n
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    beta = 1.0 + (omega - 1) * min(p, 1.0)
+    v = beta * I.colnorm2()
+    key = seed_key(I.seed)
+    thr = min(int(p * 4294967296.0), 4294967296)
+    for step in range(iters):
+        g = I.rmatvec(I.matvec(x) - I.b)
+        z = x - g / v
+        upd = np.sign(z) * np.maximum(np.abs(z) - tau / v, 0.0)
+        if p >= 1.0:
+            x = upd
+        else:
+            w0, w1, _, _ = philox4x32_10(np.arange(n // 2), step, TAG_PCDM, 0, key)
+            take = np.empty(n, dtype=bool)
+            take[0::2] = w0 < thr
+            take[1::2] = w1 < thr
+            x = np.where(take, upd, x)
+    return x

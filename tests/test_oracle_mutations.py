@@ -155,3 +155,15 @@ def test_sgt_swapped_support_values_are_caught(monkeypatch):
     monkeypatch.setattr(OH.SgtInstance, "__init__", init_wrong)
     with pytest.raises(AssertionError):
         hpins.test_support_values_and_subgradient(130, 9)   # odd s: floor(s/2) != s - floor(s/2)
+
+
+def test_pcdm_beta_without_overlap_term_is_caught(monkeypatch):
+    # beta = 1 (omega - 1 dropped) for fully parallel updates: the Jacobi step
+    # with L_i overshoots on coupled pairs
+    orig = OH.pcdm
+
+    def pcdm_wrong(I, tau, iters, p=1.0, x0=None, omega=2):
+        return orig(I, tau, iters, p=p, x0=x0, omega=1)
+    monkeypatch.setattr(OH, "pcdm", pcdm_wrong)
+    with pytest.raises(AssertionError):
+        hpins.test_pcdm_single_coordinate_step_is_exact_minimisation()
