@@ -172,8 +172,10 @@ typedef struct {
     /* Batch only: rounds of 4 tiles per workgroup task; 0: chosen per slot
      * size by the library's autotuner (timed on a slot's first pass). */
     int32_t tile_chunk;
-    /* l1ls_sgt_solve_fista only: stop once f_tau(x_k) <= f_target (0: off). */
+    /* l1ls_sgt_solve_fista / _pcdm only: stop once f_tau(x_k) <= f_target (0: off). */
     double f_target;
+    /* l1ls_sgt_solve_pcdm only: probability that a coordinate is updated in a step (<= 0: 1). */
+    double pcdm_p;
 } l1ls_solve_opts;
 
 typedef struct {
@@ -494,6 +496,20 @@ l1ls_status l1ls_sgt_solve_cg_newton(const l1ls_sgt* inst, const l1ls_solve_opts
 l1ls_status l1ls_sgt_solve_fista(const l1ls_sgt* inst, const l1ls_solve_opts* opts, double* x_dev,
                                  l1ls_report* report);
 
+/*
+ * PCDM (section 8.1 item PCDM, section 8.3) on the instance, FP64, from
+ * opts.x0_dev (NULL: 0): step k updates, in parallel and from the same x,
+ * every coordinate i of the sampled set S_k to soft(x_i - A_i^T (A x - b) /
+ * (beta L_i), tau / (beta L_i)), L_i = (A^T A)_ii.  S_k holds each coordinate
+ * independently with probability p = opts.pcdm_p (<= 0 or >= 1: every
+ * coordinate), drawn from Philox counter (pair, step, 0x600, 0); for this
+ * doubly uniform sampling beta = 1 + (omega - 1) p with omega = 2 nonzeros per
+ * row.  Stops as l1ls_sgt_solve_fista (gap tolerance, f_target, max_iter
+ * steps < 2^32).  No extra device memory beyond O(1).
+ */
+l1ls_status l1ls_sgt_solve_pcdm(const l1ls_sgt* inst, const l1ls_solve_opts* opts, double* x_dev,
+                                l1ls_report* report);
+
 /* The same CG-Newton one call at a time, for callers that report between
  * Newton steps.  create: validates opts as l1ls_sgt_solve_cg_newton (max_iter
  * is not used), allocates l1ls_sgt_solve_bytes(n), sets x_dev to the start;
@@ -512,7 +528,8 @@ void l1ls_sgt_newton_destroy(l1ls_sgt_newton* newton);
  * calls[q] launches of q = 0 the PCG iteration pass (p, dx, r; the first
  * iteration of each PCG, which reads neither p nor dx, is left out), 1 the
  * line-search pass, 2 the Newton setup pass (gradient, d, PCG start); after
- * l1ls_sgt_solve_fista: 0 the iteration pass, 1 the gap pass. */
+ * l1ls_sgt_solve_fista: 0 the iteration pass, 1 the gap pass; after
+ * l1ls_sgt_solve_pcdm: 0 the step pass. */
 l1ls_status l1ls_sgt_kernel_times(const l1ls_sgt* inst, double* ms, int64_t* calls);
 
 const char* l1ls_status_string(int32_t status);

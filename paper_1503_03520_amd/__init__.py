@@ -63,7 +63,7 @@ class SolveOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("time_kernels", ctypes.c_int32),
         ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
         ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
-        ("f_target", ctypes.c_double),
+        ("f_target", ctypes.c_double), ("pcdm_p", ctypes.c_double),
     ]
 
 
@@ -167,6 +167,7 @@ _SIGS = {
     "l1ls_sgt_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_sgt_kappa_rho": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P]),
     "l1ls_sgt_solve_fista": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_sgt_solve_pcdm": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_sgt_newton_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
     "l1ls_sgt_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
     "l1ls_sgt_newton_destroy": (None, [_P]),
@@ -600,6 +601,16 @@ class SgtInstance:
         rep = Report()
         st = _check(lib().l1ls_sgt_solve_fista(self._h, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)),
                     "l1ls_sgt_solve_fista", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
+        return x_out, rep.as_dict(), st
+
+    def solve_pcdm(self, x_out=None, **kw):
+        import torch
+        if x_out is None:
+            x_out = torch.empty(self.params["n"], dtype=torch.float64, device="cuda")
+        o = solve_opts(**kw)
+        rep = Report()
+        st = _check(lib().l1ls_sgt_solve_pcdm(self._h, ctypes.byref(o), _ptr(x_out), ctypes.byref(rep)),
+                    "l1ls_sgt_solve_pcdm", allow=(L1LS_OK, L1LS_NOT_CONVERGED))
         return x_out, rep.as_dict(), st
 
     def solve_cg_newton(self, x_out=None, **kw):

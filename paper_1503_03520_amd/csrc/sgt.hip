@@ -381,6 +381,38 @@ __global__ __launch_bounds__(kHB) void kh_fista(SgtK H, const dv2* __restrict__ 
     }
 }
 
+// ---- PCDM ----------------------------------------------------------------------
+// One synchronous step of section 8.1's PCDM on the pair: from the same x,
+// every sampled coordinate i takes x_i <- soft(x_i - A_i^T (A x - b) / v_i,
+// tau / v_i) with v_i = beta L_i, L_i = (A^T A)_ii.  Coordinate 2k + e is
+// sampled when word e of Philox counter (k, step, kTagPcdm, 0) is below thr
+// (every coordinate when thr = 2^32).  x is updated in place.
+constexpr uint32_t kTagPcdm = 0x600u;
+
+template <int SL>
+__global__ __launch_bounds__(kHB) void kh_pcdm(SgtK H, dv2* __restrict__ x, const dv2* __restrict__ b, double beta,
+                                               uint64_t thr, uint32_t step) {
+    const int64_t np = H.n / 2;
+    for (int64_t k = gtid(); k < np; k += gstride()) {
+        const double2 sg = sigma_pair<SL>(H, k);
+        const double2 cn = colnorm_pair<SL>(H, sg);
+        const dv2 xv = __builtin_nontemporal_load(x + k), bv = __builtin_nontemporal_load(b + k);
+        double ri, rj, gi, gj;
+        a_pair(H, sg, xv.x, xv.y, ri, rj);
+        at_pair(H, sg, ri - bv.x, rj - bv.y, gi, gj);
+        const double vi = beta * cn.x, vj = beta * cn.y;
+        dv2 xn;
+        xn.x = soft_threshold<double>(xv.x - gi / vi, H.tau / vi);
+        xn.y = soft_threshold<double>(xv.y - gj / vj, H.tau / vj);
+        if (thr < ((uint64_t)1 << 32)) {
+            const U4 w = philox4x32_10((uint32_t)k, step, kTagPcdm, 0u, H.key.k0, H.key.k1);
+            if (!((uint64_t)w.x < thr)) xn.x = xv.x;
+            if (!((uint64_t)w.y < thr)) xn.y = xv.y;
+        }
+        __builtin_nontemporal_store(xn, x + k);
+    }
+}
+
 // ---- CG-Newton ---------------------------------------------------------------
 // M = (diag(A^T A) + d)^{-1}, the Jacobi preconditioner, on the pair
 __device__ __forceinline__ dv2 precond(double2 cn, dv2 d) {
@@ -1044,6 +1076,93 @@ extern "C" l1ls_status l1ls_sgt_solve_fista(const l1ls_sgt* H, const l1ls_solve_
             if ((o->rel_gap_tol > 0 && gap <= o->rel_gap_tol) || (o->f_target > 0 && P <= o->f_target)) stop = true;
         }
         if (cur != x) HIP_TRY(hipMemcpyAsync(x, cur, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (k == 0) L1LS_TRY(sgt_gap(H, tau, x, s, &P, &D, &gap, part));
+        l1ls_report rr;
+        std::memset(&rr, 0, sizeof(rr));
+        rr.iterations = k;
+        rr.primal = P;
+        rr.dual = D;
+        rr.rel_gap = gap;
+        L1LS_TRY(sgt_err(H, x, s, &rr.rel_err, part));
+        rr.converged = stop ? 1 : 0;
+        rr.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = rr;
+        return stop ? L1LS_OK : L1LS_NOT_CONVERGED;
+    };
+    const l1ls_status st = run();
+    cleanup();
+    return st;
+}
+
+extern "C" l1ls_status l1ls_sgt_solve_pcdm(const l1ls_sgt* H, const l1ls_solve_opts* o, double* x,
+                                           l1ls_report* rep) {
+    if (!H || !o || !x) return L1LS_E_ARG;
+    if (o->max_iter < 0 || !aligned16(x) || (o->x0_dev && !aligned16(o->x0_dev))) return L1LS_E_ARG;
+    if (o->precision != L1LS_F64 || o->polish != 0) return L1LS_E_UNSUPPORTED;
+    if (!(o->max_iter < ((int64_t)1 << 32))) return L1LS_E_ARG;  // the step is a Philox counter word
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o->stream;
+    const double tau = o->tau > 0 ? o->tau : H->prm.tau;
+    const double p = (o->pcdm_p > 0 && o->pcdm_p < 1) ? o->pcdm_p : 1.0;
+    const int check = std::max(1, o->check_every);
+    if (!is_fin(tau)) return L1LS_E_ARG;
+    // omega = 2 nonzeros per row; beta of a doubly uniform sampling with E|S| = n p
+    const double beta = 1.0 + (2 - 1) * p;
+    const uint64_t thr = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)(p * 4294967296.0);
+    SgtK K = H->k;
+    K.tau = tau;
+    const int64_t n = K.n;
+    const int nb = blocks_for(n / 2);
+    const bool tk = o->time_kernels != 0;
+    DevArena W;
+    double* part = nullptr;
+    std::vector<hipEvent_t> ev;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        W.release();
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    };
+    auto run = [&]() -> l1ls_status {
+        L1LS_TRY(W.alloc(&part, (size_t)kHMaxBlocks * 4));
+        if (tk) {
+            for (int q = 0; q < 3; ++q) {
+                H->kt_ms[q] = 0;
+                H->kt_calls[q] = 0;
+            }
+            ev.resize(2 * (size_t)check);
+            for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+        }
+        if (o->x0_dev) {
+            if (o->x0_dev != x) HIP_TRY(hipMemcpyAsync(x, o->x0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            hipLaunchKernelGGL(kh_zero, dim3(nb), dim3(kHB), 0, s, x, n);
+        }
+        double P = 0, D = 0, gap = INFINITY;
+        int64_t k = 0;
+        bool stop = false;
+        while (k < o->max_iter && !stop) {
+            const int64_t batch = std::min<int64_t>(check - (k % check), o->max_iter - k);
+            for (int64_t q = 0; q < batch; ++q) {
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
+                by_law(K.sigma_law, [&](auto c) {
+                    hipLaunchKernelGGL(kh_pcdm<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (dv2*)x,
+                                       (const dv2*)H->b, beta, thr, (uint32_t)k);
+                });
+                if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
+                ++k;
+            }
+            HIP_TRY(hipGetLastError());
+            L1LS_TRY(sgt_gap(H, tau, x, s, &P, &D, &gap, part));
+            if (tk) {
+                for (int64_t q = 0; q < batch; ++q) {
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]);
+                    H->kt_ms[0] += ms;
+                }
+                H->kt_calls[0] += batch;
+            }
+            if ((o->rel_gap_tol > 0 && gap <= o->rel_gap_tol) || (o->f_target > 0 && P <= o->f_target)) stop = true;
+        }
         if (k == 0) L1LS_TRY(sgt_gap(H, tau, x, s, &P, &D, &gap, part));
         l1ls_report rr;
         std::memset(&rr, 0, sizeof(rr));

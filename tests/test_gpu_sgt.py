@@ -348,3 +348,27 @@ def test_section_8_5_instance_at_paper_size():
     assert np.array_equal(L.device_to_numpy(d.b_dev, n, np.float64), O.b[:n])
     assert H.kappa_rho(0.1) == pytest.approx(O.kappa_rho(0.1), rel=1e-12)
     H.free()
+
+
+@pytest.mark.parametrize("case", [CASES[1], LAW_CASES[0], LAW_CASES[1]])
+@pytest.mark.parametrize("p", [1.0, 0.5, 0.05])
+@pytest.mark.parametrize("steps", [1, 5, 50])
+def test_pcdm_trajectory_matches_oracle(case, p, steps):
+    from oracle.sgt import pcdm
+    n, s, m, kw = case
+    H, O = make(n, s, m, kw)
+    x, rep, st = H.solve_pcdm(max_iter=steps, rel_gap_tol=0.0, check_every=16, pcdm_p=p)
+    assert rep["iterations"] == steps and st == L.L1LS_NOT_CONVERGED
+    xo = pcdm(O, O.tau, steps, p=p)
+    assert np.abs(host(x) - xo).max() <= 1e-11 * max(1.0, np.abs(xo).max())
+    H.free()
+
+
+def test_pcdm_reaches_objective_target():
+    from oracle.sgt import pcdm
+    n, s, m, kw = LAW_CASES[0]
+    H, O = make(n, s, m, kw)
+    target = OF.primal(O.matvec, O.b, O.tau, pcdm(O, O.tau, 40))
+    x, rep, st = H.solve_pcdm(max_iter=5000, rel_gap_tol=0.0, f_target=target * (1 + 1e-12), check_every=8)
+    assert st == L.L1LS_OK and rep["iterations"] % 8 == 0 and rep["primal"] <= target * (1 + 1e-12)
+    H.free()
