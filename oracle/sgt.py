@@ -258,3 +258,129 @@ def pcdm(I, tau, iters, p=1.0, x0=None, omega=2):
             take[1::2] = w1 < thr
             x = np.where(take, upd, x)
     return x
+
+
+TAG_XI = 0x700
+
+
+class SgtIGen2Instance:
+    """Procedure IGen2 (section 3.2) for m < n on the A = Sigma G^T class.
+
+    B (m x m) = Sigma_B G_B^T with the class's sigma law on the m columns
+    and the adjacent-pair rotations of angle theta; N (m x (n-m)), n - m <= m,
+    is [Sigma_N G_N^T; 0]: its column pair k couples the rows of B's pair k,
+    with singular values from the same law (uniform: Philox counter
+    (k, 1, 0x500, 0); alternating: the same two values) and the same angle.
+    x* has s <= m nonzeros among the first m components (positions and values
+    as in SgtInstance with "table1" or "osgen" over [0, m)); g is sign(x*)
+    on the support and U[-0.9, 0.9] elsewhere among the first m (eq. (14)).
+    IGen2: e = tau B^{-T} g (step 3), N~_j = xi_j tau / |N_j^T e| N_j with
+    xi_j = 2u - 1 from Philox counter (j, 0, 0x700, 0) (step 4, xi uniform on
+    [-1, 1]), A = [B, N~], b = A x* + e (step 5).
+    """
+
+    def __init__(self, m, n, s, seed, theta=2.0 * math.pi / 3.0, sigma_odd=0.1, sigma_even=100.0, x_neg=-1.0e4,
+                 x_pos=0.1, tau=1.0, sigma_law="alternating", sigma_scale=1.0, sigma_shift=0.1,
+                 xstar_law="table1", gamma=1.0):
+        if not (m >= 2 and m % 2 == 0 and n > m and (n - m) % 2 == 0 and n - m <= m):
+            raise ValueError("need m even, n > m, n - m even and <= m")
+        if not (0 <= s <= m) or not tau > 0.0:
+            raise ValueError("need 0 <= s <= m, tau > 0")
+        self.m, self.n, self.s, self.seed = int(m), int(n), int(s), int(seed)
+        self.nn = n - m
+        self.theta, self.tau = float(theta), float(tau)
+        self.c, self.sn = math.cos(self.theta), math.sin(self.theta)
+        key = seed_key(seed)
+        if sigma_law == "alternating":
+            self.sigma_b = np.where(np.arange(m) % 2 == 0, float(sigma_odd), float(sigma_even))
+            self.sigma_n = np.where(np.arange(self.nn) % 2 == 0, float(sigma_odd), float(sigma_even))
+        elif sigma_law == "uniform":
+            self.sigma_b = uniform_sigmas(m, seed, float(sigma_scale), float(sigma_shift))
+            w0, w1, w2, w3 = philox4x32_10(np.arange(self.nn // 2), 1, TAG_SIGMA, 0, key)
+            self.sigma_n = np.empty(self.nn)
+            self.sigma_n[0::2] = unit_double(w0, w1) * float(sigma_scale) + float(sigma_shift)
+            self.sigma_n[1::2] = unit_double(w2, w3) * float(sigma_scale) + float(sigma_shift)
+        else:
+            raise ValueError(sigma_law)
+        # x* among the first m components
+        self.support = permutation(np.arange(s), m, TAG_PERM | SIDE_SUPPORT, key)
+        if xstar_law == "table1":
+            vals = np.where(np.arange(s) < s // 2, float(x_neg), float(x_pos))
+        elif xstar_law == "osgen":
+            u0, u1, _, _ = philox4x32_10(np.arange(s), 0, TAG_XSTAR, 0, key)
+            vals = float(gamma) * (2.0 * unit_double(u0, u1) - 1.0)
+        else:
+            raise ValueError(xstar_law)
+        self.xstar = np.zeros(n)
+        self.xstar[self.support] = vals
+        w0, w1, _, _ = philox4x32_10(np.arange(m), 0, TAG_SUBGRAD, 0, key)
+        g = 0.9 * (2.0 * unit_double(w0, w1) - 1.0)
+        g[self.support] = np.sign(vals)
+        self.g = g
+        # IGen2 step 3: e = tau B^{-T} g = tau Sigma_B^{-1} G_B^T g
+        self.e = self.tau * self._rot(g, transpose=True) / self.sigma_b
+        # IGen2 step 4: N~_j = xi_j tau / |N_j^T e| N_j
+        ntE = self._rot(self.sigma_n * self.e[: self.nn], transpose=False)   # N^T e = G_N Sigma_N e_top
+        u0, u1, _, _ = philox4x32_10(np.arange(self.nn), 0, TAG_XI, 0, key)
+        self.xi = 2.0 * unit_double(u0, u1) - 1.0
+        self.colscale = self.xi * self.tau / np.abs(ntE)
+        # IGen2 step 5
+        self.b = self.matvec(self.xstar) + self.e
+        self.fstar = self.tau * np.abs(self.xstar).sum() + 0.5 * float(self.e @ self.e)
+        A = self.sparse_A().toarray() if n <= 4096 else None
+        self.L = float(np.linalg.eigvalsh(A @ A.T).max()) if A is not None else None
+
+    def _rot(self, z, transpose):
+        z = np.array(z, dtype=np.float64, copy=True)
+        k = len(z)
+        return rotate(z, np.arange(0, k, 2), np.arange(1, k, 2), self.c, self.sn, transpose=transpose)
+
+    def matvec(self, x):
+        """A x = B x_B + N~ x_N (m entries)."""
+        x = np.asarray(x, dtype=np.float64)
+        m, nn = self.m, self.nn
+        y = self.sigma_b * self._rot(x[:m], transpose=True)
+        y[:nn] += self.sigma_n * self._rot(self.colscale * x[m:], transpose=True)
+        return y
+
+    def rmatvec(self, y):
+        """A^T y = [B^T y; N~^T y] (n entries)."""
+        y = np.asarray(y, dtype=np.float64)
+        m, nn = self.m, self.nn
+        out = np.empty(self.n)
+        out[:m] = self._rot(self.sigma_b * y, transpose=False)
+        out[m:] = self.colscale * self._rot(self.sigma_n * y[:nn], transpose=False)
+        return out
+
+    def colnorm2(self):
+        """diag(A^T A)."""
+        out = np.empty(self.n)
+        c2, s2 = self.c ** 2, self.sn ** 2
+        sb, sn_ = self.sigma_b, self.sigma_n
+        out[0:self.m:2] = sb[0::2] ** 2 * c2 + sb[1::2] ** 2 * s2
+        out[1:self.m:2] = sb[0::2] ** 2 * s2 + sb[1::2] ** 2 * c2
+        cs = self.colscale
+        out[self.m::2] = cs[0::2] ** 2 * (sn_[0::2] ** 2 * c2 + sn_[1::2] ** 2 * s2)
+        out[self.m + 1::2] = cs[1::2] ** 2 * (sn_[0::2] ** 2 * s2 + sn_[1::2] ** 2 * c2)
+        return out
+
+    def sparse_A(self):
+        """A = [B, N~] as a scipy CSR matrix, from the explicit 2 x 2 blocks."""
+        m, nn = self.m, self.nn
+        rows, cols, vals = [], [], []
+        c, s = self.c, self.sn
+        for k in range(m // 2):
+            i, j = 2 * k, 2 * k + 1
+            # B block: Sigma_B G_B^T on columns (i, j): rows i: sigma_i (c, s); j: sigma_j (-s, c)
+            rows += [i, i, j, j]
+            cols += [i, j, i, j]
+            vals += [self.sigma_b[i] * c, self.sigma_b[i] * s, -self.sigma_b[j] * s, self.sigma_b[j] * c]
+            if j < nn:
+                a, bb = self.colscale[i], self.colscale[j]
+                rows += [i, i, j, j]
+                cols += [m + i, m + j, m + i, m + j]
+                vals += [self.sigma_n[i] * c * a, self.sigma_n[i] * s * bb, -self.sigma_n[j] * s * a,
+                         self.sigma_n[j] * c * bb]
+        A = sp.csr_matrix((vals, (rows, cols)), shape=(m, self.n))
+        A.sort_indices()
+        return A

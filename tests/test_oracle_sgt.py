@@ -254,3 +254,45 @@ def test_pcdm_decreases_objective_and_reaches_minimiser(p):
     x = pcdm(I, I.tau, 3000, p=p)
     assert f(x) <= f(np.zeros(256))
     assert np.linalg.norm(x - I.xstar) / np.linalg.norm(I.xstar) <= 1e-8
+
+
+# ---- IGen2 (section 3.2, m < n) -------------------------------------------------
+@pytest.mark.parametrize("m,n,s,law", [(64, 96, 6, "alternating"), (130, 260, 9, "uniform"), (128, 130, 3, "uniform")])
+def test_igen2_optimality_conditions(m, n, s, law):
+    from oracle.sgt import SgtIGen2Instance
+    I = SgtIGen2Instance(m, n, s, SEED, tau=0.37, sigma_law=law, sigma_scale=10.0, xstar_law="osgen", gamma=3.0)
+    A = I.sparse_A().toarray()
+    B = A[:, :m]
+    # step 3 against a dense solve: e = tau B^{-T} g
+    assert np.allclose(I.e, I.tau * np.linalg.solve(B.T, I.g), rtol=1e-12, atol=1e-12 * np.abs(I.e).max())
+    # eq. (15): N~^T e in tau [-1, 1], equal to xi tau sign(N^T e)
+    nte = A[:, m:].T @ I.e
+    assert np.all(np.abs(nte) <= I.tau * (1 + 1e-12))
+    assert np.allclose(np.abs(nte), np.abs(I.xi) * I.tau, rtol=1e-12)
+    # optimality of x*: A^T (A x* - b) in -tau d||x*||_1, zero duality gap
+    grad = A.T @ (A @ I.xstar - I.b)
+    nz = np.flatnonzero(I.xstar)
+    assert len(nz) == s and np.all(nz < m)
+    assert np.allclose(grad[nz], -I.tau * np.sign(I.xstar[nz]), rtol=0, atol=1e-9)
+    assert np.all(np.abs(grad) <= I.tau * (1 + 1e-9))
+    P, D, gap = OF.duality_gap(lambda v: A @ v, lambda v: A.T @ v, I.b, I.tau, I.xstar)
+    assert abs(gap) <= 1e-9
+    assert P == pytest.approx(I.fstar, rel=1e-12)
+    # operator and diagonal against the explicit matrix
+    x = np.random.default_rng(4).standard_normal(n)
+    y = np.random.default_rng(5).standard_normal(m)
+    assert np.allclose(I.matvec(x), A @ x, rtol=0, atol=1e-12 * np.abs(A @ x).max())
+    assert np.allclose(I.rmatvec(y), A.T @ y, rtol=0, atol=1e-12 * np.abs(A.T @ y).max())
+    assert np.allclose(I.colnorm2(), (A * A).sum(0), rtol=1e-13)
+
+
+def test_igen2_fista_obeys_the_rate_towards_the_planted_optimum():
+    # x* is the minimiser by construction, so FISTA from 0 obeys Beck and
+    # Teboulle's f(x_k) - f* <= 2 L ||x*||^2 / (k + 1)^2 with f* = f(x*)
+    from oracle.sgt import SgtIGen2Instance
+    I = SgtIGen2Instance(256, 384, 8, SEED, sigma_law="uniform", sigma_scale=1.0, xstar_law="osgen", gamma=5.0)
+    fstar = OF.primal(I.matvec, I.b, I.tau, I.xstar)
+    for k in (10, 100, 1000):
+        x = OF.fista(I.matvec, I.rmatvec, I.b, I.tau, I.L, k)
+        gap = OF.primal(I.matvec, I.b, I.tau, x) - fstar
+        assert -1e-9 * fstar <= gap <= 2 * I.L * float(I.xstar @ I.xstar) / (k + 1) ** 2
