@@ -394,6 +394,16 @@ l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus,
  * bytes) and recomputes sigma, x* and g from (seed, index) where it needs
  * them.
  *
+ * m < n selects Procedure IGen2 (section 3.2): A = [B, N~] with B (m x m) =
+ * Sigma_B G_B^T as above over the first m columns and N (m x (n - m)),
+ * n - m <= m, = [Sigma_N G_N^T; 0] on the same adjacent pairs (uniform law:
+ * Philox counter (k, 1, 0x500, 0) for N's pair k); x* has its s <= m
+ * nonzeros among the first m components (TABLE1 or OSGEN law over [0, m));
+ * g (eq. (14)) is defined on the first m; e = tau B^{-T} g; N~_j = xi_j tau /
+ * |N_j^T e| N_j with xi_j = 2u - 1 from Philox counter (j, 0, 0x700, 0);
+ * b = A x* + e (m entries).  The n - m column scales are stored (8 bytes
+ * each).  kappa_rho is not defined for m < n (L1LS_E_UNSUPPORTED).
+ *
  * Device vectors passed to these calls must be 16-byte aligned
  * (L1LS_E_ARG otherwise).  Calls on the same instance must not overlap.
  * ------------------------------------------------------------------------- */
@@ -404,8 +414,9 @@ typedef struct l1ls_sgt l1ls_sgt;
 
 typedef struct {
     int64_t n;          /* variables: even, 2 <= n <= 2^32                      */
-    int64_t m;          /* rows: even, m >= n (section 8.9: 2n)                 */
-    int64_t s;          /* nonzeros of x*, 0 <= s <= n (section 8.9: n / 2^10)  */
+    int64_t m;          /* rows: even; m >= n (section 8.9: 2n), or IGen2 with  */
+                        /* n/2 <= m < n                                         */
+    int64_t s;          /* nonzeros of x*, 0 <= s <= min(m, n) (8.9: n / 2^10)  */
     double theta;       /* angle of every rotation of G (section 8.9: 2 pi / 3) */
     double sigma_odd;   /* sigma_i, odd i (section 8.9: 0.1); > 0               */
     double sigma_even;  /* sigma_i, even i (section 8.9: 100); > 0              */
@@ -427,7 +438,9 @@ typedef struct {
     double f_star;       /* f_tau(x*) = tau ||x*||_1 + 0.5 ||e||^2               */
     double c, s_rot;     /* cos theta, sin theta as used by the kernels          */
     const double* b_dev; /* n: the top n entries of b (the others are zero)       */
-    double sigma_min, sigma_max; /* kappa(A^T A) = (sigma_max / sigma_min)^2 (section 5) */
+    double sigma_min, sigma_max; /* of B's (m >= n: A's) singular values; kappa(A^T A) =
+                                    (sigma_max / sigma_min)^2 when m >= n (section 5) */
+    const double* colscale_dev;  /* IGen2: the n - m column scales xi_j tau / |N_j^T e| of N~; else NULL */
 } l1ls_sgt_desc;
 
 /* params = the section 8.9 values for n: m = 2n, s = floor(n / 1024),

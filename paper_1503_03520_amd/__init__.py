@@ -100,7 +100,7 @@ class SgtDesc(ctypes.Structure):
     _fields_ = [
         ("params", SgtParams), ("L", ctypes.c_double), ("f_star", ctypes.c_double), ("c", ctypes.c_double),
         ("s_rot", ctypes.c_double), ("b_dev", ctypes.c_void_p), ("sigma_min", ctypes.c_double),
-        ("sigma_max", ctypes.c_double),
+        ("sigma_max", ctypes.c_double), ("colscale_dev", ctypes.c_void_p),
     ]
 
 

@@ -61,6 +61,11 @@ constexpr int kSelBins = 256;                   // radix-select digit of 8 bits
 // Constants of one instance, passed by value to every kernel.
 struct SgtK {
     int64_t n, s, s1, s2;
+    int64_t np;       // row pairs with entries: min(m, n) / 2
+    int64_t nnp;      // IGen2 (m < n): column pairs of N~, in the rows of pairs k < nnp; else 0
+    int64_t noff;     // IGen2: pair index in x of N~'s first column pair (m / 2)
+    int64_t nsup;     // range of supp(x*): n, or m for IGen2
+    const double* cs; // IGen2: column scales xi_j tau / |N_j^T e| of N~ (n - m)
     int32_t sigma_law, xstar_law;
     double c, sn;              // cos, sin of the shared angle
     double so, se;             // alternating law: sigma at the first / second element of a pair
@@ -133,6 +138,78 @@ __device__ __forceinline__ double2 hess_pair(const SgtK& H, double2 sg, double2 
     return make_double2(hi + d.x * p.x, hj + d.y * p.y);
 }
 
+// IGen2: sigma of N's column pair k; uniform law from counter (k, 1, kTagSigma, 0)
+__device__ __forceinline__ double2 uniform_sigma_n_pair(const SgtK& H, int64_t k) {
+#pragma clang fp contract(off)
+    const U4 w = philox4x32_10((uint32_t)k, 1u, kTagSigma, 0u, H.key.k0, H.key.k1);
+    return make_double2(unit_double(w.x, w.y) * H.scale + H.shift, unit_double(w.z, w.w) * H.scale + H.shift);
+}
+
+template <int SL>
+__device__ __forceinline__ double2 sigma_n_pair(const SgtK& H, int64_t k) {
+    if constexpr (SL == 0)
+        return make_double2(H.so, H.se);
+    else
+        return uniform_sigma_n_pair(H, k);
+}
+
+// Row pair k: B's block (sigma sb) and, for IGen2 rows k < nnp, N~'s block
+// (sigma sn, column scales cs).  NN = 0 compiles the m >= n class alone.
+struct Row {
+    double2 sb, sn, cs;
+    bool hasN;
+};
+
+template <int SL, int NN>
+__device__ __forceinline__ Row load_row(const SgtK& H, int64_t k) {
+    Row R;
+    R.sb = sigma_pair<SL>(H, k);
+    R.hasN = NN && k < H.nnp;
+    if (NN && R.hasN) {
+        R.sn = sigma_n_pair<SL>(H, k);
+        R.cs = reinterpret_cast<const double2*>(H.cs)[k];
+    } else {
+        R.sn = make_double2(0.0, 0.0);
+        R.cs = make_double2(0.0, 0.0);
+    }
+    return R;
+}
+
+// rows of the pair: B x_B + N~ x_N (N~ = N diag(cs))
+template <int NN>
+__device__ __forceinline__ void a_row(const SgtK& H, const Row& R, double2 xb, double2 xn, double& yi, double& yj) {
+    a_pair(H, R.sb, xb.x, xb.y, yi, yj);
+    if (NN && R.hasN) {
+        double ui, uj;
+        a_pair(H, R.sn, R.cs.x * xn.x, R.cs.y * xn.y, ui, uj);
+        yi += ui;
+        yj += uj;
+    }
+}
+
+// columns of the pair: g_B = B^T r, g_N = N~^T r
+template <int NN>
+__device__ __forceinline__ void at_row(const SgtK& H, const Row& R, double ri, double rj, double2& gb, double2& gn) {
+    at_pair(H, R.sb, ri, rj, gb.x, gb.y);
+    gn = make_double2(0.0, 0.0);
+    if (NN && R.hasN) {
+        double ti, tj;
+        at_pair(H, R.sn, ri, rj, ti, tj);
+        gn = make_double2(R.cs.x * ti, R.cs.y * tj);
+    }
+}
+
+// diag(A^T A) on B's and N~'s column pairs
+template <int SL, int NN>
+__device__ __forceinline__ void colnorm_row(const SgtK& H, const Row& R, double2& cb, double2& cn) {
+    cb = colnorm_pair<SL>(H, R.sb);
+    cn = make_double2(0.0, 0.0);
+    if (NN && R.hasN) {
+        const double2 c0 = colnorm_pair<SL>(H, R.sn);
+        cn = make_double2(R.cs.x * R.cs.x * c0.x, R.cs.y * R.cs.y * c0.y);
+    }
+}
+
 // OsGen3 before selection: x = G gamma (Sigma^T Sigma)^{-1} 1_n on the pair,
 // the exact minimiser of eq. (19), in the operation order of the definition.
 __device__ __forceinline__ double2 osgen3_full_pair(const SgtK& H, double2 sg) {
@@ -161,7 +238,7 @@ __device__ __forceinline__ void planted_elem(const SgtK& H, int64_t i, double xf
         on = (H.has1 && key_le(kb, i, H.t1_bits, H.t1_idx)) || (H.has2 && key_le(H.t2_bits, H.t2_idx, kb, i));
         if (on) xs = xf;
     } else if (H.s > 0) {
-        const int64_t q = bijection_inverse(i, H.n, kTagPerm | 2u, H.key);
+        const int64_t q = bijection_inverse(i, H.nsup, kTagPerm | 2u, H.key);
         if (q < H.s) {
             on = true;
             if (H.xstar_law == L1LS_XSTAR_TABLE1) {
@@ -213,12 +290,26 @@ __device__ __forceinline__ void igen_pair(const SgtK& H, double2 sg, double2 xs,
     b.y = sg.y * (-H.sn * xs.x + H.c * xs.y) + e.y;
 }
 
-// b for every pair; part = (sum e^2, sum |x*| | max sigma, max -sigma)
-template <int SL>
-__global__ __launch_bounds__(kHB) void kh_generate(SgtK H, double2* __restrict__ b, double* __restrict__ part) {
-    double v[4] = {0.0, 0.0, -INFINITY, -INFINITY};
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
+// b for every row pair, and for IGen2 the column scales of N~ (IGen2 step 4:
+// N~_j = xi_j tau / |N_j^T e| N_j, xi_j = 2u - 1 from counter (j, 0, kTagXi, 0));
+// part = (sum e^2, sum |x*| | max sigma, max -sigma, max row eigenvalue of A A^T)
+constexpr uint32_t kTagXi = 0x700u;
+
+__device__ __forceinline__ double2 igen2_scales(const SgtK& H, int64_t k, double2 sn, double2 e) {
+#pragma clang fp contract(off)
+    const double ti = sn.x * e.x, tj = sn.y * e.y;
+    const double ni = H.c * ti - H.sn * tj, nj = H.sn * ti + H.c * tj;  // N^T e on the pair
+    const U4 wi = philox4x32_10((uint32_t)(2 * k), 0u, kTagXi, 0u, H.key.k0, H.key.k1);
+    const U4 wj = philox4x32_10((uint32_t)(2 * k + 1), 0u, kTagXi, 0u, H.key.k0, H.key.k1);
+    const double xi = 2.0 * unit_double(wi.x, wi.y) - 1.0, xj = 2.0 * unit_double(wj.x, wj.y) - 1.0;
+    return make_double2(xi * H.tau / fabs(ni), xj * H.tau / fabs(nj));
+}
+
+template <int SL, int NN>
+__global__ __launch_bounds__(kHB) void kh_generate(SgtK H, double2* __restrict__ b, double2* __restrict__ csw,
+                                                   double* __restrict__ part) {
+    double v[5] = {0.0, 0.0, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
         const double2 sg = sigma_pair<SL>(H, k);
         double2 xs, g, bv, e;
         planted_pair(H, k, sg, xs, g);
@@ -228,14 +319,30 @@ __global__ __launch_bounds__(kHB) void kh_generate(SgtK H, double2* __restrict__
         v[1] += fabs(xs.x) + fabs(xs.y);
         v[2] = fmax(v[2], fmax(sg.x, sg.y));
         v[3] = fmax(v[3], fmax(-sg.x, -sg.y));
+        double lam = fmax(sg.x * sg.x, sg.y * sg.y);
+        if (NN && k < H.nnp) {
+            const double2 sn = sigma_n_pair<SL>(H, k);
+            const double2 cs = igen2_scales(H, k, sn, e);
+            csw[k] = cs;
+            // rows of [B, N~] on the pair and the larger eigenvalue of their Gram matrix
+            const double bi0 = sg.x * H.c, bi1 = sg.x * H.sn, bj0 = -sg.y * H.sn, bj1 = sg.y * H.c;
+            const double ni0 = sn.x * H.c * cs.x, ni1 = sn.x * H.sn * cs.y;
+            const double nj0 = -sn.y * H.sn * cs.x, nj1 = sn.y * H.c * cs.y;
+            const double a11 = bi0 * bi0 + bi1 * bi1 + ni0 * ni0 + ni1 * ni1;
+            const double a22 = bj0 * bj0 + bj1 * bj1 + nj0 * nj0 + nj1 * nj1;
+            const double a12 = bi0 * bj0 + bi1 * bj1 + ni0 * nj0 + ni1 * nj1;
+            const double h = 0.5 * (a11 - a22);
+            lam = 0.5 * (a11 + a22) + sqrt(h * h + a12 * a12);
+        }
+        v[4] = fmax(v[4], lam);
     }
-    store_partials<4, 2>(v, part);
+    store_partials<5, 2>(v, part);
 }
 
-template <int SL>
+// x* and g (n each; IGen2: entries m..n-1 are 0, g being defined on the first m)
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_planted(SgtK H, double* __restrict__ xs, double* __restrict__ g) {
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
         double2 a, c;
         planted_pair(H, k, sigma_pair<SL>(H, k), a, c);
         if (xs) {
@@ -246,21 +353,29 @@ __global__ __launch_bounds__(kHB) void kh_planted(SgtK H, double* __restrict__ x
             g[2 * k] = c.x;
             g[2 * k + 1] = c.y;
         }
+        if (NN && k < H.nnp) {
+            const int64_t j = 2 * (H.noff + k);
+            if (xs) xs[j] = xs[j + 1] = 0.0;
+            if (g) g[j] = g[j + 1] = 0.0;
+        }
     }
 }
 
 // part = (sum (x - x*)^2, sum x*^2)
-template <int SL>
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_err(SgtK H, const double2* __restrict__ x, double* __restrict__ part) {
     double v[2] = {0.0, 0.0};
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
         double2 a, c;
         planted_pair(H, k, sigma_pair<SL>(H, k), a, c);
         const double2 xv = x[k];
         const double di = xv.x - a.x, dj = xv.y - a.y;
         v[0] += di * di + dj * dj;
         v[1] += a.x * a.x + a.y * a.y;
+        if (NN && k < H.nnp) {
+            const double2 xn = x[H.noff + k];  // x*_N = 0
+            v[0] += xn.x * xn.x + xn.y * xn.y;
+        }
     }
     store_partials<2, 2>(v, part);
 }
@@ -315,101 +430,133 @@ __global__ __launch_bounds__(kHB) void kh_select_hist(SgtK H, int by_index, uint
         if (lh[q]) atomicAdd(&hist[q], (unsigned long long)lh[q]);
 }
 
-// trans = 0: out (m) = A in (n), rows n..m-1 zero; trans = 1: out (n) = A^T in (top n of m)
-template <int SL>
+// trans = 0: out (m) = A in (n), rows beyond the row pairs zero; trans = 1:
+// out (n) = A^T in (m)
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_apply(SgtK H, int64_t m, int trans, const double2* __restrict__ in,
                                                 double2* __restrict__ out) {
-    const int64_t np = H.n / 2;
-    const int64_t total = trans ? np : m / 2;
+    const int64_t total = trans ? H.np : m / 2;
     for (int64_t k = gtid(); k < total; k += gstride()) {
-        if (k >= np) {
+        if (k >= H.np) {
             out[k] = make_double2(0.0, 0.0);
             continue;
         }
-        const double2 sg = sigma_pair<SL>(H, k);
-        const double2 a = in[k];
-        double oi, oj;
-        if (trans)
-            at_pair(H, sg, a.x, a.y, oi, oj);
-        else
-            a_pair(H, sg, a.x, a.y, oi, oj);
-        out[k] = make_double2(oi, oj);
+        const Row R = load_row<SL, NN>(H, k);
+        if (trans) {
+            const double2 a = in[k];
+            double2 gb, gn;
+            at_row<NN>(H, R, a.x, a.y, gb, gn);
+            out[k] = gb;
+            if (NN && R.hasN) out[H.noff + k] = gn;
+        } else {
+            const double2 xb = in[k];
+            const double2 xn = (NN && R.hasN) ? in[H.noff + k] : make_double2(0.0, 0.0);
+            double yi, yj;
+            a_row<NN>(H, R, xb, xn, yi, yj);
+            out[k] = make_double2(yi, yj);
+        }
     }
 }
 
 // part = (sum |x|, sum r^2, sum b r | max |A^T r|), r = A x - b
-template <int SL>
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_gap(SgtK H, const double2* __restrict__ x, const double2* __restrict__ b,
                                               double* __restrict__ part) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
-        const double2 sg = sigma_pair<SL>(H, k);
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row R = load_row<SL, NN>(H, k);
         const double2 xv = x[k], bv = b[k];
-        double yi, yj, gi, gj;
-        a_pair(H, sg, xv.x, xv.y, yi, yj);
+        const double2 xn = (NN && R.hasN) ? x[H.noff + k] : make_double2(0.0, 0.0);
+        double yi, yj;
+        a_row<NN>(H, R, xv, xn, yi, yj);
         const double ri = yi - bv.x, rj = yj - bv.y;
-        at_pair(H, sg, ri, rj, gi, gj);
-        v[0] += fabs(xv.x) + fabs(xv.y);
+        double2 gb, gn;
+        at_row<NN>(H, R, ri, rj, gb, gn);
+        v[0] += fabs(xv.x) + fabs(xv.y) + fabs(xn.x) + fabs(xn.y);
         v[1] += ri * ri + rj * rj;
         v[2] += bv.x * ri + bv.y * rj;
-        v[3] = fmax(v[3], fmax(fabs(gi), fabs(gj)));
+        v[3] = fmax(v[3], fmax(fmax(fabs(gb.x), fabs(gb.y)), fmax(fabs(gn.x), fabs(gn.y))));
     }
     store_partials<4, 3>(v, part);
 }
 
 // ---- FISTA -------------------------------------------------------------------
-// Iteration k of section 8.1's FISTA on the pair: y = x_{k-1} + beta
+// Iteration k of section 8.1's FISTA on a row pair: y = x_{k-1} + beta
 // (x_{k-1} - x_{k-2}), x_k = soft(y - A^T (A y - b) / L, tau / L).  xc holds
 // x_{k-1}; xo holds x_{k-2} on entry and x_k on exit.
-template <int SL>
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_fista(SgtK H, const dv2* __restrict__ xc, dv2* __restrict__ xo,
                                                 const dv2* __restrict__ b, double beta, double L, double thr) {
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
-        const double2 sg = sigma_pair<SL>(H, k);
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row R = load_row<SL, NN>(H, k);
         const dv2 xv = __builtin_nontemporal_load(xc + k), xp = __builtin_nontemporal_load(xo + k);
         const dv2 bv = __builtin_nontemporal_load(b + k);
         const dv2 y = xv + beta * (xv - xp);
-        double ri, rj, gi, gj;
-        a_pair(H, sg, y.x, y.y, ri, rj);
-        at_pair(H, sg, ri - bv.x, rj - bv.y, gi, gj);
+        dv2 yn = {0.0, 0.0};
+        if (NN && R.hasN) {
+            const dv2 xvn = xc[H.noff + k], xpn = xo[H.noff + k];
+            yn = xvn + beta * (xvn - xpn);
+        }
+        double ri, rj;
+        a_row<NN>(H, R, make_double2(y.x, y.y), make_double2(yn.x, yn.y), ri, rj);
+        double2 gb, gn;
+        at_row<NN>(H, R, ri - bv.x, rj - bv.y, gb, gn);
         dv2 xn;
-        xn.x = soft_threshold<double>(y.x - gi / L, thr);
-        xn.y = soft_threshold<double>(y.y - gj / L, thr);
+        xn.x = soft_threshold<double>(y.x - gb.x / L, thr);
+        xn.y = soft_threshold<double>(y.y - gb.y / L, thr);
         __builtin_nontemporal_store(xn, xo + k);
+        if (NN && R.hasN) {
+            dv2 xnn;
+            xnn.x = soft_threshold<double>(yn.x - gn.x / L, thr);
+            xnn.y = soft_threshold<double>(yn.y - gn.y / L, thr);
+            xo[H.noff + k] = xnn;
+        }
     }
 }
 
 // ---- PCDM ----------------------------------------------------------------------
-// One synchronous step of section 8.1's PCDM on the pair: from the same x,
+// One synchronous step of section 8.1's PCDM on a row pair: from the same x,
 // every sampled coordinate i takes x_i <- soft(x_i - A_i^T (A x - b) / v_i,
-// tau / v_i) with v_i = beta L_i, L_i = (A^T A)_ii.  Coordinate 2k + e is
-// sampled when word e of Philox counter (k, step, kTagPcdm, 0) is below thr
+// tau / v_i) with v_i = beta L_i, L_i = (A^T A)_ii.  The coordinates of the
+// pair at index q of x (q = k for B's pair, noff + k for N~'s) are sampled
+// when words 0 and 1 of Philox counter (q, step, kTagPcdm, 0) are below thr
 // (every coordinate when thr = 2^32).  x is updated in place.
 constexpr uint32_t kTagPcdm = 0x600u;
 
-template <int SL>
+__device__ __forceinline__ dv2 pcdm_pick(const SgtK& H, int64_t q, uint32_t step, uint64_t thr, dv2 upd, dv2 old) {
+    if (thr < ((uint64_t)1 << 32)) {
+        const U4 w = philox4x32_10((uint32_t)q, step, kTagPcdm, 0u, H.key.k0, H.key.k1);
+        if (!((uint64_t)w.x < thr)) upd.x = old.x;
+        if (!((uint64_t)w.y < thr)) upd.y = old.y;
+    }
+    return upd;
+}
+
+template <int SL, int NN>
 __global__ __launch_bounds__(kHB) void kh_pcdm(SgtK H, dv2* __restrict__ x, const dv2* __restrict__ b, double beta,
                                                uint64_t thr, uint32_t step) {
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
-        const double2 sg = sigma_pair<SL>(H, k);
-        const double2 cn = colnorm_pair<SL>(H, sg);
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row R = load_row<SL, NN>(H, k);
+        double2 cb, cn;
+        colnorm_row<SL, NN>(H, R, cb, cn);
         const dv2 xv = __builtin_nontemporal_load(x + k), bv = __builtin_nontemporal_load(b + k);
-        double ri, rj, gi, gj;
-        a_pair(H, sg, xv.x, xv.y, ri, rj);
-        at_pair(H, sg, ri - bv.x, rj - bv.y, gi, gj);
-        const double vi = beta * cn.x, vj = beta * cn.y;
+        const dv2 xnv = (NN && R.hasN) ? x[H.noff + k] : dv2{0.0, 0.0};
+        double ri, rj;
+        a_row<NN>(H, R, make_double2(xv.x, xv.y), make_double2(xnv.x, xnv.y), ri, rj);
+        double2 gb, gn;
+        at_row<NN>(H, R, ri - bv.x, rj - bv.y, gb, gn);
+        const double vi = beta * cb.x, vj = beta * cb.y;
         dv2 xn;
-        xn.x = soft_threshold<double>(xv.x - gi / vi, H.tau / vi);
-        xn.y = soft_threshold<double>(xv.y - gj / vj, H.tau / vj);
-        if (thr < ((uint64_t)1 << 32)) {
-            const U4 w = philox4x32_10((uint32_t)k, step, kTagPcdm, 0u, H.key.k0, H.key.k1);
-            if (!((uint64_t)w.x < thr)) xn.x = xv.x;
-            if (!((uint64_t)w.y < thr)) xn.y = xv.y;
+        xn.x = soft_threshold<double>(xv.x - gb.x / vi, H.tau / vi);
+        xn.y = soft_threshold<double>(xv.y - gb.y / vj, H.tau / vj);
+        __builtin_nontemporal_store(pcdm_pick(H, k, step, thr, xn, xv), x + k);
+        if (NN && R.hasN) {
+            const double wi = beta * cn.x, wj = beta * cn.y;
+            dv2 xnn;
+            xnn.x = soft_threshold<double>(xnv.x - gn.x / wi, H.tau / wi);
+            xnn.y = soft_threshold<double>(xnv.y - gn.y / wj, H.tau / wj);
+            x[H.noff + k] = pcdm_pick(H, H.noff + k, step, thr, xnn, xnv);
         }
-        __builtin_nontemporal_store(xn, x + k);
     }
 }
 
@@ -422,52 +569,81 @@ __device__ __forceinline__ dv2 precond(double2 cn, dv2 d) {
     return m;
 }
 
-__device__ __forceinline__ dv2 hess_v(const SgtK& H, double2 sg, dv2 p, dv2 d) {
-    const double2 h = hess_pair(H, sg, make_double2(p.x, p.y), make_double2(d.x, d.y));
-    dv2 o;
-    o.x = h.x;
-    o.y = h.y;
-    return o;
+// H p = A^T (A p) + d p on a row pair's coordinates (B's pair and, for IGen2
+// rows, N~'s pair)
+template <int NN>
+__device__ __forceinline__ void hess_row(const SgtK& H, const Row& R, dv2 pb, dv2 pn, dv2 db, dv2 dn, dv2& hb,
+                                         dv2& hn) {
+    double yi, yj;
+    a_row<NN>(H, R, make_double2(pb.x, pb.y), make_double2(pn.x, pn.y), yi, yj);
+    double2 gb, gn;
+    at_row<NN>(H, R, yi, yj, gb, gn);
+    hb.x = gb.x + db.x * pb.x;
+    hb.y = gb.y + db.y * pb.y;
+    hn.x = gn.x + dn.x * pn.x;
+    hn.y = gn.y + dn.y * pn.y;
+}
+
+// gradient of tau psi_mu at x plus a = A^T r, and the Hessian diagonal d
+__device__ __forceinline__ void newton_terms(const SgtK& H, double mu, int primal, dv2 x, dv2 gd, double2 a,
+                                             dv2& grad, dv2& d) {
+    const double wi = sqrt(mu * mu + x.x * x.x), wj = sqrt(mu * mu + x.y * x.y);
+    grad.x = H.tau * x.x / wi + a.x;
+    grad.y = H.tau * x.y / wj + a.y;
+    if (primal) {
+        d.x = H.tau * mu * mu / (wi * wi * wi);
+        d.y = H.tau * mu * mu / (wj * wj * wj);
+    } else {
+        d.x = H.tau * (1.0 - x.x * gd.x / wi) / wi;
+        d.y = H.tau * (1.0 - x.y * gd.y / wj) / wj;
+    }
 }
 
 // Start of a Newton step at x: grad f_mu = tau x / w + A^T (A x - b), the
 // Hessian diagonal d (primal: tau mu^2 / w^3; primal-dual: tau (1 - x gd / w) / w),
 // and PCG's start from dx = 0: r = -grad, u = M r.
 // part = (r.u, u.Hu, r.r | max |grad|).
-template <int SL>
-__global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const double2* __restrict__ x,
-                                                const double2* __restrict__ gd, const double2* __restrict__ b,
-                                                double mu, int primal, double2* __restrict__ d,
-                                                double2* __restrict__ r, double* __restrict__ part) {
+template <int SL, int NN>
+__global__ __launch_bounds__(kHB) void kh_setup(SgtK H, const dv2* __restrict__ x, const dv2* __restrict__ gd,
+                                                const double2* __restrict__ b, double mu, int primal,
+                                                dv2* __restrict__ d, dv2* __restrict__ r, double* __restrict__ part) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
-        const double2 sg = sigma_pair<SL>(H, k);
-        const double2 xv = x[k], bv = b[k];
-        const double2 gv = primal ? make_double2(0.0, 0.0) : gd[k];
-        double yi, yj, ai, aj;
-        a_pair(H, sg, xv.x, xv.y, yi, yj);
-        at_pair(H, sg, yi - bv.x, yj - bv.y, ai, aj);
-        const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
-        const double gri = H.tau * xv.x / wi + ai, grj = H.tau * xv.y / wj + aj;
-        dv2 dv, rv;
-        if (primal) {
-            dv.x = H.tau * mu * mu / (wi * wi * wi);
-            dv.y = H.tau * mu * mu / (wj * wj * wj);
-        } else {
-            dv.x = H.tau * (1.0 - xv.x * gv.x / wi) / wi;
-            dv.y = H.tau * (1.0 - xv.y * gv.y / wj) / wj;
+    const dv2 z2 = {0.0, 0.0};
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row R = load_row<SL, NN>(H, k);
+        const bool hn = NN && R.hasN;
+        const int64_t kn = H.noff + k;
+        const dv2 xb = x[k], xn = hn ? x[kn] : z2;
+        const dv2 gb = primal ? z2 : gd[k], gn = (primal || !hn) ? z2 : gd[kn];
+        const double2 bv = b[k];
+        double yi, yj;
+        a_row<NN>(H, R, make_double2(xb.x, xb.y), make_double2(xn.x, xn.y), yi, yj);
+        double2 ab, an;
+        at_row<NN>(H, R, yi - bv.x, yj - bv.y, ab, an);
+        dv2 grb, db, grn = z2, dn = z2;
+        newton_terms(H, mu, primal, xb, gb, ab, grb, db);
+        if (hn) newton_terms(H, mu, primal, xn, gn, an, grn, dn);
+        double2 cb, cn;
+        colnorm_row<SL, NN>(H, R, cb, cn);
+        const dv2 rb = -grb, rn = -grn;
+        const dv2 ub = precond(cb, db) * rb;
+        const dv2 un = hn ? precond(cn, dn) * rn : z2;
+        dv2 wb, wn;
+        hess_row<NN>(H, R, ub, un, db, dn, wb, wn);
+        d[k] = db;
+        r[k] = rb;
+        v[0] += rb.x * ub.x + rb.y * ub.y;
+        v[1] += wb.x * ub.x + wb.y * ub.y;
+        v[2] += rb.x * rb.x + rb.y * rb.y;
+        v[3] = fmax(v[3], fmax(fabs(grb.x), fabs(grb.y)));
+        if (hn) {
+            d[kn] = dn;
+            r[kn] = rn;
+            v[0] += rn.x * un.x + rn.y * un.y;
+            v[1] += wn.x * un.x + wn.y * un.y;
+            v[2] += rn.x * rn.x + rn.y * rn.y;
+            v[3] = fmax(v[3], fmax(fabs(grn.x), fabs(grn.y)));
         }
-        rv.x = -gri;
-        rv.y = -grj;
-        const dv2 u = precond(colnorm_pair<SL>(H, sg), dv) * rv;
-        const dv2 w = hess_v(H, sg, u, dv);
-        d[k] = make_double2(dv.x, dv.y);
-        r[k] = make_double2(rv.x, rv.y);
-        v[0] += rv.x * u.x + rv.y * u.y;
-        v[1] += w.x * u.x + w.y * u.y;
-        v[2] += rv.x * rv.x + rv.y * rv.y;
-        v[3] = fmax(v[3], fmax(fabs(gri), fabs(grj)));
     }
     store_partials<4, 3>(v, part);
 }
@@ -515,16 +691,17 @@ __device__ __forceinline__ void st2(dv2 v, dv2* p) {
 
 // One PCG iteration: u = M r, p = u + beta p, dx += alpha p, r -= alpha H p,
 // then for the next iteration u = M r, w = H u; part = (r.u, w.u, r.r).
-// first: p and dx are not read (beta = 0, dx = 0).  U pairs per thread per
-// trip (loads issued together), NT: nontemporal accesses.
-template <int SL, int U, bool NT>
+// first: p and dx are not read (beta = 0, dx = 0).  U row pairs per thread
+// per trip (B's loads issued together), NT: nontemporal accesses.
+template <int SL, int NN, int U, bool NT>
 __global__ __launch_bounds__(kHB) void kh_cg_iter(SgtK H, dv2* __restrict__ dx, dv2* __restrict__ r,
                                                   dv2* __restrict__ p, const dv2* __restrict__ d, int first,
                                                   const HCg* __restrict__ cs, double* __restrict__ part) {
     if (cs->done) return;
     const double a = cs->alpha, be = cs->beta;
+    const dv2 z2 = {0.0, 0.0};
     double v[3] = {0.0, 0.0, 0.0};
-    const int64_t np = H.n / 2;
+    const int64_t np = H.np;
     const int64_t S = gstride();
     for (int64_t base = gtid(); base < np; base += U * S) {
         dv2 R[U], D[U], P[U], X[U];
@@ -544,25 +721,165 @@ __global__ __launch_bounds__(kHB) void kh_cg_iter(SgtK H, dv2* __restrict__ dx, 
         for (int q = 0; q < U; ++q) {
             const int64_t k = base + q * S;
             if (k < np) {
-                const double2 sg = sigma_pair<SL>(H, k);
-                const dv2 mq = precond(colnorm_pair<SL>(H, sg), D[q]);
-                const dv2 u0 = mq * R[q];
+                const Row Rw = load_row<SL, NN>(H, k);
+                const bool hn = NN && Rw.hasN;
+                const int64_t kn = H.noff + k;
+                double2 cb, cn;
+                colnorm_row<SL, NN>(H, Rw, cb, cn);
+                dv2 Rn = z2, Dn = z2, Pn = z2, Xn = z2;
+                if (hn) {
+                    Rn = ld2<NT>(r + kn);
+                    Dn = ld2<NT>(d + kn);
+                    if (!first) {
+                        Pn = ld2<NT>(p + kn);
+                        Xn = ld2<NT>(dx + kn);
+                    }
+                }
+                const dv2 mq = precond(cb, D[q]);
+                const dv2 mqn = hn ? precond(cn, Dn) : z2;
+                const dv2 u0 = mq * R[q], u0n = mqn * Rn;
                 const dv2 pv = first ? u0 : u0 + be * P[q];
-                const dv2 sv = hess_v(H, sg, pv, D[q]);
+                const dv2 pvn = first ? u0n : u0n + be * Pn;
+                dv2 sv, svn;
+                hess_row<NN>(H, Rw, pv, pvn, D[q], Dn, sv, svn);
                 const dv2 xo = first ? a * pv : X[q] + a * pv;
                 const dv2 rn = R[q] - a * sv;
                 const dv2 u1 = mq * rn;
-                const dv2 w1 = hess_v(H, sg, u1, D[q]);
+                const dv2 xon = first ? a * pvn : Xn + a * pvn;
+                const dv2 rnn = Rn - a * svn;
+                const dv2 u1n = mqn * rnn;
+                dv2 w1, w1n;
+                hess_row<NN>(H, Rw, u1, u1n, D[q], Dn, w1, w1n);
                 st2<NT>(pv, p + k);
                 st2<NT>(xo, dx + k);
                 st2<NT>(rn, r + k);
                 v[0] += rn.x * u1.x + rn.y * u1.y;
                 v[1] += w1.x * u1.x + w1.y * u1.y;
                 v[2] += rn.x * rn.x + rn.y * rn.y;
+                if (hn) {
+                    st2<NT>(pvn, p + kn);
+                    st2<NT>(xon, dx + kn);
+                    st2<NT>(rnn, r + kn);
+                    v[0] += rnn.x * u1n.x + rnn.y * u1n.y;
+                    v[1] += w1n.x * u1n.x + w1n.y * u1n.y;
+                    v[2] += rnn.x * rnn.x + rnn.y * rnn.y;
+                }
             }
         }
     }
     store_partials<3, 3>(v, part);
+}
+
+// Textbook PCG (the oracle's recurrence), used where the single-reduction form
+// loses accuracy: IGen2's N~ columns carry scales xi_j tau / |N_j^T e| over many
+// orders of magnitude.  Update pass: dx += alpha p, r -= alpha H p, z = M r;
+// part = (r.z, r.r).  first: p = M r (the start direction) is formed here and
+// written, dx is not read.
+template <int SL, int NN>
+__global__ __launch_bounds__(kHB) void kh_tb_update(SgtK H, dv2* __restrict__ dx, dv2* __restrict__ r,
+                                                    dv2* __restrict__ p, const dv2* __restrict__ d, int first,
+                                                    const HCg* __restrict__ cs, double* __restrict__ part) {
+    if (cs->done) return;
+    const double a = cs->alpha;
+    const dv2 z2 = {0.0, 0.0};
+    double v[2] = {0.0, 0.0};
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row Rw = load_row<SL, NN>(H, k);
+        const bool hn = NN && Rw.hasN;
+        const int64_t kn = H.noff + k;
+        double2 cb, cn;
+        colnorm_row<SL, NN>(H, Rw, cb, cn);
+        const dv2 rb = r[k], db = d[k];
+        const dv2 rn = hn ? r[kn] : z2, dn = hn ? d[kn] : z2;
+        const dv2 mb = precond(cb, db), mn = hn ? precond(cn, dn) : z2;
+        const dv2 pb = first ? mb * rb : p[k];
+        const dv2 pn = hn ? (first ? mn * rn : p[kn]) : z2;
+        dv2 hb, hnv;
+        hess_row<NN>(H, Rw, pb, pn, db, dn, hb, hnv);
+        const dv2 xb = first ? a * pb : dx[k] + a * pb;
+        const dv2 r1 = rb - a * hb;
+        const dv2 z1 = mb * r1;
+        dx[k] = xb;
+        r[k] = r1;
+        if (first) p[k] = pb;
+        v[0] += r1.x * z1.x + r1.y * z1.y;
+        v[1] += r1.x * r1.x + r1.y * r1.y;
+        if (hn) {
+            const dv2 xn = first ? a * pn : dx[kn] + a * pn;
+            const dv2 r1n = rn - a * hnv;
+            const dv2 z1n = mn * r1n;
+            dx[kn] = xn;
+            r[kn] = r1n;
+            if (first) p[kn] = pn;
+            v[0] += r1n.x * z1n.x + r1n.y * z1n.y;
+            v[1] += r1n.x * r1n.x + r1n.y * r1n.y;
+        }
+    }
+    store_partials<2, 2>(v, part);
+}
+
+// beta = r.z / previous r.z; one iteration done; stop when ||r|| <= stop or at maxit
+__global__ __launch_bounds__(1024) void kh_tb_beta(const double* __restrict__ part, int nb, HCg* cs, int maxit) {
+    if (cs->done) return;
+    double v[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        v[0] += part[2 * q];
+        v[1] += part[2 * q + 1];
+    }
+    block_reduce_stats<2, 2>(v);
+    if (threadIdx.x == 0) {
+        cs->iters += 1;
+        if (cs->iters >= maxit || !(sqrt(v[1]) > cs->stop)) {
+            cs->done = 1;
+            return;
+        }
+        cs->beta = v[0] / cs->gamma;
+        cs->gamma = v[0];
+    }
+}
+
+// Direction pass: p = M r + beta p; part = p.Hp of the new p
+template <int SL, int NN>
+__global__ __launch_bounds__(kHB) void kh_tb_dir(SgtK H, const dv2* __restrict__ r, dv2* __restrict__ p,
+                                                 const dv2* __restrict__ d, const HCg* __restrict__ cs,
+                                                 double* __restrict__ part) {
+    if (cs->done) return;
+    const double be = cs->beta;
+    const dv2 z2 = {0.0, 0.0};
+    double v[1] = {0.0};
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row Rw = load_row<SL, NN>(H, k);
+        const bool hn = NN && Rw.hasN;
+        const int64_t kn = H.noff + k;
+        double2 cb, cn;
+        colnorm_row<SL, NN>(H, Rw, cb, cn);
+        const dv2 db = d[k], dn = hn ? d[kn] : z2;
+        const dv2 pb = precond(cb, db) * r[k] + be * p[k];
+        const dv2 pn = hn ? precond(cn, dn) * r[kn] + be * p[kn] : z2;
+        dv2 hb, hnv;
+        hess_row<NN>(H, Rw, pb, pn, db, dn, hb, hnv);
+        p[k] = pb;
+        v[0] += pb.x * hb.x + pb.y * hb.y;
+        if (hn) {
+            p[kn] = pn;
+            v[0] += pn.x * hnv.x + pn.y * hnv.y;
+        }
+    }
+    store_partials<1, 1>(v, part);
+}
+
+// alpha = r.z / p.Hp
+__global__ __launch_bounds__(1024) void kh_tb_alpha(const double* __restrict__ part, int nb, HCg* cs) {
+    if (cs->done) return;
+    double v[1] = {0.0};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) v[0] += part[q];
+    block_reduce_stats<1, 1>(v);
+    if (threadIdx.x == 0) {
+        if (v[0] > 0.0)
+            cs->alpha = cs->gamma / v[0];
+        else
+            cs->done = 1;  // no curvature left along p
+    }
 }
 
 // One iteration done: stop when ||r|| <= stop or at maxit; else
@@ -597,34 +914,49 @@ __global__ __launch_bounds__(1024) void kh_cg_next(const double* __restrict__ pa
 // Line search terms at x along dx, for the step lengths a0 2^-t, t < kLsBatch:
 // part = (sum psi(x), sum r(x)^2, grad . dx, sum psi(x + a_t dx) [t], sum r(x + a_t dx)^2 [t])
 // with psi(v) = sqrt(mu^2 + v^2) - mu and r(v) = A v - b.
-template <int SL>
-__global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const double2* __restrict__ x, const double2* __restrict__ dx,
+__device__ __forceinline__ double psi2(double mu, double a, double b) {
+    return (sqrt(mu * mu + a * a) - mu) + (sqrt(mu * mu + b * b) - mu);
+}
+
+template <int SL, int NN>
+__global__ __launch_bounds__(kHB) void kh_ls(SgtK H, const dv2* __restrict__ x, const dv2* __restrict__ dx,
                                              const double2* __restrict__ b, double mu, double a0,
                                              double* __restrict__ part) {
     double v[kLsStats];
 #pragma unroll
     for (int q = 0; q < kLsStats; ++q) v[q] = 0.0;
-    const int64_t np = H.n / 2;
-    for (int64_t k = gtid(); k < np; k += gstride()) {
-        const double2 sg = sigma_pair<SL>(H, k);
-        const double2 xv = x[k], sv = dx[k], bv = b[k];
-        double yi, yj, ai, aj;
-        a_pair(H, sg, xv.x, xv.y, yi, yj);
+    const dv2 z2 = {0.0, 0.0};
+    for (int64_t k = gtid(); k < H.np; k += gstride()) {
+        const Row R = load_row<SL, NN>(H, k);
+        const bool hn = NN && R.hasN;
+        const int64_t kn = H.noff + k;
+        const dv2 xb = x[k], sb = dx[k];
+        const dv2 xn = hn ? x[kn] : z2, sn = hn ? dx[kn] : z2;
+        const double2 bv = b[k];
+        double yi, yj;
+        a_row<NN>(H, R, make_double2(xb.x, xb.y), make_double2(xn.x, xn.y), yi, yj);
         const double ri = yi - bv.x, rj = yj - bv.y;
-        at_pair(H, sg, ri, rj, ai, aj);
-        const double wi = sqrt(mu * mu + xv.x * xv.x), wj = sqrt(mu * mu + xv.y * xv.y);
+        double2 ab, an;
+        at_row<NN>(H, R, ri, rj, ab, an);
+        const double wi = sqrt(mu * mu + xb.x * xb.x), wj = sqrt(mu * mu + xb.y * xb.y);
         v[0] += (wi - mu) + (wj - mu);
         v[1] += ri * ri + rj * rj;
-        v[2] += (H.tau * xv.x / wi + ai) * sv.x + (H.tau * xv.y / wj + aj) * sv.y;
+        v[2] += (H.tau * xb.x / wi + ab.x) * sb.x + (H.tau * xb.y / wj + ab.y) * sb.y;
+        if (hn) {
+            const double wni = sqrt(mu * mu + xn.x * xn.x), wnj = sqrt(mu * mu + xn.y * xn.y);
+            v[0] += (wni - mu) + (wnj - mu);
+            v[2] += (H.tau * xn.x / wni + an.x) * sn.x + (H.tau * xn.y / wnj + an.y) * sn.y;
+        }
         double a = a0;
 #pragma unroll
         for (int t = 0; t < kLsBatch; ++t) {
-            const double ui = xv.x + a * sv.x, uj = xv.y + a * sv.y;
+            const dv2 ub = xb + a * sb, un = xn + a * sn;
             double qi, qj;
-            a_pair(H, sg, ui, uj, qi, qj);
+            a_row<NN>(H, R, make_double2(ub.x, ub.y), make_double2(un.x, un.y), qi, qj);
             qi -= bv.x;
             qj -= bv.y;
-            v[3 + t] += (sqrt(mu * mu + ui * ui) - mu) + (sqrt(mu * mu + uj * uj) - mu);
+            v[3 + t] += psi2(mu, ub.x, ub.y);
+            if (hn) v[3 + t] += psi2(mu, un.x, un.y);
             v[3 + kLsBatch + t] += qi * qi + qj * qj;
             a *= 0.5;
         }
@@ -670,6 +1002,18 @@ void by_law(int law, F&& f) {
         f(std::integral_constant<int, 0>{});
 }
 
+// Run f(SL, NN) as integral constants: the sigma law and whether the
+// instance is IGen2's (row pairs with N~ blocks).
+template <typename F>
+void by_kind(const SgtK& K, F&& f) {
+    by_law(K.sigma_law, [&](auto c) {
+        if (K.nnp > 0)
+            f(c, std::integral_constant<int, 1>{});
+        else
+            f(c, std::integral_constant<int, 0>{});
+    });
+}
+
 }  // namespace
 
 struct l1ls_sgt {
@@ -710,8 +1054,9 @@ l1ls_status sgt_gap(const l1ls_sgt* H, double tau, const double* x, hipStream_t 
                     double* gap, double* part) {
     const int nb = blocks_for(H->k.n / 2);
     SgtK K = H->k;
-    by_law(K.sigma_law, [&](auto c) {
-        hipLaunchKernelGGL(kh_gap<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
+    by_kind(K, [&](auto c, auto nn) {
+        hipLaunchKernelGGL((kh_gap<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0, s, K,
+                           (const double2*)x,
                            (const double2*)H->b, part);
     });
     HIP_TRY(hipGetLastError());
@@ -727,8 +1072,9 @@ l1ls_status sgt_gap(const l1ls_sgt* H, double tau, const double* x, hipStream_t 
 
 l1ls_status sgt_err(const l1ls_sgt* H, const double* x, hipStream_t s, double* out, double* part) {
     const int nb = blocks_for(H->k.n / 2);
-    by_law(H->k.sigma_law, [&](auto c) {
-        hipLaunchKernelGGL(kh_err<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, H->k, (const double2*)x, part);
+    by_kind(H->k, [&](auto c, auto nn) {
+        hipLaunchKernelGGL((kh_err<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0, s, H->k,
+                           (const double2*)x, part);
     });
     HIP_TRY(hipGetLastError());
     double t[2];
@@ -785,7 +1131,9 @@ l1ls_status osgen3_select(l1ls_sgt* H, int64_t rank, hipStream_t s, uint64_t* bi
 
 bool valid_params(const l1ls_sgt_params* p) {
     const int64_t n = p->n, m = p->m;
-    if (n < 2 || n % 2 || n > kSgtMaxN || m < n || m % 2 || p->s < 0 || p->s > n) return false;
+    if (n < 2 || n % 2 || n > kSgtMaxN || m < 2 || m % 2 || p->s < 0 || p->s > std::min(m, n)) return false;
+    // IGen2 (m < n): N~ has n - m <= m columns, x* lies in the first m, OsGen3 is for m >= n
+    if (m < n && (n - m > m || p->xstar_law == L1LS_XSTAR_OSGEN3)) return false;
     if (!(p->tau > 0) || !is_fin(p->tau) || !is_fin(p->theta)) return false;
     if (p->sigma_law == L1LS_SIGMA_ALTERNATING) {
         if (!(p->sigma_odd > 0) || !(p->sigma_even > 0) || !is_fin(p->sigma_odd) || !is_fin(p->sigma_even))
@@ -857,6 +1205,10 @@ extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream,
     K.s = p->s;
     K.s1 = p->s1;
     K.s2 = p->s2;
+    K.np = std::min(p->m, n) / 2;
+    K.nnp = n > p->m ? (n - p->m) / 2 : 0;
+    K.noff = p->m / 2;
+    K.nsup = std::min(p->m, n);
     K.sigma_law = p->sigma_law;
     K.xstar_law = p->xstar_law;
     K.c = std::cos(p->theta);
@@ -881,7 +1233,10 @@ extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream,
     l1ls_status st = H->arena.alloc(&H->b, (size_t)n);
     if (st == L1LS_OK) st = H->arena.alloc(&H->part, (size_t)kHMaxBlocks * kLsStats);
     if (st == L1LS_OK) st = H->arena.alloc(&H->hist, (size_t)kSelBins);
+    double* csw = nullptr;
+    if (st == L1LS_OK && K.nnp > 0) st = H->arena.alloc(&csw, (size_t)(2 * K.nnp));
     if (st != L1LS_OK) return fail(st);
+    K.cs = csw;
     if (K.xstar_law == L1LS_XSTAR_OSGEN3) {
         // the s1 smallest: up to rank s1; the s2 largest: from rank n - s2 + 1
         if (K.s1 > 0) {
@@ -895,16 +1250,17 @@ extern "C" l1ls_status l1ls_sgt_generate(const l1ls_sgt_params* p, void* stream,
         if (st != L1LS_OK) return fail(st);
     }
     const int nb = blocks_for(n / 2);
-    by_law(K.sigma_law, [&](auto c) {
-        hipLaunchKernelGGL(kh_generate<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (double2*)H->b, H->part);
+    by_kind(K, [&](auto c, auto nn) {
+        hipLaunchKernelGGL((kh_generate<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0, s, K,
+                           (double2*)H->b, (double2*)csw, H->part);
     });
     if (hipGetLastError() != hipSuccess) return fail(L1LS_E_HIP);
-    double t[4] = {0, 0, 0, 0};
-    st = host_stats(H->part, 4, 2, nb, s, t);
+    double t[5] = {0, 0, 0, 0, 0};
+    st = host_stats(H->part, 5, 2, nb, s, t);
     if (st != L1LS_OK) return fail(st);
     H->sigma_max = t[2];
     H->sigma_min = -t[3];
-    H->L = H->sigma_max * H->sigma_max;
+    H->L = t[4];  // lambda_max(A A^T): sigma_max^2, or the largest 2 x 2 row block of IGen2's [B, N~]
     // f* = tau ||x*||_1 + 0.5 ||e||^2; Table 1's ||x*||_1 in closed form
     double l1 = t[1];
     if (K.xstar_law == L1LS_XSTAR_TABLE1) {
@@ -927,6 +1283,7 @@ extern "C" l1ls_status l1ls_sgt_describe(const l1ls_sgt* H, l1ls_sgt_desc* out) 
     out->b_dev = H->b;
     out->sigma_min = H->sigma_min;
     out->sigma_max = H->sigma_max;
+    out->colscale_dev = H->k.cs;
     return L1LS_OK;
 }
 
@@ -942,8 +1299,9 @@ extern "C" void l1ls_sgt_free(l1ls_sgt* H) {
 
 extern "C" l1ls_status l1ls_sgt_planted(const l1ls_sgt* H, double* x_star_dev, double* g_dev, void* stream) {
     if (!H || (!x_star_dev && !g_dev)) return L1LS_E_ARG;
-    by_law(H->k.sigma_law, [&](auto c) {
-        hipLaunchKernelGGL(kh_planted<decltype(c)::value>, dim3(blocks_for(H->k.n / 2)), dim3(kHB), 0,
+    by_kind(H->k, [&](auto c, auto nn) {
+        hipLaunchKernelGGL((kh_planted<decltype(c)::value, decltype(nn)::value>), dim3(blocks_for(H->k.n / 2)),
+                           dim3(kHB), 0,
                            (hipStream_t)stream, H->k, x_star_dev, g_dev);
     });
     HIP_TRY(hipGetLastError());
@@ -956,8 +1314,9 @@ extern "C" l1ls_status l1ls_sgt_apply(const l1ls_sgt* H, int32_t trans, const do
     if (!aligned16(in_dev) || !aligned16(out_dev)) return L1LS_E_ARG;
     const int64_t m = H->prm.m;
     const int nb = blocks_for(trans ? H->k.n / 2 : m / 2);
-    by_law(H->k.sigma_law, [&](auto c) {
-        hipLaunchKernelGGL(kh_apply<decltype(c)::value>, dim3(nb), dim3(kHB), 0, (hipStream_t)stream, H->k, m,
+    by_kind(H->k, [&](auto c, auto nn) {
+        hipLaunchKernelGGL((kh_apply<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0,
+                           (hipStream_t)stream, H->k, m,
                            (int)trans, (const double2*)in_dev, (double2*)out_dev);
     });
     HIP_TRY(hipGetLastError());
@@ -973,6 +1332,7 @@ extern "C" l1ls_status l1ls_sgt_objective_gap(const l1ls_sgt* H, double tau, con
 
 extern "C" l1ls_status l1ls_sgt_kappa_rho(const l1ls_sgt* H, double rho, double* kappa, void* stream) {
     if (!H || !kappa || !(rho >= 0) || !is_fin(rho)) return L1LS_E_ARG;
+    if (H->k.nnp > 0) return L1LS_E_UNSUPPORTED;  // A^T A is singular for m < n (section 5)
     hipStream_t s = (hipStream_t)stream;
     const int nb = blocks_for(H->k.n / 2);
     by_law(H->k.sigma_law, [&](auto c) {
@@ -1051,8 +1411,9 @@ extern "C" l1ls_status l1ls_sgt_solve_fista(const l1ls_sgt* H, const l1ls_solve_
             const int64_t batch = std::min<int64_t>(check - (k % check), o->max_iter - k);
             for (int64_t q = 0; q < batch; ++q) {
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
-                by_law(K.sigma_law, [&](auto c) {
-                    hipLaunchKernelGGL(kh_fista<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const dv2*)cur,
+                by_kind(K, [&](auto c, auto nn) {
+                    hipLaunchKernelGGL((kh_fista<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0,
+                                       s, K, (const dv2*)cur,
                                        (dv2*)old, (const dv2*)H->b, beta, L, tau / L);
                 });
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
@@ -1106,8 +1467,10 @@ extern "C" l1ls_status l1ls_sgt_solve_pcdm(const l1ls_sgt* H, const l1ls_solve_o
     const double p = (o->pcdm_p > 0 && o->pcdm_p < 1) ? o->pcdm_p : 1.0;
     const int check = std::max(1, o->check_every);
     if (!is_fin(tau)) return L1LS_E_ARG;
-    // omega = 2 nonzeros per row; beta of a doubly uniform sampling with E|S| = n p
-    const double beta = 1.0 + (2 - 1) * p;
+    // omega nonzeros per row (2, or 4 in IGen2's rows with an N~ block); beta of a
+    // doubly uniform sampling with E|S| = n p
+    const int omega = H->k.nnp > 0 ? 4 : 2;
+    const double beta = 1.0 + (omega - 1) * p;
     const uint64_t thr = p >= 1.0 ? ((uint64_t)1 << 32) : (uint64_t)(p * 4294967296.0);
     SgtK K = H->k;
     K.tau = tau;
@@ -1144,8 +1507,9 @@ extern "C" l1ls_status l1ls_sgt_solve_pcdm(const l1ls_sgt* H, const l1ls_solve_o
             const int64_t batch = std::min<int64_t>(check - (k % check), o->max_iter - k);
             for (int64_t q = 0; q < batch; ++q) {
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
-                by_law(K.sigma_law, [&](auto c) {
-                    hipLaunchKernelGGL(kh_pcdm<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (dv2*)x,
+                by_kind(K, [&](auto c, auto nn) {
+                    hipLaunchKernelGGL((kh_pcdm<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0,
+                                       s, K, (dv2*)x,
                                        (const dv2*)H->b, beta, thr, (uint32_t)k);
                 });
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
@@ -1262,8 +1626,24 @@ struct l1ls_sgt_newton {
             const int skip = first;  // the first iteration reads no p, dx: not timed
             for (int q = 0; q < kBatch; ++q) {
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q], s));
-                by_law(K.sigma_law, [&](auto c) {
-                    hipLaunchKernelGGL((kh_cg_iter<decltype(c)::value, kHU, kHNT>), dim3(nb), dim3(kHB), 0, s, K,
+                if (K.nnp > 0) {
+                    // IGen2: the textbook recurrence (two passes per iteration)
+                    by_law(K.sigma_law, [&](auto c) {
+                        hipLaunchKernelGGL((kh_tb_update<decltype(c)::value, 1>), dim3(nb), dim3(kHB), 0, s, K,
+                                           (dv2*)dx, (dv2*)r, (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
+                        hipLaunchKernelGGL(kh_tb_beta, dim3(1), dim3(1024), 0, s, part, nb, cs, pcgmax);
+                        hipLaunchKernelGGL((kh_tb_dir<decltype(c)::value, 1>), dim3(nb), dim3(kHB), 0, s, K,
+                                           (const dv2*)r, (dv2*)p, (const dv2*)d, (const HCg*)cs, part);
+                        hipLaunchKernelGGL(kh_tb_alpha, dim3(1), dim3(1024), 0, s, part, nb, cs);
+                    });
+                    if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
+                    first = 0;
+                    continue;
+                }
+                by_kind(K, [&](auto c, auto nn) {
+                    constexpr int NN = decltype(nn)::value;
+                    hipLaunchKernelGGL((kh_cg_iter<decltype(c)::value, NN, NN ? 1 : kHU, kHNT>), dim3(nb),
+                                       dim3(kHB), 0, s, K,
                                        (dv2*)dx, (dv2*)r, (dv2*)p, (const dv2*)d, first, (const HCg*)cs, part);
                 });
                 if (tk) HIP_TRY(hipEventRecord(ev[2 * q + 1], s));
@@ -1292,9 +1672,9 @@ struct l1ls_sgt_newton {
         for (int t0b = 0; t0b < maxbt && !found; t0b += kLsBatch) {
             const double a0 = std::ldexp(1.0, -t0b);
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
-            by_law(K.sigma_law, [&](auto c) {
-                hipLaunchKernelGGL(kh_ls<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
-                                   (const double2*)dx, (const double2*)H->b, mu, a0, part);
+            by_kind(K, [&](auto c, auto nn) {
+                hipLaunchKernelGGL((kh_ls<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0, s, K,
+                                   (const dv2*)x, (const dv2*)dx, (const double2*)H->b, mu, a0, part);
             });
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
             HIP_TRY(hipGetLastError());
@@ -1324,10 +1704,10 @@ struct l1ls_sgt_newton {
     l1ls_status steps(int64_t k) {
         for (int64_t q = 0; q < k && !converged; ++q) {
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch], s));
-            by_law(K.sigma_law, [&](auto c) {
-                hipLaunchKernelGGL(kh_setup<decltype(c)::value>, dim3(nb), dim3(kHB), 0, s, K, (const double2*)x,
-                                   (const double2*)gd, (const double2*)H->b, mu, primal, (double2*)d, (double2*)r,
-                                   part);
+            by_kind(K, [&](auto c, auto nn) {
+                hipLaunchKernelGGL((kh_setup<decltype(c)::value, decltype(nn)::value>), dim3(nb), dim3(kHB), 0, s,
+                                   K, (const dv2*)x, (const dv2*)gd, (const double2*)H->b, mu, primal, (dv2*)d,
+                                   (dv2*)r, part);
             });
             if (tk) HIP_TRY(hipEventRecord(ev[2 * kBatch + 1], s));
             hipLaunchKernelGGL(kh_cg_init, dim3(1), dim3(1024), 0, s, part, nb, cs, prtol, pcgmax);

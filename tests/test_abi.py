@@ -117,7 +117,7 @@ def test_sgt_params_default_is_section_8_9():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n", 7), ("n", 0), ("n", 2 ** 33), ("m", 6), ("m", 9), ("s", 9), ("s", -1),
+    ("n", 7), ("n", 0), ("n", 2 ** 33), ("m", 2), ("m", 9), ("s", 9), ("s", -1),
     ("sigma_odd", 0.0), ("sigma_even", -1.0), ("tau", 0.0), ("theta", float("nan")),
     ("x_neg", float("inf")), ("tau", float("nan")),
 ])
@@ -150,7 +150,10 @@ def test_sgt_null_arguments():
 def test_law_validation():
     for kw in (dict(sigma_law=2), dict(xstar_law=3), dict(sigma_law=L.SIGMA_UNIFORM, sigma_shift=0.0),
                dict(xstar_law=L.XSTAR_OSGEN, gamma=0.0), dict(xstar_law=L.XSTAR_OSGEN3, s1=3, s2=3),
-               dict(sigma_law=L.SIGMA_UNIFORM, sigma_scale=-1.0)):
-        p = L.sgt_params(64, 1, s=4, **kw)
+               dict(sigma_law=L.SIGMA_UNIFORM, sigma_scale=-1.0),
+               dict(m=30),                                   # IGen2 needs n - m <= m
+               dict(m=48, xstar_law=L.XSTAR_OSGEN3),         # OsGen3 is for m >= n
+               dict(m=48, s=50), dict(m=47)):
+        p = L.sgt_params(64, 1, s=kw.pop("s", 4), **kw)
         h = ctypes.c_void_p()
         assert L.lib().l1ls_sgt_generate(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value

@@ -372,3 +372,106 @@ def test_pcdm_reaches_objective_target():
     x, rep, st = H.solve_pcdm(max_iter=5000, rel_gap_tol=0.0, f_target=target * (1 + 1e-12), check_every=8)
     assert st == L.L1LS_OK and rep["iterations"] % 8 == 0 and rep["primal"] <= target * (1 + 1e-12)
     H.free()
+
+
+# ---- IGen2 (section 3.2, m < n) -------------------------------------------------
+IGEN2_CASES = [
+    (64, 96, 6, dict()),
+    (130, 260, 9, dict(sigma_law="uniform", sigma_scale=10.0, xstar_law="osgen", gamma=3.0, tau=0.37)),
+    (1026, 1030, 5, dict(sigma_law="uniform", sigma_scale=100.0, xstar_law="osgen", gamma=10.0)),
+    (4098, 6000, 40, dict(theta=2 * math.pi / 10, sigma_law="uniform", sigma_scale=1.0, xstar_law="osgen",
+                          gamma=5.0)),
+]
+
+
+def make_igen2(m, n, s, kw):
+    from oracle.sgt import SgtIGen2Instance
+    dev_kw = dict(kw)
+    if "sigma_law" in dev_kw:
+        dev_kw["sigma_law"] = _SIGMA[dev_kw["sigma_law"]]
+    if "xstar_law" in dev_kw:
+        dev_kw["xstar_law"] = _XSTAR[dev_kw["xstar_law"]]
+    H = L.SgtInstance(L.sgt_params(n, SEED, m=m, s=s, **dev_kw))
+    O = SgtIGen2Instance(m, n, s, SEED, **kw)
+    return H, O
+
+
+@pytest.mark.parametrize("case", IGEN2_CASES)
+def test_igen2_generation_is_bitwise_the_oracle(case):
+    m, n, s, kw = case
+    H, O = make_igen2(m, n, s, kw)
+    d = H.describe()
+    torch.cuda.synchronize()
+    assert np.array_equal(L.device_to_numpy(d.b_dev, m, np.float64), O.b)
+    assert np.array_equal(L.device_to_numpy(d.colscale_dev, n - m, np.float64), O.colscale)
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty(n, dtype=torch.float64, device="cuda")
+    H.planted(xs, g)
+    assert np.array_equal(host(xs), O.xstar)
+    assert np.array_equal(host(g)[:m], O.g) and not host(g)[m:].any()
+    assert d.f_star == pytest.approx(O.fstar, rel=1e-13)
+    if O.L is not None:
+        assert d.L == pytest.approx(O.L, rel=1e-13)
+    with pytest.raises(L.L1lsError):
+        H.kappa_rho(0.1)
+    H.free()
+
+
+@pytest.mark.parametrize("case", IGEN2_CASES[:3])
+def test_igen2_products_and_gap_match_oracle(case):
+    m, n, s, kw = case
+    H, O = make_igen2(m, n, s, kw)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    ax = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    aty = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    H.apply(0, dev(x), ax)
+    H.apply(1, dev(y), aty)
+    A = O.sparse_A()
+    scale = np.abs(A.data).max()
+    assert np.abs(host(ax) - O.matvec(x)).max() <= 16 * np.finfo(float).eps * scale * np.abs(x).max()
+    assert np.abs(host(aty) - O.rmatvec(y)).max() <= 16 * np.finfo(float).eps * scale * np.abs(y).max()
+    P, D, gap = H.objective_gap(O.tau, dev(O.xstar))
+    Po, Do, go = OF.duality_gap(lambda v: A @ v, lambda v: A.T @ v, O.b, O.tau, O.xstar)
+    assert P == pytest.approx(Po, rel=1e-12) and abs(gap) <= 1e-8
+    H.free()
+
+
+@pytest.mark.parametrize("case", IGEN2_CASES[1:3])
+@pytest.mark.parametrize("iters", [1, 10, 100])
+def test_igen2_fista_and_pcdm_trajectories_match_oracle(case, iters):
+    from oracle.sgt import pcdm
+    m, n, s, kw = case
+    H, O = make_igen2(m, n, s, kw)
+    L_dev = H.describe().L
+    x, rep, st = H.solve_fista(max_iter=iters, rel_gap_tol=0.0, check_every=7)
+    xo = OF.fista(O.matvec, O.rmatvec, O.b, O.tau, L_dev, iters)
+    assert np.abs(host(x) - xo).max() <= 1e-11 * max(1.0, np.abs(xo).max())
+    for p in (1.0, 0.3):
+        x, rep, st = H.solve_pcdm(max_iter=iters, rel_gap_tol=0.0, check_every=7, pcdm_p=p)
+        xp = pcdm(O, O.tau, iters, p=p, omega=4)
+        assert np.abs(host(x) - xp).max() <= 1e-11 * max(1.0, np.abs(xp).max())
+    H.free()
+
+
+@pytest.mark.parametrize("case", IGEN2_CASES[1:3])
+def test_igen2_cg_newton_matches_oracle(case):
+    # The first two Newton steps agree to 1e-6.  After that, N~'s column
+    # scales (over six orders of magnitude) make the Newton systems so badly
+    # conditioned that the two sides' PCGs, rounding in different orders, stop
+    # at different iterations: the comparison is then the converged minimiser.
+    m, n, s, kw = case
+    H, O = make_igen2(m, n, s, kw)
+    x, rep, st = H.solve_cg_newton(max_iter=2)
+    xo, sto = ON.newton_cg(O.matvec, O.rmatvec, O.colnorm2(), O.b, O.tau, max_newton=2)
+    assert rep["iterations"] == 2 and rep["inner"] == sto["pcg"]
+    assert np.abs(host(x) - xo).max() <= 1e-6 * np.abs(xo).max()
+    x, rep, st = H.solve_cg_newton(max_iter=200, rel_gap_tol=1e-8 / O.tau)
+    xo, sto = ON.newton_cg(O.matvec, O.rmatvec, O.colnorm2(), O.b, O.tau, max_newton=200, grad_tol=1e-8)
+    assert st == L.L1LS_OK and sto["grad_inf"] <= 1e-8
+    x = host(x)
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+    ro = np.linalg.norm(xo - O.xstar) / np.linalg.norm(O.xstar)
+    assert rep["rel_err"] == pytest.approx(ro, rel=1e-3)
+    H.free()
