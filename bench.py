@@ -682,6 +682,10 @@ def grid_instances(log2n):
     for ln in (20, 22, 24, 26):
         out.append(("8.6", 1 << ln, f"n=2^{ln} OsGen3 gamma=100 theta=2pi/10",
                     dict(theta=2 * math.pi / 10, sigma_law=1, sigma_scale=10.0, xstar_law=2, gamma=100.0)))
+    # Procedure IGen2 (section 3.2): m = n rows of B plus n/2 columns of N~
+    for q in range(3):
+        out.append(("3.2", n + n // 2, f"IGen2 m={n} n=1.5m q={q} OsGen gamma=10 theta=2pi/3",
+                    dict(m=n, sigma_law=1, sigma_scale=10.0 ** q, xstar_law=1, gamma=10.0)))
     return out
 
 
@@ -702,13 +706,13 @@ def bench_grid(args):
     for sec, n, label, kw in grid_instances(args.grid_log2n):
         if args.grid_sections and sec not in args.grid_sections:
             continue
-        p = L.sgt_params(n, 1503035207, s=n // 128, **kw)
+        p = L.sgt_params(n, 1503035207, s=min(n, kw.get("m", n)) // 128, **kw)
         t = time.perf_counter()
         H = L.SgtInstance(p, stream=stream)
         torch.cuda.synchronize()
         gen_s = time.perf_counter() - t
         d = H.describe()
-        k_rho = H.kappa_rho(0.1)
+        k_rho = H.kappa_rho(0.1) if sec != "3.2" else None  # not defined for m < n (section 5)
         x = torch.empty(n, dtype=torch.float64, device="cuda")
         _, rn, _ = H.solve_cg_newton(x_out=x, max_iter=args.grid_newton, rel_gap_tol=1e-9, stream=stream)
         f_cgn = rn["primal"]
@@ -719,7 +723,8 @@ def bench_grid(args):
             fista_pass = (n, kt["iteration"][0] / max(kt["iteration"][1], 1))
         _, rp, stp = H.solve_pcdm(x_out=x, max_iter=args.grid_fista_max, rel_gap_tol=0.0, f_target=f_cgn,
                                   check_every=args.check_every, stream=stream, pcdm_p=1.0)
-        row = {"section": sec, "instance": label, "n": n, "kappa_AtA": (d.sigma_max / d.sigma_min) ** 2,
+        row = {"section": sec, "instance": label, "n": n, "m": p.m, "L": d.L,
+               "kappa_AtA": (d.sigma_max / d.sigma_min) ** 2 if sec != "3.2" else None,
                "kappa_0.1_xstar": k_rho, "generate_s": gen_s,
                "cg_newton": {"newton_steps": rn["iterations"], "pcg_iterations": rn["inner"], "seconds": rn["seconds"],
                              "f": f_cgn, "rel_err": rn["rel_err"], "converged": rn["converged"]},
@@ -738,10 +743,11 @@ def bench_grid(args):
         "metric": "seconds for the sections 8.4-8.6 instance grid (CG-Newton, then FISTA and PCDM to CG-Newton's objective)",
         "value": total, "unit": "s", "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": total * 1e3 / max(len(rows), 1),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (sections 8.4-8.6 instances generated on the device, seed 1503035207)",
+        "data": "synthetic (sections 8.4-8.6 and IGen2 instances generated on the device, seed 1503035207)",
         "config": {"workload": "sections 8.4-8.6: A = Sigma G^T, m = 2n, s = n/2^7, sigma uniform on [0, 10^q] + 0.1; "
                                "8.4: OsGen gamma 10 / 1e3, q = 0..5, theta = 2 pi/3; 8.5: OsGen3 gamma = 100, q = 0..3, "
-                               "theta = 2 pi/10 and 2 pi/10^3; 8.6: OsGen3, q = 1, n = 2^20..2^26",
+                               "theta = 2 pi/10 and 2 pi/10^3; 8.6: OsGen3, q = 1, n = 2^20..2^26; "
+                               "3.2: IGen2 with m = 2^22, n = 1.5 m, q = 0..2",
                    "n": 1 << args.grid_log2n, "newton_cap": args.grid_newton, "fista_cap": args.grid_fista_max},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": None, "kernel": "kh_fista (FISTA iteration on the pairs)",
@@ -785,7 +791,7 @@ def main():
     ap.add_argument("--grid-log2n", type=int, default=22)
     ap.add_argument("--grid-newton", type=int, default=30)
     ap.add_argument("--grid-fista-max", type=int, default=20000)
-    ap.add_argument("--grid-sections", nargs="*", default=None, help="subset of 8.4 8.5 8.6")
+    ap.add_argument("--grid-sections", nargs="*", default=None, help="subset of 8.4 8.5 8.6 3.2")
     ap.add_argument("--newton-steps", type=int, default=8)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
