@@ -143,6 +143,20 @@ def algorithmic_bytes(m, n, nnz, es=4, ie=4):
     return k1, k2
 
 
+def blocked_bytes(m, n, nruns):
+    """Bytes one launch of each pass over the blocked operator must move (FP32).
+
+    residual pass:  run pointer (m+1), start + 4 values per row run (nruns),
+                    x gathered once (n + 2 with the wrap copies),
+                    b, r_x read, r_x write, r_y write (4 m-vectors)
+    transpose pass: start + 4 values per column run (4 per column),
+                    r_y gathered once (m + 2), x_{k-1}, x_{k-2} read, x_k write
+    """
+    k1 = 4 * (m + 1) + 20 * nruns + 4 * (n + 2) + 16 * m
+    k2 = 20 * 4 * n + 4 * (m + 2) + 12 * n
+    return k1, k2
+
+
 def mf_bytes(m, n, es=4):
     """Algorithmic bytes of one matrix-free FISTA iteration (FP32, two stages).
 
@@ -856,7 +870,8 @@ def main():
     kappa, s, tau, seed, rounds = 1e4, max(1, n // 100), 1.0, 1503035201, 2
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream)
+    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream,
+                           storage=L.STORE_F32 | L.STORE_F64 | L.STORE_BLK32)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     nnz = inst.info().nnz
@@ -892,6 +907,12 @@ def main():
     # applied on the fly), reported beside the stored-operator figure
     mfree = run(args.steps, args.warmup, 0, op=L.OP_MATRIX_FREE)
     mfree_t = run(args.steps, args.warmup, 1, op=L.OP_MATRIX_FREE)
+    # and over the blocked stored operator (runs of four stage positions)
+    blk = run(args.steps, args.warmup, 0, op=L.OP_BLOCKED)
+    blk_t = run(args.steps, args.warmup, 1, op=L.OP_BLOCKED)
+    b1, b2 = blocked_bytes(m, n, 4 * n)
+    bavg = [blk_t["kernel_ms"][i] / max(blk_t["kernel_launches"][i], 1) for i in range(3)]
+    bgap = L.l1ls_objective_gap(inst, tau, blk["x"])[2]
     ms_per_step = plain["ms"] / args.steps
     value = args.steps / (plain["ms"] / 1e3)
 
@@ -948,6 +969,16 @@ def main():
                 "kernel_avg_us": {k: mfree_t["kernel_ms"][i] / max(mfree_t["kernel_launches"][i], 1) * 1e3
                                   for i, k in enumerate(("residual_pair", "transpose_pair", "gap"))},
                 "bytes_per_iter": mf_bytes(m, n),
+            },
+            "blocked": {
+                "iters_per_s": args.steps / (blk["ms"] / 1e3),
+                "ms_per_step": blk["ms"] / args.steps,
+                "kernel_avg_us": {"residual": bavg[0] * 1e3, "transpose_prox": bavg[1] * 1e3,
+                                  "gap": bavg[2] * 1e3},
+                "algorithmic_gbs": {"residual": b1 / (bavg[0] * 1e-3) / 1e9,
+                                    "transpose_prox": b2 / (bavg[1] * 1e-3) / 1e9},
+                "bytes_per_iter": b1 + b2,
+                "final_rel_gap_fp64": bgap,
             },
         },
     }

@@ -50,7 +50,8 @@ typedef enum { L1LS_F32 = 0, L1LS_F64 = 1 } l1ls_precision;
 /* Operator used for products with A and A^T. */
 typedef enum {
     L1LS_OP_STORED = 0,      /* stored CSR (A x) and CSC (A^T y) */
-    L1LS_OP_MATRIX_FREE = 1  /* Givens stages applied on the fly (MvPA/MvPAt) */
+    L1LS_OP_MATRIX_FREE = 1, /* Givens stages applied on the fly (MvPA/MvPAt) */
+    L1LS_OP_BLOCKED = 2      /* stored runs of four (L1LS_STORE_BLK32), FP32 only */
 } l1ls_operator;
 
 /* Row/column order of the stored CSR/CSC.  NATURAL: A as defined.  STAGE:
@@ -64,6 +65,16 @@ typedef enum { L1LS_LAYOUT_NATURAL = 0, L1LS_LAYOUT_STAGE = 1 } l1ls_layout;
 /* Storage kept by l1ls_generate_ex (bit mask). */
 #define L1LS_STORE_F32 1u    /* CSR + CSC values in FP32 (int32 indices)   */
 #define L1LS_STORE_F64 2u    /* CSR + CSC values in FP64 (same indices)     */
+/* Blocked A for two stages in the STAGE layout.  With G = S_2 S_1 and
+ * Q = S~_2 S~_1 (eq. (16)), A is the sum over the middle indices i < n of
+ * sigma_i (Q e_i)(G e_i)^T, and Q e_i, G e_i each cover four consecutive
+ * stage positions (section 4.2 pairs).  Every row of A is then stored as
+ * 0..4 runs (one int32 start and four FP32 values each) and every column as
+ * exactly four, 20 bytes per four entries against 32 for CSR/CSC; values
+ * are rounded once from FP64 per term, so they differ from the CSR/CSC
+ * values (sums of terms) by FP32 rounding.  Requires rounds = 2,
+ * layout = STAGE and n >= 4 (else L1LS_E_UNSUPPORTED). */
+#define L1LS_STORE_BLK32 4u
 
 typedef struct {
     int32_t rounds;      /* Givens stages per side, 1 or 2 (nnz/col <= 4^rounds) */

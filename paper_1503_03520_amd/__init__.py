@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libl1ls.so")
 L1LS_OK = 0
 L1LS_NOT_CONVERGED = 1
 F32, F64 = 0, 1
-OP_STORED, OP_MATRIX_FREE = 0, 1
-STORE_F32, STORE_F64 = 1, 2
+OP_STORED, OP_MATRIX_FREE, OP_BLOCKED = 0, 1, 2
+STORE_F32, STORE_F64, STORE_BLK32 = 1, 2, 4
 REQ_FP64_FINISH = 1
 SIGMA_ALTERNATING, SIGMA_UNIFORM = 0, 1
 XSTAR_TABLE1, XSTAR_OSGEN, XSTAR_OSGEN3 = 0, 1, 2

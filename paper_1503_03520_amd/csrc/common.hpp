@@ -136,6 +136,15 @@ struct l1ls_instance {
     int32_t* csc_row = nullptr;
     double* csc_v64 = nullptr;
     float* csc_v32 = nullptr;
+    // Blocked operator (two stages, stage order; see blocks.hip): row runs
+    // (pointer, start, 4 FP32 values each) and exactly four runs per column
+    // (slot h of column a at h * n + a).  Starts index the extended layout.
+    int32_t* blk_rptr = nullptr;  // m+1
+    int32_t* blk_rstart = nullptr;
+    float* blk_rval = nullptr;    // 4 per run
+    int32_t* blk_cstart = nullptr;  // 4n
+    float* blk_cval = nullptr;    // 4 per run
+    int64_t blk_nruns = 0;
     DevArena arena;
 };
 

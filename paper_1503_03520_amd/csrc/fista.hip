@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -19,6 +20,14 @@ template <typename T>
 void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
                          T thr, double* part, const GapState* gs, int stats, hipStream_t s);
 int mf_grid(int64_t pairs);
+void blk_residual_launch(const l1ls_instance* I, const float* xe, const float* b, float* rx, float* rye, float beta,
+                         int init, double* part, const GapState* gs, int stats, hipStream_t s);
+void blk_transpose_launch(const l1ls_instance* I, const float* rye, const float* xc, float* xpe, float beta, float L,
+                          float thr, double* part, const GapState* gs, int stats, hipStream_t s);
+int blk_row_blocks(int64_t m);
+int blk_col_blocks(int64_t n);
+void blk_wrap_launch(float* e, int64_t N, hipStream_t s);
+l1ls_status apply_blocked(const l1ls_instance* I, int trans, const float* in, float* out, hipStream_t s);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
 
@@ -130,6 +139,10 @@ struct l1ls_fista {
     void* wbuf = nullptr;      // matrix-free: Sigma G^T x_k in n-stage order (n), made by the transpose pass
     void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in m-stage order (m), made by the residual pass
     bool mf = false;           // matrix-free operator (stage order)
+    // Blocked operator: x slots and r_y hold one leading element (the wrap
+    // copy) before the pointers above and one after their last element, the
+    // extended layout of blocks.hip.
+    bool blk = false;
     const int32_t* col_of = nullptr;   // position -> original index of x
     const int32_t* col_pos = nullptr;  // original index -> position
     double* k1part = nullptr;  // [2][g1][3], slot k & 1 written by the residual pass of iteration k
@@ -222,6 +235,13 @@ const double* mf_b<double>(const l1ls_instance* I) { return I->mf_b64; }
 template <typename T>
 l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
     const l1ls_instance* I = F->I;
+    if constexpr (std::is_same<T, float>::value) {
+        if (F->blk)
+            return timed(F, 0, [&] {
+                blk_residual_launch(I, x - 1, b_vec<float>(I), (float*)F->rx, (float*)F->ry - 1, (float)beta,
+                                    init, F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats, F->stream);
+            });
+    }
     if (F->mf)
         return timed(F, 0, [&] {
             T* rx_out = (T*)(slot ? F->rx2 : F->rx);
@@ -240,6 +260,13 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
 template <typename T>
 l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double beta, int stats) {
     const l1ls_instance* I = F->I;
+    if constexpr (std::is_same<T, float>::value) {
+        if (F->blk)
+            return timed(F, 1, [&] {
+                blk_transpose_launch(I, (const float*)F->ry - 1, xc, xp - 1, (float)beta, (float)F->L,
+                                     (float)(F->tau / F->L), F->k2part, F->gs, stats, F->stream);
+            });
+    }
     if (F->mf)
         return timed(F, 1, [&] {
             mf_transpose_launch<T>(I, (const T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
@@ -323,10 +350,12 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if (!I || !opts || !out) return L1LS_E_ARG;
     *out = nullptr;
     if (opts->precision != L1LS_F32 && opts->precision != L1LS_F64) return L1LS_E_ARG;
-    if (opts->op != L1LS_OP_STORED && opts->op != L1LS_OP_MATRIX_FREE) return L1LS_E_ARG;
+    if (opts->op != L1LS_OP_STORED && opts->op != L1LS_OP_MATRIX_FREE && opts->op != L1LS_OP_BLOCKED)
+        return L1LS_E_ARG;
     if (opts->check_every < 1 || opts->max_iter < 0 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
     if (opts->op == L1LS_OP_STORED) L1LS_TRY(check_stored(I, opts->precision));
     if (opts->op == L1LS_OP_MATRIX_FREE && !I->mf_emb) return L1LS_E_UNSUPPORTED;
+    if (opts->op == L1LS_OP_BLOCKED && (opts->precision != L1LS_F32 || !I->blk_rptr)) return L1LS_E_UNSUPPORTED;
     const double tau = opts->tau > 0 ? opts->tau : I->tau;
     const double L = opts->L > 0 ? opts->L : I->L;
     if (!is_finite(tau) || !is_finite(L)) return L1LS_E_ARG;
@@ -339,8 +368,9 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     F->tau = tau;
     F->L = L;
     F->mf = (opts->op == L1LS_OP_MATRIX_FREE);
-    F->g1 = F->mf ? mf_grid(I->m / 2) : tile_grid(I->m);
-    F->g2 = F->mf ? mf_grid(I->n / 2) : tile_grid(I->n);
+    F->blk = (opts->op == L1LS_OP_BLOCKED);
+    F->g1 = F->mf ? mf_grid(I->m / 2) : F->blk ? blk_row_blocks(I->m) : tile_grid(I->m);
+    F->g2 = F->mf ? mf_grid(I->n / 2) : F->blk ? blk_col_blocks(I->n) : tile_grid(I->n);
     F->col_of = F->mf ? I->side[0].perm : I->op_col_of;
     F->col_pos = F->mf ? I->side[0].pinv : I->op_col_pos;
     const size_t es = (F->prec == L1LS_F32) ? sizeof(float) : sizeof(double);
@@ -351,10 +381,17 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     };
     unsigned char *x0 = nullptr, *x1 = nullptr, *rx = nullptr, *ry = nullptr;
     l1ls_status st;
-    if ((st = F->arena.alloc(&x0, I->n * es)) != L1LS_OK) return fail(st);
-    if ((st = F->arena.alloc(&x1, I->n * es)) != L1LS_OK) return fail(st);
+    // extended layout (blocked operator): one element before, one after
+    const int64_t pad = F->blk ? 2 : 0;
+    if ((st = F->arena.alloc(&x0, (I->n + pad) * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&x1, (I->n + pad) * es)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&rx, I->m * es)) != L1LS_OK) return fail(st);
-    if ((st = F->arena.alloc(&ry, I->m * es)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&ry, (I->m + pad) * es)) != L1LS_OK) return fail(st);
+    if (F->blk) {
+        x0 += es;
+        x1 += es;
+        ry += es;
+    }
     if (F->mf) {
         // Sigma G^T x in n-stage order; Sigma^T Q^T r_y in m-stage order (its
         // inactive positions are never read)
@@ -395,7 +432,10 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
         else
             hipLaunchKernelGGL(k_fill<float>, g1d(I->n), dim3(L1LS_BLOCK), 0, s, (float*)x0, 0.0f, I->n);
     }
-    if (hipMemcpyAsync(x1, x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(L1LS_E_HIP);
+    if (F->blk) blk_wrap_launch((float*)x0 - 1, I->n, s);
+    if (hipMemcpyAsync(x1 - pad / 2 * es, x0 - pad / 2 * es, (I->n + pad) * es, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return fail(L1LS_E_HIP);
     if (F->x[2] && hipMemcpyAsync(F->x[2], x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(L1LS_E_HIP);
     hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
@@ -519,6 +559,10 @@ extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t
     if (op == L1LS_OP_MATRIX_FREE) {
         if (prec == L1LS_F64) return apply_matrix_free<double>(I, trans, (const double*)in, (double*)out, s);
         return apply_matrix_free<float>(I, trans, (const float*)in, (float*)out, s);
+    }
+    if (op == L1LS_OP_BLOCKED) {
+        if (prec != L1LS_F32) return L1LS_E_UNSUPPORTED;
+        return apply_blocked(I, trans, (const float*)in, (float*)out, s);
     }
     if (op != L1LS_OP_STORED) return L1LS_E_ARG;
     L1LS_TRY(check_stored(I, prec));

@@ -323,6 +323,7 @@ template l1ls_status apply_side<double>(const SideTables&, int, bool, double*, d
 template l1ls_status apply_side<float>(const SideTables&, int, bool, float*, float*, hipStream_t);
 
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s);
+l1ls_status build_blocks(l1ls_instance* I, hipStream_t s, DevArena& tmp);
 
 // l1ls_generate_ex with the instance's device memory (and the build's
 // temporaries) from `al` (nullptr: hipMalloc).
@@ -339,7 +340,9 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
     if (!(s >= 0 && s <= n) || !(kappa >= 1.0) || !is_finite(kappa) || !(tau > 0.0) || !is_finite(tau))
         return L1LS_E_ARG;
     if (rounds < 1 || rounds > L1LS_MAX_ROUNDS) return L1LS_E_ARG;
-    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64)) != 0) return L1LS_E_ARG;
+    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32)) != 0) return L1LS_E_ARG;
+    if ((storage & L1LS_STORE_BLK32) && (rounds != 2 || layout != L1LS_LAYOUT_STAGE || n < 4))
+        return L1LS_E_UNSUPPORTED;
     if ((int64_t)16 * n >= ((int64_t)1 << 31) && storage) return L1LS_E_UNSUPPORTED;
 
     l1ls_instance* I = new l1ls_instance();
@@ -475,7 +478,8 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
     hipLaunchKernelGGL((k_gather_perm<double, double>), grid1(n), dim3(L1LS_BLOCK), 0, stream, I->colnorm2,
                        I->colnorm2_op, I->op_col_of, n);
 
-    if (storage) {
+    if (storage & L1LS_STORE_BLK32) GEN_TRY(build_blocks(I, stream, tmp));
+    if (storage & (L1LS_STORE_F32 | L1LS_STORE_F64)) {
         // Stored CSC (columns A e_j) and CSR (rows A^T e_i) in operator order;
         // CSR values are looked up in the columns so both hold the same numbers.
         int32_t* cnt_op = nullptr;

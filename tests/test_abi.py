@@ -60,6 +60,19 @@ def test_generate_rejects_invalid_arguments(m, n, kappa, s, tau, rounds):
     assert st == -1 and not h.value
 
 
+@pytest.mark.parametrize("rounds,storage,layout,n,status", [
+    (2, 8, 1, 50, -1),                                    # unknown storage bit
+    (1, L.STORE_BLK32, 1, 50, -6),                        # blocks need two stages
+    (2, L.STORE_BLK32 | L.STORE_F32, 0, 50, -6),          # ... and the stage layout
+    (2, L.STORE_BLK32, 1, 2, -6),                         # ... and n >= 4
+])
+def test_generate_rejects_unsupported_block_storage(rounds, storage, layout, n, status):
+    h = ctypes.c_void_p()
+    o = L.GenOpts(rounds, storage, None, layout)
+    st = L.lib().l1ls_generate_ex(100, n, 10.0, 1, 1.0, 1, ctypes.byref(o), ctypes.byref(h))
+    assert st == status and not h.value
+
+
 def test_null_arguments_rejected():
     lib = L.lib()
     assert lib.l1ls_generate(100, 50, 10.0, 1, 1.0, 1, None) == -1
