@@ -370,6 +370,19 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def batched_configs(count):
+    """(m, n, kappa, s, tau, seed, rounds) of the batched workload's instances:
+    n log-uniform in [2^10, 2^16] (even), m = 2n, kappa from {1e2, ..., 1e6},
+    s = n/100, tau = 1, two stages; sizes drawn by numpy PCG64 seed 1503035203."""
+    import numpy as np
+    rng = np.random.default_rng(1503035203)
+    cfgs = []
+    for j in range(count):
+        n = _even(2.0 ** rng.uniform(10, 16))
+        cfgs.append((2 * n, n, float(10 ** rng.integers(2, 7)), max(1, n // 100), 1.0, 1503035203000 + j, 2))
+    return cfgs
+
+
 def bench_batched(args):
     """Many uneven instances in shared launches vs the single-solve path.
 
@@ -385,11 +398,7 @@ def bench_batched(args):
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    rng = np.random.default_rng(1503035203)
-    cfgs = []
-    for j in range(args.instances):
-        n = _even(2.0 ** rng.uniform(10, 16))
-        cfgs.append((2 * n, n, float(10 ** rng.integers(2, 7)), max(1, n // 100), 1.0, 1503035203000 + j, 2))
+    cfgs = batched_configs(args.instances)
     insts = [L.l1ls_generate(*c[:6], rounds=c[6], storage=L.STORE_F32, stream=stream) for c in cfgs]
     torch.cuda.synchronize()
     kw = dict(max_iter=args.batch_max_iter, rel_gap_tol=args.batch_tol, check_every=args.check_every,

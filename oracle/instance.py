@@ -138,13 +138,20 @@ def stage_angles(side, t, npairs, key):
     c = U/r, s = V/r, r = sqrt(U*U + V*V) (uniform direction in the disc).
     Only IEEE-exact operations are used, so the values are reproducible.
     """
-    c = np.full(npairs, np.nan)
-    s = np.full(npairs, np.nan)
-    pending = np.arange(npairs, dtype=np.int64)
+    return stage_angles_at(side, t, np.arange(npairs, dtype=np.int64), key)
+
+
+def stage_angles_at(side, t, pairs, key):
+    """(c, s) of the rotations ``pairs`` (pair indices k) of stage t, drawn
+    as in ``stage_angles`` (each rotation's draws depend on k only)."""
+    pairs = np.asarray(pairs, dtype=np.int64)
+    c = np.full(pairs.size, np.nan)
+    s = np.full(pairs.size, np.nan)
+    pending = np.arange(pairs.size, dtype=np.int64)
     for a in range(ANGLE_MAX_ATTEMPTS):
         if pending.size == 0:
             break
-        w0, w1, w2, w3 = philox4x32_10(pending, a, TAG_ANGLE | side, t, key)
+        w0, w1, w2, w3 = philox4x32_10(pairs[pending], a, TAG_ANGLE | side, t, key)
         U = 2.0 * unit_double(w0, w1) - 1.0
         V = 2.0 * unit_double(w2, w3) - 1.0
         q = U * U + V * V
@@ -302,6 +309,149 @@ class Instance:
 
     def dense_A(self):
         return self.sparse_A().toarray()
+
+
+class LocalInstance:
+    """The instance of ``Instance(m, n, kappa, s, tau, seed, rounds)``
+    evaluated at chosen indices only, for sizes where the O(n) arrays of
+    ``Instance`` are too large to build in a test (n = 2^26).
+
+    Every quantity is computed from the same definitions and draws:
+    the bijections and angles (sections 4 and 4.2) at the positions and pairs
+    that are touched, A's columns A e_j = Q Sigma G^T e_j and rows
+    A^T e_i = G Sigma^T Q^T e_i by Algorithms MvPA / MvPAt applied to sparse
+    vectors (a stage rotates only the pairs that hold an entry), and b_i of
+    Procedure IGen (section 3.1): (A x*)_i + e_i with
+    e_i = tau sum_k Q[i, k] (G^T g)_k / sigma_k over k < n (step 3 with the
+    SVD-known inverse of section 4).  Entries that land on the same index
+    are summed, so floating-point values agree with ``Instance`` up to the
+    order of the additions.
+
+    A batch of sparse vectors is kept as parallel arrays (owner, index,
+    value); ``owner`` says which vector of the batch an entry belongs to.
+    """
+
+    def __init__(self, m, n, kappa, s, tau, seed, rounds=1):
+        if not (n >= 2 and m >= n and m % 2 == 0 and n % 2 == 0):
+            raise ValueError("need m >= n >= 2, m and n even")
+        self.m, self.n, self.kappa, self.s = int(m), int(n), float(kappa), int(s)
+        self.tau, self.seed, self.rounds = float(tau), int(seed), int(rounds)
+        self.key = seed_key(seed)
+
+    def _N(self, side):
+        return self.n if side == SIDE_N else self.m
+
+    def position(self, side, i):
+        """pi^{-1}(i): the position of index i on ``side``."""
+        return permutation_inverse(np.asarray(i, dtype=np.int64), self._N(side), TAG_PERM | side, self.key)
+
+    def index(self, side, p):
+        """pi(p): the index at position p on ``side``."""
+        return permutation(np.asarray(p, dtype=np.int64), self._N(side), TAG_PERM | side, self.key)
+
+    def sigma(self, j):
+        """sigma_j = kappa^(-(j-1)/(n-1)) (0-based j), as ``sigma_values``."""
+        j = np.asarray(j, dtype=np.float64)
+        return np.power(self.kappa, -(j / float(self.n - 1)))
+
+    def _stage(self, side, t, owner, idx, val, transpose):
+        """Stage t of ``side`` (or its transpose) applied to a batch of sparse
+        vectors.  Odd t pairs positions (2k, 2k+1), even t (2k+1, 2k+2 mod N);
+        G(f, g, theta) maps (z_f, z_g) to (c z_f - s z_g, s z_f + c z_g)."""
+        N = self._N(side)
+        a = self.position(side, idx)
+        if t % 2 == 1:
+            f = a - (a & 1)
+        else:
+            f = np.where(a & 1, a, (a - 1) % N)
+        g = (f + 1) % N
+        k = f // 2
+        first = a == f
+        c, s = stage_angles_at(side, t, k, self.key)
+        partner = self.index(side, np.where(first, g, f))
+        # z at f feeds (c, s) to (f, g); z at g feeds (-s, c); the transpose
+        # swaps the signs of s
+        sgn = np.where(first, 1.0, -1.0) * (-1.0 if transpose else 1.0)
+        owner2 = np.concatenate([owner, owner])
+        idx2 = np.concatenate([idx, partner])
+        val2 = np.concatenate([c * val, sgn * s * val])
+        return self._combine(owner2, idx2, val2)
+
+    @staticmethod
+    def _combine(owner, idx, val):
+        key = owner.astype(np.int64) * (1 << 34) + idx.astype(np.int64)
+        uk, inv = np.unique(key, return_inverse=True)
+        out = np.zeros(uk.size)
+        np.add.at(out, inv, val)
+        return uk >> 34, uk & ((1 << 34) - 1), out
+
+    def columns(self, js):
+        """A e_j for each j in ``js``: (owner, row index, value) sorted."""
+        js = np.asarray(js, dtype=np.int64)
+        o, i, v = np.arange(js.size), js.copy(), np.ones(js.size)
+        for t in range(self.rounds, 0, -1):          # G^T = S_1^T ... S_r^T
+            o, i, v = self._stage(SIDE_N, t, o, i, v, transpose=True)
+        v = v * self.sigma(i)                         # Sigma: index i of R^n -> i of R^m
+        for t in range(1, self.rounds + 1):           # Q = S~_r ... S~_1
+            o, i, v = self._stage(SIDE_M, t, o, i, v, transpose=False)
+        return o, i, v
+
+    def rows(self, rs):
+        """A^T e_i for each i in ``rs``: (owner, column index, value) sorted."""
+        rs = np.asarray(rs, dtype=np.int64)
+        o, i, v = np.arange(rs.size), rs.copy(), np.ones(rs.size)
+        for t in range(self.rounds, 0, -1):          # Q^T
+            o, i, v = self._stage(SIDE_M, t, o, i, v, transpose=True)
+        keep = i < self.n                             # Sigma^T drops indices >= n
+        o, i, v = o[keep], i[keep], v[keep] * self.sigma(i[keep])
+        for t in range(1, self.rounds + 1):           # G
+            o, i, v = self._stage(SIDE_N, t, o, i, v, transpose=False)
+        return o, i, v
+
+    def xstar(self, js):
+        """x*_j: N(0,1) (Box-Muller) at support rank q if pi_sup^{-1}(j) < s."""
+        js = np.asarray(js, dtype=np.int64)
+        q = permutation_inverse(js, self.n, TAG_PERM | SIDE_SUPPORT, self.key)
+        w0, w1, w2, w3 = philox4x32_10(q, 0, TAG_XSTAR, 0, self.key)
+        u1 = unit_double(w0, w1)
+        u2 = unit_double(w2, w3)
+        vals = np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * math.pi * u2)
+        return np.where(q < self.s, vals, 0.0)
+
+    def subgradient(self, js):
+        """g_j: sign(x*_j) on the support, 0.9 (2u - 1) off it (eq. (10))."""
+        js = np.asarray(js, dtype=np.int64)
+        w0, w1, _, _ = philox4x32_10(js, 0, TAG_SUBGRAD, 0, self.key)
+        g = 0.9 * (2.0 * unit_double(w0, w1) - 1.0)
+        q = permutation_inverse(js, self.n, TAG_PERM | SIDE_SUPPORT, self.key)
+        xs = self.xstar(js)
+        return np.where(q < self.s, np.sign(xs), g)
+
+    def e(self, rs):
+        """e_i = tau (Q Sigma^{+T} G^T g)_i (IGen step 3)."""
+        rs = np.asarray(rs, dtype=np.int64)
+        o, k, q = np.arange(rs.size), rs.copy(), np.ones(rs.size)
+        for t in range(self.rounds, 0, -1):          # row i of Q: Q^T e_i
+            o, k, q = self._stage(SIDE_M, t, o, k, q, transpose=True)
+        keep = k < self.n
+        o, k, q = o[keep], k[keep], q[keep]
+        # (G^T g)_k = (G e_k)^T g
+        oo, l, gv = np.arange(k.size), k.copy(), np.ones(k.size)
+        for t in range(1, self.rounds + 1):
+            oo, l, gv = self._stage(SIDE_N, t, oo, l, gv, transpose=False)
+        gtg = np.zeros(k.size)
+        np.add.at(gtg, oo, gv * self.subgradient(l))
+        out = np.zeros(rs.size)
+        np.add.at(out, o, q * (self.tau * gtg / self.sigma(k)))
+        return out
+
+    def b(self, rs):
+        """b_i = (A x*)_i + e_i (IGen step 4)."""
+        rs = np.asarray(rs, dtype=np.int64)
+        o, j, a = self.rows(rs)
+        ax = np.zeros(rs.size)
+        np.add.at(ax, o, a * self.xstar(j))
+        return ax + self.e(rs)
 
 
 def objective(A_mv, b, tau, x):
