@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "fista_stored_f32_n2p20.txt")
-KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp"]
+KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp", "blocks.hip"]
 
 
 def kernel_source_hash():
@@ -62,7 +62,8 @@ def write_profile_summary(args):
                     return list(csv.DictReader(open(os.path.join(root, f))))
         raise SystemExit(f"no *{kind} under {d}")
 
-    names = {"residual": "k_residual<float>", "transpose_prox": "k_transpose_prox<float>", "gap": "k_gap"}
+    names = {"residual": "k_residual<float>", "transpose_prox": "k_transpose_prox<float>", "gap": "k_gap",
+             "blk_residual": "k_blk_residual<false>", "blk_transpose_prox": "k_blk_transpose_prox<false>"}
     stats = kernel_rows(args.kt, "kernel_stats.csv")
     dur = {}
     for key, pat in names.items():
@@ -79,7 +80,8 @@ def write_profile_summary(args):
     copy_w, _ = counter(args.copyw, "WRITE_SIZE", "copyBuffer")
     gib_kib = float(1 << 20)            # the copy moves 1 GiB = 2^20 KiB each way
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
-    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC, FP32 bulk, n=2^20, m=2^21, 2 stages",
+    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator), "
+             "FP32 bulk, n=2^20, m=2^21, 2 stages",
              f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
              f"python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline",
              f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
@@ -941,6 +943,12 @@ def main():
     if summ and summ.get("kernel_source_hash") == kernel_source_hash() and f"{key}_traffic_bytes" in summ:
         traffic = float(summ[f"{key}_traffic_bytes"])
 
+    blk_traffic = None
+    if summ and summ.get("kernel_source_hash") == kernel_source_hash():
+        if "blk_residual_traffic_bytes" in summ and "blk_transpose_prox_traffic_bytes" in summ:
+            blk_traffic = {"residual": float(summ["blk_residual_traffic_bytes"]),
+                           "transpose_prox": float(summ["blk_transpose_prox_traffic_bytes"])}
+
     # FP64 certificate of the final iterate (outside the timed region)
     P, D, gap = L.l1ls_objective_gap(inst, tau, plain["x"])
 
@@ -988,6 +996,7 @@ def main():
                                     "transpose_prox": b2 / (bavg[1] * 1e-3) / 1e9},
                 "bytes_per_iter": b1 + b2,
                 "final_rel_gap_fp64": bgap,
+                "traffic_per_launch": blk_traffic,
             },
         },
     }
