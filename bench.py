@@ -871,6 +871,7 @@ def main():
          "large": bench_large, "table1": bench_table1, "grid": bench_grid}[args.workload](args)
         return
 
+    import numpy as np
     import torch
 
     import paper_1503_03520_amd as L
@@ -951,6 +952,11 @@ def main():
 
     # FP64 certificate of the final iterate (outside the timed region)
     P, D, gap = L.l1ls_objective_gap(inst, tau, plain["x"])
+    # distance to the planted minimiser (IGen makes x* optimal for the FP64 A)
+    xstar = torch.from_numpy(L.device_to_numpy(inst.info().x_star_dev, n, np.float64)).cuda()
+
+    def rel_err(x):
+        return float((x - xstar).norm() / xstar.norm())
 
     line = {
         "metric": "FISTA iters/sec (SpMV pair A*y, A^T*r fused with prox, momentum, gap)",
@@ -979,6 +985,7 @@ def main():
             "bytes_per_iter": k1_bytes + k2_bytes,
             "generate_s": gen_s,
             "final_rel_gap_fp64": gap,
+            "final_rel_err_planted": rel_err(plain["x"]),
             "timed_ms_with_kernel_events": timed["ms"],
             "matrix_free": {
                 "iters_per_s": args.steps / (mfree["ms"] / 1e3),
@@ -986,6 +993,7 @@ def main():
                 "kernel_avg_us": {k: mfree_t["kernel_ms"][i] / max(mfree_t["kernel_launches"][i], 1) * 1e3
                                   for i, k in enumerate(("residual_pair", "transpose_pair", "gap"))},
                 "bytes_per_iter": mf_bytes(m, n),
+                "final_rel_err_planted": rel_err(mfree["x"]),
             },
             "blocked": {
                 "iters_per_s": args.steps / (blk["ms"] / 1e3),
@@ -996,6 +1004,7 @@ def main():
                                     "transpose_prox": b2 / (bavg[1] * 1e-3) / 1e9},
                 "bytes_per_iter": b1 + b2,
                 "final_rel_gap_fp64": bgap,
+                "final_rel_err_planted": rel_err(blk["x"]),
                 "traffic_per_launch": blk_traffic,
             },
         },

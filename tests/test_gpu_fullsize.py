@@ -110,3 +110,10 @@ def test_full_size_fista_fp32_trajectory_and_gap(op):
     assert abs(rep["primal"] - P) <= 1e-5 * abs(P)
     Pd, Dd, gap = L.l1ls_objective_gap(g, o.tau, _dev(x))
     assert math.isclose(Pd, P, rel_tol=1e-10)
+
+
+def teardown_module(module):
+    if _state:
+        _state["g"].free()
+        _state.clear()
+    _ref.clear()

@@ -142,3 +142,10 @@ def test_large_fista_first_iterate_and_operators_agree():
     print(f"stored vs matrix-free after {k}: {diff:.3e} (bound {2 * k * np.finfo(np.float32).eps * bmax:.3e})",
           flush=True)
     assert diff <= 2 * k * np.finfo(np.float32).eps * bmax
+
+
+def teardown_module(module):
+    # release the ~40 GB instance before the next test module runs
+    if _state:
+        _state["g"].free()
+        _state.clear()
