@@ -518,7 +518,8 @@ def bench_large(args):
     m = 2 * n
     kappa, s, tau, seed = 1e6, max(1, n // 1000), 1.0, 1503035202
     t0 = time.perf_counter()
-    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=2, stream=stream)
+    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=2, stream=stream,
+                           storage=L.STORE_F32 | L.STORE_F64 | L.STORE_BLK32)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     nnz = inst.info().nnz
@@ -541,6 +542,8 @@ def bench_large(args):
     print(json.dumps({"progress": "stored", "iters_per_s": stored}), file=sys.stderr, flush=True)
     mfree, x_m = fista_rate(L.OP_MATRIX_FREE, args.steps, args.warmup)
     print(json.dumps({"progress": "matrix_free", "iters_per_s": mfree}), file=sys.stderr, flush=True)
+    blocked, x_b = fista_rate(L.OP_BLOCKED, args.steps, args.warmup)
+    print(json.dumps({"progress": "blocked", "iters_per_s": blocked}), file=sys.stderr, flush=True)
     same = float((x_s - x_m).abs().max())
     newton = {}
     for prec, name in ((L.F32, "f32_hessian_products"), (L.F64, "f64")):
@@ -566,6 +569,9 @@ def bench_large(args):
                   "stored_gbs_algorithmic": (k1 + k2) * stored / 1e9,
                   "matrix_free_iters_per_s": mfree, "matrix_free_gbs_algorithmic": mf_bytes(m, n) * mfree / 1e9,
                   "matrix_free_speedup": mfree / stored,
+                  "blocked_iters_per_s": blocked,
+                  "blocked_gbs_algorithmic": sum(blocked_bytes(m, n, 4 * n)) * blocked / 1e9,
+                  "stored_vs_blocked_max_abs_diff": float((x_s - x_b).abs().max()),
                   "stored_vs_matrix_free_max_abs_diff": same,
                   "cg_newton": newton},
     }
