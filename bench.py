@@ -546,10 +546,11 @@ def bench_large(args):
     print(json.dumps({"progress": "blocked", "iters_per_s": blocked}), file=sys.stderr, flush=True)
     same = float((x_s - x_m).abs().max())
     newton = {}
-    for prec, name in ((L.F32, "f32_hessian_products"), (L.F64, "f64")):
+    for prec, op, name in ((L.F32, L.OP_STORED, "f32_hessian_products"), (L.F64, L.OP_STORED, "f64"),
+                           (L.F64, L.OP_MATRIX_FREE, "matrix_free_f64")):
         t = time.perf_counter()
         xn, rn, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, stream=stream,
-                                           precision=prec)
+                                           precision=prec, op=op)
         torch.cuda.synchronize()
         tn = time.perf_counter() - t
         P, D, gap = L.l1ls_objective_gap(inst, tau, xn)

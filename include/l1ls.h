@@ -128,7 +128,8 @@ typedef struct l1ls_instance l1ls_instance;
  * All random draws come from Philox-4x32-10 keyed by `seed`, so an instance
  * is a function of (m, n, kappa, s, tau, seed, rounds).
  * Requires m >= n >= 2, m and n even, m < 2^31, 0 <= s <= n, kappa >= 1,
- * tau > 0, 1 <= rounds <= 2.  l1ls_generate uses rounds = 1, both
+ * tau > 0, 1 <= rounds <= 2; with the CSR/CSC stored also 16 n < 2^31 and
+ * m < 2^29 (else L1LS_E_UNSUPPORTED).  l1ls_generate uses rounds = 1, both
  * storages and the STAGE layout on the null stream.  The call returns after
  * the build finished.
  */
@@ -208,6 +209,10 @@ void l1ls_solve_opts_default(l1ls_solve_opts* opts);
  * soft-threshold step of section 2) from x0, then optionally the FP64
  * polish.  x_out_dev receives n FP64 values.  Returns L1LS_OK when the
  * relative gap reached rel_gap_tol, L1LS_NOT_CONVERGED at max_iter.
+ * opts.op selects the operator: STORED (CSR/CSC in opts.precision),
+ * MATRIX_FREE (requires m times the value size below 4 GiB) or BLOCKED
+ * (L1LS_STORE_BLK32, FP32 only); L1LS_E_UNSUPPORTED when the instance lacks
+ * what the choice needs.
  */
 l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* opts,
                              double* x_out_dev, l1ls_report* report);
@@ -223,7 +228,13 @@ l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* o
  * FP64; both storages are needed).  The Newton
  * loop stops when ||grad f_mu(x)||_inf <= rel_gap_tol * tau, or after
  * max_iter Newton steps (report.iterations; report.inner = PCG iterations).
- * Uses the stored FP64 operator (L1LS_STORE_F64).
+ * opts.op = L1LS_OP_STORED uses the stored FP64 operator (L1LS_STORE_F64).
+ * opts.op = L1LS_OP_MATRIX_FREE applies A and A^T from the rotation tables
+ * in FP64 (Algorithms MvPA / MvPAt, section 4), so it needs no stored A:
+ * it requires precision L1LS_F64, the STAGE layout and 8 m < 2^32, and the
+ * final certificate (report.primal / dual / rel_gap) is evaluated with the
+ * same products; opts.polish still needs L1LS_STORE_F64.
+ * L1LS_E_UNSUPPORTED for other combinations.
  */
 l1ls_status l1ls_solve_cg_newton(const l1ls_instance* inst, const l1ls_solve_opts* opts,
                                  double* x_out_dev, l1ls_report* report);

@@ -355,6 +355,10 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     if (opts->check_every < 1 || opts->max_iter < 0 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
     if (opts->op == L1LS_OP_STORED) L1LS_TRY(check_stored(I, opts->precision));
     if (opts->op == L1LS_OP_MATRIX_FREE && !I->mf_emb) return L1LS_E_UNSUPPORTED;
+    // the matrix-free passes gather with 32-bit byte offsets: vectors below 4 GiB
+    if (opts->op == L1LS_OP_MATRIX_FREE &&
+        I->m * (int64_t)(opts->precision == L1LS_F32 ? sizeof(float) : sizeof(double)) >= ((int64_t)1 << 32))
+        return L1LS_E_UNSUPPORTED;
     if (opts->op == L1LS_OP_BLOCKED && (opts->precision != L1LS_F32 || !I->blk_rptr)) return L1LS_E_UNSUPPORTED;
     const double tau = opts->tau > 0 ? opts->tau : I->tau;
     const double L = opts->L > 0 ? opts->L : I->L;

@@ -75,8 +75,8 @@ __device__ __forceinline__ int64_t ring(int64_t p, int64_t N) {
 // handles stage-1 pair (2k, 2k+1) from x at 2k-1 .. 2k+2.
 template <typename T, int R>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ w, MfTabs<T> tb,
-                                                       const GapState* __restrict__ gs) {
-    if (gs && gs->done) return;
+                                                       const int32_t* __restrict__ done) {
+    if (done && *done) return;  // the solver's converged flag (launch-uniform)
     const int64_t n = tb.n, np = n / 2;
     const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
     if (k >= np) return;
@@ -106,18 +106,23 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T
 // 2k0+2B+1.  r_y never leaves LDS.  R = 1: pair k only.  r_x,prev (rxp) and
 // r_x (rx) are separate buffers: a neighbour's r_x,prev is read for the halo
 // while its owner writes r_x.
-template <typename T, int R>
+// MODE selects what the pass is for:
+//   kMfFista   the FISTA residual pass above;
+//   kMfProduct rx = A x only (b = 0, no v);
+//   kMfNormal  vm = Sigma_m Q^T (A x) only (b = 0, rx not written): the
+//              m side of A^T A x for the second-order path.
+constexpr int kMfFista = 0, kMfProduct = 1, kMfNormal = 2;
+template <typename T, int R, int MODE = kMfFista>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ w, const T* __restrict__ b,
                                                            const T* __restrict__ rxp, T* __restrict__ rx,
                                                            T* __restrict__ vm, T beta,
                                                            int init, MfTabs<T> tb, double* __restrict__ part,
-                                                           const GapState* __restrict__ gs, int stats) {
+                                                           const int32_t* __restrict__ done, int stats) {
     constexpr int B = L1LS_BLOCK;
     constexpr int H = (R == 2) ? 2 : 0;  // halo positions on the left
     __shared__ T zl[2 * B + 2 * H];
     __shared__ T yl[2 * B + H];  // r_y at positions 2k0 - H/2 .. (R = 2: from 2k0-1)
-    const int32_t done = gs ? gs->done : 0;
-    if (done) return;  // launch-uniform
+    if (done && *done) return;  // the solver's converged flag (launch-uniform)
     const int64_t m = tb.m, mp = m / 2;
     const int64_t k0 = (int64_t)blockIdx.x * B;
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
@@ -130,8 +135,9 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     const int64_t k = k0 + t;
     double v[3] = {0.0, 0.0, 0.0};
     if (R == 2) {
-        // own stage-2 pair k (t < B) and, in thread 0, the left neighbour pair k0-1
-        for (int h = 0; h < (t == 0 ? 2 : 1); ++h) {
+        // own stage-2 pair k (t < B) and, in thread 0, the left neighbour pair
+        // k0-1 (only Q^T reads it)
+        for (int h = 0; h < ((t == 0 && MODE != kMfProduct) ? 2 : 1); ++h) {
             const bool own = (h == 0);
             const int64_t j = own ? k : wrap(k0 - 1, mp);
             if (own && j >= mp) break;
@@ -145,12 +151,12 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int64_t i = ps[e];
-                const T bi = b[i];
+                const T bi = (MODE == kMfFista) ? b[i] : T(0);
                 const T r = rr[e] - bi;
-                const T yv = init ? r : (T(1) + beta) * r - beta * rxp[i];
+                const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rxp[i];
                 yl[(own ? 2 * t + 2 : 0) + e] = yv;
                 if (own) {
-                    rx[i] = r;
+                    if (MODE != kMfNormal) rx[i] = r;
                     v[0] += (double)r * (double)r;
                     v[1] += (double)yv * (double)yv;
                     v[2] += (double)bi * (double)yv;
@@ -165,18 +171,18 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t i = ps[e];
-            const T bi = b[i];
+            const T bi = (MODE == kMfFista) ? b[i] : T(0);
             const T r = rr[e] - bi;
-            const T yv = init ? r : (T(1) + beta) * r - beta * rxp[i];
+            const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rxp[i];
             yl[2 * t + e] = yv;
-            rx[i] = r;
+            if (MODE != kMfNormal) rx[i] = r;
             v[0] += (double)r * (double)r;
             v[1] += (double)yv * (double)yv;
             v[2] += (double)bi * (double)yv;
         }
     }
     __syncthreads();
-    if (k < mp) {
+    if (MODE != kMfProduct && k < mp) {
         // v for stage-1 pair k; pairs with both positions inactive are not read
         const T s0 = tb.sig[2 * k], s1 = tb.sig[2 * k + 1];
         if (s0 != T(0) || s1 != T(0)) {
@@ -308,6 +314,89 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     }
 }
 
+// v = Sigma_m Q^T y in m order (the m side of A^T y on its own).  Thread k
+// owns stage-1 pair k; R = 2: Q^T = S~_1^T S~_2^T reads y at 2k-1 .. 2k+2.
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ vm, MfTabs<T> tb) {
+    const int64_t m = tb.m, mp = m / 2;
+    const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
+    if (k >= mp) return;
+    T z0 = y[2 * k], z1 = y[2 * k + 1];
+    if (R == 2) {
+        const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
+        T a, b;
+        rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, z0, true, a, b);  // 2k is second of stage-2 pair k-1
+        const T z0n = b;
+        rot(cs_of(tb.csm[1], k), z1, yp, true, a, b);                // 2k+1 is first of stage-2 pair k
+        z0 = z0n;
+        z1 = a;
+    }
+    T o0, o1;
+    rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
+    vm[2 * k] = tb.sig[2 * k] * o0;
+    vm[2 * k + 1] = tb.sig[2 * k + 1] * o1;
+}
+
+// The n side of A^T from v (m order): g = G t with t_a = v[inv[a]], with the
+// Hessian epilogue of the PCG when p is given:
+//   h = g + d p (d optional), h = 0 where mask is 0 (mask optional),
+//   out = h, part[block] = sum p h (part optional);
+// without p: out = g.  Gather and halo as in k_mf_prox_gt (R = 2: thread t
+// owns stage-2 pair k0 + t, outputs at 2k+1 and 2k+2).
+template <typename T, int R>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ vm, const T* __restrict__ p,
+                                                           const T* __restrict__ d, const uint8_t* __restrict__ mask,
+                                                           T* __restrict__ out, MfTabs<T> tb,
+                                                           double* __restrict__ part,
+                                                           const int32_t* __restrict__ done) {
+    constexpr int B = L1LS_BLOCK;
+    constexpr int H = (R == 2) ? 2 : 0;
+    __shared__ T tl[2 * B + 2 * H];
+    if (done && *done) return;  // launch-uniform
+    const int64_t n = tb.n, np = n / 2;
+    const int64_t k0 = (int64_t)blockIdx.x * B;
+    for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
+        const int64_t pos = ring(2 * k0 - H + q + n, n);
+        tl[q] = ld_off32(vm, tb.inv[pos]);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
+    double acc[1] = {0.0};
+    if (k < np) {
+        T gv[2];
+        int64_t ps[2];
+        if (R == 2) {
+            const int q0 = 2 * t + 2;  // t at 2k .. 2k+3
+            T a, u1, u2, bb;
+            rot(cs_of(tb.csn[0], k), tl[q0], tl[q0 + 1], false, a, u1);
+            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tl[q0 + 2], tl[q0 + 3], false, u2, bb);
+            rot(cs_of(tb.csn[1], k), u1, u2, false, gv[0], gv[1]);
+            ps[0] = 2 * k + 1;
+            ps[1] = wrap(2 * k + 2, n);
+        } else {
+            rot(cs_of(tb.csn[0], k), tl[2 * t], tl[2 * t + 1], false, gv[0], gv[1]);
+            ps[0] = 2 * k;
+            ps[1] = 2 * k + 1;
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t j = ps[e];
+            T h = gv[e];
+            if (p) {
+                const T pj = p[j];
+                if (d) h += d[j] * pj;
+                if (mask && !mask[j]) h = T(0);
+                acc[0] += (double)pj * (double)h;
+            }
+            out[j] = h;
+        }
+    }
+    if (!part) return;  // launch-uniform
+    block_reduce_stats<1, 1>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
 // ---- tables ------------------------------------------------------------------
 __global__ void k_mf_emb(const int32_t* __restrict__ perm_m, const int32_t* __restrict__ pinv_n,
                          const double* __restrict__ sigma, int64_t n, int64_t m, int32_t* __restrict__ emb,
@@ -416,14 +505,17 @@ template <typename T>
 void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, const T* rx_prev, T* rx, T* vt,
                         T beta, int init, double* part, const GapState* gs, int stats, hipStream_t s) {
     const MfTabs<T> tb = tabs_of<T>(I);
+    const int32_t* done = gs ? &gs->done : nullptr;
     if (I->rounds == 2) {
-        if (init) hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        if (init)
+            hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, done);
         hipLaunchKernelGGL((k_mf_res_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
-                           vt, beta, init, tb, part, gs, stats);
+                           vt, beta, init, tb, part, done, stats);
     } else {
-        if (init) hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, gs);
+        if (init)
+            hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, done);
         hipLaunchKernelGGL((k_mf_res_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
-                           vt, beta, init, tb, part, gs, stats);
+                           vt, beta, init, tb, part, done, stats);
     }
 }
 
@@ -451,3 +543,57 @@ template void mf_transpose_launch<float>(const l1ls_instance*, const float*, flo
 template void mf_transpose_launch<double>(const l1ls_instance*, const double*, double*, const double*,
                                           const double*, double*, double, double, double, double*, const GapState*,
                                           int, hipStream_t);
+
+// ---- products for the second-order path (FP64, stage order) -----------------
+// A x with x (n) and out (m) in stage order: w = Sigma_n G^T x, then the
+// m-side pass writes out = A x.
+template <int MODE>
+void mf_fwd_launch(const l1ls_instance* I, const double* x, double* wn, double* out, double* vm, const int32_t* done,
+                   hipStream_t s) {
+    const MfTabs<double> tb = tabs_of<double>(I);
+    if (I->rounds == 2) {
+        hipLaunchKernelGGL((k_mf_gt<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb, done);
+        hipLaunchKernelGGL((k_mf_res_qt<double, 2, MODE>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
+                           (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
+                           done, 0);
+    } else {
+        hipLaunchKernelGGL((k_mf_gt<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb, done);
+        hipLaunchKernelGGL((k_mf_res_qt<double, 1, MODE>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
+                           (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
+                           done, 0);
+    }
+}
+
+void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s) {
+    mf_fwd_launch<kMfProduct>(I, x, wn, out, (double*)nullptr, (const int32_t*)nullptr, s);
+}
+
+// out (n) = A^T y with y (m) and out in stage order; vm is m scratch.
+void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* out, hipStream_t s) {
+    const MfTabs<double> tb = tabs_of<double>(I);
+    if (I->rounds == 2) {
+        hipLaunchKernelGGL((k_mf_qt<double, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, y, vm, tb);
+        hipLaunchKernelGGL((k_mf_g_hess<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm,
+                           (const double*)nullptr, (const double*)nullptr, (const uint8_t*)nullptr, out, tb,
+                           (double*)nullptr, (const int32_t*)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_mf_qt<double, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, y, vm, tb);
+        hipLaunchKernelGGL((k_mf_g_hess<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm,
+                           (const double*)nullptr, (const double*)nullptr, (const uint8_t*)nullptr, out, tb,
+                           (double*)nullptr, (const int32_t*)nullptr);
+    }
+}
+
+// hp = mask (A^T A p + d p) with part[block] = sum p hp over mf_grid(n/2)
+// blocks (A p itself is not stored).  Skipped once *done is set.
+void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
+             double* hp, double* part, const int32_t* done, hipStream_t s) {
+    mf_fwd_launch<kMfNormal>(I, p, wn, (double*)nullptr, vm, done, s);
+    const MfTabs<double> tb = tabs_of<double>(I);
+    if (I->rounds == 2)
+        hipLaunchKernelGGL((k_mf_g_hess<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+                           mask, hp, tb, part, done);
+    else
+        hipLaunchKernelGGL((k_mf_g_hess<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+                           mask, hp, tb, part, done);
+}

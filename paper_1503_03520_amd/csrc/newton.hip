@@ -28,6 +28,11 @@ using namespace l1ls;
 l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
                      hipStream_t s, DevAlloc* al = nullptr);
 l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out, hipStream_t s);
+void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s);
+void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* out, hipStream_t s);
+void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
+             double* hp, double* part, const int32_t* done, hipStream_t s);
+int mf_grid(int64_t pairs);
 
 namespace {
 
@@ -282,6 +287,30 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_newton_grad(const double* __rest
     }
 }
 
+// Duality-gap statistics of problem (1) at x from r = A x - b and
+// g = A^T r: part = (sum r^2, sum b r, sum |x|, max |g|).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_gap_terms(const double* __restrict__ r,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ g, int64_t n, int64_t m,
+                                                          double* __restrict__ part) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t N = n > m ? n : m;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < m) {
+            v[0] += r[i] * r[i];
+            v[1] += b[i] * r[i];
+        }
+        if (i < n) {
+            v[2] += fabs(x[i]);
+            v[3] = fmax(v[3], fabs(g[i]));
+        }
+    }
+    block_reduce_stats<4, 3>(v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) part[4 * blockIdx.x + q] = v[q];
+}
+
 // part = (grad . dx, sum psi_mu(x + a dx) | over m: sum (r + a q)^2)
 __global__ __launch_bounds__(L1LS_BLOCK) void k_ls_terms(const double* __restrict__ x,
                                                          const double* __restrict__ dx,
@@ -405,6 +434,10 @@ struct Work {
     int32_t* iters = nullptr;
     CgScalars* cs = nullptr;
     bool hv32 = false;  // Hessian-vector products of Newton directions with the FP32 values
+    // Matrix-free operator (stage order, FP64): products from the rotation
+    // tables, no stored A.  wn (n), vm (m) are its intermediate vectors.
+    bool mf = false;
+    double *wn = nullptr, *vm = nullptr;
     std::vector<double> h;
     ~Work() {
         (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
@@ -419,12 +452,18 @@ struct Work {
         L1LS_TRY(arena.alloc(&tm, m));
         L1LS_TRY(arena.alloc(&tm2, m));
         L1LS_TRY(arena.alloc(&rres, m));
-        L1LS_TRY(arena.alloc(&part, 3 * (size_t)std::max(kRedBlocks, tgrid(n))));
+        L1LS_TRY(arena.alloc(&part, 4 * (size_t)std::max(kRedBlocks, tgrid(n))));
         L1LS_TRY(arena.alloc(&mask, n));
         L1LS_TRY(arena.alloc(&counts, 2));
         L1LS_TRY(arena.alloc(&iters, 1));
         L1LS_TRY(arena.alloc(&cs, 1));
-        h.resize(3 * (size_t)std::max(kRedBlocks, tgrid(n)));
+        h.resize(4 * (size_t)std::max(kRedBlocks, tgrid(n)));
+        return L1LS_OK;
+    }
+    l1ls_status init_mf() {
+        mf = true;
+        L1LS_TRY(arena.alloc(&wn, I->n));
+        L1LS_TRY(arena.alloc(&vm, I->m));
         return L1LS_OK;
     }
     // host sums of `k` statistics over `nb` partial slots (fixed order)
@@ -440,17 +479,31 @@ struct Work {
         return L1LS_OK;
     }
     void spmv(const double* in, double* out) {  // out (m) = A in
+        if (mf) {
+            mf_apply_fwd(I, in, wn, out, s);
+            return;
+        }
         hipLaunchKernelGGL(k_tile_spmv<double>, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
                            I->csr_v64, in, out, I->m, (const CgScalars*)nullptr);
     }
     void spmv_t(const double* in, double* out) {  // out (n) = A^T in
+        if (mf) {
+            mf_apply_adj(I, in, vm, out, s);
+            return;
+        }
         hipLaunchKernelGGL(k_tile_spmv<double>, dim3(tgrid(I->n)), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
                            I->csc_v64, in, out, I->n, (const CgScalars*)nullptr);
     }
+    // partial-sum slots written by hess()
+    int hess_parts() const { return mf ? mf_grid(I->n / 2) : tgrid(I->n); }
     // H v = mask (A^T (A v) + dv v) into hp, inside a PCG (skipped once it is done)
     void hess(const double* v, const double* dv, const uint8_t* mk, bool f32) {
         const int64_t n = I->n;
         const int gt = tgrid(n);
+        if (mf) {
+            mf_hess(I, v, wn, vm, dv, mk, hp, part, &cs->done, s);
+            return;
+        }
         if (f32) {
             hipLaunchKernelGGL(k_tile_spmv<float>, dim3(tgrid(I->m)), dim3(L1LS_BLOCK), 0, s, I->csr_ptr,
                                I->csr_col, I->csr_v32, v, tm, I->m, (const CgScalars*)cs);
@@ -470,7 +523,7 @@ struct Work {
     l1ls_status pcg(double* v, const double* rhs_v, const double* dv, const uint8_t* mk, double rtol, int maxit,
                     int* out_iters, bool zero_start = false, bool f32 = false) {
         const int64_t n = I->n;
-        const int gt = tgrid(n);
+        const int gt = hess_parts();
         hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(1), 0, s, cs);
         if (!zero_start) hess(v, dv, mk, f32);  // H v for the starting residual
         hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, rhs_v,
@@ -553,7 +606,16 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
 extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_solve_opts* o, double* x_out,
                                             l1ls_report* rep) {
     if (!I || !o || !x_out) return L1LS_E_ARG;
-    if (!I->csr_v64 || !I->csc_v64) return L1LS_E_UNSUPPORTED;
+    if (o->op != L1LS_OP_STORED && o->op != L1LS_OP_MATRIX_FREE) return L1LS_E_ARG;
+    const bool mf = (o->op == L1LS_OP_MATRIX_FREE);
+    // the matrix-free products are FP64 and work in stage order (the order
+    // of the solver's vectors under the STAGE layout); the polish needs the
+    // stored FP64 A
+    if (mf && (o->precision != L1LS_F64 || !I->mf_emb || I->layout != L1LS_LAYOUT_STAGE ||
+               I->m * (int64_t)sizeof(double) >= ((int64_t)1 << 32) ||
+               (o->polish && (!I->csr_v64 || !I->csc_v64))))
+        return L1LS_E_UNSUPPORTED;
+    if (!mf && (!I->csr_v64 || !I->csc_v64)) return L1LS_E_UNSUPPORTED;
     if (o->max_iter < 0) return L1LS_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)o->stream;
@@ -567,9 +629,10 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
     if (!is_finite(tau) || !is_finite(mu)) return L1LS_E_ARG;
     const int64_t n = I->n, m = I->m;
     Work W;
-    W.hv32 = (o->precision == L1LS_F32);
+    W.hv32 = !mf && (o->precision == L1LS_F32);
     if (W.hv32 && (!I->csr_v32 || !I->csc_v32)) return L1LS_E_UNSUPPORTED;
     L1LS_TRY(W.init(I, s));
+    if (mf) L1LS_TRY(W.init_mf());
     if (o->x0_dev)
         hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, o->x0_dev, W.x,
                            I->op_col_of, n);
@@ -633,7 +696,25 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
         r.inner += ppcg;
     }
     r.polish_rounds = prounds;
-    L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));
+    if (mf && !o->polish) {
+        // FP64 certificate through the matrix-free products (stage order):
+        // P = tau ||x||_1 + 0.5 ||r||^2, theta = min(1, tau / ||A^T r||_inf),
+        // D = -0.5 theta^2 ||r||^2 - theta b^T r
+        W.spmv(W.x, W.rres);
+        hipLaunchKernelGGL(k_axpby, g1d(m), dim3(L1LS_BLOCK), 0, s, W.rres, 1.0, I->b_op, -1.0, W.rres, m);
+        W.spmv_t(W.rres, W.atr);
+        hipLaunchKernelGGL(k_gap_terms, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.rres, I->b_op, W.x, W.atr, n, m,
+                           W.part);
+        double gt4[4];
+        L1LS_TRY(W.host_sums(4, kRedBlocks, gt4, true));
+        const double theta = (gt4[3] <= tau) ? 1.0 : tau / gt4[3];
+        r.primal = tau * gt4[2] + 0.5 * gt4[0];
+        r.dual = -0.5 * theta * theta * gt4[0] - theta * gt4[1];
+        r.rel_gap = (r.primal - r.dual) / std::fabs(r.primal);
+        if (!is_finite(r.primal) || !is_finite(r.dual)) return L1LS_E_NONFINITE;
+    } else {
+        L1LS_TRY(gap_fp64(I, tau, x_out, &r.primal, &r.dual, &r.rel_gap, s));
+    }
     L1LS_TRY(rel_err_planted(I, x_out, &r.rel_err, s));
     r.converged = (gnorm <= gtol) ? 1 : 0;
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -170,3 +170,11 @@ def test_law_validation():
         p = L.sgt_params(64, 1, s=kw.pop("s", 4), **kw)
         h = ctypes.c_void_p()
         assert L.lib().l1ls_sgt_generate(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
+
+
+def test_generate_rejects_stored_operator_beyond_32bit_gathers():
+    # the stored passes gather m-vectors with 32-bit byte offsets
+    h = ctypes.c_void_p()
+    o = L.GenOpts(2, L.STORE_F32, None, 1)
+    st = L.lib().l1ls_generate_ex(1 << 29, 1 << 20, 10.0, 1, 1.0, 1, ctypes.byref(o), ctypes.byref(h))
+    assert st == -6 and not h.value

@@ -45,10 +45,11 @@ def _dev(v):
 
 @pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED])
 @pytest.mark.parametrize("hessian", [0, 1])
-def test_cg_newton_reaches_oracle_minimiser(cfg, hessian):
+@pytest.mark.parametrize("op", [L.OP_STORED, L.OP_MATRIX_FREE])
+def test_cg_newton_reaches_oracle_minimiser(cfg, hessian, op):
     g, o, A = pair(cfg)
     mu = 1e-5
-    x, rep, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, hessian=hessian)
+    x, rep, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, hessian=hessian, op=op)
     assert st == L.L1LS_OK and rep["converged"] == 1
     cn = np.asarray(A.multiply(A).sum(0)).ravel()
     xo, so = ON.newton_cg(lambda v: A @ v, lambda v: A.T @ v, cn, o.b, o.tau, mu=mu,
@@ -119,3 +120,43 @@ def test_cg_newton_fp32_hessian_products_reach_the_same_minimiser(cfg):
     scale = max(1.0, np.abs(ref).max())
     assert np.abs(x32.cpu().numpy() - ref).max() <= 1e-5 * scale
     assert np.abs(x32.cpu().numpy() - x64.cpu().numpy()).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED])
+def test_cg_newton_matrix_free_follows_the_stored_path(cfg):
+    # The same Newton iteration over two evaluations of the same A (stored
+    # FP64 values vs the rotations applied on the fly): products agree to
+    # rounding, so after one Newton step (one PCG from zero, same count) the
+    # iterates agree to rounding amplified by the PCG; the certificates of the
+    # final iterate agree with the stored-operator gap at the same x.
+    g, o, A = pair(cfg)
+    xs, rs, _ = L.l1ls_solve_cg_newton(g, max_iter=1, rel_gap_tol=1e-12)
+    xm, rm, _ = L.l1ls_solve_cg_newton(g, max_iter=1, rel_gap_tol=1e-12, op=L.OP_MATRIX_FREE)
+    assert rs["iterations"] == rm["iterations"] == 1 and rs["inner"] == rm["inner"]
+    scale = max(1.0, float(xs.abs().max()))
+    assert float((xs - xm).abs().max()) <= 1e-9 * scale
+    P, D, gap = L.l1ls_objective_gap(g, o.tau, xm)
+    assert math.isclose(rm["primal"], P, rel_tol=1e-12) and math.isclose(rm["dual"], D, rel_tol=1e-10, abs_tol=1e-12)
+
+
+def test_cg_newton_matrix_free_without_stored_operator():
+    # An instance with no stored A (storage 0): the matrix-free CG-Newton
+    # reaches the same minimiser of (8) as the stored path on the stored
+    # instance; the stored-only options are refused.
+    m, n, kappa, s, tau, seed, r = TWO_STAGE
+    g0 = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=0)
+    g, o, A = pair(TWO_STAGE)
+    xm, rm, st = L.l1ls_solve_cg_newton(g0, max_iter=300, rel_gap_tol=1e-9, op=L.OP_MATRIX_FREE)
+    xs, rs, _ = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9)
+    assert st == L.L1LS_OK and rm["converged"] == 1
+    scale = max(1.0, float(xs.abs().max()))
+    assert float((xs - xm).abs().max()) <= 1e-5 * scale
+    assert math.isclose(rm["primal"], rs["primal"], rel_tol=1e-9)
+    for kw in (dict(polish=1), dict(precision=L.F32)):
+        with pytest.raises(L.L1lsError):
+            L.l1ls_solve_cg_newton(g0, max_iter=2, op=L.OP_MATRIX_FREE, **kw)
+    with pytest.raises(L.L1lsError):       # no stored operator to fall back on
+        L.l1ls_solve_cg_newton(g0, max_iter=2)
+    gn = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, layout=L.LAYOUT_NATURAL)
+    with pytest.raises(L.L1lsError):       # the matrix-free products work in stage order
+        L.l1ls_solve_cg_newton(gn, max_iter=2, op=L.OP_MATRIX_FREE)
