@@ -125,74 +125,108 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     if (done && *done) return;  // the solver's converged flag (launch-uniform)
     const int64_t m = tb.m, mp = m / 2;
     const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
+    const bool mine = k < mp;
+    const int64_t kc = mine ? k : mp - 1;  // threads past the end load in bounds, use nothing
+    // Everything that does not depend on the gather is loaded first, so that
+    // its latency overlaps the gather's: the rotations of the thread's pairs,
+    // b and r_x,prev at its two outputs, sigma at its stage-1 pair.
+    const CS<T> c1 = cs_of(tb.csm[0], kc);  // stage-1 pair k
+    CS<T> c1n{T(0), T(0)}, c2{T(0), T(0)}, c2m{T(0), T(0)};
+    int64_t ps[2];
+    if (R == 2) {
+        c1n = cs_of(tb.csm[0], wrap(kc + 1, mp));  // stage-1 pair k+1
+        c2 = cs_of(tb.csm[1], kc);                 // stage-2 pair k
+        if (MODE != kMfProduct) c2m = cs_of(tb.csm[1], wrap(kc - 1, mp));  // stage-2 pair k-1, for Q^T
+        ps[0] = 2 * kc + 1;
+        ps[1] = wrap(2 * kc + 2, m);
+    } else {
+        ps[0] = 2 * kc;
+        ps[1] = 2 * kc + 1;
+    }
+    T bo[2] = {T(0), T(0)}, rpo[2] = {T(0), T(0)};
+    if (MODE == kMfFista) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            bo[e] = b[ps[e]];
+            if (!init) rpo[e] = rxp[ps[e]];
+        }
+    }
+    T s0 = T(0), s1 = T(0);
+    if (MODE != kMfProduct) {
+        s0 = tb.sig[2 * kc];
+        s1 = tb.sig[2 * kc + 1];
+    }
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
         const int64_t p = ring(2 * k0 - H + q + m, m);
         const int32_t a = tb.emb[p];
         zl[q] = (a >= 0) ? ld_off32(w, a) : T(0);
     }
     __syncthreads();
-    const int t = threadIdx.x;
-    const int64_t k = k0 + t;
     double v[3] = {0.0, 0.0, 0.0};
     if (R == 2) {
-        // own stage-2 pair k (t < B) and, in thread 0, the left neighbour pair
-        // k0-1 (only Q^T reads it)
-        for (int h = 0; h < ((t == 0 && MODE != kMfProduct) ? 2 : 1); ++h) {
-            const bool own = (h == 0);
-            const int64_t j = own ? k : wrap(k0 - 1, mp);
-            if (own && j >= mp) break;
-            const int q0 = own ? 2 * t + 2 : 0;  // z at 2j .. 2j+3
+        // thread 0 also evaluates the left neighbour's stage-2 pair k0-1 (not
+        // stored): Q^T of stage-1 pair k0 reads r_y at 2k0-1
+        if (t == 0 && MODE != kMfProduct) {
+            const int64_t j = wrap(k0 - 1, mp);
             T a, u1, u2, bb, rf, rg;
-            rot(cs_of(tb.csm[0], j), zl[q0], zl[q0 + 1], false, a, u1);
-            rot(cs_of(tb.csm[0], wrap(j + 1, mp)), zl[q0 + 2], zl[q0 + 3], false, u2, bb);
+            rot(cs_of(tb.csm[0], j), zl[0], zl[1], false, a, u1);
+            rot(cs_of(tb.csm[0], wrap(j + 1, mp)), zl[2], zl[3], false, u2, bb);
             rot(cs_of(tb.csm[1], j), u1, u2, false, rf, rg);
-            const int64_t ps[2] = {2 * j + 1, wrap(2 * j + 2, m)};
+            const int64_t pn[2] = {2 * j + 1, wrap(2 * j + 2, m)};
             const T rr[2] = {rf, rg};
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                const int64_t i = ps[e];
-                const T bi = (MODE == kMfFista) ? b[i] : T(0);
+                const T bi = (MODE == kMfFista) ? b[pn[e]] : T(0);
                 const T r = rr[e] - bi;
-                const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rxp[i];
-                yl[(own ? 2 * t + 2 : 0) + e] = yv;
-                if (own) {
-                    if (MODE != kMfNormal) rx[i] = r;
-                    v[0] += (double)r * (double)r;
-                    v[1] += (double)yv * (double)yv;
-                    v[2] += (double)bi * (double)yv;
-                }
+                yl[e] = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rxp[pn[e]];
             }
         }
-    } else if (k < mp) {
+        if (mine) {
+            // own stage-2 pair k: r at 2k+1, 2k+2 from z at 2k .. 2k+3
+            const int q0 = 2 * t + 2;
+            T a, u1, u2, bb, rf, rg;
+            rot(c1, zl[q0], zl[q0 + 1], false, a, u1);
+            rot(c1n, zl[q0 + 2], zl[q0 + 3], false, u2, bb);
+            rot(c2, u1, u2, false, rf, rg);
+            const T rr[2] = {rf, rg};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const T r = rr[e] - bo[e];
+                const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rpo[e];
+                yl[q0 + e] = yv;
+                if (MODE != kMfNormal) rx[ps[e]] = r;
+                v[0] += (double)r * (double)r;
+                v[1] += (double)yv * (double)yv;
+                v[2] += (double)bo[e] * (double)yv;
+            }
+        }
+    } else if (mine) {
         T rf, rg;
-        rot(cs_of(tb.csm[0], k), zl[2 * t], zl[2 * t + 1], false, rf, rg);
-        const int64_t ps[2] = {2 * k, 2 * k + 1};
+        rot(c1, zl[2 * t], zl[2 * t + 1], false, rf, rg);
         const T rr[2] = {rf, rg};
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int64_t i = ps[e];
-            const T bi = (MODE == kMfFista) ? b[i] : T(0);
-            const T r = rr[e] - bi;
-            const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rxp[i];
+            const T r = rr[e] - bo[e];
+            const T yv = (init || MODE != kMfFista) ? r : (T(1) + beta) * r - beta * rpo[e];
             yl[2 * t + e] = yv;
-            if (MODE != kMfNormal) rx[i] = r;
+            if (MODE != kMfNormal) rx[ps[e]] = r;
             v[0] += (double)r * (double)r;
             v[1] += (double)yv * (double)yv;
-            v[2] += (double)bi * (double)yv;
+            v[2] += (double)bo[e] * (double)yv;
         }
     }
     __syncthreads();
-    if (MODE != kMfProduct && k < mp) {
+    if (MODE != kMfProduct && mine) {
         // v for stage-1 pair k; pairs with both positions inactive are not read
-        const T s0 = tb.sig[2 * k], s1 = tb.sig[2 * k + 1];
         if (s0 != T(0) || s1 != T(0)) {
             T z0, z1;
             if (R == 2) {
-                const T ym = yl[2 * t], yp = yl[2 * t + 3];  // r_y at 2k-1 and 2k+2
                 T a, bq;
-                rot(cs_of(tb.csm[1], wrap(k - 1, mp)), ym, yl[2 * t + 1], true, a, bq);
+                rot(c2m, yl[2 * t], yl[2 * t + 1], true, a, bq);  // r_y at 2k-1, 2k
                 const T z0n = bq;
-                rot(cs_of(tb.csm[1], k), yl[2 * t + 2], yp, true, a, bq);
+                rot(c2, yl[2 * t + 2], yl[2 * t + 3], true, a, bq);  // r_y at 2k+1, 2k+2
                 z0 = z0n;
                 z1 = a;
             } else {
@@ -200,7 +234,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
                 z1 = yl[2 * t + 1];
             }
             T o0, o1;
-            rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
+            rot(c1, z0, z1, true, o0, o1);
             vm[2 * k] = s0 * o0;
             vm[2 * k + 1] = s1 * o1;
         }
@@ -355,41 +389,59 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
     if (done && *done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
     const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
+    const bool mine = k < np;
+    const int64_t kc = mine ? k : np - 1;  // threads past the end load in bounds, use nothing
+    // operands independent of the gather first: rotations, p, d, mask
+    const CS<T> c1 = cs_of(tb.csn[0], kc);
+    CS<T> c1n{T(0), T(0)}, c2{T(0), T(0)};
+    int64_t ps[2];
+    if (R == 2) {
+        c1n = cs_of(tb.csn[0], wrap(kc + 1, np));
+        c2 = cs_of(tb.csn[1], kc);
+        ps[0] = 2 * kc + 1;
+        ps[1] = wrap(2 * kc + 2, n);
+    } else {
+        ps[0] = 2 * kc;
+        ps[1] = 2 * kc + 1;
+    }
+    T pv[2] = {T(0), T(0)}, dv[2] = {T(0), T(0)};
+    bool on[2] = {true, true};
+    if (p) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            pv[e] = p[ps[e]];
+            if (d) dv[e] = d[ps[e]];
+            if (mask) on[e] = mask[ps[e]] != 0;
+        }
+    }
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
         const int64_t pos = ring(2 * k0 - H + q + n, n);
         tl[q] = ld_off32(vm, tb.inv[pos]);
     }
     __syncthreads();
-    const int t = threadIdx.x;
-    const int64_t k = k0 + t;
     double acc[1] = {0.0};
-    if (k < np) {
+    if (mine) {
         T gv[2];
-        int64_t ps[2];
         if (R == 2) {
             const int q0 = 2 * t + 2;  // t at 2k .. 2k+3
             T a, u1, u2, bb;
-            rot(cs_of(tb.csn[0], k), tl[q0], tl[q0 + 1], false, a, u1);
-            rot(cs_of(tb.csn[0], wrap(k + 1, np)), tl[q0 + 2], tl[q0 + 3], false, u2, bb);
-            rot(cs_of(tb.csn[1], k), u1, u2, false, gv[0], gv[1]);
-            ps[0] = 2 * k + 1;
-            ps[1] = wrap(2 * k + 2, n);
+            rot(c1, tl[q0], tl[q0 + 1], false, a, u1);
+            rot(c1n, tl[q0 + 2], tl[q0 + 3], false, u2, bb);
+            rot(c2, u1, u2, false, gv[0], gv[1]);
         } else {
-            rot(cs_of(tb.csn[0], k), tl[2 * t], tl[2 * t + 1], false, gv[0], gv[1]);
-            ps[0] = 2 * k;
-            ps[1] = 2 * k + 1;
+            rot(c1, tl[2 * t], tl[2 * t + 1], false, gv[0], gv[1]);
         }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int64_t j = ps[e];
             T h = gv[e];
             if (p) {
-                const T pj = p[j];
-                if (d) h += d[j] * pj;
-                if (mask && !mask[j]) h = T(0);
-                acc[0] += (double)pj * (double)h;
+                if (d) h += dv[e] * pv[e];
+                if (!on[e]) h = T(0);
+                acc[0] += (double)pv[e] * (double)h;
             }
-            out[j] = h;
+            out[ps[e]] = h;
         }
     }
     if (!part) return;  // launch-uniform
