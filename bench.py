@@ -9,7 +9,7 @@ soft-threshold prox, momentum) and the device-side duality-gap test every
 `--check-every` iterations.  All inputs are generated on the device before
 the timed region.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+Prints one JSON line.  `--gpus N` with N > 1 exits: the solver runs on one
 GPU.
 """
 import argparse
@@ -864,7 +864,7 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     if args.workload != "fista":
