@@ -965,6 +965,9 @@ def main():
     def rel_err(x):
         return float((x - xstar).norm() / xstar.norm())
 
+    # L: the closed form sigma_1^2 = 1 against 30 FP64 power-method steps
+    lam30 = L.l1ls_power_iteration(inst, 30, stream=stream)
+
     line = {
         "metric": "FISTA iters/sec (SpMV pair A*y, A^T*r fused with prox, momentum, gap)",
         "value": value,
@@ -993,6 +996,7 @@ def main():
             "generate_s": gen_s,
             "final_rel_gap_fp64": gap,
             "final_rel_err_planted": rel_err(plain["x"]),
+            "lipschitz": {"closed_form": inst.info().L, "power_iteration_30_steps": lam30},
             "timed_ms_with_kernel_events": timed["ms"],
             "matrix_free": {
                 "iters_per_s": args.steps / (mfree["ms"] / 1e3),

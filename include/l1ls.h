@@ -240,6 +240,21 @@ l1ls_status l1ls_solve_cg_newton(const l1ls_instance* inst, const l1ls_solve_opt
                                  double* x_out_dev, l1ls_report* report);
 
 /*
+ * lambda_max(A^T A), the Lipschitz constant L of the gradient of
+ * 0.5 ||A x - b||^2 (section 8.1 uses it as the FISTA step 1/L), by the
+ * power method in FP64: v_0 = v0_dev / ||v0_dev|| (n values in the original
+ * order, device; NULL: the all-ones vector), then `iters` steps
+ * w = A^T (A v), lambda = v^T w, v = w / ||w||; *lambda_out receives the
+ * last lambda.  The generator's sigma law gives L = sigma_1^2 = 1 in closed
+ * form (l1ls_info.L); this is the estimate for operators without one.  op is
+ * L1LS_OP_STORED (needs L1LS_STORE_F64) or L1LS_OP_MATRIX_FREE (STAGE
+ * layout).  L1LS_E_ARG for iters < 1 or a zero start, L1LS_E_UNSUPPORTED
+ * when the operator is not available.  Blocks until done.
+ */
+l1ls_status l1ls_power_iteration(const l1ls_instance* inst, int32_t op, int32_t iters,
+                                 const double* v0_dev, double* lambda_out, void* stream);
+
+/*
  * Stepping interface of FISTA (the iteration above, state kept on the
  * device).  create: x_0 = x0 (or 0), one residual pass.  iterate: enqueue
  * `iters` iterations on opts.stream without synchronising; once the gap test

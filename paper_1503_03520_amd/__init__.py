@@ -115,6 +115,8 @@ _SIGS = {
     "l1ls_instance_info": (ctypes.c_int, [_P, ctypes.POINTER(Info)]),
     "l1ls_free": (None, [_P]),
     "l1ls_apply": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "l1ls_power_iteration": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
+                                            _P]),
     "l1ls_objective_gap": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
     "l1ls_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
@@ -273,6 +275,14 @@ def solve_opts(**kw):
 def l1ls_apply(inst, trans, op, prec, x_in, x_out, stream=None):
     _check(lib().l1ls_apply(inst.handle, trans, op, prec, _ptr(x_in), _ptr(x_out), _stream(stream)),
            "l1ls_apply")
+
+
+def l1ls_power_iteration(inst, iters, op=OP_STORED, v0=None, stream=None):
+    """lambda_max(A^T A) by the FP64 power method (l1ls_power_iteration)."""
+    lam = ctypes.c_double()
+    _check(lib().l1ls_power_iteration(inst.handle, op, int(iters), _ptr(v0), ctypes.byref(lam), _stream(stream)),
+           "l1ls_power_iteration")
+    return lam.value
 
 
 def l1ls_objective_gap(inst, tau, x, stream=None):

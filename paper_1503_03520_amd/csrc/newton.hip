@@ -311,6 +311,22 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_gap_terms(const double* __restri
         for (int q = 0; q < 4; ++q) part[4 * blockIdx.x + q] = v[q];
 }
 
+// Power-method terms: part = (v . w, w . w).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_power_terms(const double* __restrict__ v,
+                                                            const double* __restrict__ w, int64_t n,
+                                                            double* __restrict__ part) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        acc[0] += v[i] * w[i];
+        acc[1] += w[i] * w[i];
+    }
+    block_reduce_stats<2, 2>(acc);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = acc[0];
+        part[2 * blockIdx.x + 1] = acc[1];
+    }
+}
+
 // part = (grad . dx, sum psi_mu(x + a dx) | over m: sum (r + a q)^2)
 __global__ __launch_bounds__(L1LS_BLOCK) void k_ls_terms(const double* __restrict__ x,
                                                          const double* __restrict__ dx,
@@ -411,6 +427,11 @@ __global__ void k_polish_apply(double* __restrict__ x, uint8_t* __restrict__ mas
 __global__ void k_mask_mul(double* __restrict__ x, const uint8_t* __restrict__ mask, int64_t n) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n && !mask[j]) x[j] = 0.0;
+}
+
+__global__ void k_fill_f64(double* __restrict__ out, double v, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) out[i] = v;
 }
 
 __global__ void k_axpby(const double* __restrict__ a, double alpha, const double* __restrict__ b, double beta,
@@ -720,4 +741,51 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = r;
     return r.converged ? L1LS_OK : L1LS_NOT_CONVERGED;
+}
+
+// lambda_max(A^T A) by the power method (the FP64 estimate of L for sigma
+// laws without a closed form): v_0 = v0 / ||v0|| (or the normalised all-ones
+// vector), then per step w = A^T (A v), lambda = v . w, v = w / ||w||.
+// Returns the last lambda.
+extern "C" l1ls_status l1ls_power_iteration(const l1ls_instance* I, int32_t op, int32_t iters, const double* v0_dev,
+                                            double* lambda_out, void* stream) {
+    if (!I || !lambda_out || iters < 1) return L1LS_E_ARG;
+    if (op != L1LS_OP_STORED && op != L1LS_OP_MATRIX_FREE) return L1LS_E_ARG;
+    const bool mf = (op == L1LS_OP_MATRIX_FREE);
+    if (!mf && (!I->csr_v64 || !I->csc_v64)) return L1LS_E_UNSUPPORTED;
+    if (mf && (!I->mf_emb || I->layout != L1LS_LAYOUT_STAGE || I->m * (int64_t)sizeof(double) >= ((int64_t)1 << 32)))
+        return L1LS_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = I->n;
+    Work W;
+    L1LS_TRY(W.init(I, s));
+    if (mf) L1LS_TRY(W.init_mf());
+    // v in operator order (W.x), w = A^T A v (W.atr), A v in W.rres
+    if (v0_dev)
+        hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, v0_dev, W.x,
+                           I->op_col_of, n);
+    else
+        hipLaunchKernelGGL(k_fill_f64, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, 1.0, n);
+    double t2[2];
+    hipLaunchKernelGGL(k_power_terms, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.x, W.x, n, W.part);
+    L1LS_TRY(W.host_sums(2, kRedBlocks, t2));
+    if (!(t2[1] > 0.0) || !is_finite(t2[1])) return L1LS_E_ARG;
+    hipLaunchKernelGGL(k_axpby, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, 1.0 / std::sqrt(t2[1]),
+                       (const double*)nullptr, 0.0, W.x, n);
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        W.spmv(W.x, W.rres);
+        W.spmv_t(W.rres, W.atr);
+        hipLaunchKernelGGL(k_power_terms, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, W.x, W.atr, n, W.part);
+        L1LS_TRY(W.host_sums(2, kRedBlocks, t2));
+        lam = t2[0];
+        if (!is_finite(lam) || !is_finite(t2[1])) return L1LS_E_NONFINITE;
+        if (!(t2[1] > 0.0)) break;  // A v = 0: v is in the null space (lambda = 0)
+        hipLaunchKernelGGL(k_axpby, g1d(n), dim3(L1LS_BLOCK), 0, s, W.atr, 1.0 / std::sqrt(t2[1]),
+                           (const double*)nullptr, 0.0, W.x, n);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    *lambda_out = lam;
+    return L1LS_OK;
 }

@@ -178,3 +178,9 @@ def test_generate_rejects_stored_operator_beyond_32bit_gathers():
     o = L.GenOpts(2, L.STORE_F32, None, 1)
     st = L.lib().l1ls_generate_ex(1 << 29, 1 << 20, 10.0, 1, 1.0, 1, ctypes.byref(o), ctypes.byref(h))
     assert st == -6 and not h.value
+
+
+def test_power_iteration_rejects_null_and_bad_counts():
+    lam = ctypes.c_double()
+    assert L.lib().l1ls_power_iteration(None, 0, 10, None, ctypes.byref(lam), None) == -1
+    assert L.lib().l1ls_power_iteration(None, 0, 0, None, ctypes.byref(lam), None) == -1

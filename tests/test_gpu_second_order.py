@@ -160,3 +160,31 @@ def test_cg_newton_matrix_free_without_stored_operator():
     gn = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, layout=L.LAYOUT_NATURAL)
     with pytest.raises(L.L1lsError):       # the matrix-free products work in stage order
         L.l1ls_solve_cg_newton(gn, max_iter=2, op=L.OP_MATRIX_FREE)
+
+
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED])
+@pytest.mark.parametrize("op", [L.OP_STORED, L.OP_MATRIX_FREE])
+def test_power_iteration_matches_oracle(cfg, op):
+    # same start vector, same steps: the Rayleigh quotients agree to rounding
+    g, o, A = pair(cfg)
+    iters, seed = 30, 3
+    v0 = np.random.default_rng(seed).standard_normal(o.n)   # the oracle's start for this seed
+    lam = L.l1ls_power_iteration(g, iters, op=op, v0=_dev(v0))
+    ref = F.power_iteration(lambda v: A @ v, lambda v: A.T @ v, o.n, iters, seed=seed)
+    assert math.isclose(lam, ref, rel_tol=1e-12)
+
+
+def test_power_iteration_reaches_sigma1_squared():
+    # lambda_max(A^T A) = sigma_1^2 = 1 for the generator's sigma law; with
+    # kappa = 10 and n = 128 the eigenvalue gap is large enough for 2000 steps
+    m, n, kappa, s, tau, seed, r = (256, 128, 10.0, 2, 1.0, 5, 2)
+    g = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r)
+    for op in (L.OP_STORED, L.OP_MATRIX_FREE):
+        lam = L.l1ls_power_iteration(g, 2000, op=op)
+        assert abs(lam - 1.0) <= 1e-6 and lam <= 1.0 + 1e-12
+    with pytest.raises(L.L1lsError):                      # zero start
+        L.l1ls_power_iteration(g, 5, v0=torch.zeros(n, dtype=torch.float64, device="cuda"))
+    g0 = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=0)
+    with pytest.raises(L.L1lsError):                      # no stored FP64 operator
+        L.l1ls_power_iteration(g0, 5)
+    assert abs(L.l1ls_power_iteration(g0, 2000, op=L.OP_MATRIX_FREE) - 1.0) <= 1e-6
