@@ -968,6 +968,21 @@ def main():
     # L: the closed form sigma_1^2 = 1 against 30 FP64 power-method steps
     lam30 = L.l1ls_power_iteration(inst, 30, stream=stream)
 
+    # the small FP64 workload (n = 1024, m = 2048, kappa = 1e2, one stage,
+    # s = 10, tau = 1): a latency-bound regime, solved to rel gap 1e-8, then
+    # the FP64 polish
+    small = L.l1ls_generate(2048, 1024, 1e2, 10, 1.0, 1503035200, rounds=1, stream=stream)
+    L.l1ls_solve_fista(small, max_iter=64, rel_gap_tol=0.0, precision=L.F64, stream=stream)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, srep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
+                                    stream=stream)
+    torch.cuda.synchronize()
+    small_s = time.perf_counter() - t0
+    _, prep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
+                                    polish=1, stream=stream)
+    small.free()
+
     line = {
         "metric": "FISTA iters/sec (SpMV pair A*y, A^T*r fused with prox, momentum, gap)",
         "value": value,
@@ -997,6 +1012,12 @@ def main():
             "final_rel_gap_fp64": gap,
             "final_rel_err_planted": rel_err(plain["x"]),
             "lipschitz": {"closed_form": inst.info().L, "power_iteration_30_steps": lam30},
+            "small_fp64": {"workload": "n=1024, m=2048, kappa=1e2, 1 stage, s=10, tau=1, FP64",
+                           "iterations_to_gap_1e-8": srep["iterations"], "seconds": small_s,
+                           "iters_per_s": srep["iterations"] / small_s, "rel_gap": srep["rel_gap"],
+                           "rel_err_planted": srep["rel_err"],
+                           "with_polish": {"seconds": prep["seconds"], "rel_gap": prep["rel_gap"],
+                                           "rel_err_planted": prep["rel_err"]}},
             "timed_ms_with_kernel_events": timed["ms"],
             "matrix_free": {
                 "iters_per_s": args.steps / (mfree["ms"] / 1e3),
