@@ -80,12 +80,13 @@ def write_profile_summary(args):
     copy_w, _ = counter(args.copyw, "WRITE_SIZE", "copyBuffer")
     gib_kib = float(1 << 20)            # the copy moves 1 GiB = 2^20 KiB each way
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
+    kt_cmd = args.kt_command or "python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline"
+    pmc_cmd = args.pmc_command or "python3 bench.py --steps 40 --warmup 4 --no-cpu-baseline"
     lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator), "
-             "FP32 bulk, n=2^20, m=2^21, 2 stages",
-             f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
-             f"python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline",
+             "FP32 bulk, " + (args.stats_title or "n=2^20, m=2^21, 2 stages"),
+             f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- {kt_cmd}",
              f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
-             f"python3 bench.py --steps 40 --warmup 4 --no-cpu-baseline",
+             f"{pmc_cmd}",
              f"# copy scale:   rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) ... -- python3 bench.py --copy-calibration",
              f"# summary:      python3 bench.py --profile-summary --kt ... --fetch ... --write ... --copyf ... --copyw ...",
              f"kernel_source_hash: {kernel_source_hash()}",
@@ -809,6 +810,8 @@ def main():
     ap.add_argument("--stats-summary", action="store_true",
                     help="write the top kernels of the rocprofv3 --stats run in --kt to --out")
     ap.add_argument("--stats-title", default="")
+    ap.add_argument("--kt-command", default="", help="profile summary: the kernel-trace command it came from")
+    ap.add_argument("--pmc-command", default="", help="profile summary: the counter command it came from")
     ap.add_argument("--stats-command", default="")
     ap.add_argument("--stats-top", type=int, default=14)
     ap.add_argument("--out", default=PROFILE_SUMMARY)
