@@ -548,7 +548,8 @@ def bench_large(args):
     same = float((x_s - x_m).abs().max())
     newton = {}
     for prec, op, name in ((L.F32, L.OP_STORED, "f32_hessian_products"), (L.F64, L.OP_STORED, "f64"),
-                           (L.F64, L.OP_MATRIX_FREE, "matrix_free_f64")):
+                           (L.F64, L.OP_MATRIX_FREE, "matrix_free_f64"),
+                           (L.F32, L.OP_MATRIX_FREE, "matrix_free_f32_hessian_products")):
         t = time.perf_counter()
         xn, rn, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, stream=stream,
                                            precision=prec, op=op)

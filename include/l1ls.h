@@ -230,10 +230,12 @@ l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* o
  * max_iter Newton steps (report.iterations; report.inner = PCG iterations).
  * opts.op = L1LS_OP_STORED uses the stored FP64 operator (L1LS_STORE_F64).
  * opts.op = L1LS_OP_MATRIX_FREE applies A and A^T from the rotation tables
- * in FP64 (Algorithms MvPA / MvPAt, section 4), so it needs no stored A:
- * it requires precision L1LS_F64, the STAGE layout and 8 m < 2^32, and the
- * final certificate (report.primal / dual / rel_gap) is evaluated with the
- * same products; opts.polish still needs L1LS_STORE_F64.
+ * (Algorithms MvPA / MvPAt, section 4), so it needs no stored A: vectors and
+ * sums are FP64, and with precision L1LS_F32 the Hessian products of the
+ * Newton directions read the FP32 copies of the rotation coefficients and
+ * sigma; it requires the STAGE layout and 8 m < 2^32, and the final
+ * certificate (report.primal / dual / rel_gap) is evaluated with FP64
+ * products; opts.polish still needs L1LS_STORE_F64.
  * L1LS_E_UNSUPPORTED for other combinations.
  */
 l1ls_status l1ls_solve_cg_newton(const l1ls_instance* inst, const l1ls_solve_opts* opts,

@@ -52,8 +52,9 @@ __device__ __forceinline__ CS<T> cs_of(const T* tab, int64_t k) {
 __device__ __forceinline__ int64_t wrap(int64_t p, int64_t N) { return p < 0 ? p + N : (p >= N ? p - N : p); }
 
 // G(f,g): (zf, zg) -> (c zf - s zg, s zf + c zg); transpose: (c zf + s zg, -s zf + c zg)
-template <typename T>
-__device__ __forceinline__ void rot(CS<T> r, T zf, T zg, bool transpose, T& of, T& og) {
+template <typename T, typename TT>
+__device__ __forceinline__ void rot(CS<TT> rt, T zf, T zg, bool transpose, T& of, T& og) {
+    const CS<T> r{(T)rt.c, (T)rt.s};  // tables of type TT, vectors of type T
     if (transpose) {
         of = r.c * zf + r.s * zg;
         og = -r.s * zf + r.c * zg;
@@ -73,8 +74,8 @@ __device__ __forceinline__ int64_t ring(int64_t p, int64_t N) {
 // w = Sigma_n G^T x in n-stage order (sigma at n-positions, 0 where the
 // column has no sigma).  R = 2: G^T = S_1^T S_2^T (S_2^T first); thread k
 // handles stage-1 pair (2k, 2k+1) from x at 2k-1 .. 2k+2.
-template <typename T, int R>
-__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ w, MfTabs<T> tb,
+template <typename T, int R, typename TT = T>
+__global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T* __restrict__ w, MfTabs<TT> tb,
                                                        const int32_t* __restrict__ done) {
     if (done && *done) return;  // the solver's converged flag (launch-uniform)
     const int64_t n = tb.n, np = n / 2;
@@ -92,8 +93,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T
     }
     T o0, o1;
     rot(cs_of(tb.csn[0], k), z0, z1, true, o0, o1);
-    w[2 * k] = tb.sig_n[2 * k] * o0;
-    w[2 * k + 1] = tb.sig_n[2 * k + 1] * o1;
+    w[2 * k] = (T)tb.sig_n[2 * k] * o0;
+    w[2 * k + 1] = (T)tb.sig_n[2 * k + 1] * o1;
 }
 
 // Residual pass fused with the m side of the next transpose product.
@@ -112,11 +113,11 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_gt(const T* __restrict__ x, T
 //   kMfNormal  vm = Sigma_m Q^T (A x) only (b = 0, rx not written): the
 //              m side of A^T A x for the second-order path.
 constexpr int kMfFista = 0, kMfProduct = 1, kMfNormal = 2;
-template <typename T, int R, int MODE = kMfFista>
+template <typename T, int R, int MODE = kMfFista, typename TT = T>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ w, const T* __restrict__ b,
                                                            const T* __restrict__ rxp, T* __restrict__ rx,
                                                            T* __restrict__ vm, T beta,
-                                                           int init, MfTabs<T> tb, double* __restrict__ part,
+                                                           int init, MfTabs<TT> tb, double* __restrict__ part,
                                                            const int32_t* __restrict__ done, int stats) {
     constexpr int B = L1LS_BLOCK;
     constexpr int H = (R == 2) ? 2 : 0;  // halo positions on the left
@@ -132,8 +133,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     // Everything that does not depend on the gather is loaded first, so that
     // its latency overlaps the gather's: the rotations of the thread's pairs,
     // b and r_x,prev at its two outputs, sigma at its stage-1 pair.
-    const CS<T> c1 = cs_of(tb.csm[0], kc);  // stage-1 pair k
-    CS<T> c1n{T(0), T(0)}, c2{T(0), T(0)}, c2m{T(0), T(0)};
+    const CS<TT> c1 = cs_of(tb.csm[0], kc);  // stage-1 pair k
+    CS<TT> c1n{TT(0), TT(0)}, c2{TT(0), TT(0)}, c2m{TT(0), TT(0)};
     int64_t ps[2];
     if (R == 2) {
         c1n = cs_of(tb.csm[0], wrap(kc + 1, mp));  // stage-1 pair k+1
@@ -155,8 +156,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     }
     T s0 = T(0), s1 = T(0);
     if (MODE != kMfProduct) {
-        s0 = tb.sig[2 * kc];
-        s1 = tb.sig[2 * kc + 1];
+        s0 = (T)tb.sig[2 * kc];
+        s1 = (T)tb.sig[2 * kc + 1];
     }
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
         const int64_t p = ring(2 * k0 - H + q + m, m);
@@ -377,10 +378,10 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T
 //   out = h, part[block] = sum p h (part optional);
 // without p: out = g.  Gather and halo as in k_mf_prox_gt (R = 2: thread t
 // owns stage-2 pair k0 + t, outputs at 2k+1 and 2k+2).
-template <typename T, int R>
+template <typename T, int R, typename TT = T>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ vm, const T* __restrict__ p,
                                                            const T* __restrict__ d, const uint8_t* __restrict__ mask,
-                                                           T* __restrict__ out, MfTabs<T> tb,
+                                                           T* __restrict__ out, MfTabs<TT> tb,
                                                            double* __restrict__ part,
                                                            const int32_t* __restrict__ done) {
     constexpr int B = L1LS_BLOCK;
@@ -394,8 +395,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
     const bool mine = k < np;
     const int64_t kc = mine ? k : np - 1;  // threads past the end load in bounds, use nothing
     // operands independent of the gather first: rotations, p, d, mask
-    const CS<T> c1 = cs_of(tb.csn[0], kc);
-    CS<T> c1n{T(0), T(0)}, c2{T(0), T(0)};
+    const CS<TT> c1 = cs_of(tb.csn[0], kc);
+    CS<TT> c1n{TT(0), TT(0)}, c2{TT(0), TT(0)};
     int64_t ps[2];
     if (R == 2) {
         c1n = cs_of(tb.csn[0], wrap(kc + 1, np));
@@ -599,25 +600,29 @@ template void mf_transpose_launch<double>(const l1ls_instance*, const double*, d
 // ---- products for the second-order path (FP64, stage order) -----------------
 // A x with x (n) and out (m) in stage order: w = Sigma_n G^T x, then the
 // m-side pass writes out = A x.
-template <int MODE>
+// TT: type of the rotation tables and sigma (double, or float for the
+// FP32-coefficient Hessian products); vectors and arithmetic are FP64.
+template <int MODE, typename TT>
 void mf_fwd_launch(const l1ls_instance* I, const double* x, double* wn, double* out, double* vm, const int32_t* done,
                    hipStream_t s) {
-    const MfTabs<double> tb = tabs_of<double>(I);
+    const MfTabs<TT> tb = tabs_of<TT>(I);
     if (I->rounds == 2) {
-        hipLaunchKernelGGL((k_mf_gt<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb, done);
-        hipLaunchKernelGGL((k_mf_res_qt<double, 2, MODE>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
+        hipLaunchKernelGGL((k_mf_gt<double, 2, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb,
+                           done);
+        hipLaunchKernelGGL((k_mf_res_qt<double, 2, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
                            (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
                            done, 0);
     } else {
-        hipLaunchKernelGGL((k_mf_gt<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb, done);
-        hipLaunchKernelGGL((k_mf_res_qt<double, 1, MODE>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
+        hipLaunchKernelGGL((k_mf_gt<double, 1, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb,
+                           done);
+        hipLaunchKernelGGL((k_mf_res_qt<double, 1, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
                            (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
                            done, 0);
     }
 }
 
 void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s) {
-    mf_fwd_launch<kMfProduct>(I, x, wn, out, (double*)nullptr, (const int32_t*)nullptr, s);
+    mf_fwd_launch<kMfProduct, double>(I, x, wn, out, (double*)nullptr, (const int32_t*)nullptr, s);
 }
 
 // out (n) = A^T y with y (m) and out in stage order; vm is m scratch.
@@ -638,14 +643,25 @@ void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* o
 
 // hp = mask (A^T A p + d p) with part[block] = sum p hp over mf_grid(n/2)
 // blocks (A p itself is not stored).  Skipped once *done is set.
-void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
-             double* hp, double* part, const int32_t* done, hipStream_t s) {
-    mf_fwd_launch<kMfNormal>(I, p, wn, (double*)nullptr, vm, done, s);
-    const MfTabs<double> tb = tabs_of<double>(I);
+template <typename TT>
+void mf_hess_t(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d,
+               const uint8_t* mask, double* hp, double* part, const int32_t* done, hipStream_t s) {
+    mf_fwd_launch<kMfNormal, TT>(I, p, wn, (double*)nullptr, vm, done, s);
+    const MfTabs<TT> tb = tabs_of<TT>(I);
     if (I->rounds == 2)
-        hipLaunchKernelGGL((k_mf_g_hess<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+        hipLaunchKernelGGL((k_mf_g_hess<double, 2, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
                            mask, hp, tb, part, done);
     else
-        hipLaunchKernelGGL((k_mf_g_hess<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+        hipLaunchKernelGGL((k_mf_g_hess<double, 1, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
                            mask, hp, tb, part, done);
+}
+
+// f32: the rotation coefficients and sigma of the products are the FP32
+// copies (vectors and sums stay FP64), as the stored path's FP32 values.
+void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
+             double* hp, double* part, const int32_t* done, hipStream_t s, bool f32) {
+    if (f32)
+        mf_hess_t<float>(I, p, wn, vm, d, mask, hp, part, done, s);
+    else
+        mf_hess_t<double>(I, p, wn, vm, d, mask, hp, part, done, s);
 }

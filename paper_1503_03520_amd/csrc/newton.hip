@@ -31,7 +31,7 @@ l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out
 void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s);
 void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* out, hipStream_t s);
 void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
-             double* hp, double* part, const int32_t* done, hipStream_t s);
+             double* hp, double* part, const int32_t* done, hipStream_t s, bool f32);
 int mf_grid(int64_t pairs);
 
 namespace {
@@ -522,7 +522,7 @@ struct Work {
         const int64_t n = I->n;
         const int gt = tgrid(n);
         if (mf) {
-            mf_hess(I, v, wn, vm, dv, mk, hp, part, &cs->done, s);
+            mf_hess(I, v, wn, vm, dv, mk, hp, part, &cs->done, s, f32);
             return;
         }
         if (f32) {
@@ -632,7 +632,7 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
     // the matrix-free products are FP64 and work in stage order (the order
     // of the solver's vectors under the STAGE layout); the polish needs the
     // stored FP64 A
-    if (mf && (o->precision != L1LS_F64 || !I->mf_emb || I->layout != L1LS_LAYOUT_STAGE ||
+    if (mf && (!I->mf_emb || I->layout != L1LS_LAYOUT_STAGE ||
                I->m * (int64_t)sizeof(double) >= ((int64_t)1 << 32) ||
                (o->polish && (!I->csr_v64 || !I->csc_v64))))
         return L1LS_E_UNSUPPORTED;
@@ -650,8 +650,8 @@ extern "C" l1ls_status l1ls_solve_cg_newton(const l1ls_instance* I, const l1ls_s
     if (!is_finite(tau) || !is_finite(mu)) return L1LS_E_ARG;
     const int64_t n = I->n, m = I->m;
     Work W;
-    W.hv32 = !mf && (o->precision == L1LS_F32);
-    if (W.hv32 && (!I->csr_v32 || !I->csc_v32)) return L1LS_E_UNSUPPORTED;
+    W.hv32 = (o->precision == L1LS_F32);
+    if (W.hv32 && !mf && (!I->csr_v32 || !I->csc_v32)) return L1LS_E_UNSUPPORTED;
     L1LS_TRY(W.init(I, s));
     if (mf) L1LS_TRY(W.init_mf());
     if (o->x0_dev)

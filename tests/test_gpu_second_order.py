@@ -106,14 +106,16 @@ def test_cg_newton_zero_when_tau_dominates():
 
 
 @pytest.mark.parametrize("cfg", [C1, TWO_STAGE])
-def test_cg_newton_fp32_hessian_products_reach_the_same_minimiser(cfg):
-    # FP32 values of A in the Hessian-vector products of the Newton directions
+@pytest.mark.parametrize("op", [L.OP_STORED, L.OP_MATRIX_FREE])
+def test_cg_newton_fp32_hessian_products_reach_the_same_minimiser(cfg, op):
+    # FP32 values of A (stored) or FP32 rotation coefficients and sigma
+    # (matrix-free) in the Hessian-vector products of the Newton directions
     # (vectors, gradient and sums in FP64): the inexact directions change the
     # path, not the minimiser of (8), which the FP64 gradient test certifies.
     g, o, A = pair(cfg)
     mu = 1e-5
     x64, r64, _ = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu)
-    x32, r32, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, precision=L.F32)
+    x32, r32, st = L.l1ls_solve_cg_newton(g, max_iter=300, rel_gap_tol=1e-9, mu=mu, precision=L.F32, op=op)
     assert st == L.L1LS_OK and r32["converged"] == 1
     cn = np.asarray(A.multiply(A).sum(0)).ravel()
     ref, _ = ON.newton_cg(lambda v: A @ v, lambda v: A.T @ v, cn, o.b, o.tau, mu=mu, max_newton=300)
@@ -152,9 +154,11 @@ def test_cg_newton_matrix_free_without_stored_operator():
     scale = max(1.0, float(xs.abs().max()))
     assert float((xs - xm).abs().max()) <= 1e-5 * scale
     assert math.isclose(rm["primal"], rs["primal"], rel_tol=1e-9)
-    for kw in (dict(polish=1), dict(precision=L.F32)):
-        with pytest.raises(L.L1lsError):
-            L.l1ls_solve_cg_newton(g0, max_iter=2, op=L.OP_MATRIX_FREE, **kw)
+    with pytest.raises(L.L1lsError):       # the polish needs the stored FP64 operator
+        L.l1ls_solve_cg_newton(g0, max_iter=2, op=L.OP_MATRIX_FREE, polish=1)
+    x32, r32, st = L.l1ls_solve_cg_newton(g0, max_iter=300, rel_gap_tol=1e-9, op=L.OP_MATRIX_FREE,
+                                          precision=L.F32)
+    assert st == L.L1LS_OK and float((xs - x32).abs().max()) <= 1e-5 * scale
     with pytest.raises(L.L1lsError):       # no stored operator to fall back on
         L.l1ls_solve_cg_newton(g0, max_iter=2)
     gn = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, layout=L.LAYOUT_NATURAL)
