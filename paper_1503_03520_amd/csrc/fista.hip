@@ -30,6 +30,9 @@ void blk_wrap_launch(float* e, int64_t N, hipStream_t s);
 l1ls_status apply_blocked(const l1ls_instance* I, int trans, const float* in, float* out, hipStream_t s);
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
+bool fista_onchip_fits(const l1ls_instance* I, const l1ls_solve_opts* o);
+l1ls_status fista_onchip_run(const l1ls_instance* I, const l1ls_solve_opts* o, double tau, double L, double* x_out,
+                             l1ls_report* rep);
 
 namespace {
 
@@ -655,36 +658,47 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
                                         l1ls_report* rep) {
     if (!I || !opts || !x_out) return L1LS_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
-    l1ls_fista* F = nullptr;
-    L1LS_TRY(l1ls_fista_create(I, opts, &F));
     l1ls_report r;
-    l1ls_status st = L1LS_OK;
-    const int check = std::max(1, opts->check_every);
-    // Enqueue several gap blocks ahead; passes after convergence are no-ops.
-    const int64_t ahead = (int64_t)check * 4;
-    F->stats_until = opts->max_iter;
-    while (F->k < opts->max_iter) {
-        const int64_t step = std::min<int64_t>(ahead, opts->max_iter - F->k);
-        if ((st = l1ls_fista_iterate(F, step)) != L1LS_OK) break;
-        st = l1ls_fista_report(F, &r);
-        if (st != L1LS_OK || r.converged) break;
+    std::memset(&r, 0, sizeof(r));
+    hipStream_t s = (hipStream_t)opts->stream;
+    double tau = opts->tau > 0 ? opts->tau : I->tau;
+    if (fista_onchip_fits(I, opts)) {
+        // small FP64 instance: every iteration in one workgroup (onchip.hip)
+        const double L = opts->L > 0 ? opts->L : I->L;
+        if (opts->check_every < 1 || !(opts->rel_gap_tol >= 0.0) || !is_finite(tau) || !is_finite(L))
+            return L1LS_E_ARG;
+        L1LS_TRY(fista_onchip_run(I, opts, tau, L, x_out, &r));
+    } else {
+        l1ls_fista* F = nullptr;
+        L1LS_TRY(l1ls_fista_create(I, opts, &F));
+        l1ls_status st = L1LS_OK;
+        const int check = std::max(1, opts->check_every);
+        // Enqueue several gap blocks ahead; passes after convergence are no-ops.
+        const int64_t ahead = (int64_t)check * 4;
+        F->stats_until = opts->max_iter;
+        while (F->k < opts->max_iter) {
+            const int64_t step = std::min<int64_t>(ahead, opts->max_iter - F->k);
+            if ((st = l1ls_fista_iterate(F, step)) != L1LS_OK) break;
+            st = l1ls_fista_report(F, &r);
+            if (st != L1LS_OK || r.converged) break;
+        }
+        if (st == L1LS_OK && opts->max_iter % check != 0) {
+            // evaluate the gap at the last iterate as well
+            hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
+                               F->k1part + (size_t)(F->k & 1) * 3 * F->g1,
+                               F->k1part + (size_t)((F->k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2, F->tau,
+                               opts->rel_gap_tol, F->k, F->gs);
+        }
+        if (st == L1LS_OK) st = l1ls_fista_report(F, &r);
+        if (st == L1LS_OK || st == L1LS_E_NONFINITE) {
+            const l1ls_status s2 = l1ls_fista_get_x(F, x_out);
+            if (st == L1LS_OK) st = s2;
+        }
+        s = F->stream;
+        tau = F->tau;
+        l1ls_fista_destroy(F);
+        if (st != L1LS_OK) return st;
     }
-    if (st == L1LS_OK && opts->max_iter % check != 0) {
-        // evaluate the gap at the last iterate as well
-        hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
-                           F->k1part + (size_t)(F->k & 1) * 3 * F->g1,
-                           F->k1part + (size_t)((F->k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2, F->tau,
-                           opts->rel_gap_tol, F->k, F->gs);
-    }
-    if (st == L1LS_OK) st = l1ls_fista_report(F, &r);
-    if (st == L1LS_OK || st == L1LS_E_NONFINITE) {
-        const l1ls_status s2 = l1ls_fista_get_x(F, x_out);
-        if (st == L1LS_OK) st = s2;
-    }
-    hipStream_t s = F->stream;
-    const double tau = F->tau;
-    l1ls_fista_destroy(F);
-    if (st != L1LS_OK) return st;
     int prounds = 0;
     int64_t pcg = 0;
     bool do_polish = opts->polish == 1;
