@@ -245,18 +245,20 @@ l1ls_status fista_onchip_run(const l1ls_instance* I, const l1ls_solve_opts* o, d
             t = t_next;
         }
     }
+    // one device block: the result record, x (n) and the momentum table (K + 1)
     DevArena tmp;
-    double *bt = nullptr, *xb = nullptr;
-    OcResult* res = nullptr;
+    double* blk = nullptr;
+    constexpr int64_t kRes = (sizeof(OcResult) + 7) / 8;
     auto done = [&](l1ls_status st) {
         (void)hipStreamSynchronize(s);
         tmp.release();
         return st;
     };
     l1ls_status st;
-    if ((st = tmp.alloc(&bt, K + 1)) != L1LS_OK) return done(st);
-    if ((st = tmp.alloc(&xb, n)) != L1LS_OK) return done(st);
-    if ((st = tmp.alloc(&res, 1)) != L1LS_OK) return done(st);
+    if ((st = tmp.alloc(&blk, kRes + n + K + 1)) != L1LS_OK) return done(st);
+    OcResult* res = reinterpret_cast<OcResult*>(blk);
+    double* xb = blk + kRes;
+    double* bt = xb + n;
     if (hipMemcpyAsync(bt, betas.data(), (K + 1) * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return done(L1LS_E_HIP);
     if (o->x0_dev)
