@@ -481,6 +481,17 @@ struct Work {
         h.resize(4 * (size_t)std::max(kRedBlocks, tgrid(n)));
         return L1LS_OK;
     }
+    // only what the products and a reduction need: x, atr (n), rres (m), part
+    l1ls_status init_products(const l1ls_instance* inst, hipStream_t stream) {
+        I = inst;
+        s = stream;
+        L1LS_TRY(arena.alloc(&x, I->n));
+        L1LS_TRY(arena.alloc(&atr, I->n));
+        L1LS_TRY(arena.alloc(&rres, I->m));
+        L1LS_TRY(arena.alloc(&part, 4 * (size_t)std::max(kRedBlocks, tgrid(I->n))));
+        h.resize(4 * (size_t)std::max(kRedBlocks, tgrid(I->n)));
+        return L1LS_OK;
+    }
     l1ls_status init_mf() {
         mf = true;
         L1LS_TRY(arena.alloc(&wn, I->n));
@@ -758,7 +769,7 @@ extern "C" l1ls_status l1ls_power_iteration(const l1ls_instance* I, int32_t op, 
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = I->n;
     Work W;
-    L1LS_TRY(W.init(I, s));
+    L1LS_TRY(W.init_products(I, s));
     if (mf) L1LS_TRY(W.init_mf());
     // v in operator order (W.x), w = A^T A v (W.atr), A v in W.rres
     if (v0_dev)
