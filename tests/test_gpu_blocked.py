@@ -35,6 +35,7 @@ CASES = [
     (6, 4, 10.0, 2, 2.0, 6),
     (600, 300, 1.0, 5, 1.0, 8),
     (8192, 4096, 1e4, 41, 1.0, 1503035201),
+    (130, 4, 10.0, 1, 1.0, 12),        # m >> n: most rows hold no run at all
 ]
 # the FP64 workload's sizes and conditioning with two stages
 C1_TWO_STAGES = (2048, 1024, 1e2, 10, 1.0, 1503035200)
