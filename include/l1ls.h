@@ -212,7 +212,9 @@ void l1ls_solve_opts_default(l1ls_solve_opts* opts);
  * opts.op selects the operator: STORED (CSR/CSC in opts.precision),
  * MATRIX_FREE (requires m times the value size below 4 GiB) or BLOCKED
  * (L1LS_STORE_BLK32, FP32 only); L1LS_E_UNSUPPORTED when the instance lacks
- * what the choice needs.
+ * what the choice needs.  FP64 solves on the stored operator whose CSR, CSC
+ * and iterates fit in one compute unit's LDS run in a single workgroup; the
+ * iterates are those of the multi-kernel passes bit for bit.
  */
 l1ls_status l1ls_solve_fista(const l1ls_instance* inst, const l1ls_solve_opts* opts,
                              double* x_out_dev, l1ls_report* report);
