@@ -168,10 +168,11 @@ def mf_bytes(m, n, es=4):
     read, x_k written, sigma (n), w written (n).
     residual pass fused with Q^T (m side): emb (int32, m), w gathered once (n),
     the m-side (c, s) of both stages, b and r_x,prev read, r_x written, sigma
-    (m), v written (m).  r_y stays on chip.
+    (m), v written at the n active positions only (n).  r_y stays on chip; the
+    per-workgroup rank bases (m / 512 int32) are left out.
     """
     tr = 4 * n + es * n + es * 2 * n + es * 3 * n + es * n + es * n
-    res = 4 * m + es * n + es * 2 * m + es * 2 * m + es * m + es * m + es * m
+    res = 4 * m + es * n + es * 2 * m + es * 2 * m + es * m + es * m + es * n
     return tr + res
 
 

@@ -117,10 +117,13 @@ struct l1ls_instance {
     const int32_t* op_row_of = nullptr;
     const int32_t* op_row_pos = nullptr;
     // Matrix-free operator in stage order (see mf.hip): Sigma links
-    // m-position i and n-position mf_emb[i] (or none, -1); mf_inv is the
-    // inverse on the n side; mf_sig* = sigma at m-positions (0 if none).
+    // m-position i and n-position mf_emb[i] (or none, -1); mf_inv[a] = rank,
+    // among the active m-positions, of the one linked to n-position a;
+    // mf_cbase[g] = active m-positions before workgroup g's first (2 g B);
+    // mf_sig* = sigma at m-positions (0 if none).
     int32_t* mf_emb = nullptr;
     int32_t* mf_inv = nullptr;
+    int32_t* mf_cbase = nullptr;
     double* mf_sig64 = nullptr;
     float* mf_sig32 = nullptr;
     double* mf_sign64 = nullptr;  // sigma at n-positions

@@ -6,21 +6,28 @@
 // pairs positions (2k, 2k+1) and stage 2 pairs (2k+1, 2k+2 mod N), so every
 // Givens stage is a local stencil.  The only non-local step is Sigma, which
 // links n-position a and m-position i when pi_n(a) = pi_m(i):
-//   emb[i] = a (or -1 when pi_m(i) >= n),  inv[a] = i,
-//   sig[i] = sigma_{pi_m(i)} (0 when inactive).
+//   emb[i] = a (or -1 when pi_m(i) >= n),  sig[i] = sigma_{pi_m(i)} (0 when
+//   inactive); inv[a] = rank, among the active m-positions, of the i linked
+//   to a.
 // A x   = Q (Sigma (G^T x)):  pass 1 (n side) w_a = sigma_a (G^T x)_a, written
 //                             in n order; pass 2 (m side) gathers
 //                             z_i = w_{emb_i}, r = Q z, fused with the
 //                             residual/momentum epilogue.
-// A^T r = G (Sigma^T (Q^T r)): pass 1 (m side) v_i = sig_i (Q^T r)_i, written
-//                             in m order; pass 2 (n side) gathers
+// A^T r = G (Sigma^T (Q^T r)): pass 1 (m side) v = sig_i (Q^T r)_i at the
+//                             active m-positions, written compactly at their
+//                             rank (n long); pass 2 (n side) gathers
 //                             t_a = v_{inv_a}, g = G t, fused with the
 //                             gradient step, prox, momentum.
 // The embedding is a random permutation, so its accesses are random: they
 // are made as gathers (one per position, staged in LDS for the stencil that
-// follows), never as scattered stores.  Each thread owns one rotation pair
-// of the last stage it applies and reads the 4 consecutive positions that
-// feed it.
+// follows), never as scattered stores.  Every XCD caches the whole vector it
+// gathers from, so the compact v (n values instead of m) halves that cost on
+// the A^T side.  The stores into the compact v keep position order, so they
+// stay near-coalesced.  Each thread owns one rotation pair of the last stage
+// it applies and reads the 4 consecutive positions that feed it.  The rank
+// of an active m-position is the workgroup's base (cbase: active positions
+// before the workgroup's first) plus a ballot count within the workgroup, so
+// no per-position table is read for it.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -33,7 +40,8 @@ struct MfTabs {
     const T* csn[L1LS_MAX_ROUNDS];  // n side, per stage: (c, s) per pair
     const T* csm[L1LS_MAX_ROUNDS];  // m side
     const int32_t* emb;             // m
-    const int32_t* inv;             // n
+    const int32_t* inv;             // n: rank of the linked m-position among the active ones
+    const int32_t* cbase;           // per workgroup of the m side: active positions before it
     const T* sig;                   // m: sigma at m-positions (0 if inactive)
     const T* sig_n;                 // n: sigma at n-positions
     int64_t n, m;
@@ -69,6 +77,66 @@ __device__ __forceinline__ int64_t ring(int64_t p, int64_t N) {
     if (p >= N) p -= N;
     if (p >= N) p %= N;  // only for sides shorter than a block's reach
     return p;
+}
+
+// A workgroup's gather into LDS: dst[q] = src[idx[p]] for the 2B + 2H
+// positions p = 2 k0 - H + q (mod N), 0 where idx[p] < 0 (an inactive
+// position).  All of a thread's index loads are issued before its gathers,
+// and all gathers before the LDS stores, so the dependent pairs of loads of
+// its two or three positions are in flight together.
+template <typename T, int B, int H>
+__device__ __forceinline__ void gather_block(const T* __restrict__ src, const int32_t* __restrict__ idx, int64_t k0,
+                                             int64_t N, T* dst) {
+    constexpr int Q = 2 * B + 2 * H;
+    constexpr int NQ = (Q + B - 1) / B;
+    int32_t a[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = threadIdx.x + u * B;
+        a[u] = (q < Q) ? idx[ring(2 * k0 - H + q + N, N)] : -1;
+    }
+    T z[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) z[u] = (a[u] >= 0) ? ld_off32(src, a[u]) : T(0);
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = threadIdx.x + u * B;
+        if (q < Q) dst[q] = z[u];
+    }
+}
+
+// Rank of the m-positions 2k and 2k+1 (k = blockIdx.x B + threadIdx.x, the
+// thread's stage-1 pair) among the active ones, or -1 where inactive.  Every
+// thread of the workgroup takes part, between two phases the caller puts a
+// __syncthreads: rank_count publishes each wave's count of active positions
+// in ws, rank_of adds the lower waves' counts to the workgroup's base.
+struct PairRank {
+    int32_t pre;  // active positions of lower lanes of the wave
+    bool a0, a1;
+};
+constexpr int kMfWaves = L1LS_BLOCK / 64;
+__device__ __forceinline__ PairRank rank_count(const int32_t* __restrict__ emb, int64_t kc, bool mine,
+                                               int32_t* ws) {
+    const int2 e = *reinterpret_cast<const int2*>(emb + 2 * kc);  // 2kc even: 8-byte aligned
+    PairRank r;
+    r.a0 = mine && e.x >= 0;
+    r.a1 = mine && e.y >= 0;
+    const uint64_t b0 = __ballot(r.a0), b1 = __ballot(r.a1);
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    r.pre = __popcll(b0 & below) + __popcll(b1 & below);
+    if (lane == 0) ws[threadIdx.x >> 6] = __popcll(b0) + __popcll(b1);
+    return r;
+}
+__device__ __forceinline__ void rank_of(const PairRank& r, const int32_t* __restrict__ cbase, const int32_t* ws,
+                                        int32_t& ci0, int32_t& ci1) {
+    int32_t base = cbase[blockIdx.x] + r.pre;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < kMfWaves; ++w)
+        if (w < wave) base += ws[w];
+    ci0 = r.a0 ? base : -1;
+    ci1 = r.a1 ? base + (r.a0 ? 1 : 0) : -1;
 }
 
 // w = Sigma_n G^T x in n-stage order (sigma at n-positions, 0 where the
@@ -155,15 +223,14 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
         }
     }
     T s0 = T(0), s1 = T(0);
+    __shared__ int32_t ws[kMfWaves];
+    PairRank pr{0, false, false};
     if (MODE != kMfProduct) {
         s0 = (T)tb.sig[2 * kc];
         s1 = (T)tb.sig[2 * kc + 1];
+        pr = rank_count(tb.emb, kc, mine, ws);
     }
-    for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
-        const int64_t p = ring(2 * k0 - H + q + m, m);
-        const int32_t a = tb.emb[p];
-        zl[q] = (a >= 0) ? ld_off32(w, a) : T(0);
-    }
+    gather_block<T, B, H>(w, tb.emb, k0, m, zl);
     __syncthreads();
     double v[3] = {0.0, 0.0, 0.0};
     if (R == 2) {
@@ -236,8 +303,10 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
             }
             T o0, o1;
             rot(c1, z0, z1, true, o0, o1);
-            vm[2 * k] = s0 * o0;
-            vm[2 * k + 1] = s1 * o1;
+            int32_t ci0, ci1;
+            rank_of(pr, tb.cbase, ws, ci0, ci1);
+            if (ci0 >= 0) vm[ci0] = s0 * o0;
+            if (ci1 >= 0) vm[ci1] = s1 * o1;
         }
     }
     if (!stats) return;
@@ -270,6 +339,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     if (done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
     const int64_t k0 = (int64_t)blockIdx.x * B;
+    // one position at a time: measured about 5% faster for this kernel than
+    // gather_block's overlapped loads
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
         const int64_t p = ring(2 * k0 - H + q + n, n);
         tl[q] = ld_off32(vm, tb.inv[p]);
@@ -349,13 +420,21 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     }
 }
 
-// v = Sigma_m Q^T y in m order (the m side of A^T y on its own).  Thread k
-// owns stage-1 pair k; R = 2: Q^T = S~_1^T S~_2^T reads y at 2k-1 .. 2k+2.
+// v = Sigma_m Q^T y at the active m-positions, compact (the m side of A^T y
+// on its own).  Thread k owns stage-1 pair k; R = 2: Q^T = S~_1^T S~_2^T
+// reads y at 2k-1 .. 2k+2.  Threads past the end take part in the rank only.
 template <typename T, int R>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ vm, MfTabs<T> tb) {
+    __shared__ int32_t ws[kMfWaves];
     const int64_t m = tb.m, mp = m / 2;
-    const int64_t k = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
-    if (k >= mp) return;
+    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
+    const bool mine = k0 < mp;
+    const int64_t k = mine ? k0 : mp - 1;
+    const PairRank pr = rank_count(tb.emb, k, mine, ws);
+    __syncthreads();
+    int32_t ci0, ci1;
+    rank_of(pr, tb.cbase, ws, ci0, ci1);
+    if (!mine) return;
     T z0 = y[2 * k], z1 = y[2 * k + 1];
     if (R == 2) {
         const T ym = y[wrap(2 * k - 1, m)], yp = y[wrap(2 * k + 2, m)];
@@ -368,11 +447,11 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T
     }
     T o0, o1;
     rot(cs_of(tb.csm[0], k), z0, z1, true, o0, o1);
-    vm[2 * k] = tb.sig[2 * k] * o0;
-    vm[2 * k + 1] = tb.sig[2 * k + 1] * o1;
+    if (ci0 >= 0) vm[ci0] = tb.sig[2 * k] * o0;
+    if (ci1 >= 0) vm[ci1] = tb.sig[2 * k + 1] * o1;
 }
 
-// The n side of A^T from v (m order): g = G t with t_a = v[inv[a]], with the
+// The n side of A^T from the compact v: g = G t with t_a = v[inv[a]], with the
 // Hessian epilogue of the PCG when p is given:
 //   h = g + d p (d optional), h = 0 where mask is 0 (mask optional),
 //   out = h, part[block] = sum p h (part optional);
@@ -417,10 +496,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
             if (mask) on[e] = mask[ps[e]] != 0;
         }
     }
-    for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
-        const int64_t pos = ring(2 * k0 - H + q + n, n);
-        tl[q] = ld_off32(vm, tb.inv[pos]);
-    }
+    gather_block<T, B, H>(vm, tb.inv, k0, n, tl);
     __syncthreads();
     double acc[1] = {0.0};
     if (mine) {
@@ -464,13 +540,26 @@ __global__ void k_mf_emb(const int32_t* __restrict__ perm_m, const int32_t* __re
     sig32[i] = (float)sg;
 }
 
+__global__ void k_mf_active(const int32_t* __restrict__ perm_m, int64_t n, int64_t m, int32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) flag[i] = perm_m[i] < n ? 1 : 0;
+}
+
+// cbase[g]: active m-positions before the first of workgroup g (positions
+// 2 g B .. 2 g B + 2B - 1 of the m side); off = exclusive scan of the flags.
+__global__ void k_mf_cbase(const int32_t* __restrict__ off, int64_t m, int64_t groups, int32_t* __restrict__ cbase) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < groups) cbase[g] = off[std::min<int64_t>(2 * g * L1LS_BLOCK, m)];
+}
+
+// inv[a]: rank, among the active m-positions, of the one linked to n-position a
 __global__ void k_mf_inv(const int32_t* __restrict__ perm_n, const int32_t* __restrict__ pinv_m,
-                         const double* __restrict__ sigma, int64_t n, int32_t* __restrict__ inv,
-                         double* __restrict__ sn64, float* __restrict__ sn32) {
+                         const int32_t* __restrict__ off, const double* __restrict__ sigma, int64_t n,
+                         int32_t* __restrict__ inv, double* __restrict__ sn64, float* __restrict__ sn32) {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
     const int32_t j = perm_n[a];
-    inv[a] = pinv_m[j];
+    inv[a] = off[pinv_m[j]];
     sn64[a] = sigma[j];
     sn32[a] = (float)sigma[j];
 }
@@ -493,6 +582,7 @@ MfTabs<double> tabs_of<double>(const l1ls_instance* I) {
     }
     t.emb = I->mf_emb;
     t.inv = I->mf_inv;
+    t.cbase = I->mf_cbase;
     t.sig = I->mf_sig64;
     t.sig_n = I->mf_sign64;
     t.n = I->n;
@@ -508,6 +598,7 @@ MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
     }
     t.emb = I->mf_emb;
     t.inv = I->mf_inv;
+    t.cbase = I->mf_cbase;
     t.sig = I->mf_sig32;
     t.sig_n = I->mf_sign32;
     t.n = I->n;
@@ -517,11 +608,15 @@ MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
 
 }  // namespace
 
+int mf_grid(int64_t pairs);
+
 // Tables of the stage-order matrix-free operator (called by the generator).
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
     const int64_t n = I->n, m = I->m;
     L1LS_TRY(I->arena.alloc(&I->mf_emb, m));
     L1LS_TRY(I->arena.alloc(&I->mf_inv, n));
+    const int64_t groups = mf_grid(m / 2);
+    L1LS_TRY(I->arena.alloc(&I->mf_cbase, groups));
     L1LS_TRY(I->arena.alloc(&I->mf_sig64, m));
     L1LS_TRY(I->arena.alloc(&I->mf_sig32, m));
     L1LS_TRY(I->arena.alloc(&I->mf_sign64, n));
@@ -530,8 +625,27 @@ l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
     L1LS_TRY(I->arena.alloc(&I->mf_b32, m));
     hipLaunchKernelGGL(k_mf_emb, g1d(m), dim3(L1LS_BLOCK), 0, s, I->side[1].perm, I->side[0].pinv, I->sigma, n, m,
                        I->mf_emb, I->mf_sig64, I->mf_sig32);
-    hipLaunchKernelGGL(k_mf_inv, g1d(n), dim3(L1LS_BLOCK), 0, s, I->side[0].perm, I->side[1].pinv, I->sigma, n,
-                       I->mf_inv, I->mf_sign64, I->mf_sign32);
+    {
+        // rank of the active m-positions in position order
+        DevArena tmp;
+        tmp.al = I->arena.al;
+        int32_t *flag = nullptr, *off = nullptr;
+        auto fail = [&](l1ls_status st) {
+            (void)hipStreamSynchronize(s);
+            tmp.release();
+            return st;
+        };
+        l1ls_status st;
+        if ((st = tmp.alloc(&flag, m)) != L1LS_OK) return fail(st);
+        if ((st = tmp.alloc(&off, m + 1)) != L1LS_OK) return fail(st);
+        hipLaunchKernelGGL(k_mf_active, g1d(m), dim3(L1LS_BLOCK), 0, s, I->side[1].perm, n, m, flag);
+        if ((st = exclusive_scan_i32(flag, off, m, s, tmp)) != L1LS_OK) return fail(st);
+        hipLaunchKernelGGL(k_mf_cbase, g1d(groups), dim3(L1LS_BLOCK), 0, s, off, m, groups, I->mf_cbase);
+        hipLaunchKernelGGL(k_mf_inv, g1d(n), dim3(L1LS_BLOCK), 0, s, I->side[0].perm, I->side[1].pinv, off,
+                           I->sigma, n, I->mf_inv, I->mf_sign64, I->mf_sign32);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(L1LS_E_HIP);
+        tmp.release();
+    }
     for (int sd = 0; sd < 2; ++sd)
         for (int t = 0; t < I->rounds; ++t) {
             const int64_t N = I->side[sd].N;
