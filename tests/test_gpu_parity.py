@@ -190,19 +190,41 @@ def test_fista_trajectory_fp64_matrix_free(cfg, iters):
     assert rep["iterations"] == iters
 
 
-MF_MULTIBLOCK = (4096, 2050, 1e3, 20, 1.0, 23, 2)   # several 256-pair workgroups per side, last one ragged
+MF_MULTIBLOCK = [
+    (4096, 2050, 1e3, 20, 1.0, 23, 2),  # several 256-pair workgroups per side, the n side's last one ragged
+    # m >> n: ten m-side workgroups (the last ragged) with 300 active positions
+    # among 5000, so the compact v's ranks carry across many workgroups
+    (5000, 300, 1e2, 6, 1.0, 29, 2),
+]
 
 
+@pytest.mark.parametrize("cfg", MF_MULTIBLOCK)
 @pytest.mark.parametrize("iters", [1, 2, 25])
-def test_fista_trajectory_fp64_matrix_free_multiblock(iters):
+def test_fista_trajectory_fp64_matrix_free_multiblock(cfg, iters):
     # The fused matrix-free passes recompute a neighbour workgroup's stage pair
     # at each workgroup edge; both sides here span several workgroups.
-    g, o, A = pair(MF_MULTIBLOCK)
+    g, o, A = pair(cfg)
     x, rep, _ = L.l1ls_solve_fista(g, max_iter=iters, rel_gap_tol=0.0, check_every=1, precision=L.F64,
                                    op=L.OP_MATRIX_FREE)
     ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, iters)
     scale = max(1.0, np.abs(ref).max())
     assert np.abs(x.cpu().numpy() - ref).max() <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("cfg", MF_MULTIBLOCK)
+def test_matrix_free_products_multiblock(cfg):
+    # A x and A^T y (the latter through the compact v) against the oracle's
+    # rotations, FP64 and FP32
+    g, o, A = pair(cfg)
+    x = SI.normal_vector(o.n, 111)
+    y = SI.normal_vector(o.m, 112)
+    ax, aty = o.matvec(x), o.rmatvec(y)
+    for prec, dt, tol in ((L.F64, torch.float64, 1e-13), (L.F32, torch.float32, 2e-6)):
+        for trans, v, ref, size in ((0, x, ax, o.m), (1, y, aty, o.n)):
+            out = torch.empty(size, dtype=dt, device="cuda")
+            L.l1ls_apply(g, trans, L.OP_MATRIX_FREE, prec, _dev(v, dt), out)
+            torch.cuda.synchronize()
+            assert np.abs(out.double().cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max()), (prec, trans)
 
 
 @pytest.mark.parametrize("cfg", CASES[:2])

@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 C1 = (2048, 1024, 1e2, 10, 1.0, 1503035200, 1)
 TWO_STAGE = (4096, 2048, 1e3, 20, 1.0, 1503035202, 2)
 RAGGED = (1010, 502, 1e2, 7, 0.5, 17, 2)
+TALL = (5000, 300, 1e2, 6, 1.0, 29, 2)  # m >> n: ten m-side workgroups, few active positions
 
 _cache = {}
 
@@ -124,7 +125,7 @@ def test_cg_newton_fp32_hessian_products_reach_the_same_minimiser(cfg, op):
     assert np.abs(x32.cpu().numpy() - x64.cpu().numpy()).max() <= 1e-5 * scale
 
 
-@pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED])
+@pytest.mark.parametrize("cfg", [C1, TWO_STAGE, RAGGED, TALL])
 def test_cg_newton_matrix_free_follows_the_stored_path(cfg):
     # The same Newton iteration over two evaluations of the same A (stored
     # FP64 values vs the rotations applied on the fly): products agree to
