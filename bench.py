@@ -63,7 +63,8 @@ def write_profile_summary(args):
         raise SystemExit(f"no *{kind} under {d}")
 
     names = {"residual": "k_residual<float>", "transpose_prox": "k_transpose_prox<float>", "gap": "k_gap",
-             "blk_residual": "k_blk_residual<false>", "blk_transpose_prox": "k_blk_transpose_prox<false>"}
+             "blk_residual": "k_blk_residual<false>", "blk_transpose_prox": "k_blk_transpose_prox<false>",
+             "mf_res_qt": "k_mf_res_qt<float, 2, 0, float>", "mf_prox_gt": "k_mf_prox_gt<float, 2>"}
     stats = kernel_rows(args.kt, "kernel_stats.csv")
     dur = {}
     for key, pat in names.items():
@@ -82,8 +83,8 @@ def write_profile_summary(args):
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
     kt_cmd = args.kt_command or "python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline"
     pmc_cmd = args.pmc_command or "python3 bench.py --steps 40 --warmup 4 --no-cpu-baseline"
-    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator), "
-             "FP32 bulk, " + (args.stats_title or "n=2^20, m=2^21, 2 stages"),
+    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator; "
+             "mf_*: the matrix-free operator), FP32 bulk, " + (args.stats_title or "n=2^20, m=2^21, 2 stages"),
              f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- {kt_cmd}",
              f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
              f"{pmc_cmd}",
