@@ -213,8 +213,9 @@ def test_fista_trajectory_fp64_matrix_free_multiblock(cfg, iters):
 
 @pytest.mark.parametrize("cfg", MF_MULTIBLOCK)
 def test_matrix_free_products_multiblock(cfg):
-    # A x and A^T y (the latter through the compact v) against the oracle's
-    # rotations, FP64 and FP32
+    # A x and A^T y of l1ls_apply (the stage-by-stage operator) against the
+    # oracle's rotations, FP64 and FP32; the fused passes and their compact v
+    # are covered by the FISTA trajectories above and the CG-Newton tests
     g, o, A = pair(cfg)
     x = SI.normal_vector(o.n, 111)
     y = SI.normal_vector(o.m, 112)
