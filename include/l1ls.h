@@ -75,6 +75,17 @@ typedef enum { L1LS_LAYOUT_NATURAL = 0, L1LS_LAYOUT_STAGE = 1 } l1ls_layout;
  * values (sums of terms) by FP32 rounding.  Requires rounds = 2,
  * layout = STAGE and n >= 4 (else L1LS_E_UNSUPPORTED). */
 #define L1LS_STORE_BLK32 4u
+/* Windowed gathers for the fused matrix-free passes (FISTA and CG-Newton with
+ * L1LS_OP_MATRIX_FREE).  Each random gather of the Sigma embedding becomes a
+ * bucketing pass, which copies the gathered vector so that the elements read
+ * by each window of consecutive target positions lie together, followed by
+ * a gather within the window.  That costs about 16 bytes per element more,
+ * and saves the whole cache line that a random load costs once the vector
+ * outgrows the caches.  Built when this bit is set, and always for
+ * n >= 2^22; results are bitwise those of the plain gathers.  Extra device
+ * memory: 4 (m + 5n) bytes for the tables, and the solvers' matrix-free
+ * buffers hold the bucketed copies (n entries each). */
+#define L1LS_STORE_MF_WINDOWS 8u
 
 typedef struct {
     int32_t rounds;      /* Givens stages per side, 1 or 2 (nnz/col <= 4^rounds) */

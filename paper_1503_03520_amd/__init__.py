@@ -15,7 +15,7 @@ L1LS_OK = 0
 L1LS_NOT_CONVERGED = 1
 F32, F64 = 0, 1
 OP_STORED, OP_MATRIX_FREE, OP_BLOCKED = 0, 1, 2
-STORE_F32, STORE_F64, STORE_BLK32 = 1, 2, 4
+STORE_F32, STORE_F64, STORE_BLK32, STORE_MF_WINDOWS = 1, 2, 4, 8
 REQ_FP64_FINISH = 1
 SIGMA_ALTERNATING, SIGMA_UNIFORM = 0, 1
 XSTAR_TABLE1, XSTAR_OSGEN, XSTAR_OSGEN3 = 0, 1, 2

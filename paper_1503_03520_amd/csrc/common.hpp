@@ -124,6 +124,19 @@ struct l1ls_instance {
     int32_t* mf_emb = nullptr;
     int32_t* mf_inv = nullptr;
     int32_t* mf_cbase = nullptr;
+    // Windowed gathers of the matrix-free passes (mfw_ws = 0: off); [0] is
+    // the m side's gather of w, [1] the n side's gather of the compact v.
+    // Target positions are grouped in windows of 2^mfw_ws, sources in chunks
+    // of 2^mfw_cs[k]; mfw_ib[k][t] = slot of the bucketed copy u that target
+    // position t reads (-1 where the position is inactive); mfw_lx[k][src] =
+    // place of source element src in its chunk's staging order (offset by
+    // the chunk's start), and mfw_wslot[k][j] = slot of u that staging place j
+    // is written to.
+    int mfw_ws = 0;
+    int mfw_cs[2] = {0, 0};
+    int32_t* mfw_ib[2] = {nullptr, nullptr};
+    int32_t* mfw_lx[2] = {nullptr, nullptr};
+    int32_t* mfw_wslot[2] = {nullptr, nullptr};
     double* mf_sig64 = nullptr;
     float* mf_sig32 = nullptr;
     double* mf_sign64 = nullptr;  // sigma at n-positions

@@ -17,9 +17,11 @@ template <typename T>
 void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, const T* rx_prev, T* rx, T* vt,
                         T beta, int init, double* part, const GapState* gs, int stats, hipStream_t s);
 template <typename T>
-void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
+void mf_transpose_launch(const l1ls_instance* I, T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
                          T thr, double* part, const GapState* gs, int stats, hipStream_t s);
 int mf_grid(int64_t pairs);
+int64_t mf_wbuf_len(const l1ls_instance* I);
+int64_t mf_vbuf_len(const l1ls_instance* I);
 void blk_residual_launch(const l1ls_instance* I, const float* xe, const float* b, float* rx, float* rye, float beta,
                          int init, double* part, const GapState* gs, int stats, hipStream_t s);
 void blk_transpose_launch(const l1ls_instance* I, const float* rye, const float* xc, float* xpe, float beta, float L,
@@ -139,8 +141,8 @@ struct l1ls_fista {
     void* rx = nullptr;
     void* rx2 = nullptr;       // matrix-free: r_x,k lives in (k & 1) ? rx2 : rx
     void* ry = nullptr;
-    void* wbuf = nullptr;      // matrix-free: Sigma G^T x_k in n-stage order (n), made by the transpose pass
-    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y in m-stage order (m), made by the residual pass
+    void* wbuf = nullptr;      // matrix-free: Sigma G^T x_k in n-stage order, made by the transpose pass
+    void* tbuf = nullptr;      // matrix-free: Sigma^T Q^T r_y (compact), made by the residual pass
     bool mf = false;           // matrix-free operator (stage order)
     // Blocked operator: x slots and r_y hold one leading element (the wrap
     // copy) before the pointers above and one after their last element, the
@@ -272,7 +274,7 @@ l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double be
     }
     if (F->mf)
         return timed(F, 1, [&] {
-            mf_transpose_launch<T>(I, (const T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
+            mf_transpose_launch<T>(I, (T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
                                    (T)(F->tau / F->L), F->k2part, F->gs, stats, F->stream);
         });
     return timed(F, 1, [&] {
@@ -400,12 +402,13 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
         ry += es;
     }
     if (F->mf) {
-        // Sigma G^T x in n-stage order; Sigma^T Q^T r_y in m-stage order (its
-        // inactive positions are never read)
+        // Sigma G^T x in n-stage order; Sigma^T Q^T r_y at the active
+        // m-positions; with windowed gathers each buffer also holds its
+        // bucketed copy
         unsigned char* wb = nullptr;
         unsigned char* tb = nullptr;
-        if ((st = F->arena.alloc(&wb, I->n * es)) != L1LS_OK) return fail(st);
-        if ((st = F->arena.alloc(&tb, I->m * es)) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&wb, mf_wbuf_len(I) * es)) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&tb, mf_vbuf_len(I) * es)) != L1LS_OK) return fail(st);
         unsigned char *x2 = nullptr, *rx2 = nullptr;
         if ((st = F->arena.alloc(&x2, I->n * es)) != L1LS_OK) return fail(st);
         if ((st = F->arena.alloc(&rx2, I->m * es)) != L1LS_OK) return fail(st);

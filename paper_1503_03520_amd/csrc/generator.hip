@@ -340,10 +340,12 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
     if (!(s >= 0 && s <= n) || !(kappa >= 1.0) || !is_finite(kappa) || !(tau > 0.0) || !is_finite(tau))
         return L1LS_E_ARG;
     if (rounds < 1 || rounds > L1LS_MAX_ROUNDS) return L1LS_E_ARG;
-    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32)) != 0) return L1LS_E_ARG;
+    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32 | L1LS_STORE_MF_WINDOWS)) != 0)
+        return L1LS_E_ARG;
     if ((storage & L1LS_STORE_BLK32) && (rounds != 2 || layout != L1LS_LAYOUT_STAGE || n < 4))
         return L1LS_E_UNSUPPORTED;
-    if ((int64_t)16 * n >= ((int64_t)1 << 31) && storage) return L1LS_E_UNSUPPORTED;
+    if ((int64_t)16 * n >= ((int64_t)1 << 31) && (storage & (L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32)))
+        return L1LS_E_UNSUPPORTED;
     // the stored passes gather FP64 vectors of m entries with 32-bit byte
     // offsets (below 4 GiB)
     if ((storage & (L1LS_STORE_F32 | L1LS_STORE_F64)) && m >= ((int64_t)1 << 29)) return L1LS_E_UNSUPPORTED;

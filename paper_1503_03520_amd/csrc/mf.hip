@@ -42,6 +42,8 @@ struct MfTabs {
     const int32_t* emb;             // m
     const int32_t* inv;             // n: rank of the linked m-position among the active ones
     const int32_t* cbase;           // per workgroup of the m side: active positions before it
+    const int32_t* gm;              // m side's gather index into its source: emb, or the window slots
+    const int32_t* gn;              // n side's gather index: inv, or the window slots
     const T* sig;                   // m: sigma at m-positions (0 if inactive)
     const T* sig_n;                 // n: sigma at n-positions
     int64_t n, m;
@@ -228,9 +230,9 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     if (MODE != kMfProduct) {
         s0 = (T)tb.sig[2 * kc];
         s1 = (T)tb.sig[2 * kc + 1];
-        pr = rank_count(tb.emb, kc, mine, ws);
+        pr = rank_count(tb.gm, kc, mine, ws);
     }
-    gather_block<T, B, H>(w, tb.emb, k0, m, zl);
+    gather_block<T, B, H>(w, tb.gm, k0, m, zl);
     __syncthreads();
     double v[3] = {0.0, 0.0, 0.0};
     if (R == 2) {
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     // gather_block's overlapped loads
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
         const int64_t p = ring(2 * k0 - H + q + n, n);
-        tl[q] = ld_off32(vm, tb.inv[p]);
+        tl[q] = ld_off32(vm, tb.gn[p]);
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T
     const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
     const bool mine = k0 < mp;
     const int64_t k = mine ? k0 : mp - 1;
-    const PairRank pr = rank_count(tb.emb, k, mine, ws);
+    const PairRank pr = rank_count(tb.gm, k, mine, ws);
     __syncthreads();
     int32_t ci0, ci1;
     rank_of(pr, tb.cbase, ws, ci0, ci1);
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
             if (mask) on[e] = mask[ps[e]] != 0;
         }
     }
-    gather_block<T, B, H>(vm, tb.inv, k0, n, tl);
+    gather_block<T, B, H>(vm, tb.gn, k0, n, tl);
     __syncthreads();
     double acc[1] = {0.0};
     if (mine) {
@@ -583,6 +585,8 @@ MfTabs<double> tabs_of<double>(const l1ls_instance* I) {
     t.emb = I->mf_emb;
     t.inv = I->mf_inv;
     t.cbase = I->mf_cbase;
+    t.gm = I->mfw_ws ? I->mfw_ib[0] : I->mf_emb;
+    t.gn = I->mfw_ws ? I->mfw_ib[1] : I->mf_inv;
     t.sig = I->mf_sig64;
     t.sig_n = I->mf_sign64;
     t.n = I->n;
@@ -599,6 +603,8 @@ MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
     t.emb = I->mf_emb;
     t.inv = I->mf_inv;
     t.cbase = I->mf_cbase;
+    t.gm = I->mfw_ws ? I->mfw_ib[0] : I->mf_emb;
+    t.gn = I->mfw_ws ? I->mfw_ib[1] : I->mf_inv;
     t.sig = I->mf_sig32;
     t.sig_n = I->mf_sign32;
     t.n = I->n;
@@ -606,9 +612,146 @@ MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
     return t;
 }
 
+// ---- windowed gathers -------------------------------------------------------
+// A gather t -> src[idx[t]] over a vector that no cache holds costs a whole
+// line per element.  The windowed form groups the targets in windows of
+// 2^ws consecutive positions and the sources in chunks of 2^cs: the slots of
+// a bucketed copy u are ordered by (target window, source chunk), so that
+//   k_win_scatter  copies one source chunk per workgroup into u: it stages
+//                  the chunk in LDS ordered by target window, then writes
+//                  each (window, chunk) run of u (about 16 elements) with
+//                  consecutive stores, and
+//   the consumer   gathers u[ib[t]], which for the targets of a workgroup
+//                  stays inside one window's segment of u, small enough to
+//                  stay in L2.
+// Slots within a (window, chunk) run are handed out by atomics, so the order
+// of u varies between builds; every target still reads its own element, so
+// the results are bitwise those of the plain gather.
+constexpr int kWinMaxCs = 14;        // chunk of at most 2^14 sources: 128 KB of FP64 staging
+constexpr int kWinThreads = 1024;
+
+__global__ void k_win_count(const int32_t* __restrict__ src, int64_t NT, int ws, int cs, int64_t nc,
+                            int32_t* __restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NT) return;
+    const int32_t a = src[t];
+    if (a >= 0) atomicAdd(&cnt[(t >> ws) * nc + (a >> cs)], 1);
+}
+
+// cnt in (window, chunk) order -> cnt_t in (chunk, window) order
+__global__ void k_win_transpose(const int32_t* __restrict__ cnt, int64_t nT, int64_t nc, int32_t* __restrict__ cnt_t) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nT * nc) return;
+    const int64_t w = q / nc, c = q - w * nc;
+    cnt_t[c * nT + w] = cnt[q];
+}
+
+// base: exclusive scan of the counts in (window, chunk) order (the runs of
+// u); cur: a copy of it, advanced here; lbase: exclusive scan in (chunk,
+// window) order (the staging order, chunk by chunk).
+__global__ void k_win_assign(const int32_t* __restrict__ src, int64_t NT, int ws, int cs, int64_t nT, int64_t nc,
+                             const int32_t* __restrict__ base, int32_t* __restrict__ cur,
+                             const int32_t* __restrict__ lbase, int32_t* __restrict__ ib, int32_t* __restrict__ lx,
+                             int32_t* __restrict__ wslot) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NT) return;
+    const int32_t a = src[t];
+    if (a < 0) {
+        ib[t] = -1;
+        return;
+    }
+    const int64_t w = t >> ws, c = a >> cs;
+    const int32_t slot = atomicAdd(&cur[w * nc + c], 1);
+    const int32_t l = lbase[c * nT + w] + (slot - base[w * nc + c]);
+    ib[t] = slot;
+    lx[a] = l;
+    wslot[l] = slot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWinThreads) void k_win_scatter(const T* __restrict__ src, const int32_t* __restrict__ lx,
+                                                              const int32_t* __restrict__ wslot, T* __restrict__ u,
+                                                              int64_t N, int cs, const int32_t* __restrict__ done) {
+    __shared__ T st[1 << kWinMaxCs];
+    if (done && *done) return;  // the solver's converged flag (launch-uniform)
+    const int64_t c0 = (int64_t)blockIdx.x << cs;
+    const int cnt = (int)std::min<int64_t>((int64_t)1 << cs, N - c0);
+    for (int j = threadIdx.x; j < cnt; j += kWinThreads) st[lx[c0 + j] - c0] = src[c0 + j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kWinThreads) u[wslot[c0 + j]] = st[j];
+}
+
+int ceil_log2(int64_t v) {
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+// Window tables of both gathers (the sources are n long on both sides).
+l1ls_status build_mf_windows(l1ls_instance* I, hipStream_t s) {
+    const int64_t n = I->n, m = I->m;
+    const int ws = std::min(17, std::max(8, ceil_log2(n) - 6));
+    DevArena tmp;
+    tmp.al = I->arena.al;
+    auto fail = [&](l1ls_status st) {
+        (void)hipStreamSynchronize(s);
+        tmp.release();
+        return st;
+    };
+    const int32_t* srcs[2] = {I->mf_emb, I->mf_inv};
+    const int64_t NT[2] = {m, n};
+    for (int k = 0; k < 2; ++k) {
+        const int64_t nT = (NT[k] + ((int64_t)1 << ws) - 1) >> ws;
+        // about 16 sources per (window, chunk) run: a 128-byte line of FP64
+        const int cs = std::min(kWinMaxCs, std::max(8, ceil_log2(nT) + 4));
+        const int64_t nc = (n + ((int64_t)1 << cs) - 1) >> cs;
+        if (nT * nc >= ((int64_t)1 << 31) - 1) return fail(L1LS_E_UNSUPPORTED);
+        l1ls_status st;
+        if ((st = I->arena.alloc(&I->mfw_ib[k], NT[k])) != L1LS_OK) return fail(st);
+        if ((st = I->arena.alloc(&I->mfw_lx[k], n)) != L1LS_OK) return fail(st);
+        if ((st = I->arena.alloc(&I->mfw_wslot[k], n)) != L1LS_OK) return fail(st);
+        int32_t *cnt = nullptr, *cnt_t = nullptr, *base = nullptr, *cur = nullptr, *lbase = nullptr;
+        const int64_t nq = nT * nc;
+        if ((st = tmp.alloc(&cnt, nq)) != L1LS_OK) return fail(st);
+        if ((st = tmp.alloc(&cnt_t, nq)) != L1LS_OK) return fail(st);
+        if ((st = tmp.alloc(&base, nq + 1)) != L1LS_OK) return fail(st);
+        if ((st = tmp.alloc(&cur, nq + 1)) != L1LS_OK) return fail(st);
+        if ((st = tmp.alloc(&lbase, nq + 1)) != L1LS_OK) return fail(st);
+        if (hipMemsetAsync(cnt, 0, nq * sizeof(int32_t), s) != hipSuccess) return fail(L1LS_E_HIP);
+        hipLaunchKernelGGL(k_win_count, g1d(NT[k]), dim3(L1LS_BLOCK), 0, s, srcs[k], NT[k], ws, cs, nc, cnt);
+        hipLaunchKernelGGL(k_win_transpose, g1d(nq), dim3(L1LS_BLOCK), 0, s, cnt, nT, nc, cnt_t);
+        if ((st = exclusive_scan_i32(cnt, base, nq, s, tmp)) != L1LS_OK) return fail(st);
+        if ((st = exclusive_scan_i32(cnt_t, lbase, nq, s, tmp)) != L1LS_OK) return fail(st);
+        if (hipMemcpyAsync(cur, base, (nq + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return fail(L1LS_E_HIP);
+        hipLaunchKernelGGL(k_win_assign, g1d(NT[k]), dim3(L1LS_BLOCK), 0, s, srcs[k], NT[k], ws, cs, nT, nc, base,
+                           cur, lbase, I->mfw_ib[k], I->mfw_lx[k], I->mfw_wslot[k]);
+        I->mfw_cs[k] = cs;
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return fail(L1LS_E_HIP);
+    tmp.release();
+    I->mfw_ws = ws;
+    return L1LS_OK;
+}
+
+// u = the bucketed copy of the n-long source of gather k (0: w, 1: compact v)
+template <typename T>
+void win_scatter(const l1ls_instance* I, int k, const T* src, T* u, const int32_t* done, hipStream_t s) {
+    const int cs = I->mfw_cs[k];
+    const int64_t N = I->n;
+    hipLaunchKernelGGL((k_win_scatter<T>), dim3((unsigned)((N + ((int64_t)1 << cs) - 1) >> cs)), dim3(kWinThreads),
+                       0, s, src, I->mfw_lx[k], I->mfw_wslot[k], u, N, cs, done);
+}
+
 }  // namespace
 
 int mf_grid(int64_t pairs);
+
+// Lengths of the buffers a caller passes as w (n side's output) and v (the
+// m side's output): with windowed gathers each also holds the bucketed copy
+// at offset n.
+int64_t mf_wbuf_len(const l1ls_instance* I) { return I->mfw_ws ? 2 * I->n : I->n; }
+int64_t mf_vbuf_len(const l1ls_instance* I) { return I->mfw_ws ? std::max(I->m, 2 * I->n) : I->m; }
 
 // Tables of the stage-order matrix-free operator (called by the generator).
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
@@ -657,6 +800,9 @@ l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s) {
     hipLaunchKernelGGL((k_gather_perm<float, double>), g1d(m), dim3(L1LS_BLOCK), 0, s, I->b, I->mf_b32,
                        I->side[1].perm, m);
     HIP_TRY(hipGetLastError());
+    // windowed gathers once the gathered vectors (n entries) outgrow the
+    // caches: measured slower at n = 2^20, faster from n = 2^22 on
+    if ((I->storage & L1LS_STORE_MF_WINDOWS) || n >= ((int64_t)1 << 22)) L1LS_TRY(build_mf_windows(I, s));
     return L1LS_OK;
 }
 
@@ -673,30 +819,41 @@ void mf_residual_launch(const l1ls_instance* I, const T* x, T* w, const T* b, co
                         T beta, int init, double* part, const GapState* gs, int stats, hipStream_t s) {
     const MfTabs<T> tb = tabs_of<T>(I);
     const int32_t* done = gs ? &gs->done : nullptr;
-    if (I->rounds == 2) {
-        if (init)
+    if (init) {
+        if (I->rounds == 2)
             hipLaunchKernelGGL((k_mf_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, done);
-        hipLaunchKernelGGL((k_mf_res_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
-                           vt, beta, init, tb, part, done, stats);
-    } else {
-        if (init)
+        else
             hipLaunchKernelGGL((k_mf_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, w, tb, done);
-        hipLaunchKernelGGL((k_mf_res_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, w, b, rx_prev, rx,
-                           vt, beta, init, tb, part, done, stats);
     }
+    const T* wg = w;  // what the m side gathers from
+    if (I->mfw_ws) {
+        win_scatter<T>(I, 0, w, w + I->n, done, s);
+        wg = w + I->n;
+    }
+    if (I->rounds == 2)
+        hipLaunchKernelGGL((k_mf_res_qt<T, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wg, b, rx_prev, rx,
+                           vt, beta, init, tb, part, done, stats);
+    else
+        hipLaunchKernelGGL((k_mf_res_qt<T, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wg, b, rx_prev, rx,
+                           vt, beta, init, tb, part, done, stats);
 }
 
 // Transpose pass (with prox) from vt; also forms w = Sigma_n G^T x_k for the
 // residual pass that follows.
 template <typename T>
-void mf_transpose_launch(const l1ls_instance* I, const T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
+void mf_transpose_launch(const l1ls_instance* I, T* vt, T* w, const T* xc, const T* xp, T* xo, T beta, T L,
                          T thr, double* part, const GapState* gs, int stats, hipStream_t s) {
     const MfTabs<T> tb = tabs_of<T>(I);
+    const T* vg = vt;  // what the n side gathers from
+    if (I->mfw_ws) {
+        win_scatter<T>(I, 1, vt, vt + I->n, gs ? &gs->done : nullptr, s);
+        vg = vt + I->n;
+    }
     if (I->rounds == 2)
-        hipLaunchKernelGGL((k_mf_prox_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, xo,
+        hipLaunchKernelGGL((k_mf_prox_gt<T, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg, xc, xp, xo,
                            w, beta, L, thr, tb, part, gs, stats);
     else
-        hipLaunchKernelGGL((k_mf_prox_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vt, xc, xp, xo,
+        hipLaunchKernelGGL((k_mf_prox_gt<T, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg, xc, xp, xo,
                            w, beta, L, thr, tb, part, gs, stats);
 }
 
@@ -705,9 +862,9 @@ template void mf_residual_launch<float>(const l1ls_instance*, const float*, floa
 template void mf_residual_launch<double>(const l1ls_instance*, const double*, double*, const double*,
                                          const double*, double*, double*, double, int, double*, const GapState*, int,
                                          hipStream_t);
-template void mf_transpose_launch<float>(const l1ls_instance*, const float*, float*, const float*, const float*,
+template void mf_transpose_launch<float>(const l1ls_instance*, float*, float*, const float*, const float*,
                                          float*, float, float, float, double*, const GapState*, int, hipStream_t);
-template void mf_transpose_launch<double>(const l1ls_instance*, const double*, double*, const double*,
+template void mf_transpose_launch<double>(const l1ls_instance*, double*, double*, const double*,
                                           const double*, double*, double, double, double, double*, const GapState*,
                                           int, hipStream_t);
 
@@ -720,39 +877,52 @@ template <int MODE, typename TT>
 void mf_fwd_launch(const l1ls_instance* I, const double* x, double* wn, double* out, double* vm, const int32_t* done,
                    hipStream_t s) {
     const MfTabs<TT> tb = tabs_of<TT>(I);
-    if (I->rounds == 2) {
+    if (I->rounds == 2)
         hipLaunchKernelGGL((k_mf_gt<double, 2, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb,
                            done);
-        hipLaunchKernelGGL((k_mf_res_qt<double, 2, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
-                           (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
-                           done, 0);
-    } else {
+    else
         hipLaunchKernelGGL((k_mf_gt<double, 1, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, x, wn, tb,
                            done);
-        hipLaunchKernelGGL((k_mf_res_qt<double, 1, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wn,
+    const double* wg = wn;
+    if (I->mfw_ws) {
+        win_scatter<double>(I, 0, wn, wn + I->n, done, s);
+        wg = wn + I->n;
+    }
+    if (I->rounds == 2)
+        hipLaunchKernelGGL((k_mf_res_qt<double, 2, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wg,
                            (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
                            done, 0);
-    }
+    else
+        hipLaunchKernelGGL((k_mf_res_qt<double, 1, MODE, TT>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, wg,
+                           (const double*)nullptr, (const double*)nullptr, out, vm, 0.0, 1, tb, (double*)nullptr,
+                           done, 0);
 }
 
 void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s) {
     mf_fwd_launch<kMfProduct, double>(I, x, wn, out, (double*)nullptr, (const int32_t*)nullptr, s);
 }
 
-// out (n) = A^T y with y (m) and out in stage order; vm is m scratch.
+// out (n) = A^T y with y (m) and out in stage order; vm is scratch of
+// mf_vbuf_len entries.
 void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* out, hipStream_t s) {
     const MfTabs<double> tb = tabs_of<double>(I);
-    if (I->rounds == 2) {
+    if (I->rounds == 2)
         hipLaunchKernelGGL((k_mf_qt<double, 2>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, y, vm, tb);
-        hipLaunchKernelGGL((k_mf_g_hess<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm,
-                           (const double*)nullptr, (const double*)nullptr, (const uint8_t*)nullptr, out, tb,
-                           (double*)nullptr, (const int32_t*)nullptr);
-    } else {
+    else
         hipLaunchKernelGGL((k_mf_qt<double, 1>), dim3(mf_grid(I->m / 2)), dim3(L1LS_BLOCK), 0, s, y, vm, tb);
-        hipLaunchKernelGGL((k_mf_g_hess<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm,
+    const double* vg = vm;
+    if (I->mfw_ws) {
+        win_scatter<double>(I, 1, vm, vm + I->n, (const int32_t*)nullptr, s);
+        vg = vm + I->n;
+    }
+    if (I->rounds == 2)
+        hipLaunchKernelGGL((k_mf_g_hess<double, 2>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg,
                            (const double*)nullptr, (const double*)nullptr, (const uint8_t*)nullptr, out, tb,
                            (double*)nullptr, (const int32_t*)nullptr);
-    }
+    else
+        hipLaunchKernelGGL((k_mf_g_hess<double, 1>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg,
+                           (const double*)nullptr, (const double*)nullptr, (const uint8_t*)nullptr, out, tb,
+                           (double*)nullptr, (const int32_t*)nullptr);
 }
 
 // hp = mask (A^T A p + d p) with part[block] = sum p hp over mf_grid(n/2)
@@ -762,11 +932,16 @@ void mf_hess_t(const l1ls_instance* I, const double* p, double* wn, double* vm, 
                const uint8_t* mask, double* hp, double* part, const int32_t* done, hipStream_t s) {
     mf_fwd_launch<kMfNormal, TT>(I, p, wn, (double*)nullptr, vm, done, s);
     const MfTabs<TT> tb = tabs_of<TT>(I);
+    const double* vg = vm;
+    if (I->mfw_ws) {
+        win_scatter<double>(I, 1, vm, vm + I->n, done, s);
+        vg = vm + I->n;
+    }
     if (I->rounds == 2)
-        hipLaunchKernelGGL((k_mf_g_hess<double, 2, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+        hipLaunchKernelGGL((k_mf_g_hess<double, 2, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg, p, d,
                            mask, hp, tb, part, done);
     else
-        hipLaunchKernelGGL((k_mf_g_hess<double, 1, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vm, p, d,
+        hipLaunchKernelGGL((k_mf_g_hess<double, 1, TT>), dim3(mf_grid(I->n / 2)), dim3(L1LS_BLOCK), 0, s, vg, p, d,
                            mask, hp, tb, part, done);
 }
 

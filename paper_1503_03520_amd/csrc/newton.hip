@@ -30,6 +30,8 @@ l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double
 l1ls_status rel_err_planted(const l1ls_instance* I, const double* x, double* out, hipStream_t s);
 void mf_apply_fwd(const l1ls_instance* I, const double* x, double* wn, double* out, hipStream_t s);
 void mf_apply_adj(const l1ls_instance* I, const double* y, double* vm, double* out, hipStream_t s);
+int64_t mf_wbuf_len(const l1ls_instance* I);
+int64_t mf_vbuf_len(const l1ls_instance* I);
 void mf_hess(const l1ls_instance* I, const double* p, double* wn, double* vm, const double* d, const uint8_t* mask,
              double* hp, double* part, const int32_t* done, hipStream_t s, bool f32);
 int mf_grid(int64_t pairs);
@@ -494,8 +496,8 @@ struct Work {
     }
     l1ls_status init_mf() {
         mf = true;
-        L1LS_TRY(arena.alloc(&wn, I->n));
-        L1LS_TRY(arena.alloc(&vm, I->m));
+        L1LS_TRY(arena.alloc(&wn, mf_wbuf_len(I)));
+        L1LS_TRY(arena.alloc(&vm, mf_vbuf_len(I)));
         return L1LS_OK;
     }
     // host sums of `k` statistics over `nb` partial slots (fixed order)

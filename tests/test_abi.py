@@ -61,7 +61,7 @@ def test_generate_rejects_invalid_arguments(m, n, kappa, s, tau, rounds):
 
 
 @pytest.mark.parametrize("rounds,storage,layout,n,status", [
-    (2, 8, 1, 50, -1),                                    # unknown storage bit
+    (2, 16, 1, 50, -1),                                   # unknown storage bit
     (1, L.STORE_BLK32, 1, 50, -6),                        # blocks need two stages
     (2, L.STORE_BLK32 | L.STORE_F32, 0, 50, -6),          # ... and the stage layout
     (2, L.STORE_BLK32, 1, 2, -6),                         # ... and n >= 4

@@ -228,6 +228,30 @@ def test_matrix_free_products_multiblock(cfg):
             assert np.abs(out.double().cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max()), (prec, trans)
 
 
+@pytest.mark.parametrize("cfg", MF_MULTIBLOCK + [C1])
+def test_matrix_free_windowed_gathers_are_bitwise_the_plain_ones(cfg):
+    # The windowed gathers (L1LS_STORE_MF_WINDOWS; windows of 256 positions
+    # at these sizes, so each side spans several) read the same elements as
+    # the plain ones: FISTA over the fused passes in FP32 and FP64, CG-Newton
+    # and the power method give bitwise the same results.
+    m, n, kappa, s, tau, seed, r = cfg
+    g, o, A = pair(cfg)
+    gw = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=L.STORE_F64 | L.STORE_MF_WINDOWS)
+    try:
+        for prec in (L.F32, L.F64):
+            kw = dict(max_iter=40, rel_gap_tol=0.0, check_every=8, precision=prec, op=L.OP_MATRIX_FREE)
+            a, ra, _ = L.l1ls_solve_fista(g, **kw)
+            b, rb, _ = L.l1ls_solve_fista(gw, **kw)
+            assert torch.equal(a, b) and ra["primal"] == rb["primal"], prec
+        xs, rs, _ = L.l1ls_solve_cg_newton(g, max_iter=3, rel_gap_tol=1e-12, op=L.OP_MATRIX_FREE)
+        xw, rw, _ = L.l1ls_solve_cg_newton(gw, max_iter=3, rel_gap_tol=1e-12, op=L.OP_MATRIX_FREE)
+        assert torch.equal(xs, xw) and rs["inner"] == rw["inner"]
+        assert (L.l1ls_power_iteration(g, 20, op=L.OP_MATRIX_FREE)
+                == L.l1ls_power_iteration(gw, 20, op=L.OP_MATRIX_FREE))
+    finally:
+        gw.free()
+
+
 @pytest.mark.parametrize("cfg", CASES[:2])
 def test_fista_matrix_free_fp32_equals_stored_gap(cfg):
     # FP32 bulk on both operators: same tolerance to the FP64 oracle, and the
