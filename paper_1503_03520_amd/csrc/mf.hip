@@ -44,6 +44,7 @@ struct MfTabs {
     const int32_t* cbase;           // per workgroup of the m side: active positions before it
     const int32_t* gm;              // m side's gather index into its source: emb, or the window slots
     const int32_t* gn;              // n side's gather index: inv, or the window slots
+    int xcd;                        // windowed gathers: place each XCD's workgroups on one range (mf_block)
     const T* sig;                   // m: sigma at m-positions (0 if inactive)
     const T* sig_n;                 // n: sigma at n-positions
     int64_t n, m;
@@ -107,7 +108,18 @@ __device__ __forceinline__ void gather_block(const T* __restrict__ src, const in
     }
 }
 
-// Rank of the m-positions 2k and 2k+1 (k = blockIdx.x B + threadIdx.x, the
+// Workgroup index of a matrix-free pass.  Workgroups are handed to the 8
+// XCDs in turn (b, b+8, ... on one XCD); with xcd set, XCD x takes one
+// contiguous range of the pairs instead, so the workgroups of one gather
+// window share one L2, which then fetches that window's segment once.
+__device__ __forceinline__ int64_t mf_block(int xcd) {
+    const int64_t b = blockIdx.x;
+    if (!xcd) return b;
+    const int64_t G = gridDim.x, q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+// Rank of the m-positions 2k and 2k+1 (k = blk B + threadIdx.x, the
 // thread's stage-1 pair) among the active ones, or -1 where inactive.  Every
 // thread of the workgroup takes part, between two phases the caller puts a
 // __syncthreads: rank_count publishes each wave's count of active positions
@@ -130,9 +142,9 @@ __device__ __forceinline__ PairRank rank_count(const int32_t* __restrict__ emb, 
     if (lane == 0) ws[threadIdx.x >> 6] = __popcll(b0) + __popcll(b1);
     return r;
 }
-__device__ __forceinline__ void rank_of(const PairRank& r, const int32_t* __restrict__ cbase, const int32_t* ws,
-                                        int32_t& ci0, int32_t& ci1) {
-    int32_t base = cbase[blockIdx.x] + r.pre;
+__device__ __forceinline__ void rank_of(const PairRank& r, const int32_t* __restrict__ cbase, int64_t blk,
+                                        const int32_t* ws, int32_t& ci0, int32_t& ci1) {
+    int32_t base = cbase[blk] + r.pre;
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int w = 0; w < kMfWaves; ++w)
@@ -195,7 +207,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     __shared__ T yl[2 * B + H];  // r_y at positions 2k0 - H/2 .. (R = 2: from 2k0-1)
     if (done && *done) return;  // the solver's converged flag (launch-uniform)
     const int64_t m = tb.m, mp = m / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int64_t blk = mf_block(tb.xcd);
+    const int64_t k0 = blk * B;
     const int t = threadIdx.x;
     const int64_t k = k0 + t;
     const bool mine = k < mp;
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
             T o0, o1;
             rot(c1, z0, z1, true, o0, o1);
             int32_t ci0, ci1;
-            rank_of(pr, tb.cbase, ws, ci0, ci1);
+            rank_of(pr, tb.cbase, blk, ws, ci0, ci1);
             if (ci0 >= 0) vm[ci0] = s0 * o0;
             if (ci1 >= 0) vm[ci1] = s1 * o1;
         }
@@ -314,9 +327,9 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_res_qt(const T* __restrict__ 
     if (!stats) return;
     block_reduce_stats<3, 3>(v);
     if (threadIdx.x == 0) {
-        part[3 * blockIdx.x + 0] = v[0];
-        part[3 * blockIdx.x + 1] = v[1];
-        part[3 * blockIdx.x + 2] = v[2];
+        part[3 * blk + 0] = v[0];
+        part[3 * blk + 1] = v[1];
+        part[3 * blk + 2] = v[2];
     }
 }
 
@@ -340,7 +353,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     const int32_t done = gs ? gs->done : 0;
     if (done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int64_t blk = mf_block(tb.xcd);
+    const int64_t k0 = blk * B;
     // one position at a time: measured about 5% faster for this kernel than
     // gather_block's overlapped loads
     for (int q = threadIdx.x; q < 2 * B + 2 * H; q += B) {
@@ -417,8 +431,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_prox_gt(const T* __restrict__
     if (!stats) return;
     block_reduce_stats<2, 1>(v);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x + 0] = v[1];
-        part[2 * blockIdx.x + 1] = v[0];
+        part[2 * blk + 0] = v[1];
+        part[2 * blk + 1] = v[0];
     }
 }
 
@@ -429,13 +443,14 @@ template <typename T, int R>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_qt(const T* __restrict__ y, T* __restrict__ vm, MfTabs<T> tb) {
     __shared__ int32_t ws[kMfWaves];
     const int64_t m = tb.m, mp = m / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * L1LS_BLOCK + threadIdx.x;
+    const int64_t blk = mf_block(tb.xcd);
+    const int64_t k0 = blk * L1LS_BLOCK + threadIdx.x;
     const bool mine = k0 < mp;
     const int64_t k = mine ? k0 : mp - 1;
     const PairRank pr = rank_count(tb.gm, k, mine, ws);
     __syncthreads();
     int32_t ci0, ci1;
-    rank_of(pr, tb.cbase, ws, ci0, ci1);
+    rank_of(pr, tb.cbase, blk, ws, ci0, ci1);
     if (!mine) return;
     T z0 = y[2 * k], z1 = y[2 * k + 1];
     if (R == 2) {
@@ -470,7 +485,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
     __shared__ T tl[2 * B + 2 * H];
     if (done && *done) return;  // launch-uniform
     const int64_t n = tb.n, np = n / 2;
-    const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int64_t blk = mf_block(tb.xcd);
+    const int64_t k0 = blk * B;
     const int t = threadIdx.x;
     const int64_t k = k0 + t;
     const bool mine = k < np;
@@ -525,7 +541,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_mf_g_hess(const T* __restrict__ 
     }
     if (!part) return;  // launch-uniform
     block_reduce_stats<1, 1>(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    if (threadIdx.x == 0) part[blk] = acc[0];
 }
 
 // ---- tables ------------------------------------------------------------------
@@ -587,6 +603,7 @@ MfTabs<double> tabs_of<double>(const l1ls_instance* I) {
     t.cbase = I->mf_cbase;
     t.gm = I->mfw_ws ? I->mfw_ib[0] : I->mf_emb;
     t.gn = I->mfw_ws ? I->mfw_ib[1] : I->mf_inv;
+    t.xcd = I->mfw_ws ? 1 : 0;
     t.sig = I->mf_sig64;
     t.sig_n = I->mf_sign64;
     t.n = I->n;
@@ -605,6 +622,7 @@ MfTabs<float> tabs_of<float>(const l1ls_instance* I) {
     t.cbase = I->mf_cbase;
     t.gm = I->mfw_ws ? I->mfw_ib[0] : I->mf_emb;
     t.gn = I->mfw_ws ? I->mfw_ib[1] : I->mf_inv;
+    t.xcd = I->mfw_ws ? 1 : 0;
     t.sig = I->mf_sig32;
     t.sig_n = I->mf_sign32;
     t.n = I->n;
