@@ -581,6 +581,7 @@ def bench_large(args):
                   "stored_gbs_algorithmic": (k1 + k2) * stored / 1e9,
                   "matrix_free_iters_per_s": mfree, "matrix_free_gbs_algorithmic": mf_bytes(m, n, windows=n >= 1 << 22) * mfree / 1e9,
                   "matrix_free_speedup": mfree / stored,
+                  "matrix_free_gathers": "windowed" if n >= 1 << 22 else "plain",
                   "blocked_iters_per_s": blocked,
                   "blocked_gbs_algorithmic": sum(blocked_bytes(m, n, 4 * n)) * blocked / 1e9,
                   "stored_vs_blocked_max_abs_diff": float((x_s - x_b).abs().max()),
