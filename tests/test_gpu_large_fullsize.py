@@ -1,7 +1,7 @@
 """GPU parity at the full size of the memory-scale workload: n = 2^26,
 m = 2^27, kappa = 1e6, two Givens stages, s = n/1000, tau = 1, the seed the
 benchmark uses, stored CSR/CSC in FP32 and FP64 plus the matrix-free
-operator.  The whole instance is too large for the oracle's full
+operator (which at this size runs its windowed gathers).  The whole instance is too large for the oracle's full
 construction in a test, so the oracle's sampled form
 (``oracle.instance.LocalInstance``) evaluates the sampled outputs one by
 one: bijections at sampled positions, the support, b and e at sampled rows,
