@@ -172,6 +172,23 @@ l1ls_status l1ls_apply(const l1ls_instance* inst, int32_t trans, int32_t op,
 l1ls_status l1ls_objective_gap(const l1ls_instance* inst, double tau, const double* x_dev,
                                double* primal, double* dual, double* rel_gap, void* stream);
 
+/*
+ * l1ls_objective_gap for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that must not call hipMalloc,
+ * harnesses that forbid it): the same kernels and the same result, bit for
+ * bit, with every temporary (x in operator order, r, the partial sums) in a
+ * fixed scratch array of the library (about 12 MB on each device it runs
+ * on, held until the process ends) instead of fresh allocations.  The call
+ * allocates nothing, neither device nor host memory.
+ *   Limit: m <= 2^19 (524288); larger instances give L1LS_E_ARG before any
+ *   HIP call.  Needs the FP64 stored operator (else L1LS_E_UNSUPPORTED).
+ *   The scratch is shared by every call on one device: calls that overlap on
+ *   the same device (from other threads or on other streams) race and must
+ *   be serialised by the caller.  Synchronises `stream`.
+ */
+l1ls_status l1ls_objective_gap_noalloc(const l1ls_instance* inst, double tau, const double* x_dev,
+                                       double* primal, double* dual, double* rel_gap, void* stream);
+
 typedef struct {
     double tau;            /* <= 0: the instance's tau                          */
     double rel_gap_tol;    /* stop when (P - D)/|P| <= tol; 0: run max_iter     */

@@ -119,6 +119,9 @@ _SIGS = {
                                             _P]),
     "l1ls_objective_gap": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
+    "l1ls_objective_gap_noalloc": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                  _P]),
     "l1ls_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "l1ls_solve_fista": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
@@ -289,6 +292,13 @@ def l1ls_objective_gap(inst, tau, x, stream=None):
     P, D, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(lib().l1ls_objective_gap(inst.handle, tau, _ptr(x), ctypes.byref(P), ctypes.byref(D),
                                     ctypes.byref(g), _stream(stream)), "l1ls_objective_gap")
+    return P.value, D.value, g.value
+
+
+def l1ls_objective_gap_noalloc(inst, tau, x, stream=None):
+    P, D, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().l1ls_objective_gap_noalloc(inst.handle, tau, _ptr(x), ctypes.byref(P), ctypes.byref(D),
+                                            ctypes.byref(g), _stream(stream)), "l1ls_objective_gap_noalloc")
     return P.value, D.value, g.value
 
 

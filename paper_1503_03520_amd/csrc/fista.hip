@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -580,6 +581,19 @@ extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t
     return apply_stored<float>(I, trans, (const float*)in, (float*)out, s);
 }
 
+// P, D and the relative gap from the four sums (no contraction, so that the
+// host and the device evaluate them bit for bit alike).
+__host__ __device__ inline void gap_from_sums(double tau, double rr, double br, double l1, double ginf, double* P,
+                                              double* D, double* gap) {
+#pragma clang fp contract(off)
+    const double Pv = tau * l1 + 0.5 * rr;
+    const double theta = (ginf <= tau) ? 1.0 : tau / ginf;
+    const double Dv = -0.5 * theta * theta * rr - theta * br;
+    *P = Pv;
+    *D = Dv;
+    *gap = (Pv - Dv) / fabs(Pv);
+}
+
 // FP64 gap at x through the stored FP64 operator.  Used by the solvers too.
 l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
                      hipStream_t s, DevAlloc* al = nullptr) {
@@ -619,12 +633,11 @@ l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double
         ginf = std::max(ginf, h2[2 * b]);
         l1 += h2[2 * b + 1];
     }
-    const double Pv = tau * l1 + 0.5 * rr;
-    const double theta = (ginf <= tau) ? 1.0 : tau / ginf;
-    const double Dv = -0.5 * theta * theta * rr - theta * br;
+    double Pv, Dv, gv;
+    gap_from_sums(tau, rr, br, l1, ginf, &Pv, &Dv, &gv);
     *P = Pv;
     *D = Dv;
-    *gap = (Pv - Dv) / std::fabs(Pv);
+    *gap = gv;
     tmp.release();
     if (!is_finite(Pv) || !is_finite(Dv)) return L1LS_E_NONFINITE;
     return L1LS_OK;
@@ -655,6 +668,110 @@ extern "C" l1ls_status l1ls_objective_gap(const l1ls_instance* I, double tau, co
     if (!I || !x || !P || !D || !gap) return L1LS_E_ARG;
     if (!(tau > 0) || !is_finite(tau)) return L1LS_E_ARG;
     return gap_fp64(I, tau, x, P, D, gap, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// The FP64 gap without allocation (l1ls_objective_gap_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Largest m the allocation-free gap accepts, and the layout of its scratch
+// array: x in operator order (n <= m doubles), r and r_y (m each), the
+// partial sums of the two passes at their largest grids, and the three
+// results.
+constexpr int64_t kNoAllocMaxM = int64_t(1) << 19;
+constexpr int kNoAllocG1 = (int)(((kNoAllocMaxM + kTile - 1) / kTile + 3) / 4);
+constexpr int kNoAllocG2 = kGridCap;
+constexpr size_t kScratchX = 0;
+constexpr size_t kScratchR = kScratchX + (size_t)kNoAllocMaxM;
+constexpr size_t kScratchRy = kScratchR + (size_t)kNoAllocMaxM;
+constexpr size_t kScratchP1 = kScratchRy + (size_t)kNoAllocMaxM;
+constexpr size_t kScratchP2 = kScratchP1 + 3 * (size_t)kNoAllocG1;
+constexpr size_t kScratchOut = kScratchP2 + 2 * (size_t)kNoAllocG2;
+constexpr size_t kScratchDoubles = kScratchOut + 4;  // about 12 MB
+
+// Every device the library runs on holds its own copy until the process
+// ends.  Host code never uses this name as an address: the device address
+// comes from hipGetSymbolAddress (scratch_base below).
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_base[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+l1ls_status scratch_base(double** out) {
+    *out = nullptr;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return L1LS_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_base[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return L1LS_E_HIP;
+        g_scratch_base[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_base[dev];
+    return L1LS_OK;
+}
+
+// The host reduction of gap_fp64 on the device: the partials in the same
+// order, then P, D, gap.
+__global__ void k_gap_from_partials(const double* __restrict__ p1, int g1, const double* __restrict__ p2, int g2,
+                                    double tau, double* __restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double rr = 0, br = 0, l1 = 0, ginf = 0;
+    for (int b = 0; b < g1; ++b) {
+        rr += p1[3 * b];
+        br += p1[3 * b + 2];
+    }
+    for (int b = 0; b < g2; ++b) {
+        ginf = fmax(ginf, p2[2 * b]);
+        l1 += p2[2 * b + 1];
+    }
+    gap_from_sums(tau, rr, br, l1, ginf, out, out + 1, out + 2);
+}
+
+}  // namespace
+
+extern "C" l1ls_status l1ls_objective_gap_noalloc(const l1ls_instance* I, double tau, const double* x, double* P,
+                                                  double* D, double* gap, void* stream) {
+    if (!I || !x || !P || !D || !gap) return L1LS_E_ARG;
+    if (!(tau > 0) || !is_finite(tau)) return L1LS_E_ARG;
+    if (I->m > kNoAllocMaxM) return L1LS_E_ARG;
+    L1LS_TRY(check_stored(I, L1LS_F64));
+    const int g1 = tile_grid(I->m);
+    const int g2 = grid_for(I->n * kW_cols, L1LS_BLOCK, kGridCap);
+    if (g1 > kNoAllocG1 || g2 > kNoAllocG2 || I->n > I->m) return L1LS_E_ARG;
+    double* base = nullptr;
+    L1LS_TRY(scratch_base(&base));
+    hipStream_t s = (hipStream_t)stream;
+    double* xo = base + kScratchX;
+    double* r = base + kScratchR;
+    double* ry = base + kScratchRy;
+    double* p1 = base + kScratchP1;
+    double* p2 = base + kScratchP2;
+    double* res = base + kScratchOut;
+    // Every slot the passes below read is written earlier in the same call,
+    // so nothing needs clearing.
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(I->n), dim3(L1LS_BLOCK), 0, s, x, xo, I->op_col_of,
+                       I->n);
+    hipLaunchKernelGGL((k_residual<double>), dim3(g1), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col,
+                       I->csr_v64, xo, I->b_op, r, ry, 0.0, I->m, 1, p1, (const GapState*)nullptr, 1);
+    hipLaunchKernelGGL((k_colstats<double, kW_cols>), dim3(g2), dim3(L1LS_BLOCK), 0, s, I->csc_ptr, I->csc_row,
+                       I->csc_v64, r, xo, I->n, p2);
+    hipLaunchKernelGGL(k_gap_from_partials, dim3(1), dim3(64), 0, s, p1, g1, p2, g2, tau, res);
+    HIP_TRY(hipGetLastError());
+    double h[3];
+    HIP_TRY(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *P = h[0];
+    *D = h[1];
+    *gap = h[2];
+    if (!is_finite(h[0]) || !is_finite(h[1])) return L1LS_E_NONFINITE;
+    return L1LS_OK;
 }
 
 extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve_opts* opts, double* x_out,
