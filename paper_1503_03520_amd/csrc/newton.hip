@@ -16,7 +16,9 @@
 // Both use one PCG whose Hessian-vector product is a CSR pass (t = A p) and
 // a CSC pass with the epilogue Hp = mask (A^T t + d p) and the partial sums
 // of p^T Hp; alpha and beta are formed on the device.
+#include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstring>
 
@@ -44,7 +46,8 @@ constexpr int kRedBlocks = 512;   // grid of the vector kernels with partial sum
 
 struct CgScalars {
     double rz, pHp, alpha, beta, rr, stop2;
-    int32_t done, pad;
+    int32_t done;
+    int32_t mnorm;  // 1: the stop test reads r^T M^-1 r (the preconditioned residual), 0: r^T r
 };
 
 // tile_products (kernels.hpp) with stored values of type TV widened to the
@@ -195,7 +198,8 @@ __global__ __launch_bounds__(1024) void k_cg_beta(const double* __restrict__ par
         cs->rz = v[0];
         cs->rr = v[1];
         *iters += 1;
-        if (v[1] <= cs->stop2 || !(v[1] == v[1])) cs->done = 1;
+        const double res2 = cs->mnorm ? v[0] : v[1];
+        if (res2 <= cs->stop2 || !(res2 == res2)) cs->done = 1;
     }
 }
 
@@ -208,14 +212,15 @@ __global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, i
         p[j] = z[j] + be * p[j];
 }
 
-// Start of PCG: r = rhs - H x0 (hx given), z = minv r, p = z; part = (r z, r r, rhs rhs)
+// Start of PCG: r = rhs - H x0 (hx given), z = minv r, p = z;
+// part = (r z, r r, rhs rhs, rhs minv rhs)
 __global__ __launch_bounds__(L1LS_BLOCK) void k_cg_start(const double* __restrict__ rhs,
                                                          const double* __restrict__ hx, double* __restrict__ r,
                                                          double* __restrict__ z, double* __restrict__ p,
                                                          const double* __restrict__ minv,
                                                          const uint8_t* __restrict__ mask, int64_t n,
                                                          double* __restrict__ part) {
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const bool on = !mask || mask[j];
         const double rj = on ? rhs[j] - (hx ? hx[j] : 0.0) : 0.0;
@@ -226,30 +231,39 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_cg_start(const double* __restric
         v[0] += rj * zj;
         v[1] += rj * rj;
         v[2] += on ? rhs[j] * rhs[j] : 0.0;
+        v[3] += on ? rhs[j] * (minv[j] * rhs[j]) : 0.0;
     }
-    block_reduce_stats<3, 3>(v);
+    block_reduce_stats<4, 4>(v);
     if (threadIdx.x == 0) {
-        part[3 * blockIdx.x] = v[0];
-        part[3 * blockIdx.x + 1] = v[1];
-        part[3 * blockIdx.x + 2] = v[2];
+        part[4 * blockIdx.x] = v[0];
+        part[4 * blockIdx.x + 1] = v[1];
+        part[4 * blockIdx.x + 2] = v[2];
+        part[4 * blockIdx.x + 3] = v[3];
     }
 }
 
+// mnorm = 0: stop once ||r|| <= rtol ||rhs|| (the relative residual of the
+// Newton systems); mnorm = 1: once r^T M^-1 r <= rtol^2 rhs^T M^-1 rhs, the
+// residual of the diagonally scaled system, which bounds the error of every
+// coordinate relative to its own scale however widely the diagonal of H
+// spreads.
 __global__ __launch_bounds__(1024) void k_cg_init(const double* __restrict__ part, int np, CgScalars* cs,
-                                                  double rtol, int32_t* __restrict__ iters) {
-    double v[3] = {0.0, 0.0, 0.0};
+                                                  double rtol, int mnorm, int32_t* __restrict__ iters) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < np; b += blockDim.x) {
-        v[0] += part[3 * b];
-        v[1] += part[3 * b + 1];
-        v[2] += part[3 * b + 2];
+        v[0] += part[4 * b];
+        v[1] += part[4 * b + 1];
+        v[2] += part[4 * b + 2];
+        v[3] += part[4 * b + 3];
     }
-    block_reduce_stats<3, 3>(v);
+    block_reduce_stats<4, 4>(v);
     if (threadIdx.x == 0) {
         cs->rz = v[0];
         cs->rr = v[1];
-        cs->stop2 = rtol * rtol * v[2];
+        cs->mnorm = mnorm;
+        cs->stop2 = rtol * rtol * (mnorm ? v[3] : v[2]);
         cs->alpha = cs->beta = cs->pHp = 0.0;
-        cs->done = (v[1] <= cs->stop2) ? 1 : 0;
+        cs->done = ((mnorm ? v[0] : v[1]) <= cs->stop2) ? 1 : 0;
         *iters = 0;
     }
 }
@@ -257,7 +271,7 @@ __global__ __launch_bounds__(1024) void k_cg_init(const double* __restrict__ par
 __global__ void k_cg_reset(CgScalars* cs) {
     cs->rz = cs->pHp = cs->alpha = cs->beta = cs->rr = cs->stop2 = 0.0;
     cs->done = 0;
-    cs->pad = 0;
+    cs->mnorm = 0;
 }
 
 // ---- CG-Newton vector kernels -------------------------------------------
@@ -442,6 +456,93 @@ __global__ void k_axpby(const double* __restrict__ a, double alpha, const double
     if (i < N) out[i] = alpha * a[i] + beta * (b ? b[i] : 0.0);
 }
 
+// ---- block preconditioner of the polish ------------------------------------
+// The reduced Hessian H_S = A_S^T A_S couples two columns of S only where they
+// share a row, so it is block diagonal over the connected components of that
+// relation: nearly all singletons, a few pairs and triples.  Two columns of a
+// component can be nearly parallel (their largest sigma on the same Givens
+// stencil), which the diagonal preconditioner leaves at condition numbers
+// near kappa^2; with each small component's block inverted exactly the
+// preconditioned system is the identity on S.
+
+// Pairs (j, k), j < k, of masked columns that share row i, one thread per row.
+__global__ __launch_bounds__(L1LS_BLOCK) void k_pairs_from_rows(const int32_t* __restrict__ ptr,
+                                                                const int32_t* __restrict__ col,
+                                                                const uint8_t* __restrict__ mask, int64_t m,
+                                                                int32_t* __restrict__ pairs, int32_t cap,
+                                                                int32_t* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t c[kMaxNnz];
+    int k = 0;
+    for (int32_t e = ptr[i]; e < ptr[i + 1] && k < kMaxNnz; ++e) {
+        const int32_t j = col[e];
+        if (mask[j]) c[k++] = j;
+    }
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b) {
+            const int32_t q = atomicAdd(count, 1);
+            if (q < cap) {
+                pairs[2 * q] = min(c[a], c[b]);
+                pairs[2 * q + 1] = max(c[a], c[b]);
+            }
+        }
+}
+
+// Column cols[t] of the CSC (at most kMaxNnz entries) into slot t.
+__global__ void k_pack_cols(const int32_t* __restrict__ ptr, const int32_t* __restrict__ row,
+                            const double* __restrict__ val, const int32_t* __restrict__ cols, int32_t nc,
+                            int32_t* __restrict__ prow, double* __restrict__ pval) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc) return;
+    const int32_t j = cols[t];
+    const int32_t b = ptr[j], e = ptr[j + 1];
+    for (int q = 0; q < kMaxNnz; ++q) {
+        prow[(size_t)t * kMaxNnz + q] = (b + q < e) ? row[b + q] : -1;
+        pval[(size_t)t * kMaxNnz + q] = (b + q < e) ? val[b + q] : 0.0;
+    }
+}
+
+constexpr int kFixBlocks = 64;  // grid of k_block_fix (partial-sum slots after the kRedBlocks ones)
+
+// z_j = sum_b W[t][b] v[bcol[t][b]] for member t (column mem[t]) of a block,
+// replacing the diagonal z_j = minv_j v_j.  part slot (kRedBlocks + block) of
+// stride `stride` receives sum v_j (z_j - minv_j v_j) at offset 0 and, when
+// rhs is given, sum rhs_j ((M^-1 rhs)_j - minv_j rhs_j) at offset 3.  With
+// p != nullptr, p_j = z_j as well (the PCG start).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_block_fix(const int32_t* __restrict__ mem,
+                                                          const int32_t* __restrict__ boff,
+                                                          const int32_t* __restrict__ bk,
+                                                          const int32_t* __restrict__ bcol,
+                                                          const double* __restrict__ w, int32_t nm,
+                                                          const double* __restrict__ v, const double* __restrict__ minv,
+                                                          double* __restrict__ z, double* __restrict__ p,
+                                                          const double* __restrict__ rhs, double* __restrict__ part,
+                                                          int stride, const CgScalars* __restrict__ cs) {
+    if (cs && cs->done) return;
+    double acc[2] = {0.0, 0.0};
+    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nm; t += gridDim.x * blockDim.x) {
+        const int32_t j = mem[t], o = boff[t], k = bk[t];
+        double zn = 0.0, mr = 0.0;
+        for (int b = 0; b < k; ++b) {
+            const int32_t c = bcol[o + b];
+            zn += w[(size_t)t * 16 + b] * v[c];
+            if (rhs) mr += w[(size_t)t * 16 + b] * rhs[c];
+        }
+        acc[0] += v[j] * (zn - minv[j] * v[j]);
+        if (rhs) acc[1] += rhs[j] * (mr - minv[j] * rhs[j]);
+        z[j] = zn;
+        if (p) p[j] = zn;
+    }
+    block_reduce_stats<2, 2>(acc);
+    if (threadIdx.x == 0) {
+        double* o = part + (size_t)stride * (kRedBlocks + blockIdx.x);
+        for (int q = 0; q < stride; ++q) o[q] = 0.0;
+        o[0] = acc[0];
+        if (stride == 4) o[3] = acc[1];
+    }
+}
+
 // ---- host side ------------------------------------------------------------
 struct Work {
     const l1ls_instance* I = nullptr;
@@ -462,6 +563,12 @@ struct Work {
     bool mf = false;
     double *wn = nullptr, *vm = nullptr;
     std::vector<double> h;
+    // Block preconditioner of the polish (k_block_fix): nm members, their
+    // columns, block offsets / sizes into bcol, and rows of the block inverses.
+    int32_t nm = 0, mcap = 0;
+    int32_t *bmem = nullptr, *boff = nullptr, *bk = nullptr, *bcol = nullptr, *pairs = nullptr, *npairs = nullptr;
+    int32_t* prow = nullptr;
+    double *bw = nullptr, *pval = nullptr;
     ~Work() {
         (void)hipStreamSynchronize(s);  // nothing queued may still use the buffers
         arena.release();
@@ -475,12 +582,12 @@ struct Work {
         L1LS_TRY(arena.alloc(&tm, m));
         L1LS_TRY(arena.alloc(&tm2, m));
         L1LS_TRY(arena.alloc(&rres, m));
-        L1LS_TRY(arena.alloc(&part, 4 * (size_t)std::max(kRedBlocks, tgrid(n))));
+        L1LS_TRY(arena.alloc(&part, 4 * (size_t)std::max(kRedBlocks + kFixBlocks, tgrid(n))));
         L1LS_TRY(arena.alloc(&mask, n));
         L1LS_TRY(arena.alloc(&counts, 2));
         L1LS_TRY(arena.alloc(&iters, 1));
         L1LS_TRY(arena.alloc(&cs, 1));
-        h.resize(4 * (size_t)std::max(kRedBlocks, tgrid(n)));
+        h.resize(4 * (size_t)std::max(kRedBlocks + kFixBlocks, tgrid(n)));
         return L1LS_OK;
     }
     // only what the products and a reduction need: x, atr (n), rres (m), part
@@ -550,19 +657,178 @@ struct Work {
                                I->csc_v64, tm, v, dv, mk, hp, n, part, (const CgScalars*)cs);
         }
     }
+    // Components of the masked columns that share rows (polish, stored FP64
+    // operator): the exact inverse of each component's block of A_S^T A_S
+    // (components of 2 to 16 columns; larger ones keep the diagonal).  The
+    // result does not depend on the order in which pairs are found.
+    l1ls_status setup_blocks() {
+        nm = 0;
+        constexpr int32_t kPairCap = 1 << 21;
+        constexpr int kMaxBlk = 16;
+        if (!pairs) {
+            L1LS_TRY(arena.alloc(&pairs, 2 * (size_t)kPairCap));
+            L1LS_TRY(arena.alloc(&npairs, 1));
+        }
+        HIP_TRY(hipMemsetAsync(npairs, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_pairs_from_rows, g1d(I->m), dim3(L1LS_BLOCK), 0, s, I->csr_ptr, I->csr_col, mask, I->m,
+                           pairs, kPairCap, npairs);
+        int32_t np = 0;
+        HIP_TRY(hipMemcpyAsync(&np, npairs, sizeof(np), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (np <= 0 || np > kPairCap) return L1LS_OK;  // none, or too many to list: the diagonal alone
+        std::vector<int32_t> hp2(2 * (size_t)np);
+        HIP_TRY(hipMemcpy(hp2.data(), pairs, hp2.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<uint64_t> keys(np);
+        for (int32_t q = 0; q < np; ++q)
+            keys[q] = ((uint64_t)(uint32_t)hp2[2 * q] << 32) | (uint32_t)hp2[2 * q + 1];
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        // union-find over the columns that appear in a pair
+        std::vector<int32_t> cols;
+        cols.reserve(2 * keys.size());
+        for (uint64_t k : keys) {
+            cols.push_back((int32_t)(k >> 32));
+            cols.push_back((int32_t)(k & 0xffffffffu));
+        }
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        auto id = [&](int32_t c) { return (int32_t)(std::lower_bound(cols.begin(), cols.end(), c) - cols.begin()); };
+        std::vector<int32_t> par(cols.size());
+        for (size_t q = 0; q < par.size(); ++q) par[q] = (int32_t)q;
+        std::function<int32_t(int32_t)> root = [&](int32_t a) {
+            while (par[a] != a) a = par[a] = par[par[a]];
+            return a;
+        };
+        for (uint64_t k : keys) {
+            int32_t a = root(id((int32_t)(k >> 32))), b = root(id((int32_t)(k & 0xffffffffu)));
+            if (a != b) par[std::max(a, b)] = std::min(a, b);
+        }
+        // components in order of their smallest column; members ascending
+        std::vector<std::vector<int32_t>> comp;
+        std::vector<int32_t> cidx(cols.size(), -1);
+        for (size_t q = 0; q < cols.size(); ++q) {
+            const int32_t r0 = root((int32_t)q);
+            if (cidx[r0] < 0) {
+                cidx[r0] = (int32_t)comp.size();
+                comp.emplace_back();
+            }
+            comp[cidx[r0]].push_back(cols[q]);
+        }
+        std::vector<int32_t> mcol, moff, mk, mbcol;
+        for (auto& c : comp) {
+            if (c.size() < 2 || c.size() > (size_t)kMaxBlk) continue;
+            const int32_t off = (int32_t)mbcol.size();
+            for (int32_t j : c) {
+                mcol.push_back(j);
+                moff.push_back(off);
+                mk.push_back((int32_t)c.size());
+            }
+            mbcol.insert(mbcol.end(), c.begin(), c.end());
+        }
+        const int32_t nmem = (int32_t)mcol.size();
+        if (nmem == 0) return L1LS_OK;
+        if (nmem > mcap) {
+            mcap = std::max(nmem, 4096);
+            L1LS_TRY(arena.alloc(&bmem, mcap));
+            L1LS_TRY(arena.alloc(&boff, mcap));
+            L1LS_TRY(arena.alloc(&bk, mcap));
+            L1LS_TRY(arena.alloc(&bcol, mcap));
+            L1LS_TRY(arena.alloc(&bw, (size_t)16 * mcap));
+            L1LS_TRY(arena.alloc(&prow, (size_t)kMaxNnz * mcap));
+            L1LS_TRY(arena.alloc(&pval, (size_t)kMaxNnz * mcap));
+        }
+        // the members' columns of A (rows and FP64 values), to the host
+        HIP_TRY(hipMemcpyAsync(bcol, mbcol.data(), nmem * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_pack_cols, dim3((nmem + 255) / 256), dim3(256), 0, s, I->csc_ptr, I->csc_row,
+                           I->csc_v64, bcol, nmem, prow, pval);
+        std::vector<int32_t> hrow((size_t)kMaxNnz * nmem);
+        std::vector<double> hval((size_t)kMaxNnz * nmem);
+        HIP_TRY(hipMemcpyAsync(hrow.data(), prow, hrow.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hval.data(), pval, hval.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        // per component: H_C = A_C^T A_C and its inverse (Gauss-Jordan with
+        // partial pivoting); a numerically singular block keeps the diagonal
+        std::vector<double> wrow((size_t)16 * nmem, 0.0);
+        std::vector<uint8_t> keep(nmem, 1);
+        for (int32_t t0 = 0; t0 < nmem;) {
+            const int k = mk[t0];
+            double H[kMaxBlk][2 * kMaxBlk];
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) {
+                    double acc = 0.0;
+                    const int32_t* ra = &hrow[(size_t)(t0 + a) * kMaxNnz];
+                    const int32_t* rb = &hrow[(size_t)(t0 + b) * kMaxNnz];
+                    for (int qa = 0; qa < kMaxNnz && ra[qa] >= 0; ++qa)
+                        for (int qb = 0; qb < kMaxNnz && rb[qb] >= 0; ++qb)
+                            if (ra[qa] == rb[qb])
+                                acc += hval[(size_t)(t0 + a) * kMaxNnz + qa] * hval[(size_t)(t0 + b) * kMaxNnz + qb];
+                    H[a][b] = acc;
+                    H[a][k + b] = (a == b) ? 1.0 : 0.0;
+                }
+            bool ok = true;
+            for (int c = 0; c < k && ok; ++c) {
+                int piv = c;
+                for (int a = c + 1; a < k; ++a)
+                    if (std::fabs(H[a][c]) > std::fabs(H[piv][c])) piv = a;
+                if (!(std::fabs(H[piv][c]) > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                if (piv != c)
+                    for (int b = 0; b < 2 * k; ++b) std::swap(H[c][b], H[piv][b]);
+                const double inv = 1.0 / H[c][c];
+                for (int b = 0; b < 2 * k; ++b) H[c][b] *= inv;
+                for (int a = 0; a < k; ++a) {
+                    if (a == c) continue;
+                    const double f = H[a][c];
+                    if (f != 0.0)
+                        for (int b = 0; b < 2 * k; ++b) H[a][b] -= f * H[c][b];
+                }
+            }
+            for (int a = 0; a < k; ++a) {
+                if (!ok) keep[t0 + a] = 0;
+                for (int b = 0; b < k; ++b) wrow[(size_t)(t0 + a) * 16 + b] = ok ? H[a][k + b] : 0.0;
+            }
+            t0 += k;
+        }
+        // drop the members of blocks that could not be inverted
+        std::vector<int32_t> fcol, foff, fk;
+        std::vector<double> fw;
+        for (int32_t t = 0; t < nmem; ++t) {
+            if (!keep[t]) continue;
+            fcol.push_back(mcol[t]);
+            foff.push_back(moff[t]);
+            fk.push_back(mk[t]);
+            fw.insert(fw.end(), wrow.begin() + (size_t)t * 16, wrow.begin() + (size_t)(t + 1) * 16);
+        }
+        nm = (int32_t)fcol.size();
+        if (nm == 0) return L1LS_OK;
+        HIP_TRY(hipMemcpyAsync(bmem, fcol.data(), nm * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(boff, foff.data(), nm * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(bk, fk.data(), nm * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(bw, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope
+        return L1LS_OK;
+    }
     // PCG on H v = rhs from v = x (in place), H = mask (A^T A + diag(dv)) mask.
     // zero_start: v is known to be 0, so H v = 0 is not computed.
     // f32: the products with A use its FP32 values (the Newton directions);
     // the polish keeps FP64.
     l1ls_status pcg(double* v, const double* rhs_v, const double* dv, const uint8_t* mk, double rtol, int maxit,
-                    int* out_iters, bool zero_start = false, bool f32 = false) {
+                    int* out_iters, bool zero_start = false, bool f32 = false, int mnorm = 0, bool blocks = false) {
+        blocks = blocks && nm > 0;
         const int64_t n = I->n;
         const int gt = hess_parts();
         hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(1), 0, s, cs);
         if (!zero_start) hess(v, dv, mk, f32);  // H v for the starting residual
         hipLaunchKernelGGL(k_cg_start, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, rhs_v,
                            zero_start ? (const double*)nullptr : hp, r, z, p, minv, mk, n, part);
-        hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1024), 0, s, part, kRedBlocks, cs, rtol, iters);
+        // with blocks, their members' z (and p) and the two sums that read z
+        const int np = blocks ? kRedBlocks + kFixBlocks : kRedBlocks;
+        if (blocks)
+            hipLaunchKernelGGL(k_block_fix, dim3(kFixBlocks), dim3(L1LS_BLOCK), 0, s, bmem, boff, bk, bcol, bw, nm, r,
+                               minv, z, p, rhs_v, part, 4, (const CgScalars*)nullptr);
+        hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1024), 0, s, part, np, cs, rtol, mnorm, iters);
         HIP_TRY(hipGetLastError());
         const int batch = 8;
         int done_iters = 0;
@@ -573,7 +839,11 @@ struct Work {
                 hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, part, gt, cs);
                 hipLaunchKernelGGL(k_cg_update, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, v, r, z, p, hp, minv, mk,
                                    n, part, (const CgScalars*)cs);
-                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, part, kRedBlocks, cs, iters);
+                if (blocks)
+                    hipLaunchKernelGGL(k_block_fix, dim3(kFixBlocks), dim3(L1LS_BLOCK), 0, s, bmem, boff, bk, bcol,
+                                       bw, nm, r, minv, z, (double*)nullptr, (const double*)nullptr, part, 2,
+                                       (const CgScalars*)cs);
+                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, part, np, cs, iters);
                 hipLaunchKernelGGL(k_cg_dir, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, p, z, n,
                                    (const CgScalars*)cs);
             }
@@ -613,7 +883,11 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
                            W.rhs, W.minv, n);
         hipLaunchKernelGGL(k_mask_mul, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, n);
         int it = 0;
-        L1LS_TRY(W.pcg(W.x, W.rhs, nullptr, W.mask, 1e-13, 2000, &it));
+        // stop on the residual of the diagonally scaled system: column norms
+        // of A_S spread over kappa^2, and a plain relative residual leaves
+        // the coordinates of the smallest columns unresolved
+        L1LS_TRY(W.setup_blocks());
+        L1LS_TRY(W.pcg(W.x, W.rhs, nullptr, W.mask, 1e-13, 2000, &it, false, false, 1, true));
         total += it;
         // A^T (A x - b)
         W.spmv(W.x, W.tm);
@@ -625,6 +899,11 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
         int32_t cnt[2];
         HIP_TRY(hipMemcpyAsync(cnt, W.counts, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (std::getenv("L1LS_DEBUG_POLISH"))
+            std::fprintf(stderr,
+                         "l1ls polish: round %d, %d columns in blocks, %d PCG iterations, %d sign changes on S, "
+                         "%d KKT violators off S\n",
+                         rounds, W.nm, it, cnt[0], cnt[1]);
         if (cnt[0] == 0 && cnt[1] == 0) break;
         hipLaunchKernelGGL(k_polish_apply, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, W.atr, tau, slack,
                            cnt[0] > 0 ? 1 : 0, n);

@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 
 import paper_1503_03520_amd as L  # noqa: E402
 import seeded_inputs as SI  # noqa: E402
+from fp32_bounds import fp32_trajectory_bound  # noqa: E402
 from oracle import fista as F  # noqa: E402
 from oracle import instance as OI  # noqa: E402
 
@@ -84,24 +85,23 @@ _ref = {}
 def oracle_trajectory():
     if not _ref:
         g, o, A = full()
-        _ref["x"] = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, ITERS)
+        _ref["x"], _ref["bound"] = fp32_trajectory_bound(A, o.b, o.tau, 1.0, ITERS)
         print("[case] oracle FISTA done", flush=True)
-    return _ref["x"]
+    return _ref["x"], _ref["bound"]
 
 
 @pytest.mark.parametrize("op", [L.OP_STORED, L.OP_BLOCKED])
 def test_full_size_fista_fp32_trajectory_and_gap(op):
     # FP32 bulk against the FP64 oracle with the bound of the FP32 path
-    # (k eps32 ||b||_inf after k steps); the device's FP64 primal value at
-    # its own iterate against the oracle's objective there.
+    # (tests/fp32_bounds.py); the device's FP64 primal value at its own
+    # iterate against the oracle's objective there.
     g, o, A = full()
-    ref = oracle_trajectory()
+    ref, bound = oracle_trajectory()
     fs = L.Fista(g, precision=L.F32, rel_gap_tol=0.0, check_every=CHECK, max_iter=ITERS, op=op)
     fs.iterate(ITERS)
     rep = fs.report()
     x = fs.get_x().cpu().numpy()
     fs.destroy()
-    bound = ITERS * np.finfo(np.float32).eps * np.abs(o.b).max()
     err = np.abs(x - ref).max()
     print(f"op {op}: max |x - x_oracle| {err:.3e} (bound {bound:.3e})", flush=True)
     assert err <= bound
@@ -110,6 +110,39 @@ def test_full_size_fista_fp32_trajectory_and_gap(op):
     assert abs(rep["primal"] - P) <= 1e-5 * abs(P)
     Pd, Dd, gap = L.l1ls_objective_gap(g, o.tau, _dev(x))
     assert math.isclose(Pd, P, rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("solver", ["fista_fp32", "cg_newton"])
+def test_full_size_certified_solve_reaches_planted_minimiser(solver):
+    # The bulk solve (FP32 FISTA, 300 iterations with the gap test every 32,
+    # or 8 CG-Newton steps in FP64), then the FP64 polish of the reduced
+    # problem (13).  Procedure IGen (section 3.1) makes x* the unique
+    # minimiser; the oracle solves the reduced system on the planted support
+    # and signs with a direct sparse solver, which reaches x* to the FP64
+    # floor of this instance (kappa(A^T A) = 1e8), and the device's x must
+    # equal that solution and x*.
+    import scipy.sparse.linalg as spla
+
+    g, o, A = full()
+    if solver == "fista_fp32":
+        x, rep, _ = L.l1ls_solve_fista(g, max_iter=300, rel_gap_tol=1e-8, check_every=CHECK, precision=L.F32,
+                                       polish=1)
+    else:
+        x, rep, _ = L.l1ls_solve_cg_newton(g, max_iter=8, rel_gap_tol=1e-12, precision=L.F64, polish=1)
+    xh = x.cpu().numpy()
+    S = np.flatnonzero(o.xstar)
+    AS = A.tocsc()[:, S]
+    xo = np.zeros(o.n)
+    xo[S] = spla.spsolve((AS.T @ AS).tocsc(), AS.T @ o.b - o.tau * np.sign(o.xstar[S]))
+    nx = np.linalg.norm(o.xstar)
+    e_oracle = np.linalg.norm(xo - o.xstar) / nx
+    e_dev = np.linalg.norm(xh - xo) / nx
+    print(f"{solver}: polish rounds {rep['polish_rounds']}, rel gap {rep['rel_gap']:.3e}, rel err {rep['rel_err']:.3e}; "
+          f"oracle reduced solve vs x* {e_oracle:.3e}, device vs oracle {e_dev:.3e}", flush=True)
+    assert rep["rel_gap"] <= 1e-8
+    assert e_oracle <= 1e-9
+    assert e_dev <= 2e-9 and rep["rel_err"] <= 1e-9
+    assert np.array_equal(np.flatnonzero(xh), S)
 
 
 def teardown_module(module):
