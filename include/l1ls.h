@@ -130,6 +130,29 @@ typedef struct {
 typedef struct l1ls_instance l1ls_instance;
 
 /*
+ * Source of the library's device memory (a contract of this boundary; the
+ * paper has nothing to say on memory management).  Every block the library
+ * allocates (instances, solver workspaces and iterates,
+ * temporaries, batch slots, the serving pool's blocks) comes from
+ * alloc(ctx, bytes) once an allocator is installed, and goes back through
+ * free(ctx, ptr, bytes) to the allocator that made it, even after another
+ * one has been installed.  alloc returns NULL when it cannot serve the
+ * request (the call then fails with L1LS_E_NOMEM).  Before it calls free the
+ * library waits for the device (as hipFree does), so the allocator may hand
+ * the block to any stream at once.  The callbacks may run on the library's
+ * worker threads (the serving loop).  NULL restores hipMalloc / hipFree for
+ * new blocks.  L1LS_E_ARG when alloc or free is NULL.  The Python binding
+ * installs PyTorch's caching allocator.  l1ls_objective_gap_noalloc never
+ * calls the allocator.
+ */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*free)(void* ctx, void* ptr, size_t bytes);
+    void* ctx;
+} l1ls_allocator;
+l1ls_status l1ls_set_allocator(const l1ls_allocator* allocator);
+
+/*
  * Build an instance on the current device (section 3.1 Procedure IGen with
  * A = Q Sigma G^T, eq. (16), section 4):
  *   sigma_j = kappa^(-(j-1)/(n-1)); G, Q = `rounds` Givens stages of random
@@ -150,6 +173,9 @@ l1ls_status l1ls_generate_ex(int64_t m, int64_t n, double kappa, int64_t s,
                              double tau, uint64_t seed, const l1ls_gen_opts* opts,
                              l1ls_instance** out);
 l1ls_status l1ls_instance_info(const l1ls_instance* inst, l1ls_info* out);
+/* Device bytes the instance holds (the sum of its blocks as requested from
+ * the allocator); 0 for NULL. */
+size_t l1ls_instance_bytes(const l1ls_instance* inst);
 void l1ls_free(l1ls_instance* inst);
 
 /*
@@ -216,6 +242,17 @@ typedef struct {
     double f_target;
     /* l1ls_sgt_solve_pcdm only: probability that a coordinate is updated in a step (<= 0: 1). */
     double pcdm_p;
+    /* Batch only: 1 = enqueue whole check periods as one HIP graph (captured
+     * once per set of resident slots, replayed; the kernels read the
+     * iteration count from device memory), 0 = launch every kernel.  The
+     * iterates are the same bit for bit. */
+    int32_t graph;
+    /* Batch only: slots with at most this many rows run all of an iterate
+     * call's iterations in one launch, one workgroup per slot (workgroup
+     * barriers only), beside the shared passes of the larger slots; 0: the
+     * library's default (4096), -1: never.  The iterates are the same bit for
+     * bit. */
+    int32_t persist_rows;
 } l1ls_solve_opts;
 
 typedef struct {

@@ -63,7 +63,8 @@ class SolveOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("time_kernels", ctypes.c_int32),
         ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
         ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
-        ("f_target", ctypes.c_double), ("pcdm_p", ctypes.c_double),
+        ("f_target", ctypes.c_double), ("pcdm_p", ctypes.c_double), ("graph", ctypes.c_int32),
+        ("persist_rows", ctypes.c_int32),
     ]
 
 
@@ -104,6 +105,14 @@ class SgtDesc(ctypes.Structure):
     ]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 # Every symbol include/l1ls.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
 _SIGS = {
@@ -112,7 +121,9 @@ _SIGS = {
     "l1ls_generate_ex": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int64,
                                         ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(GenOpts),
                                         ctypes.POINTER(_P)]),
+    "l1ls_set_allocator": (ctypes.c_int, [ctypes.POINTER(Allocator)]),
     "l1ls_instance_info": (ctypes.c_int, [_P, ctypes.POINTER(Info)]),
+    "l1ls_instance_bytes": (ctypes.c_size_t, [_P]),
     "l1ls_free": (None, [_P]),
     "l1ls_apply": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "l1ls_power_iteration": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double),
@@ -186,7 +197,9 @@ _lib = None
 
 
 def lib():
-    """The loaded libl1ls.so (raises if it was not built)."""
+    """The loaded libl1ls.so (raises if it was not built).  On first load it
+    installs PyTorch's caching allocator as the library's device-memory
+    source (l1ls_set_allocator), unless L1LS_HIP_MALLOC=1."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -197,7 +210,64 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = handle
+        if os.environ.get("L1LS_HIP_MALLOC") != "1":
+            use_torch_allocator()
     return _lib
+
+
+# State of the PyTorch allocator shim.  The callbacks are kept alive for the
+# life of the process (blocks made through them may be returned while the
+# interpreter shuts down); after exit handlers ran, returns are dropped, since
+# the process releases the device memory anyway.
+_torch_alloc = {"installed": False, "live": True, "keep": None}
+
+
+def _make_torch_callbacks():
+    import torch
+    raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc
+    raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
+    current_stream = torch.cuda.current_stream
+
+    def alloc(ctx, nbytes):
+        try:
+            return raw_alloc(int(nbytes), current_stream().cuda_stream)
+        except Exception:
+            return None  # the library reports L1LS_E_NOMEM
+
+    def free(ctx, ptr, nbytes):
+        if _torch_alloc["live"] and ptr:
+            try:
+                raw_delete(ptr)
+            except Exception:
+                pass
+
+    return _ALLOC_FN(alloc), _FREE_FN(free)
+
+
+def use_torch_allocator():
+    """Route the library's device memory through PyTorch's caching allocator
+    (torch.cuda.memory_allocated then counts it)."""
+    if _torch_alloc["installed"]:
+        return
+    try:
+        fa, ff = _make_torch_callbacks()
+    except ImportError:
+        return
+    spec = Allocator(fa, ff, None)
+    _check(_lib.l1ls_set_allocator(ctypes.byref(spec)), "l1ls_set_allocator")
+    # one reference that is never dropped: the trampolines outlive every object
+    ctypes.pythonapi.Py_IncRef(ctypes.py_object(fa))
+    ctypes.pythonapi.Py_IncRef(ctypes.py_object(ff))
+    _torch_alloc.update(installed=True, keep=(fa, ff, spec))
+    import atexit
+    atexit.register(_torch_alloc.__setitem__, "live", False)
+
+
+def use_hip_malloc():
+    """New device blocks from hipMalloc again (blocks made through PyTorch go
+    back to it)."""
+    _check(lib().l1ls_set_allocator(None), "l1ls_set_allocator")
+    _torch_alloc["installed"] = False
 
 
 def _check(status, where, allow=(L1LS_OK,)):
@@ -229,6 +299,10 @@ class Instance:
     @property
     def handle(self):
         return self._h
+
+    def nbytes(self):
+        """Device bytes the instance holds (l1ls_instance_bytes)."""
+        return int(lib().l1ls_instance_bytes(self._h))
 
     def info(self):
         inf = Info()

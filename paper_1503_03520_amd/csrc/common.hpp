@@ -44,12 +44,16 @@ struct DevAlloc {
     virtual void free(void* p, size_t bytes) = 0;
 };
 
+// Device memory of the process-wide source (alloc.hip): the allocator
+// installed with l1ls_set_allocator, else hipMalloc / hipFree.  lib_free
+// returns a block to whichever source made it.
+l1ls_status lib_alloc(void** p, size_t bytes);
+void lib_free(void* p, size_t bytes);
+
 inline l1ls_status dev_alloc(DevAlloc* al, void** p, size_t bytes) {
     *p = nullptr;
     if (al) return al->alloc(p, bytes);
-    const hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? L1LS_E_NOMEM : L1LS_E_HIP;
-    return L1LS_OK;
+    return lib_alloc(p, bytes);
 }
 
 inline void dev_free(DevAlloc* al, void* p, size_t bytes) {
@@ -57,7 +61,7 @@ inline void dev_free(DevAlloc* al, void* p, size_t bytes) {
     if (al)
         al->free(p, bytes);
     else
-        (void)hipFree(p);
+        lib_free(p, bytes);
 }
 
 // Device allocation list owned by one object; freed in reverse order.

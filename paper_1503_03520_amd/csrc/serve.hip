@@ -77,8 +77,8 @@ double iter_bytes(int64_t m, int64_t n, int64_t nnz) { return 16.0 * nnz + 24.0 
 // the device, so a free in the serving loop would stall the other size
 // classes and workers; instead freed blocks go to per-size free lists
 // (sizes rounded up to a quarter octave, at most 25% slack) and are reused.
-// Cached bytes beyond `cap` are returned to HIP; everything is returned when
-// the server is destroyed.
+// Cached bytes beyond `cap` go back to the library's device-memory source
+// (l1ls_set_allocator); everything goes back when the server is destroyed.
 class ServePool : public DevAlloc {
    public:
     explicit ServePool(size_t cap) : cap_(cap) {}
@@ -101,10 +101,9 @@ class ServePool : public DevAlloc {
                 return L1LS_OK;
             }
         }
-        const hipError_t e = hipMalloc(p, r);
-        if (e != hipSuccess) {
+        if (lib_alloc(p, r) != L1LS_OK) {
             trim(0);  // give the cache back and try once more
-            if (hipMalloc(p, r) != hipSuccess) return L1LS_E_NOMEM;
+            if (lib_alloc(p, r) != L1LS_OK) return L1LS_E_NOMEM;
         }
         return L1LS_OK;
     }
@@ -125,7 +124,7 @@ class ServePool : public DevAlloc {
     void trim_locked(size_t keep) {  // largest blocks first
         for (auto it = free_.rbegin(); it != free_.rend() && cached_ > keep; ++it)
             while (!it->second.empty() && cached_ > keep) {
-                (void)hipFree(it->second.back());
+                lib_free(it->second.back(), it->first);
                 it->second.pop_back();
                 cached_ -= it->first;
             }

@@ -184,3 +184,10 @@ def test_power_iteration_rejects_null_and_bad_counts():
     lam = ctypes.c_double()
     assert L.lib().l1ls_power_iteration(None, 0, 10, None, ctypes.byref(lam), None) == -1
     assert L.lib().l1ls_power_iteration(None, 0, 0, None, ctypes.byref(lam), None) == -1
+
+
+def test_set_allocator_rejects_missing_callbacks():
+    lib = L.lib()
+    spec = L.Allocator(L._ALLOC_FN(0), L._FREE_FN(0), None)
+    assert lib.l1ls_set_allocator(ctypes.byref(spec)) == -1
+    assert lib.l1ls_instance_bytes(None) == 0
