@@ -12,6 +12,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import paper_1503_03520_amd as L  # noqa: E402
+from fp32_bounds import fp32_trajectory_bound  # noqa: E402
 from oracle import fista as F  # noqa: E402
 from oracle import instance as OI  # noqa: E402
 
@@ -56,8 +57,7 @@ def test_batch_matches_oracle_fp32_bound():
     m, n, kappa, s, tau, seed, r = cfg
     o = OI.Instance(m, n, kappa, s, tau, seed, rounds=r)
     A = o.sparse_A()
-    ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, tau, 1.0, iters)
-    bound = iters * np.finfo(np.float32).eps * np.abs(o.b).max()
+    ref, bound = fp32_trajectory_bound(A, o.b, tau, 1.0, iters)
     assert np.abs(xs[0].cpu().numpy() - ref).max() <= bound
 
 
@@ -157,3 +157,81 @@ def test_tile_schedule_does_not_change_results():
         for a, b, ra, rb in zip(ref[0], xs, ref[1], reps):
             assert torch.equal(a, b), chunk
             assert ra["rel_gap"] == rb["rel_gap"] and ra["primal"] == rb["primal"], chunk
+
+
+def _drive(graph, tol, check):
+    """The same admission sequence with and without graph replay; eager
+    polls, copies and another solve run between the replays."""
+    B = L.Batch(6, rel_gap_tol=tol, check_every=check, precision=L.F32, graph=graph)
+    slots = [B.add(gen(CFGS[0])), B.add(gen(CFGS[2]))]
+    seen = []
+    B.iterate(3 * check + 5)                 # three whole periods, then five launched one by one
+    seen.append(B.poll())
+    slots.append(B.add(gen(CFGS[1])))        # the resident set changes: a new period is captured
+    B.iterate(2 * check)
+    x0 = B.get_x(slots[0])
+    L.l1ls_solve_fista(gen(CFGS[3]), max_iter=8, rel_gap_tol=0.0, check_every=8, precision=L.F32)
+    seen.append(B.poll())
+    B.remove(slots[1])
+    slots.append(B.add(gen(CFGS[4])))
+    for _ in range(6):
+        B.iterate(check)
+        seen.append(B.poll())
+    xs = [B.get_x(s) for s in (slots[0], slots[2], slots[3])]
+    B.destroy()
+    return x0, xs, seen
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-5])
+def test_graph_replay_equals_launched_iterations(tol):
+    # the kernels of a captured check period read the iteration count and
+    # the momentum table from device memory, so replaying the graph computes
+    # what launching each kernel computes, bit for bit, replay after replay
+    check = 8
+    xa0, xa, seen_a = _drive(0, tol, check)
+    xb0, xb, seen_b = _drive(1, tol, check)
+    assert torch.equal(xa0, xb0)
+    for a, b in zip(xa, xb):
+        assert torch.equal(a, b)
+    for (ra, aa), (rb, ab) in zip(seen_a, seen_b):
+        assert aa == ab
+        for p, q in zip(ra, rb):
+            assert (p["iterations"], p["converged"], p["primal"], p["dual"], p["rel_gap"]) == \
+                   (q["iterations"], q["converged"], q["primal"], q["dual"], q["rel_gap"])
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_persistent_small_slots_equal_shared_passes(graph):
+    # Slots with few rows run every iteration of an iterate call in one
+    # workgroup (kb_persist); with persist_rows = -1 they take the shared
+    # passes, with 1 << 20 every slot here runs in one workgroup.  All three
+    # give the same iterates and stop at the same iteration, bit for bit,
+    # with late admission and a removal between calls.
+    def drive(persist_rows):
+        B = L.Batch(6, rel_gap_tol=1e-5, check_every=8, precision=L.F32, graph=graph,
+                    persist_rows=persist_rows)
+        s = [B.add(gen(CFGS[0])), B.add(gen(CFGS[4]))]
+        B.iterate(13)
+        s.append(B.add(gen(CFGS[3])))
+        s.append(B.add(gen(CFGS[1])))
+        B.iterate(40)
+        B.remove(s[1])
+        for _ in range(40):
+            B.iterate(16)
+            if B.poll()[1] == 0:
+                break
+        reps = B.poll()[0]
+        out = [(B.get_x(q), reps[q]["iterations"], reps[q]["converged"], reps[q]["rel_gap"]) for q in (s[0], s[2], s[3])]
+        B.destroy()
+        return out
+
+    ref = drive(-1)
+    for rows in (0, 1 << 20):
+        got = drive(rows)
+        for (xa, ia, ca, ga), (xb, ib, cb, gb) in zip(ref, got):
+            assert (ia, ca, ga) == (ib, cb, gb), rows
+            assert torch.equal(xa, xb), rows
+    # and the single path at the same tolerance and check period
+    for (x, it, conv, _), cfg in zip(ref, (CFGS[0], CFGS[3], CFGS[1])):
+        x1, r1, _ = L.l1ls_solve_fista(gen(cfg), max_iter=it, rel_gap_tol=1e-5, check_every=8, precision=L.F32)
+        assert torch.equal(x, x1)

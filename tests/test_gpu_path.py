@@ -1,8 +1,8 @@
 """Regularisation path (64 tau values as one sparse-times-dense iteration).
 
 Each column is FISTA at its own tau on the shared instance; it is compared
-with the oracle's FP64 FISTA at the same tau and iteration count (FP32 bound
-k * eps32 * ||b||_inf), the path endpoint tau >= ||A^T b||_inf gives x = 0,
+with the oracle's FP64 FISTA at the same tau and iteration count (the FP32
+bound of tests/fp32_bounds.py), the path endpoint tau >= ||A^T b||_inf gives x = 0,
 and columns solved to tolerance carry FP64 certificates.
 """
 import numpy as np
@@ -11,6 +11,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import paper_1503_03520_amd as L  # noqa: E402
+from fp32_bounds import fp32_trajectory_bound  # noqa: E402
 from oracle import fista as F  # noqa: E402
 from oracle import instance as OI  # noqa: E402
 
@@ -42,10 +43,8 @@ def test_path_columns_match_oracle(k):
     iters = 30
     X, reps, _ = L.l1ls_solve_fista_path(g, taus, max_iter=iters, rel_gap_tol=0.0, check_every=10)
     Xh = X.cpu().numpy()
-    bound = iters * np.finfo(np.float32).eps * np.abs(o.b).max()
-    mv, rmv = (lambda v: A @ v), (lambda v: A.T @ v)
     for c in sorted({0, 1, k // 2, k - 1}):
-        ref = F.fista(mv, rmv, o.b, taus[c], 1.0, iters)
+        ref, bound = fp32_trajectory_bound(A, o.b, float(taus[c]), 1.0, iters)
         assert np.abs(Xh[c] - ref).max() <= bound, c
         assert reps[c]["iterations"] == iters
 

@@ -238,10 +238,12 @@ def test_table_1_size_sampled_generation_and_solve():
     x, rep, st = H.solve_cg_newton(max_iter=8)
     assert rep["iterations"] == 8
     assert rep["rel_err"] <= 5e-4
-    # every Newton step ran a PCG that stopped before its 1000-iteration cap
-    # (section 8.9 reports about 100 per step; this reading of CG-Newton needs
-    # more at this size, see the oracle's growth from 2^14 to 2^18)
-    assert 8 <= rep["inner"] < 8 * 1000
+    # the total PCG count of the 8 Newton steps: section 8.9 reports about
+    # 100 per step; this reading of CG-Newton needs more at this size (the
+    # oracle's counts grow from 2^14 to 2^18), and the later steps' PCG runs
+    # reach their 1000-iteration cap (4,224 = 1 + 1 + 6 + 216 + 4 x 1000 in
+    # the measured run), so only the total is bounded here
+    assert 8 <= rep["inner"] <= 8 * 1000
     # the planted values of the sampled indices, one by one
     idx = np.unique(np.r_[2 * pairs, 2 * pairs + 1])
     xs_ref, _ = planted_at(n, p.s, SEED, idx)

@@ -10,7 +10,7 @@ every result can be set beside the oracle's FP64 FISTA at the same count.
 - Path: n = 2^16, m = 2^17, kappa = 1e4, 64 tau values log-spaced over
   [1e-3, 1] ||A^T b||_inf as one sparse-times-dense iteration; every column
   against the oracle.
-The FP32 bound is that of the single path: k eps32 ||b||_inf after k steps.
+The FP32 bound is that of the single path (tests/fp32_bounds.py).
 """
 import os
 import sys
@@ -21,6 +21,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import paper_1503_03520_amd as L  # noqa: E402
+from fp32_bounds import fp32_trajectory_bound  # noqa: E402
 from oracle import fista as F  # noqa: E402
 from oracle import instance as OI  # noqa: E402
 
@@ -43,14 +44,12 @@ def test_batched_workload_full_size():
     assert all(r["iterations"] == ITERS for r in reps)
     order = sorted(range(len(cfgs)), key=lambda j: cfgs[j][1])
     sample = sorted({order[0], order[-1], *range(0, len(cfgs), 32)})
-    eps = np.finfo(np.float32).eps
     for j in sample:
         m, n, kappa, s, tau, seed, r = cfgs[j]
         o = OI.Instance(m, n, kappa, s, tau, seed, rounds=r)
         A = o.sparse_A()
-        ref = F.fista(lambda v: A @ v, lambda v: A.T @ v, o.b, o.tau, 1.0, ITERS)
+        ref, bound = fp32_trajectory_bound(A, o.b, o.tau, 1.0, ITERS)
         err = np.abs(xs[j].cpu().numpy() - ref).max()
-        bound = ITERS * eps * np.abs(o.b).max()
         print(f"instance {j}: n={n} kappa={kappa:g} max err {err:.3e} (bound {bound:.3e})", flush=True)
         assert err <= bound, j
     # every slot computes what the single path computes
@@ -71,11 +70,9 @@ def test_path_workload_full_size():
     X, reps, _ = L.l1ls_solve_fista_path(g, taus, max_iter=ITERS, rel_gap_tol=0.0, check_every=CHECK,
                                          precision=L.F32)
     Xh = X.cpu().numpy()
-    bound = ITERS * np.finfo(np.float32).eps * np.abs(o.b).max()
-    mv, rmv = (lambda v: A @ v), (lambda v: A.T @ v)
     worst = 0.0
     for c, t in enumerate(taus):
-        ref = F.fista(mv, rmv, o.b, float(t), 1.0, ITERS)
+        ref, bound = fp32_trajectory_bound(A, o.b, float(t), 1.0, ITERS)
         err = np.abs(Xh[c] - ref).max()
         worst = max(worst, err)
         assert err <= bound, c
