@@ -25,4 +25,6 @@ squares problems", arXiv:1503.03520, that it follows):
 * ``newton``    -- smoothed Newton-CG on the pseudo-Huber problem (8)
                    (section 2, section 8.1 item pdNCG, section 8.3 params).
 * ``polish``    -- FP64 support/sign polish on the reduced problem (13).
+* ``pcdm``      -- PCDM (section 8.1 item PCDM, beta of section 8.3) with
+                   tau-nice sampling on the generator's instances.
 """
