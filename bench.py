@@ -1,13 +1,17 @@
-"""Benchmark: FISTA iterations per second on the single large instance.
+"""Benchmark: FISTA iterations per second on the memory-scale instance.
 
-Workload: n = 2^20, m = 2^21, kappa = 1e4, two Givens stages per side,
-s = n/100, x* ~ N(0,1), tau = 1; FP32 bulk iteration on stored CSR + CSC
-(FP32 values, int32 indices), FP64 gap partials.  One step = one FISTA
+Workload (default): n = 2^26, m = 2^27, kappa = 1e6, two Givens stages per
+side, s = n/1000, x* ~ N(0,1), tau = 1; FP32 bulk iteration on stored CSR +
+CSC (FP32 values, int32 indices), FP64 gap partials.  One step = one FISTA
 iteration of the whole hot path: the CSR residual pass (A x - b with the
 momentum residual), the CSC transpose pass (A^T r, gradient step,
-soft-threshold prox, momentum) and the device-side duality-gap test every
-`--check-every` iterations.  All inputs are generated on the device before
-the timed region.
+soft-threshold prox, momentum) and, once per check period, the FP64 gap
+statistics and the device-side duality-gap test.  The check period divides
+both --warmup and --steps, so the timed window holds whole periods.  All
+inputs are generated on the device before the timed region.  The matrix-free
+and blocked operators, a certified solve (CG-Newton, then the FP64 polish),
+the single large instance (n = 2^20) and the small FP64 instance are
+reported under "extra".  Other workloads: --workload.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: the solver runs on one
 GPU.
@@ -22,7 +26,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "fista_stored_f32_n2p20.txt")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "fista_stored_f32_n2p26.txt")
+
+
+def profile_summary_path(n):
+    """The committed counter summary of the FISTA passes at size n."""
+    return os.path.join(ROOT, "profiles", "fista_stored_f32_n2p%d.txt" % (n.bit_length() - 1))
 KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp", "blocks.hip"]
 
 
@@ -62,30 +71,45 @@ def write_profile_summary(args):
                     return list(csv.DictReader(open(os.path.join(root, f))))
         raise SystemExit(f"no *{kind} under {d}")
 
-    names = {"residual": "k_residual<float>", "transpose_prox": "k_transpose_prox<float>", "gap": "k_gap",
+    names = {"residual": "k_residual<float", "transpose_prox": "k_transpose_prox<float",
              "blk_residual": "k_blk_residual<false>", "blk_transpose_prox": "k_blk_transpose_prox<false>",
              "mf_res_qt": "k_mf_res_qt<float, 2, 0, float>", "mf_prox_gt": "k_mf_prox_gt<float, 2>",
              "mf_win_scatter": "k_win_scatter<float>"}
-    stats = kernel_rows(args.kt, "kernel_stats.csv")
-    dur = {}
-    for key, pat in names.items():
-        for r in stats:
-            if pat in r["Name"]:
-                dur[key] = (float(r["AverageNs"]), int(r["Calls"]))
+    # The bench launches these kernels at the headline size and (in the
+    # n = 2^20 leg) at a smaller one: each figure is taken over the dispatches
+    # with the kernel's largest grid, the headline instance's.
+    trace = kernel_rows(args.kt, "kernel_trace.csv")
 
-    def counter(d, cname, pat):
+    def grid_of(r):
+        return int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+
+    dur = {}
+    big = {}
+    for key, pat in names.items():
+        rows = [r for r in trace if pat in r["Kernel_Name"]]
+        if not rows:
+            continue
+        g = max(grid_of(r) for r in rows)
+        rows = [r for r in rows if grid_of(r) == g]
+        ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+        dur[key] = (sum(ns) / len(ns), len(ns))
+        big[key] = g
+
+    def counter(d, cname, pat, grid=None):
         vals = [float(r["Counter_Value"]) for r in kernel_rows(d, "counter_collection.csv")
-                if pat in r["Kernel_Name"] and r["Counter_Name"] == cname]
+                if pat in r["Kernel_Name"] and r["Counter_Name"] == cname
+                and (grid is None or int(r.get("Grid_Size") or 0) == grid)]
         return statistics.median(vals), len(vals)
 
     copy_f, _ = counter(args.copyf, "FETCH_SIZE", "copyBuffer")
     copy_w, _ = counter(args.copyw, "WRITE_SIZE", "copyBuffer")
     gib_kib = float(1 << 20)            # the copy moves 1 GiB = 2^20 KiB each way
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
-    kt_cmd = args.kt_command or "python3 bench.py --steps 300 --warmup 30 --no-cpu-baseline"
-    pmc_cmd = args.pmc_command or "python3 bench.py --steps 40 --warmup 4 --no-cpu-baseline"
+    kt_cmd = args.kt_command or "python3 bench.py --steps 20 --warmup 5"
+    pmc_cmd = args.pmc_command or "python3 bench.py --steps 20 --warmup 5"
     lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator; "
-             "mf_*: the matrix-free operator, mf_win_scatter its windowed gathers' bucketing pass), FP32 bulk, " + (args.stats_title or "n=2^20, m=2^21, 2 stages"),
+             "mf_*: the matrix-free operator, mf_win_scatter its windowed gathers' bucketing pass), FP32 bulk, " + (args.stats_title or "n=2^26, m=2^27, 2 stages"),
+             "# each figure over the kernel's dispatches with its largest grid (the headline instance's launches)",
              f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- {kt_cmd}",
              f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
              f"{pmc_cmd}",
@@ -101,10 +125,9 @@ def write_profile_summary(args):
             continue  # not launched in this run (the windowed gathers' pass below n = 2^22)
         lines.append(f"{key}_avg_ns: {dur[key][0]:.0f}")
         lines.append(f"{key}_calls: {dur[key][1]}")
-        if key == "gap":
-            continue
-        fk, nf = counter(args.fetch, "FETCH_SIZE", pat)
-        wk, nw = counter(args.write, "WRITE_SIZE", pat)
+        lines.append(f"{key}_grid: {big[key]}")
+        fk, nf = counter(args.fetch, "FETCH_SIZE", pat, big[key])
+        wk, nw = counter(args.write, "WRITE_SIZE", pat, big[key])
         lines.append(f"{key}_fetch_kib_median: {fk:.1f}")
         lines.append(f"{key}_write_kib_median: {wk:.1f}")
         lines.append(f"{key}_traffic_bytes: {(fk * f_scale + wk * w_scale) * 1024:.0f}")
@@ -254,7 +277,7 @@ def bench_serve(args):
     reqs = serve_requests(args.requests + args.serve_warmup, 1503035204, args.serve_log2n_lo, args.serve_log2n_hi)
     warm, reqs = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
 
-    finish = args.serve_finish
+    finish = not args.serve_fp32_only
     storage = (L.STORE_F32 | L.STORE_F64) if finish else L.STORE_F32
 
     def plain_one(r):
@@ -336,6 +359,16 @@ def bench_serve(args):
         S.destroy()
         return [lat[i] for i in range(len(reqs))], span, conv, iters, peak
 
+    # the server's size classes (n < 2^14, n < 2^18, larger)
+    classes = [("n<2^14", 0, 1 << 14), ("2^14<=n<2^18", 1 << 14, 1 << 18), ("n>=2^18", 1 << 18, 1 << 62)]
+
+    def by_class(lat):
+        out = {}
+        for name, lo, hi in classes:
+            v = [lat[i] for i, r in enumerate(reqs) if lo <= r["n"] < hi]
+            out[name] = {"requests": len(v), "p50_s": _pct(v, 50), "p99_s": _pct(v, 99)}
+        return out
+
     results = []
     for mult in args.rate_mults:
         arr = arrivals(mult)
@@ -343,10 +376,11 @@ def bench_serve(args):
         ls, ss, conv_s, iters_s, peak = run_server(arr)
         row = {"rate_mult": mult, "rate_per_s": mult * mu,
                "server": {"solves_per_s": len(reqs) / ss, "p50_s": _pct(ls, 50), "p99_s": _pct(ls, 99),
-                          "converged": conv_s, "peak_resident": peak},
+                          "converged": conv_s, "peak_resident": peak, "by_size_class": by_class(ls)},
                }
         if lp is not None:
-            row["plain_fifo"] = {"solves_per_s": len(reqs) / sp, "p50_s": _pct(lp, 50), "p99_s": _pct(lp, 99)}
+            row["plain_fifo"] = {"solves_per_s": len(reqs) / sp, "p50_s": _pct(lp, 50), "p99_s": _pct(lp, 99),
+                                 "by_size_class": by_class(lp)}
         results.append(row)
         print(json.dumps({"progress": "serve", **row}), file=sys.stderr, flush=True)
         if args.serve_dump:
@@ -423,6 +457,23 @@ def bench_batched(args):
     xs, reps, _ = L.l1ls_solve_fista_batched(insts, **kw)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    # the same batch with every check period enqueued as one replayed HIP graph
+    L.l1ls_solve_fista_batched(insts, **dict(kw, max_iter=16, graph=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg, repg, _ = L.l1ls_solve_fista_batched(insts, **dict(kw, graph=1))
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    graph_same = sum(int(torch.equal(a, b)) for a, b in zip(xs, xg))
+    # the slots of at most 4096 rows (n <= 2048) running each call's
+    # iterations in one workgroup, beside the shared passes of the others
+    L.l1ls_solve_fista_batched(insts, **dict(kw, max_iter=16, persist_rows=4096))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xn, _, _ = L.l1ls_solve_fista_batched(insts, **dict(kw, persist_rows=4096))
+    torch.cuda.synchronize()
+    tn = time.perf_counter() - t0
+    shared_same = sum(int(torch.equal(a, b)) for a, b in zip(xs, xn))
     t0 = time.perf_counter()
     same, conv_p, iters_p = 0, 0, 0
     xp = []
@@ -446,6 +497,10 @@ def bench_batched(args):
                    "rel_gap_tol": args.batch_tol, "check_every": args.check_every,
                    "max_iter": args.batch_max_iter, "total_nnz": nnz},
         "extra": {"batched_s": tb, "plain_s": tp, "plain_solves_per_s": len(insts) / tp, "speedup": tp / tb,
+                  "graph": {"batched_s": tg, "solves_per_s": len(insts) / tg, "speedup_vs_launched": tb / tg,
+                            "bitwise_equal_to_launched": graph_same},
+                  "persistent_small_slots": {"persist_rows": 4096, "batched_s": tn, "solves_per_s": len(insts) / tn,
+                                             "bitwise_equal_to_default": shared_same},
                   "converged_batched": sum(r["converged"] == 1 for r in reps), "converged_plain": conv_p,
                   "iterations_batched": iters_b, "iterations_plain": iters_p,
                   "bitwise_equal_results": same},
@@ -493,6 +548,25 @@ def bench_path(args):
     gaps = []
     for c in range(len(taus)):
         gaps.append(L.l1ls_objective_gap(inst, taus[c], X[c].contiguous())[2])
+    # equal accuracy: every column finished in FP64 (the FP64 gap of the FP32
+    # result, the polish where it misses the tolerance), against single solves
+    # finished the same way
+    t0 = time.perf_counter()
+    Xf, repf, _ = L.l1ls_solve_fista_path(inst, taus, **dict(kw, polish=2))
+    torch.cuda.synchronize()
+    tpf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    conv_pf = 0
+    for t in taus:
+        x1, r1, _ = L.l1ls_solve_fista(inst, tau=t, polish=2, **kw)
+        conv_pf += r1["converged"] == 1
+    torch.cuda.synchronize()
+    tpf_plain = time.perf_counter() - t0
+    fp64_finish = {"path_s": tpf, "plain_s": tpf_plain, "speedup": tpf_plain / tpf,
+                   "columns_per_s": len(taus) / tpf,
+                   "converged_path_fp64": sum(r["converged"] == 1 for r in repf), "converged_plain_fp64": conv_pf,
+                   "polished_columns": sum(r["polish_rounds"] > 0 for r in repf),
+                   "fp64_gap_max": max(r["rel_gap"] for r in repf)}
     line = {
         "metric": "regularisation-path columns/sec (%d taus as one SpMM FISTA) vs single solves" % len(taus),
         "value": len(taus) / tpath, "unit": "solves/s", "n_gpus": 1, "steps": len(taus), "warmup": 1,
@@ -506,7 +580,7 @@ def bench_path(args):
                   "iterations_path_max": max(r["iterations"] for r in reps),
                   "iterations_path_sum": sum(r["iterations"] for r in reps), "iterations_plain_sum": iters_p,
                   "fp64_gap_max_converged": max([g for g, r in zip(gaps, reps) if r["converged"] == 1] or [0.0]),
-                  "fp64_gap_max": max(gaps)},
+                  "fp64_gap_max": max(gaps), "fp64_finish": fp64_finish},
     }
     print(json.dumps(line), flush=True)
 
@@ -803,15 +877,347 @@ def bench_grid(args):
     print(json.dumps(line), flush=True)
 
 
+# The two single-instance workloads of the FISTA bench: the memory-scale
+# instance (the headline) and the single large instance (reported beside it).
+FISTA_CONFIGS = {
+    "c3": dict(log2n=26, kappa=1e6, sdiv=1000, seed=1503035202,
+               name="memory-scale instance: n = 2^26, m = 2n, kappa = 1e6, 2 Givens stages, s = n/1000, tau = 1; "
+                    "FP32 bulk on stored CSR + CSC"),
+    "c2": dict(log2n=20, kappa=1e4, sdiv=100, seed=1503035201,
+               name="single large instance: n = 2^20, m = 2n, kappa = 1e4, 2 Givens stages, s = n/100, tau = 1; "
+                    "FP32 bulk on stored CSR + CSC"),
+}
+
+
+def check_period(steps, warmup, cap=32):
+    """Largest gap-check period <= cap that divides both the warm-up and the
+    timed iteration counts, so that the timed window is a whole number of
+    check periods (each ends with its gap evaluation)."""
+    import math
+    g = math.gcd(int(steps), int(warmup)) if warmup > 0 else int(steps)
+    for d in range(min(cap, max(g, 1)), 0, -1):
+        if g % d == 0:
+            return d
+    return 1
+
+
+def host_description():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "usable_cores": usable, "os_cpu_count": os.cpu_count()}
+
+
+def fista_legs(L, torch, inst, stream, steps, warmup, check, ops):
+    """FISTA on `inst` (FP32 bulk, gap test every `check` iterations, no
+    tolerance): per operator a plain run (HIP events around the whole window)
+    and a run with per-kernel HIP events, each after `warmup` untimed
+    iterations."""
+    def run(op, time_kernels):
+        fs = L.Fista(inst, precision=L.F32, rel_gap_tol=0.0, check_every=check, max_iter=warmup + steps,
+                     time_kernels=time_kernels, stream=stream, op=op)
+        fs.iterate(warmup)
+        torch.cuda.synchronize()
+        ms0, c0 = fs.kernel_times(5) if time_kernels else (None, None)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fs.iterate(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out = {"ms": e0.elapsed_time(e1)}
+        if time_kernels:
+            ms1, c1 = fs.kernel_times(5)
+            kms = [a - b for a, b in zip(ms1, ms0)]
+            kl = [a - b for a, b in zip(c1, c0)]
+            out["avg_ms"] = [kms[i] / max(kl[i], 1) for i in range(5)]
+            out["launches"] = kl
+        out["report"] = fs.report()
+        out["x"] = fs.get_x()
+        fs.destroy()
+        return out
+
+    res = {}
+    for op in ops:
+        plain = run(op, 0)
+        timed = run(op, 1)
+        res[op] = {"iters_per_s": steps / (plain["ms"] * 1e-3), "ms_per_step": plain["ms"] / steps,
+                   "avg_ms": timed["avg_ms"], "launches": timed["launches"], "x": plain["x"],
+                   "timed_window_ms_with_events": timed["ms"]}
+    return res
+
+
+def bench_fista(args):
+    """FISTA iterations per second on one instance; the headline is the
+    memory-scale instance (n = 2^26) on the stored FP32 CSR + CSC.  A step is
+    one FISTA iteration of the whole hot path: the CSR residual pass, the CSC
+    transpose pass with the prox step, and (every check period) the FP64 gap
+    statistics and the device-side gap test."""
+    import numpy as np
+    import torch
+
+    import paper_1503_03520_amd as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cfg = FISTA_CONFIGS[args.config]
+    n = 1 << (args.log2n if args.log2n else cfg["log2n"])
+    m = 2 * n
+    kappa, s, tau, seed, rounds = cfg["kappa"], max(1, n // cfg["sdiv"]), 1.0, cfg["seed"], 2
+    check = args.check_every if args.check_every else check_period(args.steps, args.warmup)
+
+    def progress(**kv):
+        print(json.dumps({"progress": kv}), file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    windows = n >= 1 << 22 and not args.no_windows
+    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream,
+                           storage=L.STORE_F32 | L.STORE_F64 | L.STORE_BLK32 | (L.STORE_WINDOWS if windows else 0))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    nnz = inst.info().nnz
+    progress(step="generated", n=n, nnz=nnz, seconds=gen_s, windowed_gathers=windows)
+
+    legs = fista_legs(L, torch, inst, stream, args.steps, args.warmup, check,
+                      (L.OP_STORED, L.OP_MATRIX_FREE, L.OP_BLOCKED))
+    st, mf, bl = legs[L.OP_STORED], legs[L.OP_MATRIX_FREE], legs[L.OP_BLOCKED]
+    progress(step="fista legs", stored=st["iters_per_s"], matrix_free=mf["iters_per_s"], blocked=bl["iters_per_s"])
+
+    k1_bytes, k2_bytes = algorithmic_bytes(m, n, nnz)
+    avg = st["avg_ms"]
+    dominant = 0 if avg[0] >= avg[1] else 1
+    dom_bytes = (k1_bytes, k2_bytes)[dominant]
+    achieved = dom_bytes / (avg[dominant] * 1e-3) / 1e9
+    pair_gbs = (k1_bytes + k2_bytes) / ((avg[0] + avg[1]) * 1e-3) / 1e9
+    key = ("residual", "transpose_prox")[dominant]
+    traffic = None
+    summ = read_profile_summary(profile_summary_path(n))
+    if summ and summ.get("kernel_source_hash") == kernel_source_hash() and f"{key}_traffic_bytes" in summ:
+        traffic = float(summ[f"{key}_traffic_bytes"])
+
+    xstar = torch.from_numpy(L.device_to_numpy(inst.info().x_star_dev, n, np.float64)).cuda()
+
+    def rel_err(x):
+        return float((x - xstar).norm() / xstar.norm())
+
+    P, D, gap = L.l1ls_objective_gap(inst, tau, st["x"])
+    b1, b2 = blocked_bytes(m, n, 4 * n)
+    bavg = bl["avg_ms"]
+    lam30 = L.l1ls_power_iteration(inst, 30, stream=stream)
+
+    # Certified solve (outside the timed window): CG-Newton on the
+    # matrix-free FP64 operator, then the FP64 polish of the reduced problem
+    # on the stored FP64 A; the result is compared with the planted x*.
+    t0 = time.perf_counter()
+    xc, rc, _ = L.l1ls_solve_cg_newton(inst, max_iter=args.newton_steps, rel_gap_tol=1e-12, precision=L.F64,
+                                       op=L.OP_MATRIX_FREE, polish=1, stream=stream)
+    torch.cuda.synchronize()
+    cert_s = time.perf_counter() - t0
+    certified = {"method": "CG-Newton (matrix-free FP64, %d Newton steps) + FP64 polish" % args.newton_steps,
+                 "seconds": cert_s, "newton_steps": rc["iterations"], "pcg_iterations": rc["inner"],
+                 "polish_rounds": rc["polish_rounds"], "rel_gap_fp64": rc["rel_gap"],
+                 "rel_err_planted": rc["rel_err"]}
+    progress(step="certified", **certified)
+    del xc
+    extra = {
+        "kernel_avg_us": {"residual": avg[0] * 1e3, "transpose_prox": avg[1] * 1e3, "gap": avg[2] * 1e3},
+        "kernel_launches_in_window": {"residual": st["launches"][0], "transpose_prox": st["launches"][1],
+                                      "gap": st["launches"][2]},
+        "spmv_pair_gbs": pair_gbs, "spmv_pair_frac": pair_gbs / HBM_PEAK_GBS,
+        "bytes_per_iter": k1_bytes + k2_bytes,
+        "algorithmic_bytes_per_launch": {"residual": k1_bytes, "transpose_prox": k2_bytes},
+        "generate_s": gen_s,
+        "fista_fp32_after_window": {"iterations": args.warmup + args.steps, "rel_gap_fp64": gap,
+                                    "rel_err_planted": rel_err(st["x"])},
+        "certified_solve": certified,
+        "lipschitz": {"closed_form": inst.info().L, "power_iteration_30_steps": lam30},
+        "matrix_free": {"iters_per_s": mf["iters_per_s"], "ms_per_step": mf["ms_per_step"],
+                        "kernel_avg_us": {k: mf["avg_ms"][i] * 1e3
+                                          for i, k in enumerate(("residual_pair", "transpose_pair", "gap"))},
+                        "bytes_per_iter": mf_bytes(m, n, windows=n >= 1 << 22),
+                        "bytes_per_iter_two_stage_model": 152 * n,
+                        "max_abs_diff_vs_stored": float((mf["x"] - st["x"]).abs().max())},
+        "blocked": {"iters_per_s": bl["iters_per_s"], "ms_per_step": bl["ms_per_step"],
+                    "kernel_avg_us": {"residual": bavg[0] * 1e3, "transpose_prox": bavg[1] * 1e3,
+                                      "gap": bavg[2] * 1e3},
+                    "algorithmic_gbs": {"residual": b1 / (bavg[0] * 1e-3) / 1e9,
+                                        "transpose_prox": b2 / (bavg[1] * 1e-3) / 1e9},
+                    "bytes_per_iter": b1 + b2,
+                    "max_abs_diff_vs_stored": float((bl["x"] - st["x"]).abs().max())},
+    }
+    if windows:
+        # the stored passes with their plain gathers, on the same instance
+        # built without the window tables
+        extra["bucketing_avg_us"] = {"x": avg[3] * 1e3, "r_y": avg[4] * 1e3}
+        extra["iteration_gbs"] = (k1_bytes + k2_bytes) / (st["ms_per_step"] * 1e-3) / 1e9
+        inst.free()
+        inst = None
+        torch.cuda.empty_cache()
+        p_inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream, storage=L.STORE_F32)
+        pl = fista_legs(L, torch, p_inst, stream, args.steps, args.warmup, check, (L.OP_STORED,))[L.OP_STORED]
+        extra["stored_plain_gathers"] = {
+            "iters_per_s": pl["iters_per_s"], "ms_per_step": pl["ms_per_step"],
+            "kernel_avg_us": {"residual": pl["avg_ms"][0] * 1e3, "transpose_prox": pl["avg_ms"][1] * 1e3,
+                              "gap": pl["avg_ms"][2] * 1e3},
+            "max_abs_diff_vs_windowed": float((pl["x"] - st["x"]).abs().max())}
+        p_inst.free()
+        progress(step="plain gathers", iters_per_s=pl["iters_per_s"])
+    for leg in legs.values():
+        leg.pop("x", None)
+    if inst is not None:
+        inst.free()
+    del xstar
+    torch.cuda.empty_cache()
+
+    if args.config == "c3" and not args.no_c2:
+        extra["c2"] = bench_c2_leg(L, torch, stream, args.steps, args.warmup, check)
+        progress(step="c2", iters_per_s=extra["c2"]["iters_per_s"])
+
+    # the small FP64 workload (n = 1024, m = 2048, kappa = 1e2, one stage,
+    # s = 10, tau = 1): latency-bound, solved to rel gap 1e-8, then polished
+    small = L.l1ls_generate(2048, 1024, 1e2, 10, 1.0, 1503035200, rounds=1, stream=stream)
+    L.l1ls_solve_fista(small, max_iter=64, rel_gap_tol=0.0, precision=L.F64, stream=stream)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, srep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
+                                    stream=stream)
+    torch.cuda.synchronize()
+    small_s = time.perf_counter() - t0
+    _, prep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
+                                    polish=1, stream=stream)
+    small.free()
+    extra["small_fp64"] = {"workload": "n=1024, m=2048, kappa=1e2, 1 stage, s=10, tau=1, FP64",
+                           "iterations_to_gap_1e-8": srep["iterations"], "seconds": small_s,
+                           "iters_per_s": srep["iterations"] / small_s, "rel_gap": srep["rel_gap"],
+                           "rel_err_planted": srep["rel_err"],
+                           "with_polish": {"seconds": prep["seconds"], "rel_gap": prep["rel_gap"],
+                                           "rel_err_planted": prep["rel_err"]}}
+    extra["host"] = host_description()
+    extra["autotuned_tile_schedule"] = {
+        "residual": L.tune_get("fista_f32_residual/%d" % (m - 1).bit_length()),
+        "transpose": L.tune_get("fista_f32_transpose/%d" % (n - 1).bit_length())}
+
+    value = st["iters_per_s"]
+    line = {
+        "metric": "FISTA iters/sec (SpMV pair A*y, A^T*r fused with prox, momentum, gap)",
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": st["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (instance generated on the device from the paper's generator, seed %d)" % seed,
+        "config": {"workload": cfg["name"] if n == 1 << cfg["log2n"] else cfg["name"] + " (n = 2^%d)" % n.bit_length(),
+                   "n": n, "m": m, "kappa": kappa, "givens_stages": rounds, "s": s, "tau": tau,
+                   "nnz": nnz, "check_every": check,
+                   "gap_checks_in_timed_window": st["launches"][2]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": ("k_residual (CSR A x - b + momentum residual)",
+                                "k_transpose_prox (CSC A^T r + prox)")[dominant],
+                     "algorithmic_bytes_per_launch": dom_bytes},
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_scaled(args, cfg, n, nnz)
+    print(json.dumps(line), flush=True)
+
+
+def bench_c2_leg(L, torch, stream, steps, warmup, check):
+    """The single large instance (n = 2^20) beside the headline: the stored
+    FP32 passes, and FP32 FISTA followed by the FP64 polish to a certified
+    gap."""
+    cfg = FISTA_CONFIGS["c2"]
+    n = 1 << cfg["log2n"]
+    m = 2 * n
+    inst = L.l1ls_generate(m, n, cfg["kappa"], n // cfg["sdiv"], 1.0, cfg["seed"], rounds=2, stream=stream,
+                           storage=L.STORE_F32 | L.STORE_F64)
+    nnz = inst.info().nnz
+    leg = fista_legs(L, torch, inst, stream, steps, warmup, check, (L.OP_STORED,))[L.OP_STORED]
+    k1, k2 = algorithmic_bytes(m, n, nnz)
+    avg = leg["avg_ms"]
+    pair = (k1 + k2) / ((avg[0] + avg[1]) * 1e-3) / 1e9
+    t0 = time.perf_counter()
+    _, rp, _ = L.l1ls_solve_fista(inst, max_iter=1000, rel_gap_tol=1e-8, check_every=32, precision=L.F32,
+                                  polish=1, stream=stream)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    inst.free()
+    return {"workload": cfg["name"], "nnz": nnz, "iters_per_s": leg["iters_per_s"], "ms_per_step": leg["ms_per_step"],
+            "kernel_avg_us": {"residual": avg[0] * 1e3, "transpose_prox": avg[1] * 1e3, "gap": avg[2] * 1e3},
+            "spmv_pair_gbs": pair, "spmv_pair_frac": pair / HBM_PEAK_GBS,
+            "certified_solve": {"method": "FP32 FISTA (at most 1000 iterations, gap test every 32) + FP64 polish",
+                                "seconds": ts, "fista_iterations": rp["iterations"], "polish_rounds": rp["polish_rounds"],
+                                "polish_pcg_iterations": rp["inner"], "rel_gap_fp64": rp["rel_gap"],
+                                "rel_err_planted": rp["rel_err"]}}
+
+
+def cpu_baseline_scaled(args, cfg, n, nnz):
+    """The oracle's FP64 FISTA on the host, on a bounded sample of the
+    workload: the same recipe (kappa, stages, s = n / sdiv) at n = 2^sample
+    (the instance built by the oracle, not timed), a fixed number of timed
+    iterations, and the rate scaled to the full instance by the ratio of the
+    stored nonzeros (both products are linear in nnz)."""
+    from oracle import fista as F
+    from oracle import instance as OI
+
+    ns = 1 << min(args.cpu_sample_log2n, n.bit_length() - 1)
+    ms_ = 2 * ns
+    t0 = time.perf_counter()
+    o = OI.Instance(ms_, ns, cfg["kappa"], max(1, ns // cfg["sdiv"]), 1.0, cfg["seed"], rounds=2)
+    A = o.sparse_A()
+    At = A.T.tocsr()
+    gen_s = time.perf_counter() - t0
+    mv, rmv = (lambda v: A @ v), (lambda v: At @ v)
+    t0 = time.perf_counter()
+    F.fista(mv, rmv, o.b, 1.0, o.L, 2)
+    per = (time.perf_counter() - t0) / 2
+    iters = max(3, min(args.cpu_iters, int(args.cpu_budget / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    F.fista(mv, rmv, o.b, 1.0, o.L, iters)
+    dt = time.perf_counter() - t0
+    rate = iters / dt
+    scale = A.nnz / float(nnz)
+    host = host_description()
+    return {"value": rate * scale, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} FP64 FISTA iterations of the CPU oracle (numpy + scipy.sparse products, one thread) "
+                      f"on the same recipe at n = 2^{ns.bit_length() - 1} (nnz {A.nnz}; instance built by the oracle "
+                      f"in {gen_s:.1f} s, not timed): {rate:.3f} iters/s there, scaled by nnz "
+                      f"{A.nnz}/{nnz} to the full instance",
+            "rate_at_sample": rate, "sample_n": ns, "host": host}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--check-every", type=int, default=32)
-    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="gap test period; 0: the largest period <= 32 dividing --steps and --warmup")
+    ap.add_argument("--config", default="c3", choices=sorted(FISTA_CONFIGS),
+                    help="fista workload: c3 the memory-scale instance (default), c2 the single large instance")
+    ap.add_argument("--log2n", type=int, default=0, help="fista workload: override log2(n) of --config")
+    ap.add_argument("--no-c2", action="store_true", help="fista workload: skip the n = 2^20 leg in extra")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="fista workload: stored passes with plain gathers only (no L1LS_STORE_WINDOWS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-sample-log2n", type=int, default=22)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (torch copy_) five times, to scale HBM counters")
     ap.add_argument("--profile-summary", action="store_true",
@@ -856,8 +1262,9 @@ def main():
     ap.add_argument("--serve-log2n-hi", type=int, default=22)
     ap.add_argument("--rate-mults", type=float, nargs="+", default=[0.7])
     ap.add_argument("--serve-dump", default=None, help="append per-request rows (JSON lines) to this file")
-    ap.add_argument("--serve-finish", action="store_true",
-                    help="FP64 finish: certify each result in FP64 and polish when it misses the tolerance")
+    ap.add_argument("--serve-fp32-only", action="store_true",
+                    help="serve FP32 results (no FP64 certificate or polish); the default finishes every "
+                         "result in FP64, as the plain path does")
     ap.add_argument("--plain-max-mult", type=float, default=1.0,
                     help="skip the real-time plain run above this rate multiple (its queue grows without bound)")
     args = ap.parse_args()
@@ -892,172 +1299,7 @@ def main():
          "large": bench_large, "table1": bench_table1, "grid": bench_grid}[args.workload](args)
         return
 
-    import numpy as np
-    import torch
-
-    import paper_1503_03520_amd as L
-
-    torch.cuda.set_device(0)
-    n = 1 << args.log2n
-    m = 2 * n
-    kappa, s, tau, seed, rounds = 1e4, max(1, n // 100), 1.0, 1503035201, 2
-    stream = torch.cuda.current_stream()
-    t0 = time.perf_counter()
-    inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream,
-                           storage=L.STORE_F32 | L.STORE_F64 | L.STORE_BLK32)
-    torch.cuda.synchronize()
-    gen_s = time.perf_counter() - t0
-    nnz = inst.info().nnz
-
-    def run(steps, warmup, time_kernels, op=L.OP_STORED):
-        fs = L.Fista(inst, precision=L.F32, rel_gap_tol=0.0, check_every=args.check_every,
-                     max_iter=warmup + steps, time_kernels=time_kernels, stream=stream, op=op)
-        fs.iterate(warmup)
-        torch.cuda.synchronize()
-        if time_kernels:
-            ms0, c0 = fs.kernel_times()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        fs.iterate(steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        out = {"ms": ms}
-        if time_kernels:
-            ms1, c1 = fs.kernel_times()
-            out["kernel_ms"] = [a - b for a, b in zip(ms1, ms0)]
-            out["kernel_launches"] = [a - b for a, b in zip(c1, c0)]
-        out["report"] = fs.report()
-        x = fs.get_x()
-        fs.destroy()
-        out["x"] = x
-        return out
-
-    plain = run(args.steps, args.warmup, 0)
-    timed = run(args.steps, args.warmup, 1)
-    # the same iteration over the matrix-free operator (rotation triplets
-    # applied on the fly), reported beside the stored-operator figure
-    mfree = run(args.steps, args.warmup, 0, op=L.OP_MATRIX_FREE)
-    mfree_t = run(args.steps, args.warmup, 1, op=L.OP_MATRIX_FREE)
-    # and over the blocked stored operator (runs of four stage positions)
-    blk = run(args.steps, args.warmup, 0, op=L.OP_BLOCKED)
-    blk_t = run(args.steps, args.warmup, 1, op=L.OP_BLOCKED)
-    b1, b2 = blocked_bytes(m, n, 4 * n)
-    bavg = [blk_t["kernel_ms"][i] / max(blk_t["kernel_launches"][i], 1) for i in range(3)]
-    bgap = L.l1ls_objective_gap(inst, tau, blk["x"])[2]
-    ms_per_step = plain["ms"] / args.steps
-    value = args.steps / (plain["ms"] / 1e3)
-
-    k1_bytes, k2_bytes = algorithmic_bytes(m, n, nnz)
-    kms, kl = timed["kernel_ms"], timed["kernel_launches"]
-    avg = [kms[i] / max(kl[i], 1) for i in range(3)]
-    dominant = 0 if kms[0] >= kms[1] else 1
-    dom_bytes = (k1_bytes, k2_bytes)[dominant]
-    achieved = dom_bytes / (avg[dominant] * 1e-3) / 1e9
-    pair_gbs = (k1_bytes + k2_bytes) / ((avg[0] + avg[1]) * 1e-3) / 1e9
-
-    # HBM traffic per launch from the committed counter summary, when it was
-    # taken on the kernels built from the current sources
-    traffic = None
-    summ = read_profile_summary()
-    key = ("residual", "transpose_prox")[dominant]
-    if summ and summ.get("kernel_source_hash") == kernel_source_hash() and f"{key}_traffic_bytes" in summ:
-        traffic = float(summ[f"{key}_traffic_bytes"])
-
-    blk_traffic = None
-    if summ and summ.get("kernel_source_hash") == kernel_source_hash():
-        if "blk_residual_traffic_bytes" in summ and "blk_transpose_prox_traffic_bytes" in summ:
-            blk_traffic = {"residual": float(summ["blk_residual_traffic_bytes"]),
-                           "transpose_prox": float(summ["blk_transpose_prox_traffic_bytes"])}
-
-    # FP64 certificate of the final iterate (outside the timed region)
-    P, D, gap = L.l1ls_objective_gap(inst, tau, plain["x"])
-    # distance to the planted minimiser (IGen makes x* optimal for the FP64 A)
-    xstar = torch.from_numpy(L.device_to_numpy(inst.info().x_star_dev, n, np.float64)).cuda()
-
-    def rel_err(x):
-        return float((x - xstar).norm() / xstar.norm())
-
-    # L: the closed form sigma_1^2 = 1 against 30 FP64 power-method steps
-    lam30 = L.l1ls_power_iteration(inst, 30, stream=stream)
-
-    # the small FP64 workload (n = 1024, m = 2048, kappa = 1e2, one stage,
-    # s = 10, tau = 1): a latency-bound regime, solved to rel gap 1e-8, then
-    # the FP64 polish
-    small = L.l1ls_generate(2048, 1024, 1e2, 10, 1.0, 1503035200, rounds=1, stream=stream)
-    L.l1ls_solve_fista(small, max_iter=64, rel_gap_tol=0.0, precision=L.F64, stream=stream)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, srep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
-                                    stream=stream)
-    torch.cuda.synchronize()
-    small_s = time.perf_counter() - t0
-    _, prep, _ = L.l1ls_solve_fista(small, max_iter=20000, rel_gap_tol=1e-8, check_every=32, precision=L.F64,
-                                    polish=1, stream=stream)
-    small.free()
-
-    line = {
-        "metric": "FISTA iters/sec (SpMV pair A*y, A^T*r fused with prox, momentum, gap)",
-        "value": value,
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (instance generated on the device from the paper's generator, seed %d)" % seed,
-        "config": {"workload": "single large instance, FP32 bulk on stored CSR+CSC",
-                   "n": n, "m": m, "kappa": kappa, "givens_stages": rounds, "s": s, "tau": tau,
-                   "nnz": nnz, "check_every": args.check_every},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("k_residual (CSR A x - b + momentum residual)",
-                                "k_transpose_prox (CSC A^T r + prox)")[dominant],
-                     "algorithmic_bytes_per_launch": dom_bytes},
-        "extra": {
-            "kernel_avg_us": {"residual": avg[0] * 1e3, "transpose_prox": avg[1] * 1e3, "gap": avg[2] * 1e3},
-            "spmv_pair_gbs": pair_gbs,
-            "bytes_per_iter": k1_bytes + k2_bytes,
-            "generate_s": gen_s,
-            "final_rel_gap_fp64": gap,
-            "final_rel_err_planted": rel_err(plain["x"]),
-            "lipschitz": {"closed_form": inst.info().L, "power_iteration_30_steps": lam30},
-            "small_fp64": {"workload": "n=1024, m=2048, kappa=1e2, 1 stage, s=10, tau=1, FP64",
-                           "iterations_to_gap_1e-8": srep["iterations"], "seconds": small_s,
-                           "iters_per_s": srep["iterations"] / small_s, "rel_gap": srep["rel_gap"],
-                           "rel_err_planted": srep["rel_err"],
-                           "with_polish": {"seconds": prep["seconds"], "rel_gap": prep["rel_gap"],
-                                           "rel_err_planted": prep["rel_err"]}},
-            "timed_ms_with_kernel_events": timed["ms"],
-            "matrix_free": {
-                "iters_per_s": args.steps / (mfree["ms"] / 1e3),
-                "ms_per_step": mfree["ms"] / args.steps,
-                "kernel_avg_us": {k: mfree_t["kernel_ms"][i] / max(mfree_t["kernel_launches"][i], 1) * 1e3
-                                  for i, k in enumerate(("residual_pair", "transpose_pair", "gap"))},
-                "bytes_per_iter": mf_bytes(m, n, windows=n >= 1 << 22),
-                "final_rel_err_planted": rel_err(mfree["x"]),
-            },
-            "blocked": {
-                "iters_per_s": args.steps / (blk["ms"] / 1e3),
-                "ms_per_step": blk["ms"] / args.steps,
-                "kernel_avg_us": {"residual": bavg[0] * 1e3, "transpose_prox": bavg[1] * 1e3,
-                                  "gap": bavg[2] * 1e3},
-                "algorithmic_gbs": {"residual": b1 / (bavg[0] * 1e-3) / 1e9,
-                                    "transpose_prox": b2 / (bavg[1] * 1e-3) / 1e9},
-                "bytes_per_iter": b1 + b2,
-                "final_rel_gap_fp64": bgap,
-                "final_rel_err_planted": rel_err(blk["x"]),
-                "traffic_per_launch": blk_traffic,
-            },
-        },
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(m, n, kappa, s, tau, seed, rounds, args.cpu_budget)
-    print(json.dumps(line), flush=True)
+    bench_fista(args)
 
 
 if __name__ == "__main__":

@@ -86,6 +86,19 @@ typedef enum { L1LS_LAYOUT_NATURAL = 0, L1LS_LAYOUT_STAGE = 1 } l1ls_layout;
  * memory: 4 (m + 5n) bytes for the tables, and the solvers' matrix-free
  * buffers hold the bucketed copies (n entries each). */
 #define L1LS_STORE_MF_WINDOWS 8u
+/* Windowed gathers for the stored FP32 FISTA passes (with L1LS_STORE_F32):
+ * the CSR pass gathers x, and the CSC pass r_y, at a few runs of four per
+ * row (column) at random places, a cache line per run once the vector
+ * outgrows the caches.  With this bit each pass's targets are grouped in
+ * windows (about 2^16 rows or 2^15 columns at two stages), and a bucketing
+ * pass before it copies the gathered vector so that each window's sources
+ * lie together (one copy per window that reads a source); the pass then
+ * gathers inside its window's segment, whose workgroups run on one XCD.
+ * Results are bitwise those of the plain passes.  Extra device memory:
+ * 4 bytes per stored entry for each pass's slot indices, 2 bytes per slot
+ * and the bucketed copies in the solver (about 4 n slots per pass at two
+ * stages), plus the run tables. */
+#define L1LS_STORE_WINDOWS 32u
 
 typedef struct {
     int32_t rounds;      /* Givens stages per side, 1 or 2 (nnz/col <= 4^rounds) */
@@ -250,9 +263,12 @@ typedef struct {
     /* Batch only: slots with at most this many rows run all of an iterate
      * call's iterations in one launch, one workgroup per slot (workgroup
      * barriers only), beside the shared passes of the larger slots; 0: the
-     * library's default (4096), -1: never.  The iterates are the same bit for
+     * library's default (none), -1: never.  The iterates are the same bit for
      * bit. */
     int32_t persist_rows;
+    /* l1ls_solve_pcdm only: coordinates updated together in a step (section
+     * 8.3's varpi), 1 <= varpi <= min(n, 1024); 0: 40. */
+    int32_t pcdm_tau_nice;
 } l1ls_solve_opts;
 
 typedef struct {
@@ -309,6 +325,28 @@ l1ls_status l1ls_solve_cg_newton(const l1ls_instance* inst, const l1ls_solve_opt
                                  double* x_out_dev, l1ls_report* report);
 
 /*
+ * PCDM (section 8.1 item PCDM, section 8.3) on the stored FP64 operator:
+ * step k updates varpi = opts.pcdm_tau_nice coordinates, each by the exact
+ * minimiser of its separable model at the current x,
+ *   x_i <- soft(x_i - A_i^T (A x - b) / (beta L_i), tau / (beta L_i)),
+ *   L_i = (A^T A)_ii, beta = 1 + (omega - 1)(varpi - 1)/(n - 1), omega the
+ *   largest number of nonzeros in a row of A,
+ * all from the same x (a synchronous step; the paper's cores update
+ * asynchronously), then keeps r = A x - b up to date on the rows those
+ * columns touch.  The varpi coordinates form a tau-nice sample: original
+ * indices pi_e((k mod q) varpi + j), j < varpi, e = k div q, q = n div varpi,
+ * with pi_e the generator's Feistel bijection of [0, n) under the instance's
+ * seed and counter tag 0x10000 + e.  From opts.x0_dev (NULL: 0).  Every
+ * opts.check_every steps (and at the end) the FP64 gap is evaluated; the
+ * solve stops when it is <= opts.rel_gap_tol (> 0) or after opts.max_iter
+ * steps (report.iterations).  Needs L1LS_STORE_F64, precision L1LS_F64, op
+ * L1LS_OP_STORED, polish 0 (else L1LS_E_UNSUPPORTED); L1LS_E_ARG for varpi
+ * outside [1, min(n, 1024)] or more than 65534 epochs.
+ */
+l1ls_status l1ls_solve_pcdm(const l1ls_instance* inst, const l1ls_solve_opts* opts, double* x_out_dev,
+                            l1ls_report* report);
+
+/*
  * lambda_max(A^T A), the Lipschitz constant L of the gradient of
  * 0.5 ||A x - b||^2 (section 8.1 uses it as the FISTA step 1/L), by the
  * power method in FP64: v_0 = v0_dev / ||v0_dev|| (n values in the original
@@ -341,6 +379,9 @@ l1ls_status l1ls_fista_get_x(l1ls_fista* st, double* x_out_dev);
  * create when opts.time_kernels = 1: [0] residual pass (CSR A x),
  * [1] transpose pass (CSC A^T r + prox), [2] gap evaluation. */
 l1ls_status l1ls_fista_kernel_times(l1ls_fista* st, double ms[3], int64_t launches[3]);
+/* The same for `count` slots (1..5): [3] the bucketing pass of x and [4] of
+ * r_y of the windowed stored passes (L1LS_STORE_WINDOWS; zero otherwise). */
+l1ls_status l1ls_fista_kernel_times_ex(l1ls_fista* st, int32_t count, double* ms, int64_t* launches);
 void l1ls_fista_destroy(l1ls_fista* st);
 
 /*
@@ -465,7 +506,12 @@ l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const do
  * tau on one instance at once, FP32 bulk over the stored operator, all
  * columns from x_0 = 0.  X_out_dev receives n x k FP64 values, column-major
  * (column c is the solution for taus[c], original order); reports[c] per
- * column.  opts: rel_gap_tol, max_iter, check_every, L, stream.
+ * column.  opts: rel_gap_tol, max_iter, check_every, L, stream, and polish:
+ * 0 returns the FP32 iterates with the device's gap; 2 finishes each column
+ * in FP64 at its tau (the FP64 gap of the FP32 result, the FP64 polish of the
+ * reduced problem (13) where it misses rel_gap_tol, then the FP64 gap of the
+ * result in reports[c]); 1 polishes every column.  polish needs
+ * L1LS_STORE_F64 (else L1LS_E_UNSUPPORTED).
  */
 l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus, int32_t k,
                                   const l1ls_solve_opts* opts, double* X_out_dev, l1ls_report* reports);
@@ -650,6 +696,23 @@ void l1ls_sgt_newton_destroy(l1ls_sgt_newton* newton);
  * l1ls_sgt_solve_fista: 0 the iteration pass, 1 the gap pass; after
  * l1ls_sgt_solve_pcdm: 0 the step pass. */
 l1ls_status l1ls_sgt_kernel_times(const l1ls_sgt* inst, double* ms, int64_t* calls);
+
+/*
+ * The autotuner's cache.  The library times its launch choices the first
+ * time it meets a size class (ceil(log2) of the rows) and keeps the fastest:
+ *   "fista_f32_residual/<class>", "fista_f32_transpose/<class>": the tile
+ *     schedule of the stored FP32 passes (0-3: entries per lane issued
+ *     together, 10/8/16/10 and 16/12/16/8, nontemporal index and value loads
+ *     in all but the residual's 3 and the transpose's 2);
+ *   "batch_rounds/<class>": rounds of four tiles per workgroup task (1, 2, 4, 8).
+ * Every choice computes the same values in the same order.  With the
+ * environment variable L1LS_TUNE_CACHE naming a file, the cache is read from
+ * it (JSON) on first use and written back after every new choice.
+ * get: the cached choice, -1 if none.  set: fix a choice (choice < 0
+ * forgets it; L1LS_E_ARG for a key with quotes, backslashes or newlines).
+ */
+int32_t l1ls_tune_get(const char* key);
+l1ls_status l1ls_tune_set(const char* key, int32_t choice);
 
 const char* l1ls_status_string(int32_t status);
 /* ABI version of this header (incremented on incompatible changes). */

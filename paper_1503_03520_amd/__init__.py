@@ -15,7 +15,7 @@ L1LS_OK = 0
 L1LS_NOT_CONVERGED = 1
 F32, F64 = 0, 1
 OP_STORED, OP_MATRIX_FREE, OP_BLOCKED = 0, 1, 2
-STORE_F32, STORE_F64, STORE_BLK32, STORE_MF_WINDOWS = 1, 2, 4, 8
+STORE_F32, STORE_F64, STORE_BLK32, STORE_MF_WINDOWS, STORE_WINDOWS = 1, 2, 4, 8, 32
 REQ_FP64_FINISH = 1
 SIGMA_ALTERNATING, SIGMA_UNIFORM = 0, 1
 XSTAR_TABLE1, XSTAR_OSGEN, XSTAR_OSGEN3 = 0, 1, 2
@@ -64,7 +64,7 @@ class SolveOpts(ctypes.Structure):
         ("mu", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("max_backtrack", ctypes.c_int32),
         ("pcg_maxit", ctypes.c_int32), ("hessian", ctypes.c_int32), ("tile_chunk", ctypes.c_int32),
         ("f_target", ctypes.c_double), ("pcdm_p", ctypes.c_double), ("graph", ctypes.c_int32),
-        ("persist_rows", ctypes.c_int32),
+        ("persist_rows", ctypes.c_int32), ("pcdm_tau_nice", ctypes.c_int32),
     ]
 
 
@@ -136,12 +136,15 @@ _SIGS = {
     "l1ls_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "l1ls_solve_fista": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_solve_cg_newton": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
+    "l1ls_solve_pcdm": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(Report)]),
     "l1ls_fista_create": (ctypes.c_int, [_P, ctypes.POINTER(SolveOpts), ctypes.POINTER(_P)]),
     "l1ls_fista_iterate": (ctypes.c_int, [_P, ctypes.c_int64]),
     "l1ls_fista_report": (ctypes.c_int, [_P, ctypes.POINTER(Report)]),
     "l1ls_fista_get_x": (ctypes.c_int, [_P, _P]),
     "l1ls_fista_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_int64)]),
+    "l1ls_fista_kernel_times_ex": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_int64)]),
     "l1ls_fista_destroy": (None, [_P]),
     "l1ls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(SolveOpts),
                                          ctypes.POINTER(_P)]),
@@ -188,6 +191,8 @@ _SIGS = {
     "l1ls_sgt_newton_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(Report)]),
     "l1ls_sgt_newton_destroy": (None, [_P]),
     "l1ls_sgt_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "l1ls_tune_get": (ctypes.c_int32, [ctypes.c_char_p]),
+    "l1ls_tune_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32]),
     "l1ls_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "l1ls_version": (ctypes.c_int32, []),
 }
@@ -396,6 +401,11 @@ def l1ls_solve_cg_newton(inst, x_out=None, **kw):
     return _solve(lib().l1ls_solve_cg_newton, "l1ls_solve_cg_newton", inst, x_out, kw)
 
 
+def l1ls_solve_pcdm(inst, x_out=None, **kw):
+    kw.setdefault("precision", F64)
+    return _solve(lib().l1ls_solve_pcdm, "l1ls_solve_pcdm", inst, x_out, kw)
+
+
 class Fista:
     """The stepping interface (l1ls_fista_create / iterate / report / get_x)."""
 
@@ -423,10 +433,10 @@ class Fista:
         _check(lib().l1ls_fista_get_x(self._h, _ptr(x_out)), "l1ls_fista_get_x")
         return x_out
 
-    def kernel_times(self):
-        ms = (ctypes.c_double * 3)()
-        cnt = (ctypes.c_int64 * 3)()
-        _check(lib().l1ls_fista_kernel_times(self._h, ms, cnt), "l1ls_fista_kernel_times")
+    def kernel_times(self, slots=3):
+        ms = (ctypes.c_double * slots)()
+        cnt = (ctypes.c_int64 * slots)()
+        _check(lib().l1ls_fista_kernel_times_ex(self._h, slots, ms, cnt), "l1ls_fista_kernel_times_ex")
         return list(ms), list(cnt)
 
     def destroy(self):
@@ -782,3 +792,12 @@ class SgtNewton:
             self.destroy()
         except Exception:
             pass
+
+
+def tune_get(key):
+    """The autotuner's cached choice for `key` (l1ls_tune_get), -1 if none."""
+    return int(lib().l1ls_tune_get(key.encode()))
+
+
+def tune_set(key, choice):
+    _check(lib().l1ls_tune_set(key.encode(), int(choice)), "l1ls_tune_set")

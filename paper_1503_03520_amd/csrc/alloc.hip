@@ -41,7 +41,7 @@ l1ls_status lib_alloc(void** p, size_t bytes) {
     return L1LS_OK;
 }
 
-void lib_free(void* p, size_t bytes) {
+void lib_free(void* p, size_t bytes, bool synced) {
     if (!p) return;
     const Source* src = nullptr;
     {
@@ -58,7 +58,8 @@ void lib_free(void* p, size_t bytes) {
     }
     // hipFree waits for the device before it releases a block; a caller's
     // allocator may hand the block to another stream at once, so wait here
-    (void)hipDeviceSynchronize();
+    // (unless the caller just did)
+    if (!synced) (void)hipDeviceSynchronize();
     src->a.free(src->a.ctx, p, bytes);
 }
 

@@ -19,10 +19,12 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 using namespace l1ls;
 
@@ -45,7 +47,8 @@ struct BInst {  // static per slot (device copy refreshed on add/remove)
     double tau, L, tol;
     int32_t nt1, nt2;
     int32_t check_every, active;
-    int32_t admit_mod, pad2;  // admit mod check_every
+    int32_t admit_mod;  // admit mod check_every
+    int32_t persist;    // 1: the slot's iterations run in kb_persist (one workgroup), not in the shared passes
 };
 
 struct BState {  // written by the gap kernel only
@@ -137,10 +140,15 @@ template <bool ONE>
 __global__ __launch_bounds__(L1LS_BLOCK, ONE ? 7 : 5) void kb_transpose(const BTask* __restrict__ tasks,
                                                            const BInst* __restrict__ bi,
                                                            const BState* __restrict__ bs,
-                                                           const float* __restrict__ btab, int64_t G, int gmod) {
+                                                           const float* __restrict__ btab,
+                                                           const int64_t* __restrict__ dG, int64_t Gh, int ce) {
     __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
+    // the iteration this launch runs: from the device count (graph replays)
+    // or from the argument (launched one by one)
+    const int64_t G = (dG ? *dG : Gh) + 1;
+    const int gmod = (int)(G % ce);
     const BTask tk = tasks[blockIdx.x];
     const BInst& I = bi[tk.slot];
     int64_t kn = 0;
@@ -214,11 +222,15 @@ template <bool ONE>
 __global__ __launch_bounds__(L1LS_BLOCK, 8) void kb_residual(const BTask* __restrict__ tasks,
                                                           const BInst* __restrict__ bi,
                                                           const BState* __restrict__ bs,
-                                                          const float* __restrict__ btab, int64_t G, int gmod,
+                                                          const float* __restrict__ btab,
+                                                          const int64_t* __restrict__ dG, int64_t Gh, int ce,
                                                           int mode) {
     __shared__ float lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
+    // as kb_transpose; mode 1 (first passes) runs at the current count G
+    const int64_t G = (dG ? *dG : Gh) + (mode == 1 ? 0 : 1);
+    const int gmod = (int)(G % ce);
     const BTask tk = tasks[blockIdx.x];
     const BInst& I = bi[tk.slot];
     int64_t kn = 0;
@@ -243,14 +255,10 @@ __global__ __launch_bounds__(L1LS_BLOCK, 8) void kb_residual(const BTask* __rest
                       lds[wid], lane);
 }
 
-// One workgroup per slot: the duality gap on the slot's check iterations
-// (the terms of k_gap, from the slot's own partials in tile order).
-__global__ __launch_bounds__(1024) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs, int64_t G,
-                                              int gmod) {
-    const BInst& I = bi[blockIdx.x];
-    BState& S = bs[blockIdx.x];
-    int64_t kn = 0;
-    if (!slot_live(I, S, G, &kn) || slot_phase(I, gmod) != 0) return;  // block-uniform
+// The duality gap of one slot at its iteration kn (a check iteration), by a
+// workgroup of 1024 threads: the terms of k_gap, from the slot's own partials
+// in tile order.
+__device__ __forceinline__ void slot_gap(const BInst& I, BState& S, int64_t kn) {
     const double* cur = I.part1 + (size_t)(kn & 1) * 3 * I.nt1;
     const double* prev = I.part1 + (size_t)((kn - 1) & 1) * 3 * I.nt1;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rr, ryy, bry, l1 | ginf
@@ -283,6 +291,63 @@ __global__ __launch_bounds__(1024) void kb_gap(const BInst* __restrict__ bi, BSt
         S.stop_iter = kn;
     }
 }
+
+// One workgroup per slot: the gap on the slot's check iterations (slots run
+// by kb_persist take their gap there).
+__global__ __launch_bounds__(1024) void kb_gap(const BInst* __restrict__ bi, BState* __restrict__ bs,
+                                              const int64_t* __restrict__ dG, int64_t Gh, int ce) {
+    const int64_t G = (dG ? *dG : Gh) + 1;
+    const int gmod = (int)(G % ce);
+    const BInst& I = bi[blockIdx.x];
+    BState& S = bs[blockIdx.x];
+    int64_t kn = 0;
+    if (I.persist || !slot_live(I, S, G, &kn) || slot_phase(I, gmod) != 0) return;  // block-uniform
+    slot_gap(I, S, kn);
+}
+
+// Small slots, one workgroup of 16 waves each: `iters` global iterations
+// G0 + 1 .. G0 + iters (G0: the count when the call began) in one
+// launch, the passes separated by workgroup barriers only.  Wave w takes
+// tiles w, w + 16, ... of each pass: every tile computes exactly what it
+// computes in the shared passes (the same tile functions, the same per-tile
+// partials), and the gap uses the 1024-thread reduction of kb_gap, so the
+// iterates and the stopping iteration are bit for bit the single path's.
+// All writes a pass makes are read by the next pass of the same workgroup,
+// which the barrier orders.
+__global__ __launch_bounds__(1024) void kb_persist(const int32_t* __restrict__ slots, const BInst* __restrict__ bi,
+                                                  BState* __restrict__ bs, const float* __restrict__ btab,
+                                                  int64_t G0, int ce, int64_t iters) {
+    __shared__ float lds[1024 / L1LS_WAVE][kTile * kMaxNnz];
+    const int lane = threadIdx.x % L1LS_WAVE;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / L1LS_WAVE);
+    constexpr int W = 1024 / L1LS_WAVE;
+    const int slot = slots[blockIdx.x];
+    const BInst& I = bi[slot];
+    BState& S = bs[slot];
+    const float Lf = (float)I.L, thr = (float)(I.tau / I.L);
+    const int r2 = (int)((I.nt2 + W - 1) / W), r1 = (int)((I.nt1 + W - 1) / W);
+    for (int64_t q = 1; q <= iters; ++q) {
+        const int64_t G = G0 + q;
+        int64_t kn = 0;
+        if (!slot_live(I, S, G, &kn)) break;  // uniform: S.done is written before the last barrier
+        const int ph = slot_phase(I, (int)(G % ce));
+        const float bt = btab[kn - 1];
+        for (int st = 0; st < r2; ++st)
+            transpose_tile(I.csc_ptr, I.csc_row, I.csc_val, I.ry, I.x[(kn - 1) & 1], I.x[kn & 1], I.part2, I.n,
+                           (int64_t)(st * W + wid) * kTile, bt, Lf, thr, ph == 0, true, lds[wid], lane);
+        const float br = btab[kn];
+        double* part1 = I.part1 + (size_t)(kn & 1) * I.nt1 * 3;
+        for (int st = 0; st < r1; ++st)
+            residual_tile(I.csr_ptr, I.csr_col, I.csr_val, I.x[kn & 1], I.b, I.rx, I.ry, part1, I.m,
+                          (int64_t)(st * W + wid) * kTile, br, 0, ph == 0 || ph == ce - 1, true, lds[wid], lane);
+        if (ph == 0) slot_gap(I, S, kn);
+        __syncthreads();
+    }
+}
+
+// End of a global iteration: the device's count G moves on (the kernels of
+// the next iteration read it).
+__global__ void kb_tick(int64_t* __restrict__ dG, int64_t by) { *dG += by; }
 
 __global__ void kb_zero(float* __restrict__ a, int64_t N) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,15 +385,28 @@ struct l1ls_batch {
     std::vector<void*> buf;                   // per-slot device block (iterates + partials)
     BInst* dinst = nullptr;
     BState* dstate = nullptr;
-    BTask* dt1 = nullptr;                     // residual-pass tasks
-    BTask* dt2 = nullptr;                     // transpose-pass tasks
-    int32_t cap1 = 0, cap2 = 0, nt1 = 0, nt2 = 0;
+    BTask* dt1 = nullptr;                     // residual-pass tasks of every slot (the first passes)
+    BTask* dt1i = nullptr;                    // residual-pass tasks of the shared-pass slots (iterations)
+    BTask* dt2 = nullptr;                     // transpose-pass tasks of the shared-pass slots
+    int32_t cap1 = 0, cap1i = 0, cap2 = 0, nt1 = 0, nt1i = 0, nt2 = 0;
+    int32_t* dsmall = nullptr;                // slots run by kb_persist
+    int32_t nsmall = 0, capsmall = 0;
+    hipStream_t side = nullptr;               // kb_persist runs here, beside the shared passes
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int32_t> steps;               // per slot: rounds per task (tile schedule)
     bool one = true;                          // every task has one round
     float* btab = nullptr;                    // beta_k, k = 0 .. nbeta-1
     int64_t nbeta = 0;
     bool tables_dirty = false, init_pending = false;
     DevAlloc* al = nullptr;                   // source of the slot blocks (nullptr: hipMalloc)
+    int64_t* dG = nullptr;                    // device copy of G (the kernels read it; kb_tick advances it)
+    // Graph mode (opts.graph): one check period of iterations captured once
+    // per task table and replayed; cap_stream is the capture stream.
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t graph_replays = 0;
+    int64_t persist_rows = 0;                 // slots with m <= this run in kb_persist (0: none)
     DevArena arena;
 };
 
@@ -342,20 +420,21 @@ size_t slot_bytes(int64_t m, int64_t n) {
     return slot_fbytes(m, n) + (size_t)(6 * tiles_of(m) + 2 * tiles_of(n)) * sizeof(double);
 }
 
-// ---- tile-schedule autotuner ------------------------------------------------
-// Rounds per task for a slot, by the size class ceil(log2(m)): on the first
-// slot of a class in the process, its first residual pass (r = A x_0 - b,
-// which the batch computes anyway) is timed with 1, 2, 4 and 8 rounds per
-// task and the fastest is kept for the class.
-constexpr int kStepChoices[4] = {1, 2, 4, 8};
-std::mutex g_sched_mu;
-std::map<int, int32_t> g_sched;  // size class -> rounds per task
+void drop_graph(l1ls_batch* B);
 
-int size_class(int64_t rows) {
-    int c = 0;
-    while (((int64_t)1 << c) < rows) ++c;
-    return c;
-}
+// Slots of at most this many rows run their iterations in one workgroup
+// (kb_persist) unless opts.persist_rows says otherwise.  Off by default: on
+// the 256-instance workload the shared passes were faster (7,446 against
+// 7,285 solves/s with m <= 4096 in one workgroup).
+constexpr int64_t kPersistRows = 0;
+
+// ---- tile-schedule autotuner ------------------------------------------------
+// Rounds per task for a slot, by the size class ceil(log2(m)): unless the
+// autotuner cache (tune.hpp, key batch_rounds/<class>) holds a choice, the
+// first residual pass of the class's first slot (r = A x_0 - b, which the
+// batch computes anyway) is timed with 1, 2, 4 and 8 rounds per task and the
+// fastest is kept.
+constexpr int kStepChoices[4] = {1, 2, 4, 8};
 
 void push_tasks(std::vector<BTask>& out, int slot, int64_t rows, int32_t steps) {
     const int64_t per = (int64_t)4 * steps * kTile;  // rows per task
@@ -386,10 +465,10 @@ l1ls_status tune_steps(l1ls_batch* B, int slot, int32_t* best) {
             if (rep == 1) (void)hipEventRecord(e0, B->stream);
             if (kStepChoices[c] == 1)
                 hipLaunchKernelGGL(kb_residual<true>, dim3((unsigned)t.size()), dim3(L1LS_BLOCK), 0, B->stream, dt,
-                                   B->dinst, B->dstate, B->btab, B->G, 0, 1);
+                                   B->dinst, B->dstate, B->btab, (const int64_t*)nullptr, B->G, B->o.check_every, 1);
             else
                 hipLaunchKernelGGL(kb_residual<false>, dim3((unsigned)t.size()), dim3(L1LS_BLOCK), 0, B->stream, dt,
-                                   B->dinst, B->dstate, B->btab, B->G, 0, 1);
+                                   B->dinst, B->dstate, B->btab, (const int64_t*)nullptr, B->G, B->o.check_every, 1);
         }
         (void)hipEventRecord(e1, B->stream);
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -409,7 +488,8 @@ l1ls_status tune_steps(l1ls_batch* B, int slot, int32_t* best) {
 l1ls_status rebuild_tables(l1ls_batch* B) {
     HIP_TRY(hipMemcpyAsync(B->dinst, B->hinst.data(), B->capacity * sizeof(BInst), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
-    std::vector<BTask> t1, t2;
+    std::vector<BTask> t1, t1i, t2;
+    std::vector<int32_t> small;
     for (int s = 0; s < B->capacity; ++s) {
         if (!B->inst[s]) continue;
         const BInst& hi = B->hinst[s];
@@ -417,42 +497,54 @@ l1ls_status rebuild_tables(l1ls_batch* B) {
             if (B->o.tile_chunk > 0) {
                 B->steps[s] = B->o.tile_chunk;
             } else {
-                const int cls = size_class(hi.m);
-                int32_t v = 0;
-                {
-                    std::lock_guard<std::mutex> lk(g_sched_mu);
-                    auto it = g_sched.find(cls);
-                    if (it != g_sched.end()) v = it->second;
-                }
-                if (v == 0 && hi.admit == B->G) {  // a fresh slot: its first pass can be timed
+                const std::string key = "batch_rounds/" + std::to_string(tune_size_class(hi.m));
+                int32_t v = tune_lookup(key);
+                if (v <= 0 && hi.admit == B->G) {  // a fresh slot: its first pass can be timed
                     L1LS_TRY(tune_steps(B, s, &v));
-                    std::lock_guard<std::mutex> lk(g_sched_mu);
-                    g_sched[cls] = v;
+                    tune_store(key, v);
                 }
                 B->steps[s] = v > 0 ? v : 1;
             }
         }
         push_tasks(t1, s, hi.m, B->steps[s]);
-        push_tasks(t2, s, hi.n, B->steps[s]);
+        if (hi.persist) {
+            small.push_back(s);
+        } else {
+            push_tasks(t1i, s, hi.m, B->steps[s]);
+            push_tasks(t2, s, hi.n, B->steps[s]);
+        }
     }
-    if ((int32_t)t1.size() > B->cap1 || (int32_t)t2.size() > B->cap2) {
-        // grow the task tables (old ones stay in the arena until destroy)
-        B->cap1 = std::max<int32_t>((int32_t)t1.size(), 2 * B->cap1);
-        B->cap2 = std::max<int32_t>((int32_t)t2.size(), 2 * B->cap2);
-        L1LS_TRY(B->arena.alloc(&B->dt1, B->cap1));
-        L1LS_TRY(B->arena.alloc(&B->dt2, B->cap2));
+    auto grow = [&](BTask** d, int32_t* cap, size_t need) -> l1ls_status {
+        if ((int32_t)need <= *cap) return L1LS_OK;
+        *cap = std::max<int32_t>((int32_t)need, 2 * *cap);  // old tables stay in the arena until destroy
+        return B->arena.alloc(d, (size_t)*cap);
+    };
+    L1LS_TRY(grow(&B->dt1, &B->cap1, t1.size()));
+    L1LS_TRY(grow(&B->dt1i, &B->cap1i, t1i.size()));
+    L1LS_TRY(grow(&B->dt2, &B->cap2, t2.size()));
+    if ((int32_t)small.size() > B->capsmall) {
+        B->capsmall = std::max<int32_t>((int32_t)small.size(), 2 * B->capsmall);
+        L1LS_TRY(B->arena.alloc(&B->dsmall, (size_t)B->capsmall));
     }
     B->nt1 = (int32_t)t1.size();
+    B->nt1i = (int32_t)t1i.size();
     B->nt2 = (int32_t)t2.size();
+    B->nsmall = (int32_t)small.size();
     B->one = true;
     for (const BTask& t : t1) B->one = B->one && t.steps == 1;
     if (!t1.empty())
         HIP_TRY(hipMemcpyAsync(B->dt1, t1.data(), t1.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream));
+    if (!t1i.empty())
+        HIP_TRY(hipMemcpyAsync(B->dt1i, t1i.data(), t1i.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream));
     if (!t2.empty())
         HIP_TRY(hipMemcpyAsync(B->dt2, t2.data(), t2.size() * sizeof(BTask), hipMemcpyHostToDevice, B->stream));
+    if (!small.empty())
+        HIP_TRY(hipMemcpyAsync(B->dsmall, small.data(), small.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               B->stream));
     // the copies read host vectors that go out of scope: wait for them
     HIP_TRY(hipStreamSynchronize(B->stream));
     B->tables_dirty = false;
+    drop_graph(B);  // a captured period names the old task tables
     return L1LS_OK;
 }
 
@@ -473,6 +565,7 @@ l1ls_status ensure_beta(l1ls_batch* B, int64_t need) {
     HIP_TRY(hipMemcpyAsync(d, h.data(), (size_t)len * sizeof(float), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
     B->btab = d;
+    drop_graph(B);  // and the old beta table
     B->nbeta = len;
     return L1LS_OK;
 }
@@ -481,10 +574,10 @@ l1ls_status run_init(l1ls_batch* B) {
     if (B->nt1 > 0) {
         if (B->one)
             hipLaunchKernelGGL(kb_residual<true>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
-                               B->dstate, B->btab, B->G, 0, 1);
+                               B->dstate, B->btab, (const int64_t*)nullptr, B->G, B->o.check_every, 1);
         else
             hipLaunchKernelGGL(kb_residual<false>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
-                               B->dstate, B->btab, B->G, 0, 1);
+                               B->dstate, B->btab, (const int64_t*)nullptr, B->G, B->o.check_every, 1);
         HIP_TRY(hipGetLastError());
     }
     B->init_pending = false;
@@ -516,11 +609,14 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     if (opts->precision != L1LS_F32 || opts->op != L1LS_OP_STORED) return L1LS_E_UNSUPPORTED;
     if (opts->check_every < 1 || !(opts->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
     if (opts->tile_chunk < 0 || opts->tile_chunk > 64) return L1LS_E_ARG;
+    if (opts->graph != 0 && opts->graph != 1) return L1LS_E_ARG;
+    if (opts->persist_rows < -1) return L1LS_E_ARG;
     l1ls_batch* B = new l1ls_batch();
     B->capacity = capacity;
     B->budget = hbm_budget_bytes;
     B->stream = (hipStream_t)opts->stream;
     B->o = *opts;
+    B->persist_rows = opts->persist_rows < 0 ? 0 : (opts->persist_rows > 0 ? opts->persist_rows : kPersistRows);
     B->inst.assign(capacity, nullptr);
     B->hinst.assign(capacity, BInst{});
     B->footprint.assign(capacity, 0);
@@ -534,7 +630,9 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     l1ls_status st;
     if ((st = B->arena.alloc(&B->dinst, capacity)) != L1LS_OK) return fail(st);
     if ((st = B->arena.alloc(&B->dstate, capacity)) != L1LS_OK) return fail(st);
+    if ((st = B->arena.alloc(&B->dG, 1)) != L1LS_OK) return fail(st);
     if ((st = ensure_beta(B, 4096)) != L1LS_OK) return fail(st);
+    if (hipMemsetAsync(B->dG, 0, sizeof(int64_t), B->stream) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipMemsetAsync(B->dstate, 0, capacity * sizeof(BState), B->stream) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipMemsetAsync(B->dinst, 0, capacity * sizeof(BInst), B->stream) != hipSuccess) return fail(L1LS_E_HIP);
     if (hipStreamSynchronize(B->stream) != hipSuccess) return fail(L1LS_E_HIP);
@@ -601,6 +699,7 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     h.check_every = B->o.check_every;
     h.admit_mod = (int32_t)(B->G % B->o.check_every);
     h.active = 1;
+    h.persist = (B->persist_rows > 0 && m <= B->persist_rows) ? 1 : 0;
     B->inst[slot] = I;
     B->buf[slot] = blk;
     B->footprint[slot] = fp;
@@ -620,12 +719,70 @@ extern "C" l1ls_status l1ls_batch_add(l1ls_batch* B, const l1ls_instance* I, dou
     return l1ls_batch_add_ex(B, I, tau, -1.0, 0, slot_out);
 }
 
+namespace {
+
+// The kernels of one global iteration of the shared-pass slots on `s`:
+// transpose pass, residual pass, the gap kernel (when `gap`; it returns at
+// once for slots not at a check iteration) and the step of the device's G.
+void enqueue_iteration(l1ls_batch* B, hipStream_t s, bool gap, bool graph) {
+    const int ce = B->o.check_every;
+    // graph replays read the count from the device (kb_tick advances it);
+    // launched iterations take it as an argument (host G before the step)
+    const int64_t* dG = graph ? B->dG : nullptr;
+    const int64_t Gh = B->G;
+    if (B->nt1i > 0) {
+        if (B->one) {
+            hipLaunchKernelGGL(kb_transpose<true>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, s, B->dt2, B->dinst,
+                               B->dstate, B->btab, dG, Gh, ce);
+            hipLaunchKernelGGL(kb_residual<true>, dim3(B->nt1i), dim3(L1LS_BLOCK), 0, s, B->dt1i, B->dinst,
+                               B->dstate, B->btab, dG, Gh, ce, 0);
+        } else {
+            hipLaunchKernelGGL(kb_transpose<false>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, s, B->dt2, B->dinst,
+                               B->dstate, B->btab, dG, Gh, ce);
+            hipLaunchKernelGGL(kb_residual<false>, dim3(B->nt1i), dim3(L1LS_BLOCK), 0, s, B->dt1i, B->dinst,
+                               B->dstate, B->btab, dG, Gh, ce, 0);
+        }
+        if (gap) hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(1024), 0, s, B->dinst, B->dstate, dG, Gh, ce);
+    }
+    if (graph) hipLaunchKernelGGL(kb_tick, dim3(1), dim3(1), 0, s, B->dG, (int64_t)1);
+}
+
+void drop_graph(l1ls_batch* B) {
+    if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->gexec = nullptr;
+    B->graph = nullptr;
+}
+
+// Capture one check period of iterations (every one with the gap kernel:
+// which iterations are check iterations moves with G) on the capture stream.
+// Kernel arguments are the task tables, the beta table and the device G, so
+// the graph stays valid until one of those is replaced.
+l1ls_status capture_period(l1ls_batch* B) {
+    drop_graph(B);
+    if (!B->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < B->o.check_every; ++q) enqueue_iteration(B, B->cap_stream, true, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+    if (e != hipSuccess || !g) return L1LS_E_HIP;
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    return L1LS_OK;
+}
+
+}  // namespace
+
 extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {
     if (!B || iters < 0) return L1LS_E_ARG;
     if (B->tables_dirty) L1LS_TRY(rebuild_tables(B));
     if (B->init_pending) L1LS_TRY(run_init(B));
-    if (B->nt1 == 0) {
-        B->G += iters;  // nothing resident: the count still advances
+    if (iters == 0) return L1LS_OK;
+    const bool graph = B->o.graph != 0;
+    if (B->nt1 == 0) {  // nothing resident: the count still advances (on the device too in graph mode)
+        if (graph) hipLaunchKernelGGL(kb_tick, dim3(1), dim3(1), 0, B->stream, B->dG, iters);
+        B->G += iters;
+        HIP_TRY(hipGetLastError());
         return L1LS_OK;
     }
     // the beta table must reach the largest k any slot can take; the gap
@@ -639,23 +796,42 @@ extern "C" l1ls_status l1ls_batch_iterate(l1ls_batch* B, int64_t iters) {
             phase[(size_t)(B->hinst[s].admit % ce)] = 1;
         }
     L1LS_TRY(ensure_beta(B, B->G + iters - oldest + 2));
-    for (int64_t q = 0; q < iters; ++q) {
-        const int64_t G = ++B->G;
-        const int gmod = (int)(G % ce);
-        if (B->one) {
-            hipLaunchKernelGGL(kb_transpose<true>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->dinst,
-                               B->dstate, B->btab, G, gmod);
-            hipLaunchKernelGGL(kb_residual<true>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
-                               B->dstate, B->btab, G, gmod, 0);
-        } else {
-            hipLaunchKernelGGL(kb_transpose<false>, dim3(B->nt2), dim3(L1LS_BLOCK), 0, B->stream, B->dt2, B->dinst,
-                               B->dstate, B->btab, G, gmod);
-            hipLaunchKernelGGL(kb_residual<false>, dim3(B->nt1), dim3(L1LS_BLOCK), 0, B->stream, B->dt1, B->dinst,
-                               B->dstate, B->btab, G, gmod, 0);
+    if (B->nsmall > 0) {
+        // the small slots: all `iters` iterations in one launch on the side
+        // stream, beside the shared passes; the stream joins at the end
+        if (!B->side) {
+            HIP_TRY(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
         }
-        if (phase[(size_t)gmod])
-            hipLaunchKernelGGL(kb_gap, dim3(B->capacity), dim3(1024), 0, B->stream, B->dinst, B->dstate, G, gmod);
+        HIP_TRY(hipEventRecord(B->ev_fork, B->stream));
+        HIP_TRY(hipStreamWaitEvent(B->side, B->ev_fork, 0));
+        hipLaunchKernelGGL(kb_persist, dim3(B->nsmall), dim3(1024), 0, B->side, (const int32_t*)B->dsmall, B->dinst,
+                           B->dstate, B->btab, B->G, (int)ce, iters);
+        HIP_TRY(hipEventRecord(B->ev_join, B->side));
     }
+    if (graph && B->nt1i > 0) {
+        // whole check periods by graph replay, the rest launched one by one
+        // (the device count follows G in graph mode)
+        while (iters >= ce) {
+            if (!B->gexec) L1LS_TRY(capture_period(B));
+            HIP_TRY(hipGraphLaunch(B->gexec, B->stream));
+            B->G += ce;
+            B->graph_replays += 1;
+            iters -= ce;
+        }
+    }
+    if (B->nt1i > 0) {
+        for (int64_t q = 0; q < iters; ++q) {
+            const int gmod = (int)((B->G + 1) % ce);
+            enqueue_iteration(B, B->stream, phase[(size_t)gmod] != 0, graph);
+            ++B->G;
+        }
+    } else {
+        if (graph) hipLaunchKernelGGL(kb_tick, dim3(1), dim3(1), 0, B->stream, B->dG, iters);
+        B->G += iters;
+    }
+    if (B->nsmall > 0) HIP_TRY(hipStreamWaitEvent(B->stream, B->ev_join, 0));
     HIP_TRY(hipGetLastError());
     return L1LS_OK;
 }
@@ -718,8 +894,16 @@ extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
 extern "C" void l1ls_batch_destroy(l1ls_batch* B) {
     if (!B) return;
     (void)hipStreamSynchronize(B->stream);
+    if (B->side) (void)hipStreamSynchronize(B->side);
+    (void)hipDeviceSynchronize();  // one wait for all the slot blocks
     for (int s = 0; s < B->capacity; ++s)
-        if (B->buf[s]) dev_free(B->al, B->buf[s], slot_bytes(B->hinst[s].m, B->hinst[s].n));
+        if (B->buf[s]) dev_free(B->al, B->buf[s], slot_bytes(B->hinst[s].m, B->hinst[s].n), true);
+    drop_graph(B);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    if (B->side) (void)hipStreamSynchronize(B->side);
+    if (B->side) (void)hipStreamDestroy(B->side);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    if (B->ev_join) (void)hipEventDestroy(B->ev_join);
     B->arena.release();
     delete B;
 }

@@ -47,8 +47,9 @@ struct DevAlloc {
 // Device memory of the process-wide source (alloc.hip): the allocator
 // installed with l1ls_set_allocator, else hipMalloc / hipFree.  lib_free
 // returns a block to whichever source made it.
+// synced: the caller has waited for the device since the block's last use.
 l1ls_status lib_alloc(void** p, size_t bytes);
-void lib_free(void* p, size_t bytes);
+void lib_free(void* p, size_t bytes, bool synced = false);
 
 inline l1ls_status dev_alloc(DevAlloc* al, void** p, size_t bytes) {
     *p = nullptr;
@@ -56,12 +57,12 @@ inline l1ls_status dev_alloc(DevAlloc* al, void** p, size_t bytes) {
     return lib_alloc(p, bytes);
 }
 
-inline void dev_free(DevAlloc* al, void* p, size_t bytes) {
+inline void dev_free(DevAlloc* al, void* p, size_t bytes, bool synced = false) {
     if (!p) return;
     if (al)
         al->free(p, bytes);
     else
-        lib_free(p, bytes);
+        lib_free(p, bytes, synced);
 }
 
 // Device allocation list owned by one object; freed in reverse order.
@@ -79,7 +80,9 @@ struct DevArena {
         return L1LS_OK;
     }
     void release() {
-        for (size_t i = ptrs.size(); i-- > 0;) dev_free(al, ptrs[i].first, ptrs[i].second);
+        // one wait for the device covers every block (hipFree would wait once per block)
+        if (!al && !ptrs.empty()) (void)hipDeviceSynchronize();
+        for (size_t i = ptrs.size(); i-- > 0;) dev_free(al, ptrs[i].first, ptrs[i].second, true);
         ptrs.clear();
     }
 };
@@ -165,6 +168,22 @@ struct l1ls_instance {
     int32_t* blk_cstart = nullptr;  // 4n
     float* blk_cval = nullptr;    // 4 per run
     int64_t blk_nruns = 0;
+    // Windowed gathers of the stored FP32 passes (L1LS_STORE_WINDOWS; see
+    // window.hip).  [0]: the CSR pass's gather of x (row windows), [1]: the
+    // CSC pass's gather of r_y (column windows).  sw_idx[k] replaces the
+    // CSR column (CSC row) indices by slots of the bucketed copy u_k, which
+    // holds, window after window and chunk after chunk, one copy of each
+    // source element a window reads; sw_src[k][slot] = offset of the slot's
+    // source in its chunk; the run of window w and chunk c spans slots
+    // [sw_start[k][c nT + w], sw_end[k][c nT + w]) (runs are window-major in u).
+    int32_t* sw_idx[2] = {nullptr, nullptr};
+    uint16_t* sw_src[2] = {nullptr, nullptr};
+    int32_t* sw_start[2] = {nullptr, nullptr};
+    int32_t* sw_end[2] = {nullptr, nullptr};
+    int64_t sw_slots[2] = {0, 0};
+    int64_t sw_nT[2] = {0, 0};
+    int64_t sw_nc[2] = {0, 0};
+    int sw_cs[2] = {0, 0};
     DevArena arena;
 };
 

@@ -2,13 +2,16 @@
 // exact soft-threshold step of section 2, t_k momentum), the stepping API,
 // operator products and the FP64 duality gap of problem (1).
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 using namespace l1ls;
 
@@ -34,6 +37,8 @@ l1ls_status apply_blocked(const l1ls_instance* I, int trans, const float* in, fl
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
 bool fista_onchip_fits(const l1ls_instance* I, const l1ls_solve_opts* o);
+void stored_window_scatter(const l1ls_instance* I, int k, const float* src, float* u, const int32_t* done,
+                           hipStream_t s);
 l1ls_status fista_onchip_run(const l1ls_instance* I, const l1ls_solve_opts* o, double tau, double L, double* x_out,
                              l1ls_report* rep);
 
@@ -153,8 +158,10 @@ struct l1ls_fista {
     const int32_t* col_pos = nullptr;  // original index -> position
     double* k1part = nullptr;  // [2][g1][3], slot k & 1 written by the residual pass of iteration k
     double* k2part = nullptr;  // [g2][2]
+    double* gstage = nullptr;  // [kGapStages][5]: first stage of the gap sums on large grids
     GapState* gs = nullptr;
     int g1 = 0, g2 = 0;
+    int vres = 0, vtr = 0;     // tile-schedule variants of the stored FP32 passes (autotuned)
     int64_t k = 0;             // iterations enqueued
     double t_k = 1.0;          // t_k for the next iteration k+1 (t_1 = 1)
     double beta_prev = 0.0;    // beta_{k-1}
@@ -162,8 +169,13 @@ struct l1ls_fista {
     // kernel timing
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-    double ms[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t launches[5] = {0, 0, 0, 0, 0};
+    // windowed stored passes (L1LS_STORE_WINDOWS): the bucketed copies of x
+    // and r_y the passes gather from
+    bool sw = false;
+    float* ux = nullptr;
+    float* uy = nullptr;
     DevArena arena;
 };
 
@@ -238,9 +250,138 @@ const float* mf_b<float>(const l1ls_instance* I) { return I->mf_b32; }
 template <>
 const double* mf_b<double>(const l1ls_instance* I) { return I->mf_b64; }
 
+// Tile schedules of the stored passes (kernels.hpp: entries per lane issued
+// together, nontemporal index/value loads).  Every variant computes the same
+// values in the same order; FP64 always takes variant 0.
+constexpr int kResVariants = 4;  // (10, nt), (8, nt), (16, nt), (10, plain)
+constexpr int kTrVariants = 4;   // (16, nt), (12, nt), (16, plain), (8, nt)
+
+template <typename T, int NQ, bool NT>
+void residual_go(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
+    const l1ls_instance* I = F->I;
+    hipLaunchKernelGGL((k_residual<T, NQ, NT>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr, I->csr_col,
+                       csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
+                       F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
+}
+
+template <typename T>
+void residual_variant(l1ls_fista* F, int v, const T* x, double beta, int init, int slot, int stats) {
+    if constexpr (std::is_same<T, float>::value) {
+        switch (v) {
+            case 1: return residual_go<float, 8, true>(F, x, beta, init, slot, stats);
+            case 2: return residual_go<float, 16, true>(F, x, beta, init, slot, stats);
+            case 3: return residual_go<float, 10, false>(F, x, beta, init, slot, stats);
+            default: break;
+        }
+    }
+    residual_go<T, 10, true>(F, x, beta, init, slot, stats);
+}
+
+template <typename T, int NQ, bool NT>
+void transpose_go(l1ls_fista* F, const T* xc, T* xp, double beta, int stats) {
+    const l1ls_instance* I = F->I;
+    hipLaunchKernelGGL((k_transpose_prox<T, NQ, NT>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream, I->csc_ptr,
+                       I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L, (T)(F->tau / F->L),
+                       I->n, F->k2part, F->gs, stats);
+}
+
+template <typename T>
+void transpose_variant(l1ls_fista* F, int v, const T* xc, T* xp, double beta, int stats) {
+    if constexpr (std::is_same<T, float>::value) {
+        switch (v) {
+            case 1: return transpose_go<float, 12, true>(F, xc, xp, beta, stats);
+            case 2: return transpose_go<float, 16, false>(F, xc, xp, beta, stats);
+            case 3: return transpose_go<float, 8, true>(F, xc, xp, beta, stats);
+            default: break;
+        }
+    }
+    transpose_go<T, 16, true>(F, xc, xp, beta, stats);
+}
+
+// The autotuner's choice for the stored FP32 passes of an instance of this
+// size: taken from the cache, or measured now (each variant of the first
+// residual pass, which the solver runs anyway and which only depends on x_0,
+// and of the transpose pass into a scratch copy of x_0: one warm-up and
+// three timed launches each, fastest kept) and cached per size class.
+l1ls_status tune_fista_f32(l1ls_fista* F) {
+    const l1ls_instance* I = F->I;
+    const std::string kr = "fista_f32_residual/" + std::to_string(tune_size_class(I->m));
+    const std::string kt = "fista_f32_transpose/" + std::to_string(tune_size_class(I->n));
+    int vr = tune_lookup(kr), vt = tune_lookup(kt);
+    if (vr >= 0 && vt >= 0) {
+        F->vres = vr < kResVariants ? vr : 0;
+        F->vtr = vt < kTrVariants ? vt : 0;
+        return L1LS_OK;
+    }
+    DevArena tmp;
+    float* xs = nullptr;
+    L1LS_TRY(tmp.alloc(&xs, I->n));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_it = [&](auto&& launch, float* best_ms, int v, int* best) -> l1ls_status {
+        launch();  // warm-up
+        float ms = 0.f, mn = 0.f;
+        for (int r = 0; r < 3; ++r) {
+            HIP_TRY(hipEventRecord(e0, F->stream));
+            launch();
+            HIP_TRY(hipEventRecord(e1, F->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            mn = (r == 0) ? ms : std::min(mn, ms);
+        }
+        if (*best < 0 || mn < *best_ms) {
+            *best_ms = mn;
+            *best = v;
+        }
+        return L1LS_OK;
+    };
+    l1ls_status st = L1LS_OK;
+    const float* x0 = (const float*)F->x[0];
+    if (vr < 0) {
+        float bms = 0.f;
+        for (int v = 0; v < kResVariants && st == L1LS_OK; ++v)
+            st = time_it([&] { residual_variant<float>(F, v, x0, 0.0, 1, 0, 1); }, &bms, v, &vr);
+    }
+    if (vt < 0 && st == L1LS_OK) {
+        float bms = 0.f;
+        for (int v = 0; v < kTrVariants && st == L1LS_OK; ++v)
+            st = time_it([&] {
+                (void)hipMemcpyAsync(xs, x0, I->n * sizeof(float), hipMemcpyDeviceToDevice, F->stream);
+                transpose_variant<float>(F, v, x0, xs, 0.0, 1);
+            }, &bms, v, &vt);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(F->stream);
+    tmp.release();
+    if (st != L1LS_OK) return st;
+    tune_store(kr, vr);
+    tune_store(kt, vt);
+    F->vres = vr;
+    F->vtr = vt;
+    return L1LS_OK;
+}
+
+const int32_t* done_flag(l1ls_fista* F) {
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(F->gs) + offsetof(GapState, done));
+}
+
 template <typename T>
 l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
     const l1ls_instance* I = F->I;
+    if constexpr (std::is_same<T, float>::value) {
+        if (F->sw) {
+            // bucket x_k by row window, then the CSR pass over the bucketed copy
+            L1LS_TRY(timed(F, 3, [&] { stored_window_scatter(I, 0, x, F->ux, done_flag(F), F->stream); }));
+            return timed(F, 0, [&] {
+                hipLaunchKernelGGL((k_residual<float, 10, true, true>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream,
+                                   I->csr_ptr, I->sw_idx[0], I->csr_v32, (const float*)F->ux, I->b32_op,
+                                   (float*)F->rx, (float*)F->ry, (float)beta, I->m, init,
+                                   F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
+            });
+        }
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (F->blk)
             return timed(F, 0, [&] {
@@ -255,17 +396,24 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
             mf_residual_launch<T>(I, x, (T*)F->wbuf, mf_b<T>(I), rx_prev, rx_out, (T*)F->tbuf, (T)beta, init,
                                   F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats, F->stream);
         });
-    return timed(F, 0, [&] {
-        hipLaunchKernelGGL((k_residual<T>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr,
-                           I->csr_col, csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
-                           F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
-    });
+    return timed(F, 0, [&] { residual_variant<T>(F, F->vres, x, beta, init, slot, stats); });
 }
 
 // xp holds x_{k-2}; x_k goes to xo (== xp for the stored passes).
 template <typename T>
 l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double beta, int stats) {
     const l1ls_instance* I = F->I;
+    if constexpr (std::is_same<T, float>::value) {
+        if (F->sw) {
+            // bucket r_y by column window, then the CSC pass over the bucketed copy
+            L1LS_TRY(timed(F, 4, [&] { stored_window_scatter(I, 1, (const float*)F->ry, F->uy, done_flag(F), F->stream); }));
+            return timed(F, 1, [&] {
+                hipLaunchKernelGGL((k_transpose_prox<float, 16, true, true>), dim3(F->g2), dim3(L1LS_BLOCK), 0,
+                                   F->stream, I->csc_ptr, I->sw_idx[1], I->csc_v32, (const float*)F->uy, xc, xp,
+                                   (float)beta, (float)F->L, (float)(F->tau / F->L), I->n, F->k2part, F->gs, stats);
+            });
+        }
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (F->blk)
             return timed(F, 1, [&] {
@@ -278,11 +426,27 @@ l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double be
             mf_transpose_launch<T>(I, (T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
                                    (T)(F->tau / F->L), F->k2part, F->gs, stats, F->stream);
         });
-    return timed(F, 1, [&] {
-        hipLaunchKernelGGL((k_transpose_prox<T>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream,
-                           I->csc_ptr, I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L,
-                           (T)(F->tau / F->L), I->n, F->k2part, F->gs, stats);
-    });
+    return timed(F, 1, [&] { transpose_variant<T>(F, F->vtr, xc, xp, beta, stats); });
+}
+
+// Gap test at iteration k from the partials of its passes: one workgroup
+// over all partials, or two stages once the grids hold more than
+// kGapTwoStage partials (one workgroup reading them all would take longer
+// than the passes' share it is meant to be).
+constexpr int kGapTwoStage = 16384;
+
+void launch_gap(l1ls_fista* F, int64_t k, double tol) {
+    const double* cur = F->k1part + (size_t)(k & 1) * 3 * F->g1;
+    const double* prev = F->k1part + (size_t)((k - 1) & 1) * 3 * F->g1;
+    if (F->g1 + F->g2 <= kGapTwoStage) {
+        hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream, cur, prev, F->g1, F->k2part, F->g2,
+                           F->tau, tol, k, F->gs);
+        return;
+    }
+    hipLaunchKernelGGL(k_gap_stage, dim3(kGapStages), dim3(kGapThreads), 0, F->stream, cur, prev, F->g1, F->k2part,
+                       F->g2, F->gstage, (const GapState*)F->gs);
+    hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapThreads), 0, F->stream, (const double*)F->gstage, F->tau, tol, k,
+                       F->gs);
 }
 
 template <typename T>
@@ -305,14 +469,7 @@ l1ls_status fista_iterate_t(l1ls_fista* F, int64_t iters) {
         const int st1 = (k % check == 0 || (k + 1) % check == 0 || last || k + 1 == F->stats_until) ? 1 : 0;
         L1LS_TRY(launch_transpose<T>(F, xcur, xprev, xslot, F->beta_prev, st2));
         L1LS_TRY(launch_residual<T>(F, xslot, beta_k, 0, (int)(k & 1), st1));
-        if (k % check == 0) {
-            L1LS_TRY(timed(F, 2, [&] {
-                hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
-                                   F->k1part + (size_t)(k & 1) * 3 * F->g1,
-                                   F->k1part + (size_t)((k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2,
-                                   F->tau, tol, k, F->gs);
-            }));
-        }
+        if (k % check == 0) L1LS_TRY(timed(F, 2, [&] { launch_gap(F, k, tol); }));
         F->beta_prev = beta_k;
         F->t_k = t_next;
         F->k = k;
@@ -379,6 +536,7 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     F->L = L;
     F->mf = (opts->op == L1LS_OP_MATRIX_FREE);
     F->blk = (opts->op == L1LS_OP_BLOCKED);
+    F->sw = (opts->op == L1LS_OP_STORED && opts->precision == L1LS_F32 && I->sw_idx[0] && I->sw_idx[1]);
     F->g1 = F->mf ? mf_grid(I->m / 2) : F->blk ? blk_row_blocks(I->m) : tile_grid(I->m);
     F->g2 = F->mf ? mf_grid(I->n / 2) : F->blk ? blk_col_blocks(I->n) : tile_grid(I->n);
     F->col_of = F->mf ? I->side[0].perm : I->op_col_of;
@@ -419,8 +577,13 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
         F->wbuf = wb;
         F->tbuf = tb;
     }
+    if (F->sw) {
+        if ((st = F->arena.alloc(&F->ux, std::max<int64_t>(I->sw_slots[0], 1))) != L1LS_OK) return fail(st);
+        if ((st = F->arena.alloc(&F->uy, std::max<int64_t>(I->sw_slots[1], 1))) != L1LS_OK) return fail(st);
+    }
     if ((st = F->arena.alloc(&F->k1part, (size_t)2 * 3 * F->g1)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&F->k2part, (size_t)2 * F->g2)) != L1LS_OK) return fail(st);
+    if ((st = F->arena.alloc(&F->gstage, (size_t)5 * kGapStages)) != L1LS_OK) return fail(st);
     if ((st = F->arena.alloc(&F->gs, 1)) != L1LS_OK) return fail(st);
     F->x[0] = x0;
     F->x[1] = x1;
@@ -449,6 +612,11 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
         return fail(L1LS_E_HIP);
     if (F->x[2] && hipMemcpyAsync(F->x[2], x0, I->n * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(L1LS_E_HIP);
+    hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
+    // stored FP32 passes: the autotuner's tile schedule (the timing runs only
+    // the first residual pass and the transpose pass into scratch; the state
+    // is set up again just below)
+    if (F->prec == L1LS_F32 && !F->mf && !F->blk && !F->sw && (st = tune_fista_f32(F)) != L1LS_OK) return fail(st);
     hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
     if (F->prec == L1LS_F64)
         st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0, 1);
@@ -506,6 +674,16 @@ extern "C" l1ls_status l1ls_fista_kernel_times(l1ls_fista* F, double ms[3], int6
     if (!F || !ms || !launches) return L1LS_E_ARG;
     L1LS_TRY(drain_events(F));
     for (int i = 0; i < 3; ++i) {
+        ms[i] = F->ms[i];
+        launches[i] = F->launches[i];
+    }
+    return L1LS_OK;
+}
+
+extern "C" l1ls_status l1ls_fista_kernel_times_ex(l1ls_fista* F, int32_t count, double* ms, int64_t* launches) {
+    if (!F || !ms || !launches || count < 1 || count > 5) return L1LS_E_ARG;
+    L1LS_TRY(drain_events(F));
+    for (int i = 0; i < count; ++i) {
         ms[i] = F->ms[i];
         launches[i] = F->launches[i];
     }
@@ -804,10 +982,7 @@ extern "C" l1ls_status l1ls_solve_fista(const l1ls_instance* I, const l1ls_solve
         }
         if (st == L1LS_OK && opts->max_iter % check != 0) {
             // evaluate the gap at the last iterate as well
-            hipLaunchKernelGGL(k_gap, dim3(1), dim3(kGapThreads), 0, F->stream,
-                               F->k1part + (size_t)(F->k & 1) * 3 * F->g1,
-                               F->k1part + (size_t)((F->k - 1) & 1) * 3 * F->g1, F->g1, F->k2part, F->g2, F->tau,
-                               opts->rel_gap_tol, F->k, F->gs);
+            launch_gap(F, F->k, opts->rel_gap_tol);
         }
         if (st == L1LS_OK) st = l1ls_fista_report(F, &r);
         if (st == L1LS_OK || st == L1LS_E_NONFINITE) {

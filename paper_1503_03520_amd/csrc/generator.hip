@@ -324,6 +324,7 @@ template l1ls_status apply_side<float>(const SideTables&, int, bool, float*, flo
 
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s);
 l1ls_status build_blocks(l1ls_instance* I, hipStream_t s, DevArena& tmp);
+l1ls_status build_stored_windows(l1ls_instance* I, hipStream_t s);
 
 // l1ls_generate_ex with the instance's device memory (and the build's
 // temporaries) from `al` (nullptr: hipMalloc).
@@ -340,7 +341,8 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
     if (!(s >= 0 && s <= n) || !(kappa >= 1.0) || !is_finite(kappa) || !(tau > 0.0) || !is_finite(tau))
         return L1LS_E_ARG;
     if (rounds < 1 || rounds > L1LS_MAX_ROUNDS) return L1LS_E_ARG;
-    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32 | L1LS_STORE_MF_WINDOWS)) != 0)
+    if ((storage & ~(L1LS_STORE_F32 | L1LS_STORE_F64 | L1LS_STORE_BLK32 | L1LS_STORE_MF_WINDOWS |
+                     L1LS_STORE_WINDOWS)) != 0)
         return L1LS_E_ARG;
     if ((storage & L1LS_STORE_BLK32) && (rounds != 2 || layout != L1LS_LAYOUT_STAGE || n < 4))
         return L1LS_E_UNSUPPORTED;
@@ -539,6 +541,7 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
                 std::fprintf(stderr, "l1ls: CSR/CSC mismatch (missing %d, nnz %d vs %d)\n", miss, csr_nnz, nnz);
             return fail(L1LS_E_STATE);
         }
+        if (storage & L1LS_STORE_WINDOWS) GEN_TRY(build_stored_windows(I, stream));
     }
     GEN_HIP(hipGetLastError());
     GEN_HIP(hipStreamSynchronize(stream));

@@ -3,10 +3,13 @@
 //   residual pass  (CSR):  r_x = A x_k - b,  r_y = (1+beta_k) r_x - beta_k r_x,prev
 //   transpose pass (CSC):  g = A^T r_y,  y = x_{k-1} + beta (x_{k-1} - x_{k-2}),
 //                          x_k = soft(y - g/L, tau/L)
-// plus FP64 partial statistics for the duality gap.  Each row (column) is
-// handled by a segment of W lanes of a wave64; a grid-stride loop keeps the
-// grid fixed so the partial arrays have one slot per workgroup and every
-// reduction runs in a fixed order (bitwise reproducible).
+// plus FP64 partial statistics for the duality gap.  Each wave owns a tile
+// of 64 consecutive rows (columns), one per lane: the tile's index and value
+// loads and gathers are issued together, the products staged in LDS, and
+// each lane sums its own row in storage order.  One workgroup (four waves)
+// writes one slot of the partial arrays, and every reduction runs in a fixed
+// order (bitwise reproducible).  k_spmv, the plain product, uses segments of
+// W lanes per row with a grid-stride loop.
 #pragma once
 
 #include "common.hpp"
@@ -57,7 +60,12 @@ __device__ __forceinline__ T ld_off32(const T* __restrict__ base, int32_t i) {
 // loads, NQ value loads and NQ gathers of a lane are all in flight together.
 // The tile's base pointers are wave-uniform (scalar registers); per-lane
 // offsets are 32-bit.  Entries beyond NQ * 64 go through a tail loop.
-template <typename T, int NQ>
+template <typename T>
+__device__ __forceinline__ T ld_maybe_nt(const T* p, bool nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T, int NQ, bool NT = true>
 __device__ __forceinline__ void tile_products(const int32_t* __restrict__ idx, const T* __restrict__ val,
                                               const T* __restrict__ vec, int32_t beg, int32_t cnt,
                                               T* __restrict__ lds, int lane) {
@@ -69,9 +77,9 @@ __device__ __forceinline__ void tile_products(const int32_t* __restrict__ idx, c
     T v[NQ];
     T g[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) c[q] = __builtin_nontemporal_load(ib + min(q * kTile + lane, last));
+    for (int q = 0; q < NQ; ++q) c[q] = ld_maybe_nt(ib + min(q * kTile + lane, last), NT);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = __builtin_nontemporal_load(vb + min(q * kTile + lane, last));
+    for (int q = 0; q < NQ; ++q) v[q] = ld_maybe_nt(vb + min(q * kTile + lane, last), NT);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) g[q] = ld_off32(vec, c[q]);
 #pragma unroll
@@ -79,10 +87,25 @@ __device__ __forceinline__ void tile_products(const int32_t* __restrict__ idx, c
     for (int32_t k = NQ * kTile + lane; k <= last; k += kTile) lds[k] = vb[k] * ld_off32(vec, ib[k]);
 }
 
+// Workgroup index under XCD placement: workgroups are dispatched to the 8
+// XCDs in turn (b, b + 8, ... on one XCD); with XCD set, XCD x takes one
+// contiguous range of the logical indices instead, so the workgroups of one
+// window of a windowed gather (window.hip) share one L2.
+template <bool XCD>
+__device__ __forceinline__ int64_t placed_block() {
+    const int64_t b = blockIdx.x;
+    if (!XCD) return b;
+    const int64_t G = gridDim.x, q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 // Residual pass: one tile of 64 rows per wave, one wave-tile per launch slot.
 // part[3*block + {0,1,2}] = sum r_x^2, sum r_y^2, sum b r_y (FP64).
 // init = 1: r_y = r_x (first pass, beta_0 = 0, r_x,prev undefined).
-template <typename T>
+// NQ, NT: the tile schedule (entries per lane issued together; nontemporal
+// index and value loads), chosen by the autotuner; every choice computes the
+// same values in the same order.
+template <typename T, int NQ = 10, bool NT = true, bool XCD = false>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_residual(
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ col, const T* __restrict__ val,
     const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ rx, T* __restrict__ ry, T beta,
@@ -94,7 +117,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_residual(
     __shared__ T lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = threadIdx.x / L1LS_WAVE;
-    const int64_t row0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t blk = placed_block<XCD>();
+    const int64_t row0 = (blk * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
     const int64_t i = row0 + lane;
     const bool live = i < m;
     int32_t pb = 0, pe = 0;
@@ -109,7 +133,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_residual(
     const int lastlane = (row0 + kTile <= m) ? kTile - 1 : (m > row0 ? (int)(m - row0 - 1) : 0);
     const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
     const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-    if (row0 < m) tile_products<T, 10>(col, val, x, beg, end - beg, lds[wid], lane);
+    if (row0 < m) tile_products<T, NQ, NT>(col, val, x, beg, end - beg, lds[wid], lane);
     __syncthreads();
     double v[3] = {0.0, 0.0, 0.0};
     if (live && !done) {
@@ -126,16 +150,16 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_residual(
     if (!stats) return;  // launch-uniform: the gap test does not read this pass
     block_reduce_stats<3, 3>(v);
     if (threadIdx.x == 0 && !done) {
-        part[3 * blockIdx.x + 0] = v[0];
-        part[3 * blockIdx.x + 1] = v[1];
-        part[3 * blockIdx.x + 2] = v[2];
+        part[3 * blk + 0] = v[0];
+        part[3 * blk + 1] = v[1];
+        part[3 * blk + 2] = v[2];
     }
 }
 
 // Transpose pass with the prox step: one tile of 64 columns per wave.
 // xc = x_{k-1}; xp = x_{k-2} on entry and x_k on exit (same slot).
-// part[2*block + {0,1}] = max |g|, sum |x_k|.
-template <typename T>
+// part[2*block + {0,1}] = max |g|, sum |x_k|.  NQ, NT as for k_residual.
+template <typename T, int NQ = 16, bool NT = true, bool XCD = false>
 __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ row, const T* __restrict__ val,
     const T* __restrict__ ry, const T* __restrict__ xc, T* __restrict__ xp, T beta, T L, T thr,
@@ -144,7 +168,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
     __shared__ T lds[L1LS_BLOCK / L1LS_WAVE][kTile * kMaxNnz];
     const int lane = threadIdx.x % L1LS_WAVE;
     const int wid = threadIdx.x / L1LS_WAVE;
-    const int64_t col0 = ((int64_t)blockIdx.x * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
+    const int64_t blk = placed_block<XCD>();
+    const int64_t col0 = (blk * (L1LS_BLOCK / L1LS_WAVE) + wid) * kTile;
     const int64_t j = col0 + lane;
     const bool live = j < n;
     int32_t pb = 0, pe = 0;
@@ -158,7 +183,7 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
     const int lastlane = (col0 + kTile <= n) ? kTile - 1 : (n > col0 ? (int)(n - col0 - 1) : 0);
     const int32_t beg = __builtin_amdgcn_readfirstlane(__shfl(pb, 0, L1LS_WAVE));
     const int32_t end = __builtin_amdgcn_readfirstlane(__shfl(pe, lastlane, L1LS_WAVE));
-    if (col0 < n) tile_products<T, 16>(row, val, ry, beg, end - beg, lds[wid], lane);
+    if (col0 < n) tile_products<T, NQ, NT>(row, val, ry, beg, end - beg, lds[wid], lane);
     __syncthreads();
     double v[2] = {0.0, 0.0};  // sum |x_k|, max |g|
     if (live && !done) {
@@ -173,8 +198,8 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
     if (!stats) return;  // launch-uniform
     block_reduce_stats<2, 1>(v);
     if (threadIdx.x == 0 && !done) {
-        part[2 * blockIdx.x + 0] = v[1];
-        part[2 * blockIdx.x + 1] = v[0];
+        part[2 * blk + 0] = v[1];
+        part[2 * blk + 1] = v[0];
     }
 }
 
@@ -184,22 +209,69 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_transpose_prox(
 //   D = -0.5 theta^2 ||r_y,k||^2 - theta b^T r_y,k,
 //   gap = (P - D) / |P|.
 // One workgroup; fixed-order sums.
+// The five gap sums (rr, ryy, bry, l1 | ginf) over the workgroup partials
+// [b1, e1) of the residual passes and [b2, e2) of the transpose pass, in a
+// fixed order (strided per thread, then block_reduce_stats).
+__device__ __forceinline__ void gap_sums(const double* __restrict__ k1_cur, const double* __restrict__ k1_prev,
+                                         int b1, int e1, const double* __restrict__ k2, int b2, int e2,
+                                         double (&v)[5]) {
+    for (int b = b1 + (int)threadIdx.x; b < e1; b += blockDim.x) {
+        v[0] += k1_cur[3 * b + 0];
+        v[1] += k1_prev[3 * b + 1];
+        v[2] += k1_prev[3 * b + 2];
+    }
+    for (int b = b2 + (int)threadIdx.x; b < e2; b += blockDim.x) {
+        v[3] += k2[2 * b + 1];
+        v[4] = fmax(v[4], k2[2 * b + 0]);
+    }
+    block_reduce_stats<5, 4>(v);
+}
+
+__device__ __forceinline__ void gap_finish(const double (&v)[5], double tau, double tol, int64_t iter, GapState* gs);
+
 static __global__ __launch_bounds__(1024) void k_gap(
     const double* __restrict__ k1_cur, const double* __restrict__ k1_prev, int g1,
     const double* __restrict__ k2, int g2, double tau, double tol, int64_t iter, GapState* gs) {
     if (gs->done) return;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rr, ryy, bry, l1 | ginf
-    for (int b = threadIdx.x; b < g1; b += blockDim.x) {
-        v[0] += k1_cur[3 * b + 0];
-        v[1] += k1_prev[3 * b + 1];
-        v[2] += k1_prev[3 * b + 2];
+    gap_sums(k1_cur, k1_prev, 0, g1, k2, 0, g2, v);
+    if (threadIdx.x == 0) gap_finish(v, tau, tol, iter, gs);
+}
+
+// Large grids (hundreds of thousands of partials): a first stage of
+// kGapStages workgroups, each over a contiguous share of the partials, then
+// k_gap_final over their kGapStages x 5 sums.
+constexpr int kGapStages = 256;
+
+static __global__ __launch_bounds__(1024) void k_gap_stage(
+    const double* __restrict__ k1_cur, const double* __restrict__ k1_prev, int g1,
+    const double* __restrict__ k2, int g2, double* __restrict__ out, const GapState* __restrict__ gs) {
+    if (gs->done) return;
+    const int c1 = (g1 + kGapStages - 1) / kGapStages, c2 = (g2 + kGapStages - 1) / kGapStages;
+    const int b = blockIdx.x;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    gap_sums(k1_cur, k1_prev, min(b * c1, g1), min((b + 1) * c1, g1), k2, min(b * c2, g2), min((b + 1) * c2, g2), v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) out[5 * b + i] = v[i];
     }
-    for (int b = threadIdx.x; b < g2; b += blockDim.x) {
-        v[3] += k2[2 * b + 1];
-        v[4] = fmax(v[4], k2[2 * b + 0]);
+}
+
+static __global__ __launch_bounds__(1024) void k_gap_final(const double* __restrict__ st, double tau, double tol,
+                                                           int64_t iter, GapState* gs) {
+    if (gs->done) return;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < kGapStages; b += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] += st[5 * b + i];
+        v[4] = fmax(v[4], st[5 * b + 4]);
     }
     block_reduce_stats<5, 4>(v);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) gap_finish(v, tau, tol, iter, gs);
+}
+
+__device__ __forceinline__ void gap_finish(const double (&v)[5], double tau, double tol, int64_t iter, GapState* gs) {
+    {
         const double P = tau * v[3] + 0.5 * v[0];
         const double theta = (v[4] <= tau) ? 1.0 : tau / v[4];
         const double D = -0.5 * theta * theta * v[1] - theta * v[2];

@@ -16,6 +16,11 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+l1ls_status gap_fp64(const l1ls_instance* I, double tau, const double* x, double* P, double* D, double* gap,
+                     hipStream_t s, DevAlloc* al = nullptr);
+l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t stream, int* rounds_out,
+                        int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr);
+
 using namespace l1ls;
 
 namespace {
@@ -315,6 +320,8 @@ extern "C" l1ls_status l1ls_solve_fista_path(const l1ls_instance* I, const doubl
     if (!I || !taus || !o || !X_out || !reports || k < 1 || k > kCols) return L1LS_E_ARG;
     if (!I->csr_v32 || !I->csc_v32) return L1LS_E_UNSUPPORTED;
     if (o->check_every < 1 || o->max_iter < 0 || !(o->rel_gap_tol >= 0.0)) return L1LS_E_ARG;
+    if (o->polish < 0 || o->polish > 2) return L1LS_E_ARG;
+    if (o->polish && (!I->csr_v64 || !I->csc_v64)) return L1LS_E_UNSUPPORTED;
     for (int c = 0; c < k; ++c)
         if (!(taus[c] > 0.0) || !is_finite(taus[c])) return L1LS_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
@@ -405,6 +412,33 @@ extern "C" l1ls_status l1ls_solve_fista_path(const l1ls_instance* I, const doubl
         r.seconds = secs;
         all = all && r.converged;
         if (got[c].nonfinite) return L1LS_E_NONFINITE;
+    }
+    if (o->polish) {
+        // FP64 finish of each column at its own tau: the FP64 gap of the FP32
+        // result, the polish of the reduced problem (13) where that gap
+        // misses the tolerance (polish = 2) or always (polish = 1), and the
+        // FP64 gap of what is returned
+        all = true;
+        for (int c = 0; c < k; ++c) {
+            l1ls_report& r = reports[c];
+            double* xc = X_out + (size_t)c * n;
+            double P, D, gap;
+            L1LS_TRY(gap_fp64(I, taus[c], xc, &P, &D, &gap, s));
+            if (o->polish == 1 || !(gap <= o->rel_gap_tol)) {
+                int rounds = 0;
+                int64_t pcg = 0;
+                L1LS_TRY(polish_fp64(I, taus[c], xc, s, &rounds, &pcg, 0.0));
+                L1LS_TRY(gap_fp64(I, taus[c], xc, &P, &D, &gap, s));
+                r.polish_rounds = rounds;
+                r.inner = pcg;
+            }
+            r.primal = P;
+            r.dual = D;
+            r.rel_gap = gap;
+            r.converged = (gap <= o->rel_gap_tol) ? 1 : 0;
+            r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            all = all && r.converged;
+        }
     }
     return all ? L1LS_OK : L1LS_NOT_CONVERGED;
 }

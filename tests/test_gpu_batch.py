@@ -204,7 +204,8 @@ def test_graph_replay_equals_launched_iterations(tol):
 def test_persistent_small_slots_equal_shared_passes(graph):
     # Slots with few rows run every iteration of an iterate call in one
     # workgroup (kb_persist); with persist_rows = -1 they take the shared
-    # passes, with 1 << 20 every slot here runs in one workgroup.  All three
+    # passes, with 4096 the slots of at most 4096 rows and with 1 << 20 every
+    # slot here runs in one workgroup.  All three
     # give the same iterates and stop at the same iteration, bit for bit,
     # with late admission and a removal between calls.
     def drive(persist_rows):
@@ -226,7 +227,7 @@ def test_persistent_small_slots_equal_shared_passes(graph):
         return out
 
     ref = drive(-1)
-    for rows in (0, 1 << 20):
+    for rows in (4096, 1 << 20):
         got = drive(rows)
         for (xa, ia, ca, ga), (xb, ib, cb, gb) in zip(ref, got):
             assert (ia, ca, ga) == (ib, cb, gb), rows

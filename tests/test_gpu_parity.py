@@ -367,3 +367,25 @@ def test_nonfinite_warm_start_reported():
     with pytest.raises(L.L1lsError) as ei:
         L.l1ls_solve_fista(g, x0=_dev(x0), max_iter=8, rel_gap_tol=0.0, check_every=4, precision=L.F64)
     assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("cfg", [CASES[0], CASES[1]])
+def test_tile_schedule_variants_are_bitwise_equal(cfg):
+    # every tile schedule the autotuner can pick for the stored FP32 passes
+    # computes the same values in the same order
+    g, o, A = pair(cfg)
+    kr = "fista_f32_residual/%d" % int(np.ceil(np.log2(o.m)))
+    kt = "fista_f32_transpose/%d" % int(np.ceil(np.log2(o.n)))
+    old = (L.tune_get(kr), L.tune_get(kt))
+    ref = None
+    try:
+        for vr, vt in ((0, 0), (1, 1), (2, 2), (3, 3), (1, 3), (3, 0)):
+            L.tune_set(kr, vr)
+            L.tune_set(kt, vt)
+            x, rep, _ = L.l1ls_solve_fista(g, max_iter=40, rel_gap_tol=0.0, check_every=8, precision=L.F32)
+            if ref is None:
+                ref = (x, rep["primal"])
+            assert torch.equal(x, ref[0]) and rep["primal"] == ref[1], (vr, vt)
+    finally:
+        L.tune_set(kr, old[0])
+        L.tune_set(kt, old[1])

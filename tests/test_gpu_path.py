@@ -81,3 +81,50 @@ def test_path_to_tolerance_with_fp64_certificates():
             assert reps[c]["rel_gap"] > 1e-5 and gap <= 5e-3, (c, reps[c]["rel_gap"], gap)
         if tau >= 0.1 * tmax:
             assert reps[c]["converged"] == 1 and reps[c]["iterations"] <= 4000
+
+
+def test_path_fp64_finish_reports_fp64_certificates():
+    # polish = 2: each column's FP32 result is finished in FP64 at its own
+    # tau (the polish of the reduced problem (13) runs where the FP64 gap
+    # misses the tolerance), and each report carries the FP64 gap of the
+    # returned column.  The polish starts from the FP32 iterate's support, so
+    # after 300 iterations at kappa = 1e3 it certifies only some columns;
+    # what is checked is that every report tells the truth.
+    g, o, A = pair()
+    taus, tmax = taus_for(o, A, 16)
+    taus = np.concatenate([taus, [o.tau]])
+    kw = dict(max_iter=300, rel_gap_tol=1e-8, check_every=10)
+    X32, r32, _ = L.l1ls_solve_fista_path(g, taus, **kw)
+    X, reps, st = L.l1ls_solve_fista_path(g, taus, polish=2, **kw)
+    done = 0
+    for c, t in enumerate(taus):
+        P, D, gap = L.l1ls_objective_gap(g, float(t), X[c].contiguous())
+        assert reps[c]["rel_gap"] == gap, c
+        assert reps[c]["converged"] == (1 if gap <= 1e-8 else 0), c
+        g32 = L.l1ls_objective_gap(g, float(t), X32[c].contiguous())[2]
+        if g32 <= 1e-8:
+            assert torch.equal(X[c], X32[c]) and reps[c]["polish_rounds"] == 0, c   # nothing to finish
+        else:
+            assert reps[c]["polish_rounds"] >= 1, c
+        done += reps[c]["converged"]
+    print(f"FP64-finished columns within 1e-8: {done} of {len(taus)}", flush=True)
+    assert reps[-1]["converged"] == 1
+    assert (st == L.L1LS_OK) == (done == len(taus))
+
+
+def test_path_polish_every_column_reaches_planted_solution():
+    # polish = 1 polishes every column: at the planted tau the FP32 path's
+    # column, finished in FP64, is x* (Procedure IGen) to the FP64 floor, as
+    # the single-instance solve with polish = 1 from the same iterations
+    g, o, A = pair()
+    taus = np.array([o.tau, 0.5 * o.tau])
+    X, reps, _ = L.l1ls_solve_fista_path(g, taus, max_iter=300, rel_gap_tol=1e-8, check_every=10, polish=1)
+    assert reps[0]["polish_rounds"] >= 1 and reps[1]["polish_rounds"] >= 1
+    err = np.linalg.norm(X[0].cpu().numpy() - o.xstar) / np.linalg.norm(o.xstar)
+    x1, r1, _ = L.l1ls_solve_fista(g, max_iter=300, rel_gap_tol=1e-8, check_every=10, precision=L.F32, polish=1)
+    err1 = np.linalg.norm(x1.cpu().numpy() - o.xstar) / np.linalg.norm(o.xstar)
+    print(f"planted tau: path polish rel err {err:.3e}, single solve {err1:.3e}", flush=True)
+    assert reps[0]["converged"] == 1 and err <= 1e-9
+    assert err1 <= 1e-9
+    for c in range(2):
+        assert reps[c]["rel_gap"] == L.l1ls_objective_gap(g, float(taus[c]), X[c].contiguous())[2]
