@@ -32,7 +32,7 @@ PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "fista_stored_f32_n2p26.txt")
 def profile_summary_path(n):
     """The committed counter summary of the FISTA passes at size n."""
     return os.path.join(ROOT, "profiles", "fista_stored_f32_n2p%d.txt" % (n.bit_length() - 1))
-KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp", "blocks.hip"]
+KERNEL_SOURCES = ["kernels.hpp", "fista.hip", "common.hpp", "blocks.hip", "window.hip"]
 
 
 def kernel_source_hash():
@@ -71,13 +71,24 @@ def write_profile_summary(args):
                     return list(csv.DictReader(open(os.path.join(root, f))))
         raise SystemExit(f"no *{kind} under {d}")
 
-    names = {"residual": "k_residual<float", "transpose_prox": "k_transpose_prox<float",
-             "blk_residual": "k_blk_residual<false>", "blk_transpose_prox": "k_blk_transpose_prox<false>",
-             "mf_res_qt": "k_mf_res_qt<float, 2, 0, float>", "mf_prox_gt": "k_mf_prox_gt<float, 2>",
-             "mf_win_scatter": "k_win_scatter<float>"}
+    import re
+
+    # key: (kernel name pattern, rank of the grid among the pattern's grids,
+    # largest first).  The plain stored passes run without XCD placement,
+    # the windowed ones with it; the windowed gathers' bucketing pass runs
+    # once per side, r_y's (m sources) with the larger grid.
+    names = {"residual": (r"k_residual<float, \d+, (true|false), false>", 0),
+             "transpose_prox": (r"k_transpose_prox<float, \d+, (true|false), false>", 0),
+             "residual_win": (r"k_residual<float, \d+, (true|false), true>", 0),
+             "transpose_prox_win": (r"k_transpose_prox<float, \d+, (true|false), true>", 0),
+             "bucket_r_y": (r"k_sw_scatter", 0), "bucket_x": (r"k_sw_scatter", 1),
+             "blk_residual": (r"k_blk_residual<false>", 0), "blk_transpose_prox": (r"k_blk_transpose_prox<false>", 0),
+             "mf_res_qt": (r"k_mf_res_qt<float, 2, 0, float>", 0), "mf_prox_gt": (r"k_mf_prox_gt<float, 2>", 0),
+             "mf_win_scatter": (r"k_win_scatter<float>", 0)}
     # The bench launches these kernels at the headline size and (in the
     # n = 2^20 leg) at a smaller one: each figure is taken over the dispatches
-    # with the kernel's largest grid, the headline instance's.
+    # with the kernel's largest grid (the headline instance's), or the grid
+    # of the given rank.
     trace = kernel_rows(args.kt, "kernel_trace.csv")
 
     def grid_of(r):
@@ -85,11 +96,12 @@ def write_profile_summary(args):
 
     dur = {}
     big = {}
-    for key, pat in names.items():
-        rows = [r for r in trace if pat in r["Kernel_Name"]]
-        if not rows:
+    for key, (pat, rank) in names.items():
+        rows = [r for r in trace if re.search(pat, r["Kernel_Name"])]
+        grids = sorted({grid_of(r) for r in rows}, reverse=True)
+        if len(grids) <= rank:
             continue
-        g = max(grid_of(r) for r in rows)
+        g = grids[rank]
         rows = [r for r in rows if grid_of(r) == g]
         ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
         dur[key] = (sum(ns) / len(ns), len(ns))
@@ -97,7 +109,7 @@ def write_profile_summary(args):
 
     def counter(d, cname, pat, grid=None):
         vals = [float(r["Counter_Value"]) for r in kernel_rows(d, "counter_collection.csv")
-                if pat in r["Kernel_Name"] and r["Counter_Name"] == cname
+                if re.search(pat, r["Kernel_Name"]) and r["Counter_Name"] == cname
                 and (grid is None or int(r.get("Grid_Size") or 0) == grid)]
         return statistics.median(vals), len(vals)
 
@@ -107,8 +119,9 @@ def write_profile_summary(args):
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
     kt_cmd = args.kt_command or "python3 bench.py --steps 20 --warmup 5"
     pmc_cmd = args.pmc_command or "python3 bench.py --steps 20 --warmup 5"
-    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (and blk_*: the blocked stored operator; "
-             "mf_*: the matrix-free operator, mf_win_scatter its windowed gathers' bucketing pass), FP32 bulk, " + (args.stats_title or "n=2^26, m=2^27, 2 stages"),
+    lines = ["# rocprofv3 summary: FISTA hot passes, stored CSR/CSC (*_win: with the windowed gathers, bucket_*: "
+             "their bucketing passes; blk_*: the blocked stored operator; mf_*: the matrix-free operator, "
+             "mf_win_scatter its windowed gathers' bucketing pass), FP32 bulk, " + (args.stats_title or "n=2^26, m=2^27, 2 stages"),
              "# each figure over the kernel's dispatches with its largest grid (the headline instance's launches)",
              f"# kernel trace: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- {kt_cmd}",
              f"# counters:     rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o bench -- "
@@ -120,7 +133,7 @@ def write_profile_summary(args):
              f"copy_write_kib_per_gib: {copy_w:.1f}",
              f"fetch_scale: {f_scale:.4f}",
              f"write_scale: {w_scale:.4f}"]
-    for key, pat in names.items():
+    for key, (pat, _) in names.items():
         if key not in dur:
             continue  # not launched in this run (the windowed gathers' pass below n = 2^22)
         lines.append(f"{key}_avg_ns: {dur[key][0]:.0f}")
@@ -980,6 +993,8 @@ def bench_fista(args):
         print(json.dumps({"progress": kv}), file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
+    # from n = 2^22 on the stored passes gather through the window tables
+    # (L1LS_STORE_WINDOWS); the plain gathers are a side leg
     windows = n >= 1 << 22 and not args.no_windows
     inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream,
                            storage=L.STORE_F32 | L.STORE_F64 | L.STORE_BLK32 | (L.STORE_WINDOWS if windows else 0))
@@ -999,7 +1014,7 @@ def bench_fista(args):
     dom_bytes = (k1_bytes, k2_bytes)[dominant]
     achieved = dom_bytes / (avg[dominant] * 1e-3) / 1e9
     pair_gbs = (k1_bytes + k2_bytes) / ((avg[0] + avg[1]) * 1e-3) / 1e9
-    key = ("residual", "transpose_prox")[dominant]
+    key = ("residual", "transpose_prox")[dominant] + ("_win" if windows else "")
     traffic = None
     summ = read_profile_summary(profile_summary_path(n))
     if summ and summ.get("kernel_source_hash") == kernel_source_hash() and f"{key}_traffic_bytes" in summ:
@@ -1056,20 +1071,26 @@ def bench_fista(args):
                     "max_abs_diff_vs_stored": float((bl["x"] - st["x"]).abs().max())},
     }
     if windows:
-        # the stored passes with their plain gathers, on the same instance
-        # built without the window tables
-        extra["bucketing_avg_us"] = {"x": avg[3] * 1e3, "r_y": avg[4] * 1e3}
-        extra["iteration_gbs"] = (k1_bytes + k2_bytes) / (st["ms_per_step"] * 1e-3) / 1e9
+        # the bucketing passes of the windowed gathers, and the stored passes
+        # with their plain gathers on the same instance built without the
+        # window tables (the iterates are the same bit for bit)
+        extra["kernel_avg_us"].update({"bucket_x": avg[3] * 1e3, "bucket_r_y": avg[4] * 1e3})
+        extra["kernel_launches_in_window"].update({"bucket_x": st["launches"][3], "bucket_r_y": st["launches"][4]})
+        extra["iteration_algorithmic_gbs"] = (k1_bytes + k2_bytes) / (st["ms_per_step"] * 1e-3) / 1e9
+        extra["instance_bytes"] = inst.nbytes()
         inst.free()
         inst = None
         torch.cuda.empty_cache()
         p_inst = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=rounds, stream=stream, storage=L.STORE_F32)
         pl = fista_legs(L, torch, p_inst, stream, args.steps, args.warmup, check, (L.OP_STORED,))[L.OP_STORED]
+        pk = (k1_bytes, k2_bytes)
         extra["stored_plain_gathers"] = {
             "iters_per_s": pl["iters_per_s"], "ms_per_step": pl["ms_per_step"],
             "kernel_avg_us": {"residual": pl["avg_ms"][0] * 1e3, "transpose_prox": pl["avg_ms"][1] * 1e3,
                               "gap": pl["avg_ms"][2] * 1e3},
-            "max_abs_diff_vs_windowed": float((pl["x"] - st["x"]).abs().max())}
+            "algorithmic_gbs": {k: pk[i] / (pl["avg_ms"][i] * 1e-3) / 1e9
+                                for i, k in enumerate(("residual", "transpose_prox"))},
+            "bitwise_equal_to_windowed": bool(torch.equal(pl["x"], st["x"]))}
         p_inst.free()
         progress(step="plain gathers", iters_per_s=pl["iters_per_s"])
     for leg in legs.values():
@@ -1128,7 +1149,8 @@ def bench_fista(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("k_residual (CSR A x - b + momentum residual)",
-                                "k_transpose_prox (CSC A^T r + prox)")[dominant],
+                                "k_transpose_prox (CSC A^T r + prox)")[dominant]
+                     + (", windowed gathers (XCD-placed)" if windows else ""),
                      "algorithmic_bytes_per_launch": dom_bytes},
         "extra": extra,
     }
@@ -1213,7 +1235,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=0, help="fista workload: override log2(n) of --config")
     ap.add_argument("--no-c2", action="store_true", help="fista workload: skip the n = 2^20 leg in extra")
     ap.add_argument("--no-windows", action="store_true",
-                    help="fista workload: stored passes with plain gathers only (no L1LS_STORE_WINDOWS)")
+                    help="fista workload: skip the side leg over the window tables (L1LS_STORE_WINDOWS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-iters", type=int, default=10)

@@ -87,17 +87,19 @@ typedef enum { L1LS_LAYOUT_NATURAL = 0, L1LS_LAYOUT_STAGE = 1 } l1ls_layout;
  * buffers hold the bucketed copies (n entries each). */
 #define L1LS_STORE_MF_WINDOWS 8u
 /* Windowed gathers for the stored FP32 FISTA passes (with L1LS_STORE_F32):
- * the CSR pass gathers x, and the CSC pass r_y, at a few runs of four per
- * row (column) at random places, a cache line per run once the vector
- * outgrows the caches.  With this bit each pass's targets are grouped in
- * windows (about 2^16 rows or 2^15 columns at two stages), and a bucketing
- * pass before it copies the gathered vector so that each window's sources
- * lie together (one copy per window that reads a source); the pass then
- * gathers inside its window's segment, whose workgroups run on one XCD.
+ * the CSR pass gathers x, and the CSC pass r_y, at a few runs of four
+ * consecutive positions per row (column) at random places, a cache line per
+ * run once the vector outgrows the caches.  With this bit each pass's
+ * targets are grouped in windows (about 2^20 stored entries each), and a
+ * bucketing pass before it copies the gathered vector in units of 4
+ * consecutive elements so that each window's units lie in whole cache lines
+ * (one copy per window that reads a unit); the pass then gathers inside
+ * those lines, which stay in the L2 of the XCD that runs the window.
  * Results are bitwise those of the plain passes.  Extra device memory:
- * 4 bytes per stored entry for each pass's slot indices, 2 bytes per slot
- * and the bucketed copies in the solver (about 4 n slots per pass at two
- * stages), plus the run tables. */
+ * 4 bytes per stored entry for each pass's positions in the copy, 2 bytes
+ * per unit, and the bucketed copies in the solver (16 bytes per unit; about
+ * n units per pass at two stages).  L1LS_E_UNSUPPORTED when a copy would
+ * reach 4 GiB. */
 #define L1LS_STORE_WINDOWS 32u
 
 typedef struct {

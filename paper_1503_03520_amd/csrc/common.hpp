@@ -170,16 +170,15 @@ struct l1ls_instance {
     int64_t blk_nruns = 0;
     // Windowed gathers of the stored FP32 passes (L1LS_STORE_WINDOWS; see
     // window.hip).  [0]: the CSR pass's gather of x (row windows), [1]: the
-    // CSC pass's gather of r_y (column windows).  sw_idx[k] replaces the
-    // CSR column (CSC row) indices by slots of the bucketed copy u_k, which
-    // holds, window after window and chunk after chunk, one copy of each
-    // source element a window reads; sw_src[k][slot] = offset of the slot's
-    // source in its chunk; the run of window w and chunk c spans slots
-    // [sw_start[k][c nT + w], sw_end[k][c nT + w]) (runs are window-major in u).
+    // CSC pass's gather of r_y (column windows).  The bucketed copy u_k is
+    // made of units of 4 consecutive source elements; sw_idx[k] replaces the
+    // CSR column (CSC row) indices by positions in u_k (4 unit + offset);
+    // sw_src[k][unit] = offset of the unit's first source in its chunk of
+    // 2^sw_cs sources; the units of chunk c are [sw_cb[k][c], sw_cb[k][c+1])
+    // (chunk-major, then window).  sw_slots[k] = 4 units (floats of u_k).
     int32_t* sw_idx[2] = {nullptr, nullptr};
     uint16_t* sw_src[2] = {nullptr, nullptr};
-    int32_t* sw_start[2] = {nullptr, nullptr};
-    int32_t* sw_end[2] = {nullptr, nullptr};
+    int32_t* sw_cb[2] = {nullptr, nullptr};
     int64_t sw_slots[2] = {0, 0};
     int64_t sw_nT[2] = {0, 0};
     int64_t sw_nc[2] = {0, 0};
