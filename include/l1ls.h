@@ -239,7 +239,9 @@ typedef struct {
     int32_t op;            /* l1ls_operator                                     */
     int32_t polish;        /* FP64 polish of the reduced problem (13) at the end:
                               0 never, 1 always, 2 only when the FP64 gap of
-                              the FISTA result exceeds rel_gap_tol            */
+                              the FISTA result exceeds rel_gap_tol; a polish
+                              whose result has a larger objective f_tau than
+                              its starting point returns the starting point */
     double L;              /* <= 0: the instance's L (sigma_1^2)                 */
     const double* x0_dev;  /* n, warm start; NULL: x0 = 0                       */
     void* stream;
@@ -512,7 +514,8 @@ l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const do
  * 0 returns the FP32 iterates with the device's gap; 2 finishes each column
  * in FP64 at its tau (the FP64 gap of the FP32 result, the FP64 polish of the
  * reduced problem (13) where it misses rel_gap_tol, then the FP64 gap of the
- * result in reports[c]); 1 polishes every column.  polish needs
+ * result in reports[c]); 1 polishes every column.  A polish that does not
+ * lower the objective f_tau leaves the column as it was.  polish needs
  * L1LS_STORE_F64 (else L1LS_E_UNSUPPORTED).
  */
 l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus, int32_t k,

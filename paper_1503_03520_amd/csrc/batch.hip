@@ -383,6 +383,13 @@ struct l1ls_batch {
     std::vector<BInst> hinst;
     std::vector<size_t> footprint;
     std::vector<void*> buf;                   // per-slot device block (iterates + partials)
+    std::vector<char> retired;                // per slot: stopped (done or capped), out of the task tables
+    // One-shot batches (l1ls_solve_fista_batched) carve the slot blocks from
+    // one allocation: pool, pool_size bytes, pool_used taken so far; slots
+    // in the pool are not freed one by one.
+    char* pool = nullptr;
+    size_t pool_size = 0, pool_used = 0;
+    std::vector<char> pooled;
     BInst* dinst = nullptr;
     BState* dstate = nullptr;
     BTask* dt1 = nullptr;                     // residual-pass tasks of every slot (the first passes)
@@ -491,7 +498,7 @@ l1ls_status rebuild_tables(l1ls_batch* B) {
     std::vector<BTask> t1, t1i, t2;
     std::vector<int32_t> small;
     for (int s = 0; s < B->capacity; ++s) {
-        if (!B->inst[s]) continue;
+        if (!B->inst[s] || B->retired[s]) continue;
         const BInst& hi = B->hinst[s];
         if (B->steps[s] == 0) {
             if (B->o.tile_chunk > 0) {
@@ -621,6 +628,8 @@ extern "C" l1ls_status l1ls_batch_create(int32_t capacity, size_t hbm_budget_byt
     B->hinst.assign(capacity, BInst{});
     B->footprint.assign(capacity, 0);
     B->buf.assign(capacity, nullptr);
+    B->retired.assign(capacity, 0);
+    B->pooled.assign(capacity, 0);
     B->steps.assign(capacity, 0);
     auto fail = [&](l1ls_status s) {
         B->arena.release();
@@ -669,7 +678,15 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     if (B->budget && B->used + fp > B->budget) return L1LS_E_NOMEM;
     const int64_t m = I->m, n = I->n;
     void* blk = nullptr;
-    L1LS_TRY(dev_alloc(B->al, &blk, slot_bytes(m, n)));
+    const size_t sb = slot_bytes(m, n);
+    if (B->pool && B->pool_used + sb <= B->pool_size) {
+        blk = B->pool + B->pool_used;
+        B->pool_used += (sb + 255) / 256 * 256;
+        B->pooled[slot] = 1;
+    } else {
+        L1LS_TRY(dev_alloc(B->al, &blk, sb));
+        B->pooled[slot] = 0;
+    }
     float* f = (float*)blk;
     hipLaunchKernelGGL(kb_zero, g1d(2 * n), dim3(L1LS_BLOCK), 0, B->stream, f, 2 * n);  // x_0 = x_{-1} = 0
     BInst& h = B->hinst[slot];
@@ -704,11 +721,10 @@ extern "C" l1ls_status l1ls_batch_add_ex(l1ls_batch* B, const l1ls_instance* I, 
     B->buf[slot] = blk;
     B->footprint[slot] = fp;
     B->used += fp;
-    BState s0;
-    std::memset(&s0, 0, sizeof(s0));
-    HIP_TRY(hipMemcpyAsync(B->dstate + slot, &s0, sizeof(s0), hipMemcpyHostToDevice, B->stream));
+    B->retired[slot] = 0;
+    // a fresh state (stream-ordered before the slot's first pass)
+    HIP_TRY(hipMemsetAsync(B->dstate + slot, 0, sizeof(BState), B->stream));
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(B->stream));
     B->tables_dirty = true;
     B->init_pending = true;
     *slot_out = slot;
@@ -857,7 +873,14 @@ extern "C" l1ls_status l1ls_batch_poll(l1ls_batch* B, l1ls_report* reports, int3
         r.converged = st[s].converged ? 1 : (st[s].nonfinite ? -1 : 0);
         r.rel_err = -1.0;
         const bool capped = h.max_iter > 0 && r.iterations >= h.max_iter;
-        if (!st[s].done && !capped) ++act;
+        if (!st[s].done && !capped) {
+            ++act;
+        } else if (!B->retired[s]) {
+            // a stopped slot's passes do nothing: drop its tasks from the
+            // shared launches (its iterate and state stay until remove)
+            B->retired[s] = 1;
+            B->tables_dirty = true;
+        }
     }
     if (active_out) *active_out = act;
     return L1LS_OK;
@@ -880,7 +903,9 @@ extern "C" l1ls_status l1ls_batch_get_x(l1ls_batch* B, int32_t slot, double* x_o
 extern "C" l1ls_status l1ls_batch_remove(l1ls_batch* B, int32_t slot) {
     if (!B || slot < 0 || slot >= B->capacity || !B->inst[slot]) return L1LS_E_ARG;
     HIP_TRY(hipStreamSynchronize(B->stream));
-    dev_free(B->al, B->buf[slot], slot_bytes(B->hinst[slot].m, B->hinst[slot].n));
+    if (!B->pooled[slot]) dev_free(B->al, B->buf[slot], slot_bytes(B->hinst[slot].m, B->hinst[slot].n));
+    B->pooled[slot] = 0;
+    B->retired[slot] = 0;
     B->buf[slot] = nullptr;
     B->used -= B->footprint[slot];
     B->footprint[slot] = 0;
@@ -897,7 +922,8 @@ extern "C" void l1ls_batch_destroy(l1ls_batch* B) {
     if (B->side) (void)hipStreamSynchronize(B->side);
     (void)hipDeviceSynchronize();  // one wait for all the slot blocks
     for (int s = 0; s < B->capacity; ++s)
-        if (B->buf[s]) dev_free(B->al, B->buf[s], slot_bytes(B->hinst[s].m, B->hinst[s].n), true);
+        if (B->buf[s] && !B->pooled[s]) dev_free(B->al, B->buf[s], slot_bytes(B->hinst[s].m, B->hinst[s].n), true);
+    if (B->pool) dev_free(B->al, B->pool, B->pool_size, true);
     drop_graph(B);
     if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
     if (B->side) (void)hipStreamSynchronize(B->side);
@@ -912,10 +938,16 @@ extern "C" l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* inst
                                                 const l1ls_solve_opts* opts, double* const* x_outs,
                                                 l1ls_report* reports) {
     if (!insts || !opts || !x_outs || !reports || count < 1) return L1LS_E_ARG;
+    for (int q = 0; q < count; ++q)
+        if (!insts[q] || !x_outs[q]) return L1LS_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     l1ls_batch* B = nullptr;
     L1LS_TRY(l1ls_batch_create(count, 0, opts, &B));
-    l1ls_status st = L1LS_OK;
+    // every slot block from one allocation
+    size_t total = 0;
+    for (int q = 0; q < count; ++q) total += (slot_bytes(insts[q]->m, insts[q]->n) + 255) / 256 * 256;
+    l1ls_status st = dev_alloc(B->al, (void**)&B->pool, total);
+    if (st == L1LS_OK) B->pool_size = total;
     std::vector<int32_t> slot(count, -1);
     for (int q = 0; q < count && st == L1LS_OK; ++q)
         st = l1ls_batch_add_ex(B, insts[q], taus ? taus[q] : 0.0, -1.0, opts->max_iter, &slot[q]);
@@ -931,12 +963,19 @@ extern "C" l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* inst
         if (act == 0) break;
     }
     if (st == L1LS_OK) st = l1ls_batch_poll(B, rep.data(), nullptr);
+    // every result from the states just polled, one wait at the end
     bool all = true;
     for (int q = 0; q < count && st == L1LS_OK; ++q) {
-        st = l1ls_batch_get_x(B, slot[q], x_outs[q]);
-        reports[q] = rep[slot[q]];
+        const int s = slot[q];
+        const l1ls_instance* I = B->inst[s];
+        const int64_t k = rep[s].iterations;
+        hipLaunchKernelGGL(kb_to_f64_perm, g1d(I->n), dim3(L1LS_BLOCK), 0, B->stream, B->hinst[s].x[k & 1],
+                           x_outs[q], I->op_col_pos, I->n);
+        reports[q] = rep[s];
         all = all && reports[q].converged == 1;
     }
+    if (st == L1LS_OK && (hipGetLastError() != hipSuccess || hipStreamSynchronize(B->stream) != hipSuccess))
+        st = L1LS_E_HIP;
     l1ls_batch_destroy(B);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int q = 0; q < count; ++q) reports[q].seconds = secs;

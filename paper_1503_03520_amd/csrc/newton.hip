@@ -144,6 +144,22 @@ __global__ __launch_bounds__(L1LS_BLOCK) void k_hess(const int32_t* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// part[block] = (sum |x_j| over n, sum r_i^2 over m): the two terms of the
+// objective f_tau(x) = tau ||x||_1 + 0.5 ||A x - b||^2 (problem (1)).
+__global__ __launch_bounds__(L1LS_BLOCK) void k_obj_parts(const double* __restrict__ x, int64_t n,
+                                                          const double* __restrict__ r, int64_t m,
+                                                          double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) v[0] += fabs(x[j]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) v[1] += r[i] * r[i];
+    block_reduce_stats<2, 2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
 // alpha = rz / p^T Hp  (one workgroup, fixed-order sum of the partials)
 __global__ __launch_bounds__(1024) void k_cg_alpha(const double* __restrict__ part, int np, CgScalars* cs) {
     if (cs->done) return;
@@ -862,7 +878,8 @@ struct Work {
 }  // namespace
 
 // FP64 polish of x_dev (original order, n entries), in place; the starting
-// support is {j : |x_j| > support_tol}.
+// support is {j : |x_j| > support_tol}.  x_dev keeps its value when the
+// polished point's objective f_tau is larger.
 l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipStream_t s, int* rounds_out,
                         int64_t* pcg_iters_out, double support_tol, DevAlloc* al = nullptr) {
     *rounds_out = 0;
@@ -873,6 +890,20 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
     L1LS_TRY(W.init(I, s));
     const int64_t n = I->n;
     hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, x_dev, W.x, I->op_col_of, n);
+    // f_tau at the starting point (the polish keeps it when it does not improve)
+    auto objective = [&](const double* xv, double* f) -> l1ls_status {
+        W.spmv(xv, W.tm);
+        hipLaunchKernelGGL(k_axpby, g1d(I->m), dim3(L1LS_BLOCK), 0, s, W.tm, 1.0, I->b_op, -1.0, W.tm, I->m);
+        hipLaunchKernelGGL(k_obj_parts, dim3(kRedBlocks), dim3(L1LS_BLOCK), 0, s, xv, n, (const double*)W.tm, I->m,
+                           W.part);
+        double sums[2];
+        L1LS_TRY(W.host_sums(2, kRedBlocks, sums));
+        *f = tau * sums[0] + 0.5 * sums[1];
+        return L1LS_OK;
+    };
+    double f_in = 0.0;
+    HIP_TRY(hipMemcpyAsync(W.grad, W.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    L1LS_TRY(objective(W.x, &f_in));
     hipLaunchKernelGGL(k_support_from_x, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, support_tol, n);
     W.spmv_t(I->b_op, W.atb);
     const double slack = 1e-10;
@@ -908,7 +939,15 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
         hipLaunchKernelGGL(k_polish_apply, g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, W.mask, W.xs, W.atr, tau, slack,
                            cnt[0] > 0 ? 1 : 0, n);
     }
-    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, W.x, x_dev, I->op_col_pos, n);
+    // a polish that ends above the starting objective (a support still far
+    // from the solution's after the last round) returns the starting point
+    double f_out = 0.0;
+    L1LS_TRY(objective(W.x, &f_out));
+    const bool keep = f_out <= f_in;
+    if (std::getenv("L1LS_DEBUG_POLISH"))
+        std::fprintf(stderr, "l1ls polish: f_tau %.17g -> %.17g (%s)\n", f_in, f_out, keep ? "kept" : "reverted");
+    hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, keep ? W.x : W.grad, x_dev,
+                       I->op_col_pos, n);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     *rounds_out = std::min(rounds, 10);

@@ -101,11 +101,14 @@ def test_path_fp64_finish_reports_fp64_certificates():
         P, D, gap = L.l1ls_objective_gap(g, float(t), X[c].contiguous())
         assert reps[c]["rel_gap"] == gap, c
         assert reps[c]["converged"] == (1 if gap <= 1e-8 else 0), c
-        g32 = L.l1ls_objective_gap(g, float(t), X32[c].contiguous())[2]
+        P32, _, g32 = L.l1ls_objective_gap(g, float(t), X32[c].contiguous())
         if g32 <= 1e-8:
             assert torch.equal(X[c], X32[c]) and reps[c]["polish_rounds"] == 0, c   # nothing to finish
         else:
             assert reps[c]["polish_rounds"] >= 1, c
+        # the finish never returns a column with a larger objective f_tau
+        # (a polish that does not improve leaves the FP32 column)
+        assert P <= P32 * (1 + 1e-12), (c, P, P32)
         done += reps[c]["converged"]
     print(f"FP64-finished columns within 1e-8: {done} of {len(taus)}", flush=True)
     assert reps[-1]["converged"] == 1
