@@ -1193,7 +1193,11 @@ def cpu_baseline_scaled(args, cfg, n, nnz):
     workload: the same recipe (kappa, stages, s = n / sdiv) at n = 2^sample
     (the instance built by the oracle, not timed), a fixed number of timed
     iterations, and the rate scaled to the full instance by the ratio of the
-    stored nonzeros (both products are linear in nnz)."""
+    stored nonzeros (both products are linear in nnz).  The value is the
+    oracle's C form with OpenMP on every usable host core (its iterates are
+    the numpy oracle's bit for bit); the numpy oracle on one thread and the
+    C form on one thread are reported beside it."""
+    from oracle import cfista as CF
     from oracle import fista as F
     from oracle import instance as OI
 
@@ -1203,24 +1207,35 @@ def cpu_baseline_scaled(args, cfg, n, nnz):
     o = OI.Instance(ms_, ns, cfg["kappa"], max(1, ns // cfg["sdiv"]), 1.0, cfg["seed"], rounds=2)
     A = o.sparse_A()
     At = A.T.tocsr()
+    pair = CF.CsrPair(A)
     gen_s = time.perf_counter() - t0
-    mv, rmv = (lambda v: A @ v), (lambda v: At @ v)
-    t0 = time.perf_counter()
-    F.fista(mv, rmv, o.b, 1.0, o.L, 2)
-    per = (time.perf_counter() - t0) / 2
-    iters = max(3, min(args.cpu_iters, int(args.cpu_budget / max(per, 1e-9))))
-    t0 = time.perf_counter()
-    F.fista(mv, rmv, o.b, 1.0, o.L, iters)
-    dt = time.perf_counter() - t0
-    rate = iters / dt
     scale = A.nnz / float(nnz)
     host = host_description()
-    return {"value": rate * scale, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} FP64 FISTA iterations of the CPU oracle (numpy + scipy.sparse products, one thread) "
-                      f"on the same recipe at n = 2^{ns.bit_length() - 1} (nnz {A.nnz}; instance built by the oracle "
-                      f"in {gen_s:.1f} s, not timed): {rate:.3f} iters/s there, scaled by nnz "
-                      f"{A.nnz}/{nnz} to the full instance",
-            "rate_at_sample": rate, "sample_n": ns, "host": host}
+    cores = host["usable_cores"]
+
+    def rate_of(run, budget):
+        t0 = time.perf_counter()
+        run(2)
+        per = (time.perf_counter() - t0) / 2
+        iters = max(3, min(args.cpu_iters * 10, int(budget / max(per, 1e-9))))
+        t0 = time.perf_counter()
+        run(iters)
+        return iters, iters / (time.perf_counter() - t0)
+
+    it_c, rate_c = rate_of(lambda k: CF.fista(pair, o.b, 1.0, o.L, k, threads=cores), args.cpu_budget / 3)
+    it_c1, rate_c1 = rate_of(lambda k: CF.fista(pair, o.b, 1.0, o.L, k, threads=1), args.cpu_budget / 3)
+    mv, rmv = (lambda v: A @ v), (lambda v: At @ v)
+    it_np, rate_np = rate_of(lambda k: F.fista(mv, rmv, o.b, 1.0, o.L, k), args.cpu_budget / 3)
+    return {"value": rate_c * scale, "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{it_c} FP64 FISTA iterations of the CPU oracle in C with OpenMP on {cores} threads "
+                      f"(bitwise the numpy oracle's iterates) on the same recipe at n = 2^{ns.bit_length() - 1} "
+                      f"(nnz {A.nnz}; instance built by the oracle in {gen_s:.1f} s, not timed): {rate_c:.3f} "
+                      f"iters/s there, scaled by nnz {A.nnz}/{nnz} to the full instance",
+            "rate_at_sample": rate_c, "sample_n": ns,
+            "one_thread": {"c_iters_per_s": rate_c1 * scale, "numpy_iters_per_s": rate_np * scale,
+                           "c_rate_at_sample": rate_c1, "numpy_rate_at_sample": rate_np,
+                           "iterations": {"c": it_c1, "numpy": it_np}},
+            "host": host}
 
 
 def main():
