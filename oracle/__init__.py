@@ -15,7 +15,10 @@ squares problems", arXiv:1503.03520, that it follows):
                    generator that every random draw of an instance comes from.
 * ``instance``  -- the instance generator: Givens rounds, Sigma, IGen
                    (section 3.1), the SVD-known A of eq. (16) (section 4),
-                   operator products MvPA / MvPAt, explicit A for tests.
+                   operator products MvPA / MvPAt, explicit A for tests;
+                   IGen2 (section 3.2) for m < n over the same matrices.
+* ``cfista``    -- the FISTA of ``fista`` in C with OpenMP (fista_omp.c),
+                   bitwise the same iterates, for the CPU baseline.
 * ``fista``     -- FISTA (section 8.1), soft-thresholding, the Lasso duality
                    gap, power iteration for L.
 * ``bruteforce``-- sign-pattern enumeration of the reduced problem (13) for

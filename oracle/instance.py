@@ -57,6 +57,8 @@ TAG_PERM = 0x100    # | side
 TAG_ANGLE = 0x200   # | side
 TAG_XSTAR = 0x300
 TAG_SUBGRAD = 0x400
+TAG_IGEN2_PICK = 0x900   # bijection choosing the columns of B that N copies
+TAG_IGEN2_XI = 0xA00     # counter (k, 0, tag, 0): xi_k of N column k
 ANGLE_MAX_ATTEMPTS = 32
 FEISTEL_ROUNDS = 4
 
@@ -309,6 +311,77 @@ class Instance:
 
     def dense_A(self):
         return self.sparse_A().toarray()
+
+
+class IGen2Instance:
+    """Procedure IGen2 (section 3.2): an instance with m < n.
+
+    Inputs of the procedure and the readings taken here:
+    * B (m x m, rank m) is the generator's square A = Q Sigma G^T (eq. (16)
+      with n = m), one rotation stage per side; x* lies in its columns (the
+      procedure's S within the first m components): support, values, g and
+      e = tau B^{-T} g are those of ``Instance(m, m, ...)`` (step 3 with the
+      SVD-known inverse, B^{-T} = Q Sigma^{-1} G^T).
+    * N (m x (n - m)): column k is a copy of column p(k) of B, p injective,
+      drawn among the columns j with |g_j| >= 1/2 (positions 0..n-m-1 of a
+      random bijection of that list, tag TAG_IGEN2_PICK).  Then
+      N_k^T e = tau g_p and the rescaled column of step 4,
+      N~_k = xi_k tau / |N_k^T e| N_k, has scale |xi_k| / |g_p| <= 2;
+      xi_k = 2u - 1 from counter (k, 0, TAG_IGEN2_XI, 0).
+    * A = [B, N~], b = A x* + e = B x*_B + e (x* is zero on N~), and
+      A^T e = tau g with g_{m+k} = xi_k sign(N_k^T e), so x* is optimal
+      (eq. (15)); with |xi_k| < 1 the condition off S is strict and x* is
+      the unique minimiser when B_S has full rank.
+    * lambda_max(A A^T) = lambda_max(B (I + P D^2 P^T) B^T) <= 1 + max_k c_k^2
+      (sigma_1 = 1, P D the placement and scales of N~): the L used here.
+    """
+
+    def __init__(self, m, n, kappa, s, tau, seed, rounds=1):
+        if not (m >= 2 and m % 2 == 0 and n > m):
+            raise ValueError("IGen2 needs n > m >= 2, m even")
+        if rounds != 1:
+            raise ValueError("IGen2 is built with one rotation stage per side")
+        if not (0 <= s <= m):
+            raise ValueError("need 0 <= s <= m")
+        self.m, self.n, self.kappa, self.s = int(m), int(n), float(kappa), int(s)
+        self.tau, self.seed, self.rounds = float(tau), int(seed), int(rounds)
+        Bi = Instance(m, m, kappa, s, tau, seed, rounds=rounds)
+        self.Bi = Bi
+        key = Bi.key
+        elig = np.flatnonzero(np.abs(Bi.g) >= 0.5)
+        k = np.arange(n - m)
+        if n - m > elig.size:
+            raise ValueError("IGen2: n - m exceeds the columns of B eligible for N")
+        self.p = elig[permutation(k, elig.size, TAG_IGEN2_PICK, key)]
+        w0, w1, w2, w3 = philox4x32_10(k, 0, TAG_IGEN2_XI, 0, key)
+        self.xi = 2.0 * unit_double(w0, w1) - 1.0
+        B = Bi.sparse_A()
+        Bc = B.tocsc()
+        dots = (Bc.T @ Bi.e)[self.p]            # N_k^T e, k = 0 .. n-m-1
+        self.c = self.xi * tau / np.abs(dots)
+        self.N_tilde = (Bc[:, self.p] @ sp.diags(self.c)).tocsc()
+        A = sp.hstack([B, self.N_tilde], format="csr")
+        A.sort_indices()
+        self._A = A
+        self.support = Bi.support
+        self.xstar = np.concatenate([Bi.xstar, np.zeros(n - m)])
+        self.g = np.concatenate([Bi.g, self.xi * np.sign(dots)])
+        self.e = Bi.e
+        self.b = Bi.b
+        self.fstar = Bi.fstar
+        self.L = float(1.0 + np.max(self.c ** 2)) if n > m else 1.0
+
+    def sparse_A(self):
+        return self._A.copy()
+
+    def dense_A(self):
+        return self._A.toarray()
+
+    def matvec(self, x):
+        return self._A @ x
+
+    def rmatvec(self, y):
+        return self._A.T @ y
 
 
 class LocalInstance:
