@@ -181,6 +181,21 @@ l1ls_status l1ls_set_allocator(const l1ls_allocator* allocator);
  * m < 2^29 (else L1LS_E_UNSUPPORTED).  l1ls_generate uses rounds = 1, both
  * storages and the STAGE layout on the null stream.  The call returns after
  * the build finished.
+ *
+ * m < n builds Procedure IGen2 (section 3.2) instead: B (m x m) is the
+ * instance above with n = m, x* (s <= m nonzeros) and g lie in its columns
+ * and e = tau B^{-T} g; column k of N (m x (n-m)) is a copy of column p(k) of
+ * B, p injective over the columns j with |g_j| >= 1/2 (a random bijection of
+ * that list), rescaled by step 4 to N~_k = xi_k tau / |N_k^T e| N_k, xi_k
+ * uniform on [-1, 1]; A = [B, N~] and b = A x* + e (x* is zero on N~).
+ * Then A^T e = tau g with g_{m+k} = xi_k sign(N_k^T e), and the instance's
+ * L = 1 + max_k (xi_k tau / |N_k^T e|)^2 bounds lambda_max(A^T A).  Only the
+ * stored operator exists (A has no rotation form): rounds must be 1 and the
+ * storage must include a CSR/CSC (F32 and/or F64; the FP64 copy is always
+ * kept), without BLK32 or MF_WINDOWS (else L1LS_E_UNSUPPORTED); m >= 2
+ * even, 0 <= s <= m, and n - m at most the number of B's columns with
+ * |g_j| >= 1/2 (about 0.44 m + s; else L1LS_E_ARG).  The rotation tables and
+ * sigma in l1ls_info describe B.
  */
 l1ls_status l1ls_generate(int64_t m, int64_t n, double kappa, int64_t s,
                           double tau, uint64_t seed, l1ls_instance** out);

@@ -20,7 +20,7 @@ FLAGS = [
     "-Wno-unused-result",
 ]
 SOURCES = ["generator.hip", "fista.hip", "operator.hip", "newton.hip", "mf.hip", "batch.hip", "path.hip", "serve.hip",
-           "blocks.hip", "onchip.hip", "sgt.hip", "alloc.hip", "pcdm.hip", "tune.hip", "window.hip"]
+           "blocks.hip", "onchip.hip", "sgt.hip", "alloc.hip", "pcdm.hip", "tune.hip", "window.hip", "igen2.hip"]
 
 
 def _compile(src):

@@ -85,6 +85,17 @@ struct DevArena {
         for (size_t i = ptrs.size(); i-- > 0;) dev_free(al, ptrs[i].first, ptrs[i].second, true);
         ptrs.clear();
     }
+    // Free one block of the list (nothing queued may still use it; nullptr:
+    // nothing to do).
+    void free_one(void* p) {
+        if (!p) return;
+        for (size_t i = 0; i < ptrs.size(); ++i)
+            if (ptrs[i].first == p) {
+                dev_free(al, p, ptrs[i].second);
+                ptrs.erase(ptrs.begin() + (long)i);
+                return;
+            }
+    }
 };
 
 // Pair tables of one side: bijection pi (position -> index), its inverse,
@@ -99,6 +110,7 @@ struct SideTables {
 struct l1ls_instance {
     int64_t m = 0, n = 0, s = 0, nnz = 0;
     int32_t rounds = 1;
+    bool igen2 = false;           // m < n: Procedure IGen2 (igen2.hip); stored operator only
     uint32_t storage = 0;
     int32_t layout = 0;
     double kappa = 1, tau = 1, L = 1, fstar = 0;

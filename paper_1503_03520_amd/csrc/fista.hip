@@ -746,6 +746,7 @@ extern "C" l1ls_status l1ls_apply(const l1ls_instance* I, int32_t trans, int32_t
     if (prec != L1LS_F32 && prec != L1LS_F64) return L1LS_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (op == L1LS_OP_MATRIX_FREE) {
+        if (!I->mf_emb) return L1LS_E_UNSUPPORTED;  // no rotation form (IGen2 instances)
         if (prec == L1LS_F64) return apply_matrix_free<double>(I, trans, (const double*)in, (double*)out, s);
         return apply_matrix_free<float>(I, trans, (const float*)in, (float*)out, s);
     }

@@ -325,6 +325,7 @@ template l1ls_status apply_side<float>(const SideTables&, int, bool, float*, flo
 l1ls_status build_mf_tables(l1ls_instance* I, hipStream_t s);
 l1ls_status build_blocks(l1ls_instance* I, hipStream_t s, DevArena& tmp);
 l1ls_status build_stored_windows(l1ls_instance* I, hipStream_t s);
+l1ls_status igen2_extend(l1ls_instance* I, int64_t n, hipStream_t s);
 
 // l1ls_generate_ex with the instance's device memory (and the build's
 // temporaries) from `al` (nullptr: hipMalloc).
@@ -337,6 +338,33 @@ l1ls_status generate_with(int64_t m, int64_t n, double kappa, int64_t s, double 
     const int layout = opts ? opts->layout : L1LS_LAYOUT_STAGE;
     if (layout != L1LS_LAYOUT_NATURAL && layout != L1LS_LAYOUT_STAGE) return L1LS_E_ARG;
     hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
+    if (m < n) {
+        // Procedure IGen2 (section 3.2): the square instance B (m x m, one
+        // stage), extended in place by the rescaled columns N~ (igen2.hip)
+        if (!(m >= 2 && (m % 2) == 0 && n < ((int64_t)1 << 31))) return L1LS_E_ARG;
+        if (!(s >= 0 && s <= m)) return L1LS_E_ARG;
+        if (rounds != 1 || !(storage & (L1LS_STORE_F32 | L1LS_STORE_F64)) ||
+            (storage & (L1LS_STORE_BLK32 | L1LS_STORE_MF_WINDOWS)))
+            return L1LS_E_UNSUPPORTED;
+        l1ls_gen_opts o2;
+        o2.rounds = 1;
+        o2.storage = (storage | L1LS_STORE_F64) & ~L1LS_STORE_WINDOWS;
+        o2.stream = stream;
+        o2.layout = layout;
+        l1ls_instance* J = nullptr;
+        L1LS_TRY(generate_with(m, m, kappa, s, tau, seed, &o2, al, &J));
+        l1ls_status st = igen2_extend(J, n, stream);
+        J->storage = storage | L1LS_STORE_F64;
+        if (st == L1LS_OK && (storage & L1LS_STORE_WINDOWS)) st = build_stored_windows(J, stream);
+        if (st != L1LS_OK) {
+            (void)hipStreamSynchronize(stream);
+            J->arena.release();
+            delete J;
+            return st;
+        }
+        *out = J;
+        return L1LS_OK;
+    }
     if (!(n >= 2 && m >= n && (m % 2) == 0 && (n % 2) == 0 && m < ((int64_t)1 << 31))) return L1LS_E_ARG;
     if (!(s >= 0 && s <= n) || !(kappa >= 1.0) || !is_finite(kappa) || !(tau > 0.0) || !is_finite(tau))
         return L1LS_E_ARG;

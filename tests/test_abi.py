@@ -40,7 +40,6 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("m,n,kappa,s,tau,rounds", [
-    (100, 200, 10.0, 1, 1.0, 1),    # m < n
     (101, 50, 10.0, 1, 1.0, 1),     # m odd
     (100, 51, 10.0, 1, 1.0, 1),     # n odd
     (100, 50, 0.5, 1, 1.0, 1),      # kappa < 1
@@ -58,6 +57,22 @@ def test_generate_rejects_invalid_arguments(m, n, kappa, s, tau, rounds):
     o = L.GenOpts(rounds, 3, None, 1)
     st = L.lib().l1ls_generate_ex(m, n, kappa, s, tau, 1, ctypes.byref(o), ctypes.byref(h))
     assert st == -1 and not h.value
+
+
+@pytest.mark.parametrize("m,n,kappa,s,rounds,storage,status", [
+    (101, 200, 10.0, 1, 1, 3, -1),                        # IGen2 (m < n): m odd
+    (0, 200, 10.0, 0, 1, 3, -1),                          # ... m < 2
+    (100, 200, 10.0, 101, 1, 3, -1),                      # ... s > m
+    (100, 200, 0.5, 1, 1, 3, -1),                         # ... kappa < 1
+    (100, 200, 10.0, 1, 2, 3, -6),                        # ... one stage only
+    (100, 200, 10.0, 1, 1, 0, -6),                        # ... a stored operator
+    (100, 200, 10.0, 1, 1, 3 | 8, -6),                    # ... no matrix-free tables
+])
+def test_generate_igen2_argument_checks(m, n, kappa, s, rounds, storage, status):
+    h = ctypes.c_void_p()
+    o = L.GenOpts(rounds, storage, None, 1)
+    st = L.lib().l1ls_generate_ex(m, n, kappa, s, 1.0, 1, ctypes.byref(o), ctypes.byref(h))
+    assert st == status and not h.value
 
 
 @pytest.mark.parametrize("rounds,storage,layout,n,status", [
