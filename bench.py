@@ -1126,7 +1126,9 @@ def bench_fista(args):
     extra["host"] = host_description()
     extra["autotuned_tile_schedule"] = {
         "residual": L.tune_get("fista_f32_residual/%d" % (m - 1).bit_length()),
-        "transpose": L.tune_get("fista_f32_transpose/%d" % (n - 1).bit_length())}
+        "transpose": L.tune_get("fista_f32_transpose/%d" % (n - 1).bit_length()),
+        "residual_windowed": L.tune_get("fista_f32_residual_win/%d" % (m - 1).bit_length()),
+        "transpose_windowed": L.tune_get("fista_f32_transpose_win/%d" % (n - 1).bit_length())}
 
     value = st["iters_per_s"]
     line = {

@@ -256,57 +256,68 @@ const double* mf_b<double>(const l1ls_instance* I) { return I->mf_b64; }
 constexpr int kResVariants = 4;  // (10, nt), (8, nt), (16, nt), (10, plain)
 constexpr int kTrVariants = 4;   // (16, nt), (12, nt), (16, plain), (8, nt)
 
-template <typename T, int NQ, bool NT>
-void residual_go(l1ls_fista* F, const T* x, double beta, int init, int slot, int stats) {
+// The passes over the stored CSR/CSC: idx and vec are the column (row)
+// indices and the gathered vector (x, r_y), or, for the windowed gathers
+// (XCD placement), the positions in the bucketed copy and the copy.
+template <typename T, int NQ, bool NT, bool XCD>
+void residual_go(l1ls_fista* F, const int32_t* idx, const T* x, double beta, int init, int slot, int stats) {
     const l1ls_instance* I = F->I;
-    hipLaunchKernelGGL((k_residual<T, NQ, NT>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr, I->csr_col,
+    hipLaunchKernelGGL((k_residual<T, NQ, NT, XCD>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream, I->csr_ptr, idx,
                        csr_vals<T>(I), x, b_vec<T>(I), (T*)F->rx, (T*)F->ry, (T)beta, I->m, init,
                        F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
 }
 
-template <typename T>
-void residual_variant(l1ls_fista* F, int v, const T* x, double beta, int init, int slot, int stats) {
+template <typename T, bool XCD = false>
+void residual_variant(l1ls_fista* F, int v, const int32_t* idx, const T* x, double beta, int init, int slot,
+                      int stats) {
     if constexpr (std::is_same<T, float>::value) {
         switch (v) {
-            case 1: return residual_go<float, 8, true>(F, x, beta, init, slot, stats);
-            case 2: return residual_go<float, 16, true>(F, x, beta, init, slot, stats);
-            case 3: return residual_go<float, 10, false>(F, x, beta, init, slot, stats);
+            case 1: return residual_go<float, 8, true, XCD>(F, idx, x, beta, init, slot, stats);
+            case 2: return residual_go<float, 16, true, XCD>(F, idx, x, beta, init, slot, stats);
+            case 3: return residual_go<float, 10, false, XCD>(F, idx, x, beta, init, slot, stats);
             default: break;
         }
     }
-    residual_go<T, 10, true>(F, x, beta, init, slot, stats);
+    residual_go<T, 10, true, XCD>(F, idx, x, beta, init, slot, stats);
 }
 
-template <typename T, int NQ, bool NT>
-void transpose_go(l1ls_fista* F, const T* xc, T* xp, double beta, int stats) {
+template <typename T, int NQ, bool NT, bool XCD>
+void transpose_go(l1ls_fista* F, const int32_t* idx, const T* ry, const T* xc, T* xp, double beta, int stats) {
     const l1ls_instance* I = F->I;
-    hipLaunchKernelGGL((k_transpose_prox<T, NQ, NT>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream, I->csc_ptr,
-                       I->csc_row, csc_vals<T>(I), (const T*)F->ry, xc, xp, (T)beta, (T)F->L, (T)(F->tau / F->L),
-                       I->n, F->k2part, F->gs, stats);
+    hipLaunchKernelGGL((k_transpose_prox<T, NQ, NT, XCD>), dim3(F->g2), dim3(L1LS_BLOCK), 0, F->stream, I->csc_ptr,
+                       idx, csc_vals<T>(I), ry, xc, xp, (T)beta, (T)F->L, (T)(F->tau / F->L), I->n, F->k2part, F->gs,
+                       stats);
 }
 
-template <typename T>
-void transpose_variant(l1ls_fista* F, int v, const T* xc, T* xp, double beta, int stats) {
+template <typename T, bool XCD = false>
+void transpose_variant(l1ls_fista* F, int v, const int32_t* idx, const T* ry, const T* xc, T* xp, double beta,
+                       int stats) {
     if constexpr (std::is_same<T, float>::value) {
         switch (v) {
-            case 1: return transpose_go<float, 12, true>(F, xc, xp, beta, stats);
-            case 2: return transpose_go<float, 16, false>(F, xc, xp, beta, stats);
-            case 3: return transpose_go<float, 8, true>(F, xc, xp, beta, stats);
+            case 1: return transpose_go<float, 12, true, XCD>(F, idx, ry, xc, xp, beta, stats);
+            case 2: return transpose_go<float, 16, false, XCD>(F, idx, ry, xc, xp, beta, stats);
+            case 3: return transpose_go<float, 8, true, XCD>(F, idx, ry, xc, xp, beta, stats);
             default: break;
         }
     }
-    transpose_go<T, 16, true>(F, xc, xp, beta, stats);
+    transpose_go<T, 16, true, XCD>(F, idx, ry, xc, xp, beta, stats);
 }
 
 // The autotuner's choice for the stored FP32 passes of an instance of this
 // size: taken from the cache, or measured now (each variant of the first
 // residual pass, which the solver runs anyway and which only depends on x_0,
 // and of the transpose pass into a scratch copy of x_0: one warm-up and
-// three timed launches each, fastest kept) and cached per size class.
+// three timed launches each, fastest kept) and cached per size class.  The
+// windowed passes (placed on the XCDs, gathering from the bucketed copies)
+// have choices of their own: x_0 and then the first pass's r_y are bucketed
+// before their variants are timed.
 l1ls_status tune_fista_f32(l1ls_fista* F) {
     const l1ls_instance* I = F->I;
-    const std::string kr = "fista_f32_residual/" + std::to_string(tune_size_class(I->m));
-    const std::string kt = "fista_f32_transpose/" + std::to_string(tune_size_class(I->n));
+    const bool w = F->sw;
+    const std::string kr = std::string(w ? "fista_f32_residual_win/" : "fista_f32_residual/") +
+                           std::to_string(tune_size_class(I->m));
+    const std::string kt = std::string(w ? "fista_f32_transpose_win/" : "fista_f32_transpose/") +
+                           std::to_string(tune_size_class(I->n));
     int vr = tune_lookup(kr), vt = tune_lookup(kt);
     if (vr >= 0 && vt >= 0) {
         F->vres = vr < kResVariants ? vr : 0;
@@ -338,17 +349,33 @@ l1ls_status tune_fista_f32(l1ls_fista* F) {
     };
     l1ls_status st = L1LS_OK;
     const float* x0 = (const float*)F->x[0];
+    const int32_t* ridx = w ? I->sw_idx[0] : I->csr_col;
+    const int32_t* tidx = w ? I->sw_idx[1] : I->csc_row;
+    const float* xg = w ? (const float*)F->ux : x0;
+    const float* ryg = w ? (const float*)F->uy : (const float*)F->ry;
+    auto residual = [&](int v) {
+        if (w)
+            residual_variant<float, true>(F, v, ridx, xg, 0.0, 1, 0, 1);
+        else
+            residual_variant<float, false>(F, v, ridx, xg, 0.0, 1, 0, 1);
+    };
+    if (w) stored_window_scatter(I, 0, x0, F->ux, nullptr, F->stream);
     if (vr < 0) {
         float bms = 0.f;
-        for (int v = 0; v < kResVariants && st == L1LS_OK; ++v)
-            st = time_it([&] { residual_variant<float>(F, v, x0, 0.0, 1, 0, 1); }, &bms, v, &vr);
+        for (int v = 0; v < kResVariants && st == L1LS_OK; ++v) st = time_it([&] { residual(v); }, &bms, v, &vr);
     }
     if (vt < 0 && st == L1LS_OK) {
+        // r_y of the first pass (any variant: they agree bit for bit)
+        residual(0);
+        if (w) stored_window_scatter(I, 1, (const float*)F->ry, F->uy, nullptr, F->stream);
         float bms = 0.f;
         for (int v = 0; v < kTrVariants && st == L1LS_OK; ++v)
             st = time_it([&] {
                 (void)hipMemcpyAsync(xs, x0, I->n * sizeof(float), hipMemcpyDeviceToDevice, F->stream);
-                transpose_variant<float>(F, v, x0, xs, 0.0, 1);
+                if (w)
+                    transpose_variant<float, true>(F, v, tidx, ryg, x0, xs, 0.0, 1);
+                else
+                    transpose_variant<float, false>(F, v, tidx, ryg, x0, xs, 0.0, 1);
             }, &bms, v, &vt);
     }
     (void)hipEventDestroy(e0);
@@ -375,10 +402,7 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
             // bucket x_k by row window, then the CSR pass over the bucketed copy
             L1LS_TRY(timed(F, 3, [&] { stored_window_scatter(I, 0, x, F->ux, done_flag(F), F->stream); }));
             return timed(F, 0, [&] {
-                hipLaunchKernelGGL((k_residual<float, 10, true, true>), dim3(F->g1), dim3(L1LS_BLOCK), 0, F->stream,
-                                   I->csr_ptr, I->sw_idx[0], I->csr_v32, (const float*)F->ux, I->b32_op,
-                                   (float*)F->rx, (float*)F->ry, (float)beta, I->m, init,
-                                   F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats);
+                residual_variant<float, true>(F, F->vres, I->sw_idx[0], (const float*)F->ux, beta, init, slot, stats);
             });
         }
     }
@@ -396,7 +420,7 @@ l1ls_status launch_residual(l1ls_fista* F, const T* x, double beta, int init, in
             mf_residual_launch<T>(I, x, (T*)F->wbuf, mf_b<T>(I), rx_prev, rx_out, (T*)F->tbuf, (T)beta, init,
                                   F->k1part + (size_t)slot * 3 * F->g1, F->gs, stats, F->stream);
         });
-    return timed(F, 0, [&] { residual_variant<T>(F, F->vres, x, beta, init, slot, stats); });
+    return timed(F, 0, [&] { residual_variant<T>(F, F->vres, I->csr_col, x, beta, init, slot, stats); });
 }
 
 // xp holds x_{k-2}; x_k goes to xo (== xp for the stored passes).
@@ -408,9 +432,7 @@ l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double be
             // bucket r_y by column window, then the CSC pass over the bucketed copy
             L1LS_TRY(timed(F, 4, [&] { stored_window_scatter(I, 1, (const float*)F->ry, F->uy, done_flag(F), F->stream); }));
             return timed(F, 1, [&] {
-                hipLaunchKernelGGL((k_transpose_prox<float, 16, true, true>), dim3(F->g2), dim3(L1LS_BLOCK), 0,
-                                   F->stream, I->csc_ptr, I->sw_idx[1], I->csc_v32, (const float*)F->uy, xc, xp,
-                                   (float)beta, (float)F->L, (float)(F->tau / F->L), I->n, F->k2part, F->gs, stats);
+                transpose_variant<float, true>(F, F->vtr, I->sw_idx[1], (const float*)F->uy, xc, xp, beta, stats);
             });
         }
     }
@@ -426,7 +448,7 @@ l1ls_status launch_transpose(l1ls_fista* F, const T* xc, T* xp, T* xo, double be
             mf_transpose_launch<T>(I, (T*)F->tbuf, (T*)F->wbuf, xc, xp, xo, (T)beta, (T)F->L,
                                    (T)(F->tau / F->L), F->k2part, F->gs, stats, F->stream);
         });
-    return timed(F, 1, [&] { transpose_variant<T>(F, F->vtr, xc, xp, beta, stats); });
+    return timed(F, 1, [&] { transpose_variant<T>(F, F->vtr, I->csc_row, (const T*)F->ry, xc, xp, beta, stats); });
 }
 
 // Gap test at iteration k from the partials of its passes: one workgroup
@@ -616,7 +638,7 @@ extern "C" l1ls_status l1ls_fista_create(const l1ls_instance* I, const l1ls_solv
     // stored FP32 passes: the autotuner's tile schedule (the timing runs only
     // the first residual pass and the transpose pass into scratch; the state
     // is set up again just below)
-    if (F->prec == L1LS_F32 && !F->mf && !F->blk && !F->sw && (st = tune_fista_f32(F)) != L1LS_OK) return fail(st);
+    if (F->prec == L1LS_F32 && !F->mf && !F->blk && (st = tune_fista_f32(F)) != L1LS_OK) return fail(st);
     hipLaunchKernelGGL(k_init_gap, dim3(1), dim3(1), 0, s, F->gs);
     if (F->prec == L1LS_F64)
         st = launch_residual<double>(F, (const double*)x0, 0.0, 1, 0, 1);

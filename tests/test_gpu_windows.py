@@ -56,3 +56,26 @@ def test_windowed_solve_to_tolerance_and_polish():
     x, rep, st = L.l1ls_solve_fista(win, max_iter=2000, rel_gap_tol=1e-8, check_every=32, precision=L.F32, polish=1)
     assert rep["rel_gap"] <= 1e-8 and rep["rel_err"] <= 1e-9
     win.free()
+
+
+def test_windowed_tile_schedules_are_bitwise_the_plain_passes():
+    # every tile schedule the autotuner can pick for the windowed passes (its
+    # own cache keys) gives the plain passes' iterates bit for bit
+    m, n, kappa, s, tau, seed, r = CASES[1]
+    plain = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=L.STORE_F32)
+    win = L.l1ls_generate(m, n, kappa, s, tau, seed, rounds=r, storage=L.STORE_F32 | L.STORE_WINDOWS)
+    kr = "fista_f32_residual_win/%d" % int(np.ceil(np.log2(m)))
+    kt = "fista_f32_transpose_win/%d" % int(np.ceil(np.log2(n)))
+    old = (L.tune_get(kr), L.tune_get(kt))
+    ref, rref, _ = L.l1ls_solve_fista(plain, max_iter=40, rel_gap_tol=0.0, check_every=8, precision=L.F32)
+    try:
+        for vr, vt in ((0, 0), (1, 1), (2, 2), (3, 3), (2, 1)):
+            L.tune_set(kr, vr)
+            L.tune_set(kt, vt)
+            x, rep, _ = L.l1ls_solve_fista(win, max_iter=40, rel_gap_tol=0.0, check_every=8, precision=L.F32)
+            assert torch.equal(x, ref) and rep["primal"] == rref["primal"], (vr, vt)
+    finally:
+        L.tune_set(kr, old[0])
+        L.tune_set(kt, old[1])
+    plain.free()
+    win.free()
