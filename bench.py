@@ -58,6 +58,20 @@ def read_profile_summary(path=PROFILE_SUMMARY):
     return out
 
 
+# key: (kernel name pattern, rank of the grid among the pattern's grids,
+# largest first).  The plain stored passes run without XCD placement,
+# the windowed ones with it; the windowed gathers' bucketing pass runs
+# once per side, r_y's (m sources) with the larger grid.
+PASS_KERNELS = {"residual": (r"k_residual<float, \d+, (true|false), false>", 0),
+                "transpose_prox": (r"k_transpose_prox<float, \d+, (true|false), false>", 0),
+                "residual_win": (r"k_residual<float, \d+, (true|false), true>", 0),
+                "transpose_prox_win": (r"k_transpose_prox<float, \d+, (true|false), true>", 0),
+                "bucket_r_y": (r"k_sw_scatter", 0), "bucket_x": (r"k_sw_scatter", 1),
+                "blk_residual": (r"k_blk_residual<false>", 0), "blk_transpose_prox": (r"k_blk_transpose_prox<false>", 0),
+                "mf_res_qt": (r"k_mf_res_qt<float, 2, 0, float>", 0), "mf_prox_gt": (r"k_mf_prox_gt<float, 2>", 0),
+                "mf_win_scatter": (r"k_win_scatter<float>", 0)}
+
+
 def write_profile_summary(args):
     """Summarise rocprofv3 CSV output (kernel trace + FETCH_SIZE / WRITE_SIZE runs
     of this script, and the same counters for a plain 1 GiB copy) into a text file."""
@@ -73,18 +87,7 @@ def write_profile_summary(args):
 
     import re
 
-    # key: (kernel name pattern, rank of the grid among the pattern's grids,
-    # largest first).  The plain stored passes run without XCD placement,
-    # the windowed ones with it; the windowed gathers' bucketing pass runs
-    # once per side, r_y's (m sources) with the larger grid.
-    names = {"residual": (r"k_residual<float, \d+, (true|false), false>", 0),
-             "transpose_prox": (r"k_transpose_prox<float, \d+, (true|false), false>", 0),
-             "residual_win": (r"k_residual<float, \d+, (true|false), true>", 0),
-             "transpose_prox_win": (r"k_transpose_prox<float, \d+, (true|false), true>", 0),
-             "bucket_r_y": (r"k_sw_scatter", 0), "bucket_x": (r"k_sw_scatter", 1),
-             "blk_residual": (r"k_blk_residual<false>", 0), "blk_transpose_prox": (r"k_blk_transpose_prox<false>", 0),
-             "mf_res_qt": (r"k_mf_res_qt<float, 2, 0, float>", 0), "mf_prox_gt": (r"k_mf_prox_gt<float, 2>", 0),
-             "mf_win_scatter": (r"k_win_scatter<float>", 0)}
+    names = PASS_KERNELS
     # The bench launches these kernels at the headline size and (in the
     # n = 2^20 leg) at a smaller one: each figure is taken over the dispatches
     # with the kernel's largest grid (the headline instance's), or the grid
@@ -144,6 +147,87 @@ def write_profile_summary(args):
         lines.append(f"{key}_fetch_kib_median: {fk:.1f}")
         lines.append(f"{key}_write_kib_median: {wk:.1f}")
         lines.append(f"{key}_traffic_bytes: {(fk * f_scale + wk * w_scale) * 1024:.0f}")
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+# Counters of the vector memory path read for the stored passes (two
+# rocprofv3 --pmc runs, each within one run's counter limits), and what the
+# summary derives from them.  GRBM_GUI_ACTIVE is summed over the 8 XCDs and
+# the TCP_ (vector L1) counters over the 256 CUs.
+PMC_PASSES = [
+    "TCP_UTCL1_TRANSLATION_MISS_sum TCP_UTCL1_REQUEST_sum TCP_TCC_READ_REQ_sum TCP_TOTAL_CACHE_ACCESSES_sum "
+    "TCC_REQ_sum TCC_HIT_sum GRBM_GUI_ACTIVE SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_BUSY_CYCLES",
+    "TA_BUSY_avr TA_ADDR_STALLED_BY_TC_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum TCP_TCR_TCP_STALL_CYCLES_sum "
+    "TCP_UTCL1_TRANSLATION_HIT_sum TCP_TCC_READ_REQ_LATENCY_sum TCC_TAG_STALL_sum TCC_BUSY_avr TCC_EA0_RDREQ_sum "
+    "GRBM_GUI_ACTIVE"]
+
+
+def write_counter_summary(args):
+    """Per-kernel medians of the PMC_PASSES counters (rocprofv3 CSV directories
+    in --pmc-dirs) for the stored passes, with the latency figures they give."""
+    import csv
+    import re
+    import statistics
+
+    per = {}
+    for d in args.pmc_dirs:
+        rows = []
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith("counter_collection.csv"):
+                    rows += list(csv.DictReader(open(os.path.join(root, f))))
+        if not rows:
+            raise SystemExit(f"no *counter_collection.csv under {d}")
+        for key, (pat, rank) in PASS_KERNELS.items():
+            rs = [r for r in rows if re.search(pat, r["Kernel_Name"])]
+            grids = sorted({int(r.get("Grid_Size") or 0) for r in rs}, reverse=True)
+            if len(grids) <= rank:
+                continue
+            by = {}
+            for r in rs:
+                if int(r.get("Grid_Size") or 0) == grids[rank]:
+                    by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            per.setdefault(key, {}).update({c: statistics.median(v) for c, v in by.items()})
+    cus, xcds = 256, 8
+    lines = ["# rocprofv3 counters of the vector memory path, stored FISTA passes (*_win: windowed gathers, "
+             "bucket_*: their bucketing passes), " + (args.stats_title or "n=2^26, m=2^27, 2 stages"),
+             "# medians over each kernel's dispatches with its largest grid; GRBM_GUI_ACTIVE summed over 8 XCDs,",
+             "# TCP_* (vector L1) over 256 CUs, TCC_* (L2) over all channels",
+             *[f"# counters:     rocprofv3 --pmc {c} --output-format csv -d <dir> -o bench -- {args.pmc_command}"
+               for c in PMC_PASSES],
+             "# summary:      python3 bench.py --counter-summary --pmc-dirs <dir> <dir> --out <file>",
+             "# derived: cycles = GRBM_GUI_ACTIVE / 8 (per XCD, i.e. per CU); l2_read_latency = "
+             "TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum;",
+             "#   reads_in_flight_per_cu = TCP_TCC_READ_REQ_LATENCY_sum / 256 / cycles; vl1d_waiting_on_l2 = "
+             "TCP_PENDING_STALL_CYCLES_sum / 256 / cycles;",
+             "#   vl1d_stalled_issuing_to_l2 = TCP_TCR_TCP_STALL_CYCLES_sum / 256 / cycles; ta_stalled_by_vl1d = "
+             "TA_ADDR_STALLED_BY_TC_CYCLES_sum / 256 / cycles;",
+             "#   l2_hit = TCC_HIT_sum / TCC_REQ_sum; utcl1_miss = TCP_UTCL1_TRANSLATION_MISS_sum / TCP_UTCL1_REQUEST_sum",
+             f"kernel_source_hash: {kernel_source_hash()}"]
+    for key, c in per.items():
+        for name in sorted(c):
+            lines.append(f"{key}.{name}: {c[name]:.6g}")
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        req = c.get("TCP_TCC_READ_REQ_sum", 0.0)
+        lat = c.get("TCP_TCC_READ_REQ_LATENCY_sum")
+        derived = {}
+        if lat is not None and req > 0:
+            derived["l2_read_latency_cycles"] = lat / req
+        if lat is not None and cyc > 0:
+            derived["reads_in_flight_per_cu"] = lat / cus / cyc
+        for dname, cname in (("vl1d_waiting_on_l2", "TCP_PENDING_STALL_CYCLES_sum"),
+                             ("vl1d_stalled_issuing_to_l2", "TCP_TCR_TCP_STALL_CYCLES_sum"),
+                             ("ta_stalled_by_vl1d", "TA_ADDR_STALLED_BY_TC_CYCLES_sum")):
+            if cname in c and cyc > 0:
+                derived[dname] = c[cname] / cus / cyc
+        if c.get("TCC_REQ_sum"):
+            derived["l2_hit"] = c.get("TCC_HIT_sum", 0.0) / c["TCC_REQ_sum"]
+        if c.get("TCP_UTCL1_REQUEST_sum"):
+            derived["utcl1_miss"] = c.get("TCP_UTCL1_TRANSLATION_MISS_sum", 0.0) / c["TCP_UTCL1_REQUEST_sum"]
+        for dname, v in derived.items():
+            lines.append(f"{key}.{dname}: {v:.4g}")
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -1265,6 +1349,9 @@ def main():
         ap.add_argument(f"--{d}")
     ap.add_argument("--stats-summary", action="store_true",
                     help="write the top kernels of the rocprofv3 --stats run in --kt to --out")
+    ap.add_argument("--counter-summary", action="store_true",
+                    help="summarise the PMC_PASSES counter runs in --pmc-dirs into --out")
+    ap.add_argument("--pmc-dirs", nargs="*", default=[])
     ap.add_argument("--stats-title", default="")
     ap.add_argument("--kt-command", default="", help="profile summary: the kernel-trace command it came from")
     ap.add_argument("--pmc-command", default="", help="profile summary: the counter command it came from")
@@ -1312,6 +1399,9 @@ def main():
         return
     if args.stats_summary:
         write_stats_summary(args)
+        return
+    if args.counter_summary:
+        write_counter_summary(args)
         return
     if args.copy_calibration:
         import torch

@@ -158,7 +158,8 @@ l1ls_status build_windows_side(l1ls_instance* I, int k, hipStream_t s) {
     if ((int64_t)units * kSwUnit * (int64_t)sizeof(float) >= ((int64_t)1 << 32)) return fail(L1LS_E_UNSUPPORTED);
     uint16_t* src = nullptr;
     int32_t* out = nullptr;
-    if ((st = I->arena.alloc(&src, std::max<int64_t>(units, 1))) != L1LS_OK) return fail(st);
+    // one spare entry: the bucketing pass reads offsets two at a time
+    if ((st = I->arena.alloc(&src, (int64_t)units + 2)) != L1LS_OK) return fail(st);
     if ((st = I->arena.alloc(&out, std::max<int64_t>(I->nnz, 1))) != L1LS_OK) return fail(st);
     if (hipMemcpyAsync(cursor, base, (nT * nc + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(L1LS_E_HIP);
@@ -193,45 +194,75 @@ l1ls_status build_stored_windows(l1ls_instance* I, hipStream_t s) {
 namespace {
 
 // u = the bucketed copy of src (N sources) for one side: one workgroup per
-// chunk stages the chunk in LDS, then writes the chunk's units (consecutive
-// in u) as 16-byte stores; a unit that runs past the chunk's end reads its
-// tail from src.  A thread's first kSwPre unit offsets are loaded beside the
-// staging, so the stores wait on LDS only.
-constexpr int kSwPre = 8;
+// chunk stages the chunk and the 3 sources after it in LDS (zero past N),
+// then writes the chunk's units (consecutive in u) as 16-byte stores, two
+// consecutive units per thread and step.  Every global load a thread needs
+// for the stores (the staging float4s and its first kSwPairs pairs of unit
+// offsets, read as 32-bit words) is issued before the barrier, so the stores
+// never wait behind a load: the vector memory counter counts loads and stores
+// in one order, and a load issued after a store would make the store's
+// completion part of the wait.
+constexpr int kSwPairs = 9;  // 2 x 9 x 1024 units per chunk before the tail loop (about 16K expected)
 
 __global__ __launch_bounds__(kSwThreads) void k_sw_scatter(const float* __restrict__ src, int64_t N,
                                                            const int32_t* __restrict__ cb,
                                                            const uint16_t* __restrict__ off, float4* __restrict__ u,
                                                            const int32_t* __restrict__ done) {
     constexpr int kC = 1 << kSwCs;
-    __shared__ float st[kC];
+    __shared__ __align__(16) float st[kC + 8];
     if (done && *done) return;  // the solver's converged flag (launch-uniform)
+    const int tid = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x << kSwCs;
     const int cnt = (int)std::min<int64_t>(kC, N - c0);
-    const int32_t q0 = cb[blockIdx.x] + (int32_t)threadIdx.x, q1 = cb[blockIdx.x + 1];
-    int o[kSwPre];
+    const int32_t q0 = cb[blockIdx.x], q1 = cb[blockIdx.x + 1];
+    // unit pairs (2p, 2p + 1) for p from q0 / 2: 32-bit loads of two offsets
+    const int32_t p0 = q0 >> 1;
+    const uint32_t* off2 = reinterpret_cast<const uint32_t*>(off);
+    const int32_t p1 = (q1 + 1) >> 1;
+    uint32_t o[kSwPairs];
 #pragma unroll
-    for (int k = 0; k < kSwPre; ++k) {
-        const int32_t q = q0 + k * kSwThreads;
-        o[k] = q < q1 ? (int)off[q] : 0;
+    for (int k = 0; k < kSwPairs; ++k) {
+        const int32_t p = p0 + tid + k * kSwThreads;
+        o[k] = p < p1 ? __builtin_nontemporal_load(off2 + p) : 0u;
     }
-    for (int j = threadIdx.x; j < cnt; j += kSwThreads) st[j] = src[c0 + j];
-    __syncthreads();
-    auto unit = [&](int oq) {
-        float v[kSwUnit];
+    const float* s0 = src + c0;
+    const int n4 = cnt >> 2;
+    if ((reinterpret_cast<uintptr_t>(s0) & 15) == 0) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 a[kC / 4 / kSwThreads];
 #pragma unroll
-        for (int k = 0; k < kSwUnit; ++k) {
-            const int ok = oq + k;
-            v[k] = ok < cnt ? st[ok] : (c0 + ok < N ? src[c0 + ok] : 0.0f);
+        for (int k = 0; k < kC / 4 / kSwThreads; ++k) {
+            const int i = tid + k * kSwThreads;
+            a[k] = i < n4 ? __builtin_nontemporal_load(reinterpret_cast<const f4*>(s0) + i) : f4{0.f, 0.f, 0.f, 0.f};
         }
-        return make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+        for (int k = 0; k < kC / 4 / kSwThreads; ++k) {
+            const int i = tid + k * kSwThreads;
+            if (i < n4) reinterpret_cast<f4*>(st)[i] = a[k];
+        }
+    } else {
+        for (int j = tid; j < 4 * n4; j += kSwThreads) st[j] = s0[j];
+    }
+    // the last cnt mod 4 sources and the 3 after the chunk (zero past N)
+    if (tid < 8) {
+        const int j = 4 * n4 + tid;
+        if (j < cnt + kSwUnit - 1) st[j] = c0 + j < N ? s0[j] : 0.0f;
+    }
+    __syncthreads();
+    auto put = [&](int32_t p, uint32_t w) {
+        const int32_t q = 2 * p;
+        if (q >= q0 && q < q1) {
+            const int a = (int)(w & 0xffffu);
+            u[q] = make_float4(st[a], st[a + 1], st[a + 2], st[a + 3]);
+        }
+        if (q + 1 >= q0 && q + 1 < q1) {
+            const int a = (int)(w >> 16);
+            u[q + 1] = make_float4(st[a], st[a + 1], st[a + 2], st[a + 3]);
+        }
     };
 #pragma unroll
-    for (int k = 0; k < kSwPre; ++k) {
-        const int32_t q = q0 + k * kSwThreads;
-        if (q < q1) u[q] = unit(o[k]);
-    }
-    for (int32_t q = q0 + kSwPre * kSwThreads; q < q1; q += kSwThreads) u[q] = unit(off[q]);
+    for (int k = 0; k < kSwPairs; ++k) put(p0 + tid + k * kSwThreads, o[k]);
+    for (int32_t p = p0 + tid + kSwPairs * kSwThreads; p < p1; p += kSwThreads) put(p, off2[p]);
 }
 
 }  // namespace

@@ -229,7 +229,11 @@ def test_matrix_free_products_multiblock(cfg):
             assert np.abs(out.double().cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max()), (prec, trans)
 
 
-@pytest.mark.parametrize("cfg", MF_MULTIBLOCK + [C1])
+# n = 2^14: source chunks of 2^11 and 2^10 sources, 8 and 16 of them per side
+MF_WIN_FULL_CHUNKS = (32768, 16384, 1e3, 160, 1.0, 31, 2)
+
+
+@pytest.mark.parametrize("cfg", MF_MULTIBLOCK + [C1, MF_WIN_FULL_CHUNKS])
 def test_matrix_free_windowed_gathers_are_bitwise_the_plain_ones(cfg):
     # The windowed gathers (L1LS_STORE_MF_WINDOWS; windows of 256 positions
     # at these sizes, so each side spans several) read the same elements as
