@@ -5,9 +5,9 @@ operator (which at this size runs its windowed gathers).  The whole instance is 
 construction in a test, so the oracle's sampled form
 (``oracle.instance.LocalInstance``) evaluates the sampled outputs one by
 one: bijections at sampled positions, the support, b and e at sampled rows,
-sampled columns and rows of A (structure and values), and the first FISTA
-iterate at sampled columns in the launch configuration the benchmark times.
-Later iterates depend on all of A.  They are checked where the optimality
+sampled columns and rows of A (structure and values), and the first two
+FISTA iterates at sampled columns in the launch configuration the benchmark
+times.  Later iterates depend on all of A.  They are checked where the optimality
 conditions of problem (1) pin them: the certified solve (CG-Newton on the
 matrix-free operator, then the FP64 polish) must reach the planted x*
 (optimal by Procedure IGen, section 3.1) to the FP64 floor, with the oracle
@@ -129,6 +129,28 @@ def test_large_fista_first_iterate():
     # FP32: b rounded once, one rounding per value and product, <= 16-term sums
     bound = 20 * np.finfo(np.float32).eps * mag + 1e-30
     assert np.all(np.abs(x1[js] - ref) <= bound)
+
+
+def test_large_fista_second_iterate():
+    # x_2 = soft(x_1 - A^T (A x_1 - b), tau) (beta_1 = 0, L = 1) at sampled
+    # columns where it is not all zero, from the oracle's sampled form in
+    # FP64, within the a-priori bound of an FP32 computation
+    # (tests/local_iterates.py), on the stored operator with the benchmark's
+    # launch configuration (windowed gathers at this size)
+    from local_iterates import second_iterate, informative_columns
+
+    g, loc, inf = inst()
+    fs = L.Fista(g, precision=L.F32, rel_gap_tol=0.0, check_every=32, op=L.OP_STORED)
+    fs.iterate(2)
+    x2 = fs.get_x().cpu().numpy()
+    fs.destroy()
+    js = informative_columns(loc, 48, 17)
+    ref, bound = second_iterate(loc, js)
+    err = np.abs(x2[js] - ref)
+    print(f"x_2 at {js.size} columns ({np.count_nonzero(ref)} nonzero): max err {err.max():.3e}, "
+          f"max err / bound {float((err / bound).max()):.3f}", flush=True)
+    assert np.count_nonzero(ref) >= 8
+    assert np.all(err <= bound)
 
 
 def test_large_cg_newton_step_matrix_free_and_stored_agree():

@@ -62,3 +62,40 @@ def test_local_instance_sampled_subsets_agree_with_whole_evaluation():
         assert a == b
     rs = np.array([1009, 3, 3, 600])
     assert np.array_equal(loc.b(rs), loc.b(np.arange(1010))[rs])
+
+
+def test_second_iterate_from_the_sampled_form():
+    # tests/local_iterates.py: x_2 at sampled columns from the sampled form
+    # equals the full oracle's FISTA (two iterations, L = 1), an FP32 run of
+    # the same iteration (numpy float32, a rounding sequence of its own) stays
+    # within the a-priori bound, and each planted mistake (x_1 reported, tau
+    # or L off by 1%, the residual's sign flipped, a nonzero first momentum
+    # step) leaves it somewhere.
+    from oracle import fista as F
+    from local_iterates import second_iterate, informative_columns, soft
+    from fp32_bounds import fista_float32
+
+    m, n, kappa, s, tau, seed = 1 << 15, 1 << 14, 1e6, 16, 1.0, 77
+    loc = I.LocalInstance(m, n, kappa, s, tau, seed, rounds=2)
+    full = I.Instance(m, n, kappa, s, tau, seed, rounds=2)
+    A = full.sparse_A().tocsr()
+    mv, rmv = (lambda v: A @ v), (lambda v: A.T @ v)
+    js = informative_columns(loc, 48, 4)
+    ref, bound = second_iterate(loc, js)
+    assert np.count_nonzero(ref) >= 8
+    x2 = F.fista(mv, rmv, full.b, tau, 1.0, 2)
+    assert np.all(np.abs(x2[js] - ref) <= 1e-12 * np.maximum(1.0, np.abs(ref)))
+    x2f = fista_float32(A, full.b, tau, 1.0, 2)
+    assert np.all(np.abs(x2f[js] - ref) <= bound)
+    x1 = F.fista(mv, rmv, full.b, tau, 1.0, 1)
+    r = A @ x1 - full.b
+    y = 1.01 * x1
+    mistakes = {
+        "x_1": x1,
+        "tau": F.fista(mv, rmv, full.b, 0.99 * tau, 1.0, 2),
+        "L": F.fista(mv, rmv, full.b, tau, 1.01, 2),
+        "sign": soft(x1 + A.T @ r, tau),
+        "momentum": soft(y - A.T @ (A @ y - full.b), tau),
+    }
+    for name, bad in mistakes.items():
+        assert np.any(np.abs(bad[js] - ref) > bound), name
