@@ -439,12 +439,13 @@ def bench_serve(args):
                 ids[rid] = nxt
                 nxt += 1
             q, res, _ = S.stats()
-            if q == 0 and res == 0:
-                if nxt < len(reqs):
-                    time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
-                continue
-            S.tick()
-            peak = max(peak, S.stats()[1])
+            if q or res:
+                S.tick()
+                peak = max(peak, S.stats()[1])
+            elif nxt < len(reqs):
+                time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+            # results of the finishing workers can land between two ticks (or
+            # after the last one): collect them on every pass
             done_t = time.perf_counter() - t0
             for rid in S.completed():
                 _, rep = S.take(rid, want_x=False)
