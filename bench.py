@@ -601,6 +601,7 @@ def bench_batched(args):
                                              "bitwise_equal_to_default": shared_same},
                   "converged_batched": sum(r["converged"] == 1 for r in reps), "converged_plain": conv_p,
                   "iterations_batched": iters_b, "iterations_plain": iters_p,
+                  "instance_iterations_per_s": {"batched": iters_b / tb, "plain": iters_p / tp},
                   "bitwise_equal_results": same},
     }
     print(json.dumps(line), flush=True)
