@@ -256,7 +256,9 @@ typedef struct {
                               0 never, 1 always, 2 only when the FP64 gap of
                               the FISTA result exceeds rel_gap_tol; a polish
                               whose result has a larger objective f_tau than
-                              its starting point returns the starting point */
+                              its starting point (by more than 1e-12 relative,
+                              the FP64 rounding of f_tau) returns the
+                              starting point */
     double L;              /* <= 0: the instance's L (sigma_1^2)                 */
     const double* x0_dev;  /* n, warm start; NULL: x0 = 0                       */
     void* stream;
@@ -529,8 +531,8 @@ l1ls_status l1ls_solve_fista_batched(const l1ls_instance* const* insts, const do
  * 0 returns the FP32 iterates with the device's gap; 2 finishes each column
  * in FP64 at its tau (the FP64 gap of the FP32 result, the FP64 polish of the
  * reduced problem (13) where it misses rel_gap_tol, then the FP64 gap of the
- * result in reports[c]); 1 polishes every column.  A polish that does not
- * lower the objective f_tau leaves the column as it was.  polish needs
+ * result in reports[c]); 1 polishes every column.  A polish that raises the
+ * objective f_tau (beyond 1e-12 relative) leaves the column as it was.  polish needs
  * L1LS_STORE_F64 (else L1LS_E_UNSUPPORTED).
  */
 l1ls_status l1ls_solve_fista_path(const l1ls_instance* inst, const double* taus, int32_t k,

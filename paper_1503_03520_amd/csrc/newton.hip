@@ -940,10 +940,14 @@ l1ls_status polish_fp64(const l1ls_instance* I, double tau, double* x_dev, hipSt
                            cnt[0] > 0 ? 1 : 0, n);
     }
     // a polish that ends above the starting objective (a support still far
-    // from the solution's after the last round) returns the starting point
+    // from the solution's after the last round) returns the starting point.
+    // The comparison allows 1e-12 relative: both values carry FP64 rounding
+    // of sums over the m + n terms of f_tau (up to a few units in 1e-15 were
+    // seen between an iterate and its certified polish), and a polish from a
+    // wrong support raises f_tau by far more.
     double f_out = 0.0;
     L1LS_TRY(objective(W.x, &f_out));
-    const bool keep = f_out <= f_in;
+    const bool keep = f_out <= f_in + 1e-12 * fabs(f_in);
     if (std::getenv("L1LS_DEBUG_POLISH"))
         std::fprintf(stderr, "l1ls polish: f_tau %.17g -> %.17g (%s)\n", f_in, f_out, keep ? "kept" : "reverted");
     hipLaunchKernelGGL((k_gather_perm<double, double>), g1d(n), dim3(L1LS_BLOCK), 0, s, keep ? W.x : W.grad, x_dev,
